@@ -1,0 +1,187 @@
+"""ctypes front end of the FP64 CPU oracle (oracle.c).
+
+TEST INFRASTRUCTURE ONLY: imported by tests, by the smoke check and by the
+benchmark's CPU-baseline leg.  The GPU library and its Python binding never
+import it.  It shares no code with them; both take their inputs from the
+seeded generators.
+
+Functions take numpy arrays and a problems.Csr-like object (attributes n,
+row_ptr, col_idx, vals).
+"""
+from __future__ import annotations
+
+import contextlib
+import ctypes
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+from .build import build as _build, library_path
+
+METHODS = {
+    "cg_classical": 0,
+    "cg_pipelined": 1,
+    "bicgstab_classical": 2,
+    "bicgstab_pipelined": 3,
+}
+STATUS = {0: "converged", 1: "not_converged", 2: "breakdown", 3: "bad_arg"}
+
+# Slots of one per-iteration trace record (see oracle.c).
+TRACE_SLOTS = {
+    "alpha": 0, "beta": 1, "omega": 2, "rr": 2, "rho": 3, "pap": 3, "apr": 4,
+    "apap": 4, "rr_new": 5, "ss": 5, "ass": 6, "asas": 7, "asr": 8,
+    "rr_expanded": 9, "rr_direct": 10,
+}
+
+class Oracle:
+    """One loaded build of oracle.c (the default build, or a test variant)."""
+
+    def __init__(self, path: str | None = None):
+        path = path or library_path()
+        if not os.path.exists(path):
+            _build()
+        lib = ctypes.CDLL(path)
+        i32p = ctypes.POINTER(ctypes.c_int32)
+        f64p = ctypes.POINTER(ctypes.c_double)
+        lib.oracle_spmv.argtypes = [ctypes.c_int64, i32p, i32p, f64p, f64p, f64p]
+        lib.oracle_spmv.restype = None
+        lib.oracle_dot.argtypes = [ctypes.c_int64, f64p, f64p]
+        lib.oracle_dot.restype = ctypes.c_double
+        lib.oracle_set_dot_mode.argtypes = [ctypes.c_int]
+        lib.oracle_set_dot_mode.restype = None
+        lib.oracle_get_dot_mode.argtypes = []
+        lib.oracle_get_dot_mode.restype = ctypes.c_int
+        lib.oracle_trace_stride.argtypes = []
+        lib.oracle_trace_stride.restype = ctypes.c_int
+        lib.oracle_solve.argtypes = [
+            ctypes.c_int, ctypes.c_int64, i32p, i32p, f64p, f64p, f64p, f64p,
+            ctypes.c_double, ctypes.c_int32, f64p, f64p, ctypes.c_int32,
+            ctypes.POINTER(ctypes.c_int32),
+        ]
+        lib.oracle_solve.restype = ctypes.c_int
+        self.lib = lib
+        self.path = path
+
+    def spmv(self, A, p) -> np.ndarray:
+        """q = A p, rows summed left to right in CSR order."""
+        rp, rpp = _i32(A.row_ptr)
+        ci, cip = _i32(A.col_idx)
+        v, vp = _f64(A.vals)
+        p, pp = _f64(p)
+        q = np.empty(A.n)
+        _, qp = _f64(q)
+        self.lib.oracle_spmv(A.n, rpp, cip, vp, pp, qp)
+        return q
+
+    def dot(self, a, b) -> float:
+        """<a, b> by the compensated dot (twice working precision, one rounding)."""
+        a, ap = _f64(a)
+        b, bp = _f64(b)
+        if a.shape != b.shape:
+            raise ValueError("shape mismatch")
+        return float(self.lib.oracle_dot(a.size, ap, bp))
+
+    @contextlib.contextmanager
+    def dot_mode(self, mode: int):
+        """Temporarily switch the summation order of every oracle dot.
+
+        0 = compensated (the oracle), 1 = plain left-to-right, 2 = plain
+        pairwise.  Only for measuring how sensitive a trajectory is to
+        summation order.
+        """
+        old = self.lib.oracle_get_dot_mode()
+        self.lib.oracle_set_dot_mode(int(mode))
+        try:
+            yield
+        finally:
+            self.lib.oracle_set_dot_mode(old)
+
+    def solve(self, A, b, x0=None, method: str = "cg_pipelined", rtol: float = 1e-8,
+              max_iter: int | None = None, trace: bool = False) -> "Result":
+        """Run one of Algorithms 1-4 on the CPU in FP64."""
+        n = A.n
+        if max_iter is None:
+            max_iter = 10 * n
+        rp, rpp = _i32(A.row_ptr)
+        ci, cip = _i32(A.col_idx)
+        v, vp = _f64(A.vals)
+        b, bp = _f64(b)
+        x = np.zeros(n) if x0 is None else np.array(x0, dtype=np.float64, copy=True)
+        _, xp = _f64(x)
+        r = np.empty(n)
+        _, rptr = _f64(r)
+        cap = max_iter + 1
+        hist = np.full(cap, np.nan)
+        _, hp = _f64(hist)
+        stride = self.lib.oracle_trace_stride()
+        tr = np.full((cap, stride), np.nan) if trace else None
+        trp = _f64(tr)[1] if trace else None
+        k = ctypes.c_int32(0)
+        st = self.lib.oracle_solve(METHODS[method], n, rpp, cip, vp, bp, xp, rptr, float(rtol),
+                                   int(max_iter), hp, trp, cap, ctypes.byref(k))
+        kk = int(k.value)
+        return Result(x=x, r=r, k=kk, status=STATUS[st], hist=hist[: kk + 1].copy(),
+                      trace=None if tr is None else tr[:kk].copy())
+
+    def true_residual(self, A, b, x) -> float:
+        """||b - A x|| / ||b|| with the oracle's product and compensated dots."""
+        ax = self.spmv(A, x)
+        r = np.asarray(b, dtype=np.float64) - ax
+        bb = self.dot(b, b)
+        rr = self.dot(r, r)
+        return float(np.sqrt(rr) / np.sqrt(bb)) if bb > 0 else float(np.sqrt(rr))
+
+
+_default = None
+
+
+def default() -> Oracle:
+    global _default
+    if _default is None:
+        _default = Oracle()
+    return _default
+
+
+def _f64(a):
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    return a, a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _i32(a):
+    a = np.ascontiguousarray(a, dtype=np.int32)
+    return a, a.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+
+
+def spmv(A, p) -> np.ndarray:
+    return default().spmv(A, p)
+
+
+def dot(a, b) -> float:
+    return default().dot(a, b)
+
+
+def dot_mode(mode: int):
+    return default().dot_mode(mode)
+
+
+def solve(A, b, x0=None, method: str = "cg_pipelined", rtol: float = 1e-8,
+          max_iter: int | None = None, trace: bool = False) -> "Result":
+    return default().solve(A, b, x0=x0, method=method, rtol=rtol, max_iter=max_iter, trace=trace)
+
+
+def true_residual(A, b, x) -> float:
+    return default().true_residual(A, b, x)
+
+
+@dataclass
+class Result:
+    x: np.ndarray
+    r: np.ndarray
+    k: int
+    status: str
+    hist: np.ndarray  # ||r_i||/||b||, i = 0..k
+    trace: np.ndarray | None  # (k, stride) per-iteration scalars
+
+    def t(self, name: str) -> np.ndarray:
+        return self.trace[:, TRACE_SLOTS[name]]

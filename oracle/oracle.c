@@ -1,0 +1,473 @@
+/*
+ * Plain FP64 CPU oracle for the Krylov solvers of Rupp, Weinbub, Juengel and
+ * Grasser, "Pipelined Iterative Solvers with Kernel Fusion for Graphics
+ * Processing Units" (arXiv:1410.4054).
+ *
+ * TEST INFRASTRUCTURE ONLY.  Tests, the smoke check and the benchmark's CPU
+ * baseline call it to obtain expected values.  The GPU library never links,
+ * loads or calls this file and shares no code, header or constant with it.
+ *
+ * Everything is sequential, in the order the paper states it:
+ *   - oracle_spmv   : q = A p, one row at a time, each row summed left to
+ *                     right in CSR order (Section 2.2, the CSR product);
+ *   - oracle_dot    : <a, b> computed as if in twice the working precision
+ *                     (the compensated "Dot2" of Ogita, Rump and Oishi,
+ *                     SIAM J. Sci. Comput. 26(6), 2005), then rounded once;
+ *   - cg_classical       : Algorithm 1;
+ *   - cg_pipelined       : Algorithm 2 with the beta recurrence of Eq. (3);
+ *   - bicgstab_classical : Algorithm 3;
+ *   - bicgstab_pipelined : Algorithm 4, beta from the orthogonality
+ *                          <s_i, r0*> = 0 and the residual norm from the
+ *                          expansion of <r_{i+1}, r_{i+1}> (Section 3.2).
+ *
+ * Build with -ffp-contract=off: every product and every sum is rounded on its
+ * own; the only fused multiply-add is the explicit fma() that extracts the
+ * exact rounding error of a product inside the compensated dot.
+ *
+ * Readings where the paper is silent or its listing is garbled:
+ *   - alpha in Algorithm 2 is <r_i,r_i>/<p_i,Ap_i> (as in Algorithm 1);
+ *   - the search-direction update of Algorithms 3 and 4 is
+ *     p_{i+1} = r_{i+1} + beta_i (p_i - omega_i A p_i);
+ *   - beta in Algorithm 4 is -<As_i,r0*>/<Ap_i,r0*>;
+ *   - r0* = r0 = b - A x0;
+ *   - convergence: ||r_k|| <= rtol ||b|| on the recursively updated residual;
+ *     pipelined BiCGStab decides on the expanded norm, clamped at 0;
+ *   - BiCGStab stops after the half step when ||s_i|| <= rtol ||b||
+ *     (x_{i+1} = x_i + alpha_i p_i), which also avoids omega = 0/0;
+ *   - k counts solution updates; b = 0 returns x = 0, k = 0.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+enum { OR_CONVERGED = 0, OR_NOT_CONVERGED = 1, OR_BREAKDOWN = 2, OR_BAD_ARG = 3 };
+enum { OR_CG_CLASSICAL = 0, OR_CG_PIPELINED = 1, OR_BICGSTAB_CLASSICAL = 2, OR_BICGSTAB_PIPELINED = 3 };
+
+/* Per-iteration trace record: TRACE_STRIDE doubles per iteration. */
+#define TRACE_STRIDE 12
+
+/* Summation mode of oracle_dot; 0 (compensated) is the oracle.  Modes 1 and 2
+ * exist only to measure how sensitive a trajectory is to summation order. */
+static int g_dot_mode = 0;
+
+void oracle_set_dot_mode(int mode) { g_dot_mode = mode; }
+int oracle_get_dot_mode(void) { return g_dot_mode; }
+
+/* ---------------------------------------------------------------- products */
+
+/* q_i = sum_j vals[j] * p[col[j]] for j = row_ptr[i] .. row_ptr[i+1]-1, summed
+ * left to right starting from 0 (Section 2.2, CSR sparse matrix-vector
+ * product). */
+void oracle_spmv(int64_t n, const int32_t *row_ptr, const int32_t *col_idx,
+                 const double *vals, const double *p, double *q)
+{
+    for (int64_t i = 0; i < n; ++i) {
+        double acc = 0.0;
+        for (int64_t j = row_ptr[i]; j < row_ptr[i + 1]; ++j)
+            acc = acc + vals[j] * p[col_idx[j]];
+        q[i] = acc;
+    }
+}
+
+/* Error-free transformations (Knuth's TwoSum; TwoProduct through fma). */
+static void two_sum(double a, double b, double *s, double *e)
+{
+    double x = a + b;
+    double z = x - a;
+    *e = (a - (x - z)) + (b - z);
+    *s = x;
+}
+
+static void two_prod(double a, double b, double *p, double *e)
+{
+    double x = a * b;
+    *e = fma(a, b, -x);
+    *p = x;
+}
+
+static double dot_compensated(int64_t n, const double *a, const double *b)
+{
+    if (n == 0)
+        return 0.0;
+    double p, s;
+    two_prod(a[0], b[0], &p, &s);
+    for (int64_t i = 1; i < n; ++i) {
+        double h, r, q;
+        two_prod(a[i], b[i], &h, &r);
+        two_sum(p, h, &p, &q);
+        s = s + (q + r);
+    }
+    return p + s;
+}
+
+static double dot_sequential(int64_t n, const double *a, const double *b)
+{
+    double acc = 0.0;
+    for (int64_t i = 0; i < n; ++i)
+        acc = acc + a[i] * b[i];
+    return acc;
+}
+
+static double dot_pairwise(int64_t n, const double *a, const double *b)
+{
+    if (n <= 8)
+        return dot_sequential(n, a, b);
+    int64_t h = n / 2;
+    return dot_pairwise(h, a, b) + dot_pairwise(n - h, a + h, b + h);
+}
+
+double oracle_dot(int64_t n, const double *a, const double *b)
+{
+    switch (g_dot_mode) {
+    case 1: return dot_sequential(n, a, b);
+    case 2: return dot_pairwise(n, a, b);
+    default: return dot_compensated(n, a, b);
+    }
+}
+
+/* ------------------------------------------------------------ small helpers */
+
+typedef struct {
+    int64_t n;
+    const int32_t *rp;
+    const int32_t *ci;
+    const double *v;
+} csr_t;
+
+static void matvec(const csr_t *A, const double *p, double *q)
+{
+    oracle_spmv(A->n, A->rp, A->ci, A->v, p, q);
+}
+
+static int finite(double a) { return isfinite(a) ? 1 : 0; }
+
+static double *vec(int64_t n)
+{
+    return (double *)calloc((size_t)(n > 0 ? n : 1), sizeof(double));
+}
+
+static void put_trace(double *trace, int32_t cap, int32_t it, int slot, double value)
+{
+    if (trace && it < cap)
+        trace[(int64_t)it * TRACE_STRIDE + slot] = value;
+}
+
+static void put_hist(double *hist, int32_t cap, int32_t it, double value)
+{
+    if (hist && it < cap)
+        hist[it] = value;
+}
+
+/* r = b - A x; returns 0 on allocation failure. */
+static int initial_residual(const csr_t *A, const double *b, const double *x, double *r)
+{
+    double *ax = vec(A->n);
+    if (!ax)
+        return 0;
+    matvec(A, x, ax);
+    for (int64_t i = 0; i < A->n; ++i)
+        r[i] = b[i] - ax[i];
+    free(ax);
+    return 1;
+}
+
+/* ---------------------------------------------------- Algorithm 1: CG */
+
+static int cg_classical(const csr_t *A, const double *b, double *x, double *r,
+                        double rtol, int32_t max_iter, double *hist, double *trace,
+                        int32_t cap, int32_t *k_out)
+{
+    int64_t n = A->n;
+    double *p = vec(n), *q = vec(n);
+    int status = OR_NOT_CONVERGED;
+    int32_t k = 0;
+    if (!p || !q) { status = OR_BAD_ARG; goto done; }
+
+    double bnorm = sqrt(oracle_dot(n, b, b));
+    double tol = rtol * bnorm;
+    if (!initial_residual(A, b, x, r)) { status = OR_BAD_ARG; goto done; }
+    memcpy(p, r, (size_t)n * sizeof(double));            /* p_0 = r_0 */
+    double rr = oracle_dot(n, r, r);
+    put_hist(hist, cap, 0, sqrt(rr) / bnorm);
+    if (!finite(rr)) { status = OR_BREAKDOWN; goto done; }
+    if (sqrt(rr) <= tol) { status = OR_CONVERGED; goto done; }
+
+    for (int32_t i = 0; i < max_iter; ++i) {
+        matvec(A, p, q);                                   /* A p_i */
+        double pq = oracle_dot(n, p, q);                   /* <p_i, A p_i> */
+        if (!(pq > 0.0) || !finite(pq)) { status = OR_BREAKDOWN; break; }
+        double alpha = rr / pq;
+        for (int64_t j = 0; j < n; ++j) x[j] = x[j] + alpha * p[j];
+        for (int64_t j = 0; j < n; ++j) r[j] = r[j] - alpha * q[j];
+        double rr_new = oracle_dot(n, r, r);               /* <r_{i+1}, r_{i+1}> */
+        k = i + 1;
+        put_hist(hist, cap, k, sqrt(rr_new) / bnorm);
+        put_trace(trace, cap, i, 0, alpha);
+        put_trace(trace, cap, i, 2, rr);
+        put_trace(trace, cap, i, 3, pq);
+        put_trace(trace, cap, i, 5, rr_new);
+        if (!finite(rr_new)) { status = OR_BREAKDOWN; break; }
+        if (sqrt(rr_new) <= tol) { status = OR_CONVERGED; break; }
+        double beta = rr_new / rr;
+        put_trace(trace, cap, i, 1, beta);
+        for (int64_t j = 0; j < n; ++j) p[j] = r[j] + beta * p[j];
+        rr = rr_new;
+    }
+done:
+    free(p); free(q);
+    *k_out = k;
+    return status;
+}
+
+/* ------------------------------------------ Algorithm 2: pipelined CG */
+
+static int cg_pipelined(const csr_t *A, const double *b, double *x, double *r,
+                        double rtol, int32_t max_iter, double *hist, double *trace,
+                        int32_t cap, int32_t *k_out)
+{
+    int64_t n = A->n;
+    double *p = vec(n), *ap = vec(n);
+    int status = OR_NOT_CONVERGED;
+    int32_t k = 0;
+    if (!p || !ap) { status = OR_BAD_ARG; goto done; }
+
+    double bnorm = sqrt(oracle_dot(n, b, b));
+    double tol = rtol * bnorm;
+    if (!initial_residual(A, b, x, r)) { status = OR_BAD_ARG; goto done; }
+    memcpy(p, r, (size_t)n * sizeof(double));            /* p_0 = r_0 */
+    double rr = oracle_dot(n, r, r);                       /* <r_0, r_0> */
+    put_hist(hist, cap, 0, sqrt(rr) / bnorm);
+    if (!finite(rr)) { status = OR_BREAKDOWN; goto done; }
+    if (sqrt(rr) <= tol) { status = OR_CONVERGED; goto done; }
+
+    matvec(A, p, ap);                                      /* A p_0 */
+    double pap = oracle_dot(n, p, ap);
+    double apap = oracle_dot(n, ap, ap);
+    if (!(pap > 0.0) || !finite(pap) || !finite(apap)) { status = OR_BREAKDOWN; goto done; }
+    double alpha = rr / pap;
+    double beta = alpha * alpha * apap / rr - 1.0;         /* Eq. (3) */
+
+    for (int32_t i = 1; i <= max_iter; ++i) {
+        put_trace(trace, cap, i - 1, 0, alpha);
+        put_trace(trace, cap, i - 1, 1, beta);
+        put_trace(trace, cap, i - 1, 2, rr);
+        put_trace(trace, cap, i - 1, 3, pap);
+        put_trace(trace, cap, i - 1, 4, apap);
+        for (int64_t j = 0; j < n; ++j) x[j] = x[j] + alpha * p[j];   /* x_i */
+        for (int64_t j = 0; j < n; ++j) r[j] = r[j] - alpha * ap[j];  /* r_i */
+        for (int64_t j = 0; j < n; ++j) p[j] = r[j] + beta * p[j];    /* p_i */
+        rr = oracle_dot(n, r, r);                                      /* <r_i, r_i> */
+        k = i;
+        put_hist(hist, cap, k, sqrt(rr) / bnorm);
+        put_trace(trace, cap, i - 1, 5, rr);
+        if (!finite(rr)) { status = OR_BREAKDOWN; break; }
+        if (sqrt(rr) <= tol) { status = OR_CONVERGED; break; }
+        if (i == max_iter) break;
+        matvec(A, p, ap);                                              /* A p_i */
+        pap = oracle_dot(n, p, ap);                                    /* <p_i, A p_i> */
+        apap = oracle_dot(n, ap, ap);                                  /* <A p_i, A p_i> */
+        if (!(pap > 0.0) || !finite(pap) || !finite(apap)) { status = OR_BREAKDOWN; break; }
+        alpha = rr / pap;
+        beta = alpha * alpha * apap / rr - 1.0;                        /* Eq. (3) */
+    }
+done:
+    free(p); free(ap);
+    *k_out = k;
+    return status;
+}
+
+/* -------------------------------------------- Algorithm 3: BiCGStab */
+
+static int bicgstab_classical(const csr_t *A, const double *b, double *x, double *r,
+                              double rtol, int32_t max_iter, double *hist, double *trace,
+                              int32_t cap, int32_t *k_out)
+{
+    int64_t n = A->n;
+    double *rs = vec(n), *p = vec(n), *v = vec(n), *s = vec(n), *t = vec(n);
+    int status = OR_NOT_CONVERGED;
+    int32_t k = 0;
+    if (!rs || !p || !v || !s || !t) { status = OR_BAD_ARG; goto done; }
+
+    double bnorm = sqrt(oracle_dot(n, b, b));
+    double tol = rtol * bnorm;
+    if (!initial_residual(A, b, x, r)) { status = OR_BAD_ARG; goto done; }
+    memcpy(rs, r, (size_t)n * sizeof(double));           /* r0* = r0 */
+    memcpy(p, r, (size_t)n * sizeof(double));            /* p0 = r0 */
+    double rr0 = oracle_dot(n, r, r);
+    put_hist(hist, cap, 0, sqrt(rr0) / bnorm);
+    if (!finite(rr0)) { status = OR_BREAKDOWN; goto done; }
+    if (sqrt(rr0) <= tol) { status = OR_CONVERGED; goto done; }
+    double rho = oracle_dot(n, r, rs);                     /* <r_0, r0*> */
+
+    for (int32_t i = 0; i < max_iter; ++i) {
+        matvec(A, p, v);                                   /* A p_i */
+        double vr = oracle_dot(n, v, rs);                  /* <A p_i, r0*> */
+        if (vr == 0.0 || !finite(vr) || rho == 0.0 || !finite(rho)) { status = OR_BREAKDOWN; break; }
+        double alpha = rho / vr;
+        for (int64_t j = 0; j < n; ++j) s[j] = r[j] - alpha * v[j];   /* s_i */
+        double ss = oracle_dot(n, s, s);
+        put_trace(trace, cap, i, 0, alpha);
+        put_trace(trace, cap, i, 3, rho);
+        put_trace(trace, cap, i, 4, vr);
+        put_trace(trace, cap, i, 5, ss);
+        if (sqrt(ss) <= tol) {                             /* half-step exit */
+            for (int64_t j = 0; j < n; ++j) x[j] = x[j] + alpha * p[j];
+            memcpy(r, s, (size_t)n * sizeof(double));
+            k = i + 1;
+            put_hist(hist, cap, k, sqrt(ss) / bnorm);
+            status = OR_CONVERGED;
+            break;
+        }
+        matvec(A, s, t);                                   /* A s_i */
+        double ts = oracle_dot(n, t, s);                   /* <A s_i, s_i> */
+        double tt = oracle_dot(n, t, t);                   /* <A s_i, A s_i> */
+        if (tt == 0.0 || !finite(tt) || !finite(ts)) { status = OR_BREAKDOWN; break; }
+        double omega = ts / tt;
+        for (int64_t j = 0; j < n; ++j) x[j] = x[j] + alpha * p[j] + omega * s[j];
+        for (int64_t j = 0; j < n; ++j) r[j] = s[j] - omega * t[j];
+        double rr = oracle_dot(n, r, r);
+        k = i + 1;
+        put_hist(hist, cap, k, sqrt(rr) / bnorm);
+        put_trace(trace, cap, i, 2, omega);
+        put_trace(trace, cap, i, 6, ts);
+        put_trace(trace, cap, i, 7, tt);
+        put_trace(trace, cap, i, 10, rr);
+        if (!finite(rr)) { status = OR_BREAKDOWN; break; }
+        if (sqrt(rr) <= tol) { status = OR_CONVERGED; break; }
+        double rho_new = oracle_dot(n, r, rs);             /* <r_{i+1}, r0*> */
+        if (omega == 0.0 || rho_new == 0.0 || !finite(rho_new)) { status = OR_BREAKDOWN; break; }
+        double beta = (rho_new / rho) * (alpha / omega);
+        put_trace(trace, cap, i, 1, beta);
+        for (int64_t j = 0; j < n; ++j) p[j] = r[j] + beta * (p[j] - omega * v[j]);
+        rho = rho_new;
+    }
+done:
+    free(rs); free(p); free(v); free(s); free(t);
+    *k_out = k;
+    return status;
+}
+
+/* ----------------------------------- Algorithm 4: pipelined BiCGStab */
+
+static int bicgstab_pipelined(const csr_t *A, const double *b, double *x, double *r,
+                              double rtol, int32_t max_iter, double *hist, double *trace,
+                              int32_t cap, int32_t *k_out)
+{
+    int64_t n = A->n;
+    double *rs = vec(n), *p = vec(n), *ap = vec(n), *s = vec(n), *as = vec(n);
+    int status = OR_NOT_CONVERGED;
+    int32_t k = 0;
+    if (!rs || !p || !ap || !s || !as) { status = OR_BAD_ARG; goto done; }
+
+    double bnorm = sqrt(oracle_dot(n, b, b));
+    double tol = rtol * bnorm;
+    if (!initial_residual(A, b, x, r)) { status = OR_BAD_ARG; goto done; }
+    memcpy(rs, r, (size_t)n * sizeof(double));           /* r0* = r0 */
+    memcpy(p, r, (size_t)n * sizeof(double));            /* p0 = r0 */
+    double rr0 = oracle_dot(n, r, r);
+    put_hist(hist, cap, 0, sqrt(rr0) / bnorm);
+    if (!finite(rr0)) { status = OR_BREAKDOWN; goto done; }
+    if (sqrt(rr0) <= tol) { status = OR_CONVERGED; goto done; }
+    double rho = oracle_dot(n, r, rs);                     /* <r_0, r0*> */
+
+    for (int32_t i = 0; i < max_iter; ++i) {
+        matvec(A, p, ap);                                  /* A p_i */
+        double apr = oracle_dot(n, ap, rs);                /* <A p_i, r0*> */
+        if (apr == 0.0 || !finite(apr) || rho == 0.0 || !finite(rho)) { status = OR_BREAKDOWN; break; }
+        double alpha = rho / apr;
+        for (int64_t j = 0; j < n; ++j) s[j] = r[j] - alpha * ap[j];  /* s_i */
+        double ss = oracle_dot(n, s, s);                   /* <s_i, s_i> */
+        put_trace(trace, cap, i, 0, alpha);
+        put_trace(trace, cap, i, 3, rho);
+        put_trace(trace, cap, i, 4, apr);
+        put_trace(trace, cap, i, 5, ss);
+        if (sqrt(ss) <= tol) {                             /* half-step exit */
+            for (int64_t j = 0; j < n; ++j) x[j] = x[j] + alpha * p[j];
+            memcpy(r, s, (size_t)n * sizeof(double));
+            k = i + 1;
+            put_hist(hist, cap, k, sqrt(ss) / bnorm);
+            status = OR_CONVERGED;
+            break;
+        }
+        matvec(A, s, as);                                  /* A s_i */
+        double ass = oracle_dot(n, as, s);                 /* <A s_i, s_i> */
+        double asas = oracle_dot(n, as, as);               /* <A s_i, A s_i> */
+        double asr = oracle_dot(n, as, rs);                /* <A s_i, r0*> */
+        if (asas == 0.0 || !finite(asas) || !finite(ass) || !finite(asr)) { status = OR_BREAKDOWN; break; }
+        double beta = -asr / apr;                          /* beta via <s_i, r0*> = 0 */
+        double omega = ass / asas;
+        /* <r_{i+1}, r_{i+1}> expanded in <s,s>, <s,As>, <As,As> */
+        double rr_next = ss - 2.0 * omega * ass + omega * omega * asas;
+        for (int64_t j = 0; j < n; ++j) x[j] = x[j] + alpha * p[j] + omega * s[j];
+        for (int64_t j = 0; j < n; ++j) r[j] = s[j] - omega * as[j];
+        for (int64_t j = 0; j < n; ++j) p[j] = r[j] + beta * (p[j] - omega * ap[j]);
+        rho = oracle_dot(n, r, rs);                        /* <r_{i+1}, r0*> */
+        double rnorm = sqrt(rr_next > 0.0 ? rr_next : 0.0);
+        k = i + 1;
+        put_hist(hist, cap, k, rnorm / bnorm);
+        put_trace(trace, cap, i, 1, beta);
+        put_trace(trace, cap, i, 2, omega);
+        put_trace(trace, cap, i, 6, ass);
+        put_trace(trace, cap, i, 7, asas);
+        put_trace(trace, cap, i, 8, asr);
+        put_trace(trace, cap, i, 9, rr_next);
+        if (trace && i < cap)
+            put_trace(trace, cap, i, 10, oracle_dot(n, r, r));   /* diagnostic only */
+        if (!finite(rr_next)) { status = OR_BREAKDOWN; break; }
+        if (rnorm <= tol) { status = OR_CONVERGED; break; }
+        if (omega == 0.0) { status = OR_BREAKDOWN; break; }
+    }
+done:
+    free(rs); free(p); free(ap); free(s); free(as);
+    *k_out = k;
+    return status;
+}
+
+/* --------------------------------------------------------------- entry */
+
+/*
+ * Solve A x = b.  x holds x0 on entry and the last iterate on return; r (may
+ * be NULL) receives the recursively updated residual.  hist (may be NULL)
+ * receives ||r_i||/||b|| for i = 0..k; trace (may be NULL) receives
+ * TRACE_STRIDE scalars per iteration; cap bounds both.  Returns OR_*.
+ */
+int oracle_solve(int method, int64_t n, const int32_t *row_ptr, const int32_t *col_idx,
+                 const double *vals, const double *b, double *x, double *r,
+                 double rtol, int32_t max_iter, double *hist, double *trace,
+                 int32_t cap, int32_t *k_out)
+{
+    *k_out = 0;
+    if (n <= 0 || !row_ptr || !col_idx || !vals || !b || !x || max_iter < 0 || !(rtol >= 0.0))
+        return OR_BAD_ARG;
+    csr_t A = {n, row_ptr, col_idx, vals};
+    double *rbuf = r ? r : vec(n);
+    if (!rbuf)
+        return OR_BAD_ARG;
+
+    double bb = oracle_dot(n, b, b);
+    int status;
+    if (bb == 0.0) {                                       /* b = 0: x = 0 */
+        for (int64_t j = 0; j < n; ++j) { x[j] = 0.0; rbuf[j] = 0.0; }
+        put_hist(hist, cap, 0, 0.0);
+        status = OR_CONVERGED;
+    } else {
+        switch (method) {
+        case OR_CG_CLASSICAL:
+            status = cg_classical(&A, b, x, rbuf, rtol, max_iter, hist, trace, cap, k_out); break;
+        case OR_CG_PIPELINED:
+            status = cg_pipelined(&A, b, x, rbuf, rtol, max_iter, hist, trace, cap, k_out); break;
+        case OR_BICGSTAB_CLASSICAL:
+            status = bicgstab_classical(&A, b, x, rbuf, rtol, max_iter, hist, trace, cap, k_out); break;
+        case OR_BICGSTAB_PIPELINED:
+            status = bicgstab_pipelined(&A, b, x, rbuf, rtol, max_iter, hist, trace, cap, k_out); break;
+        default:
+            status = OR_BAD_ARG;
+        }
+    }
+    if (!r)
+        free(rbuf);
+    return status;
+}
+
+int oracle_trace_stride(void) { return TRACE_STRIDE; }

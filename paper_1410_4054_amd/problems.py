@@ -1,0 +1,267 @@
+"""Seeded synthetic inputs: sparse matrices in CSR form and right-hand sides.
+
+This module only *builds inputs*.  It holds none of the solver arithmetic
+(no products with vectors, no inner products, no iteration), so both the HIP
+path and the CPU oracle may take their inputs from it.
+
+The paper measures on 2D/3D finite-element meshes and on a set of public
+sparse matrices (Section 4, Table 1); none of those are available here.  The
+generators below stand in for them with finite-difference stencils of the
+same sparsity regime (about 5 to 7 nonzeros per row) and the same size range,
+plus the random-column matrices of the fused SpMV+dot microbenchmark
+(Section 2.2, four and 28 uniformly random nonzeros per row).
+
+Conventions for every stencil matrix:
+  * homogeneous Dirichlet boundary, interior unknowns only;
+  * lexicographic order with x fastest: row = ix + n*iy (+ n*n*iz);
+  * column indices strictly ascending inside each row;
+  * int32 row_ptr / col_idx, float64 values.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass
+
+import numpy as np
+
+
+@dataclass(frozen=True)
+class Csr:
+    """A square CSR matrix held in host memory (numpy arrays)."""
+
+    n: int
+    row_ptr: np.ndarray  # int32[n+1]
+    col_idx: np.ndarray  # int32[nnz]
+    vals: np.ndarray  # float64[nnz]
+
+    @property
+    def nnz(self) -> int:
+        return int(self.row_ptr[-1])
+
+    def to_scipy(self):
+        import scipy.sparse as sp
+
+        return sp.csr_matrix((self.vals, self.col_idx, self.row_ptr), shape=(self.n, self.n))
+
+    def to_dense(self) -> np.ndarray:
+        d = np.zeros((self.n, self.n))
+        rows = np.repeat(np.arange(self.n), np.diff(self.row_ptr))
+        np.add.at(d, (rows, self.col_idx), self.vals)
+        return d
+
+
+def _from_coo(n: int, rows: np.ndarray, cols: np.ndarray, vals: np.ndarray) -> Csr:
+    """Sort (row, col) pairs and pack them as CSR; duplicates are kept as-is."""
+    order = np.lexsort((cols, rows))
+    rows, cols, vals = rows[order], cols[order], vals[order]
+    counts = np.bincount(rows, minlength=n)
+    row_ptr = np.zeros(n + 1, dtype=np.int64)
+    np.cumsum(counts, out=row_ptr[1:])
+    if row_ptr[-1] > np.iinfo(np.int32).max:
+        raise ValueError("nnz does not fit int32")
+    return Csr(
+        n=n,
+        row_ptr=row_ptr.astype(np.int32),
+        col_idx=cols.astype(np.int32),
+        vals=np.ascontiguousarray(vals, dtype=np.float64),
+    )
+
+
+def _stencil(shape: tuple[int, ...], diag: float, offdiag: dict[tuple[int, ...], float]) -> Csr:
+    """Constant-coefficient stencil on an interior grid of `shape` (x first).
+
+    `offdiag` maps a neighbour offset (dx, dy[, dz]) to its coefficient;
+    neighbours that fall outside the grid are dropped (Dirichlet).
+    """
+    dims = len(shape)
+    n = int(np.prod(shape))
+    coords = np.indices(shape[::-1]).reshape(dims, -1)[::-1]  # coords[0] = x index
+    strides = [1]
+    for s in shape[:-1]:
+        strides.append(strides[-1] * s)
+    idx = np.arange(n, dtype=np.int64)
+    rows = [idx]
+    cols = [idx]
+    vals = [np.full(n, diag)]
+    for off, coef in offdiag.items():
+        ok = np.ones(n, dtype=bool)
+        shift = 0
+        for d in range(dims):
+            c = coords[d] + off[d]
+            ok &= (c >= 0) & (c < shape[d])
+            shift += off[d] * strides[d]
+        rows.append(idx[ok])
+        cols.append(idx[ok] + shift)
+        vals.append(np.full(int(ok.sum()), coef))
+    return _from_coo(n, np.concatenate(rows), np.concatenate(cols), np.concatenate(vals))
+
+
+def poisson2d(n: int, diag_shift: np.ndarray | float | None = None) -> Csr:
+    """5-point Laplacian on an n x n interior grid: 4 on the diagonal, -1 off.
+
+    `diag_shift` (scalar or length n*n) is added to the diagonal.
+    """
+    a = _stencil((n, n), 4.0, {(-1, 0): -1.0, (1, 0): -1.0, (0, -1): -1.0, (0, 1): -1.0})
+    if diag_shift is not None:
+        a = _add_diag(a, diag_shift)
+    return a
+
+
+def poisson3d(n: int) -> Csr:
+    """7-point Laplacian on an n^3 interior grid: 6 on the diagonal, -1 off."""
+    off = {}
+    for d in range(3):
+        for s in (-1, 1):
+            o = [0, 0, 0]
+            o[d] = s
+            off[tuple(o)] = -1.0
+    return _stencil((n, n, n), 6.0, off)
+
+
+def convdiff2d(n: int, peclet: float = 50.0, direction=(1.0, 0.5)) -> Csr:
+    """-Laplace(u) + v.grad(u) on the unit square, first-order upwind, scaled by h^2.
+
+    v = peclet * direction (both components >= 0, so upwind = backward
+    differences); h = 1/(n+1).  Row coefficients: diagonal 4 + h(vx+vy),
+    west -(1 + h vx), south -(1 + h vy), east -1, north -1.  Nonsymmetric.
+    """
+    vx, vy = peclet * direction[0], peclet * direction[1]
+    if vx < 0 or vy < 0:
+        raise ValueError("upwind stencil here assumes nonnegative velocity")
+    h = 1.0 / (n + 1)
+    return _stencil(
+        (n, n),
+        4.0 + h * (vx + vy),
+        {(-1, 0): -(1.0 + h * vx), (1, 0): -1.0, (0, -1): -(1.0 + h * vy), (0, 1): -1.0},
+    )
+
+
+def heat2d(n: int, c: float = 4.0) -> Csr:
+    """Backward-Euler heat operator I + c*L5 on an n x n interior grid (c = dt*kappa/h^2)."""
+    return _stencil((n, n), 1.0 + 4.0 * c, {(-1, 0): -c, (1, 0): -c, (0, -1): -c, (0, 1): -c})
+
+
+def scaled_identity(n: int, lam: float) -> Csr:
+    idx = np.arange(n)
+    return _from_coo(n, idx, idx, np.full(n, float(lam)))
+
+
+def _add_diag(a: Csr, shift) -> Csr:
+    shift = np.broadcast_to(np.asarray(shift, dtype=np.float64), (a.n,))
+    rows = np.repeat(np.arange(a.n), np.diff(a.row_ptr))
+    vals = a.vals.copy()
+    on_diag = rows == a.col_idx
+    vals[on_diag] += shift[rows[on_diag]]
+    return Csr(a.n, a.row_ptr, a.col_idx, vals)
+
+
+def random_csr(n: int, nnz_per_row: int, seed: int = 0, empty_rows: int = 0,
+               long_rows: dict[int, int] | None = None) -> Csr:
+    """Rows with `nnz_per_row` column indices drawn uniformly from [0, n).
+
+    Values are uniform in [-1, 1).  Duplicated column indices inside a row are
+    kept (CSR allows them; a product sums them).  `empty_rows` rows (chosen by
+    the same generator) get no entries; `long_rows` maps row -> its own count.
+    """
+    rng = np.random.default_rng(seed)
+    counts = np.full(n, nnz_per_row, dtype=np.int64)
+    if empty_rows:
+        counts[rng.choice(n, size=empty_rows, replace=False)] = 0
+    for r, c in (long_rows or {}).items():
+        counts[r] = c
+    rows = np.repeat(np.arange(n), counts)
+    cols = rng.integers(0, n, size=rows.size)
+    vals = rng.uniform(-1.0, 1.0, size=rows.size)
+    return _from_coo(n, rows, cols, vals)
+
+
+def random_spd_dense(n: int, cond: float, seed: int = 0) -> np.ndarray:
+    """Dense SPD matrix Q diag(geomspace(1, cond)) Q^T with a seeded orthogonal Q."""
+    rng = np.random.default_rng(seed)
+    q, _ = np.linalg.qr(rng.standard_normal((n, n)))
+    lam = np.geomspace(1.0, cond, n)
+    return (q * lam) @ q.T
+
+
+def dense_to_csr(a: np.ndarray, drop_zeros: bool = True) -> Csr:
+    n = a.shape[0]
+    if drop_zeros:
+        rows, cols = np.nonzero(a)
+    else:
+        rows, cols = np.indices(a.shape).reshape(2, -1)
+    return _from_coo(n, rows, cols, a[rows, cols])
+
+
+def rhs_uniform(n: int, seed: int = 0) -> np.ndarray:
+    """b uniform in [-1, 1) from numpy's default_rng(seed)."""
+    return np.random.default_rng(seed).uniform(-1.0, 1.0, n)
+
+
+# --- Closed-form spectral data of the stencil Laplacians (inputs for pins) ---
+
+def laplacian_eigvec_2d(n: int, j: int, k: int) -> np.ndarray:
+    """Eigenvector sin(j pi a/(n+1)) sin(k pi b/(n+1)) of the 5-point Laplacian, unit 2-norm."""
+    a = np.arange(1, n + 1)
+    v = np.outer(np.sin(k * np.pi * a / (n + 1)), np.sin(j * np.pi * a / (n + 1))).ravel()
+    return v / np.linalg.norm(v)
+
+
+def laplacian_eigval_2d(n: int, j: int, k: int) -> float:
+    t = np.pi / (n + 1)
+    return 4.0 - 2.0 * np.cos(j * t) - 2.0 * np.cos(k * t)
+
+
+def laplacian_eigvec_3d(n: int, j: int, k: int, l: int) -> np.ndarray:
+    a = np.arange(1, n + 1)
+    sx = np.sin(j * np.pi * a / (n + 1))
+    sy = np.sin(k * np.pi * a / (n + 1))
+    sz = np.sin(l * np.pi * a / (n + 1))
+    v = (sz[:, None, None] * sy[None, :, None] * sx[None, None, :]).ravel()
+    return v / np.linalg.norm(v)
+
+
+def laplacian_eigval_3d(n: int, j: int, k: int, l: int) -> float:
+    t = np.pi / (n + 1)
+    return 6.0 - 2.0 * (np.cos(j * t) + np.cos(k * t) + np.cos(l * t))
+
+
+# --- The workloads -----------------------------------------------------------
+
+def workload(name: str):
+    """Return (A, b, x0) for a named workload.
+
+    poisson2d_32     : 2D 5-point Poisson, 32x32 interior grid, N = 1,024
+    poisson3d_128    : 3D 7-point Poisson, 128^3 interior grid, N = 2,097,152
+    convdiff2d_1024  : 2D upwind convection-diffusion, 1024^2, Peclet 50, v=(1,0.5)
+    poisson3d_<n>    : size variants used for sweeps and parity at reduced size
+    poisson2d_<n>, convdiff2d_<n>, heat2d_<n> likewise.
+    b = uniform[-1,1) from default_rng(0); x0 = 0.
+    """
+    kind, _, size = name.rpartition("_")
+    n = int(size)
+    if kind == "poisson2d":
+        a = poisson2d(n)
+    elif kind == "poisson3d":
+        a = poisson3d(n)
+    elif kind == "convdiff2d":
+        a = convdiff2d(n)
+    elif kind == "heat2d":
+        a = heat2d(n)
+    else:
+        raise KeyError(name)
+    b = rhs_uniform(a.n, 0)
+    return a, b, np.zeros(a.n)
+
+
+def batch_systems(count: int = 512, seed: int = 0, nmin: int = 16, nmax: int = 512):
+    """Uneven batch: 2D Poisson on n_s x n_s grids plus a random diagonal shift.
+
+    n_s = rng.integers(nmin, nmax+1, count); then, for each system in order,
+    shift = rng.uniform(0, 0.1, n_s^2) and b = rng.uniform(-1, 1, n_s^2).
+    Yields (n_s, shift, b) without assembling the matrices.
+    """
+    rng = np.random.default_rng(seed)
+    sizes = rng.integers(nmin, nmax + 1, count)
+    for ns in sizes:
+        shift = rng.uniform(0.0, 0.1, int(ns) * int(ns))
+        b = rng.uniform(-1.0, 1.0, int(ns) * int(ns))
+        yield int(ns), shift, b
