@@ -1,0 +1,182 @@
+/*
+ * fk.h -- C ABI of the MI355X (gfx950) pipelined Krylov solver library libfk.so.
+ *
+ * The library solves sparse linear systems A x = b held in CSR form, in FP64,
+ * with the pipelined conjugate gradient method (Algorithm 2 with the beta
+ * recurrence of Eq. (3), Section 3.1) and the pipelined BiCGStab method
+ * (Algorithm 4, Section 3.2) of Rupp, Weinbub, Juengel and Grasser,
+ * "Pipelined Iterative Solvers with Kernel Fusion for GPUs" (arXiv:1410.4054).
+ * The classical formulations (Algorithms 1 and 3) are provided as unfused
+ * baselines built from one kernel per vector operation.
+ *
+ * Every step of an iteration runs in hand-written HIP kernels: the CSR
+ * product fused with the first stage of the inner products that follow it
+ * (Section 2.2), the vector updates fused with the next first-stage
+ * reductions, and a second reduction stage done on the device by the last
+ * workgroup to finish, which also evaluates alpha, beta, omega and the
+ * convergence test, so no scalar crosses to the host inside an iteration.
+ *
+ * Conventions for every entry point:
+ *   - Return value: an fk_status.  No exception crosses the ABI and nothing
+ *     aborts.  On failure fk_last_error() gives a message (per thread).
+ *   - Device pointers are HIP device memory of the current device (e.g. the
+ *     data pointer of a torch.cuda tensor).  The library never frees
+ *     caller memory.
+ *   - `hip_stream` is a hipStream_t passed as void* (NULL = default stream).
+ *   - Vectors are contiguous float64 arrays of length n.
+ *   - CSR: int32 row_ptr[n+1] with row_ptr[0] = 0, nondecreasing,
+ *     row_ptr[n] = nnz; int32 col_idx[nnz] in [0, n); float64 vals[nnz].
+ *     Duplicate column indices in a row are allowed (they are summed).
+ *   - Numbers: IEEE FP64 with round to nearest.  A CSR row is summed left to
+ *     right in storage order (rows longer than FK_LONG_ROW are summed by a
+ *     fixed tree instead).  Inner products accumulate error-free products
+ *     in double-double and are rounded once, so they are independent of the
+ *     launch shape and reproducible bit for bit from run to run.
+ */
+#ifndef FK_H
+#define FK_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct fk_csr_s *fk_csr;
+typedef struct fk_solver_s *fk_solver;
+
+typedef enum {
+    FK_OK = 0,              /* success; for fk_solve: converged             */
+    FK_E_ARG = 1,           /* invalid argument (NULL, size, option)        */
+    FK_E_CSR = 2,           /* malformed CSR arrays                         */
+    FK_E_HIP = 3,           /* a HIP runtime call failed                    */
+    FK_E_OOM = 4,           /* device or host allocation failed             */
+    FK_NOT_CONVERGED = 5,   /* max_iter reached; x holds x_{max_iter}       */
+    FK_BREAKDOWN = 6,       /* zero/non-finite denominator or residual      */
+    FK_E_STATE = 7          /* call out of order (e.g. no solve yet)        */
+} fk_status;
+
+typedef enum {
+    FK_CG_PIPELINED = 0,        /* Algorithm 2 + Eq. (3): 2 kernels/iteration   */
+    FK_CG_CLASSICAL = 1,        /* Algorithm 1 as SpMV, dot, axpy, axpy, dot, xpay */
+    FK_BICGSTAB_PIPELINED = 2,  /* Algorithm 4: 4 kernels/iteration             */
+    FK_BICGSTAB_CLASSICAL = 3   /* Algorithm 3, one kernel per operation         */
+} fk_method;
+
+/* Rows with more nonzeros than this are summed by a fixed tree, not left to right. */
+#define FK_LONG_ROW 2048
+
+/* Solver options.  Zero-initialised fields take the defaults noted. */
+typedef struct {
+    int32_t method;          /* fk_method                                       */
+    double rtol;             /* stop when ||r_k||_2 <= rtol * ||b||_2 (>= 0)   */
+    int32_t max_iter;        /* >= 0; iterations allowed (0 = setup only)      */
+    int32_t record_history;  /* nonzero: keep ||r_i||/||b|| for i = 0..k        */
+    int32_t unroll;          /* iterations enqueued between status polls (0 = 32) */
+    int32_t flags;           /* FK_FLAG_* bits                                  */
+} fk_opts;
+
+/* flags */
+#define FK_FLAG_GRAPH 1      /* replay the enqueued iterations from a hipGraph */
+#define FK_FLAG_PROFILE 2    /* time every kernel with HIP events (slower)     */
+
+enum { FK_PTR_HOST = 0, FK_PTR_DEVICE = 1 };
+
+/*
+ * Create a device-resident CSR matrix (the CSR storage of Section 2.2).
+ * The arrays are validated on the host (FK_E_CSR on any violation of the
+ * conventions above, before any device work), then copied into library-owned
+ * device memory; the caller keeps ownership of its arrays and may free them
+ * as soon as this returns.  ptr_kind says where the three arrays live
+ * (FK_PTR_HOST or FK_PTR_DEVICE; device arrays are copied back to the host
+ * once for validation and row-block planning).  Requires 1 <= n,
+ * 0 <= nnz <= INT32_MAX.  *out receives the handle.
+ */
+fk_status fk_csr_create(int64_t n, int64_t nnz, const int32_t *row_ptr, const int32_t *col_idx,
+                        const double *vals, int32_t ptr_kind, void *hip_stream, fk_csr *out);
+
+/* Release a matrix.  Solvers created on it must be destroyed first. */
+fk_status fk_csr_destroy(fk_csr A);
+
+/* n and nnz of a matrix. */
+fk_status fk_csr_shape(fk_csr A, int64_t *n, int64_t *nnz);
+
+/* Row-block plan made at creation: number of row blocks (runs of at most 256
+ * consecutive rows holding at most FK_LONG_ROW nonzeros, the unit of work of
+ * the product kernels) and number of rows longer than FK_LONG_ROW. */
+fk_status fk_csr_blocks(fk_csr A, int32_t *nblocks, int32_t *long_rows);
+
+/*
+ * Create a solver for A with options *o, bound to hip_stream.  Allocates the
+ * library-owned workspace (the method's work vectors, the per-workgroup
+ * partial-sum buffer and the device scalars; about 3n doubles for CG and 6n
+ * for BiCGStab) once, so fk_solve allocates nothing.
+ */
+fk_status fk_solver_create(fk_csr A, const fk_opts *o, void *hip_stream, fk_solver *out);
+
+/*
+ * Solve A x = b.  b_dev, x_dev: caller-owned device float64[n]; x holds x0 on
+ * entry and x_k on return.  Work is enqueued on the solver's stream and the
+ * call returns once it has completed.  Returns FK_OK (converged),
+ * FK_NOT_CONVERGED (x = x_{max_iter}), FK_BREAKDOWN (x = last finite iterate
+ * before the failing step) or an error.  b = 0 gives x = 0, k = 0, FK_OK.
+ */
+fk_status fk_solve(fk_solver S, const double *b_dev, double *x_dev);
+
+/* Iterations k of the last solve: number of solution updates performed. */
+fk_status fk_get_iterations(fk_solver S, int32_t *k);
+
+/* ||r_k||_2 / ||b||_2 of the last solve, from the recursively updated residual
+ * (pipelined BiCGStab: from the expansion of <r_{k}, r_{k}> in Section 3.2). */
+fk_status fk_get_residual(fk_solver S, double *rel_res);
+
+/* Residual history of the last solve: out[i] = ||r_i||/||b||, i = 0..k.
+ * Writes min(cap, k+1) values and sets *len = k+1.  Needs record_history. */
+fk_status fk_get_residual_history(fk_solver S, double *out, int32_t cap, int32_t *len);
+
+/* Per-iteration scalars of the last solve (for diagnostics): for iteration
+ * i < min(cap, k), out[4*i + 0..3] = alpha_i, beta_i, omega_i (0 for CG),
+ * and the A-expanded (BiCGStab) or plain <r,r> used for the test.
+ * Needs record_history. */
+fk_status fk_get_scalars(fk_solver S, double *out, int32_t cap, int32_t *len);
+
+/* Average device time per launch of each kernel kind during the last solve
+ * made with FK_FLAG_PROFILE.  Kinds are the FK_KERNEL_* values below;
+ * avg_us[kind] and count[kind] are written for kind < cap. */
+enum {
+    FK_KERNEL_SETUP = 0,       /* r0 = b - A x0 and its reductions            */
+    FK_KERNEL_SPMV_DOT = 1,    /* fused CSR product + first-stage dots        */
+    FK_KERNEL_UPDATE_DOT = 2,  /* fused vector updates + first-stage dot(s)   */
+    FK_KERNEL_SPMV = 3,        /* plain CSR product (classical)               */
+    FK_KERNEL_DOT = 4,         /* plain dot (classical)                        */
+    FK_KERNEL_AXPY = 5,        /* plain vector update (classical)             */
+    FK_KERNEL_KINDS = 6
+};
+fk_status fk_get_kernel_times(fk_solver S, double *avg_us, int32_t *count, int32_t cap);
+
+fk_status fk_solver_destroy(fk_solver S);
+
+/*
+ * q = A p with optional fused first-stage reductions (the fused kernel of
+ * Section 2.2): if dots_host is not NULL it receives {<p,q>, <q,q>}.
+ * Calls on the same matrix share its reduction scratch: do not overlap them.
+ * p_dev, q_dev: device float64[n], must not alias.  Synchronous.
+ */
+fk_status fk_spmv(fk_csr A, const double *p_dev, double *q_dev, double *dots_host, void *hip_stream);
+
+/* <a, b> over n >= 0 device doubles, written to *out_host.  Synchronous. */
+fk_status fk_dot(int64_t n, const double *a_dev, const double *b_dev, double *out_host, void *hip_stream);
+
+/* Plain device copy of n_bytes (a streaming kernel, for bandwidth calibration). */
+fk_status fk_copy(void *dst_dev, const void *src_dev, int64_t n_bytes, void *hip_stream);
+
+const char *fk_status_str(fk_status s);
+const char *fk_last_error(void);
+
+/* Library build identifier (e.g. "fk 0.1 gfx950"). */
+const char *fk_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FK_H */

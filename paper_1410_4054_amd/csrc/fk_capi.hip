@@ -1,0 +1,916 @@
+// C ABI of libfk.so (declared in include/fk.h): CSR validation and row-block
+// planning on the host, device workspace, and the host drivers that enqueue
+// the per-iteration kernel sequences of Algorithms 1-4 (Sections 3.1, 3.2).
+//
+// The drivers never wait for a scalar inside an iteration: every scalar
+// (alpha, beta, omega, the convergence test) is evaluated on the device by
+// the last workgroup of each reduction point.  The host enqueues `unroll`
+// iterations at a time, keeps one batch in flight ahead of the one it is
+// waiting for, and reads back a single status word per batch; kernels
+// enqueued after convergence return at once.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstddef>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <mutex>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "fk.h"
+#include "fk_internal.hpp"
+
+using namespace fk;
+
+// ------------------------------------------------------------------ errors
+
+static thread_local std::string g_err;
+
+static fk_status fail(fk_status s, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return s;
+}
+
+#define HIP_TRY(expr)                                                                      \
+    do {                                                                                   \
+        hipError_t e_ = (expr);                                                            \
+        if (e_ != hipSuccess)                                                              \
+            return fail(FK_E_HIP, "%s failed: %s", #expr, hipGetErrorString(e_));         \
+    } while (0)
+
+static fk_status oom_or_hip(hipError_t e, const char *what)
+{
+    if (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation)
+        return fail(FK_E_OOM, "%s: out of device memory", what);
+    return fail(FK_E_HIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+template <typename T>
+static fk_status dev_alloc(T **p, size_t count, const char *what)
+{
+    *p = nullptr;
+    if (count == 0)
+        count = 1;
+    hipError_t e = hipMalloc(reinterpret_cast<void **>(p), count * sizeof(T));
+    if (e != hipSuccess) {
+        *p = nullptr;
+        return oom_or_hip(e, what);
+    }
+    return FK_OK;
+}
+
+template <typename T>
+static void dev_free(T *&p)
+{
+    if (p)
+        (void)hipFree(p);
+    p = nullptr;
+}
+
+// ------------------------------------------------------------- launch shape
+
+static int env_int(const char *name, int dflt, int lo, int hi)
+{
+    const char *s = getenv(name);
+    if (!s || !*s)
+        return dflt;
+    long v = strtol(s, nullptr, 10);
+    return (int)std::min<long>(hi, std::max<long>(lo, v));
+}
+
+// Workgroups of a product launch: at most FK_SPMV_GRID (default 2048, i.e.
+// eight 256-thread workgroups per CU of the 256-CU part), a multiple of 8 so
+// that every XCD owns the same number of them.
+static int spmv_grid(int nblocks)
+{
+    static const int gmax = env_int("FK_SPMV_GRID", 2048, 8, GMAX);
+    int g = std::min(nblocks, gmax);
+    if (g >= 8)
+        g &= ~7;
+    return std::max(g, 1);
+}
+
+static int vec_grid(int64_t n)
+{
+    static const int gmax = env_int("FK_VEC_GRID", 2048, 1, GMAX);
+    int64_t g = (n + WG - 1) / WG;
+    g = std::min<int64_t>(g, gmax);
+    return (int)std::max<int64_t>(g, 1);
+}
+
+// ------------------------------------------------------------------ matrix
+
+struct fk_csr_s {
+    int64_t n = 0, nnz = 0;
+    int32_t *row_ptr = nullptr, *col_idx = nullptr, *blocks = nullptr, *block_j0 = nullptr;
+    double *vals = nullptr;
+    int32_t nblocks = 0;
+    int32_t long_rows = 0;
+    int device = 0;
+    // scratch reduction state for fk_spmv
+    DevState *st = nullptr;
+    double *partials = nullptr;
+    int solvers = 0;
+
+    DevCsr view() const
+    {
+        return DevCsr{(int32_t)n, (int32_t)nnz, nblocks, row_ptr, col_idx, vals, blocks, block_j0};
+    }
+};
+
+static fk_status validate_csr(int64_t n, int64_t nnz, const int32_t *rp, const int32_t *ci)
+{
+    if (rp[0] != 0)
+        return fail(FK_E_CSR, "row_ptr[0] = %d, expected 0", rp[0]);
+    for (int64_t i = 0; i < n; ++i)
+        if (rp[i + 1] < rp[i])
+            return fail(FK_E_CSR, "row_ptr decreases at row %lld", (long long)i);
+    if ((int64_t)rp[n] != nnz)
+        return fail(FK_E_CSR, "row_ptr[n] = %d, expected nnz = %lld", rp[n], (long long)nnz);
+    for (int64_t j = 0; j < nnz; ++j)
+        if (ci[j] < 0 || (int64_t)ci[j] >= n)
+            return fail(FK_E_CSR, "col_idx[%lld] = %d outside [0, %lld)", (long long)j, ci[j],
+                        (long long)n);
+    return FK_OK;
+}
+
+// Row blocks: consecutive rows, at most WG rows and NNZ_MAX nonzeros per
+// block; a row with more than NNZ_MAX nonzeros forms a block of its own.
+static std::vector<int32_t> plan_blocks(const int32_t *rp, int64_t n, int32_t *long_rows)
+{
+    std::vector<int32_t> b;
+    b.reserve((size_t)(n / WG + 2));
+    b.push_back(0);
+    *long_rows = 0;
+    int64_t r = 0;
+    while (r < n) {
+        const int64_t start = r;
+        if ((int64_t)rp[r + 1] - rp[r] > NNZ_MAX) {
+            ++*long_rows;
+            b.push_back((int32_t)(r + 1));
+            ++r;
+            continue;
+        }
+        int64_t nz = 0;
+        while (r < n && r - start < WG) {
+            const int64_t len = (int64_t)rp[r + 1] - rp[r];
+            if (len > NNZ_MAX || nz + len > NNZ_MAX)
+                break;
+            nz += len;
+            ++r;
+        }
+        b.push_back((int32_t)r);
+    }
+    return b;
+}
+
+static void csr_release(fk_csr A)
+{
+    dev_free(A->row_ptr);
+    dev_free(A->col_idx);
+    dev_free(A->vals);
+    dev_free(A->blocks);
+    dev_free(A->block_j0);
+    dev_free(A->st);
+    dev_free(A->partials);
+}
+
+extern "C" fk_status fk_csr_create(int64_t n, int64_t nnz, const int32_t *row_ptr,
+                                   const int32_t *col_idx, const double *vals, int32_t ptr_kind,
+                                   void *hip_stream, fk_csr *out)
+{
+    if (!out)
+        return fail(FK_E_ARG, "out is NULL");
+    *out = nullptr;
+    if (n < 1 || n >= INT32_MAX)
+        return fail(FK_E_ARG, "n = %lld outside [1, 2^31-1)", (long long)n);
+    if (nnz < 0 || nnz > INT32_MAX)
+        return fail(FK_E_ARG, "nnz = %lld outside [0, 2^31-1]", (long long)nnz);
+    if (!row_ptr || (nnz > 0 && (!col_idx || !vals)))
+        return fail(FK_E_ARG, "NULL CSR array");
+    if (ptr_kind != FK_PTR_HOST && ptr_kind != FK_PTR_DEVICE)
+        return fail(FK_E_ARG, "ptr_kind = %d", ptr_kind);
+    hipStream_t s = (hipStream_t)hip_stream;
+
+    // Host copies of the index arrays for validation and planning.
+    std::vector<int32_t> h_rp, h_ci;
+    const int32_t *rp = row_ptr, *ci = col_idx;
+    try {
+        if (ptr_kind == FK_PTR_DEVICE) {
+            h_rp.resize((size_t)n + 1);
+            h_ci.resize((size_t)std::max<int64_t>(nnz, 1));
+            HIP_TRY(hipMemcpyAsync(h_rp.data(), row_ptr, (size_t)(n + 1) * 4, hipMemcpyDeviceToHost, s));
+            if (nnz > 0)
+                HIP_TRY(hipMemcpyAsync(h_ci.data(), col_idx, (size_t)nnz * 4, hipMemcpyDeviceToHost, s));
+            HIP_TRY(hipStreamSynchronize(s));
+            rp = h_rp.data();
+            ci = h_ci.data();
+        }
+    } catch (const std::bad_alloc &) {
+        return fail(FK_E_OOM, "host allocation failed");
+    }
+    fk_status st = validate_csr(n, nnz, rp, ci);
+    if (st != FK_OK)
+        return st;
+
+    fk_csr A = new (std::nothrow) fk_csr_s;
+    if (!A)
+        return fail(FK_E_OOM, "host allocation failed");
+    A->n = n;
+    A->nnz = nnz;
+    (void)hipGetDevice(&A->device);
+    std::vector<int32_t> blocks, block_j0;
+    try {
+        blocks = plan_blocks(rp, n, &A->long_rows);
+        block_j0.resize(blocks.size());
+        for (size_t b = 0; b < blocks.size(); ++b)
+            block_j0[b] = rp[blocks[b]];
+    } catch (const std::bad_alloc &) {
+        delete A;
+        return fail(FK_E_OOM, "host allocation failed");
+    }
+    A->nblocks = (int32_t)blocks.size() - 1;
+    const hipMemcpyKind kind = ptr_kind == FK_PTR_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+#define CSR_TRY(expr)                                                                      \
+    do {                                                                                   \
+        fk_status s_ = (expr);                                                             \
+        if (s_ != FK_OK) {                                                                 \
+            csr_release(A);                                                                \
+            delete A;                                                                      \
+            return s_;                                                                     \
+        }                                                                                  \
+    } while (0)
+#define CSR_HIP(expr)                                                                      \
+    do {                                                                                   \
+        hipError_t e_ = (expr);                                                            \
+        if (e_ != hipSuccess) {                                                            \
+            csr_release(A);                                                                \
+            delete A;                                                                      \
+            return fail(FK_E_HIP, "%s failed: %s", #expr, hipGetErrorString(e_));         \
+        }                                                                                  \
+    } while (0)
+    CSR_TRY(dev_alloc(&A->row_ptr, (size_t)n + 1, "row_ptr"));
+    CSR_TRY(dev_alloc(&A->col_idx, (size_t)nnz, "col_idx"));
+    CSR_TRY(dev_alloc(&A->vals, (size_t)nnz, "vals"));
+    CSR_TRY(dev_alloc(&A->blocks, blocks.size(), "row blocks"));
+    CSR_TRY(dev_alloc(&A->block_j0, blocks.size(), "row blocks"));
+    CSR_TRY(dev_alloc(&A->st, 1, "state"));
+    CSR_TRY(dev_alloc(&A->partials, RED_SCRATCH_DOUBLES, "partials"));
+    CSR_HIP(hipMemcpyAsync(A->row_ptr, row_ptr, (size_t)(n + 1) * 4, kind, s));
+    if (nnz > 0) {
+        CSR_HIP(hipMemcpyAsync(A->col_idx, col_idx, (size_t)nnz * 4, kind, s));
+        CSR_HIP(hipMemcpyAsync(A->vals, vals, (size_t)nnz * 8, kind, s));
+    }
+    CSR_HIP(hipMemcpyAsync(A->blocks, blocks.data(), blocks.size() * 4, hipMemcpyHostToDevice, s));
+    CSR_HIP(hipMemcpyAsync(A->block_j0, block_j0.data(), block_j0.size() * 4, hipMemcpyHostToDevice, s));
+    CSR_HIP(hipMemsetAsync(A->st, 0, sizeof(DevState), s));
+    CSR_HIP(hipMemsetAsync(A->partials, 0, RED_SCRATCH_DOUBLES * sizeof(double), s));
+    CSR_HIP(hipStreamSynchronize(s));
+#undef CSR_TRY
+#undef CSR_HIP
+    *out = A;
+    return FK_OK;
+}
+
+extern "C" fk_status fk_csr_destroy(fk_csr A)
+{
+    if (!A)
+        return fail(FK_E_ARG, "NULL matrix");
+    if (A->solvers > 0)
+        return fail(FK_E_STATE, "%d solver(s) still use this matrix", A->solvers);
+    csr_release(A);
+    delete A;
+    return FK_OK;
+}
+
+extern "C" fk_status fk_csr_shape(fk_csr A, int64_t *n, int64_t *nnz)
+{
+    if (!A || !n || !nnz)
+        return fail(FK_E_ARG, "NULL argument");
+    *n = A->n;
+    *nnz = A->nnz;
+    return FK_OK;
+}
+
+extern "C" fk_status fk_csr_blocks(fk_csr A, int32_t *nblocks, int32_t *long_rows)
+{
+    if (!A || !nblocks || !long_rows)
+        return fail(FK_E_ARG, "NULL argument");
+    *nblocks = A->nblocks;
+    *long_rows = A->long_rows;
+    return FK_OK;
+}
+
+// ------------------------------------------------------------------ solver
+
+struct TimedLaunch {
+    int kind;
+    int slot;  // index of the start event; end event is slot + 1
+};
+
+struct fk_solver_s {
+    fk_csr A = nullptr;
+    fk_opts o{};
+    hipStream_t stream = nullptr;
+    int64_t n = 0;
+    double *r = nullptr, *p = nullptr, *ap = nullptr, *s = nullptr, *as = nullptr, *rs = nullptr;
+    double *partials = nullptr, *hist = nullptr, *scal = nullptr;
+    DevState *st = nullptr;
+    int32_t hist_cap = 0;
+    DevState *h_init = nullptr;     // pinned
+    int32_t *h_status = nullptr;    // pinned, two poll slots
+    hipEvent_t poll_ev[2] = {nullptr, nullptr};
+    DevState last{};
+    bool solved = false;
+    fk_status last_status = FK_E_STATE;
+    int grid_spmv = 1, grid_vec = 1;
+    // profiling
+    std::vector<hipEvent_t> prof_ev[2];  // one event pool per batch slot
+    std::vector<TimedLaunch> prof_batch[2];
+    int prof_next[2] = {0, 0};
+    double prof_us[FK_KERNEL_KINDS] = {};
+    int32_t prof_n[FK_KERNEL_KINDS] = {};
+    // graph replay of one batch of `unroll` iterations
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t graph_exec = nullptr;
+    double *graph_x = nullptr;
+    int graph_iters = 0;
+
+    RedArgs red(int fin, uint32_t mask) const { return RedArgs{st, partials, hist, scal, fin, mask}; }
+};
+
+static void solver_release(fk_solver S)
+{
+    dev_free(S->r);
+    dev_free(S->p);
+    dev_free(S->ap);
+    dev_free(S->s);
+    dev_free(S->as);
+    dev_free(S->rs);
+    dev_free(S->partials);
+    dev_free(S->hist);
+    dev_free(S->scal);
+    dev_free(S->st);
+    if (S->h_init)
+        (void)hipHostFree(S->h_init);
+    if (S->h_status)
+        (void)hipHostFree(S->h_status);
+    S->h_init = nullptr;
+    S->h_status = nullptr;
+    for (auto &e : S->poll_ev)
+        if (e)
+            (void)hipEventDestroy(e);
+    for (auto &pool : S->prof_ev) {
+        for (auto e : pool)
+            (void)hipEventDestroy(e);
+        pool.clear();
+    }
+    if (S->graph_exec)
+        (void)hipGraphExecDestroy(S->graph_exec);
+    if (S->graph)
+        (void)hipGraphDestroy(S->graph);
+    S->graph_exec = nullptr;
+    S->graph = nullptr;
+}
+
+static bool is_bicg(int m) { return m == FK_BICGSTAB_PIPELINED || m == FK_BICGSTAB_CLASSICAL; }
+
+extern "C" fk_status fk_solver_create(fk_csr A, const fk_opts *o, void *hip_stream, fk_solver *out)
+{
+    if (!out)
+        return fail(FK_E_ARG, "out is NULL");
+    *out = nullptr;
+    if (!A || !o)
+        return fail(FK_E_ARG, "NULL argument");
+    if (o->method < FK_CG_PIPELINED || o->method > FK_BICGSTAB_CLASSICAL)
+        return fail(FK_E_ARG, "unknown method %d", o->method);
+    if (!(o->rtol >= 0.0) || !std::isfinite(o->rtol))
+        return fail(FK_E_ARG, "rtol must be finite and >= 0");
+    if (o->max_iter < 0)
+        return fail(FK_E_ARG, "max_iter < 0");
+    if (o->unroll < 0 || o->unroll > 4096)
+        return fail(FK_E_ARG, "unroll outside [0, 4096]");
+    if (o->flags & ~(FK_FLAG_GRAPH | FK_FLAG_PROFILE))
+        return fail(FK_E_ARG, "unknown flags 0x%x", o->flags);
+
+    fk_solver S = new (std::nothrow) fk_solver_s;
+    if (!S)
+        return fail(FK_E_OOM, "host allocation failed");
+    S->A = A;
+    S->o = *o;
+    if (S->o.unroll == 0)
+        S->o.unroll = 32;
+    S->stream = (hipStream_t)hip_stream;
+    S->n = A->n;
+    S->grid_spmv = spmv_grid(A->nblocks);
+    S->grid_vec = vec_grid(A->n);
+    const size_t n = (size_t)A->n;
+#define S_TRY(expr)                                                                        \
+    do {                                                                                   \
+        fk_status s_ = (expr);                                                             \
+        if (s_ != FK_OK) {                                                                 \
+            solver_release(S);                                                             \
+            delete S;                                                                      \
+            return s_;                                                                     \
+        }                                                                                  \
+    } while (0)
+#define S_HIP(expr)                                                                        \
+    do {                                                                                   \
+        hipError_t e_ = (expr);                                                            \
+        if (e_ != hipSuccess) {                                                            \
+            solver_release(S);                                                             \
+            delete S;                                                                      \
+            return fail(FK_E_HIP, "%s failed: %s", #expr, hipGetErrorString(e_));         \
+        }                                                                                  \
+    } while (0)
+    S_TRY(dev_alloc(&S->r, n, "r"));
+    S_TRY(dev_alloc(&S->p, n, "p"));
+    S_TRY(dev_alloc(&S->ap, n, "Ap"));
+    if (is_bicg(o->method)) {
+        S_TRY(dev_alloc(&S->s, n, "s"));
+        S_TRY(dev_alloc(&S->as, n, "As"));
+        S_TRY(dev_alloc(&S->rs, n, "r0*"));
+    }
+    S_TRY(dev_alloc(&S->partials, RED_SCRATCH_DOUBLES, "partials"));
+    S_TRY(dev_alloc(&S->st, 1, "state"));
+    if (o->record_history) {
+        S->hist_cap = (int32_t)std::min<int64_t>((int64_t)o->max_iter + 1, INT32_MAX);
+        S_TRY(dev_alloc(&S->hist, (size_t)S->hist_cap, "history"));
+        S_TRY(dev_alloc(&S->scal, (size_t)S->hist_cap * 4, "scalars"));
+    }
+    S_HIP(hipHostMalloc(reinterpret_cast<void **>(&S->h_init), sizeof(DevState), hipHostMallocDefault));
+    S_HIP(hipHostMalloc(reinterpret_cast<void **>(&S->h_status), 2 * sizeof(int32_t), hipHostMallocDefault));
+    for (auto &e : S->poll_ev)
+        S_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    S_HIP(hipMemsetAsync(S->st, 0, sizeof(DevState), S->stream));
+    S_HIP(hipMemsetAsync(S->partials, 0, RED_SCRATCH_DOUBLES * sizeof(double), S->stream));
+    S_HIP(hipStreamSynchronize(S->stream));
+#undef S_TRY
+#undef S_HIP
+    A->solvers++;
+    *out = S;
+    return FK_OK;
+}
+
+extern "C" fk_status fk_solver_destroy(fk_solver S)
+{
+    if (!S)
+        return fail(FK_E_ARG, "NULL solver");
+    (void)hipStreamSynchronize(S->stream);
+    solver_release(S);
+    if (S->A)
+        S->A->solvers--;
+    delete S;
+    return FK_OK;
+}
+
+// ------------------------------------------------------------------ driver
+
+namespace {
+
+struct Enq {
+    fk_solver S;
+    bool profile;
+    int batch;
+
+    template <typename F>
+    hipError_t run(int kind, F &&launch)
+    {
+        if (!profile)
+            return launch();
+        std::vector<hipEvent_t> &pool = S->prof_ev[batch];
+        const int slot = S->prof_next[batch];
+        while ((size_t)slot + 2 > pool.size()) {
+            hipEvent_t e;
+            hipError_t er = hipEventCreate(&e);
+            if (er != hipSuccess)
+                return er;
+            pool.push_back(e);
+        }
+        hipError_t e = hipEventRecord(pool[slot], S->stream);
+        if (e != hipSuccess)
+            return e;
+        e = launch();
+        if (e != hipSuccess)
+            return e;
+        e = hipEventRecord(pool[slot + 1], S->stream);
+        if (e != hipSuccess)
+            return e;
+        S->prof_batch[batch].push_back(TimedLaunch{kind, slot});
+        S->prof_next[batch] = slot + 2;
+        return hipSuccess;
+    }
+};
+
+#define ENQ(kind, call)                                                                    \
+    do {                                                                                   \
+        hipError_t e_ = q.run(kind, [&]() { return (call); });                              \
+        if (e_ != hipSuccess)                                                              \
+            return e_;                                                                     \
+    } while (0)
+
+hipError_t enqueue_setup(fk_solver S, Enq &q, const double *b, double *x)
+{
+    const DevCsr A = S->A->view();
+    const int64_t n = S->n;
+    const int gs = S->grid_spmv, gv = S->grid_vec;
+    hipStream_t st = S->stream;
+    double *rs = is_bicg(S->o.method) ? S->rs : nullptr;
+    ENQ(FK_KERNEL_SETUP, launch_residual0(A, b, x, S->r, S->p, rs, S->red(FIN_SETUP, RUN_ACTIVE), gs, st));
+    // b = 0: x = 0 (runs only in that state; not timed).
+    hipError_t ez = launch_zero(x, n, S->st, 1u << ST_ZERO_RHS, gv, st);
+    if (ez != hipSuccess)
+        return ez;
+    if (S->o.method == FK_CG_PIPELINED)
+        ENQ(FK_KERNEL_SPMV_DOT, launch_spmv_dots(A, S->p, S->ap, nullptr, D_YV | D_YY,
+                                                 S->red(FIN_CG_ALPHA, RUN_ACTIVE), gs, st));
+    return hipSuccess;
+}
+
+// `last`: this is iteration max_iter, after which nothing can run; launches
+// that would only return at once are left out.
+hipError_t enqueue_iteration(fk_solver S, Enq &q, double *x, bool last)
+{
+    const DevCsr A = S->A->view();
+    const int64_t n = S->n;
+    const int gs = S->grid_spmv, gv = S->grid_vec;
+    hipStream_t st = S->stream;
+    DevState *ds = S->st;
+    switch (S->o.method) {
+    case FK_CG_PIPELINED:
+        // Fused x, r, p update + <r_i, r_i>; then Ap_i + <p_i,Ap_i>, <Ap_i,Ap_i>.
+        ENQ(FK_KERNEL_UPDATE_DOT, launch_cg_update(n, x, S->r, S->p, S->ap, S->red(FIN_CG_RR, RUN_ACTIVE), gv, st));
+        if (!last)
+            ENQ(FK_KERNEL_SPMV_DOT, launch_spmv_dots(A, S->p, S->ap, nullptr, D_YV | D_YY,
+                                                     S->red(FIN_CG_ALPHA, RUN_ACTIVE), gs, st));
+        break;
+    case FK_CG_CLASSICAL:
+        ENQ(FK_KERNEL_SPMV, launch_spmv_dots(A, S->p, S->ap, nullptr, 0, S->red(FIN_NONE, RUN_ACTIVE), gs, st));
+        ENQ(FK_KERNEL_DOT, launch_dot(n, S->p, S->ap, nullptr, 1, S->red(FIN_C_CG_ALPHA, RUN_ACTIVE), gv, st));
+        ENQ(FK_KERNEL_AXPY, launch_axpy(n, x, x, S->p, 0, 0, ds, RUN_ACTIVE, gv, st));
+        ENQ(FK_KERNEL_AXPY, launch_axpy(n, S->r, S->r, S->ap, 0, 1, ds, RUN_ACTIVE, gv, st));
+        ENQ(FK_KERNEL_DOT, launch_dot(n, S->r, S->r, nullptr, 1, S->red(FIN_C_CG_BETA, RUN_ACTIVE), gv, st));
+        if (!last)
+            ENQ(FK_KERNEL_AXPY, launch_xpay(n, S->p, S->r, nullptr, ds, RUN_ACTIVE, gv, st));
+        break;
+    case FK_BICGSTAB_PIPELINED:
+        ENQ(FK_KERNEL_SPMV_DOT, launch_spmv_dots(A, S->p, S->ap, S->rs, D_YW,
+                                                 S->red(FIN_B_ALPHA, RUN_ACTIVE), gs, st));
+        ENQ(FK_KERNEL_UPDATE_DOT, launch_bicg_s(n, S->r, S->ap, S->s, S->red(FIN_B_SS, RUN_ACTIVE), gv, st));
+        ENQ(FK_KERNEL_SPMV_DOT, launch_spmv_dots(A, S->s, S->as, S->rs, D_YV | D_YY | D_YW,
+                                                 S->red(FIN_B_OMEGA, RUN_ACTIVE), gs, st));
+        ENQ(FK_KERNEL_UPDATE_DOT, launch_bicg_xrp(n, x, S->r, S->p, S->s, S->as, S->ap, S->rs,
+                                                  S->red(FIN_B_XRP, RUN_ACTIVE_OR_HALF), gv, st));
+        break;
+    case FK_BICGSTAB_CLASSICAL:
+        ENQ(FK_KERNEL_SPMV, launch_spmv_dots(A, S->p, S->ap, nullptr, 0, S->red(FIN_NONE, RUN_ACTIVE), gs, st));
+        ENQ(FK_KERNEL_DOT, launch_dot(n, S->ap, S->rs, nullptr, 1, S->red(FIN_B_ALPHA, RUN_ACTIVE), gv, st));
+        ENQ(FK_KERNEL_AXPY, launch_axpy(n, S->s, S->r, S->ap, 0, 1, ds, RUN_ACTIVE, gv, st));
+        ENQ(FK_KERNEL_DOT, launch_dot(n, S->s, S->s, nullptr, 1, S->red(FIN_B_SS, RUN_ACTIVE), gv, st));
+        ENQ(FK_KERNEL_SPMV, launch_spmv_dots(A, S->s, S->as, nullptr, 0, S->red(FIN_NONE, RUN_ACTIVE), gs, st));
+        ENQ(FK_KERNEL_DOT, launch_dot(n, S->as, S->s, S->as, 2, S->red(FIN_C_B_OMEGA, RUN_ACTIVE), gv, st));
+        ENQ(FK_KERNEL_AXPY, launch_axpy(n, x, x, S->p, 0, 0, ds, RUN_ACTIVE_OR_HALF, gv, st));
+        ENQ(FK_KERNEL_AXPY, launch_copy_fin(n, S->r, S->s, S->red(FIN_HALF_DONE, RUN_HALF), st));
+        ENQ(FK_KERNEL_AXPY, launch_axpy(n, x, x, S->s, 1, 0, ds, RUN_ACTIVE, gv, st));
+        ENQ(FK_KERNEL_AXPY, launch_axpy(n, S->r, S->s, S->as, 1, 1, ds, RUN_ACTIVE, gv, st));
+        ENQ(FK_KERNEL_DOT, launch_dot(n, S->r, S->r, nullptr, 1, S->red(FIN_C_B_RR, RUN_ACTIVE), gv, st));
+        ENQ(FK_KERNEL_DOT, launch_dot(n, S->r, S->rs, nullptr, 1, S->red(FIN_C_B_RHO, RUN_ACTIVE), gv, st));
+        if (!last)
+            ENQ(FK_KERNEL_AXPY, launch_xpay(n, S->p, S->r, S->ap, ds, RUN_ACTIVE, gv, st));
+        break;
+    default:
+        return hipErrorInvalidValue;
+    }
+    return hipSuccess;
+}
+
+#undef ENQ
+
+hipError_t enqueue_poll(fk_solver S, int slot)
+{
+    const char *status_addr = reinterpret_cast<const char *>(S->st) + offsetof(DevState, status);
+    hipError_t e = hipMemcpyAsync(&S->h_status[slot], status_addr, sizeof(int32_t),
+                                  hipMemcpyDeviceToHost, S->stream);
+    if (e != hipSuccess)
+        return e;
+    return hipEventRecord(S->poll_ev[slot], S->stream);
+}
+
+// Capture `iters` iterations into a graph (reused while x stays the same).
+hipError_t ensure_graph(fk_solver S, double *x, int iters)
+{
+    if (S->graph_exec && S->graph_x == x && S->graph_iters == iters)
+        return hipSuccess;
+    if (S->graph_exec)
+        (void)hipGraphExecDestroy(S->graph_exec);
+    if (S->graph)
+        (void)hipGraphDestroy(S->graph);
+    S->graph_exec = nullptr;
+    S->graph = nullptr;
+    hipError_t e = hipStreamBeginCapture(S->stream, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess)
+        return e;
+    Enq q{S, false, 0};
+    hipError_t e2 = hipSuccess;
+    for (int i = 0; i < iters && e2 == hipSuccess; ++i)
+        e2 = enqueue_iteration(S, q, x, false);
+    hipGraph_t g = nullptr;
+    e = hipStreamEndCapture(S->stream, &g);
+    if (e2 != hipSuccess) {
+        if (g)
+            (void)hipGraphDestroy(g);
+        return e2;
+    }
+    if (e != hipSuccess)
+        return e;
+    e = hipGraphInstantiate(&S->graph_exec, g, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+        (void)hipGraphDestroy(g);
+        return e;
+    }
+    S->graph = g;
+    S->graph_x = x;
+    S->graph_iters = iters;
+    return hipSuccess;
+}
+
+void harvest_profile(fk_solver S, int batch)
+{
+    const std::vector<hipEvent_t> &pool = S->prof_ev[batch];
+    for (const TimedLaunch &t : S->prof_batch[batch]) {
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, pool[t.slot], pool[t.slot + 1]) == hipSuccess) {
+            S->prof_us[t.kind] += 1000.0 * (double)ms;
+            S->prof_n[t.kind] += 1;
+        }
+    }
+}
+
+}  // namespace
+
+extern "C" fk_status fk_solve(fk_solver S, const double *b, double *x)
+{
+    if (!S || !b || !x)
+        return fail(FK_E_ARG, "NULL argument");
+    S->solved = false;
+    const bool profile = (S->o.flags & FK_FLAG_PROFILE) != 0;
+    const bool graph = !profile && (S->o.flags & FK_FLAG_GRAPH) != 0 && S->stream != nullptr;
+    if (profile) {
+        for (int k = 0; k < FK_KERNEL_KINDS; ++k) {
+            S->prof_us[k] = 0.0;
+            S->prof_n[k] = 0;
+        }
+    }
+
+    DevState init{};
+    init.status = ST_RUNNING;
+    init.rtol = S->o.rtol;
+    init.max_iter = S->o.max_iter;
+    init.hist_cap = S->hist_cap;
+    *S->h_init = init;
+    HIP_TRY(hipMemcpyAsync(S->st, S->h_init, sizeof(DevState), hipMemcpyHostToDevice, S->stream));
+
+    const int64_t max_iter = S->o.max_iter;
+    const int U = S->o.unroll;
+    int64_t launched = 0;
+    int cur = 0;
+
+    auto enqueue_batch = [&](int slot, bool with_setup) -> hipError_t {
+        S->prof_batch[slot].clear();
+        S->prof_next[slot] = 0;
+        Enq q{S, profile, slot};
+        hipError_t e = hipSuccess;
+        if (with_setup)
+            e = enqueue_setup(S, q, b, x);
+        if (e != hipSuccess)
+            return e;
+        const int64_t todo = std::min<int64_t>(U, max_iter - launched);
+        const bool reaches_end = launched + todo == max_iter;
+        if (graph && todo == U && !reaches_end) {
+            e = ensure_graph(S, x, U);
+            if (e != hipSuccess)
+                return e;
+            e = hipGraphLaunch(S->graph_exec, S->stream);
+        } else {
+            for (int64_t i = 0; i < todo && e == hipSuccess; ++i)
+                e = enqueue_iteration(S, q, x, reaches_end && i == todo - 1);
+        }
+        if (e != hipSuccess)
+            return e;
+        launched += todo;
+        return enqueue_poll(S, slot);
+    };
+
+    // A batch slot is reused only after its poll has been waited for (and its
+    // profile events harvested).
+    hipError_t e = enqueue_batch(0, true);
+    if (e != hipSuccess)
+        return fail(FK_E_HIP, "enqueue: %s", hipGetErrorString(e));
+    for (;;) {
+        const bool more = launched < max_iter;
+        if (more) {
+            e = enqueue_batch(cur ^ 1, false);
+            if (e != hipSuccess)
+                return fail(FK_E_HIP, "enqueue: %s", hipGetErrorString(e));
+        }
+        HIP_TRY(hipEventSynchronize(S->poll_ev[cur]));
+        const int32_t status = S->h_status[cur];
+        // Every launch of a batch ran if the solve was still going (or had
+        // just used up its iteration budget) when the batch ended.
+        if (profile && (status == ST_RUNNING || status == ST_NOT_CONVERGED))
+            harvest_profile(S, cur);
+        if (status != ST_RUNNING || !more)
+            break;
+        cur ^= 1;
+    }
+    HIP_TRY(hipMemcpyAsync(S->h_init, S->st, sizeof(DevState), hipMemcpyDeviceToHost, S->stream));
+    HIP_TRY(hipStreamSynchronize(S->stream));
+    S->last = *S->h_init;
+    S->solved = true;
+    switch (S->last.status) {
+    case ST_CONVERGED:
+    case ST_ZERO_RHS:
+        S->last_status = FK_OK;
+        break;
+    case ST_BREAKDOWN:
+        S->last_status = FK_BREAKDOWN;
+        break;
+    default:
+        S->last_status = FK_NOT_CONVERGED;
+        break;
+    }
+    if (S->last_status == FK_BREAKDOWN)
+        fail(FK_BREAKDOWN, "breakdown at iteration %d", S->last.it);
+    else if (S->last_status == FK_NOT_CONVERGED)
+        fail(FK_NOT_CONVERGED, "not converged after %d iterations (rel. residual %.3e)", S->last.it,
+             S->last.last_rel);
+    return S->last_status;
+}
+
+extern "C" fk_status fk_get_iterations(fk_solver S, int32_t *k)
+{
+    if (!S || !k)
+        return fail(FK_E_ARG, "NULL argument");
+    if (!S->solved)
+        return fail(FK_E_STATE, "no completed solve");
+    *k = S->last.it;
+    return FK_OK;
+}
+
+extern "C" fk_status fk_get_residual(fk_solver S, double *rel)
+{
+    if (!S || !rel)
+        return fail(FK_E_ARG, "NULL argument");
+    if (!S->solved)
+        return fail(FK_E_STATE, "no completed solve");
+    *rel = S->last.last_rel;
+    return FK_OK;
+}
+
+extern "C" fk_status fk_get_residual_history(fk_solver S, double *out, int32_t cap, int32_t *len)
+{
+    if (!S || !len || (cap > 0 && !out) || cap < 0)
+        return fail(FK_E_ARG, "bad argument");
+    if (!S->solved)
+        return fail(FK_E_STATE, "no completed solve");
+    if (!S->hist)
+        return fail(FK_E_STATE, "solver created without record_history");
+    *len = S->last.it + 1;
+    const int32_t m = std::min(std::min(cap, *len), S->hist_cap);
+    if (m > 0)
+        HIP_TRY(hipMemcpyAsync(out, S->hist, (size_t)m * sizeof(double), hipMemcpyDeviceToHost, S->stream));
+    HIP_TRY(hipStreamSynchronize(S->stream));
+    return FK_OK;
+}
+
+extern "C" fk_status fk_get_scalars(fk_solver S, double *out, int32_t cap, int32_t *len)
+{
+    if (!S || !len || (cap > 0 && !out) || cap < 0)
+        return fail(FK_E_ARG, "bad argument");
+    if (!S->solved)
+        return fail(FK_E_STATE, "no completed solve");
+    if (!S->scal)
+        return fail(FK_E_STATE, "solver created without record_history");
+    *len = S->last.it;
+    const int32_t m = std::min(std::min(cap, *len), S->hist_cap);
+    if (m > 0)
+        HIP_TRY(hipMemcpyAsync(out, S->scal, (size_t)m * 4 * sizeof(double), hipMemcpyDeviceToHost, S->stream));
+    HIP_TRY(hipStreamSynchronize(S->stream));
+    return FK_OK;
+}
+
+extern "C" fk_status fk_get_kernel_times(fk_solver S, double *avg_us, int32_t *count, int32_t cap)
+{
+    if (!S || cap < 0 || (cap > 0 && (!avg_us || !count)))
+        return fail(FK_E_ARG, "bad argument");
+    for (int k = 0; k < cap && k < FK_KERNEL_KINDS; ++k) {
+        count[k] = S->prof_n[k];
+        avg_us[k] = S->prof_n[k] ? S->prof_us[k] / S->prof_n[k] : 0.0;
+    }
+    return FK_OK;
+}
+
+// ------------------------------------------------------- kernel entry points
+
+extern "C" fk_status fk_spmv(fk_csr A, const double *p, double *q, double *dots_host, void *hip_stream)
+{
+    if (!A || !p || !q)
+        return fail(FK_E_ARG, "NULL argument");
+    if ((const void *)p == (const void *)q)
+        return fail(FK_E_ARG, "p and q must not alias");
+    hipStream_t s = (hipStream_t)hip_stream;
+    const int dots = dots_host ? (D_YV | D_YY) : 0;
+    RedArgs red{A->st, A->partials, nullptr, nullptr, FIN_NONE, RUN_ALWAYS};
+    HIP_TRY(launch_spmv_dots(A->view(), p, q, nullptr, dots, red, spmv_grid(A->nblocks), s));
+    if (dots_host) {
+        double d[KMAX];
+        HIP_TRY(hipMemcpyAsync(d, reinterpret_cast<const char *>(A->st) + offsetof(DevState, dots),
+                               sizeof d, hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        dots_host[0] = d[0];
+        dots_host[1] = d[1];
+    } else {
+        HIP_TRY(hipStreamSynchronize(s));
+    }
+    return FK_OK;
+}
+
+namespace {
+std::mutex g_dot_mu;
+DevState *g_dot_st = nullptr;
+double *g_dot_partials = nullptr;
+}  // namespace
+
+extern "C" fk_status fk_dot(int64_t n, const double *a, const double *b, double *out, void *hip_stream)
+{
+    if (!out || n < 0 || (n > 0 && (!a || !b)))
+        return fail(FK_E_ARG, "bad argument");
+    if (n == 0) {
+        *out = 0.0;
+        return FK_OK;
+    }
+    std::lock_guard<std::mutex> lock(g_dot_mu);
+    hipStream_t s = (hipStream_t)hip_stream;
+    if (!g_dot_st) {
+        fk_status st = dev_alloc(&g_dot_st, 1, "dot state");
+        if (st != FK_OK)
+            return st;
+        st = dev_alloc(&g_dot_partials, RED_SCRATCH_DOUBLES, "dot partials");
+        if (st != FK_OK) {
+            dev_free(g_dot_st);
+            return st;
+        }
+        HIP_TRY(hipMemsetAsync(g_dot_st, 0, sizeof(DevState), s));
+        HIP_TRY(hipMemsetAsync(g_dot_partials, 0, RED_SCRATCH_DOUBLES * sizeof(double), s));
+    }
+    RedArgs red{g_dot_st, g_dot_partials, nullptr, nullptr, FIN_NONE, RUN_ALWAYS};
+    HIP_TRY(launch_dot(n, a, b, nullptr, 1, red, vec_grid(n), s));
+    HIP_TRY(hipMemcpyAsync(out, reinterpret_cast<const char *>(g_dot_st) + offsetof(DevState, dots),
+                           sizeof(double), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    return FK_OK;
+}
+
+extern "C" fk_status fk_copy(void *dst, const void *src, int64_t n_bytes, void *hip_stream)
+{
+    if (n_bytes < 0 || (n_bytes > 0 && (!dst || !src)))
+        return fail(FK_E_ARG, "bad argument");
+    if (n_bytes == 0)
+        return FK_OK;
+    hipStream_t s = (hipStream_t)hip_stream;
+    static const int gmax = env_int("FK_COPY_GRID", 2048, 1, 65535);
+    const int64_t n16 = n_bytes / 16;
+    const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(gmax, (n16 + WG - 1) / WG));
+    HIP_TRY(launch_copy(dst, src, n_bytes, grid, s));
+    return FK_OK;
+}
+
+extern "C" const char *fk_status_str(fk_status s)
+{
+    switch (s) {
+    case FK_OK: return "FK_OK";
+    case FK_E_ARG: return "FK_E_ARG";
+    case FK_E_CSR: return "FK_E_CSR";
+    case FK_E_HIP: return "FK_E_HIP";
+    case FK_E_OOM: return "FK_E_OOM";
+    case FK_NOT_CONVERGED: return "FK_NOT_CONVERGED";
+    case FK_BREAKDOWN: return "FK_BREAKDOWN";
+    case FK_E_STATE: return "FK_E_STATE";
+    }
+    return "FK_UNKNOWN";
+}
+
+extern "C" const char *fk_last_error(void) { return g_err.c_str(); }
+
+extern "C" const char *fk_version(void) { return "fk 0.1 gfx950"; }

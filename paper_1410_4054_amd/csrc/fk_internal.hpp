@@ -1,0 +1,144 @@
+// Internal declarations shared by the kernels (fk_kernels.hip) and the host
+// driver / C ABI (fk_capi.hip).  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace fk {
+
+// Workgroup shape of every kernel: four wave64 wavefronts.
+constexpr int WG = 256;
+constexpr int WAVES = WG / 64;
+// Products staged in LDS per row block; rows longer than this are "long rows".
+constexpr int NNZ_MAX = 2048;
+constexpr int ITEMS = NNZ_MAX / WG;  // staged products per thread per block
+// Largest number of inner products reduced together at one reduction point.
+constexpr int KMAX = 4;
+// Upper bound on workgroups of one launch (size of the partial-sum buffer).
+constexpr int GMAX = 4096;
+// The second reduction stage is a two-level tree: workgroups arrive in
+// groups of RGROUP; the last of each group sums the group, the last group
+// sums the group sums.
+constexpr int RGROUP = 32;
+constexpr int RNGROUPS_MAX = GMAX / RGROUP;
+constexpr int CNT_STRIDE = 32;  // uint32 per arrival counter (one 128-byte line each)
+// Layout of the reduction scratch (doubles): level-1 partials [KMAX][GMAX]
+// double-double, level-2 partials [KMAX][RNGROUPS_MAX] double-double, then
+// RNGROUPS_MAX + 1 arrival counters.
+constexpr size_t RED_L2_OFFSET = (size_t)2 * KMAX * GMAX;
+constexpr size_t RED_CNT_OFFSET = RED_L2_OFFSET + (size_t)2 * KMAX * RNGROUPS_MAX;
+constexpr size_t RED_SCRATCH_DOUBLES =
+    RED_CNT_OFFSET + ((size_t)(RNGROUPS_MAX + 1) * CNT_STRIDE * 4 + 7) / 8;
+
+// Solver state kept on the device; only the last workgroup of a reduction
+// writes it, every kernel reads `status` first and returns unless it is one
+// of the states in its run mask.
+enum DevStatus : int32_t {
+    ST_RUNNING = 0,
+    ST_HALF = 1,          // BiCGStab: ||s_i|| met the tolerance; x_{i+1} = x_i + alpha p_i pending
+    ST_CONVERGED = 2,
+    ST_NOT_CONVERGED = 3, // iteration budget used up
+    ST_BREAKDOWN = 4,
+    ST_ZERO_RHS = 5,      // b = 0: x = 0, k = 0
+};
+
+constexpr uint32_t RUN_ACTIVE = 1u << ST_RUNNING;
+constexpr uint32_t RUN_ACTIVE_OR_HALF = (1u << ST_RUNNING) | (1u << ST_HALF);
+constexpr uint32_t RUN_HALF = 1u << ST_HALF;
+constexpr uint32_t RUN_ALWAYS = 0xffffffffu;
+
+struct alignas(128) DevState {
+    double alpha, beta, omega;
+    double rr;        // <r_i, r_i> (CG) / last direct <r,r> (BiCGStab, diagnostic)
+    double rho;       // <r_i, r0*>
+    double apr;       // <A p_i, r0*>
+    double ss;        // <s_i, s_i>
+    double rr_next;   // BiCGStab: expanded <r_{i+1}, r_{i+1}>
+    double bnorm, tol, rtol;
+    double last_rel;  // ||r_k|| / ||b|| of the last completed iteration
+    double dots[KMAX];  // rounded results of the last reduction
+    int32_t it;       // completed iterations k
+    int32_t status;
+    int32_t max_iter;
+    int32_t hist_cap; // entries of hist / 4-tuples of scal available
+    uint32_t pad[4];
+};
+
+// What the last workgroup does with the reduced inner products.
+enum Fin : int32_t {
+    FIN_NONE = 0,       // keep the rounded dots in state->dots only
+    FIN_SETUP,          // d = {<r0,r0>, <b,b>}
+    FIN_CG_ALPHA,       // d = {<p,Ap>, <Ap,Ap>}: alpha_i, beta_i (Eq. (3))
+    FIN_CG_RR,          // d = {<r_i,r_i>}: k, convergence
+    FIN_B_ALPHA,        // d = {<Ap,r0*>}: alpha_i
+    FIN_B_SS,           // d = {<s,s>}: half-step test
+    FIN_B_OMEGA,        // d = {<As,s>, <As,As>, <As,r0*>}: omega, beta, expanded rr
+    FIN_B_XRP,          // d = {<r,r0*>, <r,r>}: rho, k, convergence (pipelined)
+    FIN_C_CG_ALPHA,     // classical CG: d = {<p,q>}
+    FIN_C_CG_BETA,      // classical CG: d = {<r,r>}
+    FIN_C_B_OMEGA,      // classical BiCGStab: d = {<t,s>, <t,t>}
+    FIN_C_B_RR,         // classical BiCGStab: d = {<r,r>}
+    FIN_C_B_RHO,        // classical BiCGStab: d = {<r,r0*>}
+    FIN_HALF_DONE,      // BiCGStab half-step exit bookkeeping (no dots)
+};
+
+// Everything a reduction point needs.
+struct RedArgs {
+    DevState *st;
+    double *partials;  // reduction scratch, RED_SCRATCH_DOUBLES (zeroed once)
+    double *hist;      // ||r_i||/||b|| or nullptr
+    double *scal;      // 4 scalars per iteration or nullptr
+    int32_t fin;
+    uint32_t run_mask;
+};
+
+// CSR matrix on the device plus its row-block plan.
+struct DevCsr {
+    int32_t n;
+    int32_t nnz;
+    int32_t nblocks;
+    const int32_t *row_ptr;
+    const int32_t *col_idx;
+    const double *vals;
+    const int32_t *blocks;    // row index where block b starts; blocks[nblocks] = n
+    const int32_t *block_j0;  // row_ptr[blocks[b]] (first nonzero of block b)
+};
+
+// Dot selection bits for the fused product kernel y = A v.
+enum DotBits : int32_t {
+    D_YV = 1,  // <y, v>
+    D_YY = 2,  // <y, y>
+    D_YW = 4,  // <y, w>
+};
+
+// Host-side launch wrappers (fk_kernels.hip).
+hipError_t launch_spmv_dots(const DevCsr &A, const double *v, double *y, const double *w,
+                            int dots, const RedArgs &red, int grid, hipStream_t s);
+hipError_t launch_residual0(const DevCsr &A, const double *b, const double *x, double *r,
+                            double *p, double *rs, const RedArgs &red, int grid, hipStream_t s);
+hipError_t launch_cg_update(int64_t n, double *x, double *r, double *p, const double *ap,
+                            const RedArgs &red, int grid, hipStream_t s);
+hipError_t launch_bicg_s(int64_t n, const double *r, const double *ap, double *sv,
+                         const RedArgs &red, int grid, hipStream_t s);
+hipError_t launch_bicg_xrp(int64_t n, double *x, double *r, double *p, const double *sv,
+                           const double *as, const double *ap, const double *rs,
+                           const RedArgs &red, int grid, hipStream_t s);
+// Classical (unfused) building blocks.
+hipError_t launch_dot(int64_t n, const double *a, const double *b, const double *c,
+                      int ndots, const RedArgs &red, int grid, hipStream_t s);
+// out = y + coef * x (negative = 0) or y - coef * x (negative = 1),
+// coef = state->alpha (which = 0) or state->omega (which = 1)
+hipError_t launch_axpy(int64_t n, double *out, const double *y, const double *x, int which,
+                       int negative, DevState *st, uint32_t run_mask, int grid, hipStream_t s);
+// p = r + beta * (p - omega * v) when v != nullptr, else p = r + beta * p
+hipError_t launch_xpay(int64_t n, double *p, const double *r, const double *v,
+                       DevState *st, uint32_t run_mask, int grid, hipStream_t s);
+// dst = src when state->status is in run_mask; then runs `fin` on one thread.
+hipError_t launch_copy_fin(int64_t n, double *dst, const double *src, const RedArgs &red,
+                           hipStream_t s);
+hipError_t launch_copy(void *dst, const void *src, int64_t n_bytes, int grid, hipStream_t s);
+hipError_t launch_zero(double *x, int64_t n, DevState *st, uint32_t run_mask, int grid,
+                       hipStream_t s);
+
+}  // namespace fk

@@ -1,0 +1,918 @@
+// HIP kernels for gfx950 (CDNA4, wave64) of the pipelined CG and BiCGStab
+// iterations (Sections 2.2, 3.1 and 3.2 of arXiv:1410.4054).
+//
+// Structure shared by every kernel that ends in a reduction point:
+//   1. the kernel returns at once unless the solver state is in its run mask
+//      (the state is written only by the last workgroup of the previous
+//      reduction point, so the test is uniform across the grid);
+//   2. each thread accumulates its share of up to KMAX inner products as
+//      error-free double-double sums (TwoProduct through fma, TwoSum);
+//   3. the workgroup combines them with wave64 cross-lane shuffles and LDS
+//      and thread 0 stores one double-double partial per inner product
+//      (the first reduction stage of Section 2.2);
+//   4. the second stage runs in the workgroups that arrive last: a
+//      two-level tree of arrival counters (see reduce_point) sums all
+//      partials in a fixed order, rounds once, and the very last workgroup
+//      evaluates the scalar recurrences (alpha, beta, omega, convergence)
+//      on the device.
+// Partials are published with agent-scope (device-coherent) atomic stores
+// and read back with agent-scope atomic loads, and the store counter is
+// drained before arriving at a counter.  A release/acquire fence would do the
+// same but, with one L2 per XCD, it writes back and invalidates the whole
+// L2 of the issuing XCD; taken by thousands of workgroups per launch that
+// cost more than the kernel's own memory traffic.  Counters are split into
+// groups because same-address device atomics serialize: thousands of them
+// arriving together at one counter would add tens of microseconds.
+// No floating-point atomics are used: results do not depend on which
+// workgroup finishes last and are bitwise reproducible.
+//
+// Files are built with -ffp-contract=off: products and sums are rounded one
+// by one, exactly as written; fma appears only where the error of a product
+// is extracted.
+#include "fk_internal.hpp"
+
+// Minimum waves per SIMD the product kernels are compiled for (caps VGPRs).
+#ifndef FK_SPMV_MIN_WAVES
+#define FK_SPMV_MIN_WAVES 8
+#endif
+
+namespace fk {
+namespace {
+
+// ------------------------------------------------------------ double-double
+
+struct dd {
+    double hi, lo;
+};
+
+__device__ __forceinline__ void two_sum(double a, double b, double &s, double &e)
+{
+    s = a + b;
+    double z = s - a;
+    e = (a - (s - z)) + (b - z);
+}
+
+// (a.hi + a.lo) + (b.hi + b.lo), renormalised.  Commutative bit for bit.
+__device__ __forceinline__ dd dd_add(dd a, dd b)
+{
+    double s, e;
+    two_sum(a.hi, b.hi, s, e);
+    e = e + (a.lo + b.lo);
+    double h = s + e;
+    return dd{h, e - (h - s)};
+}
+
+// acc += a * b, keeping the rounding errors of the product and the sum.
+__device__ __forceinline__ void dd_fma(dd &acc, double a, double b)
+{
+    double p = a * b;
+    double pe = __builtin_fma(a, b, -p);
+    double s, e;
+    two_sum(acc.hi, p, s, e);
+    acc.hi = s;
+    acc.lo = acc.lo + (e + pe);
+}
+
+__device__ __forceinline__ dd wave_reduce(dd v)
+{
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+        dd o;
+        o.hi = __shfl_xor(v.hi, off, 64);
+        o.lo = __shfl_xor(v.lo, off, 64);
+        v = dd_add(v, o);
+    }
+    return v;
+}
+
+// Sum K double-double values over the workgroup; the result is valid in
+// thread 0.  Ends with every thread past a barrier that follows the last
+// LDS read, so `lds` may be reused right away.
+template <int K>
+__device__ __forceinline__ void block_reduce(dd (&v)[K], dd (*lds)[KMAX])
+{
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int k = 0; k < K; ++k)
+        v[k] = wave_reduce(v[k]);
+    if (lane == 0) {
+#pragma unroll
+        for (int k = 0; k < K; ++k)
+            lds[wave][k] = v[k];
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            dd a = lds[0][k];
+            for (int w = 1; w < WAVES; ++w)
+                a = dd_add(a, lds[w][k]);
+            v[k] = a;
+        }
+    }
+    __syncthreads();
+}
+
+// Fixed-order workgroup sum of one plain double (long CSR rows).
+__device__ __forceinline__ double block_sum(double v, double *lds)
+{
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1)
+        v = v + __shfl_xor(v, off, 64);
+    if (lane == 0)
+        lds[wave] = v;
+    __syncthreads();
+    double s = lds[0];
+    for (int w = 1; w < WAVES; ++w)
+        s = s + lds[w];
+    __syncthreads();
+    return s;
+}
+
+// Device-coherent (agent-scope) store and load of one double.
+__device__ __forceinline__ void store_coherent(double *p, double v)
+{
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ double load_coherent(const double *p)
+{
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ bool runs(const RedArgs &red)
+{
+    return ((1u << red.st->status) & red.run_mask) != 0u;
+}
+
+// Workgroups are dispatched to the eight XCDs round robin.  Renumber them so
+// that each XCD owns a contiguous range of logical workgroups, hence a
+// contiguous slab of rows: the gathers of neighbouring rows then hit that
+// XCD's own L2.
+__device__ __forceinline__ int logical_wg()
+{
+    const int G = gridDim.x;
+    const int b = blockIdx.x;
+    if (G < 8 || (G & 7) != 0)
+        return b;
+    return (b & 7) * (G >> 3) + (b >> 3);
+}
+
+// ------------------------------------------------------------- finalize
+
+__device__ __forceinline__ void put_hist(const RedArgs &red, int it, double v)
+{
+    if (red.hist && it < red.st->hist_cap)
+        red.hist[it] = v;
+}
+
+__device__ __forceinline__ void put_scal(const RedArgs &red, int it, int slot, double v)
+{
+    if (red.scal && it < red.st->hist_cap)
+        red.scal[4 * it + slot] = v;
+}
+
+// Scalar work of a reduction point (one thread).  The expressions and their
+// order follow Algorithms 1-4 exactly; see the comments per case.
+__device__ void finalize(const RedArgs &red, const double *d, int K)
+{
+    DevState *st = red.st;
+    for (int k = 0; k < K; ++k)
+        st->dots[k] = d[k];
+    switch (red.fin) {
+    case FIN_NONE:
+        break;
+    case FIN_SETUP: {  // d = {<r0,r0>, <b,b>}
+        const double rr = d[0], bb = d[1];
+        st->it = 0;
+        st->rr = rr;
+        st->rho = rr;  // r0* = r0, so <r0, r0*> = <r0, r0>
+        if (bb == 0.0) {
+            st->bnorm = 0.0;
+            st->tol = 0.0;
+            st->last_rel = 0.0;
+            put_hist(red, 0, 0.0);
+            st->status = ST_ZERO_RHS;
+            break;
+        }
+        const double bnorm = sqrt(bb);
+        st->bnorm = bnorm;
+        st->tol = st->rtol * bnorm;
+        const double rel = sqrt(rr) / bnorm;
+        st->last_rel = rel;
+        put_hist(red, 0, rel);
+        if (!isfinite(rr))
+            st->status = ST_BREAKDOWN;
+        else if (sqrt(rr) <= st->tol)
+            st->status = ST_CONVERGED;
+        break;
+    }
+    case FIN_CG_ALPHA: {  // Algorithm 2: d = {<p_i,Ap_i>, <Ap_i,Ap_i>}
+        const double pap = d[0], apap = d[1];
+        if (!(pap > 0.0) || !isfinite(pap) || !isfinite(apap)) {
+            st->status = ST_BREAKDOWN;
+            break;
+        }
+        const double alpha = st->rr / pap;
+        const double beta = alpha * alpha * apap / st->rr - 1.0;  // Eq. (3)
+        st->alpha = alpha;
+        st->beta = beta;
+        put_scal(red, st->it, 0, alpha);
+        put_scal(red, st->it, 1, beta);
+        if (st->it >= st->max_iter)
+            st->status = ST_NOT_CONVERGED;
+        break;
+    }
+    case FIN_CG_RR: {  // Algorithm 2: d = {<r_i,r_i>}
+        const double rr = d[0];
+        const int it = st->it + 1;
+        st->it = it;
+        st->rr = rr;
+        const double rel = sqrt(rr) / st->bnorm;
+        st->last_rel = rel;
+        put_hist(red, it, rel);
+        put_scal(red, it - 1, 3, rr);
+        if (!isfinite(rr))
+            st->status = ST_BREAKDOWN;
+        else if (sqrt(rr) <= st->tol)
+            st->status = ST_CONVERGED;
+        else if (it >= st->max_iter)
+            st->status = ST_NOT_CONVERGED;
+        break;
+    }
+    case FIN_B_ALPHA: {  // Algorithms 3/4: d = {<Ap_i, r0*>}
+        const double apr = d[0], rho = st->rho;
+        if (apr == 0.0 || !isfinite(apr) || rho == 0.0 || !isfinite(rho)) {
+            st->status = ST_BREAKDOWN;
+            break;
+        }
+        st->apr = apr;
+        st->alpha = rho / apr;
+        put_scal(red, st->it, 0, st->alpha);
+        break;
+    }
+    case FIN_B_SS: {  // d = {<s_i, s_i>}: half-step test
+        st->ss = d[0];
+        if (sqrt(d[0]) <= st->tol)
+            st->status = ST_HALF;
+        break;
+    }
+    case FIN_B_OMEGA: {  // Algorithm 4: d = {<As,s>, <As,As>, <As,r0*>}
+        const double ass = d[0], asas = d[1], asr = d[2];
+        if (asas == 0.0 || !isfinite(asas) || !isfinite(ass) || !isfinite(asr)) {
+            st->status = ST_BREAKDOWN;
+            break;
+        }
+        const double beta = -asr / st->apr;   // via <s_i, r0*> = 0
+        const double omega = ass / asas;
+        st->beta = beta;
+        st->omega = omega;
+        // <r_{i+1}, r_{i+1}> expanded in <s,s>, <s,As>, <As,As>
+        st->rr_next = st->ss - 2.0 * omega * ass + omega * omega * asas;
+        put_scal(red, st->it, 1, beta);
+        put_scal(red, st->it, 2, omega);
+        break;
+    }
+    case FIN_B_XRP: {  // Algorithm 4: d = {<r_{i+1}, r0*>, <r_{i+1}, r_{i+1}>}
+        const int it = st->it + 1;
+        st->it = it;
+        if (st->status == ST_HALF) {
+            const double rel = sqrt(st->ss) / st->bnorm;
+            st->last_rel = rel;
+            put_hist(red, it, rel);
+            put_scal(red, it - 1, 3, st->ss);
+            st->status = ST_CONVERGED;
+            break;
+        }
+        st->rho = d[0];
+        st->rr = d[1];
+        const double rr_next = st->rr_next;
+        const double rnorm = sqrt(rr_next > 0.0 ? rr_next : 0.0);
+        const double rel = rnorm / st->bnorm;
+        st->last_rel = rel;
+        put_hist(red, it, rel);
+        put_scal(red, it - 1, 3, rr_next);
+        if (!isfinite(rr_next))
+            st->status = ST_BREAKDOWN;
+        else if (rnorm <= st->tol)
+            st->status = ST_CONVERGED;
+        else if (st->omega == 0.0)
+            st->status = ST_BREAKDOWN;
+        else if (it >= st->max_iter)
+            st->status = ST_NOT_CONVERGED;
+        break;
+    }
+    case FIN_C_CG_ALPHA: {  // Algorithm 1: d = {<p_i, A p_i>}
+        const double pq = d[0];
+        if (!(pq > 0.0) || !isfinite(pq)) {
+            st->status = ST_BREAKDOWN;
+            break;
+        }
+        st->alpha = st->rr / pq;
+        put_scal(red, st->it, 0, st->alpha);
+        break;
+    }
+    case FIN_C_CG_BETA: {  // Algorithm 1: d = {<r_{i+1}, r_{i+1}>}
+        const double rr_new = d[0];
+        const int it = st->it + 1;
+        st->it = it;
+        const double rel = sqrt(rr_new) / st->bnorm;
+        st->last_rel = rel;
+        put_hist(red, it, rel);
+        put_scal(red, it - 1, 3, rr_new);
+        if (!isfinite(rr_new)) {
+            st->status = ST_BREAKDOWN;
+        } else if (sqrt(rr_new) <= st->tol) {
+            st->status = ST_CONVERGED;
+        } else if (it >= st->max_iter) {
+            st->status = ST_NOT_CONVERGED;
+        } else {
+            st->beta = rr_new / st->rr;
+            put_scal(red, it - 1, 1, st->beta);
+            st->rr = rr_new;
+        }
+        break;
+    }
+    case FIN_C_B_OMEGA: {  // Algorithm 3: d = {<t,s>, <t,t>}, t = A s_i
+        const double ts = d[0], tt = d[1];
+        if (tt == 0.0 || !isfinite(tt) || !isfinite(ts)) {
+            st->status = ST_BREAKDOWN;
+            break;
+        }
+        st->omega = ts / tt;
+        put_scal(red, st->it, 2, st->omega);
+        break;
+    }
+    case FIN_C_B_RR: {  // Algorithm 3: d = {<r_{i+1}, r_{i+1}>}
+        const double rr = d[0];
+        const int it = st->it + 1;
+        st->it = it;
+        st->rr = rr;
+        const double rel = sqrt(rr) / st->bnorm;
+        st->last_rel = rel;
+        put_hist(red, it, rel);
+        put_scal(red, it - 1, 3, rr);
+        if (!isfinite(rr))
+            st->status = ST_BREAKDOWN;
+        else if (sqrt(rr) <= st->tol)
+            st->status = ST_CONVERGED;
+        break;
+    }
+    case FIN_C_B_RHO: {  // Algorithm 3: d = {<r_{i+1}, r0*>}
+        const double rho_new = d[0];
+        if (st->omega == 0.0 || rho_new == 0.0 || !isfinite(rho_new)) {
+            st->status = ST_BREAKDOWN;
+            break;
+        }
+        st->beta = (rho_new / st->rho) * (st->alpha / st->omega);
+        put_scal(red, st->it - 1, 1, st->beta);
+        st->rho = rho_new;
+        if (st->it >= st->max_iter)
+            st->status = ST_NOT_CONVERGED;
+        break;
+    }
+    case FIN_HALF_DONE: {  // BiCGStab exit after the half step
+        const int it = st->it + 1;
+        st->it = it;
+        const double rel = sqrt(st->ss) / st->bnorm;
+        st->last_rel = rel;
+        put_hist(red, it, rel);
+        put_scal(red, it - 1, 3, st->ss);
+        st->status = ST_CONVERGED;
+        break;
+    }
+    default:
+        break;
+    }
+}
+
+// The reduction point at the end of a kernel; every thread of every
+// workgroup of the grid must call it exactly once.
+//
+// Second stage as a two-level tree.  Workgroup g publishes its partials and
+// arrives at the counter of group g / RGROUP; the last arrival of a group sums
+// that group's partials (in index order) and arrives at the top counter; the
+// last group sums the group sums (in group order), rounds and finalizes.
+// The order of every sum depends only on the grid size, never on timing.
+// Counters are reset by the workgroup that saw the last arrival, so the
+// scratch is ready for the next launch.
+template <int K>
+__device__ __forceinline__ void reduce_point(dd (&v)[K], const RedArgs &red, int g, int G)
+{
+    __shared__ dd lds[WAVES][KMAX];
+    __shared__ int s_flag;
+    double *const part1 = red.partials;
+    double *const part2 = red.partials + RED_L2_OFFSET;
+    uint32_t *const cnt = reinterpret_cast<uint32_t *>(red.partials + RED_CNT_OFFSET);
+    const int ngroups = (G + RGROUP - 1) / RGROUP;
+    const int grp = g / RGROUP;
+    const int gbase = grp * RGROUP;
+    const int gsize = min(RGROUP, G - gbase);
+
+    block_reduce<K>(v, lds);
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            double *slot = part1 + 2 * ((size_t)k * GMAX + g);
+            store_coherent(slot, v[k].hi);
+            store_coherent(slot + 1, v[k].lo);
+        }
+        // The partial stores must have reached the coherence point before
+        // another workgroup can observe this arrival.
+        __builtin_amdgcn_s_waitcnt(0);
+        const uint32_t prev = __hip_atomic_fetch_add(cnt + (size_t)grp * CNT_STRIDE, 1u,
+                                                     __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        s_flag = (prev == (uint32_t)(gsize - 1)) ? 1 : 0;
+    }
+    __syncthreads();
+    if (!s_flag)
+        return;
+
+    // Last arrival of the group: sum the group's partials.
+    dd acc[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        acc[k] = dd{0.0, 0.0};
+        if ((int)threadIdx.x < gsize) {
+            const double *slot = part1 + 2 * ((size_t)k * GMAX + gbase + threadIdx.x);
+            acc[k] = dd{load_coherent(slot), load_coherent(slot + 1)};
+        }
+    }
+    block_reduce<K>(acc, lds);
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            double *slot = part2 + 2 * ((size_t)k * RNGROUPS_MAX + grp);
+            store_coherent(slot, acc[k].hi);
+            store_coherent(slot + 1, acc[k].lo);
+        }
+        __hip_atomic_store(cnt + (size_t)grp * CNT_STRIDE, 0u, __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+        __builtin_amdgcn_s_waitcnt(0);
+        const uint32_t prev = __hip_atomic_fetch_add(cnt + (size_t)RNGROUPS_MAX * CNT_STRIDE, 1u,
+                                                     __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        s_flag = (prev == (uint32_t)(ngroups - 1)) ? 1 : 0;
+    }
+    __syncthreads();
+    if (!s_flag)
+        return;
+
+    // Last group: sum the group sums and finalize.
+#pragma unroll
+    for (int k = 0; k < K; ++k)
+        acc[k] = dd{0.0, 0.0};
+    for (int j = threadIdx.x; j < ngroups; j += WG) {
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            const double *slot = part2 + 2 * ((size_t)k * RNGROUPS_MAX + j);
+            acc[k] = dd_add(acc[k], dd{load_coherent(slot), load_coherent(slot + 1)});
+        }
+    }
+    block_reduce<K>(acc, lds);
+    if (threadIdx.x == 0) {
+        double d[K > 0 ? K : 1];
+#pragma unroll
+        for (int k = 0; k < K; ++k)
+            d[k] = acc[k].hi + acc[k].lo;
+        __hip_atomic_store(cnt + (size_t)RNGROUPS_MAX * CNT_STRIDE, 0u, __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+        finalize(red, d, K);
+    }
+}
+
+// ---------------------------------------------------- fused CSR products
+
+constexpr int popc3(int b) { return (b & 1) + ((b >> 1) & 1) + ((b >> 2) & 1); }
+
+enum RowMode : int {
+    ROW_SPMV = 0,   // y = A v, dots selected by DOTS
+    ROW_RESID = 1,  // r = b - A x, p = r (and rs = r); dots <r,r>, <b,b>
+};
+
+struct RowIo {
+    const double *v;  // vector multiplied (p, s or x)
+    double *y;        // result (ROW_SPMV) / r (ROW_RESID)
+    const double *w;  // third vector of <y,w> (ROW_SPMV) / b (ROW_RESID)
+    double *p;        // ROW_RESID: p = r
+    double *rs;       // ROW_RESID: r0* = r (may be null)
+};
+
+template <int MODE, int DOTS, int K>
+__device__ __forceinline__ void row_epilogue(const RowIo &io, int row, double q, double vrow,
+                                             double wrow, dd (&acc)[K])
+{
+    if constexpr (MODE == ROW_SPMV) {
+        io.y[row] = q;
+        int k = 0;
+        if constexpr ((DOTS & D_YV) != 0) dd_fma(acc[k++], q, vrow);
+        if constexpr ((DOTS & D_YY) != 0) dd_fma(acc[k++], q, q);
+        if constexpr ((DOTS & D_YW) != 0) dd_fma(acc[k++], q, wrow);
+        (void)k;
+        (void)vrow;
+        (void)wrow;
+    } else {
+        const double ri = wrow - q;  // wrow = b_i
+        io.y[row] = ri;
+        io.p[row] = ri;
+        if (io.rs)
+            io.rs[row] = ri;
+        dd_fma(acc[0], ri, ri);
+        dd_fma(acc[1], wrow, wrow);
+    }
+}
+
+// One launch processes the row blocks of the plan; workgroup g takes a
+// contiguous chunk of blocks.  A block holds at most WG rows and at most
+// NNZ_MAX nonzeros (or is a single long row).  Products of a block are
+// computed with coalesced loads of vals/col_idx and gathers of v, staged in
+// LDS, and each row is then summed left to right by one thread.  Every
+// load a block needs (its nonzeros, row pointers and the row entries of the
+// vectors in its inner products) is issued before the first wait.
+template <int MODE, int DOTS>
+__global__ __launch_bounds__(WG, FK_SPMV_MIN_WAVES) void k_csr_rows(DevCsr A, RowIo io, RedArgs red)
+{
+    if (!runs(red))
+        return;
+    constexpr int K = (MODE == ROW_RESID) ? 2 : popc3(DOTS);
+    constexpr int KA = K > 0 ? K : 1;
+    constexpr bool NEED_V = MODE == ROW_SPMV && (DOTS & D_YV) != 0;
+    constexpr bool NEED_W = MODE == ROW_RESID || (DOTS & D_YW) != 0;
+    __shared__ double prod[NNZ_MAX];
+    __shared__ int32_t rptr[WG + 1];
+    __shared__ double red_lds[WAVES];
+
+    const int G = gridDim.x;
+    const int g = logical_wg();
+    const int b_begin = (int)(((int64_t)A.nblocks * g) / G);
+    const int b_end = (int)(((int64_t)A.nblocks * (g + 1)) / G);
+    const int tid = threadIdx.x;
+    const double *__restrict__ v = io.v;
+    const double *__restrict__ w = io.w;
+    const int32_t *__restrict__ col = A.col_idx;
+    const double *__restrict__ vals = A.vals;
+    const int32_t *__restrict__ row_ptr = A.row_ptr;
+
+    dd acc[KA];
+#pragma unroll
+    for (int k = 0; k < KA; ++k)
+        acc[k] = dd{0.0, 0.0};
+
+    for (int blk = b_begin; blk < b_end; ++blk) {
+        const int r0 = A.blocks[blk];
+        const int r1 = A.blocks[blk + 1];
+        const int j0 = A.block_j0[blk];
+        const int nrows = r1 - r0;
+        const int nz = A.block_j0[blk + 1] - j0;
+        if (nz <= NNZ_MAX) {
+            double vrow = 0.0, wrow = 0.0;
+            if (tid < nrows) {
+                if constexpr (NEED_V)
+                    vrow = v[r0 + tid];
+                if constexpr (NEED_W)
+                    wrow = w[r0 + tid];
+                rptr[tid] = row_ptr[r0 + tid] - j0;
+            }
+            if (tid == 0)
+                rptr[nrows] = nz;
+            int ci[ITEMS];
+            double va[ITEMS];
+#pragma unroll
+            for (int i = 0; i < ITEMS; ++i) {
+                const int e = tid + i * WG;
+                if (e < nz) {
+                    ci[i] = col[j0 + e];
+                    va[i] = vals[j0 + e];
+                }
+            }
+#pragma unroll
+            for (int i = 0; i < ITEMS; ++i) {
+                const int e = tid + i * WG;
+                if (e < nz)
+                    prod[e] = va[i] * v[ci[i]];
+            }
+            __syncthreads();
+            if (tid < nrows) {
+                const int e0 = rptr[tid], e1 = rptr[tid + 1];
+                double q = 0.0;
+                for (int e = e0; e < e1; ++e)
+                    q = q + prod[e];
+                if constexpr (K > 0)
+                    row_epilogue<MODE, DOTS, KA>(io, r0 + tid, q, vrow, wrow, acc);
+                else
+                    io.y[r0 + tid] = q;
+            }
+            __syncthreads();
+        } else {
+            // A single row longer than NNZ_MAX: strided partial sums, then a
+            // fixed-order tree over the workgroup.
+            double part = 0.0;
+            for (int e = tid; e < nz; e += WG)
+                part = part + vals[j0 + e] * v[col[j0 + e]];
+            const double q = block_sum(part, red_lds);
+            if (tid == 0) {
+                if constexpr (K > 0)
+                    row_epilogue<MODE, DOTS, KA>(io, r0, q, NEED_V ? v[r0] : 0.0,
+                                                 NEED_W ? w[r0] : 0.0, acc);
+                else
+                    io.y[r0] = q;
+            }
+        }
+    }
+    if constexpr (K > 0)
+        reduce_point<KA>(acc, red, g, G);
+}
+
+// --------------------------------------------------- fused vector updates
+
+// Algorithm 2: x_i = x_{i-1} + alpha p_{i-1}; r_i = r_{i-1} - alpha A p_{i-1};
+// p_i = r_i + beta p_{i-1}; first stage of <r_i, r_i>.
+__global__ __launch_bounds__(WG) void k_cg_update(int64_t n, double *__restrict__ x,
+                                                   double *__restrict__ r, double *__restrict__ p,
+                                                   const double *__restrict__ ap, RedArgs red)
+{
+    if (!runs(red))
+        return;
+    const double alpha = red.st->alpha;
+    const double beta = red.st->beta;
+    dd acc[1] = {dd{0.0, 0.0}};
+    const int64_t stride = (int64_t)gridDim.x * WG;
+    for (int64_t i = (int64_t)blockIdx.x * WG + threadIdx.x; i < n; i += stride) {
+        const double pi = p[i];
+        x[i] = x[i] + alpha * pi;
+        const double ri = r[i] - alpha * ap[i];
+        r[i] = ri;
+        p[i] = ri + beta * pi;
+        dd_fma(acc[0], ri, ri);
+    }
+    reduce_point<1>(acc, red, blockIdx.x, gridDim.x);
+}
+
+// Algorithm 4: s_i = r_i - alpha_i A p_i; first stage of <s_i, s_i>.
+__global__ __launch_bounds__(WG) void k_bicg_s(int64_t n, const double *__restrict__ r,
+                                                const double *__restrict__ ap,
+                                                double *__restrict__ s, RedArgs red)
+{
+    if (!runs(red))
+        return;
+    const double alpha = red.st->alpha;
+    dd acc[1] = {dd{0.0, 0.0}};
+    const int64_t stride = (int64_t)gridDim.x * WG;
+    for (int64_t i = (int64_t)blockIdx.x * WG + threadIdx.x; i < n; i += stride) {
+        const double si = r[i] - alpha * ap[i];
+        s[i] = si;
+        dd_fma(acc[0], si, si);
+    }
+    reduce_point<1>(acc, red, blockIdx.x, gridDim.x);
+}
+
+// Algorithm 4: x_{i+1} = x_i + alpha p_i + omega s_i; r_{i+1} = s_i - omega A s_i;
+// p_{i+1} = r_{i+1} + beta (p_i - omega A p_i); first stages of <r_{i+1}, r0*>
+// and (for free, r is in registers) <r_{i+1}, r_{i+1}>.  After a half-step
+// exit: x_{i+1} = x_i + alpha p_i and r_{i+1} = s_i.
+__global__ __launch_bounds__(WG) void k_bicg_xrp(int64_t n, double *__restrict__ x,
+                                                  double *__restrict__ r, double *__restrict__ p,
+                                                  const double *__restrict__ s,
+                                                  const double *__restrict__ as,
+                                                  const double *__restrict__ ap,
+                                                  const double *__restrict__ rs, RedArgs red)
+{
+    if (!runs(red))
+        return;
+    const bool half = red.st->status == ST_HALF;
+    const double alpha = red.st->alpha;
+    const double omega = red.st->omega;
+    const double beta = red.st->beta;
+    dd acc[2] = {dd{0.0, 0.0}, dd{0.0, 0.0}};
+    const int64_t stride = (int64_t)gridDim.x * WG;
+    if (half) {
+        for (int64_t i = (int64_t)blockIdx.x * WG + threadIdx.x; i < n; i += stride) {
+            x[i] = x[i] + alpha * p[i];
+            r[i] = s[i];
+        }
+    } else {
+        for (int64_t i = (int64_t)blockIdx.x * WG + threadIdx.x; i < n; i += stride) {
+            const double si = s[i];
+            const double pi = p[i];
+            x[i] = x[i] + alpha * pi + omega * si;
+            const double ri = si - omega * as[i];
+            r[i] = ri;
+            p[i] = ri + beta * (pi - omega * ap[i]);
+            dd_fma(acc[0], ri, rs[i]);
+            dd_fma(acc[1], ri, ri);
+        }
+    }
+    reduce_point<2>(acc, red, blockIdx.x, gridDim.x);
+}
+
+// ------------------------------------------- classical building blocks
+
+// First stage of <a,b> (and <a,c> when NDOT == 2).
+template <int NDOT>
+__global__ __launch_bounds__(WG) void k_dot(int64_t n, const double *__restrict__ a,
+                                             const double *__restrict__ b,
+                                             const double *__restrict__ c, RedArgs red)
+{
+    if (!runs(red))
+        return;
+    dd acc[NDOT];
+#pragma unroll
+    for (int k = 0; k < NDOT; ++k)
+        acc[k] = dd{0.0, 0.0};
+    const int64_t stride = (int64_t)gridDim.x * WG;
+    for (int64_t i = (int64_t)blockIdx.x * WG + threadIdx.x; i < n; i += stride) {
+        const double ai = a[i];
+        dd_fma(acc[0], ai, b[i]);
+        if constexpr (NDOT == 2)
+            dd_fma(acc[1], ai, c[i]);
+    }
+    reduce_point<NDOT>(acc, red, blockIdx.x, gridDim.x);
+}
+
+__global__ __launch_bounds__(WG) void k_axpy(int64_t n, double *__restrict__ out,
+                                              const double *y, const double *__restrict__ x,
+                                              int which, int negative, const DevState *st,
+                                              uint32_t run_mask)
+{
+    if (((1u << st->status) & run_mask) == 0u)
+        return;
+    const double c = which == 0 ? st->alpha : st->omega;
+    const int64_t stride = (int64_t)gridDim.x * WG;
+    if (negative) {
+        for (int64_t i = (int64_t)blockIdx.x * WG + threadIdx.x; i < n; i += stride)
+            out[i] = y[i] - c * x[i];
+    } else {
+        for (int64_t i = (int64_t)blockIdx.x * WG + threadIdx.x; i < n; i += stride)
+            out[i] = y[i] + c * x[i];
+    }
+}
+
+__global__ __launch_bounds__(WG) void k_xpay(int64_t n, double *__restrict__ p,
+                                              const double *__restrict__ r,
+                                              const double *__restrict__ v, const DevState *st,
+                                              uint32_t run_mask)
+{
+    if (((1u << st->status) & run_mask) == 0u)
+        return;
+    const double beta = st->beta;
+    const double omega = st->omega;
+    const int64_t stride = (int64_t)gridDim.x * WG;
+    if (v) {
+        for (int64_t i = (int64_t)blockIdx.x * WG + threadIdx.x; i < n; i += stride)
+            p[i] = r[i] + beta * (p[i] - omega * v[i]);
+    } else {
+        for (int64_t i = (int64_t)blockIdx.x * WG + threadIdx.x; i < n; i += stride)
+            p[i] = r[i] + beta * p[i];
+    }
+}
+
+// dst = src, then the finalize step `red.fin` on one thread (no inner products).
+__global__ __launch_bounds__(WG) void k_copy_fin(int64_t n, double *__restrict__ dst,
+                                                  const double *__restrict__ src, RedArgs red)
+{
+    if (!runs(red))
+        return;
+    for (int64_t i = threadIdx.x; i < n; i += WG)
+        dst[i] = src[i];
+    if (threadIdx.x == 0)
+        finalize(red, nullptr, 0);
+}
+
+__global__ __launch_bounds__(WG) void k_zero(double *__restrict__ x, int64_t n,
+                                              const DevState *st, uint32_t run_mask)
+{
+    if (((1u << st->status) & run_mask) == 0u)
+        return;
+    const int64_t stride = (int64_t)gridDim.x * WG;
+    for (int64_t i = (int64_t)blockIdx.x * WG + threadIdx.x; i < n; i += stride)
+        x[i] = 0.0;
+}
+
+// Streaming copy with 16-byte accesses, four in flight per thread
+// (bandwidth calibration).
+__global__ __launch_bounds__(WG) void k_copy16(int4 *__restrict__ dst, const int4 *__restrict__ src,
+                                                int64_t n16)
+{
+    const int64_t stride = (int64_t)gridDim.x * WG;
+    int64_t i = (int64_t)blockIdx.x * WG + threadIdx.x;
+    for (; i + 3 * stride < n16; i += 4 * stride) {
+        const int4 a = src[i], b = src[i + stride], c = src[i + 2 * stride], d = src[i + 3 * stride];
+        dst[i] = a;
+        dst[i + stride] = b;
+        dst[i + 2 * stride] = c;
+        dst[i + 3 * stride] = d;
+    }
+    for (; i < n16; i += stride)
+        dst[i] = src[i];
+}
+
+__global__ void k_copy_tail(char *__restrict__ dst, const char *__restrict__ src, int64_t n)
+{
+    for (int64_t i = threadIdx.x; i < n; i += blockDim.x)
+        dst[i] = src[i];
+}
+
+}  // namespace
+
+// ------------------------------------------------------ launch wrappers
+
+hipError_t launch_spmv_dots(const DevCsr &A, const double *v, double *y, const double *w,
+                            int dots, const RedArgs &red, int grid, hipStream_t s)
+{
+    RowIo io{v, y, w, nullptr, nullptr};
+    switch (dots) {
+    case 0: k_csr_rows<ROW_SPMV, 0><<<grid, WG, 0, s>>>(A, io, red); break;
+    case D_YV | D_YY: k_csr_rows<ROW_SPMV, D_YV | D_YY><<<grid, WG, 0, s>>>(A, io, red); break;
+    case D_YW: k_csr_rows<ROW_SPMV, D_YW><<<grid, WG, 0, s>>>(A, io, red); break;
+    case D_YV | D_YY | D_YW: k_csr_rows<ROW_SPMV, D_YV | D_YY | D_YW><<<grid, WG, 0, s>>>(A, io, red); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_residual0(const DevCsr &A, const double *b, const double *x, double *r,
+                            double *p, double *rs, const RedArgs &red, int grid, hipStream_t s)
+{
+    RowIo io{x, r, b, p, rs};
+    k_csr_rows<ROW_RESID, 0><<<grid, WG, 0, s>>>(A, io, red);
+    return hipGetLastError();
+}
+
+hipError_t launch_cg_update(int64_t n, double *x, double *r, double *p, const double *ap,
+                            const RedArgs &red, int grid, hipStream_t s)
+{
+    k_cg_update<<<grid, WG, 0, s>>>(n, x, r, p, ap, red);
+    return hipGetLastError();
+}
+
+hipError_t launch_bicg_s(int64_t n, const double *r, const double *ap, double *sv,
+                         const RedArgs &red, int grid, hipStream_t s)
+{
+    k_bicg_s<<<grid, WG, 0, s>>>(n, r, ap, sv, red);
+    return hipGetLastError();
+}
+
+hipError_t launch_bicg_xrp(int64_t n, double *x, double *r, double *p, const double *sv,
+                           const double *as, const double *ap, const double *rs,
+                           const RedArgs &red, int grid, hipStream_t s)
+{
+    k_bicg_xrp<<<grid, WG, 0, s>>>(n, x, r, p, sv, as, ap, rs, red);
+    return hipGetLastError();
+}
+
+hipError_t launch_dot(int64_t n, const double *a, const double *b, const double *c, int ndots,
+                      const RedArgs &red, int grid, hipStream_t s)
+{
+    if (ndots == 1)
+        k_dot<1><<<grid, WG, 0, s>>>(n, a, b, c, red);
+    else if (ndots == 2)
+        k_dot<2><<<grid, WG, 0, s>>>(n, a, b, c, red);
+    else
+        return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
+hipError_t launch_axpy(int64_t n, double *out, const double *y, const double *x, int which,
+                       int negative, DevState *st, uint32_t run_mask, int grid, hipStream_t s)
+{
+    k_axpy<<<grid, WG, 0, s>>>(n, out, y, x, which, negative, st, run_mask);
+    return hipGetLastError();
+}
+
+hipError_t launch_xpay(int64_t n, double *p, const double *r, const double *v, DevState *st,
+                       uint32_t run_mask, int grid, hipStream_t s)
+{
+    k_xpay<<<grid, WG, 0, s>>>(n, p, r, v, st, run_mask);
+    return hipGetLastError();
+}
+
+hipError_t launch_copy_fin(int64_t n, double *dst, const double *src, const RedArgs &red,
+                           hipStream_t s)
+{
+    k_copy_fin<<<1, WG, 0, s>>>(n, dst, src, red);
+    return hipGetLastError();
+}
+
+hipError_t launch_zero(double *x, int64_t n, DevState *st, uint32_t run_mask, int grid,
+                       hipStream_t s)
+{
+    k_zero<<<grid, WG, 0, s>>>(x, n, st, run_mask);
+    return hipGetLastError();
+}
+
+hipError_t launch_copy(void *dst, const void *src, int64_t n_bytes, int grid, hipStream_t s)
+{
+    const int64_t n16 = n_bytes / 16;
+    if (n16 > 0)
+        k_copy16<<<grid, WG, 0, s>>>(reinterpret_cast<int4 *>(dst),
+                                     reinterpret_cast<const int4 *>(src), n16);
+    const int64_t tail = n_bytes - n16 * 16;
+    if (tail > 0)
+        k_copy_tail<<<1, 64, 0, s>>>(reinterpret_cast<char *>(dst) + n16 * 16,
+                                     reinterpret_cast<const char *>(src) + n16 * 16, tail);
+    return hipGetLastError();
+}
+
+}  // namespace fk

@@ -1,0 +1,308 @@
+"""Python binding of libfk.so (include/fk.h): argument marshalling only.
+
+Every function here forwards to the C ABI function of the same name (without
+the ``fk_`` prefix).  Device buffers are torch tensors on the current HIP
+device (float64 vectors, int32 index arrays); streams are torch streams.
+There is no fallback: if libfk.so cannot be loaded or built, every call
+raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import threading
+from dataclasses import dataclass
+
+import numpy as np
+
+from . import build as _build
+
+# fk_status
+OK, E_ARG, E_CSR, E_HIP, E_OOM, NOT_CONVERGED, BREAKDOWN, E_STATE = range(8)
+STATUS_NAMES = {
+    OK: "converged", NOT_CONVERGED: "not_converged", BREAKDOWN: "breakdown",
+}
+# fk_method
+METHODS = {"cg_pipelined": 0, "cg_classical": 1, "bicgstab_pipelined": 2, "bicgstab_classical": 3}
+FLAG_GRAPH = 1
+FLAG_PROFILE = 2
+PTR_HOST, PTR_DEVICE = 0, 1
+KERNEL_KINDS = ("setup", "spmv_dot", "update_dot", "spmv", "dot", "axpy")
+LONG_ROW = 2048
+
+
+class FkError(RuntimeError):
+    def __init__(self, status: int, where: str, msg: str):
+        super().__init__(f"{where}: status {status}: {msg}")
+        self.status = status
+
+
+class _Opts(ctypes.Structure):
+    _fields_ = [
+        ("method", ctypes.c_int32),
+        ("rtol", ctypes.c_double),
+        ("max_iter", ctypes.c_int32),
+        ("record_history", ctypes.c_int32),
+        ("unroll", ctypes.c_int32),
+        ("flags", ctypes.c_int32),
+    ]
+
+
+_lib = None
+_lock = threading.Lock()
+
+
+def library_path() -> str:
+    """libfk.so next to this file, or the path in FK_LIBRARY (alternate builds)."""
+    return os.environ.get("FK_LIBRARY") or _build.library_path()
+
+
+def lib():
+    """Load libfk.so (building it first if it is absent); raise on failure."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    with _lock:
+        if _lib is not None:
+            return _lib
+        path = library_path()
+        if not os.path.exists(path) and path == _build.library_path():
+            _build.build()
+        L = ctypes.CDLL(path)  # raises OSError if it cannot be loaded
+        vp, i32, i64, f64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+        P = ctypes.POINTER
+        sig = {
+            "fk_csr_create": [i64, i64, vp, vp, vp, i32, vp, P(vp)],
+            "fk_csr_destroy": [vp],
+            "fk_csr_shape": [vp, P(i64), P(i64)],
+            "fk_csr_blocks": [vp, P(i32), P(i32)],
+            "fk_solver_create": [vp, P(_Opts), vp, P(vp)],
+            "fk_solve": [vp, vp, vp],
+            "fk_get_iterations": [vp, P(i32)],
+            "fk_get_residual": [vp, P(f64)],
+            "fk_get_residual_history": [vp, P(f64), i32, P(i32)],
+            "fk_get_scalars": [vp, P(f64), i32, P(i32)],
+            "fk_get_kernel_times": [vp, P(f64), P(i32), i32],
+            "fk_solver_destroy": [vp],
+            "fk_spmv": [vp, vp, vp, P(f64), vp],
+            "fk_dot": [i64, vp, vp, P(f64), vp],
+            "fk_copy": [vp, vp, i64, vp],
+        }
+        for name, args in sig.items():
+            fn = getattr(L, name)
+            fn.argtypes = args
+            fn.restype = ctypes.c_int
+        for name in ("fk_status_str", "fk_last_error", "fk_version"):
+            getattr(L, name).restype = ctypes.c_char_p
+        L.fk_status_str.argtypes = [ctypes.c_int]
+        L.fk_last_error.argtypes = []
+        L.fk_version.argtypes = []
+        _lib = L
+        return L
+
+
+def exported_symbols() -> list[str]:
+    """Names every caller may rely on (the declarations of include/fk.h)."""
+    return [
+        "fk_csr_create", "fk_csr_destroy", "fk_csr_shape", "fk_csr_blocks",
+        "fk_solver_create", "fk_solve", "fk_get_iterations", "fk_get_residual",
+        "fk_get_residual_history", "fk_get_scalars", "fk_get_kernel_times",
+        "fk_solver_destroy", "fk_spmv", "fk_dot", "fk_copy", "fk_status_str",
+        "fk_last_error", "fk_version",
+    ]
+
+
+def _check(status: int, where: str, allowed=(OK,)):
+    if status not in allowed:
+        msg = lib().fk_last_error().decode(errors="replace")
+        raise FkError(status, where, msg)
+    return status
+
+
+def _stream_ptr(stream=None) -> int:
+    import torch
+
+    s = torch.cuda.current_stream() if stream is None else stream
+    return int(s.cuda_stream)
+
+
+def _dev_f64(t, n=None, name="vector"):
+    import torch
+
+    if not isinstance(t, torch.Tensor) or t.device.type != "cuda":
+        raise TypeError(f"{name} must be a torch tensor on a HIP device")
+    if t.dtype != torch.float64 or not t.is_contiguous():
+        raise TypeError(f"{name} must be a contiguous float64 tensor")
+    if n is not None and t.numel() != n:
+        raise ValueError(f"{name} has {t.numel()} entries, expected {n}")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def version() -> str:
+    return lib().fk_version().decode()
+
+
+def status_str(status: int) -> str:
+    return lib().fk_status_str(int(status)).decode()
+
+
+# ------------------------------------------------------------------ matrix
+
+class Matrix:
+    """A device-resident CSR matrix (fk_csr handle)."""
+
+    def __init__(self, csr, stream=None):
+        """`csr`: object with n, row_ptr, col_idx, vals (numpy host arrays)."""
+        L = lib()
+        rp = np.ascontiguousarray(csr.row_ptr, dtype=np.int32)
+        ci = np.ascontiguousarray(csr.col_idx, dtype=np.int32)
+        va = np.ascontiguousarray(csr.vals, dtype=np.float64)
+        h = ctypes.c_void_p()
+        st = L.fk_csr_create(int(csr.n), int(ci.size), rp.ctypes.data_as(ctypes.c_void_p),
+                             ci.ctypes.data_as(ctypes.c_void_p), va.ctypes.data_as(ctypes.c_void_p),
+                             PTR_HOST, ctypes.c_void_p(_stream_ptr(stream)), ctypes.byref(h))
+        _check(st, "fk_csr_create")
+        self._h = h
+        self.n = int(csr.n)
+        self.nnz = int(ci.size)
+
+    @property
+    def handle(self):
+        return self._h
+
+    def blocks(self) -> tuple[int, int]:
+        nb, lr = ctypes.c_int32(), ctypes.c_int32()
+        _check(lib().fk_csr_blocks(self._h, ctypes.byref(nb), ctypes.byref(lr)), "fk_csr_blocks")
+        return nb.value, lr.value
+
+    def close(self):
+        if self._h:
+            _check(lib().fk_csr_destroy(self._h), "fk_csr_destroy")
+            self._h = None
+
+    def __del__(self):
+        try:
+            if getattr(self, "_h", None):
+                lib().fk_csr_destroy(self._h)
+        except Exception:
+            pass
+
+
+def spmv(A: Matrix, p, q, dots: bool = False, stream=None):
+    """q = A p; with dots=True also returns (<p,q>, <q,q>) from the fused reduction."""
+    out = (ctypes.c_double * 2)()
+    st = lib().fk_spmv(A.handle, _dev_f64(p, A.n, "p"), _dev_f64(q, A.n, "q"),
+                       out if dots else None, ctypes.c_void_p(_stream_ptr(stream)))
+    _check(st, "fk_spmv")
+    return (out[0], out[1]) if dots else None
+
+
+def dot(a, b, stream=None) -> float:
+    n = a.numel()
+    out = ctypes.c_double()
+    st = lib().fk_dot(n, _dev_f64(a, n, "a"), _dev_f64(b, n, "b"), ctypes.byref(out),
+                      ctypes.c_void_p(_stream_ptr(stream)))
+    _check(st, "fk_dot")
+    return out.value
+
+
+def copy(dst, src, n_bytes: int, stream=None):
+    st = lib().fk_copy(ctypes.c_void_p(dst.data_ptr()), ctypes.c_void_p(src.data_ptr()),
+                       int(n_bytes), ctypes.c_void_p(_stream_ptr(stream)))
+    _check(st, "fk_copy")
+
+
+# ------------------------------------------------------------------ solver
+
+@dataclass
+class SolveResult:
+    status: str
+    k: int
+    rel_res: float
+    history: np.ndarray | None
+    scalars: np.ndarray | None  # (k, 4): alpha, beta, omega, <r,r> tested
+
+
+class Solver:
+    """fk_solver handle: workspace for one matrix, method and option set."""
+
+    def __init__(self, A: Matrix, method: str = "cg_pipelined", rtol: float = 1e-8,
+                 max_iter: int | None = None, record_history: bool = True, unroll: int = 32,
+                 graph: bool = False, profile: bool = False, stream=None):
+        self.A = A
+        if max_iter is None:
+            max_iter = min(10 * A.n, 2**31 - 2)
+        flags = (FLAG_GRAPH if graph else 0) | (FLAG_PROFILE if profile else 0)
+        o = _Opts(METHODS[method], float(rtol), int(max_iter), int(bool(record_history)),
+                  int(unroll), flags)
+        h = ctypes.c_void_p()
+        st = lib().fk_solver_create(A.handle, ctypes.byref(o), ctypes.c_void_p(_stream_ptr(stream)),
+                                    ctypes.byref(h))
+        _check(st, "fk_solver_create")
+        self._h = h
+        self.method = method
+        self.max_iter = int(max_iter)
+        self.record_history = bool(record_history)
+
+    def solve(self, b, x) -> int:
+        """Run fk_solve; returns the fk_status (OK, NOT_CONVERGED or BREAKDOWN)."""
+        st = lib().fk_solve(self._h, _dev_f64(b, self.A.n, "b"), _dev_f64(x, self.A.n, "x"))
+        return _check(st, "fk_solve", allowed=(OK, NOT_CONVERGED, BREAKDOWN))
+
+    def iterations(self) -> int:
+        k = ctypes.c_int32()
+        _check(lib().fk_get_iterations(self._h, ctypes.byref(k)), "fk_get_iterations")
+        return k.value
+
+    def residual(self) -> float:
+        r = ctypes.c_double()
+        _check(lib().fk_get_residual(self._h, ctypes.byref(r)), "fk_get_residual")
+        return r.value
+
+    def history(self) -> np.ndarray:
+        k = self.iterations()
+        buf = np.empty(k + 1)
+        ln = ctypes.c_int32()
+        _check(lib().fk_get_residual_history(self._h, buf.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                             k + 1, ctypes.byref(ln)), "fk_get_residual_history")
+        return buf[: ln.value]
+
+    def scalars(self) -> np.ndarray:
+        k = self.iterations()
+        buf = np.empty((max(k, 1), 4))
+        ln = ctypes.c_int32()
+        _check(lib().fk_get_scalars(self._h, buf.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                    k, ctypes.byref(ln)), "fk_get_scalars")
+        return buf[: ln.value]
+
+    def kernel_times(self) -> dict[str, tuple[float, int]]:
+        n = len(KERNEL_KINDS)
+        us = (ctypes.c_double * n)()
+        cnt = (ctypes.c_int32 * n)()
+        _check(lib().fk_get_kernel_times(self._h, us, cnt, n), "fk_get_kernel_times")
+        return {name: (us[i], cnt[i]) for i, name in enumerate(KERNEL_KINDS)}
+
+    def close(self):
+        if self._h:
+            _check(lib().fk_solver_destroy(self._h), "fk_solver_destroy")
+            self._h = None
+
+    def __del__(self):
+        try:
+            if getattr(self, "_h", None):
+                lib().fk_solver_destroy(self._h)
+        except Exception:
+            pass
+
+
+def solve(A: Matrix, b, x, method: str = "cg_pipelined", rtol: float = 1e-8,
+          max_iter: int | None = None, record_history: bool = True, **kw) -> SolveResult:
+    """One-shot solve of A x = b on the device (x holds x0 on entry)."""
+    S = Solver(A, method=method, rtol=rtol, max_iter=max_iter, record_history=record_history, **kw)
+    try:
+        st = S.solve(b, x)
+        hist = S.history() if record_history else None
+        scal = S.scalars() if record_history else None
+        return SolveResult(STATUS_NAMES[st], S.iterations(), S.residual(), hist, scal)
+    finally:
+        S.close()
