@@ -1,0 +1,276 @@
+"""Benchmark: pipelined CG iterations/s and achieved HBM bandwidth on one MI355X.
+
+Workload (one "step"): solve the 3D 7-point Poisson problem on a 128^3
+interior grid (N = 2,097,152, nnz = 14,581,760, CSR FP64), b uniform[-1,1)
+from seed 0, x0 = 0, with pipelined CG (Algorithm 2 + Eq. (3)) to
+||r|| <= 1e-8 ||b||: every kernel of the hot path (setup, fused vector
+update + <r,r>, fused SpMV + <p,Ap>, <Ap,Ap>, the device-side second-stage
+reductions and scalar recurrences, status polling) over one batch of
+synthetic input already resident in HBM.
+
+value = CG iterations per second over the K timed steps.  The roofline
+entry is for the dominant kernel, the fused SpMV + two dots: algorithmic
+bytes per launch (12 nnz + 20 N + 4: values, column indices, row pointers,
+one read of p, one write of Ap) over its average duration, measured with HIP
+events on the solver's stream that the device stamps at the start and end of
+each launch, in a second pass over the same K steps (the events cost wall
+time, so the timed pass runs without them).  The CPU baseline is
+the plain FP64 oracle (the same pipelined recurrence) timed on the host.
+
+    python bench.py [--steps K] [--warmup W] [--gpus 1]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import re
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+PEAK_HBM_GBS = 8000.0
+WORKLOAD = "poisson3d_128"
+RTOL = 1e-8
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def spmv_dot_bytes(n: int, nnz: int) -> int:
+    """Compulsory bytes of one fused SpMV + 2 dots launch (FP64 values, int32 indices)."""
+    return 12 * nnz + 4 * (n + 1) + 8 * n + 8 * n
+
+
+def update_bytes(n: int) -> int:
+    """x, r, p, Ap read; x, r, p written."""
+    return 56 * n
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for f in ("fk_kernels.hip", "fk_internal.hpp"):
+        with open(os.path.join(ROOT, "paper_1410_4054_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel: str, workload: str):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, or
+    None when there is none or the kernel sources changed since."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{kernel}_{workload}.md")
+    if not os.path.exists(path):
+        return None
+    text = open(path).read()
+    m_hash = re.search(r"kernel_source_hash:\s*([0-9a-f]+)", text)
+    m_bytes = re.search(r"traffic_bytes_per_launch:\s*([0-9.eE+]+)", text)
+    if not m_hash or not m_bytes or m_hash.group(1) != kernel_source_hash():
+        return None
+    return float(m_bytes.group(1))
+
+
+def time_solves(torch, S, bd, xd, steps):
+    its = 0
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        xd.zero_()
+        S.solve(bd, xd)
+        its += S.iterations()
+    torch.cuda.synchronize()
+    return time.perf_counter() - t0, its
+
+
+def copy_bandwidth(torch, fk, nbytes=1 << 30, reps=10):
+    src = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    dst = torch.empty_like(src)
+    fk.copy(dst, src, nbytes)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        fk.copy(dst, src, nbytes)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del src, dst
+    return 2 * nbytes / (ms * 1e-3) / 1e9
+
+
+def cpu_baseline(A, b, budget_iters):
+    """Time the oracle (pipelined CG, as it stands) on the host for a bounded
+    number of iterations of the same workload."""
+    import oracle
+
+    oracle.default()  # load outside the timed region
+    t0 = time.perf_counter()
+    res = oracle.solve(A, b, method="cg_pipelined", rtol=0.0, max_iter=budget_iters)
+    dt = time.perf_counter() - t0
+    return res.k / dt, dt, res.k
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true")
+    ap.add_argument("--cpu-iters", type=int, default=200,
+                    help="iterations of the oracle timed for the CPU baseline")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(how it would shard is described in DESIGN.md). Run with --gpus 1.",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_1410_4054_amd import fk, problems as P
+
+    assert torch.cuda.is_available(), "bench.py needs a HIP device"
+    torch.cuda.set_device(0)
+    A, b, _ = P.workload(WORKLOAD)
+    n, nnz = A.n, A.nnz
+    M = fk.Matrix(A)
+    bd = torch.as_tensor(b, device="cuda")
+    xd = torch.zeros_like(bd)
+
+    # Timed steps: K full solves, inputs resident in HBM.
+    S = fk.Solver(M, method="cg_pipelined", rtol=RTOL, record_history=False)
+    for _ in range(args.warmup):
+        xd.zero_()
+        S.solve(bd, xd)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    its = 0
+    for _ in range(args.steps):
+        xd.zero_()
+        st = S.solve(bd, xd)
+        its += S.iterations()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    k_final = S.iterations()
+    rel = S.residual()
+    assert st == fk.OK, f"solve did not converge (status {st})"
+    S.close()
+    ms_per_step = dt / args.steps * 1e3
+    value = its / dt
+
+    # The same K steps again with every kernel carrying HIP start/stop events
+    # that the device stamps when the kernel itself begins and ends
+    # (FK_FLAG_PROFILE); the wall clock of this pass is not used.
+    S = fk.Solver(M, method="cg_pipelined", rtol=RTOL, record_history=False, profile=True)
+    xd.zero_()
+    S.solve(bd, xd)
+    kernel_us = {k: [0.0, 0] for k in fk.KERNEL_KINDS}
+    for _ in range(args.steps):
+        xd.zero_()
+        S.solve(bd, xd)
+        for kind, (us, cnt) in S.kernel_times().items():
+            kernel_us[kind][0] += us * cnt
+            kernel_us[kind][1] += cnt
+    S.close()
+
+    spmv_us = kernel_us["spmv_dot"][0] / max(kernel_us["spmv_dot"][1], 1)
+    upd_us = kernel_us["update_dot"][0] / max(kernel_us["update_dot"][1], 1)
+    spmv_b = spmv_dot_bytes(n, nnz)
+    achieved = spmv_b / (spmv_us * 1e-6) / 1e9
+    traffic = measured_traffic("spmv_dot", WORKLOAD)
+
+    extras = {}
+    if not args.no_extras:
+        # The paper's protocol: median of 10 runs of exactly 30 iterations.
+        for method in ("cg_pipelined", "cg_classical"):
+            S = fk.Solver(M, method=method, rtol=0.0, max_iter=30, record_history=False)
+            times = []
+            for _ in range(11):
+                xd.zero_()
+                torch.cuda.synchronize()
+                t = time.perf_counter()
+                S.solve(bd, xd)
+                torch.cuda.synchronize()
+                times.append(time.perf_counter() - t)
+            S.close()
+            extras[f"{method}_us_per_iter_30fixed_median10"] = float(np.median(times[1:])) / 30 * 1e6
+        extras["pipelined_vs_classical_speedup_30fixed"] = (
+            extras["cg_classical_us_per_iter_30fixed_median10"]
+            / extras["cg_pipelined_us_per_iter_30fixed_median10"])
+        extras["spmv_dot_us"] = spmv_us
+        extras["update_dot_us"] = upd_us
+        extras["update_dot_GBps"] = update_bytes(n) / (upd_us * 1e-6) / 1e9
+        per_it_bytes = spmv_b + update_bytes(n)
+        extras["iteration_algorithmic_bytes"] = per_it_bytes
+        extras["iteration_GBps"] = per_it_bytes * value / 1e9
+        extras["iteration_frac_of_peak"] = per_it_bytes * value / 1e9 / PEAK_HBM_GBS
+        extras["copy_kernel_GBps_1GiB"] = copy_bandwidth(torch, fk)
+
+        # Nonsymmetric workload: pipelined BiCGStab on 1024^2 convection-diffusion.
+        A3, b3, _ = P.workload("convdiff2d_1024")
+        M3 = fk.Matrix(A3)
+        b3d = torch.as_tensor(b3, device="cuda")
+        x3d = torch.zeros_like(b3d)
+        S3 = fk.Solver(M3, method="bicgstab_pipelined", rtol=RTOL, record_history=False)
+        x3d.zero_(); S3.solve(b3d, x3d)
+        t3, its3 = time_solves(torch, S3, b3d, x3d, 2)
+        extras["bicgstab_convdiff2d_1024_iters_per_s"] = its3 / t3
+        extras["bicgstab_convdiff2d_1024_k"] = S3.iterations()
+        S3.close(); M3.close()
+
+        # Latency-bound workload: 2D Poisson 32x32.
+        A1, b1, _ = P.workload("poisson2d_32")
+        M1 = fk.Matrix(A1)
+        b1d = torch.as_tensor(b1, device="cuda")
+        x1d = torch.zeros_like(b1d)
+        for graph in (False, True):
+            S1 = fk.Solver(M1, method="cg_pipelined", rtol=RTOL, record_history=False, graph=graph)
+            x1d.zero_(); S1.solve(b1d, x1d)
+            t1, its1 = time_solves(torch, S1, b1d, x1d, 20)
+            extras[f"cg_poisson2d_32_{'graph' if graph else 'stream'}_iters_per_s"] = its1 / t1
+            extras[f"cg_poisson2d_32_{'graph' if graph else 'stream'}_solves_per_s"] = 20 / t1
+            S1.close()
+        M1.close()
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        ips, secs, kk = cpu_baseline(A, b, args.cpu_iters)
+        cpu = {"value": ips, "unit": "iterations/s", "cores": 1, "kind": "oracle",
+               "sample": f"{kk} iterations of the oracle's pipelined CG (rtol=0) on {WORKLOAD}, "
+                         f"{secs:.1f} s on one host core"}
+
+    out = {
+        "metric": "CG iterations/s + achieved HBM GB/s; batched solves/s at rel. residual 1e-8",
+        "value": value,
+        "unit": "iterations/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "strong",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "3D 7-point Poisson 128^3, pipelined CG to rel. residual 1e-8",
+                   "n": n, "nnz": nnz, "method": "cg_pipelined", "rtol": RTOL,
+                   "iterations_per_solve": k_final, "final_rel_residual": rel},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                     "frac": achieved / PEAK_HBM_GBS, "traffic": traffic,
+                     "kernel": "fused SpMV + <p,Ap>, <Ap,Ap> (k_csr_rows<0,3>)",
+                     "bytes_per_launch": spmv_b, "avg_us": spmv_us,
+                     "update_dot_avg_us": upd_us},
+        "cpu_baseline": cpu,
+        "extra": extras,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -103,7 +103,7 @@ static int spmv_grid(int nblocks)
 
 static int vec_grid(int64_t n)
 {
-    static const int gmax = env_int("FK_VEC_GRID", 2048, 1, GMAX);
+    static const int gmax = env_int("FK_VEC_GRID", 1024, 1, GMAX);
     int64_t g = (n + WG - 1) / WG;
     g = std::min<int64_t>(g, gmax);
     return (int)std::max<int64_t>(g, 1);
@@ -498,13 +498,11 @@ struct Enq {
                 return er;
             pool.push_back(e);
         }
-        hipError_t e = hipEventRecord(pool[slot], S->stream);
-        if (e != hipSuccess)
-            return e;
-        e = launch();
-        if (e != hipSuccess)
-            return e;
-        e = hipEventRecord(pool[slot + 1], S->stream);
+        // The events are stamped by the device at the start and end of the
+        // kernel itself (not around its dispatch).
+        set_launch_timing(pool[slot], pool[slot + 1]);
+        hipError_t e = launch();
+        set_launch_timing(nullptr, nullptr);
         if (e != hipSuccess)
             return e;
         S->prof_batch[batch].push_back(TimedLaunch{kind, slot});

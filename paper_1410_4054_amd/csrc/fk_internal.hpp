@@ -112,6 +112,12 @@ enum DotBits : int32_t {
     D_YW = 4,  // <y, w>
 };
 
+// Profiling: when set, the next kernel launched by a wrapper below carries
+// these two HIP events, stamped by the device when that kernel itself starts
+// and ends (hipExtLaunchKernel), so the measured time is the kernel's own
+// duration.  Cleared by that launch.
+void set_launch_timing(hipEvent_t start, hipEvent_t stop);
+
 // Host-side launch wrappers (fk_kernels.hip).
 hipError_t launch_spmv_dots(const DevCsr &A, const double *v, double *y, const double *w,
                             int dots, const RedArgs &red, int grid, hipStream_t s);

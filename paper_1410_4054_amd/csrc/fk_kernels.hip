@@ -31,9 +31,21 @@
 // is extracted.
 #include "fk_internal.hpp"
 
+#include <hip/hip_ext.h>
+
 // Minimum waves per SIMD the product kernels are compiled for (caps VGPRs).
 #ifndef FK_SPMV_MIN_WAVES
 #define FK_SPMV_MIN_WAVES 8
+#endif
+// Stream the CSR values and column indices with non-temporal loads (they
+// are read once per product; keeping them out of the caches leaves room for
+// the vectors that are read again).
+#ifndef FK_NT_CSR
+#define FK_NT_CSR 0
+#endif
+// Unroll factor of the grid-stride loops of the vector-update kernels.
+#ifndef FK_VEC_UNROLL
+#define FK_VEC_UNROLL 1
 #endif
 
 namespace fk {
@@ -141,6 +153,15 @@ __device__ __forceinline__ void store_coherent(double *p, double v)
 __device__ __forceinline__ double load_coherent(const double *p)
 {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+template <typename T>
+__device__ __forceinline__ T load_stream(const T *p)
+{
+    if constexpr (FK_NT_CSR != 0)
+        return __builtin_nontemporal_load(p);
+    else
+        return *p;
 }
 
 __device__ __forceinline__ bool runs(const RedArgs &red)
@@ -583,8 +604,8 @@ __global__ __launch_bounds__(WG, FK_SPMV_MIN_WAVES) void k_csr_rows(DevCsr A, Ro
             for (int i = 0; i < ITEMS; ++i) {
                 const int e = tid + i * WG;
                 if (e < nz) {
-                    ci[i] = col[j0 + e];
-                    va[i] = vals[j0 + e];
+                    ci[i] = load_stream(col + j0 + e);
+                    va[i] = load_stream(vals + j0 + e);
                 }
             }
 #pragma unroll
@@ -639,6 +660,7 @@ __global__ __launch_bounds__(WG) void k_cg_update(int64_t n, double *__restrict_
     const double beta = red.st->beta;
     dd acc[1] = {dd{0.0, 0.0}};
     const int64_t stride = (int64_t)gridDim.x * WG;
+#pragma unroll FK_VEC_UNROLL
     for (int64_t i = (int64_t)blockIdx.x * WG + threadIdx.x; i < n; i += stride) {
         const double pi = p[i];
         x[i] = x[i] + alpha * pi;
@@ -814,105 +836,120 @@ __global__ void k_copy_tail(char *__restrict__ dst, const char *__restrict__ src
         dst[i] = src[i];
 }
 
+thread_local hipEvent_t t_start = nullptr;
+thread_local hipEvent_t t_stop = nullptr;
+
+template <typename... KArgs, typename... Args>
+hipError_t launch(void (*kernel)(KArgs...), int grid, int block, hipStream_t s, Args... args)
+{
+    if (t_start) {
+        hipEvent_t a = t_start, b = t_stop;
+        t_start = t_stop = nullptr;
+        hipExtLaunchKernelGGL(kernel, dim3(grid), dim3(block), 0, s, a, b, 0,
+                              static_cast<KArgs>(args)...);
+    } else {
+        hipLaunchKernelGGL(kernel, dim3(grid), dim3(block), 0, s, static_cast<KArgs>(args)...);
+    }
+    return hipGetLastError();
+}
+
 }  // namespace
 
 // ------------------------------------------------------ launch wrappers
+
+void set_launch_timing(hipEvent_t start, hipEvent_t stop)
+{
+    t_start = start;
+    t_stop = stop;
+}
 
 hipError_t launch_spmv_dots(const DevCsr &A, const double *v, double *y, const double *w,
                             int dots, const RedArgs &red, int grid, hipStream_t s)
 {
     RowIo io{v, y, w, nullptr, nullptr};
     switch (dots) {
-    case 0: k_csr_rows<ROW_SPMV, 0><<<grid, WG, 0, s>>>(A, io, red); break;
-    case D_YV | D_YY: k_csr_rows<ROW_SPMV, D_YV | D_YY><<<grid, WG, 0, s>>>(A, io, red); break;
-    case D_YW: k_csr_rows<ROW_SPMV, D_YW><<<grid, WG, 0, s>>>(A, io, red); break;
-    case D_YV | D_YY | D_YW: k_csr_rows<ROW_SPMV, D_YV | D_YY | D_YW><<<grid, WG, 0, s>>>(A, io, red); break;
+    case 0: return launch(k_csr_rows<ROW_SPMV, 0>, grid, WG, s, A, io, red);
+    case D_YV | D_YY: return launch(k_csr_rows<ROW_SPMV, D_YV | D_YY>, grid, WG, s, A, io, red);
+    case D_YW: return launch(k_csr_rows<ROW_SPMV, D_YW>, grid, WG, s, A, io, red);
+    case D_YV | D_YY | D_YW: return launch(k_csr_rows<ROW_SPMV, D_YV | D_YY | D_YW>, grid, WG, s, A, io, red);
     default: return hipErrorInvalidValue;
     }
-    return hipGetLastError();
 }
 
 hipError_t launch_residual0(const DevCsr &A, const double *b, const double *x, double *r,
                             double *p, double *rs, const RedArgs &red, int grid, hipStream_t s)
 {
     RowIo io{x, r, b, p, rs};
-    k_csr_rows<ROW_RESID, 0><<<grid, WG, 0, s>>>(A, io, red);
-    return hipGetLastError();
+    return launch(k_csr_rows<ROW_RESID, 0>, grid, WG, s, A, io, red);
 }
 
 hipError_t launch_cg_update(int64_t n, double *x, double *r, double *p, const double *ap,
                             const RedArgs &red, int grid, hipStream_t s)
 {
-    k_cg_update<<<grid, WG, 0, s>>>(n, x, r, p, ap, red);
-    return hipGetLastError();
+    return launch(k_cg_update, grid, WG, s, n, x, r, p, ap, red);
 }
 
 hipError_t launch_bicg_s(int64_t n, const double *r, const double *ap, double *sv,
                          const RedArgs &red, int grid, hipStream_t s)
 {
-    k_bicg_s<<<grid, WG, 0, s>>>(n, r, ap, sv, red);
-    return hipGetLastError();
+    return launch(k_bicg_s, grid, WG, s, n, r, ap, sv, red);
 }
 
 hipError_t launch_bicg_xrp(int64_t n, double *x, double *r, double *p, const double *sv,
                            const double *as, const double *ap, const double *rs,
                            const RedArgs &red, int grid, hipStream_t s)
 {
-    k_bicg_xrp<<<grid, WG, 0, s>>>(n, x, r, p, sv, as, ap, rs, red);
-    return hipGetLastError();
+    return launch(k_bicg_xrp, grid, WG, s, n, x, r, p, sv, as, ap, rs, red);
 }
 
 hipError_t launch_dot(int64_t n, const double *a, const double *b, const double *c, int ndots,
                       const RedArgs &red, int grid, hipStream_t s)
 {
     if (ndots == 1)
-        k_dot<1><<<grid, WG, 0, s>>>(n, a, b, c, red);
-    else if (ndots == 2)
-        k_dot<2><<<grid, WG, 0, s>>>(n, a, b, c, red);
-    else
-        return hipErrorInvalidValue;
-    return hipGetLastError();
+        return launch(k_dot<1>, grid, WG, s, n, a, b, c, red);
+    if (ndots == 2)
+        return launch(k_dot<2>, grid, WG, s, n, a, b, c, red);
+    return hipErrorInvalidValue;
 }
 
 hipError_t launch_axpy(int64_t n, double *out, const double *y, const double *x, int which,
                        int negative, DevState *st, uint32_t run_mask, int grid, hipStream_t s)
 {
-    k_axpy<<<grid, WG, 0, s>>>(n, out, y, x, which, negative, st, run_mask);
-    return hipGetLastError();
+    return launch(k_axpy, grid, WG, s, n, out, y, x, which, negative, st, run_mask);
 }
 
 hipError_t launch_xpay(int64_t n, double *p, const double *r, const double *v, DevState *st,
                        uint32_t run_mask, int grid, hipStream_t s)
 {
-    k_xpay<<<grid, WG, 0, s>>>(n, p, r, v, st, run_mask);
-    return hipGetLastError();
+    return launch(k_xpay, grid, WG, s, n, p, r, v, st, run_mask);
 }
 
 hipError_t launch_copy_fin(int64_t n, double *dst, const double *src, const RedArgs &red,
                            hipStream_t s)
 {
-    k_copy_fin<<<1, WG, 0, s>>>(n, dst, src, red);
-    return hipGetLastError();
+    return launch(k_copy_fin, 1, WG, s, n, dst, src, red);
 }
 
 hipError_t launch_zero(double *x, int64_t n, DevState *st, uint32_t run_mask, int grid,
                        hipStream_t s)
 {
-    k_zero<<<grid, WG, 0, s>>>(x, n, st, run_mask);
-    return hipGetLastError();
+    return launch(k_zero, grid, WG, s, x, n, st, run_mask);
 }
 
 hipError_t launch_copy(void *dst, const void *src, int64_t n_bytes, int grid, hipStream_t s)
 {
     const int64_t n16 = n_bytes / 16;
-    if (n16 > 0)
-        k_copy16<<<grid, WG, 0, s>>>(reinterpret_cast<int4 *>(dst),
-                                     reinterpret_cast<const int4 *>(src), n16);
+    if (n16 > 0) {
+        hipError_t e = launch(k_copy16, grid, WG, s, reinterpret_cast<int4 *>(dst),
+                              reinterpret_cast<const int4 *>(src), n16);
+        if (e != hipSuccess)
+            return e;
+    }
     const int64_t tail = n_bytes - n16 * 16;
     if (tail > 0)
-        k_copy_tail<<<1, 64, 0, s>>>(reinterpret_cast<char *>(dst) + n16 * 16,
-                                     reinterpret_cast<const char *>(src) + n16 * 16, tail);
-    return hipGetLastError();
+        return launch(k_copy_tail, 1, 64, s, reinterpret_cast<char *>(dst) + n16 * 16,
+                      reinterpret_cast<const char *>(src) + n16 * 16, tail);
+    return hipSuccess;
 }
 
 }  // namespace fk

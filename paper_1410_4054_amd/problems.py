@@ -74,14 +74,14 @@ def _stencil(shape: tuple[int, ...], diag: float, offdiag: dict[tuple[int, ...],
     """
     dims = len(shape)
     n = int(np.prod(shape))
-    coords = np.indices(shape[::-1]).reshape(dims, -1)[::-1]  # coords[0] = x index
+    coords = np.indices(shape[::-1], dtype=np.int32).reshape(dims, -1)[::-1]  # coords[0] = x
     strides = [1]
     for s in shape[:-1]:
         strides.append(strides[-1] * s)
     idx = np.arange(n, dtype=np.int64)
-    rows = [idx]
-    cols = [idx]
-    vals = [np.full(n, diag)]
+    # (column shift, coefficient, valid rows) per stencil entry; entries are
+    # placed in ascending shift order, so columns come out sorted per row.
+    entries = [(0, diag, None)]
     for off, coef in offdiag.items():
         ok = np.ones(n, dtype=bool)
         shift = 0
@@ -89,10 +89,29 @@ def _stencil(shape: tuple[int, ...], diag: float, offdiag: dict[tuple[int, ...],
             c = coords[d] + off[d]
             ok &= (c >= 0) & (c < shape[d])
             shift += off[d] * strides[d]
-        rows.append(idx[ok])
-        cols.append(idx[ok] + shift)
-        vals.append(np.full(int(ok.sum()), coef))
-    return _from_coo(n, np.concatenate(rows), np.concatenate(cols), np.concatenate(vals))
+        entries.append((shift, coef, ok))
+    entries.sort(key=lambda e: e[0])
+    counts = np.zeros(n, dtype=np.int64)
+    for _, _, ok in entries:
+        counts += 1 if ok is None else ok
+    row_ptr = np.zeros(n + 1, dtype=np.int64)
+    np.cumsum(counts, out=row_ptr[1:])
+    nnz = int(row_ptr[-1])
+    if nnz > np.iinfo(np.int32).max:
+        raise ValueError("nnz does not fit int32")
+    col = np.empty(nnz, dtype=np.int32)
+    val = np.empty(nnz, dtype=np.float64)
+    pos = row_ptr[:-1].copy()
+    for shift, coef, ok in entries:
+        rows = idx if ok is None else idx[ok]
+        at = pos if ok is None else pos[ok]
+        col[at] = rows + shift
+        val[at] = coef
+        if ok is None:
+            pos += 1
+        else:
+            pos[ok] += 1
+    return Csr(n=n, row_ptr=row_ptr.astype(np.int32), col_idx=col, vals=val)
 
 
 def poisson2d(n: int, diag_shift: np.ndarray | float | None = None) -> Csr:
