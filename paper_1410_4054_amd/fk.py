@@ -229,9 +229,15 @@ class Solver:
     def __init__(self, A: Matrix, method: str = "cg_pipelined", rtol: float = 1e-8,
                  max_iter: int | None = None, record_history: bool = True, unroll: int = 32,
                  graph: bool = False, profile: bool = False, stream=None):
+        import torch
+
         self.A = A
         if max_iter is None:
             max_iter = min(10 * A.n, 2**31 - 2)
+        if graph and stream is None:
+            # Stream capture needs a stream other than the legacy default one.
+            stream = torch.cuda.Stream()
+        self.stream = stream
         flags = (FLAG_GRAPH if graph else 0) | (FLAG_PROFILE if profile else 0)
         o = _Opts(METHODS[method], float(rtol), int(max_iter), int(bool(record_history)),
                   int(unroll), flags)
@@ -246,6 +252,11 @@ class Solver:
 
     def solve(self, b, x) -> int:
         """Run fk_solve; returns the fk_status (OK, NOT_CONVERGED or BREAKDOWN)."""
+        if self.stream is not None:
+            import torch
+
+            # b and x were produced on the caller's stream.
+            self.stream.wait_stream(torch.cuda.current_stream())
         st = lib().fk_solve(self._h, _dev_f64(b, self.A.n, "b"), _dev_f64(x, self.A.n, "x"))
         return _check(st, "fk_solve", allowed=(OK, NOT_CONVERGED, BREAKDOWN))
 

@@ -1,0 +1,54 @@
+"""The benchmark workloads at full size, in the benchmark's launch
+configuration, against values stored by tests/golden/make_golden.py (CPU
+oracle only): iteration count, the whole residual history, the iterate at
+4099 sampled rows and its norm, and the true residual of the GPU iterate
+computed by the oracle's product."""
+import numpy as np
+import pytest
+
+import oracle
+from golden.make_golden import load
+from gpu_util import gpu_solve
+from paper_1410_4054_amd import problems as P
+
+pytestmark = pytest.mark.gpu
+
+NAMES = ["poisson3d_128_cg_pipelined", "poisson3d_128_cg_classical",
+         "poisson3d_128_cg_pipelined_30", "convdiff2d_1024_bicgstab_pipelined",
+         "convdiff2d_1024_bicgstab_pipelined_30"]
+_inputs = {}
+
+
+def inputs(workload):
+    if workload not in _inputs:
+        _inputs.clear()
+        _inputs[workload] = P.workload(workload)
+    return _inputs[workload]
+
+
+@pytest.mark.parametrize("name", NAMES)
+def test_full_size_against_oracle(name, device):
+    g = load(name)
+    A, b, x0 = inputs(g["workload"])
+    print(f"\n[case] {name} n={A.n} nnz={A.nnz}", flush=True)
+    res, x = gpu_solve(A, b, x0, method=g["method"], rtol=g["rtol"], max_iter=g["max_iter"])
+    hist = np.array([float.fromhex(h) for h in g["history_hex"]])
+    assert res.status == g["status"] and res.k == g["k"], (res.status, res.k, g["k"])
+    np.testing.assert_allclose(res.history, hist, rtol=1e-13, atol=0)
+    idx = np.array(g["x_index"])
+    xs = np.array([float.fromhex(h) for h in g["x_sample_hex"]])
+    scale = np.abs(xs).max()
+    assert np.abs(x[idx] - xs).max() <= 1e-10 * scale
+    assert abs(np.linalg.norm(x) / g["x_norm"] - 1.0) <= 1e-10
+    if g["status"] == "converged":
+        assert oracle.true_residual(A, b, x) <= g["rtol"] * 1.5
+
+
+def test_config1_full_solve(device):
+    """2D Poisson 32x32 with b from seed 0: the oracle runs live."""
+    A, b, x0 = P.workload("poisson2d_32")
+    ref = oracle.solve(A, b, method="cg_pipelined", rtol=1e-8)
+    res, x = gpu_solve(A, b, method="cg_pipelined", rtol=1e-8)
+    assert res.k == ref.k == 101
+    assert np.array_equal(res.history, ref.hist)
+    assert np.abs(x - ref.x).max() <= 1e-10 * np.abs(ref.x).max()

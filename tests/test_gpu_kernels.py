@@ -1,0 +1,121 @@
+"""Kernel-level parity through the C ABI: the fused CSR product and its
+first-stage reductions, the device dot, the copy kernel.  The oracle sums
+each row left to right, as the HIP kernels do for rows of at most
+FK_LONG_ROW nonzeros, so those rows must agree bit for bit; inner products
+are rounded once from an (almost) exact sum on both sides."""
+import numpy as np
+import pytest
+
+import oracle
+from gpu_util import dev, host
+from paper_1410_4054_amd import fk, problems as P
+
+pytestmark = pytest.mark.gpu
+
+
+def check_spmv(A, seed=0, device=None):
+    rng = np.random.default_rng(seed)
+    p = rng.uniform(-1, 1, A.n)
+    M = fk.Matrix(A)
+    pd, qd = dev(p), dev(np.zeros(A.n))
+    dots = fk.spmv(M, pd, qd, dots=True)
+    q = host(qd)
+    ref = oracle.spmv(A, p)
+    short = np.diff(A.row_ptr) <= fk.LONG_ROW
+    assert np.array_equal(q[short], ref[short]), "row sums differ from CSR-order sums"
+    if (~short).any():
+        np.testing.assert_allclose(q[~short], ref[~short], rtol=1e-12, atol=1e-12)
+    assert dots[0] == oracle.dot(p, q)
+    assert dots[1] == oracle.dot(q, q)
+    # plain product (no reductions) gives the same vector
+    q2 = dev(np.full(A.n, np.nan))
+    fk.spmv(M, pd, q2)
+    assert np.array_equal(host(q2), q)
+    M.close()
+    return M
+
+
+@pytest.mark.parametrize("nnz_row", [4, 28])
+def test_spmv_random_columns(nnz_row, device):
+    """The fused SpMV+dot benchmark matrices: 4 and 28 uniformly random
+    nonzeros per row, with empty rows and rows longer than FK_LONG_ROW."""
+    A = P.random_csr(20000, nnz_row, seed=nnz_row, empty_rows=31,
+                     long_rows={3: 3000, 9000: 20000, 19999: 2049})
+    check_spmv(A, seed=nnz_row)
+
+
+@pytest.mark.parametrize("name", ["poisson2d_33", "poisson3d_17", "convdiff2d_50", "heat2d_40",
+                                  "poisson2d_32", "poisson3d_64"])
+def test_spmv_stencils(name, device):
+    A, _, _ = P.workload(name)
+    check_spmv(A, seed=1)
+
+
+@pytest.mark.parametrize("n", [1, 2, 255, 256, 257, 511, 513, 4097])
+def test_spmv_ragged_sizes(n, device):
+    """Sizes around the 256-row block and the 8-workgroup XCD split."""
+    check_spmv(P.random_csr(n, 5, seed=n), seed=n)
+
+
+def test_spmv_degenerate(device):
+    # all rows empty
+    A = P.Csr(5, np.zeros(6, np.int32), np.zeros(0, np.int32), np.zeros(0))
+    M = fk.Matrix(A)
+    qd = dev(np.full(5, 7.0))
+    d = fk.spmv(M, dev(np.ones(5)), qd, dots=True)
+    assert np.array_equal(host(qd), np.zeros(5)) and d == (0.0, 0.0)
+    # single row holding every nonzero, and rows at the long-row threshold
+    check_spmv(P.random_csr(1, 5000, seed=2))
+    check_spmv(P.random_csr(3, 1, seed=3, long_rows={0: fk.LONG_ROW, 1: fk.LONG_ROW + 1, 2: 1}))
+    blocks = fk.Matrix(P.random_csr(3, 1, seed=3, long_rows={0: fk.LONG_ROW, 1: fk.LONG_ROW + 1})).blocks()
+    assert blocks[1] == 1
+
+
+def test_spmv_full_size_128(device):
+    """The 128^3 workload at full size in the launch configuration the
+    benchmark uses: every row equal to the CSR-order sum."""
+    A, _, _ = P.workload("poisson3d_128")
+    check_spmv(A, seed=5)
+
+
+@pytest.mark.parametrize("n", [1, 7, 255, 256, 257, 1000, 123457, 2097152])
+def test_dot(n, device):
+    rng = np.random.default_rng(n)
+    a, b = rng.standard_normal(n), rng.uniform(-1, 1, n) * 1e3
+    assert fk.dot(dev(a), dev(b)) == oracle.dot(a, b)
+    assert fk.dot(dev(a), dev(a)) == oracle.dot(a, a)
+
+
+def test_dot_cancellation(device):
+    rng = np.random.default_rng(3)
+    a = rng.standard_normal(100000) * 1e6
+    b = rng.standard_normal(100000)
+    a2 = np.concatenate([a, -a, [1e-3]])
+    b2 = np.concatenate([b, b, [1.0]])
+    got = fk.dot(dev(a2), dev(b2))
+    assert got == oracle.dot(a2, b2)
+    assert abs(got - 1e-3) < 1e-12
+
+
+def test_reproducible(device):
+    A, _, _ = P.workload("poisson3d_32")
+    p = np.random.default_rng(0).uniform(-1, 1, A.n)
+    M = fk.Matrix(A)
+    outs = []
+    for _ in range(3):
+        qd = dev(np.zeros(A.n))
+        d = fk.spmv(M, dev(p), qd, dots=True)
+        outs.append((host(qd), d))
+    for q, d in outs[1:]:
+        assert np.array_equal(q, outs[0][0]) and d == outs[0][1]
+
+
+@pytest.mark.parametrize("nbytes", [1, 15, 16, 17, 4096, 1000003, 64 << 20])
+def test_copy(nbytes, device):
+    import torch
+
+    src = torch.randint(0, 255, (nbytes,), dtype=torch.uint8, device=device)
+    dst = torch.zeros_like(src)
+    fk.copy(dst, src, nbytes)
+    torch.cuda.synchronize()
+    assert torch.equal(dst, src)
