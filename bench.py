@@ -234,19 +234,33 @@ def main():
         extras["bicgstab_convdiff2d_1024_k"] = S3.iterations()
         S3.close(); M3.close()
 
-        # Latency-bound workload: 2D Poisson 32x32.
+        # Latency-bound workload: 2D Poisson 32x32 (N = 1,024): the
+        # single-workgroup solver (one launch per solve) against the grid
+        # kernels (two launches per iteration), pipelined CG and BiCGStab.
         A1, b1, _ = P.workload("poisson2d_32")
         M1 = fk.Matrix(A1)
         b1d = torch.as_tensor(b1, device="cuda")
         x1d = torch.zeros_like(b1d)
-        for graph in (False, True):
-            S1 = fk.Solver(M1, method="cg_pipelined", rtol=RTOL, record_history=False, graph=graph)
+        for label, kw in (("single_wg", {}), ("grid_stream", {"small": False}),
+                          ("grid_graph", {"small": False, "graph": True})):
+            S1 = fk.Solver(M1, method="cg_pipelined", rtol=RTOL, record_history=False, **kw)
             x1d.zero_(); S1.solve(b1d, x1d)
-            t1, its1 = time_solves(torch, S1, b1d, x1d, 20)
-            extras[f"cg_poisson2d_32_{'graph' if graph else 'stream'}_iters_per_s"] = its1 / t1
-            extras[f"cg_poisson2d_32_{'graph' if graph else 'stream'}_solves_per_s"] = 20 / t1
+            t1, its1 = time_solves(torch, S1, b1d, x1d, 50)
+            extras[f"cg_poisson2d_32_{label}_iters_per_s"] = its1 / t1
+            extras[f"cg_poisson2d_32_{label}_solves_per_s"] = 50 / t1
             S1.close()
+        A5, b5, _ = P.workload("convdiff2d_32")
+        M5 = fk.Matrix(A5)
+        b5d = torch.as_tensor(b5, device="cuda")
+        x5d = torch.zeros_like(b5d)
+        for label, kw in (("single_wg", {}), ("grid_stream", {"small": False})):
+            S5 = fk.Solver(M5, method="bicgstab_pipelined", rtol=RTOL, record_history=False, **kw)
+            x5d.zero_(); S5.solve(b5d, x5d)
+            t5, its5 = time_solves(torch, S5, b5d, x5d, 50)
+            extras[f"bicgstab_convdiff2d_32_{label}_iters_per_s"] = its5 / t5
+            S5.close()
         M1.close()
+        M5.close()
 
     cpu = None
     if not args.no_cpu_baseline:

@@ -78,7 +78,8 @@ typedef struct {
 
 /* flags */
 #define FK_FLAG_GRAPH 1      /* replay the enqueued iterations from a hipGraph */
-#define FK_FLAG_PROFILE 2    /* time every kernel with HIP events (slower)     */
+#define FK_FLAG_PROFILE 2    /* time every kernel with HIP events              */
+#define FK_FLAG_NO_SMALL 4   /* never use the single-workgroup solver           */
 
 enum { FK_PTR_HOST = 0, FK_PTR_DEVICE = 1 };
 
@@ -111,6 +112,12 @@ fk_status fk_csr_blocks(fk_csr A, int32_t *nblocks, int32_t *long_rows);
  * library-owned workspace (the method's work vectors, the per-workgroup
  * partial-sum buffer and the device scalars; about 3n doubles for CG and 6n
  * for BiCGStab) once, so fk_solve allocates nothing.
+ *
+ * Pipelined solves of small systems (n <= 8192 for CG, n <= 2048 for
+ * BiCGStab, nnz <= 65536, no row longer than FK_LONG_ROW, vectors fitting
+ * the device's LDS) run as one single-workgroup kernel per solve, whose
+ * iterates equal those of the multi-kernel path; FK_FLAG_NO_SMALL disables
+ * that.  fk_solver_uses_small() tells which path a solver takes.
  */
 fk_status fk_solver_create(fk_csr A, const fk_opts *o, void *hip_stream, fk_solver *out);
 
@@ -150,11 +157,15 @@ enum {
     FK_KERNEL_SPMV = 3,        /* plain CSR product (classical)               */
     FK_KERNEL_DOT = 4,         /* plain dot (classical)                        */
     FK_KERNEL_AXPY = 5,        /* plain vector update (classical)             */
-    FK_KERNEL_KINDS = 6
+    FK_KERNEL_SMALL = 6,       /* whole solve in one workgroup (small systems) */
+    FK_KERNEL_KINDS = 7
 };
 fk_status fk_get_kernel_times(fk_solver S, double *avg_us, int32_t *count, int32_t cap);
 
 fk_status fk_solver_destroy(fk_solver S);
+
+/* *small = 1 if fk_solve runs the single-workgroup solver, else 0. */
+fk_status fk_solver_uses_small(fk_solver S, int32_t *small);
 
 /*
  * q = A p with optional fused first-stage reductions (the fused kernel of

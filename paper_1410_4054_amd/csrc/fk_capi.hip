@@ -346,6 +346,8 @@ struct fk_solver_s {
     hipGraphExec_t graph_exec = nullptr;
     double *graph_x = nullptr;
     int graph_iters = 0;
+    bool small = false;        // whole solve in one single-workgroup launch
+    bool small_stage = false;  // ... with the matrix staged in LDS
 
     RedArgs red(int fin, uint32_t mask) const { return RedArgs{st, partials, hist, scal, fin, mask}; }
 };
@@ -386,6 +388,33 @@ static void solver_release(fk_solver S)
 
 static bool is_bicg(int m) { return m == FK_BICGSTAB_PIPELINED || m == FK_BICGSTAB_CLASSICAL; }
 
+static size_t max_lds_per_workgroup(int device)
+{
+    int lds = 0;
+    if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, device) != hipSuccess)
+        return 0;
+    return (size_t)lds;
+}
+
+// Static LDS of the single-workgroup kernels (state, reduction scratch) plus margin.
+constexpr size_t SMALL_STATIC_LDS = 4096;
+
+// The single-workgroup solver takes pipelined solves of systems whose
+// vectors fit one workgroup's registers and LDS and whose matrix is small
+// enough to be re-read from the caches every iteration.
+static bool small_path_ok(fk_csr A, const fk_opts &o)
+{
+    if (o.flags & FK_FLAG_NO_SMALL)
+        return false;
+    if (o.method != FK_CG_PIPELINED && o.method != FK_BICGSTAB_PIPELINED)
+        return false;
+    const bool bicg = o.method == FK_BICGSTAB_PIPELINED;
+    const int rpt = small_rows_per_thread(A->n);
+    if (rpt == 0 || (bicg && rpt > 2) || A->nnz > 65536 || A->long_rows > 0)
+        return false;
+    return small_lds_bytes(bicg, A->n) + SMALL_STATIC_LDS <= max_lds_per_workgroup(A->device);
+}
+
 extern "C" fk_status fk_solver_create(fk_csr A, const fk_opts *o, void *hip_stream, fk_solver *out)
 {
     if (!out)
@@ -401,7 +430,7 @@ extern "C" fk_status fk_solver_create(fk_csr A, const fk_opts *o, void *hip_stre
         return fail(FK_E_ARG, "max_iter < 0");
     if (o->unroll < 0 || o->unroll > 4096)
         return fail(FK_E_ARG, "unroll outside [0, 4096]");
-    if (o->flags & ~(FK_FLAG_GRAPH | FK_FLAG_PROFILE))
+    if (o->flags & ~(FK_FLAG_GRAPH | FK_FLAG_PROFILE | FK_FLAG_NO_SMALL))
         return fail(FK_E_ARG, "unknown flags 0x%x", o->flags);
 
     fk_solver S = new (std::nothrow) fk_solver_s;
@@ -455,6 +484,10 @@ extern "C" fk_status fk_solver_create(fk_csr A, const fk_opts *o, void *hip_stre
         S_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
     S_HIP(hipMemsetAsync(S->st, 0, sizeof(DevState), S->stream));
     S_HIP(hipMemsetAsync(S->partials, 0, RED_SCRATCH_DOUBLES * sizeof(double), S->stream));
+    S->small = small_path_ok(A, S->o);
+    S->small_stage = S->small &&
+                     small_staged_lds_bytes(o->method == FK_BICGSTAB_PIPELINED, A->n, A->nnz) +
+                             SMALL_STATIC_LDS <= max_lds_per_workgroup(A->device);
     S_HIP(hipStreamSynchronize(S->stream));
 #undef S_TRY
 #undef S_HIP
@@ -657,6 +690,8 @@ void harvest_profile(fk_solver S, int batch)
 
 }  // namespace
 
+static fk_status finish_solve(fk_solver S);
+
 extern "C" fk_status fk_solve(fk_solver S, const double *b, double *x)
 {
     if (!S || !b || !x)
@@ -678,6 +713,38 @@ extern "C" fk_status fk_solve(fk_solver S, const double *b, double *x)
     init.hist_cap = S->hist_cap;
     *S->h_init = init;
     HIP_TRY(hipMemcpyAsync(S->st, S->h_init, sizeof(DevState), hipMemcpyHostToDevice, S->stream));
+
+    if (S->small) {
+        const bool bicg = S->o.method == FK_BICGSTAB_PIPELINED;
+        std::vector<hipEvent_t> &pool = S->prof_ev[0];
+        if (profile) {
+            while (pool.size() < 2) {
+                hipEvent_t ev;
+                HIP_TRY(hipEventCreate(&ev));
+                pool.push_back(ev);
+            }
+            set_launch_timing(pool[0], pool[1]);
+        }
+        hipError_t es = launch_small(bicg, S->A->view(), b, x, S->st, S->hist, S->scal,
+                                     S->small_stage, S->stream);
+        set_launch_timing(nullptr, nullptr);
+        if (es != hipSuccess)
+            return fail(FK_E_HIP, "single-workgroup solve: %s", hipGetErrorString(es));
+        HIP_TRY(hipMemcpyAsync(&S->last, S->st, sizeof(DevState), hipMemcpyDeviceToHost, S->stream));
+        HIP_TRY(hipStreamSynchronize(S->stream));
+        if (profile) {
+            float ms = 0.f;
+            if (hipEventElapsedTime(&ms, pool[0], pool[1]) == hipSuccess) {
+                S->prof_us[FK_KERNEL_SMALL] = 1000.0 * (double)ms;
+                S->prof_n[FK_KERNEL_SMALL] = 1;
+            }
+        }
+        if (S->last.status == ST_ZERO_RHS) {
+            HIP_TRY(hipMemsetAsync(x, 0, (size_t)S->n * sizeof(double), S->stream));
+            HIP_TRY(hipStreamSynchronize(S->stream));
+        }
+        return finish_solve(S);
+    }
 
     const int64_t max_iter = S->o.max_iter;
     const int U = S->o.unroll;
@@ -735,6 +802,12 @@ extern "C" fk_status fk_solve(fk_solver S, const double *b, double *x)
     HIP_TRY(hipMemcpyAsync(S->h_init, S->st, sizeof(DevState), hipMemcpyDeviceToHost, S->stream));
     HIP_TRY(hipStreamSynchronize(S->stream));
     S->last = *S->h_init;
+    return finish_solve(S);
+}
+
+// Map the final device state to the returned status.
+static fk_status finish_solve(fk_solver S)
+{
     S->solved = true;
     switch (S->last.status) {
     case ST_CONVERGED:
@@ -754,6 +827,14 @@ extern "C" fk_status fk_solve(fk_solver S, const double *b, double *x)
         fail(FK_NOT_CONVERGED, "not converged after %d iterations (rel. residual %.3e)", S->last.it,
              S->last.last_rel);
     return S->last_status;
+}
+
+extern "C" fk_status fk_solver_uses_small(fk_solver S, int32_t *small)
+{
+    if (!S || !small)
+        return fail(FK_E_ARG, "NULL argument");
+    *small = S->small ? 1 : 0;
+    return FK_OK;
 }
 
 extern "C" fk_status fk_get_iterations(fk_solver S, int32_t *k)

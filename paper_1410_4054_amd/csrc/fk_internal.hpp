@@ -144,6 +144,15 @@ hipError_t launch_xpay(int64_t n, double *p, const double *r, const double *v,
 hipError_t launch_copy_fin(int64_t n, double *dst, const double *src, const RedArgs &red,
                            hipStream_t s);
 hipError_t launch_copy(void *dst, const void *src, int64_t n_bytes, int grid, hipStream_t s);
+
+// Single-workgroup solver (whole solve in one launch) for small systems.
+// Rows per thread: 1, 2, 4 or 8 (0 = too large); LDS bytes it needs.
+// `stage`: copy the matrix into LDS first (needs small_staged_lds_bytes).
+int small_rows_per_thread(int64_t n);
+size_t small_lds_bytes(int method_bicg, int64_t n);
+size_t small_staged_lds_bytes(int method_bicg, int64_t n, int64_t nnz);
+hipError_t launch_small(int method_bicg, const DevCsr &A, const double *b, double *x, DevState *st,
+                        double *hist, double *scal, bool stage, hipStream_t s);
 hipError_t launch_zero(double *x, int64_t n, DevState *st, uint32_t run_mask, int grid,
                        hipStream_t s);
 

@@ -100,7 +100,7 @@ __device__ __forceinline__ dd wave_reduce(dd v)
 // Sum K double-double values over the workgroup; the result is valid in
 // thread 0.  Ends with every thread past a barrier that follows the last
 // LDS read, so `lds` may be reused right away.
-template <int K>
+template <int K, int NW = WAVES>
 __device__ __forceinline__ void block_reduce(dd (&v)[K], dd (*lds)[KMAX])
 {
     const int lane = threadIdx.x & 63;
@@ -118,7 +118,7 @@ __device__ __forceinline__ void block_reduce(dd (&v)[K], dd (*lds)[KMAX])
 #pragma unroll
         for (int k = 0; k < K; ++k) {
             dd a = lds[0][k];
-            for (int w = 1; w < WAVES; ++w)
+            for (int w = 1; w < NW; ++w)
                 a = dd_add(a, lds[w][k]);
             v[k] = a;
         }
@@ -184,26 +184,25 @@ __device__ __forceinline__ int logical_wg()
 
 // ------------------------------------------------------------- finalize
 
-__device__ __forceinline__ void put_hist(const RedArgs &red, int it, double v)
+__device__ __forceinline__ void put_hist(const DevState *st, double *hist, int it, double v)
 {
-    if (red.hist && it < red.st->hist_cap)
-        red.hist[it] = v;
+    if (hist && it < st->hist_cap)
+        hist[it] = v;
 }
 
-__device__ __forceinline__ void put_scal(const RedArgs &red, int it, int slot, double v)
+__device__ __forceinline__ void put_scal(const DevState *st, double *scal, int it, int slot, double v)
 {
-    if (red.scal && it < red.st->hist_cap)
-        red.scal[4 * it + slot] = v;
+    if (scal && it < st->hist_cap)
+        scal[4 * it + slot] = v;
 }
 
 // Scalar work of a reduction point (one thread).  The expressions and their
 // order follow Algorithms 1-4 exactly; see the comments per case.
-__device__ void finalize(const RedArgs &red, const double *d, int K)
+__device__ void finalize(DevState *st, int fin, const double *d, int K, double *hist, double *scal)
 {
-    DevState *st = red.st;
     for (int k = 0; k < K; ++k)
         st->dots[k] = d[k];
-    switch (red.fin) {
+    switch (fin) {
     case FIN_NONE:
         break;
     case FIN_SETUP: {  // d = {<r0,r0>, <b,b>}
@@ -215,7 +214,7 @@ __device__ void finalize(const RedArgs &red, const double *d, int K)
             st->bnorm = 0.0;
             st->tol = 0.0;
             st->last_rel = 0.0;
-            put_hist(red, 0, 0.0);
+            put_hist(st, hist, 0, 0.0);
             st->status = ST_ZERO_RHS;
             break;
         }
@@ -224,7 +223,7 @@ __device__ void finalize(const RedArgs &red, const double *d, int K)
         st->tol = st->rtol * bnorm;
         const double rel = sqrt(rr) / bnorm;
         st->last_rel = rel;
-        put_hist(red, 0, rel);
+        put_hist(st, hist, 0, rel);
         if (!isfinite(rr))
             st->status = ST_BREAKDOWN;
         else if (sqrt(rr) <= st->tol)
@@ -241,8 +240,8 @@ __device__ void finalize(const RedArgs &red, const double *d, int K)
         const double beta = alpha * alpha * apap / st->rr - 1.0;  // Eq. (3)
         st->alpha = alpha;
         st->beta = beta;
-        put_scal(red, st->it, 0, alpha);
-        put_scal(red, st->it, 1, beta);
+        put_scal(st, scal, st->it, 0, alpha);
+        put_scal(st, scal, st->it, 1, beta);
         if (st->it >= st->max_iter)
             st->status = ST_NOT_CONVERGED;
         break;
@@ -254,8 +253,8 @@ __device__ void finalize(const RedArgs &red, const double *d, int K)
         st->rr = rr;
         const double rel = sqrt(rr) / st->bnorm;
         st->last_rel = rel;
-        put_hist(red, it, rel);
-        put_scal(red, it - 1, 3, rr);
+        put_hist(st, hist, it, rel);
+        put_scal(st, scal, it - 1, 3, rr);
         if (!isfinite(rr))
             st->status = ST_BREAKDOWN;
         else if (sqrt(rr) <= st->tol)
@@ -272,7 +271,7 @@ __device__ void finalize(const RedArgs &red, const double *d, int K)
         }
         st->apr = apr;
         st->alpha = rho / apr;
-        put_scal(red, st->it, 0, st->alpha);
+        put_scal(st, scal, st->it, 0, st->alpha);
         break;
     }
     case FIN_B_SS: {  // d = {<s_i, s_i>}: half-step test
@@ -293,8 +292,8 @@ __device__ void finalize(const RedArgs &red, const double *d, int K)
         st->omega = omega;
         // <r_{i+1}, r_{i+1}> expanded in <s,s>, <s,As>, <As,As>
         st->rr_next = st->ss - 2.0 * omega * ass + omega * omega * asas;
-        put_scal(red, st->it, 1, beta);
-        put_scal(red, st->it, 2, omega);
+        put_scal(st, scal, st->it, 1, beta);
+        put_scal(st, scal, st->it, 2, omega);
         break;
     }
     case FIN_B_XRP: {  // Algorithm 4: d = {<r_{i+1}, r0*>, <r_{i+1}, r_{i+1}>}
@@ -303,8 +302,8 @@ __device__ void finalize(const RedArgs &red, const double *d, int K)
         if (st->status == ST_HALF) {
             const double rel = sqrt(st->ss) / st->bnorm;
             st->last_rel = rel;
-            put_hist(red, it, rel);
-            put_scal(red, it - 1, 3, st->ss);
+            put_hist(st, hist, it, rel);
+            put_scal(st, scal, it - 1, 3, st->ss);
             st->status = ST_CONVERGED;
             break;
         }
@@ -314,8 +313,8 @@ __device__ void finalize(const RedArgs &red, const double *d, int K)
         const double rnorm = sqrt(rr_next > 0.0 ? rr_next : 0.0);
         const double rel = rnorm / st->bnorm;
         st->last_rel = rel;
-        put_hist(red, it, rel);
-        put_scal(red, it - 1, 3, rr_next);
+        put_hist(st, hist, it, rel);
+        put_scal(st, scal, it - 1, 3, rr_next);
         if (!isfinite(rr_next))
             st->status = ST_BREAKDOWN;
         else if (rnorm <= st->tol)
@@ -333,7 +332,7 @@ __device__ void finalize(const RedArgs &red, const double *d, int K)
             break;
         }
         st->alpha = st->rr / pq;
-        put_scal(red, st->it, 0, st->alpha);
+        put_scal(st, scal, st->it, 0, st->alpha);
         break;
     }
     case FIN_C_CG_BETA: {  // Algorithm 1: d = {<r_{i+1}, r_{i+1}>}
@@ -342,8 +341,8 @@ __device__ void finalize(const RedArgs &red, const double *d, int K)
         st->it = it;
         const double rel = sqrt(rr_new) / st->bnorm;
         st->last_rel = rel;
-        put_hist(red, it, rel);
-        put_scal(red, it - 1, 3, rr_new);
+        put_hist(st, hist, it, rel);
+        put_scal(st, scal, it - 1, 3, rr_new);
         if (!isfinite(rr_new)) {
             st->status = ST_BREAKDOWN;
         } else if (sqrt(rr_new) <= st->tol) {
@@ -352,7 +351,7 @@ __device__ void finalize(const RedArgs &red, const double *d, int K)
             st->status = ST_NOT_CONVERGED;
         } else {
             st->beta = rr_new / st->rr;
-            put_scal(red, it - 1, 1, st->beta);
+            put_scal(st, scal, it - 1, 1, st->beta);
             st->rr = rr_new;
         }
         break;
@@ -364,7 +363,7 @@ __device__ void finalize(const RedArgs &red, const double *d, int K)
             break;
         }
         st->omega = ts / tt;
-        put_scal(red, st->it, 2, st->omega);
+        put_scal(st, scal, st->it, 2, st->omega);
         break;
     }
     case FIN_C_B_RR: {  // Algorithm 3: d = {<r_{i+1}, r_{i+1}>}
@@ -374,8 +373,8 @@ __device__ void finalize(const RedArgs &red, const double *d, int K)
         st->rr = rr;
         const double rel = sqrt(rr) / st->bnorm;
         st->last_rel = rel;
-        put_hist(red, it, rel);
-        put_scal(red, it - 1, 3, rr);
+        put_hist(st, hist, it, rel);
+        put_scal(st, scal, it - 1, 3, rr);
         if (!isfinite(rr))
             st->status = ST_BREAKDOWN;
         else if (sqrt(rr) <= st->tol)
@@ -389,7 +388,7 @@ __device__ void finalize(const RedArgs &red, const double *d, int K)
             break;
         }
         st->beta = (rho_new / st->rho) * (st->alpha / st->omega);
-        put_scal(red, st->it - 1, 1, st->beta);
+        put_scal(st, scal, st->it - 1, 1, st->beta);
         st->rho = rho_new;
         if (st->it >= st->max_iter)
             st->status = ST_NOT_CONVERGED;
@@ -400,8 +399,8 @@ __device__ void finalize(const RedArgs &red, const double *d, int K)
         st->it = it;
         const double rel = sqrt(st->ss) / st->bnorm;
         st->last_rel = rel;
-        put_hist(red, it, rel);
-        put_scal(red, it - 1, 3, st->ss);
+        put_hist(st, hist, it, rel);
+        put_scal(st, scal, it - 1, 3, st->ss);
         st->status = ST_CONVERGED;
         break;
     }
@@ -500,7 +499,7 @@ __device__ __forceinline__ void reduce_point(dd (&v)[K], const RedArgs &red, int
             d[k] = acc[k].hi + acc[k].lo;
         __hip_atomic_store(cnt + (size_t)RNGROUPS_MAX * CNT_STRIDE, 0u, __ATOMIC_RELAXED,
                            __HIP_MEMORY_SCOPE_AGENT);
-        finalize(red, d, K);
+        finalize(red.st, red.fin, d, K, red.hist, red.scal);
     }
 }
 
@@ -799,7 +798,7 @@ __global__ __launch_bounds__(WG) void k_copy_fin(int64_t n, double *__restrict__
     for (int64_t i = threadIdx.x; i < n; i += WG)
         dst[i] = src[i];
     if (threadIdx.x == 0)
-        finalize(red, nullptr, 0);
+        finalize(red.st, red.fin, nullptr, 0, red.hist, red.scal);
 }
 
 __global__ __launch_bounds__(WG) void k_zero(double *__restrict__ x, int64_t n,
@@ -810,6 +809,366 @@ __global__ __launch_bounds__(WG) void k_zero(double *__restrict__ x, int64_t n,
     const int64_t stride = (int64_t)gridDim.x * WG;
     for (int64_t i = (int64_t)blockIdx.x * WG + threadIdx.x; i < n; i += stride)
         x[i] = 0.0;
+}
+
+// ------------------------------------------- single-workgroup solver
+
+// A whole pipelined CG or BiCGStab solve in one workgroup of SWG threads,
+// for systems small enough that one CU holds them: the launch latency of the
+// multi-kernel iteration would dominate (Section 2.1's latency barrier), and
+// with one workgroup every global synchronisation of the iteration becomes a
+// workgroup barrier.  Thread t owns rows t, t + SWG, ... (RPT of them) and
+// keeps their vector entries in registers; the vectors the products gather
+// (p, and s for BiCGStab) live in LDS; the matrix is read from global memory
+// (it stays in the caches).  Rows are summed left to right and inner
+// products accumulated in double-double exactly as in the grid kernels, and
+// the scalar steps are the same `finalize` cases applied in the same order,
+// so the iterates are those of the multi-kernel path.  Because one
+// workgroup sees every partial at once, the inner products that the grid
+// path reduces at separate points are reduced together: one reduction per
+// CG iteration ({<r_i,r_i>, <p_i,Ap_i>, <Ap_i,Ap_i>}), two per BiCGStab
+// iteration.  The iteration count is bounded by max_iter.
+constexpr int SWG = 1024;
+constexpr int SWAVES = SWG / 64;
+
+// The matrix as the single-workgroup solver reads it: from LDS when it was
+// staged there at the start of the solve, else from global memory.
+struct SmallCsr {
+    const int32_t *rp;
+    const int32_t *ci;
+    const double *va;
+};
+
+__device__ __forceinline__ double row_sum(const SmallCsr &A, int i, const double *v)
+{
+    const int j0 = A.rp[i], j1 = A.rp[i + 1];
+    double q = 0.0;
+    for (int j = j0; j < j1; ++j)
+        q = q + A.va[j] * v[A.ci[j]];
+    return q;
+}
+
+// Bytes of LDS the matrix takes when staged: vals, col_idx, row_ptr.
+__host__ __device__ constexpr size_t small_csr_bytes(int64_t n, int64_t nnz)
+{
+    return (size_t)nnz * 12 + (size_t)(n + 1) * 4;
+}
+
+// Copy the matrix into LDS behind the vectors (8-byte aligned start).
+__device__ __forceinline__ SmallCsr stage_csr(const DevCsr &A, char *base)
+{
+    double *va = reinterpret_cast<double *>(base);
+    int32_t *ci = reinterpret_cast<int32_t *>(va + A.nnz);
+    int32_t *rp = ci + A.nnz;
+    for (int j = threadIdx.x; j < A.nnz; j += SWG) {
+        va[j] = A.vals[j];
+        ci[j] = A.col_idx[j];
+    }
+    for (int j = threadIdx.x; j <= A.n; j += SWG)
+        rp[j] = A.row_ptr[j];
+    return SmallCsr{rp, ci, va};
+}
+
+// Workgroup reduction of K double-doubles (each wave by shuffles, then the
+// 16 wave results by shuffles in wave 0, a fixed tree), followed by the
+// finalize steps fins[0..nf) on thread 0, each taking its slice of the
+// rounded sums and applied only while the solve is in state needs[f].  Ends
+// past a barrier, so every thread sees the updated state.
+template <int K>
+__device__ __forceinline__ void small_reduce(dd (&v)[K], dd (*lds)[KMAX], DevState &s,
+                                             const int *fins, const int *ks, const int *needs,
+                                             int nf, double *hist, double *scal)
+{
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int k = 0; k < K; ++k)
+        v[k] = wave_reduce(v[k]);
+    if (lane == 0) {
+#pragma unroll
+        for (int k = 0; k < K; ++k)
+            lds[wave][k] = v[k];
+    }
+    __syncthreads();
+    if (wave == 0) {
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            dd t = lane < SWAVES ? lds[lane][k] : dd{0.0, 0.0};
+            v[k] = wave_reduce(t);
+        }
+        if (lane == 0) {
+            double d[K];
+#pragma unroll
+            for (int k = 0; k < K; ++k)
+                d[k] = v[k].hi + v[k].lo;
+            int off = 0;
+            for (int f = 0; f < nf; ++f) {
+                if (s.status == needs[f])
+                    finalize(&s, fins[f], d + off, ks[f], hist, scal);
+                off += ks[f];
+            }
+        }
+    }
+    __syncthreads();
+}
+
+template <int RPT, bool STAGE>
+__global__ __launch_bounds__(SWG) void k_small_cg(DevCsr Ag, const double *__restrict__ b,
+                                                  double *__restrict__ x, DevState *gst,
+                                                  double *hist, double *scal)
+{
+    extern __shared__ double pv[];  // p (first x0) for the gathers, n entries; then the matrix
+    __shared__ DevState s;
+    __shared__ dd lds[SWAVES][KMAX];
+    const int tid = threadIdx.x;
+    const int n = Ag.n;
+    if (tid == 0)
+        s = *gst;
+    const SmallCsr A = STAGE ? stage_csr(Ag, reinterpret_cast<char *>(pv + n))
+                             : SmallCsr{Ag.row_ptr, Ag.col_idx, Ag.vals};
+    double xr[RPT], rr[RPT], pr[RPT], apr[RPT];
+#pragma unroll
+    for (int k = 0; k < RPT; ++k) {
+        const int i = tid + k * SWG;
+        xr[k] = rr[k] = pr[k] = apr[k] = 0.0;
+        if (i < n) {
+            xr[k] = x[i];
+            pv[i] = xr[k];
+        }
+    }
+    __syncthreads();
+    {   // r0 = b - A x0, p0 = r0, <r0,r0>, <b,b>
+        dd acc[2] = {dd{0.0, 0.0}, dd{0.0, 0.0}};
+#pragma unroll
+        for (int k = 0; k < RPT; ++k) {
+            const int i = tid + k * SWG;
+            if (i < n) {
+                const double bi = b[i];
+                const double ri = bi - row_sum(A, i, pv);
+                rr[k] = ri;
+                pr[k] = ri;
+                dd_fma(acc[0], ri, ri);
+                dd_fma(acc[1], bi, bi);
+            }
+        }
+        const int fins[1] = {FIN_SETUP}, ks[1] = {2}, needs[1] = {ST_RUNNING};
+        small_reduce<2>(acc, lds, s, fins, ks, needs, 1, hist, scal);
+    }
+    if (s.status == ST_RUNNING) {  // A p0, alpha_0, beta_0
+#pragma unroll
+        for (int k = 0; k < RPT; ++k) {
+            const int i = tid + k * SWG;
+            if (i < n)
+                pv[i] = pr[k];
+        }
+        __syncthreads();
+        dd acc[2] = {dd{0.0, 0.0}, dd{0.0, 0.0}};
+#pragma unroll
+        for (int k = 0; k < RPT; ++k) {
+            const int i = tid + k * SWG;
+            if (i < n) {
+                const double q = row_sum(A, i, pv);
+                apr[k] = q;
+                dd_fma(acc[0], q, pr[k]);
+                dd_fma(acc[1], q, q);
+            }
+        }
+        const int fins[1] = {FIN_CG_ALPHA}, ks[1] = {2}, needs[1] = {ST_RUNNING};
+        small_reduce<2>(acc, lds, s, fins, ks, needs, 1, hist, scal);
+    }
+    while (s.status == ST_RUNNING) {
+        const double alpha = s.alpha, beta = s.beta;
+        dd acc[3] = {dd{0.0, 0.0}, dd{0.0, 0.0}, dd{0.0, 0.0}};
+        // x_i, r_i, p_i and <r_i, r_i>
+#pragma unroll
+        for (int k = 0; k < RPT; ++k) {
+            const int i = tid + k * SWG;
+            if (i < n) {
+                const double pi = pr[k];
+                xr[k] = xr[k] + alpha * pi;
+                const double ri = rr[k] - alpha * apr[k];
+                rr[k] = ri;
+                const double pn = ri + beta * pi;
+                pr[k] = pn;
+                pv[i] = pn;
+                dd_fma(acc[0], ri, ri);
+            }
+        }
+        __syncthreads();
+        // A p_i, <p_i, A p_i>, <A p_i, A p_i>
+#pragma unroll
+        for (int k = 0; k < RPT; ++k) {
+            const int i = tid + k * SWG;
+            if (i < n) {
+                const double q = row_sum(A, i, pv);
+                apr[k] = q;
+                dd_fma(acc[1], q, pr[k]);
+                dd_fma(acc[2], q, q);
+            }
+        }
+        const int fins[2] = {FIN_CG_RR, FIN_CG_ALPHA}, ks[2] = {1, 2},
+                  needs[2] = {ST_RUNNING, ST_RUNNING};
+        small_reduce<3>(acc, lds, s, fins, ks, needs, 2, hist, scal);
+    }
+#pragma unroll
+    for (int k = 0; k < RPT; ++k) {
+        const int i = tid + k * SWG;
+        if (i < n)
+            x[i] = xr[k];
+    }
+    if (tid == 0)
+        *gst = s;
+}
+
+template <int RPT, bool STAGE>
+__global__ __launch_bounds__(SWG) void k_small_bicgstab(DevCsr Ag, const double *__restrict__ b,
+                                                        double *__restrict__ x, DevState *gst,
+                                                        double *hist, double *scal)
+{
+    extern __shared__ double lv[];  // p (first x0) and s for the gathers, 2n entries; then the matrix
+    const int n = Ag.n;
+    double *pv = lv;
+    double *sv = lv + n;
+    __shared__ DevState s;
+    __shared__ dd lds[SWAVES][KMAX];
+    const int tid = threadIdx.x;
+    if (tid == 0)
+        s = *gst;
+    const SmallCsr A = STAGE ? stage_csr(Ag, reinterpret_cast<char *>(lv + 2 * n))
+                             : SmallCsr{Ag.row_ptr, Ag.col_idx, Ag.vals};
+    double xr[RPT], rr[RPT], pr[RPT], apr[RPT], rsr[RPT], sr[RPT], asr[RPT];
+#pragma unroll
+    for (int k = 0; k < RPT; ++k) {
+        const int i = tid + k * SWG;
+        xr[k] = rr[k] = pr[k] = apr[k] = rsr[k] = sr[k] = asr[k] = 0.0;
+        if (i < n) {
+            xr[k] = x[i];
+            pv[i] = xr[k];
+        }
+    }
+    __syncthreads();
+    {   // r0 = b - A x0, r0* = r0, p0 = r0, <r0,r0>, <b,b>
+        dd acc[2] = {dd{0.0, 0.0}, dd{0.0, 0.0}};
+#pragma unroll
+        for (int k = 0; k < RPT; ++k) {
+            const int i = tid + k * SWG;
+            if (i < n) {
+                const double bi = b[i];
+                const double ri = bi - row_sum(A, i, pv);
+                rr[k] = rsr[k] = pr[k] = ri;
+                dd_fma(acc[0], ri, ri);
+                dd_fma(acc[1], bi, bi);
+            }
+        }
+        const int fins[1] = {FIN_SETUP}, ks[1] = {2}, needs[1] = {ST_RUNNING};
+        small_reduce<2>(acc, lds, s, fins, ks, needs, 1, hist, scal);
+    }
+    // <r, r0*> and <r, r> of the last update, reduced with the next <Ap, r0*>
+    dd carry[2] = {dd{0.0, 0.0}, dd{0.0, 0.0}};
+    bool first = true;
+    while (s.status == ST_RUNNING && s.it < s.max_iter) {
+        // A p_i and <A p_i, r0*> (with the previous update's inner products)
+#pragma unroll
+        for (int k = 0; k < RPT; ++k) {
+            const int i = tid + k * SWG;
+            if (i < n)
+                pv[i] = pr[k];
+        }
+        __syncthreads();
+        dd acc1[3] = {carry[0], carry[1], dd{0.0, 0.0}};
+#pragma unroll
+        for (int k = 0; k < RPT; ++k) {
+            const int i = tid + k * SWG;
+            if (i < n) {
+                const double q = row_sum(A, i, pv);
+                apr[k] = q;
+                dd_fma(acc1[2], q, rsr[k]);
+            }
+        }
+        {
+            const int fins[2] = {first ? FIN_NONE : FIN_B_XRP, FIN_B_ALPHA}, ks[2] = {2, 1},
+                      needs[2] = {ST_RUNNING, ST_RUNNING};
+            small_reduce<3>(acc1, lds, s, fins, ks, needs, 2, hist, scal);
+        }
+        first = false;
+        if (s.status != ST_RUNNING)
+            break;
+        // s_i = r_i - alpha A p_i, A s_i, and four inner products
+        const double alpha = s.alpha;
+        dd acc2[4] = {dd{0.0, 0.0}, dd{0.0, 0.0}, dd{0.0, 0.0}, dd{0.0, 0.0}};
+#pragma unroll
+        for (int k = 0; k < RPT; ++k) {
+            const int i = tid + k * SWG;
+            if (i < n) {
+                const double si = rr[k] - alpha * apr[k];
+                sr[k] = si;
+                sv[i] = si;
+                dd_fma(acc2[0], si, si);
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < RPT; ++k) {
+            const int i = tid + k * SWG;
+            if (i < n) {
+                const double q = row_sum(A, i, sv);
+                asr[k] = q;
+                dd_fma(acc2[1], q, sr[k]);
+                dd_fma(acc2[2], q, q);
+                dd_fma(acc2[3], q, rsr[k]);
+            }
+        }
+        {
+            const int fins[2] = {FIN_B_SS, FIN_B_OMEGA}, ks[2] = {1, 3},
+                      needs[2] = {ST_RUNNING, ST_RUNNING};
+            small_reduce<4>(acc2, lds, s, fins, ks, needs, 2, hist, scal);
+        }
+        if (s.status == ST_HALF) {
+#pragma unroll
+            for (int k = 0; k < RPT; ++k) {
+                xr[k] = xr[k] + alpha * pr[k];
+                rr[k] = sr[k];
+            }
+            if (tid == 0)
+                finalize(&s, FIN_B_XRP, nullptr, 0, hist, scal);
+            __syncthreads();
+            break;
+        }
+        if (s.status != ST_RUNNING)
+            break;
+        const double omega = s.omega, beta = s.beta;
+        carry[0] = carry[1] = dd{0.0, 0.0};
+#pragma unroll
+        for (int k = 0; k < RPT; ++k) {
+            const int i = tid + k * SWG;
+            if (i < n) {
+                const double si = sr[k];
+                const double pi = pr[k];
+                xr[k] = xr[k] + alpha * pi + omega * si;
+                const double ri = si - omega * asr[k];
+                rr[k] = ri;
+                pr[k] = ri + beta * (pi - omega * apr[k]);
+                dd_fma(carry[0], ri, rsr[k]);
+                dd_fma(carry[1], ri, ri);
+            }
+        }
+        // The last update's inner products are reduced with the next A p;
+        // when that one cannot run any more, reduce them now.
+        if (s.it + 1 >= s.max_iter) {
+            dd fin2[2] = {carry[0], carry[1]};
+            const int fins[1] = {FIN_B_XRP}, ks[1] = {2}, needs[1] = {ST_RUNNING};
+            small_reduce<2>(fin2, lds, s, fins, ks, needs, 1, hist, scal);
+            break;
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < RPT; ++k) {
+        const int i = tid + k * SWG;
+        if (i < n)
+            x[i] = xr[k];
+    }
+    if (tid == 0)
+        *gst = s;
 }
 
 // Streaming copy with 16-byte accesses, four in flight per thread
@@ -840,17 +1199,25 @@ thread_local hipEvent_t t_start = nullptr;
 thread_local hipEvent_t t_stop = nullptr;
 
 template <typename... KArgs, typename... Args>
-hipError_t launch(void (*kernel)(KArgs...), int grid, int block, hipStream_t s, Args... args)
+hipError_t launch_shm(void (*kernel)(KArgs...), int grid, int block, size_t shm, hipStream_t s,
+                      Args... args)
 {
     if (t_start) {
         hipEvent_t a = t_start, b = t_stop;
         t_start = t_stop = nullptr;
-        hipExtLaunchKernelGGL(kernel, dim3(grid), dim3(block), 0, s, a, b, 0,
+        hipExtLaunchKernelGGL(kernel, dim3(grid), dim3(block), (uint32_t)shm, s, a, b, 0,
                               static_cast<KArgs>(args)...);
     } else {
-        hipLaunchKernelGGL(kernel, dim3(grid), dim3(block), 0, s, static_cast<KArgs>(args)...);
+        hipLaunchKernelGGL(kernel, dim3(grid), dim3(block), (uint32_t)shm, s,
+                           static_cast<KArgs>(args)...);
     }
     return hipGetLastError();
+}
+
+template <typename... KArgs, typename... Args>
+hipError_t launch(void (*kernel)(KArgs...), int grid, int block, hipStream_t s, Args... args)
+{
+    return launch_shm(kernel, grid, block, 0, s, args...);
 }
 
 }  // namespace
@@ -934,6 +1301,47 @@ hipError_t launch_zero(double *x, int64_t n, DevState *st, uint32_t run_mask, in
                        hipStream_t s)
 {
     return launch(k_zero, grid, WG, s, x, n, st, run_mask);
+}
+
+size_t small_lds_bytes(int method_bicg, int64_t n)
+{
+    return (size_t)(method_bicg ? 2 : 1) * (size_t)n * sizeof(double);
+}
+
+size_t small_staged_lds_bytes(int method_bicg, int64_t n, int64_t nnz)
+{
+    return small_lds_bytes(method_bicg, n) + small_csr_bytes(n, nnz);
+}
+
+int small_rows_per_thread(int64_t n)
+{
+    const int64_t r = (n + SWG - 1) / SWG;
+    return r <= 1 ? 1 : r <= 2 ? 2 : r <= 4 ? 4 : r <= 8 ? 8 : 0;
+}
+
+template <bool STAGE>
+static hipError_t launch_small_t(int method_bicg, const DevCsr &A, const double *b, double *x,
+                                 DevState *st, double *hist, double *scal, size_t shm, hipStream_t s)
+{
+    switch (small_rows_per_thread(A.n) * 2 + (method_bicg ? 1 : 0)) {
+    case 2: return launch_shm(k_small_cg<1, STAGE>, 1, SWG, shm, s, A, b, x, st, hist, scal);
+    case 4: return launch_shm(k_small_cg<2, STAGE>, 1, SWG, shm, s, A, b, x, st, hist, scal);
+    case 8: return launch_shm(k_small_cg<4, STAGE>, 1, SWG, shm, s, A, b, x, st, hist, scal);
+    case 16: return launch_shm(k_small_cg<8, STAGE>, 1, SWG, shm, s, A, b, x, st, hist, scal);
+    case 3: return launch_shm(k_small_bicgstab<1, STAGE>, 1, SWG, shm, s, A, b, x, st, hist, scal);
+    case 5: return launch_shm(k_small_bicgstab<2, STAGE>, 1, SWG, shm, s, A, b, x, st, hist, scal);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_small(int method_bicg, const DevCsr &A, const double *b, double *x, DevState *st,
+                        double *hist, double *scal, bool stage, hipStream_t s)
+{
+    if (stage)
+        return launch_small_t<true>(method_bicg, A, b, x, st, hist, scal,
+                                    small_staged_lds_bytes(method_bicg, A.n, A.nnz), s);
+    return launch_small_t<false>(method_bicg, A, b, x, st, hist, scal,
+                                 small_lds_bytes(method_bicg, A.n), s);
 }
 
 hipError_t launch_copy(void *dst, const void *src, int64_t n_bytes, int grid, hipStream_t s)

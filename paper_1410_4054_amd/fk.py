@@ -26,8 +26,9 @@ STATUS_NAMES = {
 METHODS = {"cg_pipelined": 0, "cg_classical": 1, "bicgstab_pipelined": 2, "bicgstab_classical": 3}
 FLAG_GRAPH = 1
 FLAG_PROFILE = 2
+FLAG_NO_SMALL = 4
 PTR_HOST, PTR_DEVICE = 0, 1
-KERNEL_KINDS = ("setup", "spmv_dot", "update_dot", "spmv", "dot", "axpy")
+KERNEL_KINDS = ("setup", "spmv_dot", "update_dot", "spmv", "dot", "axpy", "small")
 LONG_ROW = 2048
 
 
@@ -84,6 +85,7 @@ def lib():
             "fk_get_scalars": [vp, P(f64), i32, P(i32)],
             "fk_get_kernel_times": [vp, P(f64), P(i32), i32],
             "fk_solver_destroy": [vp],
+            "fk_solver_uses_small": [vp, P(i32)],
             "fk_spmv": [vp, vp, vp, P(f64), vp],
             "fk_dot": [i64, vp, vp, P(f64), vp],
             "fk_copy": [vp, vp, i64, vp],
@@ -107,7 +109,7 @@ def exported_symbols() -> list[str]:
         "fk_csr_create", "fk_csr_destroy", "fk_csr_shape", "fk_csr_blocks",
         "fk_solver_create", "fk_solve", "fk_get_iterations", "fk_get_residual",
         "fk_get_residual_history", "fk_get_scalars", "fk_get_kernel_times",
-        "fk_solver_destroy", "fk_spmv", "fk_dot", "fk_copy", "fk_status_str",
+        "fk_solver_destroy", "fk_solver_uses_small", "fk_spmv", "fk_dot", "fk_copy", "fk_status_str",
         "fk_last_error", "fk_version",
     ]
 
@@ -228,7 +230,9 @@ class Solver:
 
     def __init__(self, A: Matrix, method: str = "cg_pipelined", rtol: float = 1e-8,
                  max_iter: int | None = None, record_history: bool = True, unroll: int = 32,
-                 graph: bool = False, profile: bool = False, stream=None):
+                 graph: bool = False, profile: bool = False, small: bool = True, stream=None):
+        """small=False forces the multi-kernel path even where the
+        single-workgroup solver applies."""
         import torch
 
         self.A = A
@@ -238,7 +242,8 @@ class Solver:
             # Stream capture needs a stream other than the legacy default one.
             stream = torch.cuda.Stream()
         self.stream = stream
-        flags = (FLAG_GRAPH if graph else 0) | (FLAG_PROFILE if profile else 0)
+        flags = ((FLAG_GRAPH if graph else 0) | (FLAG_PROFILE if profile else 0)
+                 | (0 if small else FLAG_NO_SMALL))
         o = _Opts(METHODS[method], float(rtol), int(max_iter), int(bool(record_history)),
                   int(unroll), flags)
         h = ctypes.c_void_p()
@@ -259,6 +264,11 @@ class Solver:
             self.stream.wait_stream(torch.cuda.current_stream())
         st = lib().fk_solve(self._h, _dev_f64(b, self.A.n, "b"), _dev_f64(x, self.A.n, "x"))
         return _check(st, "fk_solve", allowed=(OK, NOT_CONVERGED, BREAKDOWN))
+
+    def uses_small(self) -> bool:
+        v = ctypes.c_int32()
+        _check(lib().fk_solver_uses_small(self._h, ctypes.byref(v)), "fk_solver_uses_small")
+        return bool(v.value)
 
     def iterations(self) -> int:
         k = ctypes.c_int32()

@@ -10,6 +10,7 @@ import pytest
 
 import oracle
 from gpu_util import dev, gpu_solve, host, rel
+from gpu_util import gpu_solve as _gpu_solve
 from paper_1410_4054_amd import fk, problems as P
 
 pytestmark = pytest.mark.gpu
@@ -44,12 +45,15 @@ def assert_same_run(res, x, ref, label=""):
     assert rel(x, ref.x) <= 1e-10, (label, rel(x, ref.x))
 
 
+@pytest.mark.parametrize("small", [True, False], ids=["auto", "grid"])
 @pytest.mark.parametrize("wl,method", CASES, ids=[f"{w}-{m}" for w, m in CASES])
-def test_matches_oracle(wl, method, device):
+def test_matches_oracle(wl, method, small, device):
+    """small=True lets the library take its single-workgroup solver where it
+    applies (the small pipelined cases); small=False forces the grid kernels."""
     A, b, x0 = WORKLOADS[wl]()
-    print(f"\n[case] {wl} {method} n={A.n}", flush=True)
+    print(f"\n[case] {wl} {method} n={A.n} small={small}", flush=True)
     ref = oracle.solve(A, b, x0=x0, method=method, rtol=1e-8, trace=True)
-    res, x = gpu_solve(A, b, x0, method=method, rtol=1e-8)
+    res, x = gpu_solve(A, b, x0, method=method, rtol=1e-8, small=small)
     assert_same_run(res, x, ref, f"{wl}/{method}")
     assert ref.status == "converged"
     assert oracle.true_residual(A, b, x) <= 1.5e-8
@@ -105,9 +109,11 @@ def test_fixed_30_iterations(method, device):
     assert_same_run(res, x, ref, method)
 
 
+@pytest.mark.parametrize("small", [True, False], ids=["auto", "grid"])
 @pytest.mark.parametrize("method", ALL)
-def test_edge_cases(method, device):
+def test_edge_cases(method, small, device):
     A, b, _ = P.workload("poisson2d_16")
+    gpu_solve = lambda *a, **k: _gpu_solve(*a, small=small, **k)  # noqa: E731
     n = A.n
     # b = 0: x = 0, k = 0
     res, x = gpu_solve(A, np.zeros(n), np.ones(n), method=method)
@@ -139,8 +145,10 @@ def test_edge_cases(method, device):
         assert_same_run(res, x, ref, "scaled identity")
 
 
+@pytest.mark.parametrize("small", [True, False], ids=["auto", "grid"])
 @pytest.mark.parametrize("method", ALL)
-def test_breakdown(method, device):
+def test_breakdown(method, small, device):
+    gpu_solve = lambda *a, **k: _gpu_solve(*a, small=small, **k)  # noqa: E731
     if method.startswith("cg"):
         A = P.dense_to_csr(np.diag([1.0, -1.0, 2.0, -2.0]))
     else:
@@ -202,3 +210,46 @@ def test_solver_reuse_and_api(device):
         fk.solve(M, torch.zeros(A.n, dtype=torch.float32, device=device), dev(np.zeros(A.n)))
     with pytest.raises(ValueError):
         fk.solve(M, dev(np.zeros(A.n + 1)), dev(np.zeros(A.n)))
+
+
+def test_small_path_selection(device):
+    """Which solves take the single-workgroup solver, and that it agrees
+    with the grid kernels bit for bit on the latency-bound workload."""
+    A, b, _ = P.workload("poisson2d_32")
+    M = fk.Matrix(A)
+    for method, expect in (("cg_pipelined", True), ("bicgstab_pipelined", True),
+                           ("cg_classical", False), ("bicgstab_classical", False)):
+        S = fk.Solver(M, method=method)
+        assert S.uses_small() is expect, method
+        S.close()
+    S = fk.Solver(M, method="cg_pipelined", small=False)
+    assert not S.uses_small()
+    S.close()
+    big = fk.Matrix(P.workload("poisson3d_24")[0])  # n = 13824 > 8192
+    S = fk.Solver(big, method="cg_pipelined")
+    assert not S.uses_small()
+    S.close()
+    for method in ("cg_pipelined", "bicgstab_pipelined"):
+        r1, x1 = gpu_solve(A, b, method=method, matrix=M, small=True)
+        r2, x2 = gpu_solve(A, b, method=method, matrix=M, small=False)
+        assert r1.k == r2.k and np.array_equal(x1, x2), method
+        assert np.array_equal(r1.history, r2.history), method
+        S = fk.Solver(M, method=method, profile=True)
+        xd = dev(np.zeros(A.n))
+        S.solve(dev(b), xd)
+        t = S.kernel_times()
+        assert t["small"][1] == 1 and t["small"][0] > 0
+        S.close()
+
+
+@pytest.mark.parametrize("n,method", [(90, "cg_pipelined"), (60, "cg_pipelined"), (45, "cg_pipelined"),
+                                      (2, "cg_pipelined"), (40, "bicgstab_pipelined"),
+                                      (31, "bicgstab_pipelined")])
+def test_small_path_rows_per_thread(n, method, device):
+    """1, 2, 4 and 8 rows per thread of the single-workgroup solver."""
+    A = P.poisson2d(n) if method.startswith("cg") else P.convdiff2d(n)
+    b = P.rhs_uniform(A.n, 7)
+    ref = oracle.solve(A, b, method=method, rtol=1e-9)
+    res, x = gpu_solve(A, b, method=method, rtol=1e-9)
+    assert fk.Solver(fk.Matrix(A), method=method).uses_small()
+    assert_same_run(res, x, ref, f"n={n}")
