@@ -7,7 +7,11 @@
  * (Algorithm 4, Section 3.2) of Rupp, Weinbub, Juengel and Grasser,
  * "Pipelined Iterative Solvers with Kernel Fusion for GPUs" (arXiv:1410.4054).
  * The classical formulations (Algorithms 1 and 3) are provided as unfused
- * baselines built from one kernel per vector operation.
+ * baselines built from one kernel per vector operation.  FK_CG_MIXED runs
+ * the pipelined CG iteration in FP32 storage and arithmetic as the inner
+ * solver of an FP64 iterative refinement (an extension: Section 3.1 cites a
+ * mixed-precision pipelined CG on FPGAs as prior work, the paper itself
+ * stays in FP64).
  *
  * Every step of an iteration runs in hand-written HIP kernels: the CSR
  * product fused with the first stage of the inner products that follow it
@@ -60,7 +64,8 @@ typedef enum {
     FK_CG_PIPELINED = 0,        /* Algorithm 2 + Eq. (3): 2 kernels/iteration   */
     FK_CG_CLASSICAL = 1,        /* Algorithm 1 as SpMV, dot, axpy, axpy, dot, xpay */
     FK_BICGSTAB_PIPELINED = 2,  /* Algorithm 4: 4 kernels/iteration             */
-    FK_BICGSTAB_CLASSICAL = 3   /* Algorithm 3, one kernel per operation         */
+    FK_BICGSTAB_CLASSICAL = 3,  /* Algorithm 3, one kernel per operation         */
+    FK_CG_MIXED = 4             /* FP64 iterative refinement around FP32 Algorithm 2 */
 } fk_method;
 
 /* Rows with more nonzeros than this are summed by a fixed tree, not left to right. */
@@ -70,10 +75,16 @@ typedef enum {
 typedef struct {
     int32_t method;          /* fk_method                                       */
     double rtol;             /* stop when ||r_k||_2 <= rtol * ||b||_2 (>= 0)   */
-    int32_t max_iter;        /* >= 0; iterations allowed (0 = setup only)      */
-    int32_t record_history;  /* nonzero: keep ||r_i||/||b|| for i = 0..k        */
+    int32_t max_iter;        /* >= 0; iterations allowed (0 = setup only);
+                                FK_CG_MIXED: inner iterations over all sweeps  */
+    int32_t record_history;  /* nonzero: keep ||r_i||/||b|| for i = 0..k
+                                (FK_CG_MIXED: one entry per refinement sweep)  */
     int32_t unroll;          /* iterations enqueued between status polls (0 = 32) */
     int32_t flags;           /* FK_FLAG_* bits                                  */
+    double inner_rtol;       /* FK_CG_MIXED: inner stop ||r_in|| <= inner_rtol *
+                                ||r_j|| (>= 0; 0 = 1e-4)                       */
+    int32_t max_outer;       /* FK_CG_MIXED: refinement sweeps allowed
+                                (>= 0; 0 = 50)                                 */
 } fk_opts;
 
 /* flags */
@@ -122,6 +133,24 @@ fk_status fk_csr_blocks(fk_csr A, int32_t *nblocks, int32_t *long_rows);
 fk_status fk_solver_create(fk_csr A, const fk_opts *o, void *hip_stream, fk_solver *out);
 
 /*
+ * FK_CG_MIXED (iterative refinement with an FP32 inner solver): sweep
+ * j = 0, 1, ... computes r_j = b - A x_j in FP64 (values summed row by row
+ * in CSR order) and stops when ||r_j|| <= rtol ||b||; otherwise it solves
+ * A d = r_j approximately by pipelined CG (Algorithm 2, Eq. (3)) with d_0 = 0,
+ * FP32 vectors, FP32 matrix values (rounded once, when the solver is
+ * created) and FP32 arithmetic, until its recursively updated residual
+ * satisfies ||r_in|| <= inner_rtol ||(float) r_j||, and sets
+ * x_{j+1} = x_j + d in FP64.  Inner products are exact products of the FP32
+ * operands accumulated in double-double, so they are reproducible as on the
+ * FP64 path.  The solve ends FK_NOT_CONVERGED when max_iter inner
+ * iterations or max_outer sweeps are used up or an inner solve stops without
+ * an iteration (its correction would be 0), and FK_BREAKDOWN (x = x_j) when
+ * an inner solve breaks down or a residual is not finite.  k
+ * (fk_get_iterations) counts inner iterations over all sweeps, the residual
+ * and its history are those of the FP64 residuals r_j, and
+ * fk_get_refinements gives the number of sweeps (corrections applied).
+ * Workspace: 4n floats plus nnz FP32 matrix values.
+ *
  * Solve A x = b.  b_dev, x_dev: caller-owned device float64[n]; x holds x0 on
  * entry and x_k on return.  Work is enqueued on the solver's stream and the
  * call returns once it has completed.  Returns FK_OK (converged),
@@ -138,13 +167,14 @@ fk_status fk_get_iterations(fk_solver S, int32_t *k);
 fk_status fk_get_residual(fk_solver S, double *rel_res);
 
 /* Residual history of the last solve: out[i] = ||r_i||/||b||, i = 0..k.
- * Writes min(cap, k+1) values and sets *len = k+1.  Needs record_history. */
+ * Writes min(cap, k+1) values and sets *len = k+1.  Needs record_history.
+ * FK_CG_MIXED: out[j] = ||b - A x_j||/||b|| for sweeps j = 0..J, *len = J+1. */
 fk_status fk_get_residual_history(fk_solver S, double *out, int32_t cap, int32_t *len);
 
 /* Per-iteration scalars of the last solve (for diagnostics): for iteration
  * i < min(cap, k), out[4*i + 0..3] = alpha_i, beta_i, omega_i (0 for CG),
  * and the A-expanded (BiCGStab) or plain <r,r> used for the test.
- * Needs record_history. */
+ * Needs record_history; not recorded for FK_CG_MIXED (FK_E_STATE). */
 fk_status fk_get_scalars(fk_solver S, double *out, int32_t cap, int32_t *len);
 
 /* Average device time per launch of each kernel kind during the last solve
@@ -158,7 +188,8 @@ enum {
     FK_KERNEL_DOT = 4,         /* plain dot (classical)                        */
     FK_KERNEL_AXPY = 5,        /* plain vector update (classical)             */
     FK_KERNEL_SMALL = 6,       /* whole solve in one workgroup (small systems) */
-    FK_KERNEL_KINDS = 7
+    FK_KERNEL_RESIDUAL = 7,    /* FK_CG_MIXED: FP64 r_j = b - A x_j + its dots  */
+    FK_KERNEL_KINDS = 8
 };
 fk_status fk_get_kernel_times(fk_solver S, double *avg_us, int32_t *count, int32_t cap);
 
@@ -166,6 +197,10 @@ fk_status fk_solver_destroy(fk_solver S);
 
 /* *small = 1 if fk_solve runs the single-workgroup solver, else 0. */
 fk_status fk_solver_uses_small(fk_solver S, int32_t *small);
+
+/* FK_CG_MIXED: refinement sweeps (corrections x += d) of the last solve;
+ * 0 for the other methods. */
+fk_status fk_get_refinements(fk_solver S, int32_t *sweeps);
 
 /*
  * q = A p with optional fused first-stage reductions (the fused kernel of

@@ -60,6 +60,17 @@ class Oracle:
             ctypes.POINTER(ctypes.c_int32),
         ]
         lib.oracle_solve.restype = ctypes.c_int
+        lib.oracle_solve_mixed.argtypes = [
+            ctypes.c_int64, i32p, i32p, f64p, f64p, f64p, ctypes.c_double, ctypes.c_double,
+            ctypes.c_int32, ctypes.c_int32, f64p, i32p, ctypes.c_int32,
+            ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
+        ]
+        lib.oracle_solve_mixed.restype = ctypes.c_int
+        f32p = ctypes.POINTER(ctypes.c_float)
+        lib.oracle_spmv_f32.argtypes = [ctypes.c_int64, i32p, i32p, f32p, f32p, f32p]
+        lib.oracle_spmv_f32.restype = None
+        lib.oracle_dot_f32.argtypes = [ctypes.c_int64, f32p, f32p]
+        lib.oracle_dot_f32.restype = ctypes.c_double
         self.lib = lib
         self.path = path
 
@@ -73,6 +84,25 @@ class Oracle:
         _, qp = _f64(q)
         self.lib.oracle_spmv(A.n, rpp, cip, vp, pp, qp)
         return q
+
+    def spmv_f32(self, A, p) -> np.ndarray:
+        """q = A p in FP32 (values rounded to FP32, one rounding per operation)."""
+        rp, rpp = _i32(A.row_ptr)
+        ci, cip = _i32(A.col_idx)
+        v, vp = _f32(A.vals)
+        p, pp = _f32(p)
+        q = np.empty(A.n, dtype=np.float32)
+        _, qp = _f32(q)
+        self.lib.oracle_spmv_f32(A.n, rpp, cip, vp, pp, qp)
+        return q
+
+    def dot_f32(self, a, b) -> float:
+        """<a, b> of two FP32 vectors, as if in twice FP64 precision, rounded to FP64."""
+        a, ap = _f32(a)
+        b, bp = _f32(b)
+        if a.shape != b.shape:
+            raise ValueError("shape mismatch")
+        return float(self.lib.oracle_dot_f32(a.size, ap, bp))
 
     def dot(self, a, b) -> float:
         """<a, b> by the compensated dot (twice working precision, one rounding)."""
@@ -124,6 +154,32 @@ class Oracle:
         return Result(x=x, r=r, k=kk, status=STATUS[st], hist=hist[: kk + 1].copy(),
                       trace=None if tr is None else tr[:kk].copy())
 
+    def solve_mixed(self, A, b, x0=None, rtol: float = 1e-10, inner_rtol: float = 1e-4,
+                    max_iter: int | None = None, max_outer: int = 50) -> "MixedResult":
+        """Iterative refinement in FP64 around FP32 pipelined CG (oracle.c)."""
+        n = A.n
+        if max_iter is None:
+            max_iter = 10 * n
+        rp, rpp = _i32(A.row_ptr)
+        ci, cip = _i32(A.col_idx)
+        v, vp = _f64(A.vals)
+        b, bp = _f64(b)
+        x = np.zeros(n) if x0 is None else np.array(x0, dtype=np.float64, copy=True)
+        _, xp = _f64(x)
+        cap = max_outer + 1
+        hist = np.full(cap, np.nan)
+        _, hp = _f64(hist)
+        inner = np.zeros(cap, dtype=np.int32)
+        _, ip = _i32(inner)
+        k = ctypes.c_int32(0)
+        sw = ctypes.c_int32(0)
+        st = self.lib.oracle_solve_mixed(n, rpp, cip, vp, bp, xp, float(rtol), float(inner_rtol),
+                                         int(max_iter), int(max_outer), hp, ip, cap,
+                                         ctypes.byref(k), ctypes.byref(sw))
+        J = int(sw.value)
+        return MixedResult(x=x, k=int(k.value), sweeps=J, status=STATUS[st],
+                           hist=hist[: J + 1].copy(), inner_k=inner[:J].copy())
+
     def true_residual(self, A, b, x) -> float:
         """||b - A x|| / ||b|| with the oracle's product and compensated dots."""
         ax = self.spmv(A, x)
@@ -148,6 +204,11 @@ def _f64(a):
     return a, a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
 
 
+def _f32(a):
+    a = np.ascontiguousarray(a, dtype=np.float32)
+    return a, a.ctypes.data_as(ctypes.POINTER(ctypes.c_float))
+
+
 def _i32(a):
     a = np.ascontiguousarray(a, dtype=np.int32)
     return a, a.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
@@ -170,6 +231,12 @@ def solve(A, b, x0=None, method: str = "cg_pipelined", rtol: float = 1e-8,
     return default().solve(A, b, x0=x0, method=method, rtol=rtol, max_iter=max_iter, trace=trace)
 
 
+def solve_mixed(A, b, x0=None, rtol: float = 1e-10, inner_rtol: float = 1e-4,
+                max_iter: int | None = None, max_outer: int = 50) -> "MixedResult":
+    return default().solve_mixed(A, b, x0=x0, rtol=rtol, inner_rtol=inner_rtol,
+                                 max_iter=max_iter, max_outer=max_outer)
+
+
 def true_residual(A, b, x) -> float:
     return default().true_residual(A, b, x)
 
@@ -185,3 +252,13 @@ class Result:
 
     def t(self, name: str) -> np.ndarray:
         return self.trace[:, TRACE_SLOTS[name]]
+
+
+@dataclass
+class MixedResult:
+    x: np.ndarray
+    k: int              # inner iterations over all sweeps
+    sweeps: int         # corrections applied
+    status: str
+    hist: np.ndarray    # ||b - A x_j||/||b||, j = 0..sweeps
+    inner_k: np.ndarray  # inner iterations of each sweep

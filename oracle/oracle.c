@@ -18,7 +18,13 @@
  *   - bicgstab_classical : Algorithm 3;
  *   - bicgstab_pipelined : Algorithm 4, beta from the orthogonality
  *                          <s_i, r0*> = 0 and the residual norm from the
- *                          expansion of <r_{i+1}, r_{i+1}> (Section 3.2).
+ *                          expansion of <r_{i+1}, r_{i+1}> (Section 3.2);
+ *   - oracle_solve_mixed : classical iterative refinement (residual and
+ *                          update in FP64) whose correction equation is
+ *                          solved by Algorithm 2 + Eq. (3) in FP32 storage
+ *                          and arithmetic, an extension of the paper's
+ *                          pipelined CG (Section 3.1 cites mixed-precision
+ *                          pipelined CG as prior work).
  *
  * Build with -ffp-contract=off: every product and every sum is rounded on its
  * own; the only fused multiply-add is the explicit fma() that extracts the
@@ -471,3 +477,144 @@ int oracle_solve(int method, int64_t n, const int32_t *row_ptr, const int32_t *c
 }
 
 int oracle_trace_stride(void) { return TRACE_STRIDE; }
+
+/* ------------------------------- iterative refinement, FP32 inner solver */
+
+/* The product of two floats is exact in double, so the compensated dot of
+ * the widened operands is the FP32 dot "as if in twice the precision" of
+ * the FP64 oracle_dot. */
+double oracle_dot_f32(int64_t n, const float *a, const float *b)
+{
+    if (n == 0)
+        return 0.0;
+    double p = (double)a[0] * (double)b[0], s = 0.0;
+    for (int64_t i = 1; i < n; ++i) {
+        double h = (double)a[i] * (double)b[i], q;
+        two_sum(p, h, &p, &q);
+        s = s + q;
+    }
+    return p + s;
+}
+
+/* q = A p in FP32: every product and every partial row sum rounded to FP32,
+ * rows summed left to right in CSR order. */
+void oracle_spmv_f32(int64_t n, const int32_t *rp, const int32_t *ci, const float *v,
+                     const float *p, float *q)
+{
+    for (int64_t i = 0; i < n; ++i) {
+        float acc = 0.0f;
+        for (int64_t j = rp[i]; j < rp[i + 1]; ++j)
+            acc = acc + v[j] * p[ci[j]];
+        q[i] = acc;
+    }
+}
+
+/* Algorithm 2 with Eq. (3) for A d = r with d_0 = 0, in FP32: alpha, beta
+ * are formed in FP64 from the dots and rounded to FP32 for the updates.
+ * Stops when ||r_i|| <= rtol ||r_0|| (recursive residual) or after cap
+ * iterations.  r is overwritten by the inner residual.  Returns OR_*. */
+static int cg_pipelined_f32(int64_t n, const int32_t *rp, const int32_t *ci, const float *v,
+                            float *r, float *d, float *p, float *ap, double rtol, int64_t cap,
+                            int64_t *k_out)
+{
+    int64_t k = 0;
+    for (int64_t j = 0; j < n; ++j) { d[j] = 0.0f; p[j] = r[j]; }
+    double rr = oracle_dot_f32(n, r, r);
+    *k_out = 0;
+    if (rr == 0.0) return OR_CONVERGED;                     /* r = 0: d = 0, no step */
+    double tol = rtol * sqrt(rr);
+    if (!finite(rr)) return OR_BREAKDOWN;
+    if (sqrt(rr) <= tol) return OR_CONVERGED;
+    oracle_spmv_f32(n, rp, ci, v, p, ap);
+    double pap = oracle_dot_f32(n, p, ap), apap = oracle_dot_f32(n, ap, ap);
+    if (!(pap > 0.0) || !finite(pap) || !finite(apap)) return OR_BREAKDOWN;
+    double alpha = rr / pap;
+    double beta = alpha * alpha * apap / rr - 1.0;         /* Eq. (3) */
+    int status = OR_NOT_CONVERGED;
+    for (int64_t i = 1; i <= cap; ++i) {
+        const float af = (float)alpha, bf = (float)beta;
+        for (int64_t j = 0; j < n; ++j) d[j] = d[j] + af * p[j];
+        for (int64_t j = 0; j < n; ++j) r[j] = r[j] - af * ap[j];
+        for (int64_t j = 0; j < n; ++j) p[j] = r[j] + bf * p[j];
+        rr = oracle_dot_f32(n, r, r);
+        k = i;
+        if (!finite(rr)) { status = OR_BREAKDOWN; break; }
+        if (sqrt(rr) <= tol) { status = OR_CONVERGED; break; }
+        if (i == cap) break;
+        oracle_spmv_f32(n, rp, ci, v, p, ap);
+        pap = oracle_dot_f32(n, p, ap);
+        apap = oracle_dot_f32(n, ap, ap);
+        if (!(pap > 0.0) || !finite(pap) || !finite(apap)) { status = OR_BREAKDOWN; break; }
+        alpha = rr / pap;
+        beta = alpha * alpha * apap / rr - 1.0;
+    }
+    *k_out = k;
+    return status;
+}
+
+/*
+ * Iterative refinement: for j = 0, 1, ...: r_j = b - A x_j in FP64; stop when
+ * ||r_j|| <= rtol ||b||; solve A d = (float) r_j with the FP32 pipelined CG
+ * above (matrix values rounded to FP32) to inner_rtol; x_{j+1} = x_j + d.
+ * Limits: max_iter inner iterations in total, max_outer sweeps; a sweep
+ * whose inner solve makes no iteration ends the solve (not converged).
+ * hist[j] = ||r_j||/||b|| (j = 0..sweeps, up to cap); inner_k[j] (may be
+ * NULL) = inner iterations of sweep j.  *k_out = inner iterations in total.
+ * Returns OR_*; b = 0 gives x = 0.
+ */
+int oracle_solve_mixed(int64_t n, const int32_t *row_ptr, const int32_t *col_idx,
+                       const double *vals, const double *b, double *x, double rtol,
+                       double inner_rtol, int32_t max_iter, int32_t max_outer, double *hist,
+                       int32_t *inner_k, int32_t cap, int32_t *k_out, int32_t *sweeps_out)
+{
+    *k_out = 0;
+    *sweeps_out = 0;
+    if (n <= 0 || !row_ptr || !col_idx || !vals || !b || !x || max_iter < 0 || max_outer < 0 ||
+        !(rtol >= 0.0) || !(inner_rtol >= 0.0))
+        return OR_BAD_ARG;
+    const int64_t nnz = row_ptr[n];
+    csr_t A = {n, row_ptr, col_idx, vals};
+    double *r = vec(n);
+    float *v32 = (float *)calloc((size_t)(nnz > 0 ? nnz : 1), sizeof(float));
+    float *r32 = (float *)calloc((size_t)n, sizeof(float));
+    float *d = (float *)calloc((size_t)n, sizeof(float));
+    float *p = (float *)calloc((size_t)n, sizeof(float));
+    float *ap = (float *)calloc((size_t)n, sizeof(float));
+    int status = OR_BAD_ARG;
+    if (!r || !v32 || !r32 || !d || !p || !ap) goto done;
+    for (int64_t j = 0; j < nnz; ++j) v32[j] = (float)vals[j];
+
+    double bb = oracle_dot(n, b, b);
+    if (bb == 0.0) {
+        for (int64_t j = 0; j < n; ++j) x[j] = 0.0;
+        put_hist(hist, cap, 0, 0.0);
+        status = OR_CONVERGED;
+        goto done;
+    }
+    double bnorm = sqrt(bb), tol = rtol * bnorm;
+    int64_t used = 0;
+    int32_t sweeps = 0;
+    for (;;) {
+        if (!initial_residual(&A, b, x, r)) { status = OR_BAD_ARG; break; }   /* r_j */
+        double rr = oracle_dot(n, r, r);
+        put_hist(hist, cap, sweeps, sqrt(rr) / bnorm);
+        if (!finite(rr)) { status = OR_BREAKDOWN; break; }
+        if (sqrt(rr) <= tol) { status = OR_CONVERGED; break; }
+        if (sweeps >= max_outer || used >= max_iter) { status = OR_NOT_CONVERGED; break; }
+        for (int64_t j = 0; j < n; ++j) r32[j] = (float)r[j];
+        int64_t kj = 0;
+        int st = cg_pipelined_f32(n, row_ptr, col_idx, v32, r32, d, p, ap, inner_rtol,
+                                  (int64_t)max_iter - used, &kj);
+        used += kj;
+        if (inner_k && sweeps < cap) inner_k[sweeps] = (int32_t)kj;
+        if (st == OR_BREAKDOWN) { status = OR_BREAKDOWN; break; }
+        if (kj == 0) { status = OR_NOT_CONVERGED; break; }
+        for (int64_t j = 0; j < n; ++j) x[j] = x[j] + (double)d[j];       /* x_{j+1} */
+        sweeps++;
+    }
+    *k_out = (int32_t)used;
+    *sweeps_out = sweeps;
+done:
+    free(r); free(v32); free(r32); free(d); free(p); free(ap);
+    return status;
+}

@@ -328,7 +328,9 @@ struct fk_solver_s {
     double *partials = nullptr, *hist = nullptr, *scal = nullptr;
     DevState *st = nullptr;
     int32_t hist_cap = 0;
-    DevState *h_init = nullptr;     // pinned
+    // pinned: [0] state written before a (inner) solve, [1] before the
+    // refinement's first residual, [2] state read back
+    DevState *h_init = nullptr;
     int32_t *h_status = nullptr;    // pinned, two poll slots
     hipEvent_t poll_ev[2] = {nullptr, nullptr};
     DevState last{};
@@ -348,8 +350,19 @@ struct fk_solver_s {
     int graph_iters = 0;
     bool small = false;        // whole solve in one single-workgroup launch
     bool small_stage = false;  // ... with the matrix staged in LDS
+    // FK_CG_MIXED: FP32 inner vectors and matrix values; the refinement's
+    // own state (st is the inner solver's); sweeps of the last solve.
+    bool mixed = false;
+    float *r32 = nullptr, *p32 = nullptr, *ap32 = nullptr, *d32 = nullptr, *vals32 = nullptr;
+    DevState *st_outer = nullptr;
+    int32_t sweeps = 0;
 
-    RedArgs red(int fin, uint32_t mask) const { return RedArgs{st, partials, hist, scal, fin, mask}; }
+    // The mixed method records the refinement's residuals only.
+    RedArgs red(int fin, uint32_t mask) const
+    {
+        return RedArgs{st, partials, mixed ? nullptr : hist, mixed ? nullptr : scal, fin, mask};
+    }
+    RedArgs red_outer() const { return RedArgs{st_outer, partials, hist, nullptr, FIN_MIX_OUTER, RUN_ACTIVE}; }
 };
 
 static void solver_release(fk_solver S)
@@ -364,6 +377,12 @@ static void solver_release(fk_solver S)
     dev_free(S->hist);
     dev_free(S->scal);
     dev_free(S->st);
+    dev_free(S->r32);
+    dev_free(S->p32);
+    dev_free(S->ap32);
+    dev_free(S->d32);
+    dev_free(S->vals32);
+    dev_free(S->st_outer);
     if (S->h_init)
         (void)hipHostFree(S->h_init);
     if (S->h_status)
@@ -422,8 +441,12 @@ extern "C" fk_status fk_solver_create(fk_csr A, const fk_opts *o, void *hip_stre
     *out = nullptr;
     if (!A || !o)
         return fail(FK_E_ARG, "NULL argument");
-    if (o->method < FK_CG_PIPELINED || o->method > FK_BICGSTAB_CLASSICAL)
+    if (o->method < FK_CG_PIPELINED || o->method > FK_CG_MIXED)
         return fail(FK_E_ARG, "unknown method %d", o->method);
+    if (!(o->inner_rtol >= 0.0) || !std::isfinite(o->inner_rtol))
+        return fail(FK_E_ARG, "inner_rtol must be finite and >= 0");
+    if (o->max_outer < 0)
+        return fail(FK_E_ARG, "max_outer < 0");
     if (!(o->rtol >= 0.0) || !std::isfinite(o->rtol))
         return fail(FK_E_ARG, "rtol must be finite and >= 0");
     if (o->max_iter < 0)
@@ -440,6 +463,11 @@ extern "C" fk_status fk_solver_create(fk_csr A, const fk_opts *o, void *hip_stre
     S->o = *o;
     if (S->o.unroll == 0)
         S->o.unroll = 32;
+    S->mixed = o->method == FK_CG_MIXED;
+    if (S->o.inner_rtol == 0.0)
+        S->o.inner_rtol = 1e-4;
+    if (S->o.max_outer == 0)
+        S->o.max_outer = 50;
     S->stream = (hipStream_t)hip_stream;
     S->n = A->n;
     S->grid_spmv = spmv_grid(A->nblocks);
@@ -463,9 +491,18 @@ extern "C" fk_status fk_solver_create(fk_csr A, const fk_opts *o, void *hip_stre
             return fail(FK_E_HIP, "%s failed: %s", #expr, hipGetErrorString(e_));         \
         }                                                                                  \
     } while (0)
-    S_TRY(dev_alloc(&S->r, n, "r"));
-    S_TRY(dev_alloc(&S->p, n, "p"));
-    S_TRY(dev_alloc(&S->ap, n, "Ap"));
+    if (S->mixed) {
+        S_TRY(dev_alloc(&S->r32, n, "r32"));
+        S_TRY(dev_alloc(&S->p32, n, "p32"));
+        S_TRY(dev_alloc(&S->ap32, n, "Ap32"));
+        S_TRY(dev_alloc(&S->d32, n, "d32"));
+        S_TRY(dev_alloc(&S->vals32, (size_t)A->nnz, "FP32 values"));
+        S_TRY(dev_alloc(&S->st_outer, 1, "refinement state"));
+    } else {
+        S_TRY(dev_alloc(&S->r, n, "r"));
+        S_TRY(dev_alloc(&S->p, n, "p"));
+        S_TRY(dev_alloc(&S->ap, n, "Ap"));
+    }
     if (is_bicg(o->method)) {
         S_TRY(dev_alloc(&S->s, n, "s"));
         S_TRY(dev_alloc(&S->as, n, "As"));
@@ -473,17 +510,25 @@ extern "C" fk_status fk_solver_create(fk_csr A, const fk_opts *o, void *hip_stre
     }
     S_TRY(dev_alloc(&S->partials, RED_SCRATCH_DOUBLES, "partials"));
     S_TRY(dev_alloc(&S->st, 1, "state"));
-    if (o->record_history) {
+    if (o->record_history && S->mixed) {
+        S->hist_cap = (int32_t)std::min<int64_t>((int64_t)S->o.max_outer + 1, INT32_MAX);
+        S_TRY(dev_alloc(&S->hist, (size_t)S->hist_cap, "history"));
+    } else if (o->record_history) {
         S->hist_cap = (int32_t)std::min<int64_t>((int64_t)o->max_iter + 1, INT32_MAX);
         S_TRY(dev_alloc(&S->hist, (size_t)S->hist_cap, "history"));
         S_TRY(dev_alloc(&S->scal, (size_t)S->hist_cap * 4, "scalars"));
     }
-    S_HIP(hipHostMalloc(reinterpret_cast<void **>(&S->h_init), sizeof(DevState), hipHostMallocDefault));
+    S_HIP(hipHostMalloc(reinterpret_cast<void **>(&S->h_init), 3 * sizeof(DevState), hipHostMallocDefault));
     S_HIP(hipHostMalloc(reinterpret_cast<void **>(&S->h_status), 2 * sizeof(int32_t), hipHostMallocDefault));
     for (auto &e : S->poll_ev)
         S_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
     S_HIP(hipMemsetAsync(S->st, 0, sizeof(DevState), S->stream));
     S_HIP(hipMemsetAsync(S->partials, 0, RED_SCRATCH_DOUBLES * sizeof(double), S->stream));
+    if (S->mixed) {
+        S_HIP(hipMemsetAsync(S->st_outer, 0, sizeof(DevState), S->stream));
+        if (A->nnz > 0)
+            S_HIP(launch_to_f32(A->nnz, S->vals32, A->vals, vec_grid(A->nnz), S->stream));
+    }
     S->small = small_path_ok(A, S->o);
     S->small_stage = S->small &&
                      small_staged_lds_bytes(o->method == FK_BICGSTAB_PIPELINED, A->n, A->nnz) +
@@ -557,6 +602,13 @@ hipError_t enqueue_setup(fk_solver S, Enq &q, const double *b, double *x)
     const int64_t n = S->n;
     const int gs = S->grid_spmv, gv = S->grid_vec;
     hipStream_t st = S->stream;
+    if (S->mixed) {
+        // Inner solve of A d = r32 from d_0 = 0: p_0 = r_0 = r32.
+        ENQ(FK_KERNEL_SETUP, launch_inner_setup32(n, S->r32, S->p32, S->d32, S->red(FIN_SETUP, RUN_ACTIVE), gv, st));
+        ENQ(FK_KERNEL_SPMV_DOT, launch_spmv32(A, S->vals32, S->p32, S->ap32,
+                                              S->red(FIN_CG_ALPHA, RUN_ACTIVE), gs, st));
+        return hipSuccess;
+    }
     double *rs = is_bicg(S->o.method) ? S->rs : nullptr;
     ENQ(FK_KERNEL_SETUP, launch_residual0(A, b, x, S->r, S->p, rs, S->red(FIN_SETUP, RUN_ACTIVE), gs, st));
     // b = 0: x = 0 (runs only in that state; not timed).
@@ -620,9 +672,53 @@ hipError_t enqueue_iteration(fk_solver S, Enq &q, double *x, bool last)
         if (!last)
             ENQ(FK_KERNEL_AXPY, launch_xpay(n, S->p, S->r, S->ap, ds, RUN_ACTIVE, gv, st));
         break;
+    case FK_CG_MIXED:
+        // Algorithm 2 in FP32 on the correction d (x is not touched).
+        ENQ(FK_KERNEL_UPDATE_DOT, launch_cg_update32(n, S->d32, S->r32, S->p32, S->ap32,
+                                                     S->red(FIN_CG_RR, RUN_ACTIVE), gv, st));
+        if (!last)
+            ENQ(FK_KERNEL_SPMV_DOT, launch_spmv32(A, S->vals32, S->p32, S->ap32,
+                                                  S->red(FIN_CG_ALPHA, RUN_ACTIVE), gs, st));
+        break;
     default:
         return hipErrorInvalidValue;
     }
+    return hipSuccess;
+}
+
+void harvest_profile(fk_solver S, int batch)
+{
+    const std::vector<hipEvent_t> &pool = S->prof_ev[batch];
+    for (const TimedLaunch &t : S->prof_batch[batch]) {
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, pool[t.slot], pool[t.slot + 1]) == hipSuccess) {
+            S->prof_us[t.kind] += 1000.0 * (double)ms;
+            S->prof_n[t.kind] += 1;
+        }
+    }
+}
+
+// Refinement step on the FP64 side: x += d (when `add`), then
+// r32 = (float)(b - A x) with its FP64 norm test; waits and leaves the
+// refinement state in h_init[2].
+hipError_t mixed_outer(fk_solver S, const double *b, double *x, bool add, bool profile)
+{
+    const DevCsr A = S->A->view();
+    hipStream_t st = S->stream;
+    S->prof_batch[0].clear();
+    S->prof_next[0] = 0;
+    Enq q{S, profile, 0};
+    if (add)
+        ENQ(FK_KERNEL_AXPY, launch_add32(S->n, x, S->d32, S->grid_vec, st));
+    ENQ(FK_KERNEL_RESIDUAL, launch_residual32(A, b, x, S->r32, S->red_outer(), S->grid_spmv, st));
+    hipError_t e = hipMemcpyAsync(&S->h_init[2], S->st_outer, sizeof(DevState), hipMemcpyDeviceToHost, st);
+    if (e != hipSuccess)
+        return e;
+    e = hipStreamSynchronize(st);
+    if (e != hipSuccess)
+        return e;
+    if (profile)
+        harvest_profile(S, 0);
     return hipSuccess;
 }
 
@@ -676,77 +772,24 @@ hipError_t ensure_graph(fk_solver S, double *x, int iters)
     return hipSuccess;
 }
 
-void harvest_profile(fk_solver S, int batch)
-{
-    const std::vector<hipEvent_t> &pool = S->prof_ev[batch];
-    for (const TimedLaunch &t : S->prof_batch[batch]) {
-        float ms = 0.f;
-        if (hipEventElapsedTime(&ms, pool[t.slot], pool[t.slot + 1]) == hipSuccess) {
-            S->prof_us[t.kind] += 1000.0 * (double)ms;
-            S->prof_n[t.kind] += 1;
-        }
-    }
-}
-
 }  // namespace
 
 static fk_status finish_solve(fk_solver S);
 
-extern "C" fk_status fk_solve(fk_solver S, const double *b, double *x)
+// Multi-kernel solve: writes the initial state (rtol, max_iter, hist_cap),
+// enqueues the setup and batches of `unroll` iterations with one batch in
+// flight ahead of the one waited for, and leaves the final state in S->last.
+static fk_status run_batches(fk_solver S, const double *b, double *x, double rtol, int64_t max_iter,
+                             int32_t hist_cap, bool profile, bool graph)
 {
-    if (!S || !b || !x)
-        return fail(FK_E_ARG, "NULL argument");
-    S->solved = false;
-    const bool profile = (S->o.flags & FK_FLAG_PROFILE) != 0;
-    const bool graph = !profile && (S->o.flags & FK_FLAG_GRAPH) != 0 && S->stream != nullptr;
-    if (profile) {
-        for (int k = 0; k < FK_KERNEL_KINDS; ++k) {
-            S->prof_us[k] = 0.0;
-            S->prof_n[k] = 0;
-        }
-    }
-
     DevState init{};
     init.status = ST_RUNNING;
-    init.rtol = S->o.rtol;
-    init.max_iter = S->o.max_iter;
-    init.hist_cap = S->hist_cap;
-    *S->h_init = init;
-    HIP_TRY(hipMemcpyAsync(S->st, S->h_init, sizeof(DevState), hipMemcpyHostToDevice, S->stream));
+    init.rtol = rtol;
+    init.max_iter = (int32_t)max_iter;
+    init.hist_cap = hist_cap;
+    S->h_init[0] = init;
+    HIP_TRY(hipMemcpyAsync(S->st, &S->h_init[0], sizeof(DevState), hipMemcpyHostToDevice, S->stream));
 
-    if (S->small) {
-        const bool bicg = S->o.method == FK_BICGSTAB_PIPELINED;
-        std::vector<hipEvent_t> &pool = S->prof_ev[0];
-        if (profile) {
-            while (pool.size() < 2) {
-                hipEvent_t ev;
-                HIP_TRY(hipEventCreate(&ev));
-                pool.push_back(ev);
-            }
-            set_launch_timing(pool[0], pool[1]);
-        }
-        hipError_t es = launch_small(bicg, S->A->view(), b, x, S->st, S->hist, S->scal,
-                                     S->small_stage, S->stream);
-        set_launch_timing(nullptr, nullptr);
-        if (es != hipSuccess)
-            return fail(FK_E_HIP, "single-workgroup solve: %s", hipGetErrorString(es));
-        HIP_TRY(hipMemcpyAsync(&S->last, S->st, sizeof(DevState), hipMemcpyDeviceToHost, S->stream));
-        HIP_TRY(hipStreamSynchronize(S->stream));
-        if (profile) {
-            float ms = 0.f;
-            if (hipEventElapsedTime(&ms, pool[0], pool[1]) == hipSuccess) {
-                S->prof_us[FK_KERNEL_SMALL] = 1000.0 * (double)ms;
-                S->prof_n[FK_KERNEL_SMALL] = 1;
-            }
-        }
-        if (S->last.status == ST_ZERO_RHS) {
-            HIP_TRY(hipMemsetAsync(x, 0, (size_t)S->n * sizeof(double), S->stream));
-            HIP_TRY(hipStreamSynchronize(S->stream));
-        }
-        return finish_solve(S);
-    }
-
-    const int64_t max_iter = S->o.max_iter;
     const int U = S->o.unroll;
     int64_t launched = 0;
     int cur = 0;
@@ -799,9 +842,119 @@ extern "C" fk_status fk_solve(fk_solver S, const double *b, double *x)
             break;
         cur ^= 1;
     }
-    HIP_TRY(hipMemcpyAsync(S->h_init, S->st, sizeof(DevState), hipMemcpyDeviceToHost, S->stream));
+    HIP_TRY(hipMemcpyAsync(&S->h_init[2], S->st, sizeof(DevState), hipMemcpyDeviceToHost, S->stream));
     HIP_TRY(hipStreamSynchronize(S->stream));
-    S->last = *S->h_init;
+    S->last = S->h_init[2];
+    return FK_OK;
+}
+
+// Iterative refinement around the FP32 inner solver (FK_CG_MIXED).
+static fk_status solve_mixed(fk_solver S, const double *b, double *x, bool profile, bool graph)
+{
+    DevState init{};
+    init.status = ST_RUNNING;
+    init.rtol = S->o.rtol;
+    init.max_iter = S->o.max_outer;
+    init.hist_cap = S->hist_cap;
+    S->h_init[1] = init;
+    HIP_TRY(hipMemcpyAsync(S->st_outer, &S->h_init[1], sizeof(DevState), hipMemcpyHostToDevice, S->stream));
+    hipError_t e = mixed_outer(S, b, x, false, profile);  // r_0
+    if (e != hipSuccess)
+        return fail(FK_E_HIP, "refinement residual: %s", hipGetErrorString(e));
+    DevState outer = S->h_init[2];
+    int64_t used = 0;
+    while (outer.status == ST_RUNNING) {
+        if (S->sweeps >= S->o.max_outer || used >= S->o.max_iter) {
+            outer.status = ST_NOT_CONVERGED;
+            break;
+        }
+        fk_status fs = run_batches(S, nullptr, x, S->o.inner_rtol, S->o.max_iter - used, 0, profile, graph);
+        if (fs != FK_OK)
+            return fs;
+        used += S->last.it;
+        if (S->last.status == ST_BREAKDOWN) {
+            outer.status = ST_BREAKDOWN;
+            break;
+        }
+        if (S->last.it == 0) {  // no inner iteration: the correction would be 0
+            outer.status = ST_NOT_CONVERGED;
+            break;
+        }
+        e = mixed_outer(S, b, x, true, profile);  // x_{j+1} = x_j + d; r_{j+1}
+        if (e != hipSuccess)
+            return fail(FK_E_HIP, "refinement step: %s", hipGetErrorString(e));
+        S->sweeps++;
+        outer = S->h_init[2];
+    }
+    if (outer.status == ST_ZERO_RHS) {
+        HIP_TRY(hipMemsetAsync(x, 0, (size_t)S->n * sizeof(double), S->stream));
+        HIP_TRY(hipStreamSynchronize(S->stream));
+    }
+    outer.it = (int32_t)used;
+    S->last = outer;
+    return finish_solve(S);
+}
+
+extern "C" fk_status fk_solve(fk_solver S, const double *b, double *x)
+{
+    if (!S || !b || !x)
+        return fail(FK_E_ARG, "NULL argument");
+    S->solved = false;
+    S->sweeps = 0;
+    const bool profile = (S->o.flags & FK_FLAG_PROFILE) != 0;
+    const bool graph = !profile && (S->o.flags & FK_FLAG_GRAPH) != 0 && S->stream != nullptr;
+    if (profile) {
+        for (int k = 0; k < FK_KERNEL_KINDS; ++k) {
+            S->prof_us[k] = 0.0;
+            S->prof_n[k] = 0;
+        }
+    }
+    if (S->mixed)
+        return solve_mixed(S, b, x, profile, graph);
+
+    if (S->small) {
+        DevState init{};
+        init.status = ST_RUNNING;
+        init.rtol = S->o.rtol;
+        init.max_iter = S->o.max_iter;
+        init.hist_cap = S->hist_cap;
+        S->h_init[0] = init;
+        HIP_TRY(hipMemcpyAsync(S->st, &S->h_init[0], sizeof(DevState), hipMemcpyHostToDevice, S->stream));
+        const bool bicg = S->o.method == FK_BICGSTAB_PIPELINED;
+        std::vector<hipEvent_t> &pool = S->prof_ev[0];
+        if (profile) {
+            while (pool.size() < 2) {
+                hipEvent_t ev;
+                HIP_TRY(hipEventCreate(&ev));
+                pool.push_back(ev);
+            }
+            set_launch_timing(pool[0], pool[1]);
+        }
+        hipError_t es = launch_small(bicg, S->A->view(), b, x, S->st, S->hist, S->scal,
+                                     S->small_stage, S->stream);
+        set_launch_timing(nullptr, nullptr);
+        if (es != hipSuccess)
+            return fail(FK_E_HIP, "single-workgroup solve: %s", hipGetErrorString(es));
+        HIP_TRY(hipMemcpyAsync(&S->h_init[2], S->st, sizeof(DevState), hipMemcpyDeviceToHost, S->stream));
+        HIP_TRY(hipStreamSynchronize(S->stream));
+        S->last = S->h_init[2];
+        if (profile) {
+            float ms = 0.f;
+            if (hipEventElapsedTime(&ms, pool[0], pool[1]) == hipSuccess) {
+                S->prof_us[FK_KERNEL_SMALL] = 1000.0 * (double)ms;
+                S->prof_n[FK_KERNEL_SMALL] = 1;
+            }
+        }
+        if (S->last.status == ST_ZERO_RHS) {
+            HIP_TRY(hipMemsetAsync(x, 0, (size_t)S->n * sizeof(double), S->stream));
+            HIP_TRY(hipStreamSynchronize(S->stream));
+        }
+        return finish_solve(S);
+    }
+
+    fk_status fs = run_batches(S, b, x, S->o.rtol, S->o.max_iter, S->hist_cap, profile, graph);
+    if (fs != FK_OK)
+        return fs;
     return finish_solve(S);
 }
 
@@ -837,6 +990,16 @@ extern "C" fk_status fk_solver_uses_small(fk_solver S, int32_t *small)
     return FK_OK;
 }
 
+extern "C" fk_status fk_get_refinements(fk_solver S, int32_t *sweeps)
+{
+    if (!S || !sweeps)
+        return fail(FK_E_ARG, "NULL argument");
+    if (!S->solved)
+        return fail(FK_E_STATE, "no completed solve");
+    *sweeps = S->sweeps;
+    return FK_OK;
+}
+
 extern "C" fk_status fk_get_iterations(fk_solver S, int32_t *k)
 {
     if (!S || !k)
@@ -865,7 +1028,7 @@ extern "C" fk_status fk_get_residual_history(fk_solver S, double *out, int32_t c
         return fail(FK_E_STATE, "no completed solve");
     if (!S->hist)
         return fail(FK_E_STATE, "solver created without record_history");
-    *len = S->last.it + 1;
+    *len = S->mixed ? S->sweeps + 1 : S->last.it + 1;
     const int32_t m = std::min(std::min(cap, *len), S->hist_cap);
     if (m > 0)
         HIP_TRY(hipMemcpyAsync(out, S->hist, (size_t)m * sizeof(double), hipMemcpyDeviceToHost, S->stream));
@@ -879,6 +1042,8 @@ extern "C" fk_status fk_get_scalars(fk_solver S, double *out, int32_t cap, int32
         return fail(FK_E_ARG, "bad argument");
     if (!S->solved)
         return fail(FK_E_STATE, "no completed solve");
+    if (S->mixed)
+        return fail(FK_E_STATE, "no per-iteration scalars for the mixed-precision method");
     if (!S->scal)
         return fail(FK_E_STATE, "solver created without record_history");
     *len = S->last.it;

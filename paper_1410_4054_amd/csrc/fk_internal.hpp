@@ -81,6 +81,7 @@ enum Fin : int32_t {
     FIN_C_B_RR,         // classical BiCGStab: d = {<r,r>}
     FIN_C_B_RHO,        // classical BiCGStab: d = {<r,r0*>}
     FIN_HALF_DONE,      // BiCGStab half-step exit bookkeeping (no dots)
+    FIN_MIX_OUTER,      // mixed precision: d = {<r,r>, <b,b>} of the FP64 true residual
 };
 
 // Everything a reduction point needs.
@@ -144,6 +145,21 @@ hipError_t launch_xpay(int64_t n, double *p, const double *r, const double *v,
 hipError_t launch_copy_fin(int64_t n, double *dst, const double *src, const RedArgs &red,
                            hipStream_t s);
 hipError_t launch_copy(void *dst, const void *src, int64_t n_bytes, int grid, hipStream_t s);
+
+// Mixed precision (FP32 inner pipelined CG inside FP64 iterative refinement).
+// r32 = (float)(b - A x) with FP64 <r,r>, <b,b> (FIN_MIX_OUTER).
+hipError_t launch_residual32(const DevCsr &A, const double *b, const double *x, float *r32,
+                             const RedArgs &red, int grid, hipStream_t s);
+// y = A32 v with FP32 <y,v>, <y,y> (FIN_CG_ALPHA on the inner state).
+hipError_t launch_spmv32(const DevCsr &A, const float *vals32, const float *v, float *y,
+                         const RedArgs &red, int grid, hipStream_t s);
+hipError_t launch_cg_update32(int64_t n, float *d, float *r, float *p, const float *ap,
+                              const RedArgs &red, int grid, hipStream_t s);
+// p = r, d = 0, FP32 <r,r> twice (FIN_SETUP on the inner state).
+hipError_t launch_inner_setup32(int64_t n, const float *r, float *p, float *d, const RedArgs &red,
+                                int grid, hipStream_t s);
+hipError_t launch_add32(int64_t n, double *x, const float *d, int grid, hipStream_t s);
+hipError_t launch_to_f32(int64_t n, float *out, const double *in, int grid, hipStream_t s);
 
 // Single-workgroup solver (whole solve in one launch) for small systems.
 // Rows per thread: 1, 2, 4 or 8 (0 = too large); LDS bytes it needs.

@@ -394,6 +394,33 @@ __device__ void finalize(DevState *st, int fin, const double *d, int K, double *
             st->status = ST_NOT_CONVERGED;
         break;
     }
+    case FIN_MIX_OUTER: {  // mixed precision: d = {<r,r>, <b,b>} of r = b - A x in FP64
+        const double rr = d[0], bb = d[1];
+        const int it = st->it;  // residuals evaluated so far
+        if (it == 0) {
+            if (bb == 0.0) {
+                st->bnorm = 0.0;
+                st->tol = 0.0;
+                st->last_rel = 0.0;
+                put_hist(st, hist, 0, 0.0);
+                st->it = 1;
+                st->status = ST_ZERO_RHS;
+                break;
+            }
+            st->bnorm = sqrt(bb);
+            st->tol = st->rtol * st->bnorm;
+        }
+        st->rr = rr;
+        const double rel = sqrt(rr) / st->bnorm;
+        st->last_rel = rel;
+        put_hist(st, hist, it, rel);
+        st->it = it + 1;
+        if (!isfinite(rr))
+            st->status = ST_BREAKDOWN;
+        else if (sqrt(rr) <= st->tol)
+            st->status = ST_CONVERGED;
+        break;
+    }
     case FIN_HALF_DONE: {  // BiCGStab exit after the half step
         const int it = st->it + 1;
         st->it = it;
@@ -508,16 +535,18 @@ __device__ __forceinline__ void reduce_point(dd (&v)[K], const RedArgs &red, int
 constexpr int popc3(int b) { return (b & 1) + ((b >> 1) & 1) + ((b >> 2) & 1); }
 
 enum RowMode : int {
-    ROW_SPMV = 0,   // y = A v, dots selected by DOTS
-    ROW_RESID = 1,  // r = b - A x, p = r (and rs = r); dots <r,r>, <b,b>
+    ROW_SPMV = 0,    // y = A v, dots selected by DOTS
+    ROW_RESID = 1,   // r = b - A x, p = r (and rs = r); dots <r,r>, <b,b>
+    ROW_RESID32 = 2, // r = b - A x rounded to FP32 (r32); dots <r,r>, <b,b> of the FP64 r
 };
 
 struct RowIo {
     const double *v;  // vector multiplied (p, s or x)
     double *y;        // result (ROW_SPMV) / r (ROW_RESID)
-    const double *w;  // third vector of <y,w> (ROW_SPMV) / b (ROW_RESID)
+    const double *w;  // third vector of <y,w> (ROW_SPMV) / b (ROW_RESID*)
     double *p;        // ROW_RESID: p = r
     double *rs;       // ROW_RESID: r0* = r (may be null)
+    float *r32;       // ROW_RESID32: FP32 copy of r
 };
 
 template <int MODE, int DOTS, int K>
@@ -533,12 +562,17 @@ __device__ __forceinline__ void row_epilogue(const RowIo &io, int row, double q,
         (void)k;
         (void)vrow;
         (void)wrow;
-    } else {
+    } else if constexpr (MODE == ROW_RESID) {
         const double ri = wrow - q;  // wrow = b_i
         io.y[row] = ri;
         io.p[row] = ri;
         if (io.rs)
             io.rs[row] = ri;
+        dd_fma(acc[0], ri, ri);
+        dd_fma(acc[1], wrow, wrow);
+    } else {
+        const double ri = wrow - q;  // wrow = b_i
+        io.r32[row] = (float)ri;
         dd_fma(acc[0], ri, ri);
         dd_fma(acc[1], wrow, wrow);
     }
@@ -556,10 +590,10 @@ __global__ __launch_bounds__(WG, FK_SPMV_MIN_WAVES) void k_csr_rows(DevCsr A, Ro
 {
     if (!runs(red))
         return;
-    constexpr int K = (MODE == ROW_RESID) ? 2 : popc3(DOTS);
+    constexpr int K = (MODE != ROW_SPMV) ? 2 : popc3(DOTS);
     constexpr int KA = K > 0 ? K : 1;
     constexpr bool NEED_V = MODE == ROW_SPMV && (DOTS & D_YV) != 0;
-    constexpr bool NEED_W = MODE == ROW_RESID || (DOTS & D_YW) != 0;
+    constexpr bool NEED_W = MODE != ROW_SPMV || (DOTS & D_YW) != 0;
     __shared__ double prod[NNZ_MAX];
     __shared__ int32_t rptr[WG + 1];
     __shared__ double red_lds[WAVES];
@@ -809,6 +843,164 @@ __global__ __launch_bounds__(WG) void k_zero(double *__restrict__ x, int64_t n,
     const int64_t stride = (int64_t)gridDim.x * WG;
     for (int64_t i = (int64_t)blockIdx.x * WG + threadIdx.x; i < n; i += stride)
         x[i] = 0.0;
+}
+
+// ------------------------------------- mixed precision: FP32 inner solver
+
+// Fixed-order workgroup sum of one float (long CSR rows of the FP32 product).
+__device__ __forceinline__ float block_sum_f(float v, float *lds)
+{
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1)
+        v = v + __shfl_xor(v, off, 64);
+    if (lane == 0)
+        lds[wave] = v;
+    __syncthreads();
+    float s = lds[0];
+    for (int w = 1; w < WAVES; ++w)
+        s = s + lds[w];
+    __syncthreads();
+    return s;
+}
+
+// y = A v in FP32 storage and arithmetic (values rounded to FP32 once, when
+// the solver is created), each row summed left to right in FP32, fused with
+// the first stage of <y, v>, <y, y>: the product kernel of the inner
+// pipelined CG of the mixed-precision method.  The product of two floats is
+// exact in FP64, so the dots accumulate exact products in double-double, as
+// on the FP64 path, and do not depend on the launch shape.
+__global__ __launch_bounds__(WG, FK_SPMV_MIN_WAVES) void k_csr_rows32(DevCsr A, const float *vals32,
+                                                                       const float *v, float *y,
+                                                                       RedArgs red)
+{
+    if (!runs(red))
+        return;
+    __shared__ float prod[NNZ_MAX];
+    __shared__ int32_t rptr[WG + 1];
+    __shared__ float red_lds[WAVES];
+    const int G = gridDim.x;
+    const int g = logical_wg();
+    const int b_begin = (int)(((int64_t)A.nblocks * g) / G);
+    const int b_end = (int)(((int64_t)A.nblocks * (g + 1)) / G);
+    const int tid = threadIdx.x;
+    dd acc[2] = {dd{0.0, 0.0}, dd{0.0, 0.0}};
+    for (int blk = b_begin; blk < b_end; ++blk) {
+        const int r0 = A.blocks[blk];
+        const int r1 = A.blocks[blk + 1];
+        const int j0 = A.block_j0[blk];
+        const int nrows = r1 - r0;
+        const int nz = A.block_j0[blk + 1] - j0;
+        if (nz <= NNZ_MAX) {
+            float vrow = 0.f;
+            if (tid < nrows) {
+                vrow = v[r0 + tid];
+                rptr[tid] = A.row_ptr[r0 + tid] - j0;
+            }
+            if (tid == 0)
+                rptr[nrows] = nz;
+            int ci[ITEMS];
+            float va[ITEMS];
+#pragma unroll
+            for (int i = 0; i < ITEMS; ++i) {
+                const int e = tid + i * WG;
+                if (e < nz) {
+                    ci[i] = A.col_idx[j0 + e];
+                    va[i] = vals32[j0 + e];
+                }
+            }
+#pragma unroll
+            for (int i = 0; i < ITEMS; ++i) {
+                const int e = tid + i * WG;
+                if (e < nz)
+                    prod[e] = va[i] * v[ci[i]];
+            }
+            __syncthreads();
+            if (tid < nrows) {
+                const int e0 = rptr[tid], e1 = rptr[tid + 1];
+                float q = 0.f;
+                for (int e = e0; e < e1; ++e)
+                    q = q + prod[e];
+                y[r0 + tid] = q;
+                dd_fma(acc[0], (double)q, (double)vrow);
+                dd_fma(acc[1], (double)q, (double)q);
+            }
+            __syncthreads();
+        } else {
+            float part = 0.f;
+            for (int e = tid; e < nz; e += WG)
+                part = part + vals32[j0 + e] * v[A.col_idx[j0 + e]];
+            const float q = block_sum_f(part, red_lds);
+            if (tid == 0) {
+                y[r0] = q;
+                dd_fma(acc[0], (double)q, (double)v[r0]);
+                dd_fma(acc[1], (double)q, (double)q);
+            }
+        }
+    }
+    reduce_point<2>(acc, red, g, G);
+}
+
+// Inner FP32 update of Algorithm 2 (alpha, beta rounded to FP32):
+// d += alpha p; r -= alpha A p; p = r + beta p; first stage of <r, r>.
+__global__ __launch_bounds__(WG) void k_cg_update32(int64_t n, float *__restrict__ d,
+                                                     float *__restrict__ r, float *__restrict__ p,
+                                                     const float *__restrict__ ap, RedArgs red)
+{
+    if (!runs(red))
+        return;
+    const float alpha = (float)red.st->alpha;
+    const float beta = (float)red.st->beta;
+    dd acc[1] = {dd{0.0, 0.0}};
+    const int64_t stride = (int64_t)gridDim.x * WG;
+    for (int64_t i = (int64_t)blockIdx.x * WG + threadIdx.x; i < n; i += stride) {
+        const float pi = p[i];
+        d[i] = d[i] + alpha * pi;
+        const float ri = r[i] - alpha * ap[i];
+        r[i] = ri;
+        p[i] = ri + beta * pi;
+        dd_fma(acc[0], (double)ri, (double)ri);
+    }
+    reduce_point<1>(acc, red, blockIdx.x, gridDim.x);
+}
+
+// Inner start (d0 = 0): p = r, d = 0, first stage of <r, r> (reported twice,
+// as the residual norm and as the norm of the inner right-hand side).
+__global__ __launch_bounds__(WG) void k_inner_setup32(int64_t n, const float *__restrict__ r,
+                                                       float *__restrict__ p, float *__restrict__ d,
+                                                       RedArgs red)
+{
+    if (!runs(red))
+        return;
+    dd acc[2] = {dd{0.0, 0.0}, dd{0.0, 0.0}};
+    const int64_t stride = (int64_t)gridDim.x * WG;
+    for (int64_t i = (int64_t)blockIdx.x * WG + threadIdx.x; i < n; i += stride) {
+        const float ri = r[i];
+        p[i] = ri;
+        d[i] = 0.f;
+        dd_fma(acc[0], (double)ri, (double)ri);
+        dd_fma(acc[1], (double)ri, (double)ri);
+    }
+    reduce_point<2>(acc, red, blockIdx.x, gridDim.x);
+}
+
+// x += d in FP64 (the refinement's correction).
+__global__ __launch_bounds__(WG) void k_add32(int64_t n, double *__restrict__ x,
+                                               const float *__restrict__ d)
+{
+    const int64_t stride = (int64_t)gridDim.x * WG;
+    for (int64_t i = (int64_t)blockIdx.x * WG + threadIdx.x; i < n; i += stride)
+        x[i] = x[i] + (double)d[i];
+}
+
+// FP64 values rounded to FP32.
+__global__ __launch_bounds__(WG) void k_to_f32(int64_t n, float *__restrict__ out,
+                                                const double *__restrict__ in)
+{
+    const int64_t stride = (int64_t)gridDim.x * WG;
+    for (int64_t i = (int64_t)blockIdx.x * WG + threadIdx.x; i < n; i += stride)
+        out[i] = (float)in[i];
 }
 
 // ------------------------------------------- single-workgroup solver
@@ -1233,7 +1425,7 @@ void set_launch_timing(hipEvent_t start, hipEvent_t stop)
 hipError_t launch_spmv_dots(const DevCsr &A, const double *v, double *y, const double *w,
                             int dots, const RedArgs &red, int grid, hipStream_t s)
 {
-    RowIo io{v, y, w, nullptr, nullptr};
+    RowIo io{v, y, w, nullptr, nullptr, nullptr};
     switch (dots) {
     case 0: return launch(k_csr_rows<ROW_SPMV, 0>, grid, WG, s, A, io, red);
     case D_YV | D_YY: return launch(k_csr_rows<ROW_SPMV, D_YV | D_YY>, grid, WG, s, A, io, red);
@@ -1246,8 +1438,43 @@ hipError_t launch_spmv_dots(const DevCsr &A, const double *v, double *y, const d
 hipError_t launch_residual0(const DevCsr &A, const double *b, const double *x, double *r,
                             double *p, double *rs, const RedArgs &red, int grid, hipStream_t s)
 {
-    RowIo io{x, r, b, p, rs};
+    RowIo io{x, r, b, p, rs, nullptr};
     return launch(k_csr_rows<ROW_RESID, 0>, grid, WG, s, A, io, red);
+}
+
+hipError_t launch_residual32(const DevCsr &A, const double *b, const double *x, float *r32,
+                             const RedArgs &red, int grid, hipStream_t s)
+{
+    RowIo io{x, nullptr, b, nullptr, nullptr, r32};
+    return launch(k_csr_rows<ROW_RESID32, 0>, grid, WG, s, A, io, red);
+}
+
+hipError_t launch_spmv32(const DevCsr &A, const float *vals32, const float *v, float *y,
+                         const RedArgs &red, int grid, hipStream_t s)
+{
+    return launch(k_csr_rows32, grid, WG, s, A, vals32, v, y, red);
+}
+
+hipError_t launch_cg_update32(int64_t n, float *d, float *r, float *p, const float *ap,
+                              const RedArgs &red, int grid, hipStream_t s)
+{
+    return launch(k_cg_update32, grid, WG, s, n, d, r, p, ap, red);
+}
+
+hipError_t launch_inner_setup32(int64_t n, const float *r, float *p, float *d, const RedArgs &red,
+                                int grid, hipStream_t s)
+{
+    return launch(k_inner_setup32, grid, WG, s, n, r, p, d, red);
+}
+
+hipError_t launch_add32(int64_t n, double *x, const float *d, int grid, hipStream_t s)
+{
+    return launch(k_add32, grid, WG, s, n, x, d);
+}
+
+hipError_t launch_to_f32(int64_t n, float *out, const double *in, int grid, hipStream_t s)
+{
+    return launch(k_to_f32, grid, WG, s, n, out, in);
 }
 
 hipError_t launch_cg_update(int64_t n, double *x, double *r, double *p, const double *ap,

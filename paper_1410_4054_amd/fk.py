@@ -23,12 +23,13 @@ STATUS_NAMES = {
     OK: "converged", NOT_CONVERGED: "not_converged", BREAKDOWN: "breakdown",
 }
 # fk_method
-METHODS = {"cg_pipelined": 0, "cg_classical": 1, "bicgstab_pipelined": 2, "bicgstab_classical": 3}
+METHODS = {"cg_pipelined": 0, "cg_classical": 1, "bicgstab_pipelined": 2, "bicgstab_classical": 3,
+           "cg_mixed": 4}
 FLAG_GRAPH = 1
 FLAG_PROFILE = 2
 FLAG_NO_SMALL = 4
 PTR_HOST, PTR_DEVICE = 0, 1
-KERNEL_KINDS = ("setup", "spmv_dot", "update_dot", "spmv", "dot", "axpy", "small")
+KERNEL_KINDS = ("setup", "spmv_dot", "update_dot", "spmv", "dot", "axpy", "small", "residual")
 LONG_ROW = 2048
 
 
@@ -46,6 +47,8 @@ class _Opts(ctypes.Structure):
         ("record_history", ctypes.c_int32),
         ("unroll", ctypes.c_int32),
         ("flags", ctypes.c_int32),
+        ("inner_rtol", ctypes.c_double),
+        ("max_outer", ctypes.c_int32),
     ]
 
 
@@ -86,6 +89,7 @@ def lib():
             "fk_get_kernel_times": [vp, P(f64), P(i32), i32],
             "fk_solver_destroy": [vp],
             "fk_solver_uses_small": [vp, P(i32)],
+            "fk_get_refinements": [vp, P(i32)],
             "fk_spmv": [vp, vp, vp, P(f64), vp],
             "fk_dot": [i64, vp, vp, P(f64), vp],
             "fk_copy": [vp, vp, i64, vp],
@@ -109,7 +113,7 @@ def exported_symbols() -> list[str]:
         "fk_csr_create", "fk_csr_destroy", "fk_csr_shape", "fk_csr_blocks",
         "fk_solver_create", "fk_solve", "fk_get_iterations", "fk_get_residual",
         "fk_get_residual_history", "fk_get_scalars", "fk_get_kernel_times",
-        "fk_solver_destroy", "fk_solver_uses_small", "fk_spmv", "fk_dot", "fk_copy", "fk_status_str",
+        "fk_solver_destroy", "fk_solver_uses_small", "fk_get_refinements", "fk_spmv", "fk_dot", "fk_copy", "fk_status_str",
         "fk_last_error", "fk_version",
     ]
 
@@ -223,6 +227,7 @@ class SolveResult:
     rel_res: float
     history: np.ndarray | None
     scalars: np.ndarray | None  # (k, 4): alpha, beta, omega, <r,r> tested
+    sweeps: int = 0             # cg_mixed: refinement sweeps
 
 
 class Solver:
@@ -230,9 +235,11 @@ class Solver:
 
     def __init__(self, A: Matrix, method: str = "cg_pipelined", rtol: float = 1e-8,
                  max_iter: int | None = None, record_history: bool = True, unroll: int = 32,
-                 graph: bool = False, profile: bool = False, small: bool = True, stream=None):
+                 graph: bool = False, profile: bool = False, small: bool = True,
+                 inner_rtol: float = 0.0, max_outer: int = 0, stream=None):
         """small=False forces the multi-kernel path even where the
-        single-workgroup solver applies."""
+        single-workgroup solver applies.  inner_rtol, max_outer: options of
+        method "cg_mixed" (0 = library defaults 1e-4 and 50)."""
         import torch
 
         self.A = A
@@ -245,7 +252,7 @@ class Solver:
         flags = ((FLAG_GRAPH if graph else 0) | (FLAG_PROFILE if profile else 0)
                  | (0 if small else FLAG_NO_SMALL))
         o = _Opts(METHODS[method], float(rtol), int(max_iter), int(bool(record_history)),
-                  int(unroll), flags)
+                  int(unroll), flags, float(inner_rtol), int(max_outer))
         h = ctypes.c_void_p()
         st = lib().fk_solver_create(A.handle, ctypes.byref(o), ctypes.c_void_p(_stream_ptr(stream)),
                                     ctypes.byref(h))
@@ -280,8 +287,13 @@ class Solver:
         _check(lib().fk_get_residual(self._h, ctypes.byref(r)), "fk_get_residual")
         return r.value
 
+    def refinements(self) -> int:
+        v = ctypes.c_int32()
+        _check(lib().fk_get_refinements(self._h, ctypes.byref(v)), "fk_get_refinements")
+        return v.value
+
     def history(self) -> np.ndarray:
-        k = self.iterations()
+        k = self.refinements() if self.method == "cg_mixed" else self.iterations()
         buf = np.empty(k + 1)
         ln = ctypes.c_int32()
         _check(lib().fk_get_residual_history(self._h, buf.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
@@ -323,7 +335,8 @@ def solve(A: Matrix, b, x, method: str = "cg_pipelined", rtol: float = 1e-8,
     try:
         st = S.solve(b, x)
         hist = S.history() if record_history else None
-        scal = S.scalars() if record_history else None
-        return SolveResult(STATUS_NAMES[st], S.iterations(), S.residual(), hist, scal)
+        scal = S.scalars() if record_history and method != "cg_mixed" else None
+        return SolveResult(STATUS_NAMES[st], S.iterations(), S.residual(), hist, scal,
+                           S.refinements())
     finally:
         S.close()

@@ -31,7 +31,10 @@ CASES = {
     "convdiff2d_1024_bicgstab_pipelined": ("convdiff2d_1024", "bicgstab_pipelined", 1e-8, None),
     "convdiff2d_1024_bicgstab_pipelined_30": ("convdiff2d_1024", "bicgstab_pipelined", 0.0, 30),
     "poisson3d_128_cg_pipelined_30": ("poisson3d_128", "cg_pipelined", 0.0, 30),
+    # FP64 iterative refinement around FP32 pipelined CG (inner_rtol 1e-4)
+    "poisson3d_128_cg_mixed": ("poisson3d_128", "cg_mixed", 1e-10, None),
 }
+INNER_RTOL = 1e-4
 NSAMPLES = 4099
 
 
@@ -43,10 +46,16 @@ def make(name: str) -> dict:
     workload, method, rtol, max_iter = CASES[name]
     A, b, x0 = P.workload(workload)
     t0 = time.time()
-    res = oracle.solve(A, b, x0=x0, method=method, rtol=rtol, max_iter=max_iter)
+    extra = {}
+    if method == "cg_mixed":
+        res = oracle.solve_mixed(A, b, x0=x0, rtol=rtol, inner_rtol=INNER_RTOL, max_iter=max_iter)
+        extra = {"inner_rtol": INNER_RTOL, "sweeps": res.sweeps,
+                 "inner_k": [int(k) for k in res.inner_k]}
+    else:
+        res = oracle.solve(A, b, x0=x0, method=method, rtol=rtol, max_iter=max_iter)
     dt = time.time() - t0
     idx = sample_indices(A.n)
-    return {
+    return extra | {
         "case": name,
         "workload": workload,
         "method": method,

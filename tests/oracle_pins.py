@@ -299,6 +299,119 @@ def pin_breakdown(O):
         assert O.solve(A, b, method=m).status == "breakdown", m
 
 
+# ------------------------------------ iterative refinement, FP32 inner CG
+
+def pin_f32_products(O):
+    """FP32 CSR product and FP32 dot of the refinement's inner solver: the
+    product bit for bit against numpy float32 scalar arithmetic (IEEE single,
+    one rounding per operation, rows left to right); the dot within one
+    rounding of the exact rational value of the float operands."""
+    A = P.random_csr(50, 5, seed=11, empty_rows=3, long_rows={5: 30})
+    p = np.random.default_rng(12).uniform(-1, 1, A.n).astype(np.float32)
+    q = O.spmv_f32(A, p)
+    v32 = A.vals.astype(np.float32)
+    for i in range(A.n):
+        acc = np.float32(0.0)
+        for j in range(A.row_ptr[i], A.row_ptr[i + 1]):
+            acc = np.float32(acc + np.float32(v32[j] * p[A.col_idx[j]]))
+        assert q[i] == acc, (i, q[i], acc)
+    rng = np.random.default_rng(13)
+    for n in (1, 7, 300):
+        a = rng.standard_normal(n).astype(np.float32)
+        b = rng.standard_normal(n).astype(np.float32)
+        exact = sum(Fraction(float(x)) * Fraction(float(y)) for x, y in zip(a, b))
+        got = O.dot_f32(a, b)
+        assert abs(Fraction(got) - exact) <= abs(exact) * Fraction(2) ** -52, (n, got, float(exact))
+
+
+def pin_mixed_identity(O):
+    """A = 4 I with b exactly representable in FP32: the inner CG takes one
+    step (alpha = 1/4, beta = 0), the FP64 update gives x = b/4 exactly and
+    the next residual is 0, so one sweep and one inner iteration."""
+    A = P.scaled_identity(12, 4.0)
+    b = np.arange(-6.0, 6.0) / 8.0 + 0.03125
+    res = O.solve_mixed(A, b, rtol=1e-14)
+    assert res.status == "converged" and res.sweeps == 1 and res.k == 1, res
+    assert np.array_equal(res.x, b / 4.0)
+    assert res.hist[1] == 0.0 and res.hist[0] == 1.0
+
+
+def pin_mixed_eigen_termination(O):
+    """b spanning 3 Laplacian eigenvectors with distinct eigenvalues (closed
+    form): the FP32 inner CG of the first sweep terminates after exactly 3
+    iterations at inner_rtol = 1e-3 (finite termination of Algorithm 2)."""
+    n = 20
+    A = P.poisson2d(n)
+    picks = [(1, 2), (3, 3), (6, 1)]
+    b = sum((i + 1.0) * P.laplacian_eigvec_2d(n, j, k) for i, (j, k) in enumerate(picks))
+    res = O.solve_mixed(A, b, rtol=1e-10, inner_rtol=1e-3)
+    assert res.status == "converged", res
+    assert res.inner_k[0] == len(picks), res.inner_k
+
+
+def pin_mixed_exact_poisson(O):
+    """Refinement on Poisson problems solved exactly by the sine transform:
+    x within kappa*rtol of the exact solution, the last recorded residual
+    equal to the true residual computed by scipy, and every sweep cutting
+    the residual by at least 1e-3 (inner_rtol = 1e-4, kappa * eps_32 << 1)."""
+    rtol = 1e-11
+    for A, (xs, kappa) in (
+        (P.poisson2d(31), _dst_solve_2d(31, P.rhs_uniform(31 * 31, 0))),
+        (P.poisson3d(15), _dst_solve_3d(15, P.rhs_uniform(15 ** 3, 0))),
+    ):
+        b = P.rhs_uniform(A.n, 0)
+        res = O.solve_mixed(A, b, rtol=rtol, inner_rtol=1e-4)
+        assert res.status == "converged", res
+        assert _rel(res.x, xs) <= kappa * rtol * 1.01, _rel(res.x, xs)
+        tr = float(np.linalg.norm(b - A.to_scipy() @ res.x) / np.linalg.norm(b))
+        assert tr <= rtol and abs(res.hist[-1] - tr) <= 1e-3 * tr, (tr, res.hist)
+        assert res.hist[0] == 1.0
+        assert np.all(res.hist[1:] <= 1e-3 * res.hist[:-1]), res.hist
+        assert res.k == int(res.inner_k.sum())
+
+
+def pin_mixed_fp32_floor(O):
+    """One sweep with a very tight inner tolerance stops at the FP32 level:
+    the true residual of x_1 (scipy, FP64) lies between 1e-9 and 1e-4, far
+    above what the same number of FP64 iterations reaches, and equals the
+    recorded history entry."""
+    A = P.poisson2d(31)
+    b = P.rhs_uniform(A.n, 1)
+    res = O.solve_mixed(A, b, rtol=1e-14, inner_rtol=1e-13, max_iter=400, max_outer=1)
+    assert res.sweeps == 1 and res.status == "not_converged", res
+    tr = float(np.linalg.norm(b - A.to_scipy() @ res.x) / np.linalg.norm(b))
+    assert 1e-9 < tr < 1e-4, tr
+    assert abs(res.hist[1] - tr) <= 1e-6 * tr, (res.hist, tr)
+    r64 = O.solve(A, b, method="cg_pipelined", rtol=0.0, max_iter=res.k)
+    assert O.true_residual(A, b, r64.x) < 1e-3 * tr
+
+
+def pin_mixed_special_cases(O):
+    """b = 0 gives x = 0; limits on inner iterations and sweeps; an inner
+    tolerance >= 1 makes no step and ends the solve unconverged; a dense SPD
+    system reaches the LAPACK solution; a starting guess that already solves
+    the system gives no sweep."""
+    A = P.poisson2d(10)
+    b = P.rhs_uniform(A.n, 3)
+    z = O.solve_mixed(A, np.zeros(A.n), x0=np.ones(A.n))
+    assert z.status == "converged" and z.k == 0 and z.sweeps == 0 and not z.x.any()
+    r5 = O.solve_mixed(A, b, max_iter=5)
+    assert r5.status == "not_converged" and r5.k == 5 and r5.sweeps == 1, r5
+    r2 = O.solve_mixed(A, b, inner_rtol=0.5, max_outer=2)
+    assert r2.status == "not_converged" and r2.sweeps == 2 and len(r2.hist) == 3, r2
+    assert r2.hist[2] < r2.hist[1] < r2.hist[0]
+    s = O.solve_mixed(A, b, inner_rtol=2.0)
+    assert s.status == "not_converged" and s.k == 0 and s.sweeps == 0, s
+    Ad = P.random_spd_dense(30, 50.0, seed=8)
+    Ac = P.dense_to_csr(Ad)
+    bd = np.random.default_rng(9).standard_normal(30)
+    xs = np.linalg.solve(Ad, bd)
+    res = O.solve_mixed(Ac, bd, rtol=1e-12)
+    assert res.status == "converged" and _rel(res.x, xs) < 1e-10, res
+    w = O.solve_mixed(Ac, bd, x0=xs, rtol=1e-10)
+    assert w.status == "converged" and w.k == 0 and w.sweeps == 0, w
+
+
 PINS = [
     pin_spmv_bruteforce,
     pin_spmv_scipy,
@@ -313,4 +426,10 @@ PINS = [
     pin_classical_vs_pipelined,
     pin_special_cases,
     pin_breakdown,
+    pin_f32_products,
+    pin_mixed_identity,
+    pin_mixed_eigen_termination,
+    pin_mixed_exact_poisson,
+    pin_mixed_fp32_floor,
+    pin_mixed_special_cases,
 ]

@@ -39,6 +39,16 @@ MUTATIONS = [
     ("pbicg_rho_wrong_vector", "rho = oracle_dot(n, r, rs);                        /* <r_{i+1}, r0*> */",
      "rho = oracle_dot(n, r, r);", None),
     ("half_step_wrong_vector", "x[j] = x[j] + alpha * p[j];", "x[j] = x[j] + alpha * s[j];", 3),
+    ("f32_spmv_wrong_column", "acc = acc + v[j] * p[ci[j]];", "acc = acc + v[j] * p[i];", None),
+    ("f32_dot_drops_compensation", "        s = s + q;\n", "", None),
+    ("f32_cg_residual_wrong_operand", "r[j] = r[j] - af * ap[j];", "r[j] = r[j] - af * p[j];", None),
+    ("f32_cg_direction_sign", "p[j] = r[j] + bf * p[j];", "p[j] = r[j] - bf * p[j];", None),
+    ("f32_cg_beta_unrounded_alpha", "const float af = (float)alpha, bf = (float)beta;",
+     "const float af = (float)(0.5 * alpha), bf = (float)beta;", None),
+    ("mixed_update_sign", "x[j] = x[j] + (double)d[j];", "x[j] = x[j] - (double)d[j];", None),
+    ("mixed_solves_b_not_residual", "r32[j] = (float)r[j];", "r32[j] = (float)b[j];", None),
+    ("mixed_inner_tol_absolute", "double tol = rtol * sqrt(rr);", "double tol = rtol;", None),
+    ("mixed_values_perturbed", "v32[j] = (float)vals[j];", "v32[j] = (float)(vals[j] * 1.0000001);", None),
 ]
 
 
