@@ -48,6 +48,11 @@ def spmv_dot_bytes(n: int, nnz: int) -> int:
     return 12 * nnz + 4 * (n + 1) + 8 * n + 8 * n
 
 
+def spmv32_dot_bytes(n: int, nnz: int) -> int:
+    """The FP32 product + 2 dots of the mixed-precision inner solver."""
+    return 8 * nnz + 4 * (n + 1) + 4 * n + 4 * n
+
+
 def update_bytes(n: int) -> int:
     """x, r, p, Ap read; x, r, p written."""
     return 56 * n
@@ -122,6 +127,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
+    ap.add_argument("--no-learned", action="store_true",
+                    help="skip training and timing the learned initial guess")
     ap.add_argument("--cpu-iters", type=int, default=200,
                     help="iterations of the oracle timed for the CPU baseline")
     args = ap.parse_args()
@@ -233,6 +240,54 @@ def main():
         extras["bicgstab_convdiff2d_1024_iters_per_s"] = its3 / t3
         extras["bicgstab_convdiff2d_1024_k"] = S3.iterations()
         S3.close(); M3.close()
+
+        # Mixed precision: FP64 iterative refinement around FP32 pipelined CG
+        # against FP64 pipelined CG, both to 1e-10 on 128^3.
+        for label, kw in (("fp64_cg_pipelined", {"method": "cg_pipelined"}),
+                          ("mixed_fp32_inner", {"method": "cg_mixed", "inner_rtol": 1e-4})):
+            S2 = fk.Solver(M, rtol=1e-10, record_history=False, **kw)
+            xd.zero_(); S2.solve(bd, xd)
+            t2, _ = time_solves(torch, S2, bd, xd, 3)
+            extras[f"poisson3d_128_rtol1e-10_{label}_solves_per_s"] = 3 / t2
+            extras[f"poisson3d_128_rtol1e-10_{label}_iterations"] = S2.iterations()
+            if kw["method"] == "cg_mixed":
+                extras["poisson3d_128_rtol1e-10_mixed_sweeps"] = S2.refinements()
+            S2.close()
+        S2 = fk.Solver(M, method="cg_mixed", rtol=1e-10, record_history=False, profile=True)
+        xd.zero_(); S2.solve(bd, xd)
+        kt = S2.kernel_times()
+        S2.close()
+        extras["mixed_spmv32_dot_us"] = kt["spmv_dot"][0]
+        extras["mixed_spmv32_dot_GBps"] = spmv32_dot_bytes(n, nnz) / (kt["spmv_dot"][0] * 1e-6) / 1e9
+        extras["mixed_update32_dot_us"] = kt["update_dot"][0]
+        extras["mixed_update32_dot_GBps"] = 28 * n / (kt["update_dot"][0] * 1e-6) / 1e9
+        extras["mixed_residual_fp64_us"] = kt["residual"][0]
+
+        # Learned initial guess on the transient heat problem (512^2, 400
+        # steps, FP64 pipelined CG to 1e-8 per step): the network is trained
+        # on the solver's own solutions for seeds 1 and 2, then the 400 steps
+        # of seed 0 are run with each guess.
+        if not args.no_learned:
+            from paper_1410_4054_amd import warmstart as W
+
+            tg = time.perf_counter()
+            data = W.generate([1, 2])
+            torch.cuda.synchronize()
+            extras["heat512_training_data_seconds"] = time.perf_counter() - tg
+            net = fk.Net(4, P.net_init(4, 0))
+            tt = time.perf_counter()
+            losses = W.train(net, data, 800, report_every=799)
+            torch.cuda.synchronize()
+            extras["heat512_training_seconds_800_steps"] = time.perf_counter() - tt
+            extras["heat512_training_loss_first_last"] = [losses[0][1], losses[-1][1]]
+            del data
+            T = W.Transient(512, 0)
+            for pol in W.POLICIES:
+                T.run(pol, net=net)  # warm-up pass
+                r, _ = T.run(pol, net=net)
+                extras[f"heat512_400steps_{pol}_total_cg_iterations"] = r.total_iterations
+                extras[f"heat512_400steps_{pol}_solves_per_s"] = r.solves_per_s
+            net.close()
 
         # Latency-bound workload: 2D Poisson 32x32 (N = 1,024): the
         # single-workgroup solver (one launch per solve) against the grid

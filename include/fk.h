@@ -48,6 +48,7 @@ extern "C" {
 
 typedef struct fk_csr_s *fk_csr;
 typedef struct fk_solver_s *fk_solver;
+typedef struct fk_net_s *fk_net;
 
 typedef enum {
     FK_OK = 0,              /* success; for fk_solve: converged             */
@@ -213,8 +214,81 @@ fk_status fk_spmv(fk_csr A, const double *p_dev, double *q_dev, double *dots_hos
 /* <a, b> over n >= 0 device doubles, written to *out_host.  Synchronous. */
 fk_status fk_dot(int64_t n, const double *a_dev, const double *b_dev, double *out_host, void *hip_stream);
 
+/* out = alpha x + beta y over n >= 0 device doubles (out may alias x or y);
+ * enqueued on hip_stream, not waited for. */
+fk_status fk_axpby(int64_t n, double alpha, const double *x_dev, double beta, const double *y_dev,
+                   double *out_dev, void *hip_stream);
+
 /* Plain device copy of n_bytes (a streaming kernel, for bandwidth calibration). */
 fk_status fk_copy(void *dst_dev, const void *src_dev, int64_t n_bytes, void *hip_stream);
+
+/*
+ * Learned initial guess for a sequence of solves on an nx-by-ny grid (an
+ * extension for the many related small-to-medium systems of transient
+ * problems that motivate the paper, Section 1; the network itself is not in
+ * the paper).  Row i of the matrix is grid point (i % nx, i / nx), so
+ * n = nx * ny.  The network N is a learned local approximate inverse: from
+ * the residual r = b - A x of a guess x (FP64, rows summed in CSR order) it
+ * predicts a correction, x <- x + N(r).  A step starts from the
+ * extrapolation x = 2 u_m - u_{m-1} of the solutions of the two previous
+ * steps (pass u_m twice at the first step) and applies N `passes` times.
+ * N is a BF16 convolutional network run on the matrix cores: `layers` 3x3
+ * cross-correlations with zero padding and no bias (1 -> 16 -> ... -> 16 ->
+ * 1 channels, `channels` = 16), FP32 accumulation, with FK_NET_RELU or
+ * FK_NET_LINEAR (identity: a deep linear network, a learned linear
+ * approximate inverse) between layers.  N has no bias, so N(a r) = a N(r)
+ * for a > 0 (every a when linear): each pass works at the scale of its own
+ * residual and no normalisation is needed.
+ *
+ * Weights are FP32, layer after layer, each as W[co][ci][ky][kx] (kx along
+ * x, tap (kx, ky) reads the point (x + kx - 1, y + ky - 1)); the count is
+ * 16*9 + (layers-2)*16*16*9 + 16*9 (fk_net_num_weights).  The caller
+ * supplies the initial weights (the library draws no random numbers).
+ * Vectors are device float64[n]; calls on one network must not overlap.
+ */
+enum { FK_NET_RELU = 0, FK_NET_LINEAR = 1 };
+fk_status fk_net_num_weights(int32_t layers, int32_t channels, int64_t *count);
+fk_status fk_net_create(int32_t layers, int32_t channels, int32_t activation, const float *weights_host,
+                        int64_t count, fk_net *out);
+fk_status fk_net_destroy(fk_net N);
+fk_status fk_net_get_weights(fk_net N, float *weights_host, int64_t count);
+/* Replace the weights and reset the optimiser state. */
+fk_status fk_net_set_weights(fk_net N, const float *weights_host, int64_t count);
+
+/* Raw network output N(r) for r = b - A (2 u_m - u_{m-1}) into device
+ * float32 y[n].  Synchronous. */
+fk_status fk_net_forward(fk_net N, fk_csr A, int32_t nx, int32_t ny, const double *b_dev,
+                         const double *um_dev, const double *um1_dev, float *y_dev, void *hip_stream);
+
+/*
+ * x0 = g + N(b - A g) with g = 2 u_m - u_{m-1}, then passes - 1 more times
+ * x0 += N(b - A x0) (1 <= passes <= 16); then the fallback: if
+ * ||b - A x0|| > ||b - A u_m|| (or is not finite), x0 = u_m, the previous
+ * step's solution.  The guess only changes where the solver starts;
+ * fk_solve decides convergence.  Enqueued on hip_stream; if fallback_host
+ * is not NULL the call waits and writes 1 there when it fell back, else 0.
+ * x0 must not alias the inputs.
+ */
+fk_status fk_net_guess(fk_net N, fk_csr A, int32_t nx, int32_t ny, const double *b_dev,
+                       const double *um_dev, const double *um1_dev, int32_t passes, double *x0_dev,
+                       int32_t *fallback_host, void *hip_stream);
+
+/*
+ * Training on one sample (b, u_m, u_{m-1}) with known solution u_next:
+ * the plane r = b - A g and the target u_next - g are divided by s = max|r|
+ * (exact, order-independent), and the loss is mean((N - target)^2) over
+ * the grid.  (With u_m = u_{m-1} = 0 the sample is any pair r = b,
+ * target u_next.)  fk_net_gradient writes dloss/dweights (canonical order) and the
+ * loss to the host without changing the weights; fk_net_train_step takes
+ * one Adam step (beta1 0.9, beta2 0.999, eps 1e-8, step size lr) and, if
+ * loss_host is not NULL, waits and writes the loss before the step.
+ */
+fk_status fk_net_gradient(fk_net N, fk_csr A, int32_t nx, int32_t ny, const double *b_dev,
+                          const double *um_dev, const double *um1_dev, const double *unext_dev,
+                          float *grad_host, double *loss_host, void *hip_stream);
+fk_status fk_net_train_step(fk_net N, fk_csr A, int32_t nx, int32_t ny, const double *b_dev,
+                            const double *um_dev, const double *um1_dev, const double *unext_dev,
+                            float lr, double *loss_host, void *hip_stream);
 
 const char *fk_status_str(fk_status s);
 const char *fk_last_error(void);

@@ -42,6 +42,17 @@ static fk_status fail(fk_status s, const char *fmt, ...)
     return s;
 }
 
+fk_status fk::internal_fail(fk_status s, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return s;
+}
+
 #define HIP_TRY(expr)                                                                      \
     do {                                                                                   \
         hipError_t e_ = (expr);                                                            \
@@ -128,6 +139,8 @@ struct fk_csr_s {
         return DevCsr{(int32_t)n, (int32_t)nnz, nblocks, row_ptr, col_idx, vals, blocks, block_j0};
     }
 };
+
+DevCsr fk::internal_csr_view(fk_csr A) { return A->view(); }
 
 static fk_status validate_csr(int64_t n, int64_t nnz, const int32_t *rp, const int32_t *ci)
 {
@@ -1137,6 +1150,17 @@ extern "C" fk_status fk_copy(void *dst, const void *src, int64_t n_bytes, void *
     const int64_t n16 = n_bytes / 16;
     const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(gmax, (n16 + WG - 1) / WG));
     HIP_TRY(launch_copy(dst, src, n_bytes, grid, s));
+    return FK_OK;
+}
+
+extern "C" fk_status fk_axpby(int64_t n, double alpha, const double *x, double beta, const double *y,
+                              double *out, void *hip_stream)
+{
+    if (n < 0 || (n > 0 && (!x || !y || !out)))
+        return fail(FK_E_ARG, "bad argument");
+    if (n == 0)
+        return FK_OK;
+    HIP_TRY(launch_axpby(n, alpha, x, beta, y, out, vec_grid(n), (hipStream_t)hip_stream));
     return FK_OK;
 }
 

@@ -5,6 +5,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "fk.h"
+
 namespace fk {
 
 // Workgroup shape of every kernel: four wave64 wavefronts.
@@ -145,6 +147,9 @@ hipError_t launch_xpay(int64_t n, double *p, const double *r, const double *v,
 hipError_t launch_copy_fin(int64_t n, double *dst, const double *src, const RedArgs &red,
                            hipStream_t s);
 hipError_t launch_copy(void *dst, const void *src, int64_t n_bytes, int grid, hipStream_t s);
+// out = alpha x + beta y
+hipError_t launch_axpby(int64_t n, double alpha, const double *x, double beta, const double *y,
+                        double *out, int grid, hipStream_t s);
 
 // Mixed precision (FP32 inner pipelined CG inside FP64 iterative refinement).
 // r32 = (float)(b - A x) with FP64 <r,r>, <b,b> (FIN_MIX_OUTER).
@@ -171,5 +176,10 @@ hipError_t launch_small(int method_bicg, const DevCsr &A, const double *b, doubl
                         double *hist, double *scal, bool stage, hipStream_t s);
 hipError_t launch_zero(double *x, int64_t n, DevState *st, uint32_t run_mask, int grid,
                        hipStream_t s);
+
+// Shared by the C ABI sources: record the thread's error message and
+// return `s`; the device view of a matrix handle.
+fk_status internal_fail(fk_status s, const char *fmt, ...);
+DevCsr internal_csr_view(fk_csr A);
 
 }  // namespace fk

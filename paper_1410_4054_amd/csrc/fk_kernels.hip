@@ -985,6 +985,16 @@ __global__ __launch_bounds__(WG) void k_inner_setup32(int64_t n, const float *__
     reduce_point<2>(acc, red, blockIdx.x, gridDim.x);
 }
 
+// out = alpha x + beta y.
+// (out may alias x or y: each element is read before it is written)
+__global__ __launch_bounds__(WG) void k_axpby(int64_t n, double alpha, const double *x, double beta,
+                                               const double *y, double *out)
+{
+    const int64_t stride = (int64_t)gridDim.x * WG;
+    for (int64_t i = (int64_t)blockIdx.x * WG + threadIdx.x; i < n; i += stride)
+        out[i] = alpha * x[i] + beta * y[i];
+}
+
 // x += d in FP64 (the refinement's correction).
 __global__ __launch_bounds__(WG) void k_add32(int64_t n, double *__restrict__ x,
                                                const float *__restrict__ d)
@@ -1465,6 +1475,12 @@ hipError_t launch_inner_setup32(int64_t n, const float *r, float *p, float *d, c
                                 int grid, hipStream_t s)
 {
     return launch(k_inner_setup32, grid, WG, s, n, r, p, d, red);
+}
+
+hipError_t launch_axpby(int64_t n, double alpha, const double *x, double beta, const double *y,
+                        double *out, int grid, hipStream_t s)
+{
+    return launch(k_axpby, grid, WG, s, n, alpha, x, beta, y, out);
 }
 
 hipError_t launch_add32(int64_t n, double *x, const float *d, int grid, hipStream_t s)

@@ -93,6 +93,16 @@ def lib():
             "fk_spmv": [vp, vp, vp, P(f64), vp],
             "fk_dot": [i64, vp, vp, P(f64), vp],
             "fk_copy": [vp, vp, i64, vp],
+            "fk_axpby": [i64, f64, vp, f64, vp, vp, vp],
+            "fk_net_num_weights": [i32, i32, P(i64)],
+            "fk_net_create": [i32, i32, i32, vp, i64, P(vp)],
+            "fk_net_destroy": [vp],
+            "fk_net_get_weights": [vp, vp, i64],
+            "fk_net_set_weights": [vp, vp, i64],
+            "fk_net_forward": [vp, vp, i32, i32, vp, vp, vp, vp, vp],
+            "fk_net_guess": [vp, vp, i32, i32, vp, vp, vp, i32, vp, P(i32), vp],
+            "fk_net_gradient": [vp, vp, i32, i32, vp, vp, vp, vp, vp, P(f64), vp],
+            "fk_net_train_step": [vp, vp, i32, i32, vp, vp, vp, vp, ctypes.c_float, P(f64), vp],
         }
         for name, args in sig.items():
             fn = getattr(L, name)
@@ -113,8 +123,10 @@ def exported_symbols() -> list[str]:
         "fk_csr_create", "fk_csr_destroy", "fk_csr_shape", "fk_csr_blocks",
         "fk_solver_create", "fk_solve", "fk_get_iterations", "fk_get_residual",
         "fk_get_residual_history", "fk_get_scalars", "fk_get_kernel_times",
-        "fk_solver_destroy", "fk_solver_uses_small", "fk_get_refinements", "fk_spmv", "fk_dot", "fk_copy", "fk_status_str",
-        "fk_last_error", "fk_version",
+        "fk_solver_destroy", "fk_solver_uses_small", "fk_get_refinements", "fk_spmv", "fk_dot", "fk_copy",
+        "fk_axpby", "fk_net_num_weights", "fk_net_create", "fk_net_destroy", "fk_net_get_weights",
+        "fk_net_set_weights", "fk_net_forward", "fk_net_guess", "fk_net_gradient", "fk_net_train_step",
+        "fk_status_str", "fk_last_error", "fk_version",
     ]
 
 
@@ -210,6 +222,14 @@ def dot(a, b, stream=None) -> float:
                       ctypes.c_void_p(_stream_ptr(stream)))
     _check(st, "fk_dot")
     return out.value
+
+
+def axpby(alpha: float, x, beta: float, y, out, stream=None):
+    """out = alpha x + beta y on the device (enqueued, not waited for)."""
+    n = out.numel()
+    st = lib().fk_axpby(n, float(alpha), _dev_f64(x, n, "x"), float(beta), _dev_f64(y, n, "y"),
+                        _dev_f64(out, n, "out"), ctypes.c_void_p(_stream_ptr(stream)))
+    _check(st, "fk_axpby")
 
 
 def copy(dst, src, n_bytes: int, stream=None):
@@ -340,3 +360,95 @@ def solve(A: Matrix, b, x, method: str = "cg_pipelined", rtol: float = 1e-8,
                            S.refinements())
     finally:
         S.close()
+
+
+# ------------------------------------------------------- warm-start network
+
+def net_num_weights(layers: int, channels: int = 16) -> int:
+    c = ctypes.c_int64()
+    _check(lib().fk_net_num_weights(int(layers), int(channels), ctypes.byref(c)), "fk_net_num_weights")
+    return c.value
+
+
+NET_ACTIVATIONS = {"relu": 0, "linear": 1}
+
+
+class Net:
+    """fk_net handle: the BF16 convolutional initial-guess network."""
+
+    def __init__(self, layers: int, weights, channels: int = 16, activation: str = "relu"):
+        w = np.ascontiguousarray(weights, dtype=np.float32)
+        h = ctypes.c_void_p()
+        st = lib().fk_net_create(int(layers), int(channels), NET_ACTIVATIONS[activation],
+                                 w.ctypes.data_as(ctypes.c_void_p), w.size, ctypes.byref(h))
+        _check(st, "fk_net_create")
+        self._h = h
+        self.layers = int(layers)
+        self.activation = activation
+        self.count = int(w.size)
+
+    def weights(self) -> np.ndarray:
+        out = np.empty(self.count, dtype=np.float32)
+        _check(lib().fk_net_get_weights(self._h, out.ctypes.data_as(ctypes.c_void_p), self.count),
+               "fk_net_get_weights")
+        return out
+
+    def set_weights(self, w):
+        w = np.ascontiguousarray(w, dtype=np.float32)
+        _check(lib().fk_net_set_weights(self._h, w.ctypes.data_as(ctypes.c_void_p), w.size),
+               "fk_net_set_weights")
+
+    def forward(self, A: Matrix, nx: int, ny: int, b, um, um1, y, stream=None):
+        import torch
+
+        if not isinstance(y, torch.Tensor) or y.dtype != torch.float32 or y.numel() != A.n:
+            raise TypeError("y must be a float32 device tensor of n entries")
+        st = lib().fk_net_forward(self._h, A.handle, int(nx), int(ny), _dev_f64(b, A.n, "b"),
+                                  _dev_f64(um, A.n, "u_m"), _dev_f64(um1, A.n, "u_m1"),
+                                  ctypes.c_void_p(y.data_ptr()), ctypes.c_void_p(_stream_ptr(stream)))
+        _check(st, "fk_net_forward")
+
+    def guess(self, A: Matrix, nx: int, ny: int, b, um, um1, x0, passes: int = 1, report: bool = False,
+              stream=None):
+        """x0 = extrapolation corrected `passes` times by the network, with the
+        fallback to u_m.  With report=True waits and returns True when it fell back."""
+        fb = ctypes.c_int32(0)
+        st = lib().fk_net_guess(self._h, A.handle, int(nx), int(ny), _dev_f64(b, A.n, "b"),
+                                _dev_f64(um, A.n, "u_m"), _dev_f64(um1, A.n, "u_m1"), int(passes),
+                                _dev_f64(x0, A.n, "x0"), ctypes.byref(fb) if report else None,
+                                ctypes.c_void_p(_stream_ptr(stream)))
+        _check(st, "fk_net_guess")
+        return bool(fb.value) if report else None
+
+    def gradient(self, A: Matrix, nx: int, ny: int, b, um, um1, unext, stream=None):
+        g = np.empty(self.count, dtype=np.float32)
+        loss = ctypes.c_double()
+        st = lib().fk_net_gradient(self._h, A.handle, int(nx), int(ny), _dev_f64(b, A.n, "b"),
+                                   _dev_f64(um, A.n, "u_m"), _dev_f64(um1, A.n, "u_m1"),
+                                   _dev_f64(unext, A.n, "u_next"), g.ctypes.data_as(ctypes.c_void_p),
+                                   ctypes.byref(loss), ctypes.c_void_p(_stream_ptr(stream)))
+        _check(st, "fk_net_gradient")
+        return g, loss.value
+
+    def train_step(self, A: Matrix, nx: int, ny: int, b, um, um1, unext, lr: float,
+                   report: bool = False, stream=None):
+        loss = ctypes.c_double()
+        st = lib().fk_net_train_step(self._h, A.handle, int(nx), int(ny), _dev_f64(b, A.n, "b"),
+                                     _dev_f64(um, A.n, "u_m"), _dev_f64(um1, A.n, "u_m1"),
+                                     _dev_f64(unext, A.n, "u_next"), ctypes.c_float(lr),
+                                     ctypes.byref(loss) if report else None,
+                                     ctypes.c_void_p(_stream_ptr(stream)))
+        _check(st, "fk_net_train_step")
+        return loss.value if report else None
+
+    def close(self):
+        if self._h:
+            _check(lib().fk_net_destroy(self._h), "fk_net_destroy")
+            self._h = None
+
+    def __del__(self):
+        try:
+            if getattr(self, "_h", None):
+                lib().fk_net_destroy(self._h)
+        except Exception:
+            pass

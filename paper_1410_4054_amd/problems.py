@@ -154,9 +154,11 @@ def convdiff2d(n: int, peclet: float = 50.0, direction=(1.0, 0.5)) -> Csr:
     )
 
 
-def heat2d(n: int, c: float = 4.0) -> Csr:
-    """Backward-Euler heat operator I + c*L5 on an n x n interior grid (c = dt*kappa/h^2)."""
-    return _stencil((n, n), 1.0 + 4.0 * c, {(-1, 0): -c, (1, 0): -c, (0, -1): -c, (0, 1): -c})
+def heat2d(n: int, c: float = 4.0, ny: int | None = None) -> Csr:
+    """Backward-Euler heat operator I + c*L5 on an n x n (or n x ny) interior
+    grid, x fastest (c = dt*kappa/h^2)."""
+    return _stencil((n, n if ny is None else ny), 1.0 + 4.0 * c,
+                    {(-1, 0): -c, (1, 0): -c, (0, -1): -c, (0, 1): -c})
 
 
 def scaled_identity(n: int, lam: float) -> Csr:
@@ -269,6 +271,60 @@ def workload(name: str):
         raise KeyError(name)
     b = rhs_uniform(a.n, 0)
     return a, b, np.zeros(a.n)
+
+
+def heat_transient(n: int = 512, seed: int = 0, steps: int = 400, c: float = 4.0):
+    """Transient 2D heat equation, backward Euler: A u^{m} = u^{m-1} + dt f^{m}.
+
+    A = I + c L5 on the n x n interior grid of the unit square (points
+    (i+1)/(n+1)).  u^0 is a sum of 16 Gaussians from default_rng(seed):
+    centres uniform in [0.1, 0.9]^2, widths uniform in [0.03, 0.1], amplitudes
+    uniform in [-1, 1].  dt f^m is a unit-amplitude Gaussian of width 0.05
+    whose centre moves on a circle about (0.5, 0.5): for seed 0 radius 0.25,
+    phase 0, counter-clockwise, one turn in `steps` steps; other seeds draw
+    radius in [0.15, 0.35], a phase and a direction after the initial field.
+    Returns (A, u0, source) with source(m) = dt f^m (m = 1 .. steps).
+    """
+    A = heat2d(n, c)
+    rng = np.random.default_rng(seed)
+    centres = rng.uniform(0.1, 0.9, (16, 2))
+    widths = rng.uniform(0.03, 0.1, 16)
+    amps = rng.uniform(-1.0, 1.0, 16)
+    if seed == 0:
+        radius, phase, direction = 0.25, 0.0, 1.0
+    else:
+        radius = rng.uniform(0.15, 0.35)
+        phase = rng.uniform(0.0, 2.0 * np.pi)
+        direction = float(rng.choice([-1.0, 1.0]))
+    h = 1.0 / (n + 1)
+    t = (np.arange(n) + 1.0) * h
+    X = np.tile(t, n)      # x fastest: row = ix + n * iy
+    Y = np.repeat(t, n)
+    u0 = np.zeros(n * n)
+    for (cx, cy), w, a in zip(centres, widths, amps):
+        u0 += a * np.exp(-((X - cx) ** 2 + (Y - cy) ** 2) / (2.0 * w * w))
+
+    def source(m: int) -> np.ndarray:
+        th = phase + direction * 2.0 * np.pi * m / steps
+        cx, cy = 0.5 + radius * np.cos(th), 0.5 + radius * np.sin(th)
+        return np.exp(-((X - cx) ** 2 + (Y - cy) ** 2) / (2.0 * 0.05 * 0.05))
+
+    return A, u0, source
+
+
+def net_init(layers: int, seed: int = 0, channels: int = 16) -> np.ndarray:
+    """Initial weights of the warm-start network, canonical order (layer after
+    layer, W[co][ci][ky][kx]; 1 input and 1 output channel): uniform in
+    +-sqrt(6 / (9 cin)) from default_rng(seed), the last layer scaled by 0.1
+    so that the first guesses stay close to the extrapolation.  float32."""
+    rng = np.random.default_rng(seed)
+    parts = []
+    for l in range(layers):
+        cin = 1 if l == 0 else channels
+        cout = 1 if l == layers - 1 else channels
+        bound = np.sqrt(6.0 / (9 * cin)) * (0.1 if l == layers - 1 else 1.0)
+        parts.append(rng.uniform(-bound, bound, cout * cin * 9))
+    return np.concatenate(parts).astype(np.float32)
 
 
 def batch_systems(count: int = 512, seed: int = 0, nmin: int = 16, nmax: int = 512):

@@ -1,0 +1,164 @@
+"""The learned initial guess on the device (fk_net_*) against the network
+oracle (oracle/net.py) on the same seeded inputs and weights, and the gain
+of the trained network on the transient heat problem.
+
+The oracle rounds to BF16 and FP32 where the device stores them, so the two
+differ only by accumulation order (FP32 matrix-core sums against FP64), which
+can move a BF16 rounding by one unit now and then: outputs and gradients are
+compared in relative norm with the bounds below."""
+import numpy as np
+import pytest
+
+import oracle
+from gpu_util import dev, host
+from oracle import net as ON
+from paper_1410_4054_amd import fk, problems as P
+
+pytestmark = pytest.mark.gpu
+
+LAYERS = 4
+# output and loss within 1e-2 in relative 2-norm, gradients within 3e-2
+Y_TOL, G_TOL = 1e-2, 3e-2
+
+GRIDS = [(16, 16), (37, 23), (64, 48), (1, 40), (300, 7)]
+
+
+def _inputs(nx, ny, seed):
+    """Smooth-ish fields like those of the heat problem plus noise."""
+    rng = np.random.default_rng(seed)
+    X, Y = np.meshgrid(np.linspace(0, 1, nx), np.linspace(0, 1, ny))
+    base = np.sin(3 * X + 1) * np.cos(2 * Y)
+    um = (base + 0.1 * rng.standard_normal((ny, nx))).ravel()
+    um1 = (0.97 * base + 0.1 * rng.standard_normal((ny, nx))).ravel()
+    b = um + 0.05 * rng.standard_normal(nx * ny)
+    un = (1.02 * base).ravel()
+    return b, um, um1, un
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(np.asarray(a, float) - b) / max(np.linalg.norm(b), 1e-300))
+
+
+@pytest.mark.parametrize("nx,ny", GRIDS, ids=[f"{a}x{b}" for a, b in GRIDS])
+def test_forward_matches_oracle(nx, ny, device):
+    import torch
+
+    print(f"\n[case] net forward {nx}x{ny}", flush=True)
+    A = P.heat2d(nx, ny=ny)
+    w = P.net_init(LAYERS, 1)
+    b, um, um1, _ = _inputs(nx, ny, 2)
+    N = fk.Net(LAYERS, w)
+    M = fk.Matrix(A)
+    y = torch.empty(A.n, dtype=torch.float32, device="cuda")
+    N.forward(M, nx, ny, dev(b), dev(um), dev(um1), y)
+    planes, g, _, _ = ON.features(A, nx, ny, b, um, um1)
+    y_ref, _ = ON.forward(w, planes, LAYERS)
+    err = _rel(host(y), y_ref.ravel())
+    print(f"[result] forward rel err {err:.2e}", flush=True)
+    assert err <= Y_TOL
+
+
+def test_guess_and_fallback(device):
+    """x0 - g is the network output (FP64 add of the FP32 output); a
+    network whose guess is worse than u_m falls back to u_m exactly."""
+    import torch
+
+    nx, ny = 40, 30
+    A = P.heat2d(nx, ny=ny)
+    M = fk.Matrix(A)
+    b, um, um1, _ = _inputs(nx, ny, 3)
+    bd, umd, um1d = dev(b), dev(um), dev(um1)
+    w = P.net_init(LAYERS, 4)
+    N = fk.Net(LAYERS, w)
+    y = torch.empty(A.n, dtype=torch.float32, device="cuda")
+    N.forward(M, nx, ny, bd, umd, um1d, y)
+    x0 = dev(np.zeros(A.n))
+    fb = N.guess(M, nx, ny, bd, umd, um1d, x0, report=True)
+    g = 2.0 * um - um1
+    xg = host(x0)
+    r_guess = np.linalg.norm(b - A.to_scipy() @ (g + host(y).astype(np.float64)))
+    r_prev = np.linalg.norm(b - A.to_scipy() @ um)
+    assert fb == (r_guess > r_prev)
+    if fb:
+        assert np.array_equal(xg, um)
+    else:
+        assert np.array_equal(xg, g + host(y).astype(np.float64))
+    # a huge last layer: the guess is far off and the fallback must engage
+    w2 = w.copy()
+    w2[-16 * 9:] *= 1e4
+    N.set_weights(w2)
+    assert N.guess(M, nx, ny, bd, umd, um1d, x0, report=True) is True
+    assert np.array_equal(host(x0), um)
+    # all-zero last layer: x0 is the extrapolation, or u_m if that is better
+    w3 = w.copy()
+    w3[-16 * 9:] = 0.0
+    N.set_weights(w3)
+    fb = N.guess(M, nx, ny, bd, umd, um1d, x0, report=True)
+    r_ext = np.linalg.norm(b - A.to_scipy() @ g)
+    assert fb == (r_ext > r_prev)
+    assert np.array_equal(host(x0), um if fb else g)
+
+
+@pytest.mark.parametrize("nx,ny", [(37, 23), (64, 64)])
+def test_gradient_matches_oracle(nx, ny, device):
+    print(f"\n[case] net gradient {nx}x{ny}", flush=True)
+    A = P.heat2d(nx, ny=ny)
+    M = fk.Matrix(A)
+    b, um, um1, un = _inputs(nx, ny, 5)
+    w = P.net_init(LAYERS, 6)
+    N = fk.Net(LAYERS, w)
+    grad, loss = N.gradient(M, nx, ny, dev(b), dev(um), dev(um1), dev(un))
+    planes, _, target, _ = ON.features(A, nx, ny, b, um, um1, unext=un, normalize=True)
+    loss_ref, grad_ref = ON.loss_and_gradient(w, planes, target.reshape(ny, nx), LAYERS)
+    assert abs(loss - loss_ref) <= Y_TOL * loss_ref, (loss, loss_ref)
+    off = 0
+    for l, (co, ci) in enumerate(ON.shapes(LAYERS)):
+        k = co * ci * 9
+        err = _rel(grad[off: off + k], grad_ref[off: off + k])
+        print(f"[result] layer {l} gradient rel err {err:.2e}", flush=True)
+        assert err <= G_TOL, (l, err)
+        off += k
+    # the step of an update is the oracle's gradient direction
+    assert np.dot(grad, grad_ref) > 0.99 * np.linalg.norm(grad) * np.linalg.norm(grad_ref)
+
+
+def test_training_reproducible_and_descends(device):
+    """Two networks trained from the same weights on the same samples end
+    bit-identical; the loss falls."""
+    nx = ny = 48
+    A = P.heat2d(nx, ny=ny)
+    M = fk.Matrix(A)
+    b, um, um1, un = (dev(v) for v in _inputs(nx, ny, 7))
+    w = P.net_init(LAYERS, 8)
+    nets = [fk.Net(LAYERS, w), fk.Net(LAYERS, w)]
+    losses = []
+    for N in nets:
+        first = N.train_step(M, nx, ny, b, um, um1, un, 2e-3, report=True)
+        for _ in range(150):
+            N.train_step(M, nx, ny, b, um, um1, un, 2e-3)
+        last = N.train_step(M, nx, ny, b, um, um1, un, 2e-3, report=True)
+        losses.append((first, last))
+    assert np.array_equal(nets[0].weights(), nets[1].weights())
+    assert losses[0] == losses[1]
+    assert losses[0][1] < 0.2 * losses[0][0], losses
+
+
+def test_learned_guess_gain(device):
+    """The transient heat problem at 512^2 (400 steps, CG to 1e-8): a network
+    trained on the solver's own solutions for two other seeds needs fewer
+    CG iterations in total than the previous-step guess and than the
+    extrapolation; every solve still converges."""
+    from paper_1410_4054_amd import warmstart as W
+
+    data = W.generate([1, 2])
+    net = fk.Net(LAYERS, P.net_init(LAYERS, 0))
+    losses = W.train(net, data, 800, report_every=200)
+    print(f"\n[result] losses {[(i, f'{l:.2e}') for i, l in losses]}", flush=True)
+    T = W.Transient(512, 0)
+    res = {p: T.run(p, net=net)[0] for p in W.POLICIES}
+    for p, r in res.items():
+        print(f"[result] {p}: total CG iterations {r.total_iterations}, "
+              f"{r.solves_per_s:.0f} solves/s", flush=True)
+        assert all(s == fk.OK for s in r.statuses), p
+    assert res["learned"].total_iterations < 0.6 * res["prev"].total_iterations
+    assert res["learned"].total_iterations < res["extrap"].total_iterations
