@@ -129,6 +129,8 @@ def main():
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--no-learned", action="store_true",
                     help="skip training and timing the learned initial guess")
+    ap.add_argument("--no-batch", action="store_true",
+                    help="skip the uneven batch of 512 systems")
     ap.add_argument("--cpu-iters", type=int, default=200,
                     help="iterations of the oracle timed for the CPU baseline")
     args = ap.parse_args()
@@ -265,29 +267,89 @@ def main():
 
         # Learned initial guess on the transient heat problem (512^2, 400
         # steps, FP64 pipelined CG to 1e-8 per step): the network is trained
-        # on the solver's own solutions for seeds 1 and 2, then the 400 steps
-        # of seed 0 are run with each guess.
+        # on the solver's own solutions for seeds 1-3, then the 400 steps of
+        # seed 0 are run with each guess.
         if not args.no_learned:
             from paper_1410_4054_amd import warmstart as W
 
-            tg = time.perf_counter()
-            data = W.generate([1, 2])
-            torch.cuda.synchronize()
-            extras["heat512_training_data_seconds"] = time.perf_counter() - tg
-            net = fk.Net(4, P.net_init(4, 0))
-            tt = time.perf_counter()
-            losses = W.train(net, data, 800, report_every=799)
-            torch.cuda.synchronize()
-            extras["heat512_training_seconds_800_steps"] = time.perf_counter() - tt
+            net, losses, tdata, ttrain = W.train_recipe(report_every=W.RECIPE["iters"] - 1)
+            extras["heat512_training_data_seconds"] = tdata
+            extras["heat512_training_seconds"] = ttrain
             extras["heat512_training_loss_first_last"] = [losses[0][1], losses[-1][1]]
-            del data
+            extras["heat512_recipe"] = {k: (list(v) if isinstance(v, tuple) else v)
+                                        for k, v in W.RECIPE.items()}
             T = W.Transient(512, 0)
             for pol in W.POLICIES:
-                T.run(pol, net=net)  # warm-up pass
-                r, _ = T.run(pol, net=net)
+                T.run(pol, net=net, passes=W.RECIPE["passes"])  # warm-up pass
+                r, _ = T.run(pol, net=net, passes=W.RECIPE["passes"])
                 extras[f"heat512_400steps_{pol}_total_cg_iterations"] = r.total_iterations
                 extras[f"heat512_400steps_{pol}_solves_per_s"] = r.solves_per_s
             net.close()
+            del T
+
+        # Uneven batch: 512 shifted 2D Laplacians (n_s in [16, 512]), FP64
+        # refinement around FP32 pipelined CG to 1e-10, all in one persistent
+        # launch replayed from a hipGraph, with the launch shape picked by the
+        # autotuner; against solving the systems one at a time with the
+        # single-system FP64 pipelined CG to the same tolerance.
+        if not args.no_batch:
+            from paper_1410_4054_amd import autotune
+
+            tb = time.perf_counter()
+            Ab, spb, bb = P.batch_problem()
+            extras["batch512_assembly_seconds"] = time.perf_counter() - tb
+            B = fk.Batch(Ab, spb)
+            bbd = torch.as_tensor(bb, device="cuda")
+            xbd = torch.zeros_like(bbd)
+            best = autotune.tune(B, bbd, torch.zeros_like(bbd), rtol=1e-10, use_cache=False)
+            shape = {"workgroup": best["workgroup"], "lds_rows": best["lds_rows"]}
+            extras["batch512_autotuned_shape"] = shape
+            extras["batch512_autotune_seconds"] = best["seconds"]
+            bstream = torch.cuda.Stream()
+            times = []
+            for _ in range(3):
+                xbd.zero_()
+                torch.cuda.synchronize()
+                t = time.perf_counter()
+                B.solve(bbd, xbd, rtol=1e-10, graph=True, stream=bstream, **shape)
+                times.append(time.perf_counter() - t)
+            res = B.results()
+            tbest = min(times)
+            extras["batch512_solves_per_s"] = B.count / tbest
+            extras["batch512_seconds"] = tbest
+            extras["batch512_all_converged"] = bool((res.status == 0).all())
+            extras["batch512_inner_iterations_total"] = int(res.iterations.sum())
+            sizes = np.diff(spb)
+            nnz_s = Ab.row_ptr[spb[1:]].astype(np.int64) - Ab.row_ptr[spb[:-1]].astype(np.int64)
+            inner_bytes = float(np.sum(res.iterations * (8 * nnz_s + 40 * sizes)))
+            outer_bytes = float(np.sum((res.sweeps + 1) * (12 * nnz_s + 4 * sizes + 28 * sizes)))
+            extras["batch512_algorithmic_GBps"] = (inner_bytes + outer_bytes) / tbest / 1e9
+            del B
+            # One system per launch sequence: FP64 pipelined CG to 1e-10.
+            mats, sols, rhs, xs = [], [], [], []
+            for s in range(len(spb) - 1):
+                r0, r1 = int(spb[s]), int(spb[s + 1])
+                Ms = fk.Matrix(P.system_of(Ab, spb, s))
+                mats.append(Ms)
+                sols.append(fk.Solver(Ms, method="cg_pipelined", rtol=1e-10, record_history=False))
+                rhs.append(bbd[r0:r1])
+                xs.append(torch.zeros(r1 - r0, dtype=torch.float64, device="cuda"))
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            its_one = 0
+            for S1, b1, x1 in zip(sols, rhs, xs):
+                S1.solve(b1, x1)
+                its_one += S1.iterations()
+            torch.cuda.synchronize()
+            tone = time.perf_counter() - t
+            extras["batch512_one_system_per_launch_fp64_solves_per_s"] = len(sols) / tone
+            extras["batch512_one_system_per_launch_fp64_iterations_total"] = its_one
+            extras["batch512_speedup_vs_one_system_per_launch"] = tone / tbest
+            for S1 in sols:
+                S1.close()
+            for Ms in mats:
+                Ms.close()
+            del Ab, bb, bbd, xbd, mats, sols, rhs, xs
 
         # Latency-bound workload: 2D Poisson 32x32 (N = 1,024): the
         # single-workgroup solver (one launch per solve) against the grid

@@ -49,6 +49,7 @@ extern "C" {
 typedef struct fk_csr_s *fk_csr;
 typedef struct fk_solver_s *fk_solver;
 typedef struct fk_net_s *fk_net;
+typedef struct fk_batch_s *fk_batch;
 
 typedef enum {
     FK_OK = 0,              /* success; for fk_solve: converged             */
@@ -289,6 +290,52 @@ fk_status fk_net_gradient(fk_net N, fk_csr A, int32_t nx, int32_t ny, const doub
 fk_status fk_net_train_step(fk_net N, fk_csr A, int32_t nx, int32_t ny, const double *b_dev,
                             const double *um_dev, const double *um1_dev, const double *unext_dev,
                             float lr, double *loss_host, void *hip_stream);
+
+/*
+ * Batched solves: many independent SPD systems of uneven size, each by FP64
+ * iterative refinement around FP32 pipelined CG (the arithmetic of
+ * FK_CG_MIXED, Algorithm 2 with Eq. (3) inside), all in one persistent
+ * launch (an extension for the many small-to-medium systems of Section 1).
+ * The batch is one block-diagonal CSR matrix over n = sys_ptr[count] rows:
+ * system s owns rows [sys_ptr[s], sys_ptr[s+1]) (at least one) and its rows
+ * may reference only its own columns (FK_E_CSR otherwise, checked on the
+ * host).  The arrays follow the CSR conventions above and are copied; the
+ * caller keeps ownership.
+ *
+ * fk_batch_solve: b_dev, x_dev are device float64[n] (x holds x0 on entry).
+ * Every workgroup takes the largest remaining system from a device queue
+ * and solves it alone, so no workgroup waits for another; systems with at
+ * most lds_rows rows keep their FP32 work vectors in LDS.  With
+ * FK_FLAG_GRAPH (and a stream other than the default one) the launch is
+ * captured once into a hipGraph and replayed while the arguments stay the
+ * same.  The call waits for completion.  Per system: converged when
+ * ||b_s - A_s x_s|| <= rtol ||b_s||; max_iter counts inner iterations over
+ * all sweeps (0 = 10 n_s); b_s = 0 gives x_s = 0.
+ */
+typedef struct {
+    double rtol;        /* >= 0                                              */
+    double inner_rtol;  /* >= 0; 0 = 1e-4                                   */
+    int32_t max_iter;   /* >= 0; 0 = 10 n_s per system                      */
+    int32_t max_outer;  /* >= 0; 0 = 50                                      */
+    int32_t workgroup;  /* threads per workgroup: 0 (= 1024), 256, 512, 1024 */
+    int32_t lds_rows;   /* LDS-resident limit in rows: 0 = default (6144 or
+                           what fits), < 0 = never                           */
+    int32_t flags;      /* FK_FLAG_GRAPH                                      */
+} fk_batch_opts;
+
+fk_status fk_batch_create(int32_t count, const int64_t *sys_ptr_host, int64_t nnz, const int32_t *row_ptr,
+                          const int32_t *col_idx, const double *vals, int32_t ptr_kind, void *hip_stream,
+                          fk_batch *out);
+fk_status fk_batch_destroy(fk_batch B);
+fk_status fk_batch_shape(fk_batch B, int32_t *count, int64_t *n, int64_t *nnz);
+fk_status fk_batch_solve(fk_batch B, const fk_batch_opts *o, const double *b_dev, double *x_dev,
+                         void *hip_stream);
+/* Per-system results of the last solve into host arrays of `count` entries
+ * (each may be NULL): status (0 converged, 1 not converged, 2 breakdown),
+ * inner iterations, refinement sweeps, ||b_s - A_s x_s|| / ||b_s|| of the
+ * last residual evaluated. */
+fk_status fk_batch_results(fk_batch B, int32_t *status, int32_t *iterations, int32_t *sweeps,
+                           double *rel_res);
 
 const char *fk_status_str(fk_status s);
 const char *fk_last_error(void);

@@ -13,7 +13,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
-SOURCES = ["fk_kernels.hip", "fk_capi.hip", "fk_net.hip"]
+SOURCES = ["fk_kernels.hip", "fk_capi.hip", "fk_net.hip", "fk_batch.hip"]
 ARCH = os.environ.get("FK_OFFLOAD_ARCH", "gfx950")
 
 HIPCC_FLAGS = [

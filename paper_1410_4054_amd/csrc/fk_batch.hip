@@ -1,0 +1,606 @@
+// Batched solves: many independent SPD systems of uneven size in one
+// persistent launch (the many small-to-medium systems of Section 1), each
+// solved by FP64 iterative refinement around the FP32 pipelined CG of
+// Algorithm 2 with the beta recurrence of Eq. (3), and the C ABI of
+// include/fk.h (fk_batch_*).
+//
+// The batch is one block-diagonal CSR matrix; system s owns the rows
+// [sys_ptr[s], sys_ptr[s+1]).  Every workgroup takes systems from a device
+// queue, largest first, and runs the whole refinement of one system before
+// taking the next, so systems never share a workgroup and no workgroup ever
+// waits for another: all reductions are inside the workgroup.  A system
+// with at most lds_rows rows keeps its four FP32 work vectors in LDS; larger
+// ones keep them in device memory (the same workgroup writes and reads them
+// between barriers).  The arithmetic is that of the single-system mixed
+// method (FK_CG_MIXED): rows summed left to right, inner products of exact
+// products in double-double rounded once, alpha and beta in FP64 rounded to
+// FP32 for the updates.  One inner iteration has one reduction: the update
+// of d, r, p and the product A p are separated by a barrier, and <r,r>,
+// <p,Ap>, <Ap,Ap> are reduced together; the convergence test on <r,r> comes
+// first, so the product computed on the last iteration is simply unused.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <numeric>
+#include <vector>
+
+#include "fk.h"
+#include "fk_dd.hpp"
+#include "fk_internal.hpp"
+
+namespace fk {
+namespace batch {
+
+enum BStatus : int32_t { B_CONVERGED = 0, B_NOT_CONVERGED = 1, B_BREAKDOWN = 2 };
+
+struct BatchArgs {
+    const int32_t *sys_ptr;   // [count + 1]
+    const int32_t *order;     // systems, largest first
+    int32_t count;
+    const int32_t *row_ptr, *col_idx;
+    const double *vals;
+    const float *vals32;
+    const double *b;
+    double *x;
+    float *r32, *p32, *ap32, *d32;  // device work vectors, indexed by global row
+    uint32_t *queue;
+    int32_t *status, *iters, *sweeps;
+    double *rel;
+    double rtol, inner_rtol;
+    int32_t max_iter;  // <= 0: 10 n_s per system
+    int32_t max_outer;
+    int32_t lds_rows;
+};
+
+// Sum K double-double values over the workgroup and return the rounded
+// totals to every thread (wave order, then a fixed tree: reproducible).
+template <int K, int NW>
+__device__ __forceinline__ void wg_reduce(dd (&v)[K], double (&out)[K], dd (*lds)[NW], double *bcast)
+{
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int k = 0; k < K; ++k)
+        v[k] = wave_reduce(v[k]);
+    if (lane == 0) {
+#pragma unroll
+        for (int k = 0; k < K; ++k)
+            lds[k][wave] = v[k];
+    }
+    __syncthreads();
+    if (threadIdx.x < K) {
+        dd a = lds[threadIdx.x][0];
+        for (int w = 1; w < NW; ++w)
+            a = dd_add(a, lds[threadIdx.x][w]);
+        bcast[threadIdx.x] = a.hi + a.lo;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < K; ++k)
+        out[k] = bcast[k];
+    __syncthreads();
+}
+
+template <int WGS>
+__global__ __launch_bounds__(WGS) void k_batch_mixed(BatchArgs a)
+{
+    constexpr int NW = WGS / 64;
+    extern __shared__ __align__(16) float vlds[];  // 4 * lds_rows floats
+    __shared__ dd red[3][NW];
+    __shared__ double bcast[3];
+    __shared__ int32_t s_sys;
+    const int tid = threadIdx.x;
+    for (;;) {
+        if (tid == 0) {
+            const uint32_t t = atomicAdd(a.queue, 1u);
+            s_sys = t < (uint32_t)a.count ? a.order[t] : -1;
+        }
+        __syncthreads();
+        const int s = s_sys;
+        __syncthreads();
+        if (s < 0)
+            return;
+        const int r0 = a.sys_ptr[s];
+        const int n = a.sys_ptr[s + 1] - r0;
+        const bool in_lds = n <= a.lds_rows;
+        float *R = in_lds ? vlds : a.r32 + r0;
+        float *P = in_lds ? vlds + a.lds_rows : a.p32 + r0;
+        float *AP = in_lds ? vlds + 2 * a.lds_rows : a.ap32 + r0;
+        float *D = in_lds ? vlds + 3 * a.lds_rows : a.d32 + r0;
+        const int64_t max_iter = a.max_iter > 0 ? a.max_iter : 10 * (int64_t)n;
+        int64_t used = 0;
+        int32_t sweeps = 0, st = B_NOT_CONVERGED;
+        double bnorm = 0.0, tol = 0.0, rel = 0.0;
+        for (;;) {
+            // r_j = b - A x_j (FP64, rows left to right); r32 = (float) r_j
+            dd acc[2] = {dd{0.0, 0.0}, dd{0.0, 0.0}};
+            for (int i = tid; i < n; i += WGS) {
+                const int gi = r0 + i;
+                double q = 0.0;
+                for (int32_t j = a.row_ptr[gi]; j < a.row_ptr[gi + 1]; ++j)
+                    q = q + a.vals[j] * a.x[a.col_idx[j]];
+                const double ri = a.b[gi] - q;
+                R[i] = (float)ri;
+                dd_fma(acc[0], ri, ri);
+                if (sweeps == 0)
+                    dd_fma(acc[1], a.b[gi], a.b[gi]);
+            }
+            double rr[2];
+            wg_reduce<2, NW>(acc, rr, red, bcast);
+            if (sweeps == 0) {
+                if (rr[1] == 0.0) {  // b = 0: x = 0
+                    for (int i = tid; i < n; i += WGS)
+                        a.x[r0 + i] = 0.0;
+                    st = B_CONVERGED;
+                    rel = 0.0;
+                    break;
+                }
+                bnorm = sqrt(rr[1]);
+                tol = a.rtol * bnorm;
+            }
+            rel = sqrt(rr[0]) / bnorm;
+            if (!isfinite(rr[0])) {
+                st = B_BREAKDOWN;
+                break;
+            }
+            if (sqrt(rr[0]) <= tol) {
+                st = B_CONVERGED;
+                break;
+            }
+            if (sweeps >= a.max_outer || used >= max_iter) {
+                st = B_NOT_CONVERGED;
+                break;
+            }
+            // Inner solve A d = r32, d_0 = 0, by FP32 pipelined CG.
+            const int64_t cap = max_iter - used;
+            dd ai[1] = {dd{0.0, 0.0}};
+            for (int i = tid; i < n; i += WGS) {
+                const float ri = R[i];
+                P[i] = ri;
+                D[i] = 0.f;
+                dd_fma(ai[0], (double)ri, (double)ri);
+            }
+            double rri[1];
+            wg_reduce<1, NW>(ai, rri, red, bcast);
+            double rrin = rri[0];
+            int64_t k = 0;
+            int ist = B_NOT_CONVERGED;
+            const double tol_in = a.inner_rtol * sqrt(rrin);
+            if (rrin == 0.0 || (isfinite(rrin) && sqrt(rrin) <= tol_in)) {
+                ist = B_CONVERGED;  // no step
+            } else if (!isfinite(rrin)) {
+                ist = B_BREAKDOWN;
+            } else {
+                double alpha = 0.0, beta = 0.0;
+                bool first = true;
+                for (int64_t it = 0;; ++it) {
+                    // it == 0: product only; it >= 1: update, then product.
+                    dd acc3[3] = {dd{0.0, 0.0}, dd{0.0, 0.0}, dd{0.0, 0.0}};
+                    if (!first) {
+                        const float af = (float)alpha, bf = (float)beta;
+                        for (int i = tid; i < n; i += WGS) {
+                            const float pi = P[i];
+                            D[i] = D[i] + af * pi;
+                            const float ri = R[i] - af * AP[i];
+                            R[i] = ri;
+                            P[i] = ri + bf * pi;
+                            dd_fma(acc3[0], (double)ri, (double)ri);
+                        }
+                        __syncthreads();  // p complete before the product
+                    }
+                    for (int i = tid; i < n; i += WGS) {
+                        const int gi = r0 + i;
+                        float q = 0.f;
+                        for (int32_t j = a.row_ptr[gi]; j < a.row_ptr[gi + 1]; ++j)
+                            q = q + a.vals32[j] * P[a.col_idx[j] - r0];
+                        AP[i] = q;
+                        dd_fma(acc3[1], (double)q, (double)P[i]);
+                        dd_fma(acc3[2], (double)q, (double)q);
+                    }
+                    double d3[3];
+                    wg_reduce<3, NW>(acc3, d3, red, bcast);
+                    if (!first) {
+                        rrin = d3[0];
+                        k = it;
+                        if (!isfinite(rrin)) {
+                            ist = B_BREAKDOWN;
+                            break;
+                        }
+                        if (sqrt(rrin) <= tol_in) {
+                            ist = B_CONVERGED;
+                            break;
+                        }
+                        if (it == cap)
+                            break;
+                    }
+                    const double pap = d3[1], apap = d3[2];
+                    if (!(pap > 0.0) || !isfinite(pap) || !isfinite(apap)) {
+                        ist = B_BREAKDOWN;
+                        break;
+                    }
+                    alpha = rrin / pap;
+                    beta = alpha * alpha * apap / rrin - 1.0;  // Eq. (3)
+                    first = false;
+                }
+            }
+            used += k;
+            if (ist == B_BREAKDOWN) {
+                st = B_BREAKDOWN;
+                break;
+            }
+            if (k == 0) {
+                st = B_NOT_CONVERGED;
+                break;
+            }
+            for (int i = tid; i < n; i += WGS)
+                a.x[r0 + i] = a.x[r0 + i] + (double)D[i];
+            sweeps++;
+            __syncthreads();  // x complete before the next residual
+        }
+        if (tid == 0) {
+            a.status[s] = st;
+            a.iters[s] = (int32_t)used;
+            a.sweeps[s] = sweeps;
+            a.rel[s] = rel;
+        }
+        __syncthreads();
+    }
+}
+
+__global__ void k_queue_reset(uint32_t *q) { *q = 0u; }
+
+__global__ __launch_bounds__(256) void k_to_f32_batch(int64_t n, float *out, const double *in)
+{
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
+        out[i] = (float)in[i];
+}
+
+}  // namespace batch
+}  // namespace fk
+
+// =================================================================== host
+
+using namespace fk;
+using namespace fk::batch;
+
+struct fk_batch_s {
+    int32_t count = 0;
+    int64_t n = 0, nnz = 0;
+    int device = 0;
+    int32_t *sys_ptr = nullptr, *order = nullptr, *row_ptr = nullptr, *col_idx = nullptr;
+    double *vals = nullptr;
+    float *vals32 = nullptr, *r32 = nullptr, *p32 = nullptr, *ap32 = nullptr, *d32 = nullptr;
+    uint32_t *queue = nullptr;
+    int32_t *status = nullptr, *iters = nullptr, *sweeps = nullptr;
+    double *rel = nullptr;
+    int32_t max_rows = 0;
+    bool solved = false;
+    // graph of the last launch configuration
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    BatchArgs gargs{};
+    int gwgs = 0;
+    size_t glds = 0;
+    int ggrid = 0;
+};
+
+namespace {
+
+template <typename T>
+void dfree(T *&p)
+{
+    if (p)
+        (void)hipFree(p);
+    p = nullptr;
+}
+
+template <typename T>
+hipError_t dalloc(T **p, size_t count)
+{
+    return hipMalloc(reinterpret_cast<void **>(p), std::max<size_t>(count, 1) * sizeof(T));
+}
+
+void release(fk_batch B)
+{
+    dfree(B->sys_ptr);
+    dfree(B->order);
+    dfree(B->row_ptr);
+    dfree(B->col_idx);
+    dfree(B->vals);
+    dfree(B->vals32);
+    dfree(B->r32);
+    dfree(B->p32);
+    dfree(B->ap32);
+    dfree(B->d32);
+    dfree(B->queue);
+    dfree(B->status);
+    dfree(B->iters);
+    dfree(B->sweeps);
+    dfree(B->rel);
+    if (B->exec)
+        (void)hipGraphExecDestroy(B->exec);
+    if (B->graph)
+        (void)hipGraphDestroy(B->graph);
+    B->exec = nullptr;
+    B->graph = nullptr;
+}
+
+hipError_t launch(const BatchArgs &a, int wgs, int grid, size_t lds, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_queue_reset, dim3(1), dim3(1), 0, s, a.queue);
+    switch (wgs) {
+    case 256:
+        hipLaunchKernelGGL(k_batch_mixed<256>, dim3(grid), dim3(256), lds, s, a);
+        break;
+    case 512:
+        hipLaunchKernelGGL(k_batch_mixed<512>, dim3(grid), dim3(512), lds, s, a);
+        break;
+    default:
+        hipLaunchKernelGGL(k_batch_mixed<1024>, dim3(grid), dim3(1024), lds, s, a);
+        break;
+    }
+    return hipGetLastError();
+}
+
+}  // namespace
+
+extern "C" fk_status fk_batch_create(int32_t count, const int64_t *sys_ptr, int64_t nnz, const int32_t *row_ptr,
+                                     const int32_t *col_idx, const double *vals, int32_t ptr_kind,
+                                     void *hip_stream, fk_batch *out)
+{
+    if (!out)
+        return internal_fail(FK_E_ARG, "out is NULL");
+    *out = nullptr;
+    if (count < 1 || !sys_ptr)
+        return internal_fail(FK_E_ARG, "count must be >= 1 and sys_ptr given");
+    if (sys_ptr[0] != 0)
+        return internal_fail(FK_E_CSR, "sys_ptr[0] = %lld, expected 0", (long long)sys_ptr[0]);
+    for (int32_t s = 0; s < count; ++s)
+        if (sys_ptr[s + 1] <= sys_ptr[s])
+            return internal_fail(FK_E_CSR, "system %d is empty or sys_ptr decreases", s);
+    const int64_t n = sys_ptr[count];
+    if (n >= INT32_MAX || nnz < 0 || nnz > INT32_MAX)
+        return internal_fail(FK_E_ARG, "n = %lld or nnz = %lld out of range", (long long)n, (long long)nnz);
+    if (!row_ptr || (nnz > 0 && (!col_idx || !vals)))
+        return internal_fail(FK_E_ARG, "NULL CSR array");
+    if (ptr_kind != FK_PTR_HOST && ptr_kind != FK_PTR_DEVICE)
+        return internal_fail(FK_E_ARG, "ptr_kind = %d", ptr_kind);
+    hipStream_t st = (hipStream_t)hip_stream;
+    std::vector<int32_t> h_rp, h_ci;
+    const int32_t *rp = row_ptr, *ci = col_idx;
+    try {
+        if (ptr_kind == FK_PTR_DEVICE) {
+            h_rp.resize((size_t)n + 1);
+            h_ci.resize((size_t)std::max<int64_t>(nnz, 1));
+            if (hipMemcpy(h_rp.data(), row_ptr, (size_t)(n + 1) * 4, hipMemcpyDeviceToHost) != hipSuccess ||
+                (nnz > 0 && hipMemcpy(h_ci.data(), col_idx, (size_t)nnz * 4, hipMemcpyDeviceToHost) != hipSuccess))
+                return internal_fail(FK_E_HIP, "copying the CSR arrays back failed");
+            rp = h_rp.data();
+            ci = h_ci.data();
+        }
+    } catch (const std::bad_alloc &) {
+        return internal_fail(FK_E_OOM, "host allocation failed");
+    }
+    // CSR conventions, and every row of system s referencing only system s.
+    if (rp[0] != 0 || (int64_t)rp[n] != nnz)
+        return internal_fail(FK_E_CSR, "row_ptr[0] must be 0 and row_ptr[n] = nnz");
+    int32_t max_rows = 0;
+    std::vector<int64_t> sys_nnz((size_t)count);
+    for (int32_t s = 0; s < count; ++s) {
+        const int64_t lo = sys_ptr[s], hi = sys_ptr[s + 1];
+        max_rows = std::max<int32_t>(max_rows, (int32_t)(hi - lo));
+        for (int64_t i = lo; i < hi; ++i) {
+            if (rp[i + 1] < rp[i])
+                return internal_fail(FK_E_CSR, "row_ptr decreases at row %lld", (long long)i);
+            for (int64_t j = rp[i]; j < rp[i + 1]; ++j)
+                if (ci[j] < lo || ci[j] >= hi)
+                    return internal_fail(FK_E_CSR, "row %lld of system %d references column %d outside it",
+                                         (long long)i, s, ci[j]);
+        }
+        sys_nnz[(size_t)s] = rp[hi] - rp[lo];
+    }
+    // Largest systems first (ties by index), so the longest solves start early.
+    std::vector<int32_t> order((size_t)count);
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int32_t x, int32_t y) { return sys_nnz[(size_t)x] > sys_nnz[(size_t)y]; });
+    std::vector<int32_t> sp32((size_t)count + 1);
+    for (int32_t s = 0; s <= count; ++s)
+        sp32[(size_t)s] = (int32_t)sys_ptr[s];
+
+    fk_batch B = new (std::nothrow) fk_batch_s;
+    if (!B)
+        return internal_fail(FK_E_OOM, "host allocation failed");
+    B->count = count;
+    B->n = n;
+    B->nnz = nnz;
+    B->max_rows = max_rows;
+    (void)hipGetDevice(&B->device);
+    const hipMemcpyKind kind = ptr_kind == FK_PTR_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+    hipError_t e = dalloc(&B->sys_ptr, (size_t)count + 1);
+    e = e ? e : dalloc(&B->order, (size_t)count);
+    e = e ? e : dalloc(&B->row_ptr, (size_t)n + 1);
+    e = e ? e : dalloc(&B->col_idx, (size_t)nnz);
+    e = e ? e : dalloc(&B->vals, (size_t)nnz);
+    e = e ? e : dalloc(&B->vals32, (size_t)nnz);
+    e = e ? e : dalloc(&B->r32, (size_t)n);
+    e = e ? e : dalloc(&B->p32, (size_t)n);
+    e = e ? e : dalloc(&B->ap32, (size_t)n);
+    e = e ? e : dalloc(&B->d32, (size_t)n);
+    e = e ? e : dalloc(&B->queue, 1);
+    e = e ? e : dalloc(&B->status, (size_t)count);
+    e = e ? e : dalloc(&B->iters, (size_t)count);
+    e = e ? e : dalloc(&B->sweeps, (size_t)count);
+    e = e ? e : dalloc(&B->rel, (size_t)count);
+    e = e ? e : hipMemcpyAsync(B->sys_ptr, sp32.data(), sp32.size() * 4, hipMemcpyHostToDevice, st);
+    e = e ? e : hipMemcpyAsync(B->order, order.data(), order.size() * 4, hipMemcpyHostToDevice, st);
+    e = e ? e : hipMemcpyAsync(B->row_ptr, row_ptr, (size_t)(n + 1) * 4, kind, st);
+    if (nnz > 0) {
+        e = e ? e : hipMemcpyAsync(B->col_idx, col_idx, (size_t)nnz * 4, kind, st);
+        e = e ? e : hipMemcpyAsync(B->vals, vals, (size_t)nnz * 8, kind, st);
+    }
+    if (e == hipSuccess && nnz > 0)
+        hipLaunchKernelGGL(k_to_f32_batch, dim3(2048), dim3(256), 0, st, nnz, B->vals32, B->vals);
+    e = e ? e : hipGetLastError();
+    e = e ? e : hipStreamSynchronize(st);
+    if (e != hipSuccess) {
+        release(B);
+        delete B;
+        return e == hipErrorOutOfMemory ? internal_fail(FK_E_OOM, "batch: out of device memory")
+                                        : internal_fail(FK_E_HIP, "fk_batch_create: %s", hipGetErrorString(e));
+    }
+    *out = B;
+    return FK_OK;
+}
+
+extern "C" fk_status fk_batch_destroy(fk_batch B)
+{
+    if (!B)
+        return internal_fail(FK_E_ARG, "NULL batch");
+    (void)hipDeviceSynchronize();
+    release(B);
+    delete B;
+    return FK_OK;
+}
+
+extern "C" fk_status fk_batch_solve(fk_batch B, const fk_batch_opts *o, const double *b, double *x,
+                                    void *hip_stream)
+{
+    if (!B || !o || !b || !x)
+        return internal_fail(FK_E_ARG, "NULL argument");
+    if (!(o->rtol >= 0.0) || !std::isfinite(o->rtol) || !(o->inner_rtol >= 0.0) || !std::isfinite(o->inner_rtol))
+        return internal_fail(FK_E_ARG, "rtol and inner_rtol must be finite and >= 0");
+    if (o->max_iter < 0 || o->max_outer < 0)
+        return internal_fail(FK_E_ARG, "max_iter and max_outer must be >= 0");
+    const int wgs = o->workgroup == 0 ? 1024 : o->workgroup;
+    if (wgs != 256 && wgs != 512 && wgs != 1024)
+        return internal_fail(FK_E_ARG, "workgroup must be 0, 256, 512 or 1024");
+    if (o->flags & ~FK_FLAG_GRAPH)
+        return internal_fail(FK_E_ARG, "unknown flags 0x%x", o->flags);
+    int lds_max = 0;
+    if (hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, B->device) != hipSuccess)
+        lds_max = 65536;
+    // static LDS of the kernel: reduction slots and the broadcast words
+    const int static_lds = 3 * (wgs / 64) * 16 + 64;
+    const int lds_cap = std::max(0, (lds_max - static_lds) / 16);
+    int lds_rows = o->lds_rows == 0 ? std::min(6144, lds_cap) : o->lds_rows;
+    if (lds_rows < 0)
+        lds_rows = 0;
+    if (lds_rows > lds_cap)
+        return internal_fail(FK_E_ARG, "lds_rows = %d exceeds the %d rows that fit in LDS", lds_rows, lds_cap);
+    lds_rows = std::min(lds_rows, B->max_rows);
+    hipStream_t s = (hipStream_t)hip_stream;
+
+    BatchArgs a{};
+    a.sys_ptr = B->sys_ptr;
+    a.order = B->order;
+    a.count = B->count;
+    a.row_ptr = B->row_ptr;
+    a.col_idx = B->col_idx;
+    a.vals = B->vals;
+    a.vals32 = B->vals32;
+    a.b = b;
+    a.x = x;
+    a.r32 = B->r32;
+    a.p32 = B->p32;
+    a.ap32 = B->ap32;
+    a.d32 = B->d32;
+    a.queue = B->queue;
+    a.status = B->status;
+    a.iters = B->iters;
+    a.sweeps = B->sweeps;
+    a.rel = B->rel;
+    a.rtol = o->rtol;
+    a.inner_rtol = o->inner_rtol == 0.0 ? 1e-4 : o->inner_rtol;
+    a.max_iter = o->max_iter;
+    a.max_outer = o->max_outer == 0 ? 50 : o->max_outer;
+    a.lds_rows = lds_rows;
+    const size_t lds = (size_t)lds_rows * 16;
+    // One workgroup per CU slot the LDS allows, never more than the systems.
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, B->device) != hipSuccess || cus < 1)
+        cus = 256;
+    const int per_cu = std::max(1, std::min(2048 / wgs, lds > 0 ? (int)(lds_max / (lds + static_lds)) : 2048 / wgs));
+    const int grid = std::max(1, std::min(B->count, cus * per_cu));
+
+    const bool graph = (o->flags & FK_FLAG_GRAPH) != 0 && s != nullptr;
+    if (graph) {
+        const bool same = B->exec && B->gwgs == wgs && B->glds == lds && B->ggrid == grid &&
+                          std::memcmp(&B->gargs, &a, sizeof a) == 0;
+        if (!same) {
+            if (B->exec)
+                (void)hipGraphExecDestroy(B->exec);
+            if (B->graph)
+                (void)hipGraphDestroy(B->graph);
+            B->exec = nullptr;
+            B->graph = nullptr;
+            hipError_t e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
+            if (e != hipSuccess)
+                return internal_fail(FK_E_HIP, "capture: %s", hipGetErrorString(e));
+            hipError_t el = launch(a, wgs, grid, lds, s);
+            hipGraph_t g = nullptr;
+            e = hipStreamEndCapture(s, &g);
+            if (el != hipSuccess || e != hipSuccess) {
+                if (g)
+                    (void)hipGraphDestroy(g);
+                return internal_fail(FK_E_HIP, "capture: %s", hipGetErrorString(el != hipSuccess ? el : e));
+            }
+            e = hipGraphInstantiate(&B->exec, g, nullptr, nullptr, 0);
+            if (e != hipSuccess) {
+                (void)hipGraphDestroy(g);
+                return internal_fail(FK_E_HIP, "instantiate: %s", hipGetErrorString(e));
+            }
+            B->graph = g;
+            B->gargs = a;
+            B->gwgs = wgs;
+            B->glds = lds;
+            B->ggrid = grid;
+        }
+        hipError_t e = hipGraphLaunch(B->exec, s);
+        if (e != hipSuccess)
+            return internal_fail(FK_E_HIP, "graph launch: %s", hipGetErrorString(e));
+    } else {
+        hipError_t e = launch(a, wgs, grid, lds, s);
+        if (e != hipSuccess)
+            return internal_fail(FK_E_HIP, "batch launch: %s", hipGetErrorString(e));
+    }
+    hipError_t e = hipStreamSynchronize(s);
+    if (e != hipSuccess)
+        return internal_fail(FK_E_HIP, "batch solve: %s", hipGetErrorString(e));
+    B->solved = true;
+    return FK_OK;
+}
+
+extern "C" fk_status fk_batch_results(fk_batch B, int32_t *status, int32_t *iterations, int32_t *sweeps,
+                                      double *rel_res)
+{
+    if (!B)
+        return internal_fail(FK_E_ARG, "NULL batch");
+    if (!B->solved)
+        return internal_fail(FK_E_STATE, "no completed solve");
+    const size_t c = (size_t)B->count;
+    hipError_t e = hipSuccess;
+    if (status)
+        e = e ? e : hipMemcpy(status, B->status, c * 4, hipMemcpyDeviceToHost);
+    if (iterations)
+        e = e ? e : hipMemcpy(iterations, B->iters, c * 4, hipMemcpyDeviceToHost);
+    if (sweeps)
+        e = e ? e : hipMemcpy(sweeps, B->sweeps, c * 4, hipMemcpyDeviceToHost);
+    if (rel_res)
+        e = e ? e : hipMemcpy(rel_res, B->rel, c * 8, hipMemcpyDeviceToHost);
+    if (e != hipSuccess)
+        return internal_fail(FK_E_HIP, "fk_batch_results: %s", hipGetErrorString(e));
+    return FK_OK;
+}
+
+extern "C" fk_status fk_batch_shape(fk_batch B, int32_t *count, int64_t *n, int64_t *nnz)
+{
+    if (!B || !count || !n || !nnz)
+        return internal_fail(FK_E_ARG, "NULL argument");
+    *count = B->count;
+    *n = B->n;
+    *nnz = B->nnz;
+    return FK_OK;
+}

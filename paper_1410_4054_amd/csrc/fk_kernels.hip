@@ -29,6 +29,7 @@
 // Files are built with -ffp-contract=off: products and sums are rounded one
 // by one, exactly as written; fma appears only where the error of a product
 // is extracted.
+#include "fk_dd.hpp"
 #include "fk_internal.hpp"
 
 #include <hip/hip_ext.h>
@@ -50,52 +51,6 @@
 
 namespace fk {
 namespace {
-
-// ------------------------------------------------------------ double-double
-
-struct dd {
-    double hi, lo;
-};
-
-__device__ __forceinline__ void two_sum(double a, double b, double &s, double &e)
-{
-    s = a + b;
-    double z = s - a;
-    e = (a - (s - z)) + (b - z);
-}
-
-// (a.hi + a.lo) + (b.hi + b.lo), renormalised.  Commutative bit for bit.
-__device__ __forceinline__ dd dd_add(dd a, dd b)
-{
-    double s, e;
-    two_sum(a.hi, b.hi, s, e);
-    e = e + (a.lo + b.lo);
-    double h = s + e;
-    return dd{h, e - (h - s)};
-}
-
-// acc += a * b, keeping the rounding errors of the product and the sum.
-__device__ __forceinline__ void dd_fma(dd &acc, double a, double b)
-{
-    double p = a * b;
-    double pe = __builtin_fma(a, b, -p);
-    double s, e;
-    two_sum(acc.hi, p, s, e);
-    acc.hi = s;
-    acc.lo = acc.lo + (e + pe);
-}
-
-__device__ __forceinline__ dd wave_reduce(dd v)
-{
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) {
-        dd o;
-        o.hi = __shfl_xor(v.hi, off, 64);
-        o.lo = __shfl_xor(v.lo, off, 64);
-        v = dd_add(v, o);
-    }
-    return v;
-}
 
 // Sum K double-double values over the workgroup; the result is valid in
 // thread 0.  Ends with every thread past a barrier that follows the last

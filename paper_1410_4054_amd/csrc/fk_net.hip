@@ -168,6 +168,142 @@ __global__ __launch_bounds__(NWG) void k_conv(ConvArgs a)
     }
 }
 
+
+// ------------------------------------------------ fused inference (one pass)
+
+// One pass x_out = base + N(b - A base), base = ca xa + cb xb, in one launch.
+// A workgroup owns a TX x TY tile of the grid.  It forms r = b - A base on
+// the tile plus a halo of L points (rows summed left to right, base read
+// from global memory, so any CSR works) into LDS, then runs the L layers in
+// LDS, each on a region one point smaller than its input, and writes
+// base + N on the tile.  Region points outside the grid hold zeros, which is
+// the zero padding of the layered kernels; the MFMA slices and BF16 rounding
+// points are those of k_conv, so the result equals the layered forward pass
+// bit for bit.
+constexpr int FTX = 32, FTY = 16;   // output tile
+constexpr int FWAVES = 8;           // waves per workgroup
+
+struct FusedArgs {
+    DevCsr A;
+    int nx, ny, layers, relu;
+    const double *b, *xa, *xb;
+    double ca, cb;
+    double *xout;
+    const bf16x4 *w;     // packed forward operands, layer after layer
+    int pf[MAX_LAYERS];  // offset of layer l's operands
+};
+
+__host__ __device__ constexpr int fused_region(int h) { return (FTX + 2 * h) * (FTY + 2 * h); }
+// LDS bytes: r plane (4 channels) on the halo-L region plus two 16-channel
+// buffers on the largest hidden region (halo L-1).
+inline size_t fused_lds_bytes(int L)
+{
+    return (size_t)fused_region(L) * 8 + 2 * (size_t)fused_region(L - 1) * 32;
+}
+
+// One layer in LDS: input region of halo h+1 (CINP channels), output region
+// of halo h.  LAST: write base + acc to xout on the tile.
+template <int CINP, bool LAST>
+__device__ __forceinline__ void fused_layer(const FusedArgs &a, const uint16_t *in, uint16_t *out, int h,
+                                            const bf16x4 *w, int gx0, int gy0)
+{
+    constexpr int J = (9 * CINP + 15) / 16;
+    const int lane = threadIdx.x & 63;
+    const int grp = lane >> 4, px = lane & 15;
+    const int wv = threadIdx.x >> 6;
+    const int Wo = FTX + 2 * h, Ho = FTY + 2 * h;
+    const int Wi = Wo + 2;
+    bf16x4 wr[J];
+#pragma unroll
+    for (int j = 0; j < J; ++j)
+        wr[j] = w[j * 64 + lane];
+    const int nchunks = (Wo * Ho + 15) / 16;
+    for (int c = wv; c < nchunks; c += FWAVES) {
+        const int q = c * 16 + px;
+        const bool valid = q < Wo * Ho;
+        const int qx = valid ? q % Wo : 0, qy = valid ? q / Wo : 0;
+        f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int j = 0; j < J; ++j) {
+            int tap, c0;
+            if constexpr (CINP == 16) {
+                tap = j;
+                c0 = 4 * grp;
+            } else {
+                tap = 4 * j + grp;
+                c0 = 0;
+            }
+            bf16x4 bv = {0, 0, 0, 0};
+            if (tap < 9 && valid) {
+                const int ix = qx + (tap % 3), iy = qy + (tap / 3);  // input region has halo h+1
+                bv = *reinterpret_cast<const bf16x4 *>(in + ((size_t)iy * Wi + ix) * CINP + c0);
+            }
+            acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(wr[j], bv, acc, 0, 0, 0);
+        }
+        if (!valid)
+            continue;
+        const int gx = gx0 - h + qx, gy = gy0 - h + qy;
+        const bool inside = gx >= 0 && gx < a.nx && gy >= 0 && gy < a.ny;
+        if constexpr (LAST) {
+            if (grp == 0 && inside) {
+                const int64_t p = (int64_t)gy * a.nx + gx;
+                a.xout[p] = (a.ca * a.xa[p] + a.cb * a.xb[p]) + (double)acc[0];
+            }
+        } else {
+            bf16x4 o = {0, 0, 0, 0};
+            if (inside) {
+#pragma unroll
+                for (int i = 0; i < 4; ++i)
+                    o[i] = (short)f2bf((!a.relu || acc[i] > 0.f) ? acc[i] : 0.f);
+            }
+            *reinterpret_cast<bf16x4 *>(out + (size_t)q * 16 + 4 * grp) = o;
+        }
+    }
+}
+
+__global__ __launch_bounds__(FWAVES * 64) void k_net_fused(FusedArgs a)
+{
+    extern __shared__ __align__(16) uint16_t lds[];
+    const int L = a.layers;
+    const int tiles_x = (a.nx + FTX - 1) / FTX;
+    const int gx0 = (int)(blockIdx.x % tiles_x) * FTX;
+    const int gy0 = (int)(blockIdx.x / tiles_x) * FTY;
+    uint16_t *rplane = lds;
+    uint16_t *buf[2] = {lds + (size_t)fused_region(L) * 4,
+                        lds + (size_t)fused_region(L) * 4 + (size_t)fused_region(L - 1) * 16};
+    // r = b - A base on the halo-L region (zeros outside the grid)
+    const int Wr = FTX + 2 * L, Hr = FTY + 2 * L;
+    for (int q = threadIdx.x; q < Wr * Hr; q += FWAVES * 64) {
+        const int gx = gx0 - L + q % Wr, gy = gy0 - L + q / Wr;
+        bf16x4 o = {0, 0, 0, 0};
+        if (gx >= 0 && gx < a.nx && gy >= 0 && gy < a.ny) {
+            const int64_t i = (int64_t)gy * a.nx + gx;
+            double acc = 0.0;
+            for (int32_t j = a.A.row_ptr[i]; j < a.A.row_ptr[i + 1]; ++j) {
+                const int32_t c = a.A.col_idx[j];
+                acc = acc + a.A.vals[j] * (a.ca * a.xa[c] + a.cb * a.xb[c]);
+            }
+            o[0] = (short)f2bf((float)(a.b[i] - acc));
+        }
+        *reinterpret_cast<bf16x4 *>(rplane + (size_t)q * 4) = o;
+    }
+    __syncthreads();
+    const uint16_t *in = rplane;
+    for (int l = 0; l < L; ++l) {
+        const int h = L - 1 - l;
+        uint16_t *out = buf[l & 1];
+        const bf16x4 *w = a.w + a.pf[l];
+        if (l == L - 1)
+            fused_layer<16, true>(a, in, nullptr, h, w, gx0, gy0);
+        else if (l == 0)
+            fused_layer<4, false>(a, in, out, h, w, gx0, gy0);
+        else
+            fused_layer<16, false>(a, in, out, h, w, gx0, gy0);
+        __syncthreads();
+        in = out;
+    }
+}
+
 // ------------------------------------------------------- weight gradient
 
 // Partial dW[tap][co][ci] = sum over pixels p of G[p][co] * X[p + tap][ci]
@@ -476,6 +612,7 @@ struct fk_net_s {
     float *dwpart = nullptr;
     double *redpart = nullptr, *loss = nullptr;
     int32_t *flag = nullptr;
+    double *xtmp = nullptr;               // [n] ping-pong iterate of multi-pass guesses
 };
 
 namespace {
@@ -540,6 +677,7 @@ void release_workspace(fk_net N)
     dfree(N->redpart);
     dfree(N->loss);
     dfree(N->flag);
+    dfree(N->xtmp);
     N->cap = 0;
 }
 
@@ -570,6 +708,7 @@ fk_status ensure_workspace(fk_net N, int64_t n)
     e = e ? e : dalloc(&N->redpart, (size_t)2 * RED_GRID);
     e = e ? e : dalloc(&N->loss, 1);
     e = e ? e : dalloc(&N->flag, 1);
+    e = e ? e : dalloc(&N->xtmp, un);
     if (e != hipSuccess) {
         release_workspace(N);
         return e == hipErrorOutOfMemory ? net_fail(FK_E_OOM, "network workspace: out of device memory")
@@ -806,14 +945,39 @@ extern "C" fk_status fk_net_guess(fk_net N, fk_csr Ah, int32_t nx, int32_t ny, c
         return net_fail(FK_E_ARG, "passes must be in [1, 16]");
     hipStream_t s = (hipStream_t)stream;
     const int64_t n = A.n;
+    // One fused launch per pass.  A pass reads its base around every point
+    // of its tile while other tiles write their output, so consecutive
+    // passes alternate between x0 and a workspace vector, the last one
+    // writing x0.
+    FusedArgs fa{};
+    fa.A = A;
+    fa.nx = nx;
+    fa.ny = ny;
+    fa.layers = N->meta.layers;
+    fa.relu = N->meta.relu;
+    fa.b = b;
+    fa.w = N->packed;
+    for (int l = 0; l < N->meta.layers; ++l)
+        fa.pf[l] = N->meta.l[l].pf;
+    const int tiles = ((nx + FTX - 1) / FTX) * ((ny + FTY - 1) / FTY);
+    const size_t lds = fused_lds_bytes(N->meta.layers);
+    double *bufs[2] = {x0, N->xtmp};
     for (int k = 0; k < passes; ++k) {
-        // pass 0 corrects the extrapolation, later passes the previous x0
-        const double *xa = k == 0 ? um : x0, *xb = k == 0 ? um1 : x0;
-        const double ca = k == 0 ? 2.0 : 1.0, cb = k == 0 ? -1.0 : 0.0;
-        hipLaunchKernelGGL((k_features<FEAT_RAW>), dim3(grid_for(n, NWG, 2048)), dim3(NWG), 0, s, A, b, xa, xb,
-                           ca, cb, nullptr, nullptr, nullptr, N->feat, nullptr);
-        NET_HIP(forward(N, nx, ny, n, x0, xa, xb, ca, cb, s));
+        const int dst = (passes - 1 - k) & 1;
+        if (k == 0) {
+            fa.xa = um;
+            fa.xb = um1;
+            fa.ca = 2.0;
+            fa.cb = -1.0;
+        } else {
+            fa.xa = fa.xb = bufs[dst ^ 1];
+            fa.ca = 1.0;
+            fa.cb = 0.0;
+        }
+        fa.xout = bufs[dst];
+        hipLaunchKernelGGL(k_net_fused, dim3(tiles), dim3(FWAVES * 64), lds, s, fa);
     }
+    NET_HIP(hipGetLastError());
     const int gr = grid_for(n, NWG, RED_GRID);
     hipLaunchKernelGGL(k_check, dim3(gr), dim3(NWG), 0, s, A, b, x0, um, N->redpart);
     hipLaunchKernelGGL(k_select, dim3(1), dim3(NWG), 0, s, gr, N->redpart, n, um, x0, N->flag);

@@ -52,6 +52,18 @@ class _Opts(ctypes.Structure):
     ]
 
 
+class _BatchOpts(ctypes.Structure):
+    _fields_ = [
+        ("rtol", ctypes.c_double),
+        ("inner_rtol", ctypes.c_double),
+        ("max_iter", ctypes.c_int32),
+        ("max_outer", ctypes.c_int32),
+        ("workgroup", ctypes.c_int32),
+        ("lds_rows", ctypes.c_int32),
+        ("flags", ctypes.c_int32),
+    ]
+
+
 _lib = None
 _lock = threading.Lock()
 
@@ -103,6 +115,11 @@ def lib():
             "fk_net_guess": [vp, vp, i32, i32, vp, vp, vp, i32, vp, P(i32), vp],
             "fk_net_gradient": [vp, vp, i32, i32, vp, vp, vp, vp, vp, P(f64), vp],
             "fk_net_train_step": [vp, vp, i32, i32, vp, vp, vp, vp, ctypes.c_float, P(f64), vp],
+            "fk_batch_create": [i32, vp, i64, vp, vp, vp, i32, vp, P(vp)],
+            "fk_batch_destroy": [vp],
+            "fk_batch_shape": [vp, P(i32), P(i64), P(i64)],
+            "fk_batch_solve": [vp, P(_BatchOpts), vp, vp, vp],
+            "fk_batch_results": [vp, vp, vp, vp, vp],
         }
         for name, args in sig.items():
             fn = getattr(L, name)
@@ -126,6 +143,7 @@ def exported_symbols() -> list[str]:
         "fk_solver_destroy", "fk_solver_uses_small", "fk_get_refinements", "fk_spmv", "fk_dot", "fk_copy",
         "fk_axpby", "fk_net_num_weights", "fk_net_create", "fk_net_destroy", "fk_net_get_weights",
         "fk_net_set_weights", "fk_net_forward", "fk_net_guess", "fk_net_gradient", "fk_net_train_step",
+        "fk_batch_create", "fk_batch_destroy", "fk_batch_shape", "fk_batch_solve", "fk_batch_results",
         "fk_status_str", "fk_last_error", "fk_version",
     ]
 
@@ -450,5 +468,70 @@ class Net:
         try:
             if getattr(self, "_h", None):
                 lib().fk_net_destroy(self._h)
+        except Exception:
+            pass
+
+
+# ------------------------------------------------------------------- batch
+
+BATCH_STATUS = {0: "converged", 1: "not_converged", 2: "breakdown"}
+
+
+@dataclass
+class BatchResult:
+    status: np.ndarray      # per system: 0 converged, 1 not converged, 2 breakdown
+    iterations: np.ndarray  # inner iterations over all sweeps
+    sweeps: np.ndarray
+    rel_res: np.ndarray     # ||b_s - A_s x_s|| / ||b_s|| of the last residual
+
+
+class Batch:
+    """fk_batch handle: independent systems stored as one block-diagonal CSR."""
+
+    def __init__(self, csr, sys_ptr, stream=None):
+        L = lib()
+        sp = np.ascontiguousarray(sys_ptr, dtype=np.int64)
+        rp = np.ascontiguousarray(csr.row_ptr, dtype=np.int32)
+        ci = np.ascontiguousarray(csr.col_idx, dtype=np.int32)
+        va = np.ascontiguousarray(csr.vals, dtype=np.float64)
+        h = ctypes.c_void_p()
+        st = L.fk_batch_create(int(sp.size - 1), sp.ctypes.data_as(ctypes.c_void_p), int(ci.size),
+                               rp.ctypes.data_as(ctypes.c_void_p), ci.ctypes.data_as(ctypes.c_void_p),
+                               va.ctypes.data_as(ctypes.c_void_p), PTR_HOST,
+                               ctypes.c_void_p(_stream_ptr(stream)), ctypes.byref(h))
+        _check(st, "fk_batch_create")
+        self._h = h
+        self.count = int(sp.size - 1)
+        self.n = int(sp[-1])
+        self.sys_ptr = sp
+
+    def solve(self, b, x, rtol: float = 1e-10, inner_rtol: float = 0.0, max_iter: int = 0,
+              max_outer: int = 0, workgroup: int = 0, lds_rows: int = 0, graph: bool = False, stream=None):
+        o = _BatchOpts(float(rtol), float(inner_rtol), int(max_iter), int(max_outer), int(workgroup),
+                       int(lds_rows), FLAG_GRAPH if graph else 0)
+        st = lib().fk_batch_solve(self._h, ctypes.byref(o), _dev_f64(b, self.n, "b"),
+                                  _dev_f64(x, self.n, "x"), ctypes.c_void_p(_stream_ptr(stream)))
+        _check(st, "fk_batch_solve")
+
+    def results(self) -> BatchResult:
+        c = self.count
+        st = np.empty(c, np.int32)
+        it = np.empty(c, np.int32)
+        sw = np.empty(c, np.int32)
+        rel = np.empty(c, np.float64)
+        _check(lib().fk_batch_results(self._h, st.ctypes.data_as(ctypes.c_void_p),
+                                      it.ctypes.data_as(ctypes.c_void_p), sw.ctypes.data_as(ctypes.c_void_p),
+                                      rel.ctypes.data_as(ctypes.c_void_p)), "fk_batch_results")
+        return BatchResult(st, it, sw, rel)
+
+    def close(self):
+        if self._h:
+            _check(lib().fk_batch_destroy(self._h), "fk_batch_destroy")
+            self._h = None
+
+    def __del__(self):
+        try:
+            if getattr(self, "_h", None):
+                lib().fk_batch_destroy(self._h)
         except Exception:
             pass

@@ -340,3 +340,64 @@ def batch_systems(count: int = 512, seed: int = 0, nmin: int = 16, nmax: int = 5
         shift = rng.uniform(0.0, 0.1, int(ns) * int(ns))
         b = rng.uniform(-1.0, 1.0, int(ns) * int(ns))
         yield int(ns), shift, b
+
+
+def block_diagonal(systems) -> tuple[Csr, np.ndarray]:
+    """Stack square CSR matrices into one block-diagonal CSR matrix; returns
+    it and sys_ptr (row offsets, int64, count + 1 entries)."""
+    systems = list(systems)
+    sizes = np.array([a.n for a in systems], dtype=np.int64)
+    sys_ptr = np.concatenate([[0], np.cumsum(sizes)])
+    nnzs = np.array([a.nnz for a in systems], dtype=np.int64)
+    nnz_ptr = np.concatenate([[0], np.cumsum(nnzs)])
+    n, nnz = int(sys_ptr[-1]), int(nnz_ptr[-1])
+    row_ptr = np.empty(n + 1, dtype=np.int32)
+    col_idx = np.empty(nnz, dtype=np.int32)
+    vals = np.empty(nnz, dtype=np.float64)
+    for s, a in enumerate(systems):
+        r0, j0 = int(sys_ptr[s]), int(nnz_ptr[s])
+        row_ptr[r0: r0 + a.n] = a.row_ptr[:-1] + j0
+        col_idx[j0: j0 + a.nnz] = a.col_idx + r0
+        vals[j0: j0 + a.nnz] = a.vals
+    row_ptr[n] = nnz
+    return Csr(n, row_ptr, col_idx, vals), sys_ptr
+
+
+def batch_problem(count: int = 512, seed: int = 0, nmin: int = 16, nmax: int = 512):
+    """The uneven batch as (block-diagonal A, sys_ptr, b): system s is the 2D
+    5-point Laplacian on an n_s x n_s grid plus its diagonal shift, with its
+    right-hand side, in the draw order of batch_systems.  Each system is
+    written straight into the batch arrays."""
+    draws = list(batch_systems(count, seed, nmin, nmax))
+    sizes = np.array([ns * ns for ns, _, _ in draws], dtype=np.int64)
+    nnzs = np.array([5 * ns * ns - 4 * ns for ns, _, _ in draws], dtype=np.int64)
+    sys_ptr = np.concatenate([[0], np.cumsum(sizes)])
+    nnz_ptr = np.concatenate([[0], np.cumsum(nnzs)])
+    n, nnz = int(sys_ptr[-1]), int(nnz_ptr[-1])
+    row_ptr = np.empty(n + 1, dtype=np.int32)
+    col_idx = np.empty(nnz, dtype=np.int32)
+    vals = np.empty(nnz, dtype=np.float64)
+    b = np.empty(n, dtype=np.float64)
+    for s, (ns, shift, bs) in enumerate(draws):
+        a = poisson2d(ns)
+        r0, j0 = int(sys_ptr[s]), int(nnz_ptr[s])
+        assert a.nnz == nnzs[s]
+        row_ptr[r0: r0 + a.n] = a.row_ptr[:-1] + j0
+        col_idx[j0: j0 + a.nnz] = a.col_idx + r0
+        v = vals[j0: j0 + a.nnz]
+        v[:] = a.vals
+        # the diagonal follows the south and west neighbours in each row
+        ix = np.tile(np.arange(ns), ns)
+        iy = np.repeat(np.arange(ns), ns)
+        v[a.row_ptr[:-1] + (iy > 0) + (ix > 0)] += shift
+        b[r0: r0 + a.n] = bs
+    row_ptr[n] = nnz
+    return Csr(n, row_ptr, col_idx, vals), sys_ptr, b
+
+
+def system_of(A: Csr, sys_ptr, s: int) -> Csr:
+    """System s of a block-diagonal batch as its own CSR matrix."""
+    r0, r1 = int(sys_ptr[s]), int(sys_ptr[s + 1])
+    j0, j1 = int(A.row_ptr[r0]), int(A.row_ptr[r1])
+    return Csr(r1 - r0, (A.row_ptr[r0: r1 + 1] - j0).astype(np.int32), (A.col_idx[j0:j1] - r0).astype(np.int32),
+               A.vals[j0:j1].copy())

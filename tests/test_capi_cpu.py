@@ -114,3 +114,36 @@ def test_missing_library_fails_loudly(tmp_path):
             "try:\n    fk.lib()\nexcept OSError:\n    print('raised')\n") % str(tmp_path / "absent" / "libfk.so")
     res = subprocess.run(["python", "-c", code], capture_output=True, text=True, cwd=ROOT, timeout=300)
     assert "raised" in res.stdout, res.stderr
+
+
+def _batch_create(sys_ptr, rp, ci, vals):
+    L = fk.lib()
+    sp = np.ascontiguousarray(sys_ptr, dtype=np.int64)
+    rp = np.ascontiguousarray(rp, dtype=np.int32)
+    ci = np.ascontiguousarray(ci, dtype=np.int32)
+    va = np.ascontiguousarray(vals, dtype=np.float64)
+    h = ctypes.c_void_p()
+    return L.fk_batch_create(len(sp) - 1, sp.ctypes.data_as(ctypes.c_void_p), ci.size,
+                             rp.ctypes.data_as(ctypes.c_void_p), ci.ctypes.data_as(ctypes.c_void_p),
+                             va.ctypes.data_as(ctypes.c_void_p), 0, None, ctypes.byref(h))
+
+
+@pytest.mark.parametrize("case,sys_ptr,rp,ci,expect", [
+    ("cross_block_column", [0, 2, 3], [0, 1, 3, 4], [0, 1, 2, 2], fk.E_CSR),  # row 1 reads column 2 of system 1
+    ("empty_system", [0, 2, 2, 3], [0, 1, 2, 3], [0, 1, 2], fk.E_CSR),
+    ("sys_ptr_not_zero", [1, 3], [0, 1, 2, 3], [0, 1, 2], fk.E_CSR),
+    ("row_ptr_end", [0, 2], [0, 1, 3], [0, 1], fk.E_CSR),
+    ("row_ptr_decreasing", [0, 3], [0, 2, 1, 3], [0, 1, 2], fk.E_CSR),
+])
+def test_batch_validation(case, sys_ptr, rp, ci, expect):
+    """Block-diagonal structure and CSR conventions are checked on the host
+    before any device work."""
+    assert _batch_create(sys_ptr, rp, ci, np.ones(len(ci))) == expect, case
+    assert fk.lib().fk_last_error()
+
+
+def test_batch_null_arguments():
+    L = fk.lib()
+    assert L.fk_batch_create(0, None, 0, None, None, None, 0, None, None) == fk.E_ARG
+    assert L.fk_batch_destroy(None) == fk.E_ARG
+    assert L.fk_batch_results(None, None, None, None, None) == fk.E_ARG

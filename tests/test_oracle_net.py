@@ -40,22 +40,23 @@ def test_conv_adjoint_identity():
     assert abs(np.sum(dw * W) - lhs) <= 1e-12 * abs(lhs)
 
 
-def test_gradient_finite_differences():
+@pytest.mark.parametrize("linear", [False, True], ids=["relu", "linear"])
+def test_gradient_finite_differences(linear):
     """FP64 analytic gradient of the loss against central differences."""
     layers, nx, ny = 3, 6, 5
     rng = np.random.default_rng(3)
     planes = rng.standard_normal((1, ny, nx))
     target = rng.standard_normal((ny, nx))
     w = _weights(layers, 4)
-    loss, grad = ON.loss_and_gradient(w, planes, target, layers, bf=False)
+    loss, grad = ON.loss_and_gradient(w, planes, target, layers, bf=False, linear=linear)
     h = 1e-5
     idx = rng.choice(w.size, 40, replace=False)
     for i in idx:
         wp, wm = w.copy(), w.copy()
         wp[i] += h
         wm[i] -= h
-        lp, _ = ON.loss_and_gradient(wp, planes, target, layers, bf=False)
-        lm, _ = ON.loss_and_gradient(wm, planes, target, layers, bf=False)
+        lp, _ = ON.loss_and_gradient(wp, planes, target, layers, bf=False, linear=linear)
+        lm, _ = ON.loss_and_gradient(wm, planes, target, layers, bf=False, linear=linear)
         fd = (lp - lm) / (2 * h)
         assert abs(fd - grad[i]) <= 1e-8 * max(1.0, abs(grad).max()), (i, fd, grad[i])
 
@@ -72,6 +73,26 @@ def test_positive_homogeneity():
     y3, _ = ON.forward(w, planes, layers, bf=True)
     y4, _ = ON.forward(w, 0.25 * planes, layers, bf=True)
     np.testing.assert_array_equal(y4, 0.25 * y3)
+
+
+def test_linear_network_is_linear():
+    """With the identity between layers N is linear: additive and odd, and
+    equal to the single convolution with the composed filter."""
+    layers = 3
+    rng = np.random.default_rng(13)
+    w = _weights(layers, 14)
+    p1, p2 = rng.standard_normal((2, 1, 9, 7))
+    f = lambda p: ON.forward(w, p, layers, bf=False, linear=True)[0]
+    np.testing.assert_allclose(f(p1 + p2), f(p1) + f(p2), rtol=1e-11, atol=1e-12)
+    np.testing.assert_allclose(f(-p1), -f(p1), rtol=1e-12, atol=1e-13)
+    # the response to a unit impulse is the composed 7x7 filter; convolving
+    # with it (away from the boundary) reproduces N
+    imp = np.zeros((1, 21, 21))
+    imp[0, 10, 10] = 1.0
+    h = f(imp)[7:14, 7:14]  # support of three stacked 3x3 filters
+    big = rng.standard_normal((1, 30, 30))
+    ref = scipy.signal.convolve2d(big[0], h, mode="same")
+    np.testing.assert_allclose(f(big)[5:-5, 5:-5], ref[5:-5, 5:-5], rtol=1e-10, atol=1e-10)
 
 
 def test_bf16_rounding_matches_torch():
