@@ -66,6 +66,11 @@ class Oracle:
             ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
         ]
         lib.oracle_solve_mixed.restype = ctypes.c_int
+        lib.oracle_solve_gmres.argtypes = [
+            ctypes.c_int, ctypes.c_int32, ctypes.c_int64, i32p, i32p, f64p, f64p, f64p, f64p,
+            ctypes.c_double, ctypes.c_int32, f64p, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32),
+        ]
+        lib.oracle_solve_gmres.restype = ctypes.c_int
         f32p = ctypes.POINTER(ctypes.c_float)
         lib.oracle_spmv_f32.argtypes = [ctypes.c_int64, i32p, i32p, f32p, f32p, f32p]
         lib.oracle_spmv_f32.restype = None
@@ -154,6 +159,29 @@ class Oracle:
         return Result(x=x, r=r, k=kk, status=STATUS[st], hist=hist[: kk + 1].copy(),
                       trace=None if tr is None else tr[:kk].copy())
 
+    def solve_gmres(self, A, b, x0=None, m: int = 30, pipelined: bool = True, rtol: float = 1e-8,
+                    max_iter: int | None = None) -> "Result":
+        """Restarted simpler GMRES(m): Algorithm 6 (pipelined) or 5 (classical)."""
+        n = A.n
+        if max_iter is None:
+            max_iter = 10 * n
+        rp, rpp = _i32(A.row_ptr)
+        ci, cip = _i32(A.col_idx)
+        v, vp = _f64(A.vals)
+        b, bp = _f64(b)
+        x = np.zeros(n) if x0 is None else np.array(x0, dtype=np.float64, copy=True)
+        _, xp = _f64(x)
+        r = np.empty(n)
+        _, rptr = _f64(r)
+        cap = max_iter + 1
+        hist = np.full(cap, np.nan)
+        _, hp = _f64(hist)
+        k = ctypes.c_int32(0)
+        st = self.lib.oracle_solve_gmres(1 if pipelined else 0, int(m), n, rpp, cip, vp, bp, xp, rptr,
+                                         float(rtol), int(max_iter), hp, cap, ctypes.byref(k))
+        kk = int(k.value)
+        return Result(x=x, r=r, k=kk, status=STATUS[st], hist=hist[: kk + 1].copy(), trace=None)
+
     def solve_mixed(self, A, b, x0=None, rtol: float = 1e-10, inner_rtol: float = 1e-4,
                     max_iter: int | None = None, max_outer: int = 50) -> "MixedResult":
         """Iterative refinement in FP64 around FP32 pipelined CG (oracle.c)."""
@@ -235,6 +263,11 @@ def solve_mixed(A, b, x0=None, rtol: float = 1e-10, inner_rtol: float = 1e-4,
                 max_iter: int | None = None, max_outer: int = 50) -> "MixedResult":
     return default().solve_mixed(A, b, x0=x0, rtol=rtol, inner_rtol=inner_rtol,
                                  max_iter=max_iter, max_outer=max_outer)
+
+
+def solve_gmres(A, b, x0=None, m: int = 30, pipelined: bool = True, rtol: float = 1e-8,
+                max_iter: int | None = None) -> "Result":
+    return default().solve_gmres(A, b, x0=x0, m=m, pipelined=pipelined, rtol=rtol, max_iter=max_iter)
 
 
 def true_residual(A, b, x) -> float:

@@ -19,6 +19,10 @@
  *   - bicgstab_pipelined : Algorithm 4, beta from the orthogonality
  *                          <s_i, r0*> = 0 and the residual norm from the
  *                          expansion of <r_{i+1}, r_{i+1}> (Section 3.2);
+ *   - gmres (methods 4, 5): restarted simpler GMRES(m) with classical
+ *                          Gram-Schmidt, Algorithm 5 (residual updated in
+ *                          the loop) and Algorithm 6 (pipelined: xi_i from
+ *                          the initial residual, no update) of Section 3.3;
  *   - oracle_solve_mixed : classical iterative refinement (residual and
  *                          update in FP64) whose correction equation is
  *                          solved by Algorithm 2 + Eq. (3) in FP32 storage
@@ -48,7 +52,8 @@
 #include <string.h>
 
 enum { OR_CONVERGED = 0, OR_NOT_CONVERGED = 1, OR_BREAKDOWN = 2, OR_BAD_ARG = 3 };
-enum { OR_CG_CLASSICAL = 0, OR_CG_PIPELINED = 1, OR_BICGSTAB_CLASSICAL = 2, OR_BICGSTAB_PIPELINED = 3 };
+enum { OR_CG_CLASSICAL = 0, OR_CG_PIPELINED = 1, OR_BICGSTAB_CLASSICAL = 2, OR_BICGSTAB_PIPELINED = 3,
+       OR_GMRES_CLASSICAL = 4, OR_GMRES_PIPELINED = 5 };
 
 /* Per-iteration trace record: TRACE_STRIDE doubles per iteration. */
 #define TRACE_STRIDE 12
@@ -427,6 +432,115 @@ static int bicgstab_pipelined(const csr_t *A, const double *b, double *x, double
 done:
     free(rs); free(p); free(ap); free(s); free(as);
     *k_out = k;
+    return status;
+}
+
+
+/* ------------------------------------------- Algorithms 5 and 6: GMRES(m) */
+
+/*
+ * Restarted simpler GMRES(m) (Walker and Zhou) with classical Gram-Schmidt.
+ * A cycle starts from r0 = b - A x (its true norm rho0 is the history entry
+ * at the restart and decides convergence), v_0 = r0/rho0, and for
+ * i = 1..m: w = A v_{i-1}; R[j][i] = <v_j, w> for j = 1..i-1, all from the
+ * same w; w = w - sum_j R[j][i] v_j (j in order); R[i][i] = ||w||;
+ * v_i = w / R[i][i]; xi_i = <r, v_i> with r = v_0 (pipelined) or the
+ * residual updated as r = r - xi_i v_i (classical).  The estimate
+ * rho0 * zeta_i, zeta_i^2 = max(zeta_{i-1}^2 - xi_i^2, 0), zeta_0 = 1, is the
+ * history entry of iteration i and ends the cycle early when it meets the
+ * tolerance.  Then R eta = xi is solved by back substitution and
+ * x = x + rho0 (eta_1 v_0 + sum_{j=2}^{i} eta_j v_{j-1}).  R[i][i] = 0 or
+ * not finite ends the cycle before step i (breakdown if that leaves no
+ * step).  k counts products A v over all cycles.
+ */
+static int gmres(const csr_t *A, const double *b, double *x, double *r, int pipelined, int32_t m,
+                 double rtol, int32_t max_iter, double *hist, int32_t cap, int32_t *k_out)
+{
+    int64_t n = A->n;
+    int status = OR_NOT_CONVERGED;
+    int32_t k = 0;
+    double *V = (double *)calloc((size_t)(m + 1) * (size_t)n, sizeof(double));
+    double *w = vec(n), *rr = vec(n);
+    double *R = (double *)calloc((size_t)(m + 1) * (size_t)(m + 1), sizeof(double));
+    double *xi = (double *)calloc((size_t)(m + 1), sizeof(double));
+    double *eta = (double *)calloc((size_t)(m + 1), sizeof(double));
+    if (!V || !w || !rr || !R || !xi || !eta) { status = OR_BAD_ARG; goto done; }
+    double bnorm = sqrt(oracle_dot(n, b, b));
+    double tol = rtol * bnorm;
+    for (;;) {
+        if (!initial_residual(A, b, x, r)) { status = OR_BAD_ARG; break; }
+        double rho0 = sqrt(oracle_dot(n, r, r));
+        put_hist(hist, cap, k, rho0 / bnorm);
+        if (!finite(rho0)) { status = OR_BREAKDOWN; break; }
+        if (rho0 <= tol) { status = OR_CONVERGED; break; }
+        if (k >= max_iter) { status = OR_NOT_CONVERGED; break; }
+        double *v0 = V;
+        for (int64_t t = 0; t < n; ++t) { v0[t] = r[t] / rho0; rr[t] = v0[t]; }
+        double zeta2 = 1.0;
+        int32_t used = 0;
+        for (int32_t i = 1; i <= m && k < max_iter; ++i) {
+            double *vi = V + (size_t)i * n;
+            matvec(A, V + (size_t)(i - 1) * n, w);                          /* w = A v_{i-1} */
+            for (int32_t j = 1; j < i; ++j)
+                R[j * (m + 1) + i] = oracle_dot(n, V + (size_t)j * n, w);    /* R_{j,i} */
+            for (int32_t j = 1; j < i; ++j) {
+                const double rj = R[j * (m + 1) + i];
+                const double *vj = V + (size_t)j * n;
+                for (int64_t t = 0; t < n; ++t) w[t] = w[t] - rj * vj[t];
+            }
+            const double rii = sqrt(oracle_dot(n, w, w));
+            if (!(rii > 0.0) || !finite(rii)) break;                        /* no step i */
+            R[i * (m + 1) + i] = rii;
+            for (int64_t t = 0; t < n; ++t) vi[t] = w[t] / rii;
+            xi[i] = oracle_dot(n, rr, vi);
+            if (!pipelined)
+                for (int64_t t = 0; t < n; ++t) rr[t] = rr[t] - xi[i] * vi[t];
+            zeta2 = zeta2 - xi[i] * xi[i];
+            if (zeta2 < 0.0) zeta2 = 0.0;
+            ++k;
+            used = i;
+            put_hist(hist, cap, k, rho0 * sqrt(zeta2) / bnorm);
+            if (rho0 * sqrt(zeta2) <= tol) break;
+        }
+        if (used == 0) { status = OR_BREAKDOWN; break; }
+        for (int32_t i = used; i >= 1; --i) {                               /* R eta = xi */
+            double s = xi[i];
+            for (int32_t j = i + 1; j <= used; ++j) s = s - R[i * (m + 1) + j] * eta[j];
+            eta[i] = s / R[i * (m + 1) + i];
+        }
+        for (int64_t t = 0; t < n; ++t) {
+            double s = eta[1] * V[t];
+            for (int32_t j = 2; j <= used; ++j) s = s + eta[j] * V[(size_t)(j - 1) * n + t];
+            x[t] = x[t] + rho0 * s;
+        }
+    }
+done:
+    free(V); free(w); free(rr); free(R); free(xi); free(eta);
+    *k_out = k;
+    return status;
+}
+
+int oracle_solve_gmres(int pipelined, int32_t m, int64_t n, const int32_t *row_ptr, const int32_t *col_idx,
+                       const double *vals, const double *b, double *x, double *r, double rtol,
+                       int32_t max_iter, double *hist, int32_t cap, int32_t *k_out)
+{
+    *k_out = 0;
+    if (n <= 0 || m < 1 || !row_ptr || !col_idx || !vals || !b || !x || max_iter < 0 || !(rtol >= 0.0))
+        return OR_BAD_ARG;
+    csr_t A = {n, row_ptr, col_idx, vals};
+    double *rbuf = r ? r : vec(n);
+    if (!rbuf)
+        return OR_BAD_ARG;
+    int status;
+    if (oracle_dot(n, b, b) == 0.0) {                                        /* b = 0: x = 0 */
+        for (int64_t j = 0; j < n; ++j) { x[j] = 0.0; rbuf[j] = 0.0; }
+        put_hist(hist, cap, 0, 0.0);
+        status = OR_CONVERGED;
+    } else {
+        status = gmres(&A, b, x, rbuf, pipelined, m, rtol, max_iter, hist, cap, k_out);
+    }
+    if (!r)
+        free(rbuf);
     return status;
 }
 

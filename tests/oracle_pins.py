@@ -299,6 +299,69 @@ def pin_breakdown(O):
         assert O.solve(A, b, method=m).status == "breakdown", m
 
 
+# ------------------------------------------------- GMRES(m), Algorithms 5-6
+
+def _krylov_lstsq(M, b, x0, k):
+    """Minimiser of ||b - M x|| over x0 + K_k(M, r0), by dense least squares."""
+    r0 = b - M @ x0
+    K = np.zeros((len(b), k))
+    v = r0.copy()
+    for j in range(k):
+        K[:, j] = v / np.linalg.norm(v)
+        v = M @ K[:, j]
+    Q, _ = np.linalg.qr(K)
+    c, *_ = np.linalg.lstsq(M @ Q, r0, rcond=None)
+    return x0 + Q @ c
+
+
+def pin_gmres_least_squares(O):
+    """Without a restart, GMRES's iterate after k steps is the minimiser of
+    the residual over x0 + K_k (dense least squares), and its history entry
+    is that minimum residual; both Gram-Schmidt forms agree."""
+    n = 30
+    rng = np.random.default_rng(21)
+    M = 3.0 * np.eye(n) + rng.uniform(-0.5, 0.5, (n, n))
+    A = P.dense_to_csr(M)
+    b = rng.standard_normal(n)
+    x0 = rng.standard_normal(n) * 0.1
+    for k in (1, 2, 5, 9):
+        xr = _krylov_lstsq(M, b, x0, k)
+        res_ref = np.linalg.norm(b - M @ xr) / np.linalg.norm(b)
+        for pip in (True, False):
+            r = O.solve_gmres(A, b, x0=x0, m=40, pipelined=pip, rtol=0.0, max_iter=k)
+            assert r.k == k and r.status == "not_converged", (k, pip, r.k, r.status)
+            assert _rel(r.x, xr) < 1e-11, (k, pip, _rel(r.x, xr))
+            assert abs(r.hist[k - 1 + 1] - res_ref) <= 1e-10 * res_ref + 1e-15, (k, pip)
+
+
+def pin_gmres_termination_and_restarts(O):
+    """A diagonalizable matrix with 3 distinct eigenvalues: GMRES stops after
+    3 steps; lambda I after 1; restarted GMRES(m) on convection-diffusion
+    meets the tolerance on the true residual; b = 0 gives x = 0."""
+    n = 24
+    rng = np.random.default_rng(22)
+    S = np.eye(n) + 0.2 * rng.standard_normal((n, n))
+    lam = np.repeat([1.0, 2.5, 4.0], n // 3)
+    M = S @ np.diag(lam) @ np.linalg.inv(S)
+    A = P.dense_to_csr(M)
+    b = rng.standard_normal(n)
+    for pip in (True, False):
+        r = O.solve_gmres(A, b, m=10, pipelined=pip, rtol=1e-10)
+        assert r.status == "converged" and r.k == 3, (pip, r.k, r.status)
+        assert np.linalg.norm(b - M @ r.x) <= 1e-9 * np.linalg.norm(b)
+        z = O.solve_gmres(P.scaled_identity(9, 2.0), np.arange(1.0, 10.0), m=5, pipelined=pip, rtol=1e-12)
+        assert z.k == 1 and np.allclose(z.x, np.arange(1.0, 10.0) / 2.0, rtol=1e-15)
+        e = O.solve_gmres(A, np.zeros(n), x0=np.ones(n), pipelined=pip)
+        assert e.k == 0 and e.status == "converged" and not e.x.any()
+    Ac, bc, _ = P.workload("convdiff2d_32")
+    for m in (5, 20):
+        rs = [O.solve_gmres(Ac, bc, m=m, pipelined=pip, rtol=1e-9) for pip in (True, False)]
+        for r in rs:
+            assert r.status == "converged"
+            assert np.linalg.norm(bc - Ac.to_scipy() @ r.x) <= 1.0001e-9 * np.linalg.norm(bc)
+        assert abs(rs[0].k - rs[1].k) <= 1 and _rel(rs[0].x, rs[1].x) < 1e-8
+
+
 # ------------------------------------ iterative refinement, FP32 inner CG
 
 def pin_f32_products(O):
@@ -426,6 +489,8 @@ PINS = [
     pin_classical_vs_pipelined,
     pin_special_cases,
     pin_breakdown,
+    pin_gmres_least_squares,
+    pin_gmres_termination_and_restarts,
     pin_f32_products,
     pin_mixed_identity,
     pin_mixed_eigen_termination,

@@ -39,6 +39,13 @@ MUTATIONS = [
     ("pbicg_rho_wrong_vector", "rho = oracle_dot(n, r, rs);                        /* <r_{i+1}, r0*> */",
      "rho = oracle_dot(n, r, r);", None),
     ("half_step_wrong_vector", "x[j] = x[j] + alpha * p[j];", "x[j] = x[j] + alpha * s[j];", 3),
+    ("gmres_gs_update_sign", "w[t] = w[t] - rj * vj[t];", "w[t] = w[t] + rj * vj[t];", None),
+    ("gmres_normalise_wrong", "vi[t] = w[t] / rii;", "vi[t] = w[t] * rii;", None),
+    ("gmres_backsub_order", "s = s - R[i * (m + 1) + j] * eta[j];", "s = s - R[j * (m + 1) + i] * eta[j];", None),
+    ("gmres_update_drops_v0", "double s = eta[1] * V[t];", "double s = 0.0;", None),
+    ("gmres_update_unscaled", "x[t] = x[t] + rho0 * s;", "x[t] = x[t] + s;", None),
+    ("gmres_monitor_drops_xi", "zeta2 = zeta2 - xi[i] * xi[i];", "zeta2 = zeta2 - xi[i];", None),
+    ("gmres_xi_unnormalised", "xi[i] = oracle_dot(n, rr, vi);", "xi[i] = oracle_dot(n, rr, w);", None),
     ("f32_spmv_wrong_column", "acc = acc + v[j] * p[ci[j]];", "acc = acc + v[j] * p[i];", None),
     ("f32_dot_drops_compensation", "        s = s + q;\n", "", None),
     ("f32_cg_residual_wrong_operand", "r[j] = r[j] - af * ap[j];", "r[j] = r[j] - af * p[j];", None),
