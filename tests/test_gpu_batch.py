@@ -95,7 +95,11 @@ def test_batch_edge_cases(device):
         xd = dev(x0)
         B.solve(dev(b), xd, **opts)
         assert_batch_equal(B, host(xd), refs, sp, str(kw))
-    assert refs[2].status == "breakdown"
+        if not kw:
+            assert refs[0].status == "converged" and not host(xd)[sp[0]:sp[1]].any()
+            assert refs[2].status == "breakdown"
+        if "inner_rtol" in kw:
+            assert all(r.status == "not_converged" for r in refs if r.k == 0 and r.hist[0] > 0)
 
 
 def test_batch_config_full(device):

@@ -17,8 +17,9 @@ from paper_1410_4054_amd import fk, problems as P
 pytestmark = pytest.mark.gpu
 
 LAYERS = 4
-# output and loss within 1e-2 in relative 2-norm, gradients within 3e-2
-Y_TOL, G_TOL = 1e-2, 3e-2
+# output, loss and gradients within 1e-3 in relative 2-norm (measured: at
+# most 7e-5; a BF16 rounding moved by one unit changes a value by 2^-8)
+Y_TOL, G_TOL = 1e-3, 1e-3
 
 GRIDS = [(16, 16), (37, 23), (64, 48), (1, 40), (300, 7)]
 
@@ -87,6 +88,7 @@ def test_fused_passes_equal_layered(nx, ny, act, device):
     A = P.heat2d(nx, ny=ny)
     M = fk.Matrix(A)
     w = P.net_init(LAYERS, 21)
+    w[-16 * 9:] *= 0.01  # small corrections: no pass may trigger the fallback
     N = fk.Net(LAYERS, w, activation=act)
     b, um, um1 = _inputs_good_extrapolation(A, nx, ny, 22)
     bd, umd, um1d = dev(b), dev(um), dev(um1)
