@@ -153,6 +153,7 @@ def main():
     bd = torch.as_tensor(b, device="cuda")
     xd = torch.zeros_like(bd)
 
+    log(f"[bench] {WORKLOAD}: n={n} nnz={nnz}; timing {args.steps} solves")
     # Timed steps: K full solves, inputs resident in HBM.
     S = fk.Solver(M, method="cg_pipelined", rtol=RTOL, record_history=False)
     for _ in range(args.warmup):
@@ -206,6 +207,7 @@ def main():
 
     extras = {}
     if not args.no_extras:
+        log("[bench] extras: 30 fixed iterations, classical vs pipelined")
         # The paper's protocol: median of 10 runs of exactly 30 iterations.
         for method in ("cg_pipelined", "cg_classical"):
             S = fk.Solver(M, method=method, rtol=0.0, max_iter=30, record_history=False)
@@ -231,6 +233,7 @@ def main():
         extras["iteration_frac_of_peak"] = per_it_bytes * value / 1e9 / PEAK_HBM_GBS
         extras["copy_kernel_GBps_1GiB"] = copy_bandwidth(torch, fk)
 
+        log("[bench] extras: BiCGStab 1024^2")
         # Nonsymmetric workload: pipelined BiCGStab on 1024^2 convection-diffusion.
         A3, b3, _ = P.workload("convdiff2d_1024")
         M3 = fk.Matrix(A3)
@@ -243,6 +246,7 @@ def main():
         extras["bicgstab_convdiff2d_1024_k"] = S3.iterations()
         S3.close(); M3.close()
 
+        log("[bench] extras: mixed precision 128^3")
         # Mixed precision: FP64 iterative refinement around FP32 pipelined CG
         # against FP64 pipelined CG, both to 1e-10 on 128^3.
         for label, kw in (("fp64_cg_pipelined", {"method": "cg_pipelined"}),
@@ -272,6 +276,8 @@ def main():
         if not args.no_learned:
             from paper_1410_4054_amd import warmstart as W
 
+            log("[bench] extras: learned initial guess (data, training, 3 x 400 steps)")
+
             net, losses, tdata, ttrain = W.train_recipe(report_every=W.RECIPE["iters"] - 1)
             extras["heat512_training_data_seconds"] = tdata
             extras["heat512_training_seconds"] = ttrain
@@ -295,12 +301,15 @@ def main():
         if not args.no_batch:
             from paper_1410_4054_amd import autotune
 
+            log("[bench] extras: batch of 512 systems (assembly, autotuning, solves)")
+
             tb = time.perf_counter()
             Ab, spb, bb = P.batch_problem()
             extras["batch512_assembly_seconds"] = time.perf_counter() - tb
             B = fk.Batch(Ab, spb)
             bbd = torch.as_tensor(bb, device="cuda")
             xbd = torch.zeros_like(bbd)
+            log(f"[bench] batch assembled in {extras['batch512_assembly_seconds']:.1f} s; autotuning")
             best = autotune.tune(B, bbd, torch.zeros_like(bbd), rtol=1e-10, use_cache=False)
             shape = {"workgroup": best["workgroup"], "lds_rows": best["lds_rows"]}
             extras["batch512_autotuned_shape"] = shape
@@ -325,6 +334,7 @@ def main():
             outer_bytes = float(np.sum((res.sweeps + 1) * (12 * nnz_s + 4 * sizes + 28 * sizes)))
             extras["batch512_algorithmic_GBps"] = (inner_bytes + outer_bytes) / tbest / 1e9
             del B
+            log("[bench] batch: one system per launch baseline")
             # One system per launch sequence: FP64 pipelined CG to 1e-10.
             mats, sols, rhs, xs = [], [], [], []
             for s in range(len(spb) - 1):
@@ -351,6 +361,7 @@ def main():
                 Ms.close()
             del Ab, bb, bbd, xbd, mats, sols, rhs, xs
 
+        log("[bench] extras: latency-bound 32^2")
         # Latency-bound workload: 2D Poisson 32x32 (N = 1,024): the
         # single-workgroup solver (one launch per solve) against the grid
         # kernels (two launches per iteration), pipelined CG and BiCGStab.
