@@ -67,7 +67,9 @@ typedef enum {
     FK_CG_CLASSICAL = 1,        /* Algorithm 1 as SpMV, dot, axpy, axpy, dot, xpay */
     FK_BICGSTAB_PIPELINED = 2,  /* Algorithm 4: 4 kernels/iteration             */
     FK_BICGSTAB_CLASSICAL = 3,  /* Algorithm 3, one kernel per operation         */
-    FK_CG_MIXED = 4             /* FP64 iterative refinement around FP32 Algorithm 2 */
+    FK_CG_MIXED = 4,            /* FP64 iterative refinement around FP32 Algorithm 2 */
+    FK_GMRES_PIPELINED = 5,     /* Algorithm 6: restarted GMRES(m), 4 kernels/iteration */
+    FK_GMRES_CLASSICAL = 6      /* Algorithm 5: residual updated in the loop (+1 kernel) */
 } fk_method;
 
 /* Rows with more nonzeros than this are summed by a fixed tree, not left to right. */
@@ -87,6 +89,7 @@ typedef struct {
                                 ||r_j|| (>= 0; 0 = 1e-4)                       */
     int32_t max_outer;       /* FK_CG_MIXED: refinement sweeps allowed
                                 (>= 0; 0 = 50)                                 */
+    int32_t restart;         /* GMRES: restart length m (0 = 30; at most 64)    */
 } fk_opts;
 
 /* flags */
@@ -153,6 +156,24 @@ fk_status fk_solver_create(fk_csr A, const fk_opts *o, void *hip_stream, fk_solv
  * fk_get_refinements gives the number of sweeps (corrections applied).
  * Workspace: 4n floats plus nnz FP32 matrix values.
  *
+ * FK_GMRES_PIPELINED / FK_GMRES_CLASSICAL (restarted simpler GMRES(m) with
+ * classical Gram-Schmidt, Section 3.3): a cycle starts from r0 = b - A x
+ * (its true norm rho0 is the history entry at the restart and decides
+ * convergence), v_0 = r0 / rho0, and for i = 1..m: w = A v_{i-1};
+ * R[j][i] = <v_j, w> for j = 1..i-1 (all from the same w); w -= sum_j
+ * R[j][i] v_j; R[i][i] = ||w||; v_i = w / R[i][i]; xi_i = <r, v_i> with
+ * r = v_0 (pipelined: no residual update) or r updated as r -= xi_i v_i
+ * (classical).  Per iteration the pipelined form runs four kernels: the CSR
+ * product with <v_{i-1}, w>, the remaining inner products, the update with
+ * ||w||^2, the normalisation with xi_i; every second reduction stage runs on
+ * the device.  The device ends a cycle early when rho0 sqrt(1 - sum xi^2)
+ * (floored at 0) meets the tolerance (that value is the history entry of the
+ * iteration), after m steps, when max_iter products are used, or before a
+ * step whose ||w|| is 0 or not finite.  Per cycle the host reads R and xi,
+ * solves R eta = xi and the device sets x += rho0 (eta_1 v_0 +
+ * sum_{j>=2} eta_j v_{j-1}).  k counts products A v over all cycles.  A cycle
+ * with no step is a breakdown.  Workspace: (m+2) n doubles.
+ *
  * Solve A x = b.  b_dev, x_dev: caller-owned device float64[n]; x holds x0 on
  * entry and x_k on return.  Work is enqueued on the solver's stream and the
  * call returns once it has completed.  Returns FK_OK (converged),
@@ -176,7 +197,7 @@ fk_status fk_get_residual_history(fk_solver S, double *out, int32_t cap, int32_t
 /* Per-iteration scalars of the last solve (for diagnostics): for iteration
  * i < min(cap, k), out[4*i + 0..3] = alpha_i, beta_i, omega_i (0 for CG),
  * and the A-expanded (BiCGStab) or plain <r,r> used for the test.
- * Needs record_history; not recorded for FK_CG_MIXED (FK_E_STATE). */
+ * Needs record_history; not recorded for FK_CG_MIXED or GMRES (FK_E_STATE). */
 fk_status fk_get_scalars(fk_solver S, double *out, int32_t cap, int32_t *len);
 
 /* Average device time per launch of each kernel kind during the last solve

@@ -369,6 +369,12 @@ struct fk_solver_s {
     float *r32 = nullptr, *p32 = nullptr, *ap32 = nullptr, *d32 = nullptr, *vals32 = nullptr;
     DevState *st_outer = nullptr;
     int32_t sweeps = 0;
+    // GMRES(m): basis V ((m+1) x n), triangular factor R ((m+1)^2, row 0 =
+    // xi), eta (m+1), multi-dot scratch, host copies of R and eta.
+    bool gmres = false;
+    int32_t gm = 0;
+    double *V = nullptr, *gR = nullptr, *geta = nullptr, *gpart = nullptr;
+    std::vector<double> hR, heta;
 
     // The mixed method records the refinement's residuals only.
     RedArgs red(int fin, uint32_t mask) const
@@ -396,6 +402,10 @@ static void solver_release(fk_solver S)
     dev_free(S->d32);
     dev_free(S->vals32);
     dev_free(S->st_outer);
+    dev_free(S->V);
+    dev_free(S->gR);
+    dev_free(S->geta);
+    dev_free(S->gpart);
     if (S->h_init)
         (void)hipHostFree(S->h_init);
     if (S->h_status)
@@ -419,6 +429,7 @@ static void solver_release(fk_solver S)
 }
 
 static bool is_bicg(int m) { return m == FK_BICGSTAB_PIPELINED || m == FK_BICGSTAB_CLASSICAL; }
+static bool is_gmres(int m) { return m == FK_GMRES_PIPELINED || m == FK_GMRES_CLASSICAL; }
 
 static size_t max_lds_per_workgroup(int device)
 {
@@ -454,8 +465,10 @@ extern "C" fk_status fk_solver_create(fk_csr A, const fk_opts *o, void *hip_stre
     *out = nullptr;
     if (!A || !o)
         return fail(FK_E_ARG, "NULL argument");
-    if (o->method < FK_CG_PIPELINED || o->method > FK_CG_MIXED)
+    if (o->method < FK_CG_PIPELINED || o->method > FK_GMRES_CLASSICAL)
         return fail(FK_E_ARG, "unknown method %d", o->method);
+    if (o->restart < 0 || o->restart > GM_MAX)
+        return fail(FK_E_ARG, "restart outside [0, %d]", GM_MAX);
     if (!(o->inner_rtol >= 0.0) || !std::isfinite(o->inner_rtol))
         return fail(FK_E_ARG, "inner_rtol must be finite and >= 0");
     if (o->max_outer < 0)
@@ -477,6 +490,8 @@ extern "C" fk_status fk_solver_create(fk_csr A, const fk_opts *o, void *hip_stre
     if (S->o.unroll == 0)
         S->o.unroll = 32;
     S->mixed = o->method == FK_CG_MIXED;
+    S->gmres = is_gmres(o->method);
+    S->gm = o->restart == 0 ? 30 : o->restart;
     if (S->o.inner_rtol == 0.0)
         S->o.inner_rtol = 1e-4;
     if (S->o.max_outer == 0)
@@ -504,7 +519,22 @@ extern "C" fk_status fk_solver_create(fk_csr A, const fk_opts *o, void *hip_stre
             return fail(FK_E_HIP, "%s failed: %s", #expr, hipGetErrorString(e_));         \
         }                                                                                  \
     } while (0)
-    if (S->mixed) {
+    if (S->gmres) {
+        const size_t m1 = (size_t)S->gm + 1;
+        S_TRY(dev_alloc(&S->r, n, "r"));
+        S_TRY(dev_alloc(&S->V, m1 * n, "Krylov basis"));
+        S_TRY(dev_alloc(&S->gR, m1 * m1, "R"));
+        S_TRY(dev_alloc(&S->geta, m1, "eta"));
+        S_TRY(dev_alloc(&S->gpart, GM_PART_DOUBLES, "multi-dot partials"));
+        try {
+            S->hR.assign(m1 * m1, 0.0);
+            S->heta.assign(m1, 0.0);
+        } catch (const std::bad_alloc &) {
+            solver_release(S);
+            delete S;
+            return fail(FK_E_OOM, "host allocation failed");
+        }
+    } else if (S->mixed) {
         S_TRY(dev_alloc(&S->r32, n, "r32"));
         S_TRY(dev_alloc(&S->p32, n, "p32"));
         S_TRY(dev_alloc(&S->ap32, n, "Ap32"));
@@ -537,6 +567,10 @@ extern "C" fk_status fk_solver_create(fk_csr A, const fk_opts *o, void *hip_stre
         S_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
     S_HIP(hipMemsetAsync(S->st, 0, sizeof(DevState), S->stream));
     S_HIP(hipMemsetAsync(S->partials, 0, RED_SCRATCH_DOUBLES * sizeof(double), S->stream));
+    if (S->gmres) {
+        S_HIP(hipMemsetAsync(S->gR, 0, ((size_t)S->gm + 1) * ((size_t)S->gm + 1) * sizeof(double), S->stream));
+        S_HIP(hipMemsetAsync(S->gpart, 0, GM_PART_DOUBLES * sizeof(double), S->stream));
+    }
     if (S->mixed) {
         S_HIP(hipMemsetAsync(S->st_outer, 0, sizeof(DevState), S->stream));
         if (A->nnz > 0)
@@ -861,6 +895,100 @@ static fk_status run_batches(fk_solver S, const double *b, double *x, double rto
     return FK_OK;
 }
 
+// Restarted GMRES(m), Algorithm 6 (pipelined) or Algorithm 5 (classical
+// residual update): a cycle is enqueued at once (its kernels return at once
+// after the device ends the cycle), then R and xi are read back, R eta = xi
+// is solved on the host and x is updated on the device.
+#define ENQ(kind, call)                                                                    \
+    do {                                                                                   \
+        hipError_t e_ = q.run(kind, [&]() { return (call); });                              \
+        if (e_ != hipSuccess)                                                              \
+            return e_;                                                                     \
+    } while (0)
+
+static fk_status solve_gmres(fk_solver S, const double *b, double *x, bool profile)
+{
+    const DevCsr A = S->A->view();
+    const int64_t n = S->n;
+    const int m = S->gm, m1 = m + 1;
+    const int gs = S->grid_spmv, gv = S->grid_vec;
+    hipStream_t st = S->stream;
+    const bool classical = S->o.method == FK_GMRES_CLASSICAL;
+    DevState init{};
+    init.status = ST_RUNNING;
+    init.rtol = S->o.rtol;
+    init.max_iter = S->o.max_iter;
+    init.hist_cap = S->hist_cap;
+    init.gm = m;
+    S->h_init[0] = init;
+    HIP_TRY(hipMemcpyAsync(S->st, &S->h_init[0], sizeof(DevState), hipMemcpyHostToDevice, st));
+    auto vec = [&](int j) { return S->V + (size_t)j * n; };
+    auto red = [&](int fin) { return RedArgs{S->st, S->partials, S->hist, S->gR, fin, RUN_ACTIVE}; };
+    for (;;) {
+        S->prof_batch[0].clear();
+        S->prof_next[0] = 0;
+        Enq q{S, profile, 0};
+        hipError_t e = [&]() -> hipError_t {
+            // r0 = b - A x, ||r0||, ||b|| (first cycle); v_0 = r0 / rho0
+            ENQ(FK_KERNEL_SETUP, launch_residual0(A, b, x, S->r, vec(0), nullptr, red(FIN_GM_SETUP), gs, st));
+            ENQ(FK_KERNEL_SETUP, launch_gm_scale(n, vec(0), S->r, S->st, RUN_ACTIVE, gv, st));
+            if (classical)
+                ENQ(FK_KERNEL_AXPY, launch_gm_scale(n, S->r, S->r, S->st, RUN_ACTIVE, gv, st));
+            const double *rxi = classical ? S->r : vec(0);
+            for (int i = 1; i <= m; ++i) {
+                // w = A v_{i-1} (into slot i), with <v_{i-1}, w> when i >= 2
+                ENQ(FK_KERNEL_SPMV_DOT, launch_spmv_dots(A, vec(i - 1), vec(i), nullptr, i >= 2 ? D_YV : 0,
+                                                         red(i >= 2 ? FIN_GM_R1 : FIN_NONE), gs, st));
+                if (i >= 3)
+                    ENQ(FK_KERNEL_DOT, launch_gm_multidot(n, S->V, vec(i), 1, i - 1, i, S->gR, m1, S->gpart,
+                                                          S->st, RUN_ACTIVE, st));
+                ENQ(FK_KERNEL_UPDATE_DOT, launch_gm_update(n, vec(i), S->V, i, m1, red(FIN_GM_NORM), gv, st));
+                ENQ(FK_KERNEL_UPDATE_DOT, launch_gm_normalize(n, vec(i), rxi, i, m1, red(FIN_GM_XI), gv, st));
+                if (classical)
+                    ENQ(FK_KERNEL_AXPY, launch_gm_rupdate(n, S->r, vec(i), i, S->gR, S->st, RUN_ACTIVE, gv, st));
+            }
+            return hipSuccess;
+        }();
+        if (e != hipSuccess)
+            return fail(FK_E_HIP, "GMRES enqueue: %s", hipGetErrorString(e));
+        HIP_TRY(hipMemcpyAsync(&S->h_init[2], S->st, sizeof(DevState), hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipMemcpyAsync(S->hR.data(), S->gR, S->hR.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipStreamSynchronize(st));
+        if (profile)
+            harvest_profile(S, 0);
+        DevState cur = S->h_init[2];
+        if (cur.status == ST_ZERO_RHS) {
+            HIP_TRY(hipMemsetAsync(x, 0, (size_t)n * sizeof(double), st));
+            HIP_TRY(hipStreamSynchronize(st));
+        }
+        if (cur.status != ST_CYCLE_DONE) {  // decided at the cycle start
+            S->last = cur;
+            return finish_solve(S);
+        }
+        const int used = cur.gi - 1;
+        if (used == 0) {
+            cur.status = ST_BREAKDOWN;
+            S->last = cur;
+            return finish_solve(S);
+        }
+        const double *R = S->hR.data();
+        for (int i = used; i >= 1; --i) {  // R eta = xi by back substitution
+            double sacc = R[i];
+            for (int j = i + 1; j <= used; ++j)
+                sacc = sacc - R[(size_t)i * m1 + j] * S->heta[j];
+            S->heta[i] = sacc / R[(size_t)i * m1 + i];
+        }
+        HIP_TRY(hipMemcpyAsync(S->geta, S->heta.data(), (size_t)m1 * sizeof(double), hipMemcpyHostToDevice, st));
+        HIP_TRY(launch_gm_xupdate(n, x, S->V, S->geta, used, S->st, gv, st));
+        // next cycle: status back to running (the pinned word is free again)
+        S->h_status[0] = ST_RUNNING;
+        HIP_TRY(hipMemcpyAsync(reinterpret_cast<char *>(S->st) + offsetof(DevState, status), &S->h_status[0],
+                               sizeof(int32_t), hipMemcpyHostToDevice, st));
+    }
+}
+
+#undef ENQ
+
 // Iterative refinement around the FP32 inner solver (FK_CG_MIXED).
 static fk_status solve_mixed(fk_solver S, const double *b, double *x, bool profile, bool graph)
 {
@@ -924,6 +1052,8 @@ extern "C" fk_status fk_solve(fk_solver S, const double *b, double *x)
     }
     if (S->mixed)
         return solve_mixed(S, b, x, profile, graph);
+    if (S->gmres)
+        return solve_gmres(S, b, x, profile);
 
     if (S->small) {
         DevState init{};
@@ -1055,8 +1185,8 @@ extern "C" fk_status fk_get_scalars(fk_solver S, double *out, int32_t cap, int32
         return fail(FK_E_ARG, "bad argument");
     if (!S->solved)
         return fail(FK_E_STATE, "no completed solve");
-    if (S->mixed)
-        return fail(FK_E_STATE, "no per-iteration scalars for the mixed-precision method");
+    if (S->mixed || S->gmres)
+        return fail(FK_E_STATE, "no per-iteration scalars for this method");
     if (!S->scal)
         return fail(FK_E_STATE, "solver created without record_history");
     *len = S->last.it;

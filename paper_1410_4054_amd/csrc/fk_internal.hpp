@@ -43,6 +43,7 @@ enum DevStatus : int32_t {
     ST_NOT_CONVERGED = 3, // iteration budget used up
     ST_BREAKDOWN = 4,
     ST_ZERO_RHS = 5,      // b = 0: x = 0, k = 0
+    ST_CYCLE_DONE = 6,    // GMRES: the current restart cycle has ended
 };
 
 constexpr uint32_t RUN_ACTIVE = 1u << ST_RUNNING;
@@ -60,11 +61,15 @@ struct alignas(128) DevState {
     double bnorm, tol, rtol;
     double last_rel;  // ||r_k|| / ||b|| of the last completed iteration
     double dots[KMAX];  // rounded results of the last reduction
+    double rho0;      // GMRES: ||r0|| of the current cycle
+    double zeta2;     // GMRES: (norm estimate / rho0)^2
     int32_t it;       // completed iterations k
     int32_t status;
     int32_t max_iter;
     int32_t hist_cap; // entries of hist / 4-tuples of scal available
-    uint32_t pad[4];
+    int32_t gi;       // GMRES: step of the current cycle (1-based, next to do)
+    int32_t gm;       // GMRES: restart length m
+    uint32_t pad[2];
 };
 
 // What the last workgroup does with the reduced inner products.
@@ -84,6 +89,10 @@ enum Fin : int32_t {
     FIN_C_B_RHO,        // classical BiCGStab: d = {<r,r0*>}
     FIN_HALF_DONE,      // BiCGStab half-step exit bookkeeping (no dots)
     FIN_MIX_OUTER,      // mixed precision: d = {<r,r>, <b,b>} of the FP64 true residual
+    FIN_GM_SETUP,       // GMRES cycle start: d = {<r0,r0>, <b,b>}
+    FIN_GM_R1,          // GMRES: d = {<v_{i-1}, w>} -> R[i-1][i]
+    FIN_GM_NORM,        // GMRES: d = {<w,w>} -> R[i][i]
+    FIN_GM_XI,          // GMRES: d = {<r, v_i>} -> xi_i, norm estimate, step done
 };
 
 // Everything a reduction point needs.
@@ -165,6 +174,34 @@ hipError_t launch_inner_setup32(int64_t n, const float *r, float *p, float *d, c
                                 int grid, hipStream_t s);
 hipError_t launch_add32(int64_t n, double *x, const float *d, int grid, hipStream_t s);
 hipError_t launch_to_f32(int64_t n, float *out, const double *in, int grid, hipStream_t s);
+
+// GMRES(m) (Algorithms 5 and 6).  The basis V holds m+1 vectors of n
+// doubles (v_0 = r0 / rho0, v_1..v_m orthonormal); R is (m+1) x (m+1)
+// row-major, row 0 holding xi_1..xi_m.  In `red`, scal points to R.
+constexpr int GM_MAX = 64;          // largest restart length
+constexpr int GM_GRID = 256;        // workgroups of the multi-dot kernel
+// Multi-dot scratch (doubles): double-double partials [GM_MAX][GM_GRID], then
+// one arrival counter on its own 128-byte line.
+constexpr size_t GM_PART_DOUBLES = (size_t)2 * GM_MAX * GM_GRID + 16;
+// out = in / rho0 (the cycle's first basis vector)
+hipError_t launch_gm_scale(int64_t n, double *out, const double *in, DevState *st, uint32_t run_mask, int grid,
+                           hipStream_t s);
+// R[j][i] = <v_j, w> for j0 <= j < j1 (first and second stage; the last
+// workgroup writes R)
+hipError_t launch_gm_multidot(int64_t n, const double *V, const double *w, int j0, int j1, int i, double *R,
+                              int m1, double *part, DevState *st, uint32_t run_mask, hipStream_t s);
+// w -= sum_{j=1}^{i-1} R[j][i] v_j; first stage of <w,w> (FIN_GM_NORM)
+hipError_t launch_gm_update(int64_t n, double *w, const double *V, int i, int m1, const RedArgs &red, int grid,
+                            hipStream_t s);
+// v_i = w / R[i][i] in place; first stage of <r, v_i> (FIN_GM_XI)
+hipError_t launch_gm_normalize(int64_t n, double *v, const double *r, int i, int m1, const RedArgs &red,
+                               int grid, hipStream_t s);
+// r -= xi_i v_i (the classical form's residual update)
+hipError_t launch_gm_rupdate(int64_t n, double *r, const double *v, int i, const double *R, DevState *st,
+                             uint32_t run_mask, int grid, hipStream_t s);
+// x += rho0 (eta_1 v_0 + sum_{j=2}^{used} eta_j v_{j-1})
+hipError_t launch_gm_xupdate(int64_t n, double *x, const double *V, const double *eta, int used,
+                             const DevState *st, int grid, hipStream_t s);
 
 // Single-workgroup solver (whole solve in one launch) for small systems.
 // Rows per thread: 1, 2, 4 or 8 (0 = too large); LDS bytes it needs.

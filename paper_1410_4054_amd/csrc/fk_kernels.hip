@@ -376,6 +376,63 @@ __device__ void finalize(DevState *st, int fin, const double *d, int K, double *
             st->status = ST_CONVERGED;
         break;
     }
+    case FIN_GM_SETUP: {  // GMRES cycle start: d = {<r0,r0>, <b,b>}
+        const double rr = d[0], bb = d[1];
+        if (st->bnorm == 0.0) {  // first cycle of the solve
+            if (bb == 0.0) {
+                st->last_rel = 0.0;
+                put_hist(st, hist, 0, 0.0);
+                st->status = ST_ZERO_RHS;
+                break;
+            }
+            st->bnorm = sqrt(bb);
+            st->tol = st->rtol * st->bnorm;
+        }
+        const double rho0 = sqrt(rr);
+        st->rho0 = rho0;
+        st->last_rel = rho0 / st->bnorm;
+        put_hist(st, hist, st->it, rho0 / st->bnorm);
+        if (!isfinite(rho0))
+            st->status = ST_BREAKDOWN;
+        else if (rho0 <= st->tol)
+            st->status = ST_CONVERGED;
+        else if (st->it >= st->max_iter)
+            st->status = ST_NOT_CONVERGED;
+        else {
+            st->zeta2 = 1.0;
+            st->gi = 1;
+        }
+        break;
+    }
+    case FIN_GM_R1:  // R[i-1][i] = <v_{i-1}, w> (scal points to R)
+        scal[(st->gi - 1) * (st->gm + 1) + st->gi] = d[0];
+        break;
+    case FIN_GM_NORM: {  // R[i][i] = ||w||; a zero or non-finite norm ends the cycle before step i
+        const double rii = sqrt(d[0]);
+        if (!(rii > 0.0) || !isfinite(rii))
+            st->status = ST_CYCLE_DONE;
+        else
+            scal[st->gi * (st->gm + 1) + st->gi] = rii;
+        break;
+    }
+    case FIN_GM_XI: {  // xi_i = <r, v_i>; norm estimate rho0 sqrt(zeta2)
+        const double xi = d[0];
+        const int i = st->gi;
+        scal[i] = xi;  // row 0 of R
+        double z = st->zeta2 - xi * xi;
+        if (z < 0.0)
+            z = 0.0;
+        st->zeta2 = z;
+        const int it = st->it + 1;
+        st->it = it;
+        const double est = st->rho0 * sqrt(z);
+        st->last_rel = est / st->bnorm;
+        put_hist(st, hist, it, est / st->bnorm);
+        st->gi = i + 1;
+        if (est <= st->tol || i + 1 > st->gm || it >= st->max_iter)
+            st->status = ST_CYCLE_DONE;
+        break;
+    }
     case FIN_HALF_DONE: {  // BiCGStab exit after the half step
         const int it = st->it + 1;
         st->it = it;
@@ -968,6 +1025,175 @@ __global__ __launch_bounds__(WG) void k_to_f32(int64_t n, float *__restrict__ ou
         out[i] = (float)in[i];
 }
 
+
+// -------------------------------------------------------------- GMRES(m)
+
+__device__ __forceinline__ bool runs_mask(const DevState *st, uint32_t mask)
+{
+    return ((1u << st->status) & mask) != 0u;
+}
+
+// out = in / rho0 (out may be in: each element is read before it is written).
+__global__ __launch_bounds__(WG) void k_gm_scale(int64_t n, double *out, const double *in, DevState *st,
+                                                  uint32_t mask)
+{
+    if (!runs_mask(st, mask))
+        return;
+    const double rho0 = st->rho0;
+    const int64_t stride = (int64_t)gridDim.x * WG;
+    for (int64_t t = (int64_t)blockIdx.x * WG + threadIdx.x; t < n; t += stride)
+        out[t] = in[t] / rho0;
+}
+
+// R[j][i] = <v_j, w> for j0 <= j < j1, all from the same w (classical
+// Gram-Schmidt).  Workgroup g owns a contiguous chunk of rows and keeps
+// GM_JT double-double accumulators at a time; its partials go to
+// part[j][g].  The last workgroup to arrive sums every dot's partials in
+// workgroup order, four threads per dot (a fixed split and a fixed 4-lane
+// tree), and writes R.
+constexpr int GM_JT = 8;
+__global__ __launch_bounds__(WG) void k_gm_multidot(int64_t n, const double *__restrict__ V,
+                                                     const double *__restrict__ w, int j0, int j1, int i,
+                                                     double *R, int m1, double *part, DevState *st,
+                                                     uint32_t mask)
+{
+    if (!runs_mask(st, mask))
+        return;
+    __shared__ dd lds[WAVES][KMAX];
+    __shared__ int s_last;
+    const int G = gridDim.x, g = blockIdx.x;
+    const int64_t lo = n * g / G, hi = n * (g + 1) / G;
+    for (int jt = j0; jt < j1; jt += GM_JT) {
+        dd acc[GM_JT];
+#pragma unroll
+        for (int q = 0; q < GM_JT; ++q)
+            acc[q] = dd{0.0, 0.0};
+        for (int64_t t = lo + threadIdx.x; t < hi; t += WG) {
+            const double wt = w[t];
+#pragma unroll
+            for (int q = 0; q < GM_JT; ++q)
+                if (jt + q < j1)
+                    dd_fma(acc[q], V[(size_t)(jt + q) * n + t], wt);
+        }
+        // block sums, KMAX at a time
+#pragma unroll
+        for (int q0 = 0; q0 < GM_JT; q0 += KMAX) {
+            dd v4[KMAX];
+#pragma unroll
+            for (int q = 0; q < KMAX; ++q)
+                v4[q] = acc[q0 + q];
+            block_reduce<KMAX>(v4, lds);
+            if (threadIdx.x == 0) {
+#pragma unroll
+                for (int q = 0; q < KMAX; ++q) {
+                    const int j = jt + q0 + q;
+                    if (j < j1) {
+                        double *slot = part + 2 * ((size_t)j * GM_GRID + g);
+                        store_coherent(slot, v4[q].hi);
+                        store_coherent(slot + 1, v4[q].lo);
+                    }
+                }
+            }
+        }
+    }
+    uint32_t *cnt = reinterpret_cast<uint32_t *>(part + (size_t)2 * GM_MAX * GM_GRID);
+    if (threadIdx.x == 0) {
+        __builtin_amdgcn_s_waitcnt(0);
+        const uint32_t prev = __hip_atomic_fetch_add(cnt, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        s_last = prev == (uint32_t)(G - 1) ? 1 : 0;
+    }
+    __syncthreads();
+    if (!s_last)
+        return;
+    const int j = j0 + (int)threadIdx.x / 4, q = (int)threadIdx.x % 4;
+    dd a = dd{0.0, 0.0};
+    if (j < j1) {
+        const int ga = G * q / 4, gb = G * (q + 1) / 4;
+        for (int gg = ga; gg < gb; ++gg) {
+            const double *slot = part + 2 * ((size_t)j * GM_GRID + gg);
+            a = dd_add(a, dd{load_coherent(slot), load_coherent(slot + 1)});
+        }
+    }
+    // lanes 4k..4k+3 hold the four quarters of one dot
+    dd o;
+    o.hi = __shfl_xor(a.hi, 1, 64);
+    o.lo = __shfl_xor(a.lo, 1, 64);
+    a = (q & 1) ? dd_add(o, a) : dd_add(a, o);
+    o.hi = __shfl_xor(a.hi, 2, 64);
+    o.lo = __shfl_xor(a.lo, 2, 64);
+    a = (q & 2) ? dd_add(o, a) : dd_add(a, o);
+    if (j < j1 && q == 0)
+        R[(size_t)j * m1 + i] = a.hi + a.lo;
+    if (threadIdx.x == 0)
+        __hip_atomic_store(cnt, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// w -= sum_{j=1}^{i-1} R[j][i] v_j (j in order); first stage of <w, w>.
+__global__ __launch_bounds__(WG) void k_gm_update(int64_t n, double *__restrict__ w,
+                                                   const double *__restrict__ V, int i, int m1, RedArgs red)
+{
+    if (!runs(red))
+        return;
+    const double *R = red.scal;
+    dd acc[1] = {dd{0.0, 0.0}};
+    const int64_t stride = (int64_t)gridDim.x * WG;
+    for (int64_t t = (int64_t)blockIdx.x * WG + threadIdx.x; t < n; t += stride) {
+        double wt = w[t];
+        for (int j = 1; j < i; ++j)
+            wt = wt - R[(size_t)j * m1 + i] * V[(size_t)j * n + t];
+        w[t] = wt;
+        dd_fma(acc[0], wt, wt);
+    }
+    reduce_point<1>(acc, red, blockIdx.x, gridDim.x);
+}
+
+// v_i = w / R[i][i] (in place); first stage of <r, v_i>.
+__global__ __launch_bounds__(WG) void k_gm_normalize(int64_t n, double *__restrict__ v,
+                                                      const double *__restrict__ r, int i, int m1, RedArgs red)
+{
+    if (!runs(red))
+        return;
+    const double rii = red.scal[(size_t)i * m1 + i];
+    dd acc[1] = {dd{0.0, 0.0}};
+    const int64_t stride = (int64_t)gridDim.x * WG;
+    for (int64_t t = (int64_t)blockIdx.x * WG + threadIdx.x; t < n; t += stride) {
+        const double vt = v[t] / rii;
+        v[t] = vt;
+        dd_fma(acc[0], r[t], vt);
+    }
+    reduce_point<1>(acc, red, blockIdx.x, gridDim.x);
+}
+
+// r -= xi_i v_i (xi_i in row 0 of R).  Runs after the step was counted,
+// so it checks the step index rather than the status.
+__global__ __launch_bounds__(WG) void k_gm_rupdate(int64_t n, double *__restrict__ r,
+                                                    const double *__restrict__ v, int i,
+                                                    const double *__restrict__ R, DevState *st, uint32_t mask)
+{
+    if (!runs_mask(st, mask) || st->gi != i + 1)
+        return;
+    const double xi = R[i];
+    const int64_t stride = (int64_t)gridDim.x * WG;
+    for (int64_t t = (int64_t)blockIdx.x * WG + threadIdx.x; t < n; t += stride)
+        r[t] = r[t] - xi * v[t];
+}
+
+// x += rho0 (eta_1 v_0 + sum_{j=2}^{used} eta_j v_{j-1}), the sum in j order.
+__global__ __launch_bounds__(WG) void k_gm_xupdate(int64_t n, double *__restrict__ x,
+                                                    const double *__restrict__ V,
+                                                    const double *__restrict__ eta, int used,
+                                                    const DevState *st)
+{
+    const double rho0 = st->rho0;
+    const int64_t stride = (int64_t)gridDim.x * WG;
+    for (int64_t t = (int64_t)blockIdx.x * WG + threadIdx.x; t < n; t += stride) {
+        double s = eta[1] * V[t];
+        for (int j = 2; j <= used; ++j)
+            s = s + eta[j] * V[(size_t)(j - 1) * n + t];
+        x[t] = x[t] + rho0 * s;
+    }
+}
+
 // ------------------------------------------- single-workgroup solver
 
 // A whole pipelined CG or BiCGStab solve in one workgroup of SWG threads,
@@ -1393,6 +1619,7 @@ hipError_t launch_spmv_dots(const DevCsr &A, const double *v, double *y, const d
     RowIo io{v, y, w, nullptr, nullptr, nullptr};
     switch (dots) {
     case 0: return launch(k_csr_rows<ROW_SPMV, 0>, grid, WG, s, A, io, red);
+    case D_YV: return launch(k_csr_rows<ROW_SPMV, D_YV>, grid, WG, s, A, io, red);
     case D_YV | D_YY: return launch(k_csr_rows<ROW_SPMV, D_YV | D_YY>, grid, WG, s, A, io, red);
     case D_YW: return launch(k_csr_rows<ROW_SPMV, D_YW>, grid, WG, s, A, io, red);
     case D_YV | D_YY | D_YW: return launch(k_csr_rows<ROW_SPMV, D_YV | D_YY | D_YW>, grid, WG, s, A, io, red);
@@ -1405,6 +1632,42 @@ hipError_t launch_residual0(const DevCsr &A, const double *b, const double *x, d
 {
     RowIo io{x, r, b, p, rs, nullptr};
     return launch(k_csr_rows<ROW_RESID, 0>, grid, WG, s, A, io, red);
+}
+
+hipError_t launch_gm_scale(int64_t n, double *out, const double *in, DevState *st, uint32_t run_mask, int grid,
+                           hipStream_t s)
+{
+    return launch(k_gm_scale, grid, WG, s, n, out, in, st, run_mask);
+}
+
+hipError_t launch_gm_multidot(int64_t n, const double *V, const double *w, int j0, int j1, int i, double *R,
+                              int m1, double *part, DevState *st, uint32_t run_mask, hipStream_t s)
+{
+    return launch(k_gm_multidot, GM_GRID, WG, s, n, V, w, j0, j1, i, R, m1, part, st, run_mask);
+}
+
+hipError_t launch_gm_update(int64_t n, double *w, const double *V, int i, int m1, const RedArgs &red, int grid,
+                            hipStream_t s)
+{
+    return launch(k_gm_update, grid, WG, s, n, w, V, i, m1, red);
+}
+
+hipError_t launch_gm_normalize(int64_t n, double *v, const double *r, int i, int m1, const RedArgs &red,
+                               int grid, hipStream_t s)
+{
+    return launch(k_gm_normalize, grid, WG, s, n, v, r, i, m1, red);
+}
+
+hipError_t launch_gm_rupdate(int64_t n, double *r, const double *v, int i, const double *R, DevState *st,
+                             uint32_t run_mask, int grid, hipStream_t s)
+{
+    return launch(k_gm_rupdate, grid, WG, s, n, r, v, i, R, st, run_mask);
+}
+
+hipError_t launch_gm_xupdate(int64_t n, double *x, const double *V, const double *eta, int used,
+                             const DevState *st, int grid, hipStream_t s)
+{
+    return launch(k_gm_xupdate, grid, WG, s, n, x, V, eta, used, st);
 }
 
 hipError_t launch_residual32(const DevCsr &A, const double *b, const double *x, float *r32,

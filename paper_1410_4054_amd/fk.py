@@ -24,7 +24,7 @@ STATUS_NAMES = {
 }
 # fk_method
 METHODS = {"cg_pipelined": 0, "cg_classical": 1, "bicgstab_pipelined": 2, "bicgstab_classical": 3,
-           "cg_mixed": 4}
+           "cg_mixed": 4, "gmres_pipelined": 5, "gmres_classical": 6}
 FLAG_GRAPH = 1
 FLAG_PROFILE = 2
 FLAG_NO_SMALL = 4
@@ -49,6 +49,7 @@ class _Opts(ctypes.Structure):
         ("flags", ctypes.c_int32),
         ("inner_rtol", ctypes.c_double),
         ("max_outer", ctypes.c_int32),
+        ("restart", ctypes.c_int32),
     ]
 
 
@@ -274,10 +275,11 @@ class Solver:
     def __init__(self, A: Matrix, method: str = "cg_pipelined", rtol: float = 1e-8,
                  max_iter: int | None = None, record_history: bool = True, unroll: int = 32,
                  graph: bool = False, profile: bool = False, small: bool = True,
-                 inner_rtol: float = 0.0, max_outer: int = 0, stream=None):
+                 inner_rtol: float = 0.0, max_outer: int = 0, restart: int = 0, stream=None):
         """small=False forces the multi-kernel path even where the
         single-workgroup solver applies.  inner_rtol, max_outer: options of
-        method "cg_mixed" (0 = library defaults 1e-4 and 50)."""
+        method "cg_mixed" (0 = library defaults 1e-4 and 50); restart: the
+        GMRES restart length m (0 = 30)."""
         import torch
 
         self.A = A
@@ -290,7 +292,7 @@ class Solver:
         flags = ((FLAG_GRAPH if graph else 0) | (FLAG_PROFILE if profile else 0)
                  | (0 if small else FLAG_NO_SMALL))
         o = _Opts(METHODS[method], float(rtol), int(max_iter), int(bool(record_history)),
-                  int(unroll), flags, float(inner_rtol), int(max_outer))
+                  int(unroll), flags, float(inner_rtol), int(max_outer), int(restart))
         h = ctypes.c_void_p()
         st = lib().fk_solver_create(A.handle, ctypes.byref(o), ctypes.c_void_p(_stream_ptr(stream)),
                                     ctypes.byref(h))
@@ -373,7 +375,7 @@ def solve(A: Matrix, b, x, method: str = "cg_pipelined", rtol: float = 1e-8,
     try:
         st = S.solve(b, x)
         hist = S.history() if record_history else None
-        scal = S.scalars() if record_history and method != "cg_mixed" else None
+        scal = S.scalars() if record_history and method in METHODS and METHODS[method] < 4 else None
         return SolveResult(STATUS_NAMES[st], S.iterations(), S.residual(), hist, scal,
                            S.refinements())
     finally:
