@@ -246,6 +246,28 @@ def main():
         extras["bicgstab_convdiff2d_1024_k"] = S3.iterations()
         S3.close(); M3.close()
 
+        log("[bench] extras: GMRES(30) 1024^2")
+        # GMRES(30) on the nonsymmetric workload: two cycles of 30 iterations,
+        # pipelined (4 kernels per iteration) against classical (residual
+        # updated in the loop), median of 5 runs.
+        A3g, b3g, _ = P.workload("convdiff2d_1024")
+        M3g = fk.Matrix(A3g)
+        b3gd = torch.as_tensor(b3g, device="cuda")
+        x3gd = torch.zeros_like(b3gd)
+        for method in ("gmres_pipelined", "gmres_classical"):
+            Sg = fk.Solver(M3g, method=method, rtol=0.0, max_iter=60, restart=30, record_history=False)
+            times = []
+            for _ in range(6):
+                x3gd.zero_()
+                torch.cuda.synchronize()
+                t = time.perf_counter()
+                Sg.solve(b3gd, x3gd)
+                torch.cuda.synchronize()
+                times.append(time.perf_counter() - t)
+            Sg.close()
+            extras[f"{method}_convdiff2d_1024_m30_us_per_iter"] = float(np.median(times[1:])) / 60 * 1e6
+        M3g.close()
+
         log("[bench] extras: mixed precision 128^3")
         # Mixed precision: FP64 iterative refinement around FP32 pipelined CG
         # against FP64 pipelined CG, both to 1e-10 on 128^3.
