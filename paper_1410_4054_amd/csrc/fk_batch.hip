@@ -83,6 +83,38 @@ __device__ __forceinline__ void wg_reduce(dd (&v)[K], double (&out)[K], dd (*lds
     __syncthreads();
 }
 
+// One CSR row summed left to right, with the column indices and values of
+// up to RB nonzeros requested together and their gathers next, so a thread
+// has many loads in flight instead of a dependent chain per nonzero.
+constexpr int RB = 8;
+
+template <typename T, typename V>
+__device__ __forceinline__ T row_sum(const int32_t *__restrict__ col, const T *__restrict__ vals,
+                                     const V *__restrict__ x, int j0, int j1, int shift)
+{
+    T q = T(0);
+    for (int j = j0; j < j1; j += RB) {
+        int c[RB];
+        T v[RB];
+#pragma unroll
+        for (int k = 0; k < RB; ++k)
+            if (j + k < j1) {
+                c[k] = col[j + k] - shift;
+                v[k] = vals[j + k];
+            }
+        T g[RB];
+#pragma unroll
+        for (int k = 0; k < RB; ++k)
+            if (j + k < j1)
+                g[k] = (T)x[c[k]];
+#pragma unroll
+        for (int k = 0; k < RB; ++k)
+            if (j + k < j1)
+                q = q + v[k] * g[k];
+    }
+    return q;
+}
+
 template <int WGS>
 __global__ __launch_bounds__(WGS) void k_batch_mixed(BatchArgs a)
 {
@@ -118,9 +150,8 @@ __global__ __launch_bounds__(WGS) void k_batch_mixed(BatchArgs a)
             dd acc[2] = {dd{0.0, 0.0}, dd{0.0, 0.0}};
             for (int i = tid; i < n; i += WGS) {
                 const int gi = r0 + i;
-                double q = 0.0;
-                for (int32_t j = a.row_ptr[gi]; j < a.row_ptr[gi + 1]; ++j)
-                    q = q + a.vals[j] * a.x[a.col_idx[j]];
+                const double q = row_sum<double, double>(a.col_idx, a.vals, a.x, a.row_ptr[gi],
+                                                         a.row_ptr[gi + 1], 0);
                 const double ri = a.b[gi] - q;
                 R[i] = (float)ri;
                 dd_fma(acc[0], ri, ri);
@@ -192,9 +223,8 @@ __global__ __launch_bounds__(WGS) void k_batch_mixed(BatchArgs a)
                     }
                     for (int i = tid; i < n; i += WGS) {
                         const int gi = r0 + i;
-                        float q = 0.f;
-                        for (int32_t j = a.row_ptr[gi]; j < a.row_ptr[gi + 1]; ++j)
-                            q = q + a.vals32[j] * P[a.col_idx[j] - r0];
+                        const float q = row_sum<float, float>(a.col_idx, a.vals32, P, a.row_ptr[gi],
+                                                              a.row_ptr[gi + 1], r0);
                         AP[i] = q;
                         dd_fma(acc3[1], (double)q, (double)P[i]);
                         dd_fma(acc3[2], (double)q, (double)q);
