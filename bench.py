@@ -10,8 +10,11 @@ synthetic input already resident in HBM.
 
 value = CG iterations per second over the K timed steps.  The roofline
 entry is for the dominant kernel, the fused SpMV + two dots: algorithmic
-bytes per launch (12 nnz + 20 N + 4: values, column indices, row pointers,
-one read of p, one write of Ap) over its average duration, measured with HIP
+bytes per launch of the layout it reads over its average duration.  The
+library stores this matrix in 64-row slices (sliced ELLPACK): 12 bytes per
+stored entry (values and column indices, padding included), 4 per slice
+offset, one read of p and one write of Ap, 16 N; in CSR row blocks it would
+be 12 nnz + 4 (N + 1) + 16 N.  Durations are measured with HIP
 events on the solver's stream that the device stamps at the start and end of
 each launch, in a second pass over the same K steps (the events cost wall
 time, so the timed pass runs without them).  The CPU baseline is
@@ -43,14 +46,21 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def spmv_dot_bytes(n: int, nnz: int) -> int:
-    """Compulsory bytes of one fused SpMV + 2 dots launch (FP64 values, int32 indices)."""
-    return 12 * nnz + 4 * (n + 1) + 8 * n + 8 * n
+def index_bytes(n: int, layout: str) -> int:
+    """Row pointers (row blocks) or slice offsets (sliced), int32."""
+    return 4 * (n + 1) if layout == "row_blocks" else 4 * (-(-n // 64) + 1)
 
 
-def spmv32_dot_bytes(n: int, nnz: int) -> int:
+def spmv_dot_bytes(n: int, entries: int, layout: str) -> int:
+    """Compulsory bytes of one fused SpMV + 2 dots launch: FP64 values and
+    int32 column indices of the `entries` the layout stores, its index
+    array, one read of p, one write of Ap."""
+    return 12 * entries + index_bytes(n, layout) + 8 * n + 8 * n
+
+
+def spmv32_dot_bytes(n: int, entries: int, layout: str) -> int:
     """The FP32 product + 2 dots of the mixed-precision inner solver."""
-    return 8 * nnz + 4 * (n + 1) + 4 * n + 4 * n
+    return 8 * entries + index_bytes(n, layout) + 4 * n + 4 * n
 
 
 def update_bytes(n: int) -> int:
@@ -150,10 +160,11 @@ def main():
     A, b, _ = P.workload(WORKLOAD)
     n, nnz = A.n, A.nnz
     M = fk.Matrix(A)
+    layout, entries = M.layout()
     bd = torch.as_tensor(b, device="cuda")
     xd = torch.zeros_like(bd)
 
-    log(f"[bench] {WORKLOAD}: n={n} nnz={nnz}; timing {args.steps} solves")
+    log(f"[bench] {WORKLOAD}: n={n} nnz={nnz} layout={layout} entries={entries}; timing {args.steps} solves")
     # Timed steps: K full solves, inputs resident in HBM.
     S = fk.Solver(M, method="cg_pipelined", rtol=RTOL, record_history=False)
     for _ in range(args.warmup):
@@ -201,7 +212,7 @@ def main():
 
     spmv_us = kernel_us["spmv_dot"][0] / max(kernel_us["spmv_dot"][1], 1)
     upd_us = kernel_us["update_dot"][0] / max(kernel_us["update_dot"][1], 1)
-    spmv_b = spmv_dot_bytes(n, nnz)
+    spmv_b = spmv_dot_bytes(n, entries, layout)
     achieved = spmv_b / (spmv_us * 1e-6) / 1e9
     traffic = measured_traffic("spmv_dot", WORKLOAD)
 
@@ -225,6 +236,16 @@ def main():
             extras["cg_classical_us_per_iter_30fixed_median10"]
             / extras["cg_pipelined_us_per_iter_30fixed_median10"])
         extras["spmv_dot_us"] = spmv_us
+        extras["spmv_layout"] = layout
+        extras["spmv_stored_entries"] = entries
+        # The same fused product on the CSR row-block layout, for comparison.
+        Mrb = fk.Matrix(A, layout="row_blocks")
+        Srb = fk.Solver(Mrb, method="cg_pipelined", rtol=RTOL, record_history=False, profile=True)
+        xd.zero_(); Srb.solve(bd, xd)
+        rb_us = Srb.kernel_times()["spmv_dot"][0]
+        Srb.close(); Mrb.close()
+        extras["row_blocks_spmv_dot_us"] = rb_us
+        extras["row_blocks_spmv_dot_GBps"] = spmv_dot_bytes(n, nnz, "row_blocks") / (rb_us * 1e-6) / 1e9
         extras["update_dot_us"] = upd_us
         extras["update_dot_GBps"] = update_bytes(n) / (upd_us * 1e-6) / 1e9
         per_it_bytes = spmv_b + update_bytes(n)
@@ -286,7 +307,7 @@ def main():
         kt = S2.kernel_times()
         S2.close()
         extras["mixed_spmv32_dot_us"] = kt["spmv_dot"][0]
-        extras["mixed_spmv32_dot_GBps"] = spmv32_dot_bytes(n, nnz) / (kt["spmv_dot"][0] * 1e-6) / 1e9
+        extras["mixed_spmv32_dot_GBps"] = spmv32_dot_bytes(n, entries, layout) / (kt["spmv_dot"][0] * 1e-6) / 1e9
         extras["mixed_update32_dot_us"] = kt["update_dot"][0]
         extras["mixed_update32_dot_GBps"] = 28 * n / (kt["update_dot"][0] * 1e-6) / 1e9
         extras["mixed_residual_fp64_us"] = kt["residual"][0]
@@ -437,7 +458,9 @@ def main():
                    "iterations_per_solve": k_final, "final_rel_residual": rel},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
                      "frac": achieved / PEAK_HBM_GBS, "traffic": traffic,
-                     "kernel": "fused SpMV + <p,Ap>, <Ap,Ap> (k_csr_rows<0,3>)",
+                     "kernel": "fused SpMV + <p,Ap>, <Ap,Ap> ("
+                               + ("k_sell_rows<0,3>" if layout == "sliced" else "k_csr_rows<0,3>") + ")",
+                     "layout": layout,
                      "bytes_per_launch": spmv_b, "avg_us": spmv_us,
                      "update_dot_avg_us": upd_us},
         "cpu_baseline": cpu,

@@ -99,6 +99,13 @@ typedef struct {
 
 enum { FK_PTR_HOST = 0, FK_PTR_DEVICE = 1 };
 
+/* Layouts the product kernels read (fk_csr_layout, fk_csr_set_layout). */
+enum {
+    FK_LAYOUT_AUTO = 0,        /* the creation rule below                      */
+    FK_LAYOUT_ROW_BLOCKS = 1,  /* the CSR arrays, cut into row blocks          */
+    FK_LAYOUT_SLICED = 2       /* the nonzeros regrouped into 64-row slices    */
+};
+
 /*
  * Create a device-resident CSR matrix (the CSR storage of Section 2.2).
  * The arrays are validated on the host (FK_E_CSR on any violation of the
@@ -122,6 +129,36 @@ fk_status fk_csr_shape(fk_csr A, int64_t *n, int64_t *nnz);
  * consecutive rows holding at most FK_LONG_ROW nonzeros, the unit of work of
  * the product kernels) and number of rows longer than FK_LONG_ROW. */
 fk_status fk_csr_blocks(fk_csr A, int32_t *nblocks, int32_t *long_rows);
+
+/*
+ * Layout of the sparse products.  Both compute y_i as the sum of the row's
+ * products a_ij v_j taken left to right in CSR order (the SpMV of Section
+ * 2.2), so every result is bitwise the same in either layout; they differ
+ * only in how the nonzeros sit in device memory (Section 4 compares solvers
+ * across storage formats, ELLPACK among them):
+ *  - FK_LAYOUT_ROW_BLOCKS: the CSR arrays; a workgroup stages the products
+ *    of a run of rows in LDS and one thread sums each row.
+ *  - FK_LAYOUT_SLICED: a copy of the nonzeros in slices of 64 consecutive
+ *    rows; slice s stores w_s entries per row, w_s being its longest row,
+ *    entry k of each row of the slice side by side (sliced ELLPACK without
+ *    row sorting), shorter rows padded.  One lane sums one row; no LDS.
+ *    Costs 12 bytes of device memory per stored entry next to the CSR
+ *    arrays, which stay (other kernels read them).
+ * fk_csr_create picks SLICED when no row has more than 64 nonzeros and the
+ * padding adds at most 25 % to the entries read, else ROW_BLOCKS.
+ * fk_csr_layout reports the layout in use and the entries its products read
+ * per call (nnz, or the slice entries with padding).
+ */
+fk_status fk_csr_layout(fk_csr A, int32_t *layout, int64_t *stored_entries);
+
+/*
+ * Force a layout: FK_LAYOUT_ROW_BLOCKS, FK_LAYOUT_SLICED (builds the slices
+ * when absent, whatever their padding; FK_E_ARG if they would need more than
+ * INT32_MAX entries) or FK_LAYOUT_AUTO (the creation rule).  Solvers read the
+ * layout when they are created, so FK_E_STATE while any solver exists on A.
+ * Runs on hip_stream and returns after it has drained.
+ */
+fk_status fk_csr_set_layout(fk_csr A, int32_t layout, void *hip_stream);
 
 /*
  * Create a solver for A with options *o, bound to hip_stream.  Allocates the

@@ -129,6 +129,12 @@ struct fk_csr_s {
     int32_t nblocks = 0;
     int32_t long_rows = 0;
     int device = 0;
+    // sliced layout (built when it pays, or on request)
+    int32_t *sell_ptr = nullptr, *sell_col = nullptr;
+    double *sell_vals = nullptr;
+    int32_t nslices = 0;      // > 0 once the sliced arrays exist
+    int64_t sell_entries = 0;
+    int32_t layout = FK_LAYOUT_ROW_BLOCKS;  // layout the products read
     // scratch reduction state for fk_spmv
     DevState *st = nullptr;
     double *partials = nullptr;
@@ -136,8 +142,14 @@ struct fk_csr_s {
 
     DevCsr view() const
     {
-        return DevCsr{(int32_t)n, (int32_t)nnz, nblocks, row_ptr, col_idx, vals, blocks, block_j0};
+        const bool sliced = layout == FK_LAYOUT_SLICED;
+        return DevCsr{(int32_t)n,  (int32_t)nnz, nblocks,  row_ptr,
+                      col_idx,     vals,         blocks,   block_j0,
+                      sliced ? nslices : 0,      sell_ptr, sell_col,
+                      sell_vals};
     }
+    // Entries the products read: nnz, or the slice entries with padding.
+    int64_t stored_entries() const { return layout == FK_LAYOUT_SLICED ? sell_entries : nnz; }
 };
 
 DevCsr fk::internal_csr_view(fk_csr A) { return A->view(); }
@@ -188,8 +200,112 @@ static std::vector<int32_t> plan_blocks(const int32_t *rp, int64_t n, int32_t *l
     return b;
 }
 
+// Sliced layout: slice s covers rows [s*SLICE, (s+1)*SLICE) and stores
+// width_s = longest row of the slice entries per row.  Returns the entry
+// offsets of the slices (entries[nslices] = total, padding included) and
+// the longest row.
+static std::vector<int64_t> plan_slices(const int32_t *rp, int64_t n, int64_t *max_len)
+{
+    const int64_t ns = (n + SLICE - 1) / SLICE;
+    std::vector<int64_t> off((size_t)ns + 1, 0);
+    *max_len = 0;
+    for (int64_t sl = 0; sl < ns; ++sl) {
+        int64_t w = 0;
+        for (int64_t r = sl * SLICE; r < std::min<int64_t>(n, (sl + 1) * SLICE); ++r)
+            w = std::max<int64_t>(w, (int64_t)rp[r + 1] - rp[r]);
+        *max_len = std::max(*max_len, w);
+        off[(size_t)sl + 1] = off[(size_t)sl] + w * SLICE;
+    }
+    return off;
+}
+
+// Rows longer than this are left to the row-block layout: one lane would
+// walk them alone while its wave waits.
+constexpr int64_t SLICED_MAX_ROW = 64;
+
+// The creation rule: slices when no row is long and padding adds at most a
+// quarter to the entries read.
+static bool sliced_pays(const std::vector<int64_t> &off, int64_t nnz, int64_t max_len)
+{
+    const int64_t entries = off.back();
+    return nnz > 0 && max_len <= SLICED_MAX_ROW && 4 * entries <= 5 * nnz && entries <= INT32_MAX;
+}
+
+// Uploads the sliced arrays of A from host copies of its row pointers and
+// column indices; values are gathered on the device from A->vals.
+static fk_status build_slices(fk_csr A, const int32_t *rp, const int32_t *ci,
+                              const std::vector<int64_t> &off, hipStream_t s)
+{
+    const int64_t n = A->n;
+    const int64_t ns = (int64_t)off.size() - 1;
+    const int64_t entries = off.back();
+    if (entries > INT32_MAX)
+        return fail(FK_E_ARG, "sliced layout needs %lld entries, more than int32 offsets hold",
+                    (long long)entries);
+    std::vector<int32_t> ptr, col, map;
+    try {
+        ptr.resize((size_t)ns + 1);
+        col.assign((size_t)std::max<int64_t>(entries, 1), -1);
+        map.assign((size_t)std::max<int64_t>(entries, 1), -1);
+    } catch (const std::bad_alloc &) {
+        return fail(FK_E_OOM, "host allocation failed");
+    }
+    for (int64_t sl = 0; sl <= ns; ++sl)
+        ptr[(size_t)sl] = (int32_t)off[(size_t)sl];
+    for (int64_t r = 0; r < n; ++r) {
+        const int64_t sl = r / SLICE, lane = r % SLICE;
+        for (int32_t j = rp[r]; j < rp[r + 1]; ++j) {
+            const size_t e = (size_t)(off[(size_t)sl] + (int64_t)(j - rp[r]) * SLICE + lane);
+            col[e] = ci[j];
+            map[e] = j;
+        }
+    }
+    int32_t *d_ptr = nullptr, *d_col = nullptr, *d_map = nullptr;
+    double *d_vals = nullptr;
+    fk_status st = dev_alloc(&d_ptr, (size_t)ns + 1, "slice offsets");
+    if (st == FK_OK)
+        st = dev_alloc(&d_col, col.size(), "slice columns");
+    if (st == FK_OK)
+        st = dev_alloc(&d_vals, col.size(), "slice values");
+    if (st == FK_OK)
+        st = dev_alloc(&d_map, map.size(), "slice map");
+    hipError_t e = hipSuccess;
+    if (st == FK_OK) {
+        e = hipMemcpyAsync(d_ptr, ptr.data(), ptr.size() * 4, hipMemcpyHostToDevice, s);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(d_col, col.data(), col.size() * 4, hipMemcpyHostToDevice, s);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(d_map, map.data(), map.size() * 4, hipMemcpyHostToDevice, s);
+        if (e == hipSuccess)
+            e = launch_gather_vals((int64_t)col.size(), d_vals, A->vals, d_map, vec_grid((int64_t)col.size()), s);
+        if (e == hipSuccess)
+            e = hipStreamSynchronize(s);
+        if (e != hipSuccess)
+            st = fail(FK_E_HIP, "building the sliced layout: %s", hipGetErrorString(e));
+    }
+    dev_free(d_map);
+    if (st != FK_OK) {
+        dev_free(d_ptr);
+        dev_free(d_col);
+        dev_free(d_vals);
+        return st;
+    }
+    dev_free(A->sell_ptr);
+    dev_free(A->sell_col);
+    dev_free(A->sell_vals);
+    A->sell_ptr = d_ptr;
+    A->sell_col = d_col;
+    A->sell_vals = d_vals;
+    A->nslices = (int32_t)ns;
+    A->sell_entries = entries;
+    return FK_OK;
+}
+
 static void csr_release(fk_csr A)
 {
+    dev_free(A->sell_ptr);
+    dev_free(A->sell_col);
+    dev_free(A->sell_vals);
     dev_free(A->row_ptr);
     dev_free(A->col_idx);
     dev_free(A->vals);
@@ -290,6 +406,19 @@ extern "C" fk_status fk_csr_create(int64_t n, int64_t nnz, const int32_t *row_pt
     CSR_HIP(hipMemsetAsync(A->st, 0, sizeof(DevState), s));
     CSR_HIP(hipMemsetAsync(A->partials, 0, RED_SCRATCH_DOUBLES * sizeof(double), s));
     CSR_HIP(hipStreamSynchronize(s));
+    {
+        int64_t max_len = 0;
+        std::vector<int64_t> off;
+        try {
+            off = plan_slices(rp, n, &max_len);
+        } catch (const std::bad_alloc &) {
+            CSR_TRY(fail(FK_E_OOM, "host allocation failed"));
+        }
+        if (sliced_pays(off, nnz, max_len)) {
+            CSR_TRY(build_slices(A, rp, ci, off, s));
+            A->layout = FK_LAYOUT_SLICED;
+        }
+    }
 #undef CSR_TRY
 #undef CSR_HIP
     *out = A;
@@ -313,6 +442,64 @@ extern "C" fk_status fk_csr_shape(fk_csr A, int64_t *n, int64_t *nnz)
         return fail(FK_E_ARG, "NULL argument");
     *n = A->n;
     *nnz = A->nnz;
+    return FK_OK;
+}
+
+extern "C" fk_status fk_csr_layout(fk_csr A, int32_t *layout, int64_t *stored_entries)
+{
+    if (!A || !layout || !stored_entries)
+        return fail(FK_E_ARG, "NULL argument");
+    *layout = A->layout;
+    *stored_entries = A->stored_entries();
+    return FK_OK;
+}
+
+extern "C" fk_status fk_csr_set_layout(fk_csr A, int32_t layout, void *hip_stream)
+{
+    if (!A)
+        return fail(FK_E_ARG, "NULL matrix");
+    if (layout != FK_LAYOUT_AUTO && layout != FK_LAYOUT_ROW_BLOCKS && layout != FK_LAYOUT_SLICED)
+        return fail(FK_E_ARG, "unknown layout %d", layout);
+    if (A->solvers > 0)
+        return fail(FK_E_STATE, "%d solver(s) use this matrix; destroy them first", A->solvers);
+    if (layout == FK_LAYOUT_ROW_BLOCKS) {
+        A->layout = FK_LAYOUT_ROW_BLOCKS;
+        return FK_OK;
+    }
+    if (A->nslices == 0 || layout == FK_LAYOUT_AUTO) {
+        hipStream_t s = reinterpret_cast<hipStream_t>(hip_stream);
+        std::vector<int32_t> rp, ci;
+        std::vector<int64_t> off;
+        int64_t max_len = 0;
+        try {
+            rp.resize((size_t)A->n + 1);
+            ci.resize((size_t)std::max<int64_t>(A->nnz, 1));
+        } catch (const std::bad_alloc &) {
+            return fail(FK_E_OOM, "host allocation failed");
+        }
+        hipError_t e = hipMemcpyAsync(rp.data(), A->row_ptr, rp.size() * 4, hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess && A->nnz > 0)
+            e = hipMemcpyAsync(ci.data(), A->col_idx, (size_t)A->nnz * 4, hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess)
+            e = hipStreamSynchronize(s);
+        if (e != hipSuccess)
+            return fail(FK_E_HIP, "reading the CSR arrays back: %s", hipGetErrorString(e));
+        try {
+            off = plan_slices(rp.data(), A->n, &max_len);
+        } catch (const std::bad_alloc &) {
+            return fail(FK_E_OOM, "host allocation failed");
+        }
+        if (layout == FK_LAYOUT_AUTO && !sliced_pays(off, A->nnz, max_len)) {
+            A->layout = FK_LAYOUT_ROW_BLOCKS;
+            return FK_OK;
+        }
+        if (A->nslices == 0) {
+            fk_status st = build_slices(A, rp.data(), ci.data(), off, s);
+            if (st != FK_OK)
+                return st;
+        }
+    }
+    A->layout = FK_LAYOUT_SLICED;
     return FK_OK;
 }
 
@@ -382,6 +569,15 @@ struct fk_solver_s {
         return RedArgs{st, partials, mixed ? nullptr : hist, mixed ? nullptr : scal, fin, mask};
     }
     RedArgs red_outer() const { return RedArgs{st_outer, partials, hist, nullptr, FIN_MIX_OUTER, RUN_ACTIVE}; }
+    // A reduction point that also folds in the `kpub` dots published by the
+    // `npub` workgroups of an earlier FIN_PUBLISH launch.
+    RedArgs red_fold(int fin, uint32_t mask, int npub, int kpub) const
+    {
+        RedArgs a = red(fin, mask);
+        a.npub = npub;
+        a.kpub = kpub;
+        return a;
+    }
 };
 
 static void solver_release(fk_solver S)
@@ -539,7 +735,7 @@ extern "C" fk_status fk_solver_create(fk_csr A, const fk_opts *o, void *hip_stre
         S_TRY(dev_alloc(&S->p32, n, "p32"));
         S_TRY(dev_alloc(&S->ap32, n, "Ap32"));
         S_TRY(dev_alloc(&S->d32, n, "d32"));
-        S_TRY(dev_alloc(&S->vals32, (size_t)A->nnz, "FP32 values"));
+        S_TRY(dev_alloc(&S->vals32, (size_t)A->stored_entries(), "FP32 values"));
         S_TRY(dev_alloc(&S->st_outer, 1, "refinement state"));
     } else {
         S_TRY(dev_alloc(&S->r, n, "r"));
@@ -573,8 +769,11 @@ extern "C" fk_status fk_solver_create(fk_csr A, const fk_opts *o, void *hip_stre
     }
     if (S->mixed) {
         S_HIP(hipMemsetAsync(S->st_outer, 0, sizeof(DevState), S->stream));
-        if (A->nnz > 0)
-            S_HIP(launch_to_f32(A->nnz, S->vals32, A->vals, vec_grid(A->nnz), S->stream));
+        if (A->nnz > 0) {
+            const bool sliced = A->layout == FK_LAYOUT_SLICED;
+            const int64_t m = A->stored_entries();
+            S_HIP(launch_to_f32(m, S->vals32, sliced ? A->sell_vals : A->vals, vec_grid(m), S->stream));
+        }
     }
     S->small = small_path_ok(A, S->o);
     S->small_stage = S->small &&
@@ -679,11 +878,13 @@ hipError_t enqueue_iteration(fk_solver S, Enq &q, double *x, bool last)
     DevState *ds = S->st;
     switch (S->o.method) {
     case FK_CG_PIPELINED:
-        // Fused x, r, p update + <r_i, r_i>; then Ap_i + <p_i,Ap_i>, <Ap_i,Ap_i>.
-        ENQ(FK_KERNEL_UPDATE_DOT, launch_cg_update(n, x, S->r, S->p, S->ap, S->red(FIN_CG_RR, RUN_ACTIVE), gv, st));
-        if (!last)
-            ENQ(FK_KERNEL_SPMV_DOT, launch_spmv_dots(A, S->p, S->ap, nullptr, D_YV | D_YY,
-                                                     S->red(FIN_CG_ALPHA, RUN_ACTIVE), gs, st));
+        // Fused x, r, p update + first stage of <r_i, r_i> (published); then
+        // Ap_i + <p_i,Ap_i>, <Ap_i,Ap_i>, whose second stage also completes
+        // <r_i, r_i>: one reduction round trip per iteration.  The product
+        // runs in the last iteration too: it carries the convergence test.
+        ENQ(FK_KERNEL_UPDATE_DOT, launch_cg_update(n, x, S->r, S->p, S->ap, S->red(FIN_PUBLISH, RUN_ACTIVE), gv, st));
+        ENQ(FK_KERNEL_SPMV_DOT, launch_spmv_dots(A, S->p, S->ap, nullptr, D_YV | D_YY,
+                                                 S->red_fold(FIN_CG_RR_ALPHA, RUN_ACTIVE, gv, 1), gs, st));
         break;
     case FK_CG_CLASSICAL:
         ENQ(FK_KERNEL_SPMV, launch_spmv_dots(A, S->p, S->ap, nullptr, 0, S->red(FIN_NONE, RUN_ACTIVE), gs, st));
@@ -722,10 +923,9 @@ hipError_t enqueue_iteration(fk_solver S, Enq &q, double *x, bool last)
     case FK_CG_MIXED:
         // Algorithm 2 in FP32 on the correction d (x is not touched).
         ENQ(FK_KERNEL_UPDATE_DOT, launch_cg_update32(n, S->d32, S->r32, S->p32, S->ap32,
-                                                     S->red(FIN_CG_RR, RUN_ACTIVE), gv, st));
-        if (!last)
-            ENQ(FK_KERNEL_SPMV_DOT, launch_spmv32(A, S->vals32, S->p32, S->ap32,
-                                                  S->red(FIN_CG_ALPHA, RUN_ACTIVE), gs, st));
+                                                     S->red(FIN_PUBLISH, RUN_ACTIVE), gv, st));
+        ENQ(FK_KERNEL_SPMV_DOT, launch_spmv32(A, S->vals32, S->p32, S->ap32,
+                                              S->red_fold(FIN_CG_RR_ALPHA, RUN_ACTIVE, gv, 1), gs, st));
         break;
     default:
         return hipErrorInvalidValue;

@@ -25,13 +25,16 @@ constexpr int GMAX = 4096;
 constexpr int RGROUP = 32;
 constexpr int RNGROUPS_MAX = GMAX / RGROUP;
 constexpr int CNT_STRIDE = 32;  // uint32 per arrival counter (one 128-byte line each)
+// Published first-stage partials (FIN_PUBLISH) of at most this many dots.
+constexpr int KPUB = 2;
 // Layout of the reduction scratch (doubles): level-1 partials [KMAX][GMAX]
-// double-double, level-2 partials [KMAX][RNGROUPS_MAX] double-double, then
-// RNGROUPS_MAX + 1 arrival counters.
+// double-double, level-2 partials [KMAX][RNGROUPS_MAX] double-double,
+// RNGROUPS_MAX + 1 arrival counters, then published partials [KPUB][GMAX]
+// double-double.
 constexpr size_t RED_L2_OFFSET = (size_t)2 * KMAX * GMAX;
 constexpr size_t RED_CNT_OFFSET = RED_L2_OFFSET + (size_t)2 * KMAX * RNGROUPS_MAX;
-constexpr size_t RED_SCRATCH_DOUBLES =
-    RED_CNT_OFFSET + ((size_t)(RNGROUPS_MAX + 1) * CNT_STRIDE * 4 + 7) / 8;
+constexpr size_t RED_PUB_OFFSET = RED_CNT_OFFSET + ((size_t)(RNGROUPS_MAX + 1) * CNT_STRIDE * 4 + 7) / 8;
+constexpr size_t RED_SCRATCH_DOUBLES = RED_PUB_OFFSET + (size_t)2 * KPUB * GMAX;
 
 // Solver state kept on the device; only the last workgroup of a reduction
 // writes it, every kernel reads `status` first and returns unless it is one
@@ -93,6 +96,10 @@ enum Fin : int32_t {
     FIN_GM_R1,          // GMRES: d = {<v_{i-1}, w>} -> R[i-1][i]
     FIN_GM_NORM,        // GMRES: d = {<w,w>} -> R[i][i]
     FIN_GM_XI,          // GMRES: d = {<r, v_i>} -> xi_i, norm estimate, step done
+    FIN_PUBLISH,        // first stage only: store the workgroup partials for the
+                        // next reduction point to fold in (no second stage here)
+    FIN_CG_RR_ALPHA,    // d = {<p_i,Ap_i>, <Ap_i,Ap_i>, <r_i,r_i>} (the last one
+                        // published by the update): FIN_CG_RR, then FIN_CG_ALPHA
 };
 
 // Everything a reduction point needs.
@@ -103,9 +110,25 @@ struct RedArgs {
     double *scal;      // 4 scalars per iteration or nullptr
     int32_t fin;
     uint32_t run_mask;
+    // Published partials folded into this reduction point: `npub` workgroup
+    // partials of `kpub` dots (0: none), appended after the kernel's own dots.
+    int32_t npub = 0;
+    int32_t kpub = 0;
 };
 
-// CSR matrix on the device plus its row-block plan.
+// Rows per slice of the sliced layout: one wave64, one row per lane.
+constexpr int SLICE = 64;
+
+// CSR matrix on the device plus the layout its products read.
+//  - Row blocks (nslices == 0): the CSR arrays themselves, cut into blocks
+//    of consecutive rows whose products are staged in LDS.
+//  - Sliced (nslices > 0): the same nonzeros regrouped once, when the
+//    matrix is created, into slices of SLICE consecutive rows.  Slice s
+//    holds width_s = (sell_ptr[s+1] - sell_ptr[s]) / SLICE entries per row,
+//    stored entry-major: the k-th nonzero of row s*SLICE + l is at
+//    sell_ptr[s] + k*SLICE + l, in the row's CSR order; rows shorter than
+//    width_s are padded with column -1 and value 0.  One lane sums one row
+//    left to right, so every row sum is rounded exactly as in CSR order.
 struct DevCsr {
     int32_t n;
     int32_t nnz;
@@ -115,6 +138,10 @@ struct DevCsr {
     const double *vals;
     const int32_t *blocks;    // row index where block b starts; blocks[nblocks] = n
     const int32_t *block_j0;  // row_ptr[blocks[b]] (first nonzero of block b)
+    int32_t nslices;          // 0: row blocks; > 0: sliced layout, ceil(n / SLICE) slices
+    const int32_t *sell_ptr;  // nslices + 1 entry offsets
+    const int32_t *sell_col;  // column of each entry, -1 for padding
+    const double *sell_vals;  // value of each entry, 0 for padding
 };
 
 // Dot selection bits for the fused product kernel y = A v.
@@ -165,8 +192,14 @@ hipError_t launch_axpby(int64_t n, double alpha, const double *x, double beta, c
 hipError_t launch_residual32(const DevCsr &A, const double *b, const double *x, float *r32,
                              const RedArgs &red, int grid, hipStream_t s);
 // y = A32 v with FP32 <y,v>, <y,y> (FIN_CG_ALPHA on the inner state).
+// vals32 holds the FP32 values in the layout A's products read: CSR order
+// (nnz entries) for row blocks, slice order (sell_ptr[nslices] entries)
+// for the sliced layout.
 hipError_t launch_spmv32(const DevCsr &A, const float *vals32, const float *v, float *y,
                          const RedArgs &red, int grid, hipStream_t s);
+// out[e] = map[e] >= 0 ? vals[map[e]] : 0 (the values of the sliced layout).
+hipError_t launch_gather_vals(int64_t n, double *out, const double *vals, const int32_t *map,
+                              int grid, hipStream_t s);
 hipError_t launch_cg_update32(int64_t n, float *d, float *r, float *p, const float *ap,
                               const RedArgs &red, int grid, hipStream_t s);
 // p = r, d = 0, FP32 <r,r> twice (FIN_SETUP on the inner state).

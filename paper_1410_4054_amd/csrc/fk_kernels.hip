@@ -48,6 +48,10 @@
 #ifndef FK_VEC_UNROLL
 #define FK_VEC_UNROLL 1
 #endif
+// Entries of a row requested together by the sliced-layout products.
+#ifndef FK_SELL_UNROLL
+#define FK_SELL_UNROLL 4
+#endif
 
 namespace fk {
 namespace {
@@ -153,6 +157,41 @@ __device__ __forceinline__ void put_scal(const DevState *st, double *scal, int i
 
 // Scalar work of a reduction point (one thread).  The expressions and their
 // order follow Algorithms 1-4 exactly; see the comments per case.
+// Algorithm 2, alpha_i = <r_i,r_i> / <p_i,Ap_i> and beta_i by Eq. (3).
+__device__ void cg_alpha(DevState *st, double pap, double apap, double *scal)
+{
+    if (!(pap > 0.0) || !isfinite(pap) || !isfinite(apap)) {
+        st->status = ST_BREAKDOWN;
+        return;
+    }
+    const double alpha = st->rr / pap;
+    const double beta = alpha * alpha * apap / st->rr - 1.0;  // Eq. (3)
+    st->alpha = alpha;
+    st->beta = beta;
+    put_scal(st, scal, st->it, 0, alpha);
+    put_scal(st, scal, st->it, 1, beta);
+    if (st->it >= st->max_iter)
+        st->status = ST_NOT_CONVERGED;
+}
+
+// Algorithm 2, <r_i, r_i>: iteration i done, residual history, convergence.
+__device__ void cg_rr(DevState *st, double rr, double *hist, double *scal)
+{
+    const int it = st->it + 1;
+    st->it = it;
+    st->rr = rr;
+    const double rel = sqrt(rr) / st->bnorm;
+    st->last_rel = rel;
+    put_hist(st, hist, it, rel);
+    put_scal(st, scal, it - 1, 3, rr);
+    if (!isfinite(rr))
+        st->status = ST_BREAKDOWN;
+    else if (sqrt(rr) <= st->tol)
+        st->status = ST_CONVERGED;
+    else if (it >= st->max_iter)
+        st->status = ST_NOT_CONVERGED;
+}
+
 __device__ void finalize(DevState *st, int fin, const double *d, int K, double *hist, double *scal)
 {
     for (int k = 0; k < K; ++k)
@@ -185,39 +224,19 @@ __device__ void finalize(DevState *st, int fin, const double *d, int K, double *
             st->status = ST_CONVERGED;
         break;
     }
-    case FIN_CG_ALPHA: {  // Algorithm 2: d = {<p_i,Ap_i>, <Ap_i,Ap_i>}
-        const double pap = d[0], apap = d[1];
-        if (!(pap > 0.0) || !isfinite(pap) || !isfinite(apap)) {
-            st->status = ST_BREAKDOWN;
-            break;
-        }
-        const double alpha = st->rr / pap;
-        const double beta = alpha * alpha * apap / st->rr - 1.0;  // Eq. (3)
-        st->alpha = alpha;
-        st->beta = beta;
-        put_scal(st, scal, st->it, 0, alpha);
-        put_scal(st, scal, st->it, 1, beta);
-        if (st->it >= st->max_iter)
-            st->status = ST_NOT_CONVERGED;
+    case FIN_CG_ALPHA:  // Algorithm 2: d = {<p_i,Ap_i>, <Ap_i,Ap_i>}
+        cg_alpha(st, d[0], d[1], scal);
         break;
-    }
-    case FIN_CG_RR: {  // Algorithm 2: d = {<r_i,r_i>}
-        const double rr = d[0];
-        const int it = st->it + 1;
-        st->it = it;
-        st->rr = rr;
-        const double rel = sqrt(rr) / st->bnorm;
-        st->last_rel = rel;
-        put_hist(st, hist, it, rel);
-        put_scal(st, scal, it - 1, 3, rr);
-        if (!isfinite(rr))
-            st->status = ST_BREAKDOWN;
-        else if (sqrt(rr) <= st->tol)
-            st->status = ST_CONVERGED;
-        else if (it >= st->max_iter)
-            st->status = ST_NOT_CONVERGED;
+    case FIN_CG_RR:  // Algorithm 2: d = {<r_i,r_i>}
+        cg_rr(st, d[0], hist, scal);
         break;
-    }
+    case FIN_CG_RR_ALPHA:  // d = {<p_i,Ap_i>, <Ap_i,Ap_i>, <r_i,r_i>}
+        // The convergence test on r_i comes first, as when <r_i,r_i> is
+        // reduced on its own; alpha_i, beta_i only while still running.
+        cg_rr(st, d[2], hist, scal);
+        if (st->status == ST_RUNNING)
+            cg_alpha(st, d[0], d[1], scal);
+        break;
     case FIN_B_ALPHA: {  // Algorithms 3/4: d = {<Ap_i, r0*>}
         const double apr = d[0], rho = st->rho;
         if (apr == 0.0 || !isfinite(apr) || rho == 0.0 || !isfinite(rho)) {
@@ -458,6 +477,15 @@ __device__ void finalize(DevState *st, int fin, const double *d, int K, double *
 // The order of every sum depends only on the grid size, never on timing.
 // Counters are reset by the workgroup that saw the last arrival, so the
 // scratch is ready for the next launch.
+//
+// Published partials.  With fin == FIN_PUBLISH a kernel only stores its
+// workgroup partials (first stage) and ends: no counter, no finalize.  A
+// reduction point in a later kernel with kpub > 0 folds them in: the last
+// arrival of group j also sums the j-th of ngroups equal slices of the npub
+// published partials, so they ride the same two levels as the kernel's own
+// dots and cost no extra round trip.  Algorithm 2 needs <r_i, r_i> only with
+// the product's two dots (alpha_i and beta_i need all three), which is what
+// lets the update kernel publish it instead of reducing it.
 template <int K>
 __device__ __forceinline__ void reduce_point(dd (&v)[K], const RedArgs &red, int g, int G)
 {
@@ -465,6 +493,7 @@ __device__ __forceinline__ void reduce_point(dd (&v)[K], const RedArgs &red, int
     __shared__ int s_flag;
     double *const part1 = red.partials;
     double *const part2 = red.partials + RED_L2_OFFSET;
+    double *const pub = red.partials + RED_PUB_OFFSET;
     uint32_t *const cnt = reinterpret_cast<uint32_t *>(red.partials + RED_CNT_OFFSET);
     const int ngroups = (G + RGROUP - 1) / RGROUP;
     const int grp = g / RGROUP;
@@ -472,6 +501,19 @@ __device__ __forceinline__ void reduce_point(dd (&v)[K], const RedArgs &red, int
     const int gsize = min(RGROUP, G - gbase);
 
     block_reduce<K>(v, lds);
+    if (red.fin == FIN_PUBLISH) {
+        // First stage only; a later reduction point of the same solver, in
+        // a later kernel, folds these partials into its own second stage.
+        if (threadIdx.x == 0) {
+#pragma unroll
+            for (int k = 0; k < K; ++k) {
+                double *slot = pub + 2 * ((size_t)k * GMAX + g);
+                store_coherent(slot, v[k].hi);
+                store_coherent(slot + 1, v[k].lo);
+            }
+        }
+        return;
+    }
     if (threadIdx.x == 0) {
 #pragma unroll
         for (int k = 0; k < K; ++k) {
@@ -490,23 +532,45 @@ __device__ __forceinline__ void reduce_point(dd (&v)[K], const RedArgs &red, int
     if (!s_flag)
         return;
 
-    // Last arrival of the group: sum the group's partials.
-    dd acc[K];
+    // Last arrival of the group: sum the group's partials, and this group's
+    // share of the published partials (dots K .. K + kpub - 1).
+    constexpr int KP = (K + KPUB <= KMAX) ? KPUB : 0;
+    constexpr int KT = K + KP;
+    const int kpub = KP > 0 ? red.kpub : 0;
+    const int kt = K + kpub;
+    dd acc[KT];
+#pragma unroll
+    for (int k = 0; k < KT; ++k)
+        acc[k] = dd{0.0, 0.0};
 #pragma unroll
     for (int k = 0; k < K; ++k) {
-        acc[k] = dd{0.0, 0.0};
         if ((int)threadIdx.x < gsize) {
             const double *slot = part1 + 2 * ((size_t)k * GMAX + gbase + threadIdx.x);
             acc[k] = dd{load_coherent(slot), load_coherent(slot + 1)};
         }
     }
-    block_reduce<K>(acc, lds);
+    if (kpub > 0) {
+        const int p0 = (int)(((int64_t)red.npub * grp) / ngroups);
+        const int p1 = (int)(((int64_t)red.npub * (grp + 1)) / ngroups);
+        for (int j = p0 + (int)threadIdx.x; j < p1; j += WG) {
+#pragma unroll
+            for (int k = 0; k < KP; ++k) {
+                if (k < kpub) {
+                    const double *slot = pub + 2 * ((size_t)k * GMAX + j);
+                    acc[K + k] = dd_add(acc[K + k], dd{load_coherent(slot), load_coherent(slot + 1)});
+                }
+            }
+        }
+    }
+    block_reduce<KT>(acc, lds);
     if (threadIdx.x == 0) {
 #pragma unroll
-        for (int k = 0; k < K; ++k) {
-            double *slot = part2 + 2 * ((size_t)k * RNGROUPS_MAX + grp);
-            store_coherent(slot, acc[k].hi);
-            store_coherent(slot + 1, acc[k].lo);
+        for (int k = 0; k < KT; ++k) {
+            if (k < kt) {
+                double *slot = part2 + 2 * ((size_t)k * RNGROUPS_MAX + grp);
+                store_coherent(slot, acc[k].hi);
+                store_coherent(slot + 1, acc[k].lo);
+            }
         }
         __hip_atomic_store(cnt + (size_t)grp * CNT_STRIDE, 0u, __ATOMIC_RELAXED,
                            __HIP_MEMORY_SCOPE_AGENT);
@@ -521,24 +585,26 @@ __device__ __forceinline__ void reduce_point(dd (&v)[K], const RedArgs &red, int
 
     // Last group: sum the group sums and finalize.
 #pragma unroll
-    for (int k = 0; k < K; ++k)
+    for (int k = 0; k < KT; ++k)
         acc[k] = dd{0.0, 0.0};
     for (int j = threadIdx.x; j < ngroups; j += WG) {
 #pragma unroll
-        for (int k = 0; k < K; ++k) {
-            const double *slot = part2 + 2 * ((size_t)k * RNGROUPS_MAX + j);
-            acc[k] = dd_add(acc[k], dd{load_coherent(slot), load_coherent(slot + 1)});
+        for (int k = 0; k < KT; ++k) {
+            if (k < kt) {
+                const double *slot = part2 + 2 * ((size_t)k * RNGROUPS_MAX + j);
+                acc[k] = dd_add(acc[k], dd{load_coherent(slot), load_coherent(slot + 1)});
+            }
         }
     }
-    block_reduce<K>(acc, lds);
+    block_reduce<KT>(acc, lds);
     if (threadIdx.x == 0) {
-        double d[K > 0 ? K : 1];
+        double d[KT > 0 ? KT : 1];
 #pragma unroll
-        for (int k = 0; k < K; ++k)
+        for (int k = 0; k < KT; ++k)
             d[k] = acc[k].hi + acc[k].lo;
         __hip_atomic_store(cnt + (size_t)RNGROUPS_MAX * CNT_STRIDE, 0u, __ATOMIC_RELAXED,
                            __HIP_MEMORY_SCOPE_AGENT);
-        finalize(red.st, red.fin, d, K, red.hist, red.scal);
+        finalize(red.st, red.fin, d, kt, red.hist, red.scal);
     }
 }
 
@@ -689,6 +755,103 @@ __global__ __launch_bounds__(WG, FK_SPMV_MIN_WAVES) void k_csr_rows(DevCsr A, Ro
     }
     if constexpr (K > 0)
         reduce_point<KA>(acc, red, g, G);
+}
+
+// ------------------------------------------------ sliced-layout products
+
+// One row of a slice summed left to right (the row's CSR order): the lane's
+// entries k = 0 .. width-1 sit SLICE apart; FK_SELL_UNROLL of them, with
+// their gathers, are requested before the first is added.  Padding (column
+// -1) only follows a row's last nonzero and is skipped.
+template <typename T>
+__device__ __forceinline__ T slice_row_sum(const int32_t *__restrict__ col, const T *__restrict__ vals,
+                                           const T *__restrict__ v, int width)
+{
+    constexpr int U = FK_SELL_UNROLL;
+    T q = T(0);
+    for (int k = 0; k < width; k += U) {
+        int c[U];
+        T a[U], x[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            c[u] = -1;
+            a[u] = T(0);
+            if (k + u < width) {
+                c[u] = load_stream(col + (size_t)(k + u) * SLICE);
+                a[u] = load_stream(vals + (size_t)(k + u) * SLICE);
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            x[u] = c[u] >= 0 ? v[c[u]] : T(0);
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            if (c[u] >= 0)
+                q = q + a[u] * x[u];
+    }
+    return q;
+}
+
+// The products of k_csr_rows on the sliced layout: one wave per slice, one
+// lane per row, no LDS staging and no barrier before the reduction point.
+// Workgroup g takes a contiguous range of slices, its waves take them in
+// turn.  Row sums, epilogues and the reduction are those of k_csr_rows, so
+// results are bitwise identical to it.
+template <int MODE, int DOTS>
+__global__ __launch_bounds__(WG, FK_SPMV_MIN_WAVES) void k_sell_rows(DevCsr A, RowIo io, RedArgs red)
+{
+    if (!runs(red))
+        return;
+    constexpr int K = (MODE != ROW_SPMV) ? 2 : popc3(DOTS);
+    constexpr int KA = K > 0 ? K : 1;
+    constexpr bool NEED_V = MODE == ROW_SPMV && (DOTS & D_YV) != 0;
+    constexpr bool NEED_W = MODE != ROW_SPMV || (DOTS & D_YW) != 0;
+    const int G = gridDim.x;
+    const int g = logical_wg();
+    const int s_begin = (int)(((int64_t)A.nslices * g) / G);
+    const int s_end = (int)(((int64_t)A.nslices * (g + 1)) / G);
+    const int lane = threadIdx.x & (SLICE - 1);
+
+    dd acc[KA];
+#pragma unroll
+    for (int k = 0; k < KA; ++k)
+        acc[k] = dd{0.0, 0.0};
+
+    for (int sl = s_begin + (int)(threadIdx.x / SLICE); sl < s_end; sl += WG / SLICE) {
+        const int e0 = A.sell_ptr[sl];
+        const int width = (A.sell_ptr[sl + 1] - e0) / SLICE;
+        const int row = sl * SLICE + lane;
+        const bool live = row < A.n;
+        double vrow = 0.0, wrow = 0.0;
+        if (live) {
+            if constexpr (NEED_V)
+                vrow = io.v[row];
+            if constexpr (NEED_W)
+                wrow = io.w[row];
+        }
+        const double q = slice_row_sum<double>(A.sell_col + e0 + lane, A.sell_vals + e0 + lane, io.v, width);
+        if (live) {
+            if constexpr (K > 0)
+                row_epilogue<MODE, DOTS, KA>(io, row, q, vrow, wrow, acc);
+            else
+                io.y[row] = q;
+        }
+    }
+    if constexpr (K > 0)
+        reduce_point<KA>(acc, red, g, G);
+}
+
+// out[e] = vals[map[e]], or 0 where map[e] < 0: the values of the sliced
+// layout gathered once from the CSR values.
+__global__ __launch_bounds__(WG) void k_gather_vals(int64_t n, double *__restrict__ out,
+                                                     const double *__restrict__ vals,
+                                                     const int32_t *__restrict__ map)
+{
+    const int64_t stride = (int64_t)gridDim.x * WG;
+    for (int64_t i = (int64_t)blockIdx.x * WG + threadIdx.x; i < n; i += stride) {
+        const int32_t j = map[i];
+        out[i] = j >= 0 ? vals[j] : 0.0;
+    }
 }
 
 // --------------------------------------------------- fused vector updates
@@ -949,6 +1112,35 @@ __global__ __launch_bounds__(WG, FK_SPMV_MIN_WAVES) void k_csr_rows32(DevCsr A, 
                 dd_fma(acc[0], (double)q, (double)v[r0]);
                 dd_fma(acc[1], (double)q, (double)q);
             }
+        }
+    }
+    reduce_point<2>(acc, red, g, G);
+}
+
+// k_csr_rows32 on the sliced layout (vals32 in slice order).
+__global__ __launch_bounds__(WG, FK_SPMV_MIN_WAVES) void k_sell_rows32(DevCsr A, const float *vals32,
+                                                                        const float *v, float *y,
+                                                                        RedArgs red)
+{
+    if (!runs(red))
+        return;
+    const int G = gridDim.x;
+    const int g = logical_wg();
+    const int s_begin = (int)(((int64_t)A.nslices * g) / G);
+    const int s_end = (int)(((int64_t)A.nslices * (g + 1)) / G);
+    const int lane = threadIdx.x & (SLICE - 1);
+    dd acc[2] = {dd{0.0, 0.0}, dd{0.0, 0.0}};
+    for (int sl = s_begin + (int)(threadIdx.x / SLICE); sl < s_end; sl += WG / SLICE) {
+        const int e0 = A.sell_ptr[sl];
+        const int width = (A.sell_ptr[sl + 1] - e0) / SLICE;
+        const int row = sl * SLICE + lane;
+        const bool live = row < A.n;
+        const float vrow = live ? v[row] : 0.f;
+        const float q = slice_row_sum<float>(A.sell_col + e0 + lane, vals32 + e0 + lane, v, width);
+        if (live) {
+            y[row] = q;
+            dd_fma(acc[0], (double)q, (double)vrow);
+            dd_fma(acc[1], (double)q, (double)q);
         }
     }
     reduce_point<2>(acc, red, g, G);
@@ -1613,16 +1805,26 @@ void set_launch_timing(hipEvent_t start, hipEvent_t stop)
     t_stop = stop;
 }
 
+// The product kernel of A's layout.
+template <int MODE, int DOTS>
+static hipError_t launch_rows(const DevCsr &A, const RowIo &io, const RedArgs &red, int grid,
+                              hipStream_t s)
+{
+    if (A.nslices > 0)
+        return launch(k_sell_rows<MODE, DOTS>, grid, WG, s, A, io, red);
+    return launch(k_csr_rows<MODE, DOTS>, grid, WG, s, A, io, red);
+}
+
 hipError_t launch_spmv_dots(const DevCsr &A, const double *v, double *y, const double *w,
                             int dots, const RedArgs &red, int grid, hipStream_t s)
 {
     RowIo io{v, y, w, nullptr, nullptr, nullptr};
     switch (dots) {
-    case 0: return launch(k_csr_rows<ROW_SPMV, 0>, grid, WG, s, A, io, red);
-    case D_YV: return launch(k_csr_rows<ROW_SPMV, D_YV>, grid, WG, s, A, io, red);
-    case D_YV | D_YY: return launch(k_csr_rows<ROW_SPMV, D_YV | D_YY>, grid, WG, s, A, io, red);
-    case D_YW: return launch(k_csr_rows<ROW_SPMV, D_YW>, grid, WG, s, A, io, red);
-    case D_YV | D_YY | D_YW: return launch(k_csr_rows<ROW_SPMV, D_YV | D_YY | D_YW>, grid, WG, s, A, io, red);
+    case 0: return launch_rows<ROW_SPMV, 0>(A, io, red, grid, s);
+    case D_YV: return launch_rows<ROW_SPMV, D_YV>(A, io, red, grid, s);
+    case D_YV | D_YY: return launch_rows<ROW_SPMV, D_YV | D_YY>(A, io, red, grid, s);
+    case D_YW: return launch_rows<ROW_SPMV, D_YW>(A, io, red, grid, s);
+    case D_YV | D_YY | D_YW: return launch_rows<ROW_SPMV, D_YV | D_YY | D_YW>(A, io, red, grid, s);
     default: return hipErrorInvalidValue;
     }
 }
@@ -1631,7 +1833,13 @@ hipError_t launch_residual0(const DevCsr &A, const double *b, const double *x, d
                             double *p, double *rs, const RedArgs &red, int grid, hipStream_t s)
 {
     RowIo io{x, r, b, p, rs, nullptr};
-    return launch(k_csr_rows<ROW_RESID, 0>, grid, WG, s, A, io, red);
+    return launch_rows<ROW_RESID, 0>(A, io, red, grid, s);
+}
+
+hipError_t launch_gather_vals(int64_t n, double *out, const double *vals, const int32_t *map,
+                              int grid, hipStream_t s)
+{
+    return launch(k_gather_vals, grid, WG, s, n, out, vals, map);
 }
 
 hipError_t launch_gm_scale(int64_t n, double *out, const double *in, DevState *st, uint32_t run_mask, int grid,
@@ -1674,12 +1882,14 @@ hipError_t launch_residual32(const DevCsr &A, const double *b, const double *x, 
                              const RedArgs &red, int grid, hipStream_t s)
 {
     RowIo io{x, nullptr, b, nullptr, nullptr, r32};
-    return launch(k_csr_rows<ROW_RESID32, 0>, grid, WG, s, A, io, red);
+    return launch_rows<ROW_RESID32, 0>(A, io, red, grid, s);
 }
 
 hipError_t launch_spmv32(const DevCsr &A, const float *vals32, const float *v, float *y,
                          const RedArgs &red, int grid, hipStream_t s)
 {
+    if (A.nslices > 0)
+        return launch(k_sell_rows32, grid, WG, s, A, vals32, v, y, red);
     return launch(k_csr_rows32, grid, WG, s, A, vals32, v, y, red);
 }
 

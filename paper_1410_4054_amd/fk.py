@@ -93,6 +93,8 @@ def lib():
             "fk_csr_destroy": [vp],
             "fk_csr_shape": [vp, P(i64), P(i64)],
             "fk_csr_blocks": [vp, P(i32), P(i32)],
+            "fk_csr_layout": [vp, P(i32), P(i64)],
+            "fk_csr_set_layout": [vp, i32, vp],
             "fk_solver_create": [vp, P(_Opts), vp, P(vp)],
             "fk_solve": [vp, vp, vp],
             "fk_get_iterations": [vp, P(i32)],
@@ -138,7 +140,8 @@ def lib():
 def exported_symbols() -> list[str]:
     """Names every caller may rely on (the declarations of include/fk.h)."""
     return [
-        "fk_csr_create", "fk_csr_destroy", "fk_csr_shape", "fk_csr_blocks",
+        "fk_csr_create", "fk_csr_destroy", "fk_csr_shape", "fk_csr_blocks", "fk_csr_layout",
+        "fk_csr_set_layout",
         "fk_solver_create", "fk_solve", "fk_get_iterations", "fk_get_residual",
         "fk_get_residual_history", "fk_get_scalars", "fk_get_kernel_times",
         "fk_solver_destroy", "fk_solver_uses_small", "fk_get_refinements", "fk_spmv", "fk_dot", "fk_copy",
@@ -185,11 +188,15 @@ def status_str(status: int) -> str:
 
 # ------------------------------------------------------------------ matrix
 
+LAYOUTS = {"auto": 0, "row_blocks": 1, "sliced": 2}
+
+
 class Matrix:
     """A device-resident CSR matrix (fk_csr handle)."""
 
-    def __init__(self, csr, stream=None):
-        """`csr`: object with n, row_ptr, col_idx, vals (numpy host arrays)."""
+    def __init__(self, csr, stream=None, layout: str | None = None):
+        """`csr`: object with n, row_ptr, col_idx, vals (numpy host arrays).
+        `layout`: None keeps the library's choice; else one of LAYOUTS."""
         L = lib()
         rp = np.ascontiguousarray(csr.row_ptr, dtype=np.int32)
         ci = np.ascontiguousarray(csr.col_idx, dtype=np.int32)
@@ -202,6 +209,8 @@ class Matrix:
         self._h = h
         self.n = int(csr.n)
         self.nnz = int(ci.size)
+        if layout is not None:
+            self.set_layout(layout, stream)
 
     @property
     def handle(self):
@@ -211,6 +220,19 @@ class Matrix:
         nb, lr = ctypes.c_int32(), ctypes.c_int32()
         _check(lib().fk_csr_blocks(self._h, ctypes.byref(nb), ctypes.byref(lr)), "fk_csr_blocks")
         return nb.value, lr.value
+
+    def layout(self) -> tuple[str, int]:
+        """(layout the products read, entries they read per product)."""
+        lay, ent = ctypes.c_int32(), ctypes.c_int64()
+        _check(lib().fk_csr_layout(self._h, ctypes.byref(lay), ctypes.byref(ent)), "fk_csr_layout")
+        name = {v: k for k, v in LAYOUTS.items()}[lay.value]
+        return name, ent.value
+
+    def set_layout(self, layout: str, stream=None):
+        if layout not in LAYOUTS:
+            raise ValueError(f"layout must be one of {sorted(LAYOUTS)}")
+        st = lib().fk_csr_set_layout(self._h, LAYOUTS[layout], ctypes.c_void_p(_stream_ptr(stream)))
+        _check(st, "fk_csr_set_layout")
 
     def close(self):
         if self._h:

@@ -21,9 +21,11 @@ def rel(a, b) -> float:
     return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / (nb if nb > 0 else 1.0))
 
 
-def gpu_solve(A, b, x0=None, method="cg_pipelined", rtol=1e-8, max_iter=None, matrix=None, **kw):
-    """Solve on the device through the C ABI; returns (SolveResult, x as numpy)."""
-    M = matrix or fk.Matrix(A)
+def gpu_solve(A, b, x0=None, method="cg_pipelined", rtol=1e-8, max_iter=None, matrix=None, layout=None,
+              **kw):
+    """Solve on the device through the C ABI; returns (SolveResult, x as numpy).
+    `layout` forces the layout of the products (None: the library's choice)."""
+    M = matrix or fk.Matrix(A, layout=layout)
     bd = dev(b)
     xd = dev(np.zeros(A.n) if x0 is None else x0)
     res = fk.solve(M, bd, xd, method=method, rtol=rtol, max_iter=max_iter, **kw)

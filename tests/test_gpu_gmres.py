@@ -43,13 +43,14 @@ def assert_same(res, x, ref, label):
     assert np.array_equal(x, ref.x), (label, rel(x, ref.x))
 
 
+@pytest.mark.parametrize("layout", ["row_blocks", "sliced"])
 @pytest.mark.parametrize("m", [5, 30])
 @pytest.mark.parametrize("method", list(METHODS))
 @pytest.mark.parametrize("wl", list(WORKLOADS))
-def test_gmres_matches_oracle(wl, method, m, device):
+def test_gmres_matches_oracle(wl, method, m, layout, device):
     A, b, x0 = WORKLOADS[wl]()
-    print(f"\n[case] {wl} {method} m={m} n={A.n}", flush=True)
-    res, x, ref = run(A, b, x0, method, m)
+    print(f"\n[case] {wl} {method} m={m} n={A.n} layout={layout}", flush=True)
+    res, x, ref = run(A, b, x0, method, m, layout=layout)
     assert_same(res, x, ref, f"{wl}/{method}/{m}")
     assert ref.status == "converged"
     assert oracle.true_residual(A, b, x) <= 1e-8

@@ -13,15 +13,22 @@ from paper_1410_4054_amd import fk, problems as P
 pytestmark = pytest.mark.gpu
 
 
-def check_spmv(A, seed=0, device=None):
+LAYOUTS = ["row_blocks", "sliced"]
+
+
+def check_spmv(A, seed=0, layout=None):
     rng = np.random.default_rng(seed)
     p = rng.uniform(-1, 1, A.n)
-    M = fk.Matrix(A)
+    M = fk.Matrix(A, layout=layout)
+    if layout is not None:
+        assert M.layout()[0] == layout
     pd, qd = dev(p), dev(np.zeros(A.n))
     dots = fk.spmv(M, pd, qd, dots=True)
     q = host(qd)
     ref = oracle.spmv(A, p)
-    short = np.diff(A.row_ptr) <= fk.LONG_ROW
+    # The sliced layout sums every row left to right; row blocks use a
+    # fixed tree for rows longer than FK_LONG_ROW.
+    short = np.diff(A.row_ptr) <= (fk.LONG_ROW if M.layout()[0] == "row_blocks" else np.inf)
     assert np.array_equal(q[short], ref[short]), "row sums differ from CSR-order sums"
     if (~short).any():
         np.testing.assert_allclose(q[~short], ref[~short], rtol=1e-12, atol=1e-12)
@@ -35,26 +42,82 @@ def check_spmv(A, seed=0, device=None):
     return M
 
 
+@pytest.mark.parametrize("layout", LAYOUTS)
 @pytest.mark.parametrize("nnz_row", [4, 28])
-def test_spmv_random_columns(nnz_row, device):
+def test_spmv_random_columns(nnz_row, layout, device):
     """The fused SpMV+dot benchmark matrices: 4 and 28 uniformly random
     nonzeros per row, with empty rows and rows longer than FK_LONG_ROW."""
     A = P.random_csr(20000, nnz_row, seed=nnz_row, empty_rows=31,
                      long_rows={3: 3000, 9000: 20000, 19999: 2049})
-    check_spmv(A, seed=nnz_row)
+    check_spmv(A, seed=nnz_row, layout=layout)
 
 
+@pytest.mark.parametrize("layout", LAYOUTS)
 @pytest.mark.parametrize("name", ["poisson2d_33", "poisson3d_17", "convdiff2d_50", "heat2d_40",
                                   "poisson2d_32", "poisson3d_64"])
-def test_spmv_stencils(name, device):
+def test_spmv_stencils(name, layout, device):
     A, _, _ = P.workload(name)
-    check_spmv(A, seed=1)
+    check_spmv(A, seed=1, layout=layout)
 
 
-@pytest.mark.parametrize("n", [1, 2, 255, 256, 257, 511, 513, 4097])
-def test_spmv_ragged_sizes(n, device):
-    """Sizes around the 256-row block and the 8-workgroup XCD split."""
-    check_spmv(P.random_csr(n, 5, seed=n), seed=n)
+@pytest.mark.parametrize("layout", LAYOUTS)
+@pytest.mark.parametrize("n", [1, 2, 63, 64, 65, 255, 256, 257, 511, 513, 4097])
+def test_spmv_ragged_sizes(n, layout, device):
+    """Sizes around the 64-row slice, the 256-row block and the
+    8-workgroup XCD split."""
+    check_spmv(P.random_csr(n, 5, seed=n), seed=n, layout=layout)
+
+
+def _slice_entries(A):
+    """Entries of the sliced layout, padding included: 64 times the longest
+    row of each run of 64 rows."""
+    lens = np.diff(A.row_ptr)
+    pad = np.zeros(-(-A.n // 64) * 64, dtype=np.int64)
+    pad[:A.n] = lens
+    return int(pad.reshape(-1, 64).max(axis=1).sum() * 64), int(lens.max(initial=0))
+
+
+@pytest.mark.parametrize("case", ["poisson3d_17", "convdiff2d_50", "random5", "long_row", "padding",
+                                  "empty"])
+def test_layout_rule(case, device):
+    """fk_csr_create takes the sliced layout when no row exceeds 64
+    nonzeros and padding adds at most a quarter; the entries it reports
+    are counted here independently."""
+    if case in ("poisson3d_17", "convdiff2d_50"):
+        A = P.workload(case)[0]
+    elif case == "random5":
+        A = P.random_csr(1000, 5, seed=1)
+    elif case == "long_row":
+        A = P.random_csr(1000, 5, seed=1, long_rows={7: 65})
+    elif case == "padding":
+        A = P.random_csr(6400, 1, seed=2, long_rows={64 * k: 3 for k in range(100)})
+    else:
+        A = P.Csr(5, np.zeros(6, np.int32), np.zeros(0, np.int32), np.zeros(0))
+    entries, longest = _slice_entries(A)
+    sliced = A.nnz > 0 and longest <= 64 and 4 * entries <= 5 * A.nnz
+    assert sliced == (case in ("poisson3d_17", "convdiff2d_50", "random5"))
+    M = fk.Matrix(A)
+    assert M.layout() == (("sliced", entries) if sliced else ("row_blocks", A.nnz))
+    M.set_layout("sliced")
+    assert M.layout() == ("sliced", entries)
+    M.set_layout("row_blocks")
+    assert M.layout() == ("row_blocks", A.nnz)
+    M.set_layout("auto")
+    assert M.layout()[0] == ("sliced" if sliced else "row_blocks")
+
+
+def test_layout_errors(device):
+    A = P.workload("poisson2d_33")[0]
+    M = fk.Matrix(A)
+    assert fk.lib().fk_csr_set_layout(M.handle, 3, None) == fk.E_ARG
+    assert fk.lib().fk_csr_set_layout(None, 1, None) == fk.E_ARG
+    S = fk.Solver(M)
+    with pytest.raises(fk.FkError) as e:
+        M.set_layout("row_blocks")
+    assert e.value.status == fk.E_STATE
+    S.close()
+    M.set_layout("row_blocks")
+    assert M.layout()[0] == "row_blocks"
 
 
 def test_spmv_degenerate(device):
@@ -71,11 +134,13 @@ def test_spmv_degenerate(device):
     assert blocks[1] == 1
 
 
-def test_spmv_full_size_128(device):
+@pytest.mark.parametrize("layout", [None, "row_blocks"], ids=["auto", "row_blocks"])
+def test_spmv_full_size_128(layout, device):
     """The 128^3 workload at full size in the launch configuration the
-    benchmark uses: every row equal to the CSR-order sum."""
+    benchmark uses (the library's own layout choice, sliced), and in row
+    blocks: every row equal to the CSR-order sum."""
     A, _, _ = P.workload("poisson3d_128")
-    check_spmv(A, seed=5)
+    check_spmv(A, seed=5, layout=layout)
 
 
 @pytest.mark.parametrize("n", [1, 7, 255, 256, 257, 1000, 123457, 2097152])

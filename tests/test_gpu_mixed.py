@@ -53,8 +53,9 @@ def _random_spd_csr(n, seed):
     return A, P.rhs_uniform(n, seed), np.zeros(n)
 
 
-def mixed_solve(A, b, x0=None, rtol=1e-10, inner_rtol=1e-4, max_iter=None, max_outer=0, **kw):
-    M = fk.Matrix(A)
+def mixed_solve(A, b, x0=None, rtol=1e-10, inner_rtol=1e-4, max_iter=None, max_outer=0, layout=None,
+                **kw):
+    M = fk.Matrix(A, layout=layout)
     bd = dev(b)
     xd = dev(np.zeros(A.n) if x0 is None else x0)
     res = fk.solve(M, bd, xd, method="cg_mixed", rtol=rtol, max_iter=max_iter,
@@ -70,12 +71,13 @@ def assert_same(res, x, ref, label=""):
     assert np.array_equal(x, ref.x), (label, rel(x, ref.x))
 
 
+@pytest.mark.parametrize("layout", ["row_blocks", "sliced"])
 @pytest.mark.parametrize("wl", list(WORKLOADS))
-def test_mixed_matches_oracle(wl, device):
+def test_mixed_matches_oracle(wl, layout, device):
     A, b, x0 = WORKLOADS[wl]()
-    print(f"\n[case] mixed {wl} n={A.n} nnz={A.nnz}", flush=True)
+    print(f"\n[case] mixed {wl} n={A.n} nnz={A.nnz} layout={layout}", flush=True)
     ref = oracle.solve_mixed(A, b, x0=x0, rtol=1e-10, inner_rtol=1e-4)
-    res, x = mixed_solve(A, b, x0)
+    res, x = mixed_solve(A, b, x0, layout=layout)
     assert_same(res, x, ref, wl)
     assert ref.status == "converged"
     # Error against the FP64 solver's solution (pipelined CG to 1e-13).

@@ -45,15 +45,17 @@ def assert_same_run(res, x, ref, label=""):
     assert rel(x, ref.x) <= 1e-10, (label, rel(x, ref.x))
 
 
-@pytest.mark.parametrize("small", [True, False], ids=["auto", "grid"])
+@pytest.mark.parametrize("small,layout", [(True, None), (False, "row_blocks"), (False, "sliced")],
+                         ids=["auto", "grid-row_blocks", "grid-sliced"])
 @pytest.mark.parametrize("wl,method", CASES, ids=[f"{w}-{m}" for w, m in CASES])
-def test_matches_oracle(wl, method, small, device):
+def test_matches_oracle(wl, method, small, layout, device):
     """small=True lets the library take its single-workgroup solver where it
-    applies (the small pipelined cases); small=False forces the grid kernels."""
+    applies (the small pipelined cases); small=False forces the grid kernels,
+    on either layout of the products."""
     A, b, x0 = WORKLOADS[wl]()
-    print(f"\n[case] {wl} {method} n={A.n} small={small}", flush=True)
+    print(f"\n[case] {wl} {method} n={A.n} small={small} layout={layout}", flush=True)
     ref = oracle.solve(A, b, x0=x0, method=method, rtol=1e-8, trace=True)
-    res, x = gpu_solve(A, b, x0, method=method, rtol=1e-8, small=small)
+    res, x = gpu_solve(A, b, x0, method=method, rtol=1e-8, small=small, layout=layout)
     assert_same_run(res, x, ref, f"{wl}/{method}")
     assert ref.status == "converged"
     assert oracle.true_residual(A, b, x) <= 1.5e-8
