@@ -100,16 +100,21 @@ static int env_int(const char *name, int dflt, int lo, int hi)
     return (int)std::min<long>(hi, std::max<long>(lo, v));
 }
 
-// Workgroups of a product launch: at most FK_SPMV_GRID (default 2048, i.e.
-// eight 256-thread workgroups per CU of the 256-CU part), a multiple of 8 so
-// that every XCD owns the same number of them.
-static int spmv_grid(int nblocks)
+// Workgroups of a product launch, a multiple of 8 so that every XCD owns
+// the same number of them, at most FK_SPMV_GRID when that is set.
+//  - Row blocks: one block per workgroup up to 2048 (eight 256-thread
+//    workgroups per CU of the 256-CU part), each taking a contiguous chunk.
+//  - Sliced: two slices per wave.  Measured on MI355X, that beats one and
+//    four on the 128^3 Poisson matrix (32768 slices) and on the 1024^2
+//    convection-diffusion matrix (16384 slices) alike.
+static int spmv_grid(bool sliced, int64_t units)
 {
-    static const int gmax = env_int("FK_SPMV_GRID", 2048, 8, GMAX);
-    int g = std::min(nblocks, gmax);
+    static const int gcap = env_int("FK_SPMV_GRID", GMAX, 8, GMAX);
+    int64_t g = sliced ? (units + 2 * WAVES - 1) / (2 * WAVES) : std::min<int64_t>(units, 2048);
+    g = std::min<int64_t>(g, gcap);
     if (g >= 8)
         g &= ~7;
-    return std::max(g, 1);
+    return (int)std::max<int64_t>(g, 1);
 }
 
 static int vec_grid(int64_t n)
@@ -150,6 +155,11 @@ struct fk_csr_s {
     }
     // Entries the products read: nnz, or the slice entries with padding.
     int64_t stored_entries() const { return layout == FK_LAYOUT_SLICED ? sell_entries : nnz; }
+    int spmv_grid() const
+    {
+        const bool sliced = layout == FK_LAYOUT_SLICED;
+        return ::spmv_grid(sliced, sliced ? nslices : nblocks);
+    }
 };
 
 DevCsr fk::internal_csr_view(fk_csr A) { return A->view(); }
@@ -694,7 +704,7 @@ extern "C" fk_status fk_solver_create(fk_csr A, const fk_opts *o, void *hip_stre
         S->o.max_outer = 50;
     S->stream = (hipStream_t)hip_stream;
     S->n = A->n;
-    S->grid_spmv = spmv_grid(A->nblocks);
+    S->grid_spmv = A->spmv_grid();
     S->grid_vec = vec_grid(A->n);
     const size_t n = (size_t)A->n;
 #define S_TRY(expr)                                                                        \
@@ -1419,7 +1429,7 @@ extern "C" fk_status fk_spmv(fk_csr A, const double *p, double *q, double *dots_
     hipStream_t s = (hipStream_t)hip_stream;
     const int dots = dots_host ? (D_YV | D_YY) : 0;
     RedArgs red{A->st, A->partials, nullptr, nullptr, FIN_NONE, RUN_ALWAYS};
-    HIP_TRY(launch_spmv_dots(A->view(), p, q, nullptr, dots, red, spmv_grid(A->nblocks), s));
+    HIP_TRY(launch_spmv_dots(A->view(), p, q, nullptr, dots, red, A->spmv_grid(), s));
     if (dots_host) {
         double d[KMAX];
         HIP_TRY(hipMemcpyAsync(d, reinterpret_cast<const char *>(A->st) + offsetof(DevState, dots),

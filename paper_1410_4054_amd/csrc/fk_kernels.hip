@@ -50,7 +50,7 @@
 #endif
 // Entries of a row requested together by the sliced-layout products.
 #ifndef FK_SELL_UNROLL
-#define FK_SELL_UNROLL 4
+#define FK_SELL_UNROLL 8
 #endif
 
 namespace fk {
@@ -794,9 +794,10 @@ __device__ __forceinline__ T slice_row_sum(const int32_t *__restrict__ col, cons
 
 // The products of k_csr_rows on the sliced layout: one wave per slice, one
 // lane per row, no LDS staging and no barrier before the reduction point.
-// Workgroup g takes a contiguous range of slices, its waves take them in
-// turn.  Row sums, epilogues and the reduction are those of k_csr_rows, so
-// results are bitwise identical to it.
+// Wave w of the grid (logical workgroup order) takes slices w, w + W, ...
+// for W waves: at any moment the chip streams one contiguous window of the
+// slices, each XCD a contiguous eighth of it.  Row sums, epilogues and the
+// reduction are those of k_csr_rows, so y is bitwise identical to it.
 template <int MODE, int DOTS>
 __global__ __launch_bounds__(WG, FK_SPMV_MIN_WAVES) void k_sell_rows(DevCsr A, RowIo io, RedArgs red)
 {
@@ -808,16 +809,15 @@ __global__ __launch_bounds__(WG, FK_SPMV_MIN_WAVES) void k_sell_rows(DevCsr A, R
     constexpr bool NEED_W = MODE != ROW_SPMV || (DOTS & D_YW) != 0;
     const int G = gridDim.x;
     const int g = logical_wg();
-    const int s_begin = (int)(((int64_t)A.nslices * g) / G);
-    const int s_end = (int)(((int64_t)A.nslices * (g + 1)) / G);
     const int lane = threadIdx.x & (SLICE - 1);
+    const int nw = G * (WG / SLICE);
 
     dd acc[KA];
 #pragma unroll
     for (int k = 0; k < KA; ++k)
         acc[k] = dd{0.0, 0.0};
 
-    for (int sl = s_begin + (int)(threadIdx.x / SLICE); sl < s_end; sl += WG / SLICE) {
+    for (int sl = g * (WG / SLICE) + (int)(threadIdx.x / SLICE); sl < A.nslices; sl += nw) {
         const int e0 = A.sell_ptr[sl];
         const int width = (A.sell_ptr[sl + 1] - e0) / SLICE;
         const int row = sl * SLICE + lane;
@@ -1126,11 +1126,10 @@ __global__ __launch_bounds__(WG, FK_SPMV_MIN_WAVES) void k_sell_rows32(DevCsr A,
         return;
     const int G = gridDim.x;
     const int g = logical_wg();
-    const int s_begin = (int)(((int64_t)A.nslices * g) / G);
-    const int s_end = (int)(((int64_t)A.nslices * (g + 1)) / G);
     const int lane = threadIdx.x & (SLICE - 1);
+    const int nw = G * (WG / SLICE);
     dd acc[2] = {dd{0.0, 0.0}, dd{0.0, 0.0}};
-    for (int sl = s_begin + (int)(threadIdx.x / SLICE); sl < s_end; sl += WG / SLICE) {
+    for (int sl = g * (WG / SLICE) + (int)(threadIdx.x / SLICE); sl < A.nslices; sl += nw) {
         const int e0 = A.sell_ptr[sl];
         const int width = (A.sell_ptr[sl + 1] - e0) / SLICE;
         const int row = sl * SLICE + lane;
