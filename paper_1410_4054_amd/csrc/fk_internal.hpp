@@ -22,7 +22,10 @@ constexpr int GMAX = 4096;
 // The second reduction stage is a two-level tree: workgroups arrive in
 // groups of RGROUP; the last of each group sums the group, the last group
 // sums the group sums.
-constexpr int RGROUP = 32;
+constexpr int RGROUP = 64;
+// A launch with at most this many double-double partials (workgroups times
+// dots, published ones included) is summed by its last workgroup alone.
+constexpr int FLAT_PARTIALS = 4096;
 constexpr int RNGROUPS_MAX = GMAX / RGROUP;
 constexpr int CNT_STRIDE = 32;  // uint32 per arrival counter (one 128-byte line each)
 // Published first-stage partials (FIN_PUBLISH) of at most this many dots.

@@ -46,7 +46,7 @@
 #endif
 // Unroll factor of the grid-stride loops of the vector-update kernels.
 #ifndef FK_VEC_UNROLL
-#define FK_VEC_UNROLL 1
+#define FK_VEC_UNROLL 4
 #endif
 // Entries of a row requested together by the sliced-layout products.
 #ifndef FK_SELL_UNROLL
@@ -470,10 +470,15 @@ __device__ void finalize(DevState *st, int fin, const double *d, int K, double *
 // The reduction point at the end of a kernel; every thread of every
 // workgroup of the grid must call it exactly once.
 //
-// Second stage as a two-level tree.  Workgroup g publishes its partials and
-// arrives at the counter of group g / RGROUP; the last arrival of a group sums
-// that group's partials (in index order) and arrives at the top counter; the
-// last group sums the group sums (in group order), rounds and finalizes.
+// Second stage.  Workgroup g stores its partials and arrives at the counter
+// of group g / RGROUP; the last arrival of a group arrives at the top
+// counter, and the last of those finishes:
+//  - with at most FLAT_PARTIALS partials in all, it sums every partial
+//    itself (thread t takes indices t, t + WG, ..., then a fixed tree);
+//  - else as a two-level tree: the last arrival of each group first sums
+//    that group's partials (in index order) and stores the group sum, and
+//    the last group sums the group sums (in group order).
+// Either way the result is rounded once and finalized.
 // The order of every sum depends only on the grid size, never on timing.
 // Counters are reset by the workgroup that saw the last arrival, so the
 // scratch is ready for the next launch.
@@ -532,8 +537,6 @@ __device__ __forceinline__ void reduce_point(dd (&v)[K], const RedArgs &red, int
     if (!s_flag)
         return;
 
-    // Last arrival of the group: sum the group's partials, and this group's
-    // share of the published partials (dots K .. K + kpub - 1).
     constexpr int KP = (K + KPUB <= KMAX) ? KPUB : 0;
     constexpr int KT = K + KP;
     const int kpub = KP > 0 ? red.kpub : 0;
@@ -542,57 +545,95 @@ __device__ __forceinline__ void reduce_point(dd (&v)[K], const RedArgs &red, int
 #pragma unroll
     for (int k = 0; k < KT; ++k)
         acc[k] = dd{0.0, 0.0};
-#pragma unroll
-    for (int k = 0; k < K; ++k) {
-        if ((int)threadIdx.x < gsize) {
-            const double *slot = part1 + 2 * ((size_t)k * GMAX + gbase + threadIdx.x);
-            acc[k] = dd{load_coherent(slot), load_coherent(slot + 1)};
+
+    // Few partials: the last group only signals, and the very last
+    // workgroup sums every partial itself (one load round trip instead of
+    // a load, a store and a second arrival).  Many: two levels of sums.
+    const bool flat = (int64_t)G * K + (int64_t)red.npub * kpub <= FLAT_PARTIALS;
+    if (flat) {
+        if (threadIdx.x == 0) {
+            __hip_atomic_store(cnt + (size_t)grp * CNT_STRIDE, 0u, __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
+            const uint32_t prev = __hip_atomic_fetch_add(cnt + (size_t)RNGROUPS_MAX * CNT_STRIDE, 1u,
+                                                         __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            s_flag = (prev == (uint32_t)(ngroups - 1)) ? 1 : 0;
         }
-    }
-    if (kpub > 0) {
-        const int p0 = (int)(((int64_t)red.npub * grp) / ngroups);
-        const int p1 = (int)(((int64_t)red.npub * (grp + 1)) / ngroups);
-        for (int j = p0 + (int)threadIdx.x; j < p1; j += WG) {
+        __syncthreads();
+        if (!s_flag)
+            return;
+        for (int j = threadIdx.x; j < G; j += WG) {
 #pragma unroll
-            for (int k = 0; k < KP; ++k) {
-                if (k < kpub) {
-                    const double *slot = pub + 2 * ((size_t)k * GMAX + j);
-                    acc[K + k] = dd_add(acc[K + k], dd{load_coherent(slot), load_coherent(slot + 1)});
+            for (int k = 0; k < K; ++k) {
+                const double *slot = part1 + 2 * ((size_t)k * GMAX + j);
+                acc[k] = dd_add(acc[k], dd{load_coherent(slot), load_coherent(slot + 1)});
+            }
+        }
+        if (kpub > 0) {
+            for (int j = threadIdx.x; j < red.npub; j += WG) {
+#pragma unroll
+                for (int k = 0; k < KP; ++k) {
+                    if (k < kpub) {
+                        const double *slot = pub + 2 * ((size_t)k * GMAX + j);
+                        acc[K + k] = dd_add(acc[K + k], dd{load_coherent(slot), load_coherent(slot + 1)});
+                    }
                 }
             }
         }
-    }
-    block_reduce<KT>(acc, lds);
-    if (threadIdx.x == 0) {
+    } else {
+        // Last arrival of the group: sum the group's partials, and this
+        // group's share of the published partials (dots K .. K + kpub - 1).
 #pragma unroll
-        for (int k = 0; k < KT; ++k) {
-            if (k < kt) {
-                double *slot = part2 + 2 * ((size_t)k * RNGROUPS_MAX + grp);
-                store_coherent(slot, acc[k].hi);
-                store_coherent(slot + 1, acc[k].lo);
+        for (int k = 0; k < K; ++k) {
+            if ((int)threadIdx.x < gsize) {
+                const double *slot = part1 + 2 * ((size_t)k * GMAX + gbase + threadIdx.x);
+                acc[k] = dd{load_coherent(slot), load_coherent(slot + 1)};
             }
         }
-        __hip_atomic_store(cnt + (size_t)grp * CNT_STRIDE, 0u, __ATOMIC_RELAXED,
-                           __HIP_MEMORY_SCOPE_AGENT);
-        __builtin_amdgcn_s_waitcnt(0);
-        const uint32_t prev = __hip_atomic_fetch_add(cnt + (size_t)RNGROUPS_MAX * CNT_STRIDE, 1u,
-                                                     __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        s_flag = (prev == (uint32_t)(ngroups - 1)) ? 1 : 0;
-    }
-    __syncthreads();
-    if (!s_flag)
-        return;
+        if (kpub > 0) {
+            const int p0 = (int)(((int64_t)red.npub * grp) / ngroups);
+            const int p1 = (int)(((int64_t)red.npub * (grp + 1)) / ngroups);
+            for (int j = p0 + (int)threadIdx.x; j < p1; j += WG) {
+#pragma unroll
+                for (int k = 0; k < KP; ++k) {
+                    if (k < kpub) {
+                        const double *slot = pub + 2 * ((size_t)k * GMAX + j);
+                        acc[K + k] = dd_add(acc[K + k], dd{load_coherent(slot), load_coherent(slot + 1)});
+                    }
+                }
+            }
+        }
+        block_reduce<KT>(acc, lds);
+        if (threadIdx.x == 0) {
+#pragma unroll
+            for (int k = 0; k < KT; ++k) {
+                if (k < kt) {
+                    double *slot = part2 + 2 * ((size_t)k * RNGROUPS_MAX + grp);
+                    store_coherent(slot, acc[k].hi);
+                    store_coherent(slot + 1, acc[k].lo);
+                }
+            }
+            __hip_atomic_store(cnt + (size_t)grp * CNT_STRIDE, 0u, __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
+            __builtin_amdgcn_s_waitcnt(0);
+            const uint32_t prev = __hip_atomic_fetch_add(cnt + (size_t)RNGROUPS_MAX * CNT_STRIDE, 1u,
+                                                         __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            s_flag = (prev == (uint32_t)(ngroups - 1)) ? 1 : 0;
+        }
+        __syncthreads();
+        if (!s_flag)
+            return;
 
-    // Last group: sum the group sums and finalize.
+        // Last group: sum the group sums.
 #pragma unroll
-    for (int k = 0; k < KT; ++k)
-        acc[k] = dd{0.0, 0.0};
-    for (int j = threadIdx.x; j < ngroups; j += WG) {
+        for (int k = 0; k < KT; ++k)
+            acc[k] = dd{0.0, 0.0};
+        for (int j = threadIdx.x; j < ngroups; j += WG) {
 #pragma unroll
-        for (int k = 0; k < KT; ++k) {
-            if (k < kt) {
-                const double *slot = part2 + 2 * ((size_t)k * RNGROUPS_MAX + j);
-                acc[k] = dd_add(acc[k], dd{load_coherent(slot), load_coherent(slot + 1)});
+            for (int k = 0; k < KT; ++k) {
+                if (k < kt) {
+                    const double *slot = part2 + 2 * ((size_t)k * RNGROUPS_MAX + j);
+                    acc[k] = dd_add(acc[k], dd{load_coherent(slot), load_coherent(slot + 1)});
+                }
             }
         }
     }
@@ -760,14 +801,13 @@ __global__ __launch_bounds__(WG, FK_SPMV_MIN_WAVES) void k_csr_rows(DevCsr A, Ro
 // ------------------------------------------------ sliced-layout products
 
 // One row of a slice summed left to right (the row's CSR order): the lane's
-// entries k = 0 .. width-1 sit SLICE apart; FK_SELL_UNROLL of them, with
-// their gathers, are requested before the first is added.  Padding (column
+// entries k = 0 .. width-1 sit SLICE apart; U of them, with their gathers,
+// are requested before the first is added.  Padding (column
 // -1) only follows a row's last nonzero and is skipped.
-template <typename T>
+template <typename T, int U = FK_SELL_UNROLL>
 __device__ __forceinline__ T slice_row_sum(const int32_t *__restrict__ col, const T *__restrict__ vals,
                                            const T *__restrict__ v, int width)
 {
-    constexpr int U = FK_SELL_UNROLL;
     T q = T(0);
     for (int k = 0; k < width; k += U) {
         int c[U];
@@ -829,7 +869,9 @@ __global__ __launch_bounds__(WG, FK_SPMV_MIN_WAVES) void k_sell_rows(DevCsr A, R
             if constexpr (NEED_W)
                 wrow = io.w[row];
         }
-        const double q = slice_row_sum<double>(A.sell_col + e0 + lane, A.sell_vals + e0 + lane, io.v, width);
+        // (Three double-double accumulators leave room for fewer entries.)
+        const double q = slice_row_sum<double, (KA >= 3 ? FK_SELL_UNROLL / 2 : FK_SELL_UNROLL)>(
+            A.sell_col + e0 + lane, A.sell_vals + e0 + lane, io.v, width);
         if (live) {
             if constexpr (K > 0)
                 row_epilogue<MODE, DOTS, KA>(io, row, q, vrow, wrow, acc);
