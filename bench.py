@@ -11,10 +11,13 @@ synthetic input already resident in HBM.
 value = CG iterations per second over the K timed steps.  The roofline
 entry is for the dominant kernel, the fused SpMV + two dots: algorithmic
 bytes per launch of the layout it reads over its average duration.  The
-library stores this matrix in 64-row slices (sliced ELLPACK): 12 bytes per
-stored entry (values and column indices, padding included), 4 per slice
-offset, one read of p and one write of Ap, 16 N; in CSR row blocks it would
-be 12 nnz + 4 (N + 1) + 16 N.  Durations are measured with HIP
+library stores this matrix in 64-row slices (sliced ELLPACK) with columns
+as 16-bit offsets from the row, read four at a time: 8 bytes of value per
+stored entry plus 8 per group of four offsets (padding included) and two
+int32 slice pointers per slice, as fk_csr_layout reports them, and one read
+of p and one write of Ap, 16 N; with int32 columns it would be 12 per
+entry, in CSR row blocks 12 nnz + 4 (N + 1) + 16 N.  Durations are measured
+with HIP
 events on the solver's stream that the device stamps at the start and end of
 each launch, in a second pass over the same K steps (the events cost wall
 time, so the timed pass runs without them).  The CPU baseline is
@@ -46,21 +49,17 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def index_bytes(n: int, layout: str) -> int:
-    """Row pointers (row blocks) or slice offsets (sliced), int32."""
-    return 4 * (n + 1) if layout == "row_blocks" else 4 * (-(-n // 64) + 1)
+def spmv_dot_bytes(n: int, matrix_bytes: int) -> int:
+    """Compulsory bytes of one fused SpMV + 2 dots launch: the matrix data of
+    its layout (FP64 values, column indices or 16-bit offsets, row or slice
+    pointers, as fk_csr_layout reports them), one read of p, one write of Ap."""
+    return matrix_bytes + 8 * n + 8 * n
 
 
-def spmv_dot_bytes(n: int, entries: int, layout: str) -> int:
-    """Compulsory bytes of one fused SpMV + 2 dots launch: FP64 values and
-    int32 column indices of the `entries` the layout stores, its index
-    array, one read of p, one write of Ap."""
-    return 12 * entries + index_bytes(n, layout) + 8 * n + 8 * n
-
-
-def spmv32_dot_bytes(n: int, entries: int, layout: str) -> int:
-    """The FP32 product + 2 dots of the mixed-precision inner solver."""
-    return 8 * entries + index_bytes(n, layout) + 4 * n + 4 * n
+def spmv32_dot_bytes(n: int, entries: int, matrix_bytes: int) -> int:
+    """The FP32 product + 2 dots of the mixed-precision inner solver: the
+    same matrix data with 4-byte values, one read of p, one write of Ap."""
+    return matrix_bytes - 4 * entries + 4 * n + 4 * n
 
 
 def update_bytes(n: int) -> int:
@@ -161,6 +160,7 @@ def main():
     n, nnz = A.n, A.nnz
     M = fk.Matrix(A)
     layout, entries = M.layout()
+    mat_bytes = M.matrix_bytes()
     bd = torch.as_tensor(b, device="cuda")
     xd = torch.zeros_like(bd)
 
@@ -212,7 +212,7 @@ def main():
 
     spmv_us = kernel_us["spmv_dot"][0] / max(kernel_us["spmv_dot"][1], 1)
     upd_us = kernel_us["update_dot"][0] / max(kernel_us["update_dot"][1], 1)
-    spmv_b = spmv_dot_bytes(n, entries, layout)
+    spmv_b = spmv_dot_bytes(n, mat_bytes)
     achieved = spmv_b / (spmv_us * 1e-6) / 1e9
     traffic = measured_traffic("spmv_dot", WORKLOAD)
 
@@ -238,14 +238,18 @@ def main():
         extras["spmv_dot_us"] = spmv_us
         extras["spmv_layout"] = layout
         extras["spmv_stored_entries"] = entries
-        # The same fused product on the CSR row-block layout, for comparison.
-        Mrb = fk.Matrix(A, layout="row_blocks")
-        Srb = fk.Solver(Mrb, method="cg_pipelined", rtol=RTOL, record_history=False, profile=True)
-        xd.zero_(); Srb.solve(bd, xd)
-        rb_us = Srb.kernel_times()["spmv_dot"][0]
-        Srb.close(); Mrb.close()
-        extras["row_blocks_spmv_dot_us"] = rb_us
-        extras["row_blocks_spmv_dot_GBps"] = spmv_dot_bytes(n, nnz, "row_blocks") / (rb_us * 1e-6) / 1e9
+        # The same fused product on the other layouts, for comparison.
+        for other in ("sliced16", "sliced", "row_blocks"):
+            if other == layout:
+                continue
+            Mo = fk.Matrix(A, layout=other)
+            So = fk.Solver(Mo, method="cg_pipelined", rtol=RTOL, record_history=False, profile=True)
+            xd.zero_(); So.solve(bd, xd)
+            o_us = So.kernel_times()["spmv_dot"][0]
+            o_bytes = Mo.matrix_bytes()
+            So.close(); Mo.close()
+            extras[f"{other}_spmv_dot_us"] = o_us
+            extras[f"{other}_spmv_dot_GBps"] = spmv_dot_bytes(n, o_bytes) / (o_us * 1e-6) / 1e9
         extras["update_dot_us"] = upd_us
         extras["update_dot_GBps"] = update_bytes(n) / (upd_us * 1e-6) / 1e9
         per_it_bytes = spmv_b + update_bytes(n)
@@ -307,7 +311,7 @@ def main():
         kt = S2.kernel_times()
         S2.close()
         extras["mixed_spmv32_dot_us"] = kt["spmv_dot"][0]
-        extras["mixed_spmv32_dot_GBps"] = spmv32_dot_bytes(n, entries, layout) / (kt["spmv_dot"][0] * 1e-6) / 1e9
+        extras["mixed_spmv32_dot_GBps"] = spmv32_dot_bytes(n, entries, mat_bytes) / (kt["spmv_dot"][0] * 1e-6) / 1e9
         extras["mixed_update32_dot_us"] = kt["update_dot"][0]
         extras["mixed_update32_dot_GBps"] = 28 * n / (kt["update_dot"][0] * 1e-6) / 1e9
         extras["mixed_residual_fp64_us"] = kt["residual"][0]

@@ -103,7 +103,8 @@ enum { FK_PTR_HOST = 0, FK_PTR_DEVICE = 1 };
 enum {
     FK_LAYOUT_AUTO = 0,        /* the creation rule below                      */
     FK_LAYOUT_ROW_BLOCKS = 1,  /* the CSR arrays, cut into row blocks          */
-    FK_LAYOUT_SLICED = 2       /* the nonzeros regrouped into 64-row slices    */
+    FK_LAYOUT_SLICED = 2,      /* the nonzeros regrouped into 64-row slices    */
+    FK_LAYOUT_SLICED16 = 3     /* the same, columns as 16-bit row offsets      */
 };
 
 /*
@@ -144,17 +145,28 @@ fk_status fk_csr_blocks(fk_csr A, int32_t *nblocks, int32_t *long_rows);
  *    row sorting), shorter rows padded.  One lane sums one row; no LDS.
  *    Costs 12 bytes of device memory per stored entry next to the CSR
  *    arrays, which stay (other kernels read them).
- * fk_csr_create picks SLICED when no row has more than 64 nonzeros and the
- * padding adds at most 25 % to the entries read, else ROW_BLOCKS.
- * fk_csr_layout reports the layout in use and the entries its products read
- * per call (nnz, or the slice entries with padding).
+ *  - FK_LAYOUT_SLICED16: the sliced layout with each column stored as a
+ *    16-bit offset from its row, so a product reads about 10 bytes per
+ *    entry instead of 12 (6 instead of 8 for FP32 values).  Possible when every
+ *    column lies within 32767 of its row (banded and stencil matrices);
+ *    2 more bytes of device memory per stored entry.
+ * fk_csr_create picks a sliced layout when no row has more than 64 nonzeros
+ * and the padding adds at most 25 % to the entries read (SLICED16 when the
+ * offsets fit, else SLICED), else ROW_BLOCKS.  fk_csr_layout reports the
+ * layout in use, the entries its products read per call (nnz, or the slice
+ * entries with padding) and, when matrix_bytes is not NULL, the bytes of
+ * matrix data one FP64 product reads (values, column indices or offsets,
+ * row or slice pointers; the 16-bit offsets are read four at a time, so a
+ * row's last group counts whole).
  */
-fk_status fk_csr_layout(fk_csr A, int32_t *layout, int64_t *stored_entries);
+fk_status fk_csr_layout(fk_csr A, int32_t *layout, int64_t *stored_entries, int64_t *matrix_bytes);
 
 /*
  * Force a layout: FK_LAYOUT_ROW_BLOCKS, FK_LAYOUT_SLICED (builds the slices
  * when absent, whatever their padding; FK_E_ARG if they would need more than
- * INT32_MAX entries) or FK_LAYOUT_AUTO (the creation rule).  Solvers read the
+ * INT32_MAX entries), FK_LAYOUT_SLICED16 (the same; FK_E_ARG when a column
+ * lies more than 32767 from its row) or FK_LAYOUT_AUTO (the creation
+ * rule).  Solvers read the
  * layout when they are created, so FK_E_STATE while any solver exists on A.
  * Runs on hip_stream and returns after it has drained.
  */

@@ -134,8 +134,10 @@ struct fk_csr_s {
     int32_t nblocks = 0;
     int32_t long_rows = 0;
     int device = 0;
-    // sliced layout (built when it pays, or on request)
-    int32_t *sell_ptr = nullptr, *sell_col = nullptr;
+    // sliced layout (built when it pays, or on request); sell_off4 exists
+    // when every column is within 32767 of its row
+    int32_t *sell_ptr = nullptr, *sell_col = nullptr, *sell_ptr4 = nullptr;
+    short4 *sell_off4 = nullptr;
     double *sell_vals = nullptr;
     int32_t nslices = 0;      // > 0 once the sliced arrays exist
     int64_t sell_entries = 0;
@@ -145,21 +147,29 @@ struct fk_csr_s {
     double *partials = nullptr;
     int solvers = 0;
 
+    bool sliced() const { return layout == FK_LAYOUT_SLICED || layout == FK_LAYOUT_SLICED16; }
     DevCsr view() const
     {
-        const bool sliced = layout == FK_LAYOUT_SLICED;
         return DevCsr{(int32_t)n,  (int32_t)nnz, nblocks,  row_ptr,
                       col_idx,     vals,         blocks,   block_j0,
-                      sliced ? nslices : 0,      sell_ptr, sell_col,
-                      sell_vals};
+                      sliced() ? nslices : 0,    sell_ptr, sell_col,
+                      sell_vals,   sell_ptr4,
+                      layout == FK_LAYOUT_SLICED16 ? sell_off4 : nullptr};
     }
     // Entries the products read: nnz, or the slice entries with padding.
-    int64_t stored_entries() const { return layout == FK_LAYOUT_SLICED ? sell_entries : nnz; }
-    int spmv_grid() const
+    int64_t stored_entries() const { return sliced() ? sell_entries : nnz; }
+    int64_t sell_words4 = 0;  // 8-byte words of the 16-bit column offsets
+    // Bytes of matrix data one FP64 product reads: values, column indices
+    // (or offsets), row pointers (or slice pointers).
+    int64_t matrix_bytes() const
     {
-        const bool sliced = layout == FK_LAYOUT_SLICED;
-        return ::spmv_grid(sliced, sliced ? nslices : nblocks);
+        if (layout == FK_LAYOUT_SLICED16)
+            return 8 * sell_entries + 8 * sell_words4 + 8 * ((int64_t)nslices + 1);
+        if (layout == FK_LAYOUT_SLICED)
+            return 12 * sell_entries + 4 * ((int64_t)nslices + 1);
+        return 12 * nnz + 4 * (n + 1);
     }
+    int spmv_grid() const { return ::spmv_grid(sliced(), sliced() ? nslices : nblocks); }
 };
 
 DevCsr fk::internal_csr_view(fk_csr A) { return A->view(); }
@@ -252,29 +262,60 @@ static fk_status build_slices(fk_csr A, const int32_t *rp, const int32_t *ci,
     if (entries > INT32_MAX)
         return fail(FK_E_ARG, "sliced layout needs %lld entries, more than int32 offsets hold",
                     (long long)entries);
-    std::vector<int32_t> ptr, col, map;
+    // 16-bit offsets: four entries of a row per 8-byte word; slice s has
+    // ceil(width_s / 4) * SLICE words from ptr4[s].
+    std::vector<int32_t> ptr, col, map, ptr4;
+    std::vector<short4> rel;
     try {
         ptr.resize((size_t)ns + 1);
+        ptr4.resize((size_t)ns + 1);
         col.assign((size_t)std::max<int64_t>(entries, 1), -1);
         map.assign((size_t)std::max<int64_t>(entries, 1), -1);
+        ptr4[0] = 0;
+        for (int64_t sl = 0; sl < ns; ++sl) {
+            const int64_t w = (off[(size_t)sl + 1] - off[(size_t)sl]) / SLICE;
+            ptr4[(size_t)sl + 1] = ptr4[(size_t)sl] + (int32_t)((w + 3) / 4 * SLICE);
+        }
+        rel.assign((size_t)std::max<int32_t>(ptr4[(size_t)ns], 1),
+                   make_short4(SELL_PAD, SELL_PAD, SELL_PAD, SELL_PAD));
     } catch (const std::bad_alloc &) {
         return fail(FK_E_OOM, "host allocation failed");
     }
     for (int64_t sl = 0; sl <= ns; ++sl)
         ptr[(size_t)sl] = (int32_t)off[(size_t)sl];
+    bool narrow = true;
     for (int64_t r = 0; r < n; ++r) {
         const int64_t sl = r / SLICE, lane = r % SLICE;
         for (int32_t j = rp[r]; j < rp[r + 1]; ++j) {
-            const size_t e = (size_t)(off[(size_t)sl] + (int64_t)(j - rp[r]) * SLICE + lane);
+            const int64_t k = j - rp[r];
+            const size_t e = (size_t)(off[(size_t)sl] + k * SLICE + lane);
             col[e] = ci[j];
             map[e] = j;
+            const int64_t d = (int64_t)ci[j] - r;
+            if (d < -32767 || d > 32767) {
+                narrow = false;
+                continue;
+            }
+            short4 &wd = rel[(size_t)(ptr4[(size_t)sl] + (k / 4) * SLICE + lane)];
+            const int16_t v16 = (int16_t)d;
+            switch (k % 4) {
+            case 0: wd.x = v16; break;
+            case 1: wd.y = v16; break;
+            case 2: wd.z = v16; break;
+            default: wd.w = v16; break;
+            }
         }
     }
-    int32_t *d_ptr = nullptr, *d_col = nullptr, *d_map = nullptr;
+    int32_t *d_ptr = nullptr, *d_col = nullptr, *d_map = nullptr, *d_ptr4 = nullptr;
+    short4 *d_rel = nullptr;
     double *d_vals = nullptr;
     fk_status st = dev_alloc(&d_ptr, (size_t)ns + 1, "slice offsets");
     if (st == FK_OK)
         st = dev_alloc(&d_col, col.size(), "slice columns");
+    if (st == FK_OK && narrow)
+        st = dev_alloc(&d_ptr4, ptr4.size(), "slice offsets (16-bit columns)");
+    if (st == FK_OK && narrow)
+        st = dev_alloc(&d_rel, rel.size(), "slice column offsets");
     if (st == FK_OK)
         st = dev_alloc(&d_vals, col.size(), "slice values");
     if (st == FK_OK)
@@ -284,6 +325,10 @@ static fk_status build_slices(fk_csr A, const int32_t *rp, const int32_t *ci,
         e = hipMemcpyAsync(d_ptr, ptr.data(), ptr.size() * 4, hipMemcpyHostToDevice, s);
         if (e == hipSuccess)
             e = hipMemcpyAsync(d_col, col.data(), col.size() * 4, hipMemcpyHostToDevice, s);
+        if (e == hipSuccess && narrow)
+            e = hipMemcpyAsync(d_ptr4, ptr4.data(), ptr4.size() * 4, hipMemcpyHostToDevice, s);
+        if (e == hipSuccess && narrow)
+            e = hipMemcpyAsync(d_rel, rel.data(), rel.size() * sizeof(short4), hipMemcpyHostToDevice, s);
         if (e == hipSuccess)
             e = hipMemcpyAsync(d_map, map.data(), map.size() * 4, hipMemcpyHostToDevice, s);
         if (e == hipSuccess)
@@ -297,14 +342,21 @@ static fk_status build_slices(fk_csr A, const int32_t *rp, const int32_t *ci,
     if (st != FK_OK) {
         dev_free(d_ptr);
         dev_free(d_col);
+        dev_free(d_ptr4);
+        dev_free(d_rel);
         dev_free(d_vals);
         return st;
     }
     dev_free(A->sell_ptr);
     dev_free(A->sell_col);
+    dev_free(A->sell_ptr4);
+    dev_free(A->sell_off4);
     dev_free(A->sell_vals);
     A->sell_ptr = d_ptr;
     A->sell_col = d_col;
+    A->sell_ptr4 = d_ptr4;
+    A->sell_off4 = d_rel;
+    A->sell_words4 = narrow ? ptr4[(size_t)ns] : 0;
     A->sell_vals = d_vals;
     A->nslices = (int32_t)ns;
     A->sell_entries = entries;
@@ -315,6 +367,8 @@ static void csr_release(fk_csr A)
 {
     dev_free(A->sell_ptr);
     dev_free(A->sell_col);
+    dev_free(A->sell_ptr4);
+    dev_free(A->sell_off4);
     dev_free(A->sell_vals);
     dev_free(A->row_ptr);
     dev_free(A->col_idx);
@@ -426,7 +480,7 @@ extern "C" fk_status fk_csr_create(int64_t n, int64_t nnz, const int32_t *row_pt
         }
         if (sliced_pays(off, nnz, max_len)) {
             CSR_TRY(build_slices(A, rp, ci, off, s));
-            A->layout = FK_LAYOUT_SLICED;
+            A->layout = A->sell_off4 ? FK_LAYOUT_SLICED16 : FK_LAYOUT_SLICED;
         }
     }
 #undef CSR_TRY
@@ -455,12 +509,14 @@ extern "C" fk_status fk_csr_shape(fk_csr A, int64_t *n, int64_t *nnz)
     return FK_OK;
 }
 
-extern "C" fk_status fk_csr_layout(fk_csr A, int32_t *layout, int64_t *stored_entries)
+extern "C" fk_status fk_csr_layout(fk_csr A, int32_t *layout, int64_t *stored_entries, int64_t *matrix_bytes)
 {
     if (!A || !layout || !stored_entries)
         return fail(FK_E_ARG, "NULL argument");
     *layout = A->layout;
     *stored_entries = A->stored_entries();
+    if (matrix_bytes)
+        *matrix_bytes = A->matrix_bytes();
     return FK_OK;
 }
 
@@ -468,7 +524,8 @@ extern "C" fk_status fk_csr_set_layout(fk_csr A, int32_t layout, void *hip_strea
 {
     if (!A)
         return fail(FK_E_ARG, "NULL matrix");
-    if (layout != FK_LAYOUT_AUTO && layout != FK_LAYOUT_ROW_BLOCKS && layout != FK_LAYOUT_SLICED)
+    if (layout != FK_LAYOUT_AUTO && layout != FK_LAYOUT_ROW_BLOCKS && layout != FK_LAYOUT_SLICED &&
+        layout != FK_LAYOUT_SLICED16)
         return fail(FK_E_ARG, "unknown layout %d", layout);
     if (A->solvers > 0)
         return fail(FK_E_STATE, "%d solver(s) use this matrix; destroy them first", A->solvers);
@@ -509,7 +566,11 @@ extern "C" fk_status fk_csr_set_layout(fk_csr A, int32_t layout, void *hip_strea
                 return st;
         }
     }
-    A->layout = FK_LAYOUT_SLICED;
+    if (layout == FK_LAYOUT_SLICED16 && !A->sell_off4)
+        return fail(FK_E_ARG, "a column lies more than 32767 away from its row: no 16-bit offsets");
+    if (layout == FK_LAYOUT_AUTO)
+        layout = A->sell_off4 ? FK_LAYOUT_SLICED16 : FK_LAYOUT_SLICED;
+    A->layout = layout;
     return FK_OK;
 }
 
@@ -780,7 +841,7 @@ extern "C" fk_status fk_solver_create(fk_csr A, const fk_opts *o, void *hip_stre
     if (S->mixed) {
         S_HIP(hipMemsetAsync(S->st_outer, 0, sizeof(DevState), S->stream));
         if (A->nnz > 0) {
-            const bool sliced = A->layout == FK_LAYOUT_SLICED;
+            const bool sliced = A->sliced();
             const int64_t m = A->stored_entries();
             S_HIP(launch_to_f32(m, S->vals32, sliced ? A->sell_vals : A->vals, vec_grid(m), S->stream));
         }

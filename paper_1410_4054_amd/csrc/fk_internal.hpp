@@ -145,7 +145,16 @@ struct DevCsr {
     const int32_t *sell_ptr;  // nslices + 1 entry offsets
     const int32_t *sell_col;  // column of each entry, -1 for padding
     const double *sell_vals;  // value of each entry, 0 for padding
+    // Narrow sliced layout (when non-null, read instead of sell_col): the
+    // column of each entry as a 16-bit offset from its row, SELL_PAD for
+    // padding, packed four entries per lane: entries 4j .. 4j+3 of row
+    // s*SLICE + l are the short4 at sell_off4[sell_ptr4[s] + j*SLICE + l]
+    // (the last group of a slice padded to four).
+    const int32_t *sell_ptr4;
+    const short4 *sell_off4;
 };
+
+constexpr int16_t SELL_PAD = -32768;
 
 // Dot selection bits for the fused product kernel y = A v.
 enum DotBits : int32_t {

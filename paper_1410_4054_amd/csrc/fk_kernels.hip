@@ -44,7 +44,8 @@
 #ifndef FK_NT_CSR
 #define FK_NT_CSR 0
 #endif
-// Unroll factor of the grid-stride loops of the vector-update kernels.
+// Unroll factor of the grid-stride loops of the per-iteration vector-update
+// kernels (measured: 4 beats 1 and 2 on MI355X).
 #ifndef FK_VEC_UNROLL
 #define FK_VEC_UNROLL 4
 #endif
@@ -800,27 +801,54 @@ __global__ __launch_bounds__(WG, FK_SPMV_MIN_WAVES) void k_csr_rows(DevCsr A, Ro
 
 // ------------------------------------------------ sliced-layout products
 
+// Column indices of the lane's row: absolute int32 (-1 = padding), or
+// 16-bit offsets from the row (SELL_PAD = padding) four to a load.
+template <bool NARROW>
+struct SliceCols {
+    const int32_t *__restrict__ col;  // sell_col + e0 + lane
+    const short4 *__restrict__ off4;  // sell_off4 + sell_ptr4[s] + lane
+    int row;
+};
+
+// Columns of entries k .. k+U-1 (k a multiple of U, U of 4), -1 past width.
+template <int U, bool NARROW>
+__device__ __forceinline__ void slice_cols(const SliceCols<NARROW> &sc, int k, int width, int (&c)[U])
+{
+    if constexpr (NARROW) {
+        static_assert(U % 4 == 0, "16-bit offsets come four to a load");
+#pragma unroll
+        for (int j = 0; j < U / 4; ++j) {
+            short4 o = make_short4(SELL_PAD, SELL_PAD, SELL_PAD, SELL_PAD);
+            if (k + 4 * j < width)
+                o = load_stream(sc.off4 + (size_t)(k / 4 + j) * SLICE);
+            const int16_t os[4] = {o.x, o.y, o.z, o.w};
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+                c[4 * j + i] = (k + 4 * j + i < width && os[i] != SELL_PAD) ? sc.row + (int)os[i] : -1;
+        }
+    } else {
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            c[u] = k + u < width ? load_stream(sc.col + (size_t)(k + u) * SLICE) : -1;
+    }
+}
+
 // One row of a slice summed left to right (the row's CSR order): the lane's
 // entries k = 0 .. width-1 sit SLICE apart; U of them, with their gathers,
-// are requested before the first is added.  Padding (column
-// -1) only follows a row's last nonzero and is skipped.
-template <typename T, int U = FK_SELL_UNROLL>
-__device__ __forceinline__ T slice_row_sum(const int32_t *__restrict__ col, const T *__restrict__ vals,
+// are requested before the first is added.  Padding only follows a row's
+// last nonzero and is skipped.
+template <typename T, int U, bool NARROW>
+__device__ __forceinline__ T slice_row_sum(const SliceCols<NARROW> &cols, const T *__restrict__ vals,
                                            const T *__restrict__ v, int width)
 {
     T q = T(0);
     for (int k = 0; k < width; k += U) {
         int c[U];
         T a[U], x[U];
+        slice_cols<U, NARROW>(cols, k, width, c);
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
-            c[u] = -1;
-            a[u] = T(0);
-            if (k + u < width) {
-                c[u] = load_stream(col + (size_t)(k + u) * SLICE);
-                a[u] = load_stream(vals + (size_t)(k + u) * SLICE);
-            }
-        }
+        for (int u = 0; u < U; ++u)
+            a[u] = k + u < width ? load_stream(vals + (size_t)(k + u) * SLICE) : T(0);
 #pragma unroll
         for (int u = 0; u < U; ++u)
             x[u] = c[u] >= 0 ? v[c[u]] : T(0);
@@ -838,7 +866,7 @@ __device__ __forceinline__ T slice_row_sum(const int32_t *__restrict__ col, cons
 // for W waves: at any moment the chip streams one contiguous window of the
 // slices, each XCD a contiguous eighth of it.  Row sums, epilogues and the
 // reduction are those of k_csr_rows, so y is bitwise identical to it.
-template <int MODE, int DOTS>
+template <int MODE, int DOTS, bool NARROW>
 __global__ __launch_bounds__(WG, FK_SPMV_MIN_WAVES) void k_sell_rows(DevCsr A, RowIo io, RedArgs red)
 {
     if (!runs(red))
@@ -869,9 +897,11 @@ __global__ __launch_bounds__(WG, FK_SPMV_MIN_WAVES) void k_sell_rows(DevCsr A, R
             if constexpr (NEED_W)
                 wrow = io.w[row];
         }
+        const SliceCols<NARROW> cols{A.sell_col + e0 + lane,
+                                     NARROW ? A.sell_off4 + A.sell_ptr4[sl] + lane : nullptr, row};
         // (Three double-double accumulators leave room for fewer entries.)
-        const double q = slice_row_sum<double, (KA >= 3 ? FK_SELL_UNROLL / 2 : FK_SELL_UNROLL)>(
-            A.sell_col + e0 + lane, A.sell_vals + e0 + lane, io.v, width);
+        const double q = slice_row_sum<double, (KA >= 3 ? FK_SELL_UNROLL / 2 : FK_SELL_UNROLL), NARROW>(
+            cols, A.sell_vals + e0 + lane, io.v, width);
         if (live) {
             if constexpr (K > 0)
                 row_epilogue<MODE, DOTS, KA>(io, row, q, vrow, wrow, acc);
@@ -932,6 +962,7 @@ __global__ __launch_bounds__(WG) void k_bicg_s(int64_t n, const double *__restri
     const double alpha = red.st->alpha;
     dd acc[1] = {dd{0.0, 0.0}};
     const int64_t stride = (int64_t)gridDim.x * WG;
+#pragma unroll FK_VEC_UNROLL
     for (int64_t i = (int64_t)blockIdx.x * WG + threadIdx.x; i < n; i += stride) {
         const double si = r[i] - alpha * ap[i];
         s[i] = si;
@@ -960,6 +991,7 @@ __global__ __launch_bounds__(WG) void k_bicg_xrp(int64_t n, double *__restrict__
     dd acc[2] = {dd{0.0, 0.0}, dd{0.0, 0.0}};
     const int64_t stride = (int64_t)gridDim.x * WG;
     if (half) {
+#pragma unroll FK_VEC_UNROLL
         for (int64_t i = (int64_t)blockIdx.x * WG + threadIdx.x; i < n; i += stride) {
             x[i] = x[i] + alpha * p[i];
             r[i] = s[i];
@@ -1160,6 +1192,7 @@ __global__ __launch_bounds__(WG, FK_SPMV_MIN_WAVES) void k_csr_rows32(DevCsr A, 
 }
 
 // k_csr_rows32 on the sliced layout (vals32 in slice order).
+template <bool NARROW>
 __global__ __launch_bounds__(WG, FK_SPMV_MIN_WAVES) void k_sell_rows32(DevCsr A, const float *vals32,
                                                                         const float *v, float *y,
                                                                         RedArgs red)
@@ -1177,7 +1210,9 @@ __global__ __launch_bounds__(WG, FK_SPMV_MIN_WAVES) void k_sell_rows32(DevCsr A,
         const int row = sl * SLICE + lane;
         const bool live = row < A.n;
         const float vrow = live ? v[row] : 0.f;
-        const float q = slice_row_sum<float>(A.sell_col + e0 + lane, vals32 + e0 + lane, v, width);
+        const SliceCols<NARROW> cols{A.sell_col + e0 + lane,
+                                     NARROW ? A.sell_off4 + A.sell_ptr4[sl] + lane : nullptr, row};
+        const float q = slice_row_sum<float, FK_SELL_UNROLL, NARROW>(cols, vals32 + e0 + lane, v, width);
         if (live) {
             y[row] = q;
             dd_fma(acc[0], (double)q, (double)vrow);
@@ -1199,6 +1234,7 @@ __global__ __launch_bounds__(WG) void k_cg_update32(int64_t n, float *__restrict
     const float beta = (float)red.st->beta;
     dd acc[1] = {dd{0.0, 0.0}};
     const int64_t stride = (int64_t)gridDim.x * WG;
+#pragma unroll FK_VEC_UNROLL
     for (int64_t i = (int64_t)blockIdx.x * WG + threadIdx.x; i < n; i += stride) {
         const float pi = p[i];
         d[i] = d[i] + alpha * pi;
@@ -1851,8 +1887,10 @@ template <int MODE, int DOTS>
 static hipError_t launch_rows(const DevCsr &A, const RowIo &io, const RedArgs &red, int grid,
                               hipStream_t s)
 {
+    if (A.nslices > 0 && A.sell_off4)
+        return launch(k_sell_rows<MODE, DOTS, true>, grid, WG, s, A, io, red);
     if (A.nslices > 0)
-        return launch(k_sell_rows<MODE, DOTS>, grid, WG, s, A, io, red);
+        return launch(k_sell_rows<MODE, DOTS, false>, grid, WG, s, A, io, red);
     return launch(k_csr_rows<MODE, DOTS>, grid, WG, s, A, io, red);
 }
 
@@ -1929,8 +1967,10 @@ hipError_t launch_residual32(const DevCsr &A, const double *b, const double *x, 
 hipError_t launch_spmv32(const DevCsr &A, const float *vals32, const float *v, float *y,
                          const RedArgs &red, int grid, hipStream_t s)
 {
+    if (A.nslices > 0 && A.sell_off4)
+        return launch(k_sell_rows32<true>, grid, WG, s, A, vals32, v, y, red);
     if (A.nslices > 0)
-        return launch(k_sell_rows32, grid, WG, s, A, vals32, v, y, red);
+        return launch(k_sell_rows32<false>, grid, WG, s, A, vals32, v, y, red);
     return launch(k_csr_rows32, grid, WG, s, A, vals32, v, y, red);
 }
 

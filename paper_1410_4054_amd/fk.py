@@ -93,7 +93,7 @@ def lib():
             "fk_csr_destroy": [vp],
             "fk_csr_shape": [vp, P(i64), P(i64)],
             "fk_csr_blocks": [vp, P(i32), P(i32)],
-            "fk_csr_layout": [vp, P(i32), P(i64)],
+            "fk_csr_layout": [vp, P(i32), P(i64), P(i64)],
             "fk_csr_set_layout": [vp, i32, vp],
             "fk_solver_create": [vp, P(_Opts), vp, P(vp)],
             "fk_solve": [vp, vp, vp],
@@ -188,7 +188,7 @@ def status_str(status: int) -> str:
 
 # ------------------------------------------------------------------ matrix
 
-LAYOUTS = {"auto": 0, "row_blocks": 1, "sliced": 2}
+LAYOUTS = {"auto": 0, "row_blocks": 1, "sliced": 2, "sliced16": 3}
 
 
 class Matrix:
@@ -224,9 +224,16 @@ class Matrix:
     def layout(self) -> tuple[str, int]:
         """(layout the products read, entries they read per product)."""
         lay, ent = ctypes.c_int32(), ctypes.c_int64()
-        _check(lib().fk_csr_layout(self._h, ctypes.byref(lay), ctypes.byref(ent)), "fk_csr_layout")
+        _check(lib().fk_csr_layout(self._h, ctypes.byref(lay), ctypes.byref(ent), None), "fk_csr_layout")
         name = {v: k for k, v in LAYOUTS.items()}[lay.value]
         return name, ent.value
+
+    def matrix_bytes(self) -> int:
+        """Bytes of matrix data one FP64 product reads in the current layout."""
+        lay, ent, nb = ctypes.c_int32(), ctypes.c_int64(), ctypes.c_int64()
+        _check(lib().fk_csr_layout(self._h, ctypes.byref(lay), ctypes.byref(ent), ctypes.byref(nb)),
+               "fk_csr_layout")
+        return nb.value
 
     def set_layout(self, layout: str, stream=None):
         if layout not in LAYOUTS:

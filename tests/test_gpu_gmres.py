@@ -43,7 +43,7 @@ def assert_same(res, x, ref, label):
     assert np.array_equal(x, ref.x), (label, rel(x, ref.x))
 
 
-@pytest.mark.parametrize("layout", ["row_blocks", "sliced"])
+@pytest.mark.parametrize("layout", ["row_blocks", "sliced", "sliced16"])
 @pytest.mark.parametrize("m", [5, 30])
 @pytest.mark.parametrize("method", list(METHODS))
 @pytest.mark.parametrize("wl", list(WORKLOADS))

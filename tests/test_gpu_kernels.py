@@ -13,7 +13,7 @@ from paper_1410_4054_amd import fk, problems as P
 pytestmark = pytest.mark.gpu
 
 
-LAYOUTS = ["row_blocks", "sliced"]
+LAYOUTS = ["row_blocks", "sliced", "sliced16"]
 
 
 def check_spmv(A, seed=0, layout=None):
@@ -70,11 +70,28 @@ def test_spmv_ragged_sizes(n, layout, device):
 
 def _slice_entries(A):
     """Entries of the sliced layout, padding included: 64 times the longest
-    row of each run of 64 rows."""
+    row of each run of 64 rows; the longest row; whether every column lies
+    within 32767 of its row."""
     lens = np.diff(A.row_ptr)
     pad = np.zeros(-(-A.n // 64) * 64, dtype=np.int64)
     pad[:A.n] = lens
-    return int(pad.reshape(-1, 64).max(axis=1).sum() * 64), int(lens.max(initial=0))
+    rows = np.repeat(np.arange(A.n), lens)
+    narrow = bool(np.all(np.abs(A.col_idx.astype(np.int64) - rows) <= 32767))
+    return int(pad.reshape(-1, 64).max(axis=1).sum() * 64), int(lens.max(initial=0)), narrow
+
+
+def _matrix_bytes(A, layout):
+    """Bytes of matrix data one FP64 product reads, counted from the CSR."""
+    lens = np.diff(A.row_ptr)
+    pad = np.zeros(-(-A.n // 64) * 64, dtype=np.int64)
+    pad[:A.n] = lens
+    widths = pad.reshape(-1, 64).max(axis=1)
+    slices = widths.size
+    if layout == "row_blocks":
+        return 12 * A.nnz + 4 * (A.n + 1)
+    if layout == "sliced":
+        return 12 * int(widths.sum()) * 64 + 4 * (slices + 1)
+    return 8 * int(widths.sum()) * 64 + 8 * int(((widths + 3) // 4).sum()) * 64 + 8 * (slices + 1)
 
 
 @pytest.mark.parametrize("case", ["poisson3d_17", "convdiff2d_50", "random5", "long_row", "padding",
@@ -93,24 +110,38 @@ def test_layout_rule(case, device):
         A = P.random_csr(6400, 1, seed=2, long_rows={64 * k: 3 for k in range(100)})
     else:
         A = P.Csr(5, np.zeros(6, np.int32), np.zeros(0, np.int32), np.zeros(0))
-    entries, longest = _slice_entries(A)
+    entries, longest, narrow = _slice_entries(A)
     sliced = A.nnz > 0 and longest <= 64 and 4 * entries <= 5 * A.nnz
     assert sliced == (case in ("poisson3d_17", "convdiff2d_50", "random5"))
+    auto = ("sliced16" if narrow else "sliced") if sliced else "row_blocks"
     M = fk.Matrix(A)
-    assert M.layout() == (("sliced", entries) if sliced else ("row_blocks", A.nnz))
+    assert M.layout() == ((auto, entries) if sliced else ("row_blocks", A.nnz))
     M.set_layout("sliced")
     assert M.layout() == ("sliced", entries)
     M.set_layout("row_blocks")
     assert M.layout() == ("row_blocks", A.nnz)
+    assert M.matrix_bytes() == _matrix_bytes(A, "row_blocks")
+    M.set_layout("sliced16")
+    assert M.layout() == ("sliced16", entries)
+    assert M.matrix_bytes() == _matrix_bytes(A, "sliced16")
+    M.set_layout("sliced")
+    assert M.matrix_bytes() == _matrix_bytes(A, "sliced")
     M.set_layout("auto")
-    assert M.layout()[0] == ("sliced" if sliced else "row_blocks")
+    assert M.layout()[0] == auto
 
 
 def test_layout_errors(device):
     A = P.workload("poisson2d_33")[0]
     M = fk.Matrix(A)
-    assert fk.lib().fk_csr_set_layout(M.handle, 3, None) == fk.E_ARG
+    assert fk.lib().fk_csr_set_layout(M.handle, 4, None) == fk.E_ARG
     assert fk.lib().fk_csr_set_layout(None, 1, None) == fk.E_ARG
+    # a column 40000 away from its row: no 16-bit offsets, 32-bit ones work
+    far = P.Csr(40001, np.array([0, 1] + [2] * 40000, np.int32), np.array([40000, 0], np.int32),
+                np.array([1.0, 2.0]))
+    F = fk.Matrix(far, layout="sliced")
+    assert fk.lib().fk_csr_set_layout(F.handle, fk.LAYOUTS["sliced16"], None) == fk.E_ARG
+    assert F.layout()[0] == "sliced"
+    check_spmv(far, layout="sliced")
     S = fk.Solver(M)
     with pytest.raises(fk.FkError) as e:
         M.set_layout("row_blocks")
@@ -134,7 +165,7 @@ def test_spmv_degenerate(device):
     assert blocks[1] == 1
 
 
-@pytest.mark.parametrize("layout", [None, "row_blocks"], ids=["auto", "row_blocks"])
+@pytest.mark.parametrize("layout", [None, "sliced", "row_blocks"], ids=["auto", "sliced", "row_blocks"])
 def test_spmv_full_size_128(layout, device):
     """The 128^3 workload at full size in the launch configuration the
     benchmark uses (the library's own layout choice, sliced), and in row

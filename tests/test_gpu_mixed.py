@@ -71,7 +71,7 @@ def assert_same(res, x, ref, label=""):
     assert np.array_equal(x, ref.x), (label, rel(x, ref.x))
 
 
-@pytest.mark.parametrize("layout", ["row_blocks", "sliced"])
+@pytest.mark.parametrize("layout", ["row_blocks", "sliced", "sliced16"])
 @pytest.mark.parametrize("wl", list(WORKLOADS))
 def test_mixed_matches_oracle(wl, layout, device):
     A, b, x0 = WORKLOADS[wl]()

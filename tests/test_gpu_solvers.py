@@ -45,8 +45,9 @@ def assert_same_run(res, x, ref, label=""):
     assert rel(x, ref.x) <= 1e-10, (label, rel(x, ref.x))
 
 
-@pytest.mark.parametrize("small,layout", [(True, None), (False, "row_blocks"), (False, "sliced")],
-                         ids=["auto", "grid-row_blocks", "grid-sliced"])
+@pytest.mark.parametrize("small,layout", [(True, None), (False, "row_blocks"), (False, "sliced"),
+                                         (False, "sliced16")],
+                         ids=["auto", "grid-row_blocks", "grid-sliced", "grid-sliced16"])
 @pytest.mark.parametrize("wl,method", CASES, ids=[f"{w}-{m}" for w, m in CASES])
 def test_matches_oracle(wl, method, small, layout, device):
     """small=True lets the library take its single-workgroup solver where it
