@@ -462,8 +462,9 @@ def main():
                    "iterations_per_solve": k_final, "final_rel_residual": rel},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
                      "frac": achieved / PEAK_HBM_GBS, "traffic": traffic,
-                     "kernel": "fused SpMV + <p,Ap>, <Ap,Ap> ("
-                               + ("k_sell_rows<0,3>" if layout == "sliced" else "k_csr_rows<0,3>") + ")",
+                     "kernel": "fused SpMV + <p,Ap>, <Ap,Ap> (" + {
+                         "sliced16": "k_sell_rows<0,3,true>", "sliced": "k_sell_rows<0,3,false>",
+                         "row_blocks": "k_csr_rows<0,3>"}[layout] + ")",
                      "layout": layout,
                      "bytes_per_launch": spmv_b, "avg_us": spmv_us,
                      "update_dot_avg_us": upd_us},
