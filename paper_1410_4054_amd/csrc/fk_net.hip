@@ -563,25 +563,30 @@ __global__ __launch_bounds__(NWG) void k_check(DevCsr A, const double *b, const 
     }
 }
 
-// Fallback: keep x0 unless its residual is larger than that of u_m (or not
-// finite); then x0 = u_m.  One workgroup; flag[0] = 1 when it fell back.
-__global__ __launch_bounds__(NWG) void k_select(int nparts, const double *partials, int64_t n,
-                                                const double *um, double *x0, int32_t *flag)
+// Fallback decision: flag[0] = 1 when the residual of x0 is larger than
+// that of u_m (or not finite).  One workgroup sums the partials of k_check,
+// thread t taking partials t, t + NWG, ..., then a fixed tree.
+__global__ __launch_bounds__(NWG) void k_select(int nparts, const double *partials, int32_t *flag)
 {
-    __shared__ int s_fb;
-    if (threadIdx.x == 0) {
-        double r0 = 0.0, r1 = 0.0;
-        for (int w = 0; w < nparts; ++w) {
-            r0 += partials[2 * w];
-            r1 += partials[2 * w + 1];
-        }
-        s_fb = (!(r0 <= r1)) ? 1 : 0;
-        *flag = s_fb;
+    __shared__ double lds[NWG];
+    double a0 = 0.0, a1 = 0.0;
+    for (int w = threadIdx.x; w < nparts; w += NWG) {
+        a0 += partials[2 * w];
+        a1 += partials[2 * w + 1];
     }
-    __syncthreads();
-    if (!s_fb)
+    const double r0 = wg_sum(a0, lds);
+    const double r1 = wg_sum(a1, lds);
+    if (threadIdx.x == 0)
+        *flag = (!(r0 <= r1)) ? 1 : 0;
+}
+
+// x0 = u_m where k_select fell back; returns at once otherwise.
+__global__ __launch_bounds__(NWG) void k_fallback(int64_t n, const int32_t *flag, const double *um,
+                                                  double *x0)
+{
+    if (*flag == 0)
         return;
-    for (int64_t i = threadIdx.x; i < n; i += NWG)
+    for (int64_t i = (int64_t)blockIdx.x * NWG + threadIdx.x; i < n; i += (int64_t)gridDim.x * NWG)
         x0[i] = um[i];
 }
 
@@ -980,7 +985,8 @@ extern "C" fk_status fk_net_guess(fk_net N, fk_csr Ah, int32_t nx, int32_t ny, c
     NET_HIP(hipGetLastError());
     const int gr = grid_for(n, NWG, RED_GRID);
     hipLaunchKernelGGL(k_check, dim3(gr), dim3(NWG), 0, s, A, b, x0, um, N->redpart);
-    hipLaunchKernelGGL(k_select, dim3(1), dim3(NWG), 0, s, gr, N->redpart, n, um, x0, N->flag);
+    hipLaunchKernelGGL(k_select, dim3(1), dim3(NWG), 0, s, gr, N->redpart, N->flag);
+    hipLaunchKernelGGL(k_fallback, dim3(gr), dim3(NWG), 0, s, n, N->flag, um, x0);
     NET_HIP(hipGetLastError());
     if (fallback) {
         NET_HIP(hipMemcpyAsync(fallback, N->flag, 4, hipMemcpyDeviceToHost, s));
