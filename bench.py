@@ -312,6 +312,90 @@ def main():
             extras[f"{method}_convdiff2d_1024_m30_us_per_iter"] = float(np.median(times[1:])) / 60 * 1e6
         M3g.close()
 
+        log("[bench] extras: 192^3, a working set beyond the Infinity Cache")
+        # SURVEY's HBM-true point: 192^3 (N = 7.08M) moves ~0.9 GB per
+        # iteration, far above the 256 MB Infinity Cache.  100 fixed
+        # iterations per solve.
+        A5, b5, _ = P.workload("poisson3d_192")
+        M5 = fk.Matrix(A5)
+        lay5, ent5 = M5.layout()
+        b5d = torch.as_tensor(b5, device="cuda")
+        x5d = torch.zeros_like(b5d)
+        S5 = fk.Solver(M5, method="cg_pipelined", rtol=0.0, max_iter=100, record_history=False)
+        x5d.zero_(); S5.solve(b5d, x5d)
+        t5, its5 = time_solves(torch, S5, b5d, x5d, 3)
+        S5.close()
+        S5 = fk.Solver(M5, method="cg_pipelined", rtol=0.0, max_iter=100, record_history=False, profile=True)
+        x5d.zero_(); S5.solve(b5d, x5d)
+        kt5 = S5.kernel_times()
+        S5.close()
+        csr5 = csr_spmv_dot_bytes(A5.n, A5.nnz) + update_bytes(A5.n)
+        lay5_b = spmv_dot_bytes(A5.n, M5.matrix_bytes()) + update_bytes(A5.n)
+        extras["poisson3d_192_layout"] = lay5
+        extras["poisson3d_192_iters_per_s"] = its5 / t5
+        extras["poisson3d_192_spmv_dot_us"] = kt5["spmv_dot"][0]
+        extras["poisson3d_192_update_dot_us"] = kt5["update_dot"][0]
+        extras["poisson3d_192_iteration_frac_of_peak"] = csr5 * its5 / t5 / 1e9 / PEAK_HBM_GBS
+        extras["poisson3d_192_iteration_layout_frac_of_peak"] = lay5_b * its5 / t5 / 1e9 / PEAK_HBM_GBS
+        M5.close()
+        del A5, b5, b5d, x5d
+
+        log("[bench] extras: size sweep, 2D Poisson n^2, n = 15 .. 511")
+        # The x-axis of the paper's Fig. 4: time per iteration (median of 10
+        # runs of 30 fixed iterations) of the pipelined and classical
+        # methods.  Pipelined solves of up to 8192 (CG) / 2048 (BiCGStab)
+        # unknowns run in the single-workgroup kernel.
+        sweep = {}
+        for nn in (15, 31, 63, 127, 255, 511):
+            As, bs, _ = P.workload(f"poisson2d_{nn}")
+            Ms = fk.Matrix(As)
+            bsd = torch.as_tensor(bs, device="cuda")
+            xsd = torch.zeros_like(bsd)
+            row = {}
+            for method in ("cg_pipelined", "cg_classical", "bicgstab_pipelined", "bicgstab_classical"):
+                Ssw = fk.Solver(Ms, method=method, rtol=0.0, max_iter=30, record_history=False)
+                times = []
+                for _ in range(11):
+                    xsd.zero_()
+                    torch.cuda.synchronize()
+                    t = time.perf_counter()
+                    Ssw.solve(bsd, xsd)
+                    torch.cuda.synchronize()
+                    times.append(time.perf_counter() - t)
+                Ssw.close()
+                row[method] = float(np.median(times[1:])) / 30 * 1e6
+            Ms.close()
+            sweep[str(nn * nn)] = row
+        extras["poisson2d_size_sweep_us_per_iter_30fixed_median10"] = sweep
+
+        log("[bench] extras: fused vs unfused SpMV + dot, random 4 and 28 nonzeros per row")
+        # The kernel-fusion example of Section 2.2: q = A p and <p, q> with
+        # the result on the host, as one fused launch or as a product then a
+        # dot; median of 20 calls.
+        fusion = {}
+        for k in (4, 28):
+            for nrow in (1000, 10000, 100000, 1000000):
+                Ar = P.random_csr(nrow, k, seed=k)
+                Mr = fk.Matrix(Ar)
+                pr = torch.rand(nrow, dtype=torch.float64, device="cuda")
+                qr = torch.zeros_like(pr)
+                res = {}
+                for label in ("fused", "unfused"):
+                    times = []
+                    for rep in range(23):
+                        torch.cuda.synchronize()
+                        t = time.perf_counter()
+                        if label == "fused":
+                            fk.spmv(Mr, pr, qr, dots=True)
+                        else:
+                            fk.spmv(Mr, pr, qr)
+                            fk.dot(pr, qr)
+                        times.append(time.perf_counter() - t)
+                    res[label + "_us"] = float(np.median(times[3:])) * 1e6
+                Mr.close()
+                fusion[f"{k}nnz_n{nrow}"] = res
+        extras["spmv_dot_fusion_host_result"] = fusion
+
         log("[bench] extras: mixed precision 128^3")
         # Mixed precision: FP64 iterative refinement around FP32 pipelined CG
         # against FP64 pipelined CG, both to 1e-10 on 128^3.

@@ -50,8 +50,9 @@ class Csr:
 
 
 def _from_coo(n: int, rows: np.ndarray, cols: np.ndarray, vals: np.ndarray) -> Csr:
-    """Sort (row, col) pairs and pack them as CSR; duplicates are kept as-is."""
-    order = np.lexsort((cols, rows))
+    """Sort (row, col) pairs and pack them as CSR; duplicates are kept as-is
+    (in their input order: a stable sort on the key row * n + col)."""
+    order = np.argsort(rows.astype(np.int64) * n + cols.astype(np.int64), kind="stable")
     rows, cols, vals = rows[order], cols[order], vals[order]
     counts = np.bincount(rows, minlength=n)
     row_ptr = np.zeros(n + 1, dtype=np.int64)
