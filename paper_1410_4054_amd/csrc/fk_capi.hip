@@ -969,9 +969,11 @@ hipError_t enqueue_iteration(fk_solver S, Enq &q, double *x, bool last)
     case FK_BICGSTAB_PIPELINED:
         ENQ(FK_KERNEL_SPMV_DOT, launch_spmv_dots(A, S->p, S->ap, S->rs, D_YW,
                                                  S->red(FIN_B_ALPHA, RUN_ACTIVE), gs, st));
-        ENQ(FK_KERNEL_UPDATE_DOT, launch_bicg_s(n, S->r, S->ap, S->s, S->red(FIN_B_SS, RUN_ACTIVE), gv, st));
+        // s update publishes <s,s>; the product A s completes it with its
+        // own three dots (half-step test, then omega and beta).
+        ENQ(FK_KERNEL_UPDATE_DOT, launch_bicg_s(n, S->r, S->ap, S->s, S->red(FIN_PUBLISH, RUN_ACTIVE), gv, st));
         ENQ(FK_KERNEL_SPMV_DOT, launch_spmv_dots(A, S->s, S->as, S->rs, D_YV | D_YY | D_YW,
-                                                 S->red(FIN_B_OMEGA, RUN_ACTIVE), gs, st));
+                                                 S->red_fold(FIN_B_SS_OMEGA, RUN_ACTIVE, gv, 1), gs, st));
         ENQ(FK_KERNEL_UPDATE_DOT, launch_bicg_xrp(n, x, S->r, S->p, S->s, S->as, S->ap, S->rs,
                                                   S->red(FIN_B_XRP, RUN_ACTIVE_OR_HALF), gv, st));
         break;

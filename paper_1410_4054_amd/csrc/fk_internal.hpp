@@ -103,6 +103,8 @@ enum Fin : int32_t {
                         // next reduction point to fold in (no second stage here)
     FIN_CG_RR_ALPHA,    // d = {<p_i,Ap_i>, <Ap_i,Ap_i>, <r_i,r_i>} (the last one
                         // published by the update): FIN_CG_RR, then FIN_CG_ALPHA
+    FIN_B_SS_OMEGA,     // d = {<As,s>, <As,As>, <As,r0*>, <s,s>} (the last one
+                        // published by the s update): FIN_B_SS, then FIN_B_OMEGA
 };
 
 // Everything a reduction point needs.

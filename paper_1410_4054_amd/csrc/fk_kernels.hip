@@ -193,6 +193,24 @@ __device__ void cg_rr(DevState *st, double rr, double *hist, double *scal)
         st->status = ST_NOT_CONVERGED;
 }
 
+// Algorithm 4: omega_i = <As,s>/<As,As>, beta_i = -<As,r0*>/<Ap,r0*> (the
+// form of Section 3.2), and <r_{i+1}, r_{i+1}> expanded in <s,s>, <s,As>,
+// <As,As>.
+__device__ void b_omega(DevState *st, double ass, double asas, double asr, double *scal)
+{
+    if (asas == 0.0 || !isfinite(asas) || !isfinite(ass) || !isfinite(asr)) {
+        st->status = ST_BREAKDOWN;
+        return;
+    }
+    const double beta = -asr / st->apr;  // via <s_i, r0*> = 0
+    const double omega = ass / asas;
+    st->beta = beta;
+    st->omega = omega;
+    st->rr_next = st->ss - 2.0 * omega * ass + omega * omega * asas;
+    put_scal(st, scal, st->it, 1, beta);
+    put_scal(st, scal, st->it, 2, omega);
+}
+
 __device__ void finalize(DevState *st, int fin, const double *d, int K, double *hist, double *scal)
 {
     for (int k = 0; k < K; ++k)
@@ -255,22 +273,19 @@ __device__ void finalize(DevState *st, int fin, const double *d, int K, double *
             st->status = ST_HALF;
         break;
     }
-    case FIN_B_OMEGA: {  // Algorithm 4: d = {<As,s>, <As,As>, <As,r0*>}
-        const double ass = d[0], asas = d[1], asr = d[2];
-        if (asas == 0.0 || !isfinite(asas) || !isfinite(ass) || !isfinite(asr)) {
-            st->status = ST_BREAKDOWN;
+    case FIN_B_OMEGA:  // Algorithm 4: d = {<As,s>, <As,As>, <As,r0*>}
+        b_omega(st, d[0], d[1], d[2], scal);
+        break;
+    case FIN_B_SS_OMEGA:  // d = {<As,s>, <As,As>, <As,r0*>, <s,s>}
+        // The half-step test on s_i first, as when <s_i,s_i> is reduced on
+        // its own; omega, beta only while still running.
+        st->ss = d[3];
+        if (sqrt(d[3]) <= st->tol) {
+            st->status = ST_HALF;
             break;
         }
-        const double beta = -asr / st->apr;   // via <s_i, r0*> = 0
-        const double omega = ass / asas;
-        st->beta = beta;
-        st->omega = omega;
-        // <r_{i+1}, r_{i+1}> expanded in <s,s>, <s,As>, <As,As>
-        st->rr_next = st->ss - 2.0 * omega * ass + omega * omega * asas;
-        put_scal(st, scal, st->it, 1, beta);
-        put_scal(st, scal, st->it, 2, omega);
+        b_omega(st, d[0], d[1], d[2], scal);
         break;
-    }
     case FIN_B_XRP: {  // Algorithm 4: d = {<r_{i+1}, r0*>, <r_{i+1}, r_{i+1}>}
         const int it = st->it + 1;
         st->it = it;
@@ -538,7 +553,7 @@ __device__ __forceinline__ void reduce_point(dd (&v)[K], const RedArgs &red, int
     if (!s_flag)
         return;
 
-    constexpr int KP = (K + KPUB <= KMAX) ? KPUB : 0;
+    constexpr int KP = (K + KPUB <= KMAX) ? KPUB : KMAX - K;
     constexpr int KT = K + KP;
     const int kpub = KP > 0 ? red.kpub : 0;
     const int kt = K + kpub;
