@@ -967,15 +967,17 @@ hipError_t enqueue_iteration(fk_solver S, Enq &q, double *x, bool last)
             ENQ(FK_KERNEL_AXPY, launch_xpay(n, S->p, S->r, nullptr, ds, RUN_ACTIVE, gv, st));
         break;
     case FK_BICGSTAB_PIPELINED:
+        // The product A p also completes the previous update's <r,r0*>,
+        // <r,r> (rho_i), then alpha_i.
         ENQ(FK_KERNEL_SPMV_DOT, launch_spmv_dots(A, S->p, S->ap, S->rs, D_YW,
-                                                 S->red(FIN_B_ALPHA, RUN_ACTIVE), gs, st));
+                                                 S->red_fold(FIN_B_RHO_ALPHA, RUN_ACTIVE, gv, 2), gs, st));
         // s update publishes <s,s>; the product A s completes it with its
         // own three dots (half-step test, then omega and beta).
         ENQ(FK_KERNEL_UPDATE_DOT, launch_bicg_s(n, S->r, S->ap, S->s, S->red(FIN_PUBLISH, RUN_ACTIVE), gv, st));
         ENQ(FK_KERNEL_SPMV_DOT, launch_spmv_dots(A, S->s, S->as, S->rs, D_YV | D_YY | D_YW,
                                                  S->red_fold(FIN_B_SS_OMEGA, RUN_ACTIVE, gv, 1), gs, st));
         ENQ(FK_KERNEL_UPDATE_DOT, launch_bicg_xrp(n, x, S->r, S->p, S->s, S->as, S->ap, S->rs,
-                                                  S->red(FIN_B_XRP, RUN_ACTIVE_OR_HALF), gv, st));
+                                                  S->red(FIN_B_XRP_PUB, RUN_BICG_UPDATE), gv, st));
         break;
     case FK_BICGSTAB_CLASSICAL:
         ENQ(FK_KERNEL_SPMV, launch_spmv_dots(A, S->p, S->ap, nullptr, 0, S->red(FIN_NONE, RUN_ACTIVE), gs, st));

@@ -50,11 +50,19 @@ enum DevStatus : int32_t {
     ST_BREAKDOWN = 4,
     ST_ZERO_RHS = 5,      // b = 0: x = 0, k = 0
     ST_CYCLE_DONE = 6,    // GMRES: the current restart cycle has ended
+    // Pipelined BiCGStab: iteration i+1 is decided (converged, budget used
+    // up, breakdown after the step), its x, r, p update still to run; that
+    // update then sets the matching final state.
+    ST_FINAL_CONVERGED = 7,
+    ST_FINAL_NOT_CONVERGED = 8,
+    ST_FINAL_BREAKDOWN = 9,
 };
 
 constexpr uint32_t RUN_ACTIVE = 1u << ST_RUNNING;
 constexpr uint32_t RUN_ACTIVE_OR_HALF = (1u << ST_RUNNING) | (1u << ST_HALF);
 constexpr uint32_t RUN_HALF = 1u << ST_HALF;
+constexpr uint32_t RUN_BICG_UPDATE = RUN_ACTIVE_OR_HALF | (1u << ST_FINAL_CONVERGED) |
+                                     (1u << ST_FINAL_NOT_CONVERGED) | (1u << ST_FINAL_BREAKDOWN);
 constexpr uint32_t RUN_ALWAYS = 0xffffffffu;
 
 struct alignas(128) DevState {
@@ -75,7 +83,8 @@ struct alignas(128) DevState {
     int32_t hist_cap; // entries of hist / 4-tuples of scal available
     int32_t gi;       // GMRES: step of the current cycle (1-based, next to do)
     int32_t gm;       // GMRES: restart length m
-    uint32_t pad[2];
+    int32_t rho_pub;  // BiCGStab: <r,r0*>, <r,r> published by the last update
+    uint32_t pad;
 };
 
 // What the last workgroup does with the reduced inner products.
@@ -104,7 +113,12 @@ enum Fin : int32_t {
     FIN_CG_RR_ALPHA,    // d = {<p_i,Ap_i>, <Ap_i,Ap_i>, <r_i,r_i>} (the last one
                         // published by the update): FIN_CG_RR, then FIN_CG_ALPHA
     FIN_B_SS_OMEGA,     // d = {<As,s>, <As,As>, <As,r0*>, <s,s>} (the last one
-                        // published by the s update): FIN_B_SS, then FIN_B_OMEGA
+                        // published by the s update): FIN_B_SS, then FIN_B_OMEGA,
+                        // then the convergence decision on the expanded rr
+    FIN_B_RHO_ALPHA,    // d = {<Ap,r0*>, <r,r0*>, <r,r>} (the last two published by
+                        // the previous update, if any): rho, then FIN_B_ALPHA
+    FIN_B_XRP_PUB,      // the x, r, p update: publishes <r,r0*>, <r,r> while the
+                        // solve runs; after a decision, finalizes (FIN_B_XRP role)
 };
 
 // Everything a reduction point needs.

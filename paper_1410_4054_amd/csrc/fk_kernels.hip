@@ -196,6 +196,19 @@ __device__ void cg_rr(DevState *st, double rr, double *hist, double *scal)
 // Algorithm 4: omega_i = <As,s>/<As,As>, beta_i = -<As,r0*>/<Ap,r0*> (the
 // form of Section 3.2), and <r_{i+1}, r_{i+1}> expanded in <s,s>, <s,As>,
 // <As,As>.
+// Algorithms 3/4: alpha_i = rho_i / <Ap_i, r0*>.
+__device__ void b_alpha(DevState *st, double apr, double *scal)
+{
+    const double rho = st->rho;
+    if (apr == 0.0 || !isfinite(apr) || rho == 0.0 || !isfinite(rho)) {
+        st->status = ST_BREAKDOWN;
+        return;
+    }
+    st->apr = apr;
+    st->alpha = rho / apr;
+    put_scal(st, scal, st->it, 0, st->alpha);
+}
+
 __device__ void b_omega(DevState *st, double ass, double asas, double asr, double *scal)
 {
     if (asas == 0.0 || !isfinite(asas) || !isfinite(ass) || !isfinite(asr)) {
@@ -221,6 +234,7 @@ __device__ void finalize(DevState *st, int fin, const double *d, int K, double *
     case FIN_SETUP: {  // d = {<r0,r0>, <b,b>}
         const double rr = d[0], bb = d[1];
         st->it = 0;
+        st->rho_pub = 0;
         st->rr = rr;
         st->rho = rr;  // r0* = r0, so <r0, r0*> = <r0, r0>
         if (bb == 0.0) {
@@ -256,17 +270,19 @@ __device__ void finalize(DevState *st, int fin, const double *d, int K, double *
         if (st->status == ST_RUNNING)
             cg_alpha(st, d[0], d[1], scal);
         break;
-    case FIN_B_ALPHA: {  // Algorithms 3/4: d = {<Ap_i, r0*>}
-        const double apr = d[0], rho = st->rho;
-        if (apr == 0.0 || !isfinite(apr) || rho == 0.0 || !isfinite(rho)) {
-            st->status = ST_BREAKDOWN;
-            break;
-        }
-        st->apr = apr;
-        st->alpha = rho / apr;
-        put_scal(st, scal, st->it, 0, st->alpha);
+    case FIN_B_ALPHA:  // Algorithms 3/4: d = {<Ap_i, r0*>}
+        b_alpha(st, d[0], scal);
         break;
-    }
+    case FIN_B_RHO_ALPHA:  // d = {<Ap_i, r0*>, <r_i, r0*>, <r_i, r_i>}
+        // rho_i and the direct <r_i,r_i> come from the update's published
+        // partials, except in the first iteration (rho_0 from the setup).
+        if (st->rho_pub) {
+            st->rho = d[1];
+            st->rr = d[2];
+            st->rho_pub = 0;
+        }
+        b_alpha(st, d[0], scal);
+        break;
     case FIN_B_SS: {  // d = {<s_i, s_i>}: half-step test
         st->ss = d[0];
         if (sqrt(d[0]) <= st->tol)
@@ -276,15 +292,53 @@ __device__ void finalize(DevState *st, int fin, const double *d, int K, double *
     case FIN_B_OMEGA:  // Algorithm 4: d = {<As,s>, <As,As>, <As,r0*>}
         b_omega(st, d[0], d[1], d[2], scal);
         break;
-    case FIN_B_SS_OMEGA:  // d = {<As,s>, <As,As>, <As,r0*>, <s,s>}
+    case FIN_B_SS_OMEGA: {  // d = {<As,s>, <As,As>, <As,r0*>, <s,s>}
         // The half-step test on s_i first, as when <s_i,s_i> is reduced on
-        // its own; omega, beta only while still running.
+        // its own; omega, beta only while still running.  The decision on
+        // iteration i+1 needs only the expanded <r_{i+1}, r_{i+1}> and omega,
+        // so it is taken here; the x, r, p update still runs after it.
         st->ss = d[3];
         if (sqrt(d[3]) <= st->tol) {
             st->status = ST_HALF;
             break;
         }
         b_omega(st, d[0], d[1], d[2], scal);
+        if (st->status != ST_RUNNING)
+            break;
+        const int it = st->it + 1;
+        st->it = it;
+        const double rr_next = st->rr_next;
+        const double rnorm = sqrt(rr_next > 0.0 ? rr_next : 0.0);
+        const double rel = rnorm / st->bnorm;
+        st->last_rel = rel;
+        put_hist(st, hist, it, rel);
+        put_scal(st, scal, it - 1, 3, rr_next);
+        if (!isfinite(rr_next))
+            st->status = ST_FINAL_BREAKDOWN;
+        else if (rnorm <= st->tol)
+            st->status = ST_FINAL_CONVERGED;
+        else if (st->omega == 0.0)
+            st->status = ST_FINAL_BREAKDOWN;
+        else if (it >= st->max_iter)
+            st->status = ST_FINAL_NOT_CONVERGED;
+        break;
+    }
+    case FIN_B_XRP_PUB:  // the update after a decision: d = {<r,r0*>, <r,r>}
+        if (st->status == ST_HALF) {
+            const int it = st->it + 1;
+            st->it = it;
+            const double rel = sqrt(st->ss) / st->bnorm;
+            st->last_rel = rel;
+            put_hist(st, hist, it, rel);
+            put_scal(st, scal, it - 1, 3, st->ss);
+            st->status = ST_CONVERGED;
+            break;
+        }
+        st->rho = d[0];
+        st->rr = d[1];
+        st->status = st->status == ST_FINAL_CONVERGED       ? ST_CONVERGED
+                     : st->status == ST_FINAL_NOT_CONVERGED ? ST_NOT_CONVERGED
+                                                            : ST_BREAKDOWN;
         break;
     case FIN_B_XRP: {  // Algorithm 4: d = {<r_{i+1}, r0*>, <r_{i+1}, r_{i+1}>}
         const int it = st->it + 1;
@@ -914,8 +968,9 @@ __global__ __launch_bounds__(WG, FK_SPMV_MIN_WAVES) void k_sell_rows(DevCsr A, R
         }
         const SliceCols<NARROW> cols{A.sell_col + e0 + lane,
                                      NARROW ? A.sell_off4 + A.sell_ptr4[sl] + lane : nullptr, row};
-        // (Three double-double accumulators leave room for fewer entries.)
-        const double q = slice_row_sum<double, (KA >= 3 ? FK_SELL_UNROLL / 2 : FK_SELL_UNROLL), NARROW>(
+        // (With int32 columns, three double-double accumulators leave room
+        // for fewer entries in 64 VGPRs.)
+        const double q = slice_row_sum<double, (KA >= 3 && !NARROW ? FK_SELL_UNROLL / 2 : FK_SELL_UNROLL), NARROW>(
             cols, A.sell_vals + e0 + lane, io.v, width);
         if (live) {
             if constexpr (K > 0)
@@ -999,10 +1054,20 @@ __global__ __launch_bounds__(WG) void k_bicg_xrp(int64_t n, double *__restrict__
 {
     if (!runs(red))
         return;
-    const bool half = red.st->status == ST_HALF;
+    const int32_t status = red.st->status;
+    const bool half = status == ST_HALF;
     const double alpha = red.st->alpha;
     const double omega = red.st->omega;
     const double beta = red.st->beta;
+    // While the solve runs, <r,r0*>, <r,r> are published for the next
+    // product's reduction (FIN_B_RHO_ALPHA); after a decision (half step or
+    // iteration i+1 decided) this launch finishes the solve itself.
+    RedArgs rd = red;
+    if (red.fin == FIN_B_XRP_PUB && status == ST_RUNNING) {
+        rd.fin = FIN_PUBLISH;
+        if (blockIdx.x == 0 && threadIdx.x == 0)
+            red.st->rho_pub = 1;
+    }
     dd acc[2] = {dd{0.0, 0.0}, dd{0.0, 0.0}};
     const int64_t stride = (int64_t)gridDim.x * WG;
     if (half) {
@@ -1023,7 +1088,7 @@ __global__ __launch_bounds__(WG) void k_bicg_xrp(int64_t n, double *__restrict__
             dd_fma(acc[1], ri, ri);
         }
     }
-    reduce_point<2>(acc, red, blockIdx.x, gridDim.x);
+    reduce_point<2>(acc, rd, blockIdx.x, gridDim.x);
 }
 
 // ------------------------------------------- classical building blocks
