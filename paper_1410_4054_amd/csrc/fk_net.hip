@@ -169,6 +169,75 @@ __global__ __launch_bounds__(NWG) void k_conv(ConvArgs a)
 }
 
 
+// ------------------------------------------------------ residual rows
+
+// Nonzeros of a row requested together (with their gathers) before the
+// first is added; the sum itself runs left to right in CSR order.
+constexpr int RB = 8;
+
+// sum_j a_ij (ca xa_c + cb xb_c) over row i, left to right.
+__device__ __forceinline__ double row_base(const DevCsr &A, int64_t i, const double *xa, const double *xb,
+                                           double ca, double cb)
+{
+    const int32_t j0 = A.row_ptr[i], j1 = A.row_ptr[i + 1];
+    double q = 0.0;
+    for (int32_t j = j0; j < j1; j += RB) {
+        int32_t c[RB];
+        double v[RB], g[RB];
+#pragma unroll
+        for (int k = 0; k < RB; ++k) {
+            c[k] = 0;
+            v[k] = 0.0;
+            if (j + k < j1) {
+                c[k] = A.col_idx[j + k];
+                v[k] = A.vals[j + k];
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < RB; ++k)
+            g[k] = j + k < j1 ? ca * xa[c[k]] + cb * xb[c[k]] : 0.0;
+#pragma unroll
+        for (int k = 0; k < RB; ++k)
+            if (j + k < j1)
+                q = q + v[k] * g[k];
+    }
+    return q;
+}
+
+// (sum_j a_ij x_c, sum_j a_ij y_c) over row i, each left to right.
+__device__ __forceinline__ void row_dot2(const DevCsr &A, int64_t i, const double *x, const double *y,
+                                         double &qx, double &qy)
+{
+    const int32_t j0 = A.row_ptr[i], j1 = A.row_ptr[i + 1];
+    qx = 0.0;
+    qy = 0.0;
+    for (int32_t j = j0; j < j1; j += RB) {
+        int32_t c[RB];
+        double v[RB], gx[RB], gy[RB];
+#pragma unroll
+        for (int k = 0; k < RB; ++k) {
+            c[k] = 0;
+            v[k] = 0.0;
+            if (j + k < j1) {
+                c[k] = A.col_idx[j + k];
+                v[k] = A.vals[j + k];
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < RB; ++k) {
+            gx[k] = j + k < j1 ? x[c[k]] : 0.0;
+            gy[k] = j + k < j1 ? y[c[k]] : 0.0;
+        }
+#pragma unroll
+        for (int k = 0; k < RB; ++k) {
+            if (j + k < j1) {
+                qx = qx + v[k] * gx[k];
+                qy = qy + v[k] * gy[k];
+            }
+        }
+    }
+}
+
 // ------------------------------------------------ fused inference (one pass)
 
 // One pass x_out = base + N(b - A base), base = ca xa + cb xb, in one launch.
@@ -201,10 +270,15 @@ inline size_t fused_lds_bytes(int L)
     return (size_t)fused_region(L) * 8 + 2 * (size_t)fused_region(L - 1) * 32;
 }
 
-// One layer in LDS: input region of halo h+1 (CINP channels), output region
-// of halo h.  LAST: write base + acc to xout on the tile.
+// The workgroup's dynamic LDS.  Activations are addressed by offsets into
+// it (not by pointers), so every access compiles to ds_read / ds_write.
+extern __shared__ __align__(16) uint16_t fused_lds[];
+
+// One layer in LDS: input region of halo h+1 (CINP channels) at element
+// offset in_off, output region of halo h at out_off.  LAST: write base + acc
+// to xout on the tile.
 template <int CINP, bool LAST>
-__device__ __forceinline__ void fused_layer(const FusedArgs &a, const uint16_t *in, uint16_t *out, int h,
+__device__ __forceinline__ void fused_layer(const FusedArgs &a, int in_off, int out_off, int h,
                                             const bf16x4 *w, int gx0, int gy0)
 {
     constexpr int J = (9 * CINP + 15) / 16;
@@ -235,8 +309,8 @@ __device__ __forceinline__ void fused_layer(const FusedArgs &a, const uint16_t *
             }
             bf16x4 bv = {0, 0, 0, 0};
             if (tap < 9 && valid) {
-                const int ix = qx + (tap % 3), iy = qy + (tap / 3);  // input region has halo h+1
-                bv = *reinterpret_cast<const bf16x4 *>(in + ((size_t)iy * Wi + ix) * CINP + c0);
+                const int ix = qx + (tap % 3), iy = qy + (tap / 3);
+                bv = *reinterpret_cast<const bf16x4 *>(&fused_lds[in_off + (iy * Wi + ix) * CINP + c0]);
             }
             acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(wr[j], bv, acc, 0, 0, 0);
         }
@@ -256,21 +330,19 @@ __device__ __forceinline__ void fused_layer(const FusedArgs &a, const uint16_t *
                 for (int i = 0; i < 4; ++i)
                     o[i] = (short)f2bf((!a.relu || acc[i] > 0.f) ? acc[i] : 0.f);
             }
-            *reinterpret_cast<bf16x4 *>(out + (size_t)q * 16 + 4 * grp) = o;
+            *reinterpret_cast<bf16x4 *>(&fused_lds[out_off + q * 16 + 4 * grp]) = o;
         }
     }
 }
 
 __global__ __launch_bounds__(FWAVES * 64) void k_net_fused(FusedArgs a)
 {
-    extern __shared__ __align__(16) uint16_t lds[];
     const int L = a.layers;
     const int tiles_x = (a.nx + FTX - 1) / FTX;
     const int gx0 = (int)(blockIdx.x % tiles_x) * FTX;
     const int gy0 = (int)(blockIdx.x / tiles_x) * FTY;
-    uint16_t *rplane = lds;
-    uint16_t *buf[2] = {lds + (size_t)fused_region(L) * 4,
-                        lds + (size_t)fused_region(L) * 4 + (size_t)fused_region(L - 1) * 16};
+    // r plane at element 0, then two 16-channel buffers
+    const int buf[2] = {fused_region(L) * 4, fused_region(L) * 4 + fused_region(L - 1) * 16};
     // r = b - A base on the halo-L region (zeros outside the grid)
     const int Wr = FTX + 2 * L, Hr = FTY + 2 * L;
     for (int q = threadIdx.x; q < Wr * Hr; q += FWAVES * 64) {
@@ -278,23 +350,19 @@ __global__ __launch_bounds__(FWAVES * 64) void k_net_fused(FusedArgs a)
         bf16x4 o = {0, 0, 0, 0};
         if (gx >= 0 && gx < a.nx && gy >= 0 && gy < a.ny) {
             const int64_t i = (int64_t)gy * a.nx + gx;
-            double acc = 0.0;
-            for (int32_t j = a.A.row_ptr[i]; j < a.A.row_ptr[i + 1]; ++j) {
-                const int32_t c = a.A.col_idx[j];
-                acc = acc + a.A.vals[j] * (a.ca * a.xa[c] + a.cb * a.xb[c]);
-            }
+            const double acc = row_base(a.A, i, a.xa, a.xb, a.ca, a.cb);
             o[0] = (short)f2bf((float)(a.b[i] - acc));
         }
-        *reinterpret_cast<bf16x4 *>(rplane + (size_t)q * 4) = o;
+        *reinterpret_cast<bf16x4 *>(&fused_lds[q * 4]) = o;
     }
     __syncthreads();
-    const uint16_t *in = rplane;
+    int in = 0;
     for (int l = 0; l < L; ++l) {
         const int h = L - 1 - l;
-        uint16_t *out = buf[l & 1];
+        const int out = buf[l & 1];
         const bf16x4 *w = a.w + a.pf[l];
         if (l == L - 1)
-            fused_layer<16, true>(a, in, nullptr, h, w, gx0, gy0);
+            fused_layer<16, true>(a, in, 0, h, w, gx0, gy0);
         else if (l == 0)
             fused_layer<4, false>(a, in, out, h, w, gx0, gy0);
         else
@@ -465,12 +533,7 @@ __global__ __launch_bounds__(NWG) void k_features(DevCsr A, const double *b, con
         if constexpr (MODE == FEAT_NORM) {
             r = rbuf[i];
         } else {
-            double q = 0.0;
-            for (int32_t j = A.row_ptr[i]; j < A.row_ptr[i + 1]; ++j) {
-                const int32_t c = A.col_idx[j];
-                q = q + A.vals[j] * (ca * xa[c] + cb * xb[c]);
-            }
-            r = b[i] - q;
+            r = b[i] - row_base(A, i, xa, xb, ca, cb);
         }
         if constexpr (MODE == FEAT_SCAN) {
             rbuf[i] = r;
@@ -546,11 +609,8 @@ __global__ __launch_bounds__(NWG) void k_check(DevCsr A, const double *b, const 
     __shared__ double lds[NWG];
     double a0 = 0.0, a1 = 0.0;
     for (int64_t i = (int64_t)blockIdx.x * NWG + threadIdx.x; i < A.n; i += (int64_t)gridDim.x * NWG) {
-        double q0 = 0.0, q1 = 0.0;
-        for (int32_t j = A.row_ptr[i]; j < A.row_ptr[i + 1]; ++j) {
-            q0 = q0 + A.vals[j] * x0[A.col_idx[j]];
-            q1 = q1 + A.vals[j] * um[A.col_idx[j]];
-        }
+        double q0, q1;
+        row_dot2(A, i, x0, um, q0, q1);
         const double r0 = b[i] - q0, r1 = b[i] - q1;
         a0 += r0 * r0;
         a1 += r1 * r1;
