@@ -115,6 +115,159 @@ __device__ __forceinline__ T row_sum(const int32_t *__restrict__ col, const T *_
     return q;
 }
 
+// One system of the batch, solved by the whole workgroup.  IN_LDS: its four
+// FP32 work vectors live in the workgroup's LDS (n <= lds_rows), else in
+// global memory.
+template <int WGS, bool IN_LDS>
+__device__ __forceinline__ void solve_one(const BatchArgs &a, int s, float *vlds, dd (*red)[WGS / 64],
+                                          double *bcast)
+{
+    constexpr int NW = WGS / 64;
+    const int tid = threadIdx.x;
+    const int r0 = a.sys_ptr[s];
+    const int n = a.sys_ptr[s + 1] - r0;
+    // IN_LDS is a compile-time choice, so each vector has one address
+    // space and compiles to ds_* or global_* accesses (not flat).
+    float *R = IN_LDS ? vlds : a.r32 + r0;
+    float *P = IN_LDS ? vlds + a.lds_rows : a.p32 + r0;
+    float *AP = IN_LDS ? vlds + 2 * a.lds_rows : a.ap32 + r0;
+    float *D = IN_LDS ? vlds + 3 * a.lds_rows : a.d32 + r0;
+    const int64_t max_iter = a.max_iter > 0 ? a.max_iter : 10 * (int64_t)n;
+    int64_t used = 0;
+    int32_t sweeps = 0, st = B_NOT_CONVERGED;
+    double bnorm = 0.0, tol = 0.0, rel = 0.0;
+    for (;;) {
+        // r_j = b - A x_j (FP64, rows left to right); r32 = (float) r_j
+        dd acc[2] = {dd{0.0, 0.0}, dd{0.0, 0.0}};
+        for (int i = tid; i < n; i += WGS) {
+            const int gi = r0 + i;
+            const double q = row_sum<double, double>(a.col_idx, a.vals, a.x, a.row_ptr[gi],
+                                                     a.row_ptr[gi + 1], 0);
+            const double ri = a.b[gi] - q;
+            R[i] = (float)ri;
+            dd_fma(acc[0], ri, ri);
+            if (sweeps == 0)
+                dd_fma(acc[1], a.b[gi], a.b[gi]);
+        }
+        double rr[2];
+        wg_reduce<2, NW>(acc, rr, red, bcast);
+        if (sweeps == 0) {
+            if (rr[1] == 0.0) {  // b = 0: x = 0
+                for (int i = tid; i < n; i += WGS)
+                    a.x[r0 + i] = 0.0;
+                st = B_CONVERGED;
+                rel = 0.0;
+                break;
+            }
+            bnorm = sqrt(rr[1]);
+            tol = a.rtol * bnorm;
+        }
+        rel = sqrt(rr[0]) / bnorm;
+        if (!isfinite(rr[0])) {
+            st = B_BREAKDOWN;
+            break;
+        }
+        if (sqrt(rr[0]) <= tol) {
+            st = B_CONVERGED;
+            break;
+        }
+        if (sweeps >= a.max_outer || used >= max_iter) {
+            st = B_NOT_CONVERGED;
+            break;
+        }
+        // Inner solve A d = r32, d_0 = 0, by FP32 pipelined CG.
+        const int64_t cap = max_iter - used;
+        dd ai[1] = {dd{0.0, 0.0}};
+        for (int i = tid; i < n; i += WGS) {
+            const float ri = R[i];
+            P[i] = ri;
+            D[i] = 0.f;
+            dd_fma(ai[0], (double)ri, (double)ri);
+        }
+        double rri[1];
+        wg_reduce<1, NW>(ai, rri, red, bcast);
+        double rrin = rri[0];
+        int64_t k = 0;
+        int ist = B_NOT_CONVERGED;
+        const double tol_in = a.inner_rtol * sqrt(rrin);
+        if (rrin == 0.0 || (isfinite(rrin) && sqrt(rrin) <= tol_in)) {
+            ist = B_CONVERGED;  // no step
+        } else if (!isfinite(rrin)) {
+            ist = B_BREAKDOWN;
+        } else {
+            double alpha = 0.0, beta = 0.0;
+            bool first = true;
+            for (int64_t it = 0;; ++it) {
+                // it == 0: product only; it >= 1: update, then product.
+                dd acc3[3] = {dd{0.0, 0.0}, dd{0.0, 0.0}, dd{0.0, 0.0}};
+                if (!first) {
+                    const float af = (float)alpha, bf = (float)beta;
+                    for (int i = tid; i < n; i += WGS) {
+                        const float pi = P[i];
+                        D[i] = D[i] + af * pi;
+                        const float ri = R[i] - af * AP[i];
+                        R[i] = ri;
+                        P[i] = ri + bf * pi;
+                        dd_fma(acc3[0], (double)ri, (double)ri);
+                    }
+                    __syncthreads();  // p complete before the product
+                }
+                for (int i = tid; i < n; i += WGS) {
+                    const int gi = r0 + i;
+                    const float q = row_sum<float, float>(a.col_idx, a.vals32, P, a.row_ptr[gi],
+                                                          a.row_ptr[gi + 1], r0);
+                    AP[i] = q;
+                    dd_fma(acc3[1], (double)q, (double)P[i]);
+                    dd_fma(acc3[2], (double)q, (double)q);
+                }
+                double d3[3];
+                wg_reduce<3, NW>(acc3, d3, red, bcast);
+                if (!first) {
+                    rrin = d3[0];
+                    k = it;
+                    if (!isfinite(rrin)) {
+                        ist = B_BREAKDOWN;
+                        break;
+                    }
+                    if (sqrt(rrin) <= tol_in) {
+                        ist = B_CONVERGED;
+                        break;
+                    }
+                    if (it == cap)
+                        break;
+                }
+                const double pap = d3[1], apap = d3[2];
+                if (!(pap > 0.0) || !isfinite(pap) || !isfinite(apap)) {
+                    ist = B_BREAKDOWN;
+                    break;
+                }
+                alpha = rrin / pap;
+                beta = alpha * alpha * apap / rrin - 1.0;  // Eq. (3)
+                first = false;
+            }
+        }
+        used += k;
+        if (ist == B_BREAKDOWN) {
+            st = B_BREAKDOWN;
+            break;
+        }
+        if (k == 0) {
+            st = B_NOT_CONVERGED;
+            break;
+        }
+        for (int i = tid; i < n; i += WGS)
+            a.x[r0 + i] = a.x[r0 + i] + (double)D[i];
+        sweeps++;
+        __syncthreads();  // x complete before the next residual
+    }
+    if (tid == 0) {
+        a.status[s] = st;
+        a.iters[s] = (int32_t)used;
+        a.sweeps[s] = sweeps;
+        a.rel[s] = rel;
+    }
+}
+
 template <int WGS>
 __global__ __launch_bounds__(WGS) void k_batch_mixed(BatchArgs a)
 {
@@ -134,147 +287,11 @@ __global__ __launch_bounds__(WGS) void k_batch_mixed(BatchArgs a)
         __syncthreads();
         if (s < 0)
             return;
-        const int r0 = a.sys_ptr[s];
-        const int n = a.sys_ptr[s + 1] - r0;
-        const bool in_lds = n <= a.lds_rows;
-        float *R = in_lds ? vlds : a.r32 + r0;
-        float *P = in_lds ? vlds + a.lds_rows : a.p32 + r0;
-        float *AP = in_lds ? vlds + 2 * a.lds_rows : a.ap32 + r0;
-        float *D = in_lds ? vlds + 3 * a.lds_rows : a.d32 + r0;
-        const int64_t max_iter = a.max_iter > 0 ? a.max_iter : 10 * (int64_t)n;
-        int64_t used = 0;
-        int32_t sweeps = 0, st = B_NOT_CONVERGED;
-        double bnorm = 0.0, tol = 0.0, rel = 0.0;
-        for (;;) {
-            // r_j = b - A x_j (FP64, rows left to right); r32 = (float) r_j
-            dd acc[2] = {dd{0.0, 0.0}, dd{0.0, 0.0}};
-            for (int i = tid; i < n; i += WGS) {
-                const int gi = r0 + i;
-                const double q = row_sum<double, double>(a.col_idx, a.vals, a.x, a.row_ptr[gi],
-                                                         a.row_ptr[gi + 1], 0);
-                const double ri = a.b[gi] - q;
-                R[i] = (float)ri;
-                dd_fma(acc[0], ri, ri);
-                if (sweeps == 0)
-                    dd_fma(acc[1], a.b[gi], a.b[gi]);
-            }
-            double rr[2];
-            wg_reduce<2, NW>(acc, rr, red, bcast);
-            if (sweeps == 0) {
-                if (rr[1] == 0.0) {  // b = 0: x = 0
-                    for (int i = tid; i < n; i += WGS)
-                        a.x[r0 + i] = 0.0;
-                    st = B_CONVERGED;
-                    rel = 0.0;
-                    break;
-                }
-                bnorm = sqrt(rr[1]);
-                tol = a.rtol * bnorm;
-            }
-            rel = sqrt(rr[0]) / bnorm;
-            if (!isfinite(rr[0])) {
-                st = B_BREAKDOWN;
-                break;
-            }
-            if (sqrt(rr[0]) <= tol) {
-                st = B_CONVERGED;
-                break;
-            }
-            if (sweeps >= a.max_outer || used >= max_iter) {
-                st = B_NOT_CONVERGED;
-                break;
-            }
-            // Inner solve A d = r32, d_0 = 0, by FP32 pipelined CG.
-            const int64_t cap = max_iter - used;
-            dd ai[1] = {dd{0.0, 0.0}};
-            for (int i = tid; i < n; i += WGS) {
-                const float ri = R[i];
-                P[i] = ri;
-                D[i] = 0.f;
-                dd_fma(ai[0], (double)ri, (double)ri);
-            }
-            double rri[1];
-            wg_reduce<1, NW>(ai, rri, red, bcast);
-            double rrin = rri[0];
-            int64_t k = 0;
-            int ist = B_NOT_CONVERGED;
-            const double tol_in = a.inner_rtol * sqrt(rrin);
-            if (rrin == 0.0 || (isfinite(rrin) && sqrt(rrin) <= tol_in)) {
-                ist = B_CONVERGED;  // no step
-            } else if (!isfinite(rrin)) {
-                ist = B_BREAKDOWN;
-            } else {
-                double alpha = 0.0, beta = 0.0;
-                bool first = true;
-                for (int64_t it = 0;; ++it) {
-                    // it == 0: product only; it >= 1: update, then product.
-                    dd acc3[3] = {dd{0.0, 0.0}, dd{0.0, 0.0}, dd{0.0, 0.0}};
-                    if (!first) {
-                        const float af = (float)alpha, bf = (float)beta;
-                        for (int i = tid; i < n; i += WGS) {
-                            const float pi = P[i];
-                            D[i] = D[i] + af * pi;
-                            const float ri = R[i] - af * AP[i];
-                            R[i] = ri;
-                            P[i] = ri + bf * pi;
-                            dd_fma(acc3[0], (double)ri, (double)ri);
-                        }
-                        __syncthreads();  // p complete before the product
-                    }
-                    for (int i = tid; i < n; i += WGS) {
-                        const int gi = r0 + i;
-                        const float q = row_sum<float, float>(a.col_idx, a.vals32, P, a.row_ptr[gi],
-                                                              a.row_ptr[gi + 1], r0);
-                        AP[i] = q;
-                        dd_fma(acc3[1], (double)q, (double)P[i]);
-                        dd_fma(acc3[2], (double)q, (double)q);
-                    }
-                    double d3[3];
-                    wg_reduce<3, NW>(acc3, d3, red, bcast);
-                    if (!first) {
-                        rrin = d3[0];
-                        k = it;
-                        if (!isfinite(rrin)) {
-                            ist = B_BREAKDOWN;
-                            break;
-                        }
-                        if (sqrt(rrin) <= tol_in) {
-                            ist = B_CONVERGED;
-                            break;
-                        }
-                        if (it == cap)
-                            break;
-                    }
-                    const double pap = d3[1], apap = d3[2];
-                    if (!(pap > 0.0) || !isfinite(pap) || !isfinite(apap)) {
-                        ist = B_BREAKDOWN;
-                        break;
-                    }
-                    alpha = rrin / pap;
-                    beta = alpha * alpha * apap / rrin - 1.0;  // Eq. (3)
-                    first = false;
-                }
-            }
-            used += k;
-            if (ist == B_BREAKDOWN) {
-                st = B_BREAKDOWN;
-                break;
-            }
-            if (k == 0) {
-                st = B_NOT_CONVERGED;
-                break;
-            }
-            for (int i = tid; i < n; i += WGS)
-                a.x[r0 + i] = a.x[r0 + i] + (double)D[i];
-            sweeps++;
-            __syncthreads();  // x complete before the next residual
-        }
-        if (tid == 0) {
-            a.status[s] = st;
-            a.iters[s] = (int32_t)used;
-            a.sweeps[s] = sweeps;
-            a.rel[s] = rel;
-        }
+        const int n = a.sys_ptr[s + 1] - a.sys_ptr[s];
+        if (n <= a.lds_rows)
+            solve_one<WGS, true>(a, s, vlds, red, bcast);
+        else
+            solve_one<WGS, false>(a, s, vlds, red, bcast);
         __syncthreads();
     }
 }
