@@ -1214,9 +1214,10 @@ static fk_status solve_gmres(fk_solver S, const double *b, double *x, bool profi
                 // w = A v_{i-1} (into slot i), with <v_{i-1}, w> when i >= 2
                 ENQ(FK_KERNEL_SPMV_DOT, launch_spmv_dots(A, vec(i - 1), vec(i), nullptr, i >= 2 ? D_YV : 0,
                                                          red(i >= 2 ? FIN_GM_R1 : FIN_NONE), gs, st));
-                if (i >= 3)
-                    ENQ(FK_KERNEL_DOT, launch_gm_multidot(n, S->V, vec(i), 1, i - 1, i, S->gR, m1, S->gpart,
-                                                          S->st, RUN_ACTIVE, st));
+                if (i >= 3) {
+                    ENQ(FK_KERNEL_DOT, launch_gm_multidot(n, S->V, vec(i), 1, i - 1, S->gpart, S->st, RUN_ACTIVE, st));
+                    ENQ(FK_KERNEL_DOT, launch_gm_multidot_fin(1, i - 1, i, S->gR, m1, S->gpart, S->st, RUN_ACTIVE, st));
+                }
                 ENQ(FK_KERNEL_UPDATE_DOT, launch_gm_update(n, vec(i), S->V, i, m1, red(FIN_GM_NORM), gv, st));
                 ENQ(FK_KERNEL_UPDATE_DOT, launch_gm_normalize(n, vec(i), rxi, i, m1, red(FIN_GM_XI), gv, st));
                 if (classical)

@@ -240,17 +240,21 @@ hipError_t launch_to_f32(int64_t n, float *out, const double *in, int grid, hipS
 // doubles (v_0 = r0 / rho0, v_1..v_m orthonormal); R is (m+1) x (m+1)
 // row-major, row 0 holding xi_1..xi_m.  In `red`, scal points to R.
 constexpr int GM_MAX = 64;          // largest restart length
-constexpr int GM_GRID = 256;        // workgroups of the multi-dot kernel
-// Multi-dot scratch (doubles): double-double partials [GM_MAX][GM_GRID], then
-// one arrival counter on its own 128-byte line.
-constexpr size_t GM_PART_DOUBLES = (size_t)2 * GM_MAX * GM_GRID + 16;
+#ifndef FK_GM_GRID
+#define FK_GM_GRID 1024
+#endif
+constexpr int GM_GRID = FK_GM_GRID;  // workgroups of the multi-dot kernel
+// Multi-dot scratch (doubles): double-double partials [GM_MAX][GM_GRID].
+constexpr size_t GM_PART_DOUBLES = (size_t)2 * GM_MAX * GM_GRID;
 // out = in / rho0 (the cycle's first basis vector)
 hipError_t launch_gm_scale(int64_t n, double *out, const double *in, DevState *st, uint32_t run_mask, int grid,
                            hipStream_t s);
-// R[j][i] = <v_j, w> for j0 <= j < j1 (first and second stage; the last
-// workgroup writes R)
-hipError_t launch_gm_multidot(int64_t n, const double *V, const double *w, int j0, int j1, int i, double *R,
-                              int m1, double *part, DevState *st, uint32_t run_mask, hipStream_t s);
+// R[j][i] = <v_j, w> for j0 <= j < j1: first stage (per-workgroup partials
+// into part), then the second stage, one workgroup per dot, writing R.
+hipError_t launch_gm_multidot(int64_t n, const double *V, const double *w, int j0, int j1, double *part,
+                              DevState *st, uint32_t run_mask, hipStream_t s);
+hipError_t launch_gm_multidot_fin(int j0, int j1, int i, double *R, int m1, const double *part, DevState *st,
+                                  uint32_t run_mask, hipStream_t s);
 // w -= sum_{j=1}^{i-1} R[j][i] v_j; first stage of <w,w> (FIN_GM_NORM)
 hipError_t launch_gm_update(int64_t n, double *w, const double *V, int i, int m1, const RedArgs &red, int grid,
                             hipStream_t s);

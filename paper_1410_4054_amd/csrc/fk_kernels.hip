@@ -1394,22 +1394,18 @@ __global__ __launch_bounds__(WG) void k_gm_scale(int64_t n, double *out, const d
         out[t] = in[t] / rho0;
 }
 
-// R[j][i] = <v_j, w> for j0 <= j < j1, all from the same w (classical
-// Gram-Schmidt).  Workgroup g owns a contiguous chunk of rows and keeps
-// GM_JT double-double accumulators at a time; its partials go to
-// part[j][g].  The last workgroup to arrive sums every dot's partials in
-// workgroup order, four threads per dot (a fixed split and a fixed 4-lane
-// tree), and writes R.
+// First stage of R[j][i] = <v_j, w> for j0 <= j < j1, all from the same w
+// (classical Gram-Schmidt).  Workgroup g owns a contiguous chunk of rows and
+// keeps GM_JT double-double accumulators at a time; its partials go to
+// part[j][g].  k_gm_multidot_fin does the second stage.
 constexpr int GM_JT = 8;
 __global__ __launch_bounds__(WG) void k_gm_multidot(int64_t n, const double *__restrict__ V,
-                                                     const double *__restrict__ w, int j0, int j1, int i,
-                                                     double *R, int m1, double *part, DevState *st,
-                                                     uint32_t mask)
+                                                     const double *__restrict__ w, int j0, int j1,
+                                                     double *part, DevState *st, uint32_t mask)
 {
     if (!runs_mask(st, mask))
         return;
     __shared__ dd lds[WAVES][KMAX];
-    __shared__ int s_last;
     const int G = gridDim.x, g = blockIdx.x;
     const int64_t lo = n * g / G, hi = n * (g + 1) / G;
     for (int jt = j0; jt < j1; jt += GM_JT) {
@@ -1438,43 +1434,34 @@ __global__ __launch_bounds__(WG) void k_gm_multidot(int64_t n, const double *__r
                     const int j = jt + q0 + q;
                     if (j < j1) {
                         double *slot = part + 2 * ((size_t)j * GM_GRID + g);
-                        store_coherent(slot, v4[q].hi);
-                        store_coherent(slot + 1, v4[q].lo);
+                        slot[0] = v4[q].hi;
+                        slot[1] = v4[q].lo;
                     }
                 }
             }
         }
     }
-    uint32_t *cnt = reinterpret_cast<uint32_t *>(part + (size_t)2 * GM_MAX * GM_GRID);
-    if (threadIdx.x == 0) {
-        __builtin_amdgcn_s_waitcnt(0);
-        const uint32_t prev = __hip_atomic_fetch_add(cnt, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        s_last = prev == (uint32_t)(G - 1) ? 1 : 0;
-    }
-    __syncthreads();
-    if (!s_last)
+}
+
+// Second stage: workgroup b sums dot j = j0 + b over the G partials of
+// k_gm_multidot (thread t takes partials t, t + WG, ..., then a fixed tree)
+// and writes R[j][i].
+__global__ __launch_bounds__(WG) void k_gm_multidot_fin(int G, int j0, int i, double *R, int m1,
+                                                         const double *__restrict__ part, DevState *st,
+                                                         uint32_t mask)
+{
+    if (!runs_mask(st, mask))
         return;
-    const int j = j0 + (int)threadIdx.x / 4, q = (int)threadIdx.x % 4;
-    dd a = dd{0.0, 0.0};
-    if (j < j1) {
-        const int ga = G * q / 4, gb = G * (q + 1) / 4;
-        for (int gg = ga; gg < gb; ++gg) {
-            const double *slot = part + 2 * ((size_t)j * GM_GRID + gg);
-            a = dd_add(a, dd{load_coherent(slot), load_coherent(slot + 1)});
-        }
+    __shared__ dd lds[WAVES][KMAX];
+    const int j = j0 + (int)blockIdx.x;
+    dd a[1] = {dd{0.0, 0.0}};
+    for (int g = threadIdx.x; g < G; g += WG) {
+        const double *slot = part + 2 * ((size_t)j * GM_GRID + g);
+        a[0] = dd_add(a[0], dd{slot[0], slot[1]});
     }
-    // lanes 4k..4k+3 hold the four quarters of one dot
-    dd o;
-    o.hi = __shfl_xor(a.hi, 1, 64);
-    o.lo = __shfl_xor(a.lo, 1, 64);
-    a = (q & 1) ? dd_add(o, a) : dd_add(a, o);
-    o.hi = __shfl_xor(a.hi, 2, 64);
-    o.lo = __shfl_xor(a.lo, 2, 64);
-    a = (q & 2) ? dd_add(o, a) : dd_add(a, o);
-    if (j < j1 && q == 0)
-        R[(size_t)j * m1 + i] = a.hi + a.lo;
+    block_reduce<1>(a, lds);
     if (threadIdx.x == 0)
-        __hip_atomic_store(cnt, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        R[(size_t)j * m1 + i] = a[0].hi + a[0].lo;
 }
 
 // w -= sum_{j=1}^{i-1} R[j][i] v_j (j in order); first stage of <w, w>.
@@ -2007,10 +1994,16 @@ hipError_t launch_gm_scale(int64_t n, double *out, const double *in, DevState *s
     return launch(k_gm_scale, grid, WG, s, n, out, in, st, run_mask);
 }
 
-hipError_t launch_gm_multidot(int64_t n, const double *V, const double *w, int j0, int j1, int i, double *R,
-                              int m1, double *part, DevState *st, uint32_t run_mask, hipStream_t s)
+hipError_t launch_gm_multidot(int64_t n, const double *V, const double *w, int j0, int j1, double *part,
+                              DevState *st, uint32_t run_mask, hipStream_t s)
 {
-    return launch(k_gm_multidot, GM_GRID, WG, s, n, V, w, j0, j1, i, R, m1, part, st, run_mask);
+    return launch(k_gm_multidot, GM_GRID, WG, s, n, V, w, j0, j1, part, st, run_mask);
+}
+
+hipError_t launch_gm_multidot_fin(int j0, int j1, int i, double *R, int m1, const double *part, DevState *st,
+                                  uint32_t run_mask, hipStream_t s)
+{
+    return launch(k_gm_multidot_fin, j1 - j0, WG, s, GM_GRID, j0, i, R, m1, part, st, run_mask);
 }
 
 hipError_t launch_gm_update(int64_t n, double *w, const double *V, int i, int m1, const RedArgs &red, int grid,
