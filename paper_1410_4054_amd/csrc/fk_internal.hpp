@@ -24,8 +24,12 @@ constexpr int GMAX = 4096;
 // sums the group sums.
 constexpr int RGROUP = 64;
 // A launch with at most this many double-double partials (workgroups times
-// dots, published ones included) is summed by its last workgroup alone.
-constexpr int FLAT_PARTIALS = 4096;
+// dots, published ones included) is summed by one wave of its last
+// workgroup alone.
+#ifndef FK_FLAT_PARTIALS
+#define FK_FLAT_PARTIALS 1024
+#endif
+constexpr int FLAT_PARTIALS = FK_FLAT_PARTIALS;
 constexpr int RNGROUPS_MAX = GMAX / RGROUP;
 constexpr int CNT_STRIDE = 32;  // uint32 per arrival counter (one 128-byte line each)
 // Published first-stage partials (FIN_PUBLISH) of at most this many dots.

@@ -538,16 +538,23 @@ __device__ void finalize(DevState *st, int fin, const double *d, int K, double *
 }
 
 // The reduction point at the end of a kernel; every thread of every
-// workgroup of the grid must call it exactly once.
+// workgroup of the grid must call it exactly once, and return right after.
+//
+// First stage.  Each wave sums its lanes' partials (butterfly); waves 1 ..
+// WAVES-1 leave theirs in LDS, meet wave 0 at one barrier and exit.  Wave 0
+// adds them in wave order and carries on alone: the stores, the wait for
+// them and the arrival below hold one wave of the workgroup, not four, and
+// there is no further barrier.
 //
 // Second stage.  Workgroup g stores its partials and arrives at the counter
 // of group g / RGROUP; the last arrival of a group arrives at the top
 // counter, and the last of those finishes:
 //  - with at most FLAT_PARTIALS partials in all, it sums every partial
-//    itself (thread t takes indices t, t + WG, ..., then a fixed tree);
+//    itself (lane l takes indices l, l + 64, ..., then the butterfly);
 //  - else as a two-level tree: the last arrival of each group first sums
-//    that group's partials (in index order) and stores the group sum, and
-//    the last group sums the group sums (in group order).
+//    that group's partials (one per lane; RGROUP is the wave width) and
+//    stores the group sum, and the last group sums the group sums (at most
+//    GMAX / RGROUP = 64, again one per lane).
 // Either way the result is rounded once and finalized.
 // The order of every sum depends only on the grid size, never on timing.
 // Counters are reset by the workgroup that saw the last arrival, so the
@@ -561,25 +568,49 @@ __device__ void finalize(DevState *st, int fin, const double *d, int K, double *
 // dots and cost no extra round trip.  Algorithm 2 needs <r_i, r_i> only with
 // the product's two dots (alpha_i and beta_i need all three), which is what
 // lets the update kernel publish it instead of reducing it.
+static_assert(RGROUP == 64 && GMAX / RGROUP <= 64, "group and top level are one wave64 each");
+
+// Lane 0's value of a wave-uniform arrival count, in every lane.
+__device__ __forceinline__ uint32_t wave_bcast(uint32_t x)
+{
+    return (uint32_t)__builtin_amdgcn_readfirstlane((int)x);
+}
+
 template <int K>
 __device__ __forceinline__ void reduce_point(dd (&v)[K], const RedArgs &red, int g, int G)
 {
     __shared__ dd lds[WAVES][KMAX];
-    __shared__ int s_flag;
     double *const part1 = red.partials;
     double *const part2 = red.partials + RED_L2_OFFSET;
     double *const pub = red.partials + RED_PUB_OFFSET;
     uint32_t *const cnt = reinterpret_cast<uint32_t *>(red.partials + RED_CNT_OFFSET);
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
     const int ngroups = (G + RGROUP - 1) / RGROUP;
     const int grp = g / RGROUP;
     const int gbase = grp * RGROUP;
     const int gsize = min(RGROUP, G - gbase);
 
-    block_reduce<K>(v, lds);
+#pragma unroll
+    for (int k = 0; k < K; ++k)
+        v[k] = wave_reduce(v[k]);
+    if (wave > 0 && lane == 0) {
+#pragma unroll
+        for (int k = 0; k < K; ++k)
+            lds[wave][k] = v[k];
+    }
+    __syncthreads();
+    if (wave > 0)
+        return;
+#pragma unroll
+    for (int k = 0; k < K; ++k)
+        for (int w = 1; w < WAVES; ++w)
+            v[k] = dd_add(v[k], lds[w][k]);
+
     if (red.fin == FIN_PUBLISH) {
         // First stage only; a later reduction point of the same solver, in
         // a later kernel, folds these partials into its own second stage.
-        if (threadIdx.x == 0) {
+        if (lane == 0) {
 #pragma unroll
             for (int k = 0; k < K; ++k) {
                 double *slot = pub + 2 * ((size_t)k * GMAX + g);
@@ -589,7 +620,8 @@ __device__ __forceinline__ void reduce_point(dd (&v)[K], const RedArgs &red, int
         }
         return;
     }
-    if (threadIdx.x == 0) {
+    uint32_t prev = 0;
+    if (lane == 0) {
 #pragma unroll
         for (int k = 0; k < K; ++k) {
             double *slot = part1 + 2 * ((size_t)k * GMAX + g);
@@ -599,12 +631,10 @@ __device__ __forceinline__ void reduce_point(dd (&v)[K], const RedArgs &red, int
         // The partial stores must have reached the coherence point before
         // another workgroup can observe this arrival.
         __builtin_amdgcn_s_waitcnt(0);
-        const uint32_t prev = __hip_atomic_fetch_add(cnt + (size_t)grp * CNT_STRIDE, 1u,
-                                                     __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        s_flag = (prev == (uint32_t)(gsize - 1)) ? 1 : 0;
+        prev = __hip_atomic_fetch_add(cnt + (size_t)grp * CNT_STRIDE, 1u, __ATOMIC_RELAXED,
+                                      __HIP_MEMORY_SCOPE_AGENT);
     }
-    __syncthreads();
-    if (!s_flag)
+    if (wave_bcast(prev) != (uint32_t)(gsize - 1))
         return;
 
     constexpr int KP = (K + KPUB <= KMAX) ? KPUB : KMAX - K;
@@ -621,30 +651,57 @@ __device__ __forceinline__ void reduce_point(dd (&v)[K], const RedArgs &red, int
     // a load, a store and a second arrival).  Many: two levels of sums.
     const bool flat = (int64_t)G * K + (int64_t)red.npub * kpub <= FLAT_PARTIALS;
     if (flat) {
-        if (threadIdx.x == 0) {
+        if (lane == 0) {
             __hip_atomic_store(cnt + (size_t)grp * CNT_STRIDE, 0u, __ATOMIC_RELAXED,
                                __HIP_MEMORY_SCOPE_AGENT);
-            const uint32_t prev = __hip_atomic_fetch_add(cnt + (size_t)RNGROUPS_MAX * CNT_STRIDE, 1u,
-                                                         __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            s_flag = (prev == (uint32_t)(ngroups - 1)) ? 1 : 0;
+            prev = __hip_atomic_fetch_add(cnt + (size_t)RNGROUPS_MAX * CNT_STRIDE, 1u,
+                                          __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
-        __syncthreads();
-        if (!s_flag)
+        if (wave_bcast(prev) != (uint32_t)(ngroups - 1))
             return;
-        for (int j = threadIdx.x; j < G; j += WG) {
+        // Lane l adds partials l, l + 64, ... in index order; UB of them
+        // are requested before the first is added.
+        constexpr int UB = K <= 1 ? 8 : (K == 2 ? 4 : 2);
+        for (int j0 = lane; j0 < G; j0 += 64 * UB) {
+            dd t[UB][K];
 #pragma unroll
-            for (int k = 0; k < K; ++k) {
-                const double *slot = part1 + 2 * ((size_t)k * GMAX + j);
-                acc[k] = dd_add(acc[k], dd{load_coherent(slot), load_coherent(slot + 1)});
+            for (int u = 0; u < UB; ++u) {
+#pragma unroll
+                for (int k = 0; k < K; ++k) {
+                    const double *slot = part1 + 2 * ((size_t)k * GMAX + j0 + 64 * u);
+                    if (j0 + 64 * u < G)
+                        t[u][k] = dd{load_coherent(slot), load_coherent(slot + 1)};
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < UB; ++u) {
+                if (j0 + 64 * u < G) {
+#pragma unroll
+                    for (int k = 0; k < K; ++k)
+                        acc[k] = dd_add(acc[k], t[u][k]);
+                }
             }
         }
         if (kpub > 0) {
-            for (int j = threadIdx.x; j < red.npub; j += WG) {
+            constexpr int UP = KP <= 1 ? 8 : 4;
+            for (int j0 = lane; j0 < red.npub; j0 += 64 * UP) {
+                dd t[UP][KP > 0 ? KP : 1];
 #pragma unroll
-                for (int k = 0; k < KP; ++k) {
-                    if (k < kpub) {
-                        const double *slot = pub + 2 * ((size_t)k * GMAX + j);
-                        acc[K + k] = dd_add(acc[K + k], dd{load_coherent(slot), load_coherent(slot + 1)});
+                for (int u = 0; u < UP; ++u) {
+#pragma unroll
+                    for (int k = 0; k < KP; ++k) {
+                        const double *slot = pub + 2 * ((size_t)k * GMAX + j0 + 64 * u);
+                        if (k < kpub && j0 + 64 * u < red.npub)
+                            t[u][k] = dd{load_coherent(slot), load_coherent(slot + 1)};
+                    }
+                }
+#pragma unroll
+                for (int u = 0; u < UP; ++u) {
+                    if (j0 + 64 * u < red.npub) {
+#pragma unroll
+                        for (int k = 0; k < KP; ++k)
+                            if (k < kpub)
+                                acc[K + k] = dd_add(acc[K + k], t[u][k]);
                     }
                 }
             }
@@ -654,15 +711,15 @@ __device__ __forceinline__ void reduce_point(dd (&v)[K], const RedArgs &red, int
         // group's share of the published partials (dots K .. K + kpub - 1).
 #pragma unroll
         for (int k = 0; k < K; ++k) {
-            if ((int)threadIdx.x < gsize) {
-                const double *slot = part1 + 2 * ((size_t)k * GMAX + gbase + threadIdx.x);
+            if (lane < gsize) {
+                const double *slot = part1 + 2 * ((size_t)k * GMAX + gbase + lane);
                 acc[k] = dd{load_coherent(slot), load_coherent(slot + 1)};
             }
         }
         if (kpub > 0) {
             const int p0 = (int)(((int64_t)red.npub * grp) / ngroups);
             const int p1 = (int)(((int64_t)red.npub * (grp + 1)) / ngroups);
-            for (int j = p0 + (int)threadIdx.x; j < p1; j += WG) {
+            for (int j = p0 + lane; j < p1; j += 64) {
 #pragma unroll
                 for (int k = 0; k < KP; ++k) {
                     if (k < kpub) {
@@ -672,8 +729,10 @@ __device__ __forceinline__ void reduce_point(dd (&v)[K], const RedArgs &red, int
                 }
             }
         }
-        block_reduce<KT>(acc, lds);
-        if (threadIdx.x == 0) {
+#pragma unroll
+        for (int k = 0; k < KT; ++k)
+            acc[k] = wave_reduce(acc[k]);
+        if (lane == 0) {
 #pragma unroll
             for (int k = 0; k < KT; ++k) {
                 if (k < kt) {
@@ -685,30 +744,26 @@ __device__ __forceinline__ void reduce_point(dd (&v)[K], const RedArgs &red, int
             __hip_atomic_store(cnt + (size_t)grp * CNT_STRIDE, 0u, __ATOMIC_RELAXED,
                                __HIP_MEMORY_SCOPE_AGENT);
             __builtin_amdgcn_s_waitcnt(0);
-            const uint32_t prev = __hip_atomic_fetch_add(cnt + (size_t)RNGROUPS_MAX * CNT_STRIDE, 1u,
-                                                         __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            s_flag = (prev == (uint32_t)(ngroups - 1)) ? 1 : 0;
+            prev = __hip_atomic_fetch_add(cnt + (size_t)RNGROUPS_MAX * CNT_STRIDE, 1u,
+                                          __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
-        __syncthreads();
-        if (!s_flag)
+        if (wave_bcast(prev) != (uint32_t)(ngroups - 1))
             return;
 
-        // Last group: sum the group sums.
+        // Last group: sum the group sums, one per lane.
 #pragma unroll
-        for (int k = 0; k < KT; ++k)
+        for (int k = 0; k < KT; ++k) {
             acc[k] = dd{0.0, 0.0};
-        for (int j = threadIdx.x; j < ngroups; j += WG) {
-#pragma unroll
-            for (int k = 0; k < KT; ++k) {
-                if (k < kt) {
-                    const double *slot = part2 + 2 * ((size_t)k * RNGROUPS_MAX + j);
-                    acc[k] = dd_add(acc[k], dd{load_coherent(slot), load_coherent(slot + 1)});
-                }
+            if (k < kt && lane < ngroups) {
+                const double *slot = part2 + 2 * ((size_t)k * RNGROUPS_MAX + lane);
+                acc[k] = dd{load_coherent(slot), load_coherent(slot + 1)};
             }
         }
     }
-    block_reduce<KT>(acc, lds);
-    if (threadIdx.x == 0) {
+#pragma unroll
+    for (int k = 0; k < KT; ++k)
+        acc[k] = wave_reduce(acc[k]);
+    if (lane == 0) {
         double d[KT > 0 ? KT : 1];
 #pragma unroll
         for (int k = 0; k < KT; ++k)
