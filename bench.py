@@ -445,8 +445,9 @@ def main():
 
         # Uneven batch: 512 shifted 2D Laplacians (n_s in [16, 512]), FP64
         # refinement around FP32 pipelined CG to 1e-10, all in one persistent
-        # launch replayed from a hipGraph, with the launch shape picked by the
-        # autotuner; against solving the systems one at a time with the
+        # launch replayed from a hipGraph, with the launch shape (workgroup
+        # size, LDS limit, team size) picked by the autotuner; against
+        # solving the systems one at a time with the
         # single-system FP64 pipelined CG to the same tolerance.
         if not args.no_batch:
             from paper_1410_4054_amd import autotune
@@ -461,7 +462,7 @@ def main():
             xbd = torch.zeros_like(bbd)
             log(f"[bench] batch assembled in {extras['batch512_assembly_seconds']:.1f} s; autotuning")
             best = autotune.tune(B, bbd, torch.zeros_like(bbd), rtol=1e-10, use_cache=False)
-            shape = {"workgroup": best["workgroup"], "lds_rows": best["lds_rows"]}
+            shape = {"workgroup": best["workgroup"], "lds_rows": best["lds_rows"], "team": best["team"]}
             extras["batch512_autotuned_shape"] = shape
             extras["batch512_autotune_seconds"] = best["seconds"]
             bstream = torch.cuda.Stream()

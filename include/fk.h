@@ -373,9 +373,19 @@ fk_status fk_net_train_step(fk_net N, fk_csr A, int32_t nx, int32_t ny, const do
  * caller keeps ownership.
  *
  * fk_batch_solve: b_dev, x_dev are device float64[n] (x holds x0 on entry).
- * Every workgroup takes the largest remaining system from a device queue
- * and solves it alone, so no workgroup waits for another; systems with at
- * most lds_rows rows keep their FP32 work vectors in LDS.  With
+ * Systems are claimed from a largest-first order.  A single workgroup
+ * solves a system alone; systems with at most lds_rows rows keep their FP32
+ * work vectors in LDS.  With team > 1, `teams` teams of `team` workgroups
+ * (0 = as many as the resident workgroups hold; fewer if asked for more)
+ * take systems from the large end, each system's rows split into one
+ * contiguous chunk per member; the remaining resident workgroups take
+ * systems alone from the small end.  team = 0 chooses teams of 16 when some
+ * system has more rows than lds_rows, else no teams.  Team members meet at barriers
+ * and all-reduces in device memory; every wait is bounded by spin_limit
+ * polls (0 = about 4 M, some seconds).  A wait that runs out aborts every
+ * team: systems not solved keep status 3 and the call returns FK_E_HIP
+ * (the kernel still ends).  Team and single results are the same, bit for
+ * bit.  With
  * FK_FLAG_GRAPH (and a stream other than the default one) the launch is
  * captured once into a hipGraph and replayed while the arguments stay the
  * same.  The call waits for completion.  Per system: converged when
@@ -391,6 +401,9 @@ typedef struct {
     int32_t lds_rows;   /* LDS-resident limit in rows: 0 = default (6144 or
                            what fits), < 0 = never                           */
     int32_t flags;      /* FK_FLAG_GRAPH                                      */
+    int32_t team;       /* workgroups per team, 0..64: 0 = default, 1 = none  */
+    int32_t teams;      /* >= 0: number of teams, 0 = default (above)         */
+    int32_t spin_limit; /* >= 0: polls a team wait makes, 0 = default        */
 } fk_batch_opts;
 
 fk_status fk_batch_create(int32_t count, const int64_t *sys_ptr_host, int64_t nnz, const int32_t *row_ptr,
@@ -401,7 +414,8 @@ fk_status fk_batch_shape(fk_batch B, int32_t *count, int64_t *n, int64_t *nnz);
 fk_status fk_batch_solve(fk_batch B, const fk_batch_opts *o, const double *b_dev, double *x_dev,
                          void *hip_stream);
 /* Per-system results of the last solve into host arrays of `count` entries
- * (each may be NULL): status (0 converged, 1 not converged, 2 breakdown),
+ * (each may be NULL): status (0 converged, 1 not converged, 2 breakdown,
+ * 3 not solved: a team gave up waiting),
  * inner iterations, refinement sweeps, ||b_s - A_s x_s|| / ||b_s|| of the
  * last residual evaluated. */
 fk_status fk_batch_results(fk_batch B, int32_t *status, int32_t *iterations, int32_t *sweeps,

@@ -1,14 +1,15 @@
 """Autotuner for the batched solver's launch shape.
 
-The batched kernel has two shape parameters: the workgroup size (rows a
-workgroup sweeps per step: 256, 512 or 1024 threads) and the row limit
-under which a system keeps its work vectors in LDS (which also fixes how
-many workgroups fit on a CU).  tune() times every candidate on the batch
-itself (same right-hand side, same start) and keeps the fastest; results
-are cached in a JSON file keyed by device and batch shape, so a batch of
-the same shape is tuned once.
+The batched kernel has three shape parameters: the workgroup size (rows a
+workgroup sweeps per step: 256, 512 or 1024 threads), the row limit under
+which a system keeps its work vectors in LDS (which also fixes how many
+workgroups fit on a CU), and the team size (workgroups that solve one large
+system together; 1 = every system alone).  tune() times every candidate on
+the batch itself (same right-hand side, same start) and keeps the fastest;
+results are cached in a JSON file keyed by device and batch shape, so a
+batch of the same shape is tuned once.
 
-    best = tune(batch, b, x0, rtol=1e-10)          # {'workgroup': ..., 'lds_rows': ...}
+    best = tune(batch, b, x0, rtol=1e-10)   # {'workgroup': ..., 'lds_rows': ..., 'team': ...}
 """
 from __future__ import annotations
 
@@ -16,7 +17,8 @@ import json
 import os
 import time
 
-CANDIDATES = [{"workgroup": wg, "lds_rows": lds} for wg in (256, 512, 1024) for lds in (0, 2048, -1)]
+CANDIDATES = ([{"workgroup": wg, "lds_rows": lds, "team": 1} for wg in (256, 512, 1024) for lds in (0, 2048, -1)]
+              + [{"workgroup": 1024, "lds_rows": 0, "team": t} for t in (4, 8, 16, 32)])
 
 
 def default_cache_path() -> str:
@@ -29,7 +31,7 @@ def batch_key(batch, rtol: float) -> str:
 
     dev = torch.cuda.get_device_name(torch.cuda.current_device())
     sizes = batch.sys_ptr[1:] - batch.sys_ptr[:-1]
-    return (f"{dev}|batch|count={batch.count}|n={batch.n}|max_rows={int(sizes.max())}"
+    return (f"{dev}|batch-v2|count={batch.count}|n={batch.n}|max_rows={int(sizes.max())}"
             f"|min_rows={int(sizes.min())}|rtol={rtol:g}")
 
 
@@ -43,7 +45,7 @@ def _load(path):
 
 def tune(batch, b, x0, rtol: float = 1e-10, candidates=None, reps: int = 1, cache_path: str | None = None,
          use_cache: bool = True) -> dict:
-    """Fastest {'workgroup', 'lds_rows'} for this batch; also returns the
+    """Fastest {'workgroup', 'lds_rows', 'team'} for this batch; also returns the
     timings under 'seconds' (candidate index -> seconds) when measured."""
     import torch
 

@@ -5,13 +5,18 @@
 // include/fk.h (fk_batch_*).
 //
 // The batch is one block-diagonal CSR matrix; system s owns the rows
-// [sys_ptr[s], sys_ptr[s+1]).  Every workgroup takes systems from a device
-// queue, largest first, and runs the whole refinement of one system before
-// taking the next, so systems never share a workgroup and no workgroup ever
-// waits for another: all reductions are inside the workgroup.  A system
-// with at most lds_rows rows keeps its four FP32 work vectors in LDS; larger
-// ones keep them in device memory (the same workgroup writes and reads them
-// between barriers).  The arithmetic is that of the single-system mixed
+// [sys_ptr[s], sys_ptr[s+1]).  Systems are claimed from a largest-first
+// order and each is solved, whole refinement included, before the claimant
+// takes the next.
+//  - Single workgroups: all reductions are inside the workgroup and no
+//    workgroup waits for another.  A system with at most lds_rows rows keeps
+//    its four FP32 work vectors in LDS; larger ones keep them in device
+//    memory (the same workgroup writes and reads them between barriers).
+//  - Teams (optional): `team` resident workgroups solve one system
+//    together, each a contiguous chunk of its rows, and meet at team
+//    barriers and all-reduces through device memory.  Teams claim from the
+//    large end of the order and single workgroups from the small end, so
+//    the two meet where their work balances.  The arithmetic is that of the single-system mixed
 // method (FK_CG_MIXED): rows summed left to right, inner products of exact
 // products in double-double rounded once, alpha and beta in FP64 rounded to
 // FP32 for the updates.  One inner iteration has one reduction: the update
@@ -34,7 +39,11 @@
 namespace fk {
 namespace batch {
 
-enum BStatus : int32_t { B_CONVERGED = 0, B_NOT_CONVERGED = 1, B_BREAKDOWN = 2 };
+enum BStatus : int32_t { B_CONVERGED = 0, B_NOT_CONVERGED = 1, B_BREAKDOWN = 2, B_UNSOLVED = 3 };
+
+constexpr int TEAM_MAX = 64;                      // workgroups per team
+constexpr int TEAM_DEFAULT = 16;                  // measured best on the 512-system batch
+constexpr uint32_t TEAM_SPIN_DEFAULT = 1u << 22;  // polls of one team wait (seconds)
 
 struct BatchArgs {
     const int32_t *sys_ptr;   // [count + 1]
@@ -46,14 +55,189 @@ struct BatchArgs {
     const double *b;
     double *x;
     float *r32, *p32, *ap32, *d32;  // device work vectors, indexed by global row
-    uint32_t *queue;
+    uint64_t *deque;  // systems claimed from the front (low word) and back (high word) of order
     int32_t *status, *iters, *sweeps;
     double *rel;
     double rtol, inner_rtol;
     int32_t max_iter;  // <= 0: 10 n_s per system
     int32_t max_outer;
     int32_t lds_rows;
+    // teams: workgroups [0, team * nteams) form nteams teams of `team`
+    int32_t team, nteams;
+    uint32_t *team_cnt;   // [nteams][CNT_STRIDE] arrivals, counting up within a launch
+    double *team_slots;   // [nteams][2][team][KMAX] double-double partials
+    int32_t *team_sys;    // [nteams] the system a team is solving
+    int32_t *abort_flag;  // set when a team wait runs out of patience
+    uint32_t spin_limit;  // polls a team wait makes before it gives up
 };
+
+// Device-coherent accesses (agent scope) for the vectors that several
+// workgroups of a team share: p of the inner solve and x.
+template <typename T>
+__device__ __forceinline__ T ld_coh(const T *p)
+{
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+template <typename T>
+__device__ __forceinline__ void st_coh(T *p, T v)
+{
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Claim the next system: from the front of `order` (largest first) or from
+// its back.  One 64-bit word counts both ends, so a system is claimed once
+// and the two ends stop where they meet.  -1 when none is left.  Lock-free:
+// a failed exchange means another claim succeeded.
+__device__ __forceinline__ int claim(const BatchArgs &a, bool front)
+{
+    uint64_t old = ld_coh(a.deque);
+    for (;;) {
+        const uint32_t f = (uint32_t)old, b = (uint32_t)(old >> 32);
+        if ((int64_t)f + (int64_t)b >= (int64_t)a.count)
+            return -1;
+        const uint64_t want = front ? old + 1u : old + (uint64_t(1) << 32);
+        if (__hip_atomic_compare_exchange_strong(a.deque, &old, want, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                                 __HIP_MEMORY_SCOPE_AGENT))
+            return a.order[front ? (int)f : a.count - 1 - (int)b];
+    }
+}
+
+// Sum of a double-double over lanes 0 .. width-1 (width a power of two, at
+// most 64; the other lanes' values are ignored): an xor butterfly, so every
+// lane of a group of `width` ends with the same sum after log2(width)
+// dependent additions.
+__device__ __forceinline__ dd lanes_sum(dd v, int width)
+{
+    for (int off = width >> 1; off >= 1; off >>= 1) {
+        dd o;
+        o.hi = __shfl_xor(v.hi, off, 64);
+        o.lo = __shfl_xor(v.lo, off, 64);
+        v = dd_add(v, o);
+    }
+    return v;
+}
+
+// A workgroup's place in its team; `epoch` counts the team's meetings.
+struct Team {
+    int t, j, T;
+    uint32_t epoch;
+};
+
+// Thread 0: arrive at the team's counter for this epoch and wait until all
+// T members have.  The wait is bounded: after spin_limit polls, or when
+// another wait has already given up, it sets the abort flag and returns
+// false.  The caller's stores must be complete (s_waitcnt) before it.
+__device__ bool team_arrive_wait(const BatchArgs &a, const Team &tm)
+{
+    uint32_t *cnt = a.team_cnt + (size_t)tm.t * CNT_STRIDE;
+    __hip_atomic_fetch_add(cnt, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const uint32_t target = (uint32_t)tm.T * (tm.epoch + 1u);
+    for (uint32_t polls = 0;; ++polls) {
+        if (ld_coh(cnt) >= target)
+            return true;
+        if (polls >= a.spin_limit || ((polls & 15u) == 15u && ld_coh(a.abort_flag) != 0)) {
+            st_coh(a.abort_flag, 1);
+            return false;
+        }
+        __builtin_amdgcn_s_sleep(1);
+    }
+}
+
+// The team's double-double partials of one meeting: member jj's slot.
+__device__ __forceinline__ double *team_slot(const BatchArgs &a, const Team &tm, int jj)
+{
+    return a.team_slots + (((size_t)tm.t * 2 + (tm.epoch & 1u)) * tm.T + jj) * (2 * KMAX);
+}
+
+// Team barrier: every member's earlier stores are visible to every member
+// after it.  false if the team gave up.
+__device__ bool team_barrier(const BatchArgs &a, Team &tm, double *bcast)
+{
+    __builtin_amdgcn_s_waitcnt(0);  // this thread's stores have completed
+    __syncthreads();
+    if (threadIdx.x == 0)
+        bcast[0] = team_arrive_wait(a, tm) ? 1.0 : 0.0;
+    __syncthreads();
+    const bool ok = bcast[0] != 0.0;
+    __syncthreads();
+    tm.epoch++;
+    return ok;
+}
+
+// Team all-reduce of K double-double values: each member sums its
+// workgroup (waves in order), publishes the sum, meets the others, and adds
+// the T sums in member order, so every member gets the same rounded totals.
+// After the barrier wave 0 alone finishes: its lanes add the wave sums and
+// later the T members' sums, which lanes 0 .. T-1 fetch at once, by
+// butterflies (a fixed order, so every member rounds the same totals);
+// lane 0 publishes and waits in between.  It is also a team barrier.
+// false if the team gave up.
+template <int K, int NW>
+__device__ bool team_reduce(const BatchArgs &a, Team &tm, dd (&v)[K], double (&out)[K], dd (*lds)[NW],
+                            double *bcast)
+{
+    static_assert(K < 4 && K <= KMAX, "broadcast words");
+    __builtin_amdgcn_s_waitcnt(0);  // this thread's stores have completed
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int k = 0; k < K; ++k)
+        v[k] = wave_reduce(v[k]);
+    if (lane == 0) {
+#pragma unroll
+        for (int k = 0; k < K; ++k)
+            lds[k][wave] = v[k];
+    }
+    __syncthreads();
+    if (wave == 0) {
+        dd w[K];
+#pragma unroll
+        for (int k = 0; k < K; ++k)
+            w[k] = lanes_sum(lane < NW ? lds[k][lane] : dd{0.0, 0.0}, NW);
+        int ok = 1;
+        if (lane == 0) {
+            double *mine = team_slot(a, tm, tm.j);
+#pragma unroll
+            for (int k = 0; k < K; ++k) {
+                st_coh(mine + 2 * k, w[k].hi);
+                st_coh(mine + 2 * k + 1, w[k].lo);
+            }
+            __builtin_amdgcn_s_waitcnt(0);
+            ok = team_arrive_wait(a, tm) ? 1 : 0;
+        }
+        ok = __builtin_amdgcn_readfirstlane(ok);
+        if (ok) {
+            dd m[K];
+#pragma unroll
+            for (int k = 0; k < K; ++k) {
+                m[k] = dd{0.0, 0.0};
+                if (lane < tm.T) {
+                    const double *o = team_slot(a, tm, lane);
+                    m[k] = dd{ld_coh(o + 2 * k), ld_coh(o + 2 * k + 1)};
+                }
+            }
+            int width = 1;
+            while (width < tm.T)
+                width <<= 1;
+#pragma unroll
+            for (int k = 0; k < K; ++k) {
+                const dd sum = lanes_sum(m[k], width);
+                if (lane == 0)
+                    bcast[k] = sum.hi + sum.lo;
+            }
+        }
+        if (lane == 0)
+            bcast[3] = ok ? 1.0 : 0.0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < K; ++k)
+        out[k] = bcast[k];
+    const bool ok = bcast[3] != 0.0;
+    __syncthreads();
+    tm.epoch++;
+    return ok;
+}
 
 // Sum K double-double values over the workgroup and return the rounded
 // totals to every thread (wave order, then a fixed tree: reproducible).
@@ -88,7 +272,7 @@ __device__ __forceinline__ void wg_reduce(dd (&v)[K], double (&out)[K], dd (*lds
 // has many loads in flight instead of a dependent chain per nonzero.
 constexpr int RB = 8;
 
-template <typename T, typename V>
+template <typename T, typename V, bool COH = false>
 __device__ __forceinline__ T row_sum(const int32_t *__restrict__ col, const T *__restrict__ vals,
                                      const V *__restrict__ x, int j0, int j1, int shift)
 {
@@ -106,7 +290,7 @@ __device__ __forceinline__ T row_sum(const int32_t *__restrict__ col, const T *_
 #pragma unroll
         for (int k = 0; k < RB; ++k)
             if (j + k < j1)
-                g[k] = (T)x[c[k]];
+                g[k] = (T)(COH ? ld_coh(x + c[k]) : x[c[k]]);
 #pragma unroll
         for (int k = 0; k < RB; ++k)
             if (j + k < j1)
@@ -268,20 +452,206 @@ __device__ __forceinline__ void solve_one(const BatchArgs &a, int s, float *vlds
     }
 }
 
+// One system solved by a team: the steps, arithmetic and decisions of
+// solve_one, with member j taking rows [j c, (j+1) c) of the system
+// (c = ceil(n / T)) and every workgroup reduction replaced by a team
+// all-reduce.  p and x are read and written through device-coherent
+// accesses (other members gather them); r, Ap and d are only ever touched by
+// the member that owns the row.  Every member takes every decision on the
+// same reduced values, so all meet the same number of times.  false: the
+// team gave up waiting (the system keeps status B_UNSOLVED).
+template <int WGS>
+__device__ bool solve_team(const BatchArgs &a, int s, Team &tm, dd (*red)[WGS / 64], double *bcast)
+{
+    constexpr int NW = WGS / 64;
+    const int tid = threadIdx.x;
+    const int r0 = a.sys_ptr[s];
+    const int n = a.sys_ptr[s + 1] - r0;
+    const int chunk = (n + tm.T - 1) / tm.T;
+    const int lo = min(n, tm.j * chunk), hi = min(n, lo + chunk);
+    float *R = a.r32 + r0, *P = a.p32 + r0, *AP = a.ap32 + r0, *D = a.d32 + r0;
+    double *X = a.x + r0;
+    const int64_t max_iter = a.max_iter > 0 ? a.max_iter : 10 * (int64_t)n;
+    int64_t used = 0;
+    int32_t sweeps = 0, st = B_NOT_CONVERGED;
+    double bnorm = 0.0, tol = 0.0, rel = 0.0;
+    for (;;) {
+        // r_j = b - A x_j (FP64, rows left to right); r32 = (float) r_j
+        dd acc[2] = {dd{0.0, 0.0}, dd{0.0, 0.0}};
+        for (int i = lo + tid; i < hi; i += WGS) {
+            const int gi = r0 + i;
+            const double q = row_sum<double, double, true>(a.col_idx, a.vals, a.x, a.row_ptr[gi],
+                                                           a.row_ptr[gi + 1], 0);
+            const double ri = a.b[gi] - q;
+            R[i] = (float)ri;
+            dd_fma(acc[0], ri, ri);
+            if (sweeps == 0)
+                dd_fma(acc[1], a.b[gi], a.b[gi]);
+        }
+        double rr[2];
+        if (!team_reduce<2, NW>(a, tm, acc, rr, red, bcast))
+            return false;
+        if (sweeps == 0) {
+            if (rr[1] == 0.0) {  // b = 0: x = 0
+                for (int i = lo + tid; i < hi; i += WGS)
+                    st_coh(X + i, 0.0);
+                st = B_CONVERGED;
+                rel = 0.0;
+                break;
+            }
+            bnorm = sqrt(rr[1]);
+            tol = a.rtol * bnorm;
+        }
+        rel = sqrt(rr[0]) / bnorm;
+        if (!isfinite(rr[0])) {
+            st = B_BREAKDOWN;
+            break;
+        }
+        if (sqrt(rr[0]) <= tol) {
+            st = B_CONVERGED;
+            break;
+        }
+        if (sweeps >= a.max_outer || used >= max_iter) {
+            st = B_NOT_CONVERGED;
+            break;
+        }
+        // Inner solve A d = r32, d_0 = 0, by FP32 pipelined CG.
+        const int64_t cap = max_iter - used;
+        dd ai[1] = {dd{0.0, 0.0}};
+        for (int i = lo + tid; i < hi; i += WGS) {
+            const float ri = R[i];
+            st_coh(P + i, ri);
+            D[i] = 0.f;
+            dd_fma(ai[0], (double)ri, (double)ri);
+        }
+        double rri[1];
+        if (!team_reduce<1, NW>(a, tm, ai, rri, red, bcast))  // also: p complete
+            return false;
+        double rrin = rri[0];
+        int64_t k = 0;
+        int ist = B_NOT_CONVERGED;
+        const double tol_in = a.inner_rtol * sqrt(rrin);
+        if (rrin == 0.0 || (isfinite(rrin) && sqrt(rrin) <= tol_in)) {
+            ist = B_CONVERGED;  // no step
+        } else if (!isfinite(rrin)) {
+            ist = B_BREAKDOWN;
+        } else {
+            double alpha = 0.0, beta = 0.0;
+            bool first = true;
+            for (int64_t it = 0;; ++it) {
+                // it == 0: product only; it >= 1: update, then product.
+                dd acc3[3] = {dd{0.0, 0.0}, dd{0.0, 0.0}, dd{0.0, 0.0}};
+                if (!first) {
+                    const float af = (float)alpha, bf = (float)beta;
+                    for (int i = lo + tid; i < hi; i += WGS) {
+                        const float pi = ld_coh(P + i);
+                        D[i] = D[i] + af * pi;
+                        const float ri = R[i] - af * AP[i];
+                        R[i] = ri;
+                        st_coh(P + i, ri + bf * pi);
+                        dd_fma(acc3[0], (double)ri, (double)ri);
+                    }
+                    if (!team_barrier(a, tm, bcast))  // p complete before the product
+                        return false;
+                }
+                for (int i = lo + tid; i < hi; i += WGS) {
+                    const int gi = r0 + i;
+                    const float q = row_sum<float, float, true>(a.col_idx, a.vals32, P, a.row_ptr[gi],
+                                                                a.row_ptr[gi + 1], r0);
+                    AP[i] = q;
+                    dd_fma(acc3[1], (double)q, (double)ld_coh(P + i));
+                    dd_fma(acc3[2], (double)q, (double)q);
+                }
+                double d3[3];
+                if (!team_reduce<3, NW>(a, tm, acc3, d3, red, bcast))
+                    return false;
+                if (!first) {
+                    rrin = d3[0];
+                    k = it;
+                    if (!isfinite(rrin)) {
+                        ist = B_BREAKDOWN;
+                        break;
+                    }
+                    if (sqrt(rrin) <= tol_in) {
+                        ist = B_CONVERGED;
+                        break;
+                    }
+                    if (it == cap)
+                        break;
+                }
+                const double pap = d3[1], apap = d3[2];
+                if (!(pap > 0.0) || !isfinite(pap) || !isfinite(apap)) {
+                    ist = B_BREAKDOWN;
+                    break;
+                }
+                alpha = rrin / pap;
+                beta = alpha * alpha * apap / rrin - 1.0;  // Eq. (3)
+                first = false;
+            }
+        }
+        used += k;
+        if (ist == B_BREAKDOWN) {
+            st = B_BREAKDOWN;
+            break;
+        }
+        if (k == 0) {
+            st = B_NOT_CONVERGED;
+            break;
+        }
+        for (int i = lo + tid; i < hi; i += WGS)
+            st_coh(X + i, ld_coh(X + i) + (double)D[i]);
+        sweeps++;
+        if (!team_barrier(a, tm, bcast))  // x complete before the next residual
+            return false;
+    }
+    if (tm.j == 0 && tid == 0) {
+        a.status[s] = st;
+        a.iters[s] = (int32_t)used;
+        a.sweeps[s] = sweeps;
+        a.rel[s] = rel;
+    }
+    return true;
+}
+
+// A team's life: its first member claims the largest remaining system and
+// announces it at a team barrier; the team solves it and claims again.
+template <int WGS>
+__device__ void team_loop(const BatchArgs &a, Team tm, dd (*red)[WGS / 64], double *bcast, int32_t *s_sys)
+{
+    for (;;) {
+        if (threadIdx.x == 0 && tm.j == 0)
+            st_coh(a.team_sys + tm.t, claim(a, true));
+        if (!team_barrier(a, tm, bcast))
+            return;
+        if (threadIdx.x == 0)
+            *s_sys = ld_coh(a.team_sys + tm.t);
+        __syncthreads();
+        const int s = *s_sys;
+        __syncthreads();
+        if (s < 0 || !solve_team<WGS>(a, s, tm, red, bcast))
+            return;
+    }
+}
+
 template <int WGS>
 __global__ __launch_bounds__(WGS) void k_batch_mixed(BatchArgs a)
 {
     constexpr int NW = WGS / 64;
     extern __shared__ __align__(16) float vlds[];  // 4 * lds_rows floats
     __shared__ dd red[3][NW];
-    __shared__ double bcast[3];
+    __shared__ double bcast[4];
     __shared__ int32_t s_sys;
     const int tid = threadIdx.x;
+    if ((int)blockIdx.x < a.team * a.nteams) {
+        team_loop<WGS>(a, Team{(int)blockIdx.x / a.team, (int)blockIdx.x % a.team, a.team, 0u}, red, bcast,
+                       &s_sys);
+        return;
+    }
+    // Single workgroups: largest first, or smallest first beside teams.
+    const bool front = a.nteams == 0;
     for (;;) {
-        if (tid == 0) {
-            const uint32_t t = atomicAdd(a.queue, 1u);
-            s_sys = t < (uint32_t)a.count ? a.order[t] : -1;
-        }
+        if (tid == 0)
+            s_sys = claim(a, front);
         __syncthreads();
         const int s = s_sys;
         __syncthreads();
@@ -296,7 +666,21 @@ __global__ __launch_bounds__(WGS) void k_batch_mixed(BatchArgs a)
     }
 }
 
-__global__ void k_queue_reset(uint32_t *q) { *q = 0u; }
+// Before each launch: both claim counts, the team counters and the abort
+// flag to zero, every status to B_UNSOLVED (a kernel, so that a captured
+// graph holds no memset node).
+__global__ __launch_bounds__(256) void k_batch_reset(BatchArgs a)
+{
+    const int i = (int)(blockIdx.x * 256 + threadIdx.x);
+    if (i == 0) {
+        *a.deque = 0;
+        *a.abort_flag = 0;
+    }
+    if (i < a.nteams)
+        a.team_cnt[(size_t)i * CNT_STRIDE] = 0u;
+    for (int s = i; s < a.count; s += (int)(gridDim.x * 256))
+        a.status[s] = B_UNSOLVED;
+}
 
 __global__ __launch_bounds__(256) void k_to_f32_batch(int64_t n, float *out, const double *in)
 {
@@ -319,10 +703,16 @@ struct fk_batch_s {
     int32_t *sys_ptr = nullptr, *order = nullptr, *row_ptr = nullptr, *col_idx = nullptr;
     double *vals = nullptr;
     float *vals32 = nullptr, *r32 = nullptr, *p32 = nullptr, *ap32 = nullptr, *d32 = nullptr;
-    uint32_t *queue = nullptr;
+    uint64_t *deque = nullptr;
     int32_t *status = nullptr, *iters = nullptr, *sweeps = nullptr;
     double *rel = nullptr;
     int32_t max_rows = 0;
+    // team scratch, grown on demand: counters, partial slots, announced
+    // systems for up to team_cap_n teams of up to team_cap_t members
+    uint32_t *team_cnt = nullptr;
+    double *team_slots = nullptr;
+    int32_t *team_sys = nullptr, *abort_flag = nullptr;
+    int team_cap_n = 0, team_cap_t = 0;
     bool solved = false;
     // graph of the last launch configuration
     hipGraph_t graph = nullptr;
@@ -361,7 +751,12 @@ void release(fk_batch B)
     dfree(B->p32);
     dfree(B->ap32);
     dfree(B->d32);
-    dfree(B->queue);
+    dfree(B->deque);
+    dfree(B->team_cnt);
+    dfree(B->team_slots);
+    dfree(B->team_sys);
+    dfree(B->abort_flag);
+    B->team_cap_n = B->team_cap_t = 0;
     dfree(B->status);
     dfree(B->iters);
     dfree(B->sweeps);
@@ -374,9 +769,23 @@ void release(fk_batch B)
     B->graph = nullptr;
 }
 
+// Resident workgroups of the batch kernel per CU (registers, LDS, waves).
+hipError_t occupancy(int wgs, size_t lds, int *per_cu)
+{
+    switch (wgs) {
+    case 256:
+        return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, k_batch_mixed<256>, 256, lds);
+    case 512:
+        return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, k_batch_mixed<512>, 512, lds);
+    default:
+        return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, k_batch_mixed<1024>, 1024, lds);
+    }
+}
+
 hipError_t launch(const BatchArgs &a, int wgs, int grid, size_t lds, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_queue_reset, dim3(1), dim3(1), 0, s, a.queue);
+    const int rgrid = std::max(1, std::min(64, (std::max(a.count, a.nteams) + 255) / 256));
+    hipLaunchKernelGGL(k_batch_reset, dim3(rgrid), dim3(256), 0, s, a);
     switch (wgs) {
     case 256:
         hipLaunchKernelGGL(k_batch_mixed<256>, dim3(grid), dim3(256), lds, s, a);
@@ -476,7 +885,8 @@ extern "C" fk_status fk_batch_create(int32_t count, const int64_t *sys_ptr, int6
     e = e ? e : dalloc(&B->p32, (size_t)n);
     e = e ? e : dalloc(&B->ap32, (size_t)n);
     e = e ? e : dalloc(&B->d32, (size_t)n);
-    e = e ? e : dalloc(&B->queue, 1);
+    e = e ? e : dalloc(&B->deque, 1);
+    e = e ? e : dalloc(&B->abort_flag, 1);
     e = e ? e : dalloc(&B->status, (size_t)count);
     e = e ? e : dalloc(&B->iters, (size_t)count);
     e = e ? e : dalloc(&B->sweeps, (size_t)count);
@@ -526,6 +936,8 @@ extern "C" fk_status fk_batch_solve(fk_batch B, const fk_batch_opts *o, const do
         return internal_fail(FK_E_ARG, "workgroup must be 0, 256, 512 or 1024");
     if (o->flags & ~FK_FLAG_GRAPH)
         return internal_fail(FK_E_ARG, "unknown flags 0x%x", o->flags);
+    if (o->team < 0 || o->team > TEAM_MAX || o->teams < 0 || o->spin_limit < 0)
+        return internal_fail(FK_E_ARG, "team must be in [0, %d], teams and spin_limit >= 0", TEAM_MAX);
     int lds_max = 0;
     if (hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, B->device) != hipSuccess)
         lds_max = 65536;
@@ -554,7 +966,8 @@ extern "C" fk_status fk_batch_solve(fk_batch B, const fk_batch_opts *o, const do
     a.p32 = B->p32;
     a.ap32 = B->ap32;
     a.d32 = B->d32;
-    a.queue = B->queue;
+    a.deque = B->deque;
+    a.abort_flag = B->abort_flag;
     a.status = B->status;
     a.iters = B->iters;
     a.sweeps = B->sweeps;
@@ -570,7 +983,48 @@ extern "C" fk_status fk_batch_solve(fk_batch B, const fk_batch_opts *o, const do
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, B->device) != hipSuccess || cus < 1)
         cus = 256;
     const int per_cu = std::max(1, std::min(2048 / wgs, lds > 0 ? (int)(lds_max / (lds + static_lds)) : 2048 / wgs));
-    const int grid = std::max(1, std::min(B->count, cus * per_cu));
+    int grid = std::max(1, std::min(B->count, cus * per_cu));
+
+    // Teams wait for one another, so every member must be resident at once:
+    // the kernel's occupancy bounds them, and the remaining resident slots
+    // go to single workgroups.  Teams take the lowest workgroup ids, which
+    // are dispatched first.
+    //  Default (team = 0): teams of TEAM_DEFAULT over every resident
+    //  workgroup when some system does not fit in LDS, else none.
+    const int team = o->team == 0 ? (B->max_rows > lds_rows ? TEAM_DEFAULT : 1) : o->team;
+    int nteams = 0;
+    if (team > 1) {
+        int occ = 0;
+        if (occupancy(wgs, lds, &occ) != hipSuccess || occ < 1)
+            return internal_fail(FK_E_HIP, "batch: occupancy query failed");
+        const int resident = cus * occ;
+        nteams = o->teams > 0 ? o->teams : resident / team;
+        nteams = std::min({nteams, resident / team, B->count});
+        if (nteams < 1)
+            return internal_fail(FK_E_ARG, "team = %d exceeds the %d resident workgroups", team, resident);
+        grid = nteams * team + std::max(0, std::min(B->count, resident - nteams * team));
+        if (nteams > B->team_cap_n || team > B->team_cap_t) {
+            dfree(B->team_cnt);
+            dfree(B->team_slots);
+            dfree(B->team_sys);
+            B->team_cap_n = B->team_cap_t = 0;
+            hipError_t e = dalloc(&B->team_cnt, (size_t)nteams * CNT_STRIDE);
+            e = e ? e : dalloc(&B->team_slots, (size_t)nteams * 2 * team * KMAX * 2);
+            e = e ? e : dalloc(&B->team_sys, (size_t)nteams);
+            if (e != hipSuccess)
+                return e == hipErrorOutOfMemory ? internal_fail(FK_E_OOM, "batch: out of device memory")
+                                                : internal_fail(FK_E_HIP, "batch: %s", hipGetErrorString(e));
+            B->team_cap_n = nteams;
+            B->team_cap_t = team;
+        }
+    }
+    a.team = team;
+    a.nteams = nteams;
+    a.team_cnt = B->team_cnt;
+    a.team_slots = B->team_slots;
+    a.team_sys = B->team_sys;
+    const uint32_t spin_limit = o->spin_limit > 0 ? (uint32_t)o->spin_limit : TEAM_SPIN_DEFAULT;
+    a.spin_limit = spin_limit;
 
     const bool graph = (o->flags & FK_FLAG_GRAPH) != 0 && s != nullptr;
     if (graph) {
@@ -617,6 +1071,15 @@ extern "C" fk_status fk_batch_solve(fk_batch B, const fk_batch_opts *o, const do
     if (e != hipSuccess)
         return internal_fail(FK_E_HIP, "batch solve: %s", hipGetErrorString(e));
     B->solved = true;
+    if (nteams > 0) {
+        int32_t aborted = 0;
+        e = hipMemcpy(&aborted, B->abort_flag, sizeof aborted, hipMemcpyDeviceToHost);
+        if (e != hipSuccess)
+            return internal_fail(FK_E_HIP, "batch solve: %s", hipGetErrorString(e));
+        if (aborted)
+            return internal_fail(FK_E_HIP, "batch: a team wait exceeded %u polls; systems with status 3 were "
+                                 "not solved", spin_limit);
+    }
     return FK_OK;
 }
 

@@ -62,6 +62,9 @@ class _BatchOpts(ctypes.Structure):
         ("workgroup", ctypes.c_int32),
         ("lds_rows", ctypes.c_int32),
         ("flags", ctypes.c_int32),
+        ("team", ctypes.c_int32),
+        ("teams", ctypes.c_int32),
+        ("spin_limit", ctypes.c_int32),
     ]
 
 
@@ -505,7 +508,7 @@ class Net:
 
 # ------------------------------------------------------------------- batch
 
-BATCH_STATUS = {0: "converged", 1: "not_converged", 2: "breakdown"}
+BATCH_STATUS = {0: "converged", 1: "not_converged", 2: "breakdown", 3: "unsolved"}
 
 
 @dataclass
@@ -537,9 +540,10 @@ class Batch:
         self.sys_ptr = sp
 
     def solve(self, b, x, rtol: float = 1e-10, inner_rtol: float = 0.0, max_iter: int = 0,
-              max_outer: int = 0, workgroup: int = 0, lds_rows: int = 0, graph: bool = False, stream=None):
+              max_outer: int = 0, workgroup: int = 0, lds_rows: int = 0, graph: bool = False, stream=None,
+              team: int = 0, teams: int = 0, spin_limit: int = 0):
         o = _BatchOpts(float(rtol), float(inner_rtol), int(max_iter), int(max_outer), int(workgroup),
-                       int(lds_rows), FLAG_GRAPH if graph else 0)
+                       int(lds_rows), FLAG_GRAPH if graph else 0, int(team), int(teams), int(spin_limit))
         st = lib().fk_batch_solve(self._h, ctypes.byref(o), _dev_f64(b, self.n, "b"),
                                   _dev_f64(x, self.n, "x"), ctypes.c_void_p(_stream_ptr(stream)))
         _check(st, "fk_batch_solve")

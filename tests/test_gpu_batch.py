@@ -1,10 +1,11 @@
 """Batched solves (fk_batch_*) against the oracle's refinement run system by
 system (oracle.solve_mixed) on the same seeded inputs.
 
-Each workgroup solves one system with the arithmetic of the single-system
-mixed method, so status, inner iterations, sweeps, the last relative
-residual and the iterate must equal the oracle's bit for bit, whatever the
-workgroup size, the LDS limit or graph replay."""
+A system is solved by one workgroup or by a team of workgroups, either way
+with the arithmetic of the single-system mixed method, so status, inner
+iterations, sweeps, the last relative residual and the iterate must equal
+the oracle's bit for bit, whatever the workgroup size, the LDS limit, the
+team size or graph replay."""
 import numpy as np
 import pytest
 
@@ -14,7 +15,7 @@ from paper_1410_4054_amd import fk, problems as P
 
 pytestmark = pytest.mark.gpu
 
-STATUS = {0: "converged", 1: "not_converged", 2: "breakdown"}
+STATUS = {0: "converged", 1: "not_converged", 2: "breakdown", 3: "unsolved"}
 
 
 def oracle_batch(A, sp, b, x0=None, **kw):
@@ -55,6 +56,42 @@ def test_batch_matches_oracle(small, workgroup, lds_rows, device):
     assert all(r.status == "converged" for r in refs)
 
 
+@pytest.mark.parametrize("team,teams", [(2, 3), (3, 5), (8, 2), (8, 1000)],
+                         ids=["t2x3", "t3x5", "t8x2", "t8-all"])
+def test_batch_teams_match_oracle(small, team, teams, device):
+    """Teams take the largest systems and single workgroups the smallest;
+    teams=1000 is clamped to the resident workgroups, so teams solve
+    everything."""
+    A, sp, b, refs = small
+    print(f"\n[case] batch 40 systems team={team} teams={teams}", flush=True)
+    B = fk.Batch(A, sp)
+    xd = dev(np.zeros(A.n))
+    B.solve(dev(b), xd, rtol=1e-10, inner_rtol=1e-4, team=team, teams=teams)
+    assert_batch_equal(B, host(xd), refs, sp, f"team{team}x{teams}")
+
+
+def test_batch_team_gives_up(small, device):
+    """A team wait bounded at two polls gives up: the kernel still ends, the
+    call reports the error, the systems it left have status 3 and the rest
+    equal the oracle; the next solve with the default patience is whole."""
+    A, sp, b, refs = small
+    print("\n[case] batch 40 systems team=4 spin_limit=1", flush=True)
+    B = fk.Batch(A, sp)
+    xd = dev(np.zeros(A.n))
+    with pytest.raises(RuntimeError, match="team wait"):
+        B.solve(dev(b), xd, rtol=1e-10, inner_rtol=1e-4, team=4, teams=4, spin_limit=1)
+    res = B.results()
+    assert set(np.unique(res.status)) <= {0, 3} and (res.status == 3).any(), res.status
+    x = host(xd)
+    for s, ref in enumerate(refs):
+        if res.status[s] == 0:
+            r0, r1 = int(sp[s]), int(sp[s + 1])
+            assert np.array_equal(x[r0:r1], ref.x), s
+    xd = dev(np.zeros(A.n))
+    B.solve(dev(b), xd, rtol=1e-10, inner_rtol=1e-4, team=4, teams=4)
+    assert_batch_equal(B, host(xd), refs, sp, "after give-up")
+
+
 def test_batch_graph_replay(small, device):
     """The captured launch replayed several times, with other work and
     synchronisation between replays, gives the eager result every time."""
@@ -64,21 +101,25 @@ def test_batch_graph_replay(small, device):
     B = fk.Batch(A, sp)
     bd = dev(b)
     stream = torch.cuda.Stream()
-    for rep in range(3):
+    for rep in range(4):
+        team = 4 if rep >= 2 else 0
         xd = dev(np.zeros(A.n))
         torch.cuda.synchronize()
         with torch.cuda.stream(stream):
-            B.solve(bd, xd, rtol=1e-10, inner_rtol=1e-4, graph=True, stream=stream)
+            B.solve(bd, xd, rtol=1e-10, inner_rtol=1e-4, graph=True, stream=stream, team=team, teams=3)
         torch.cuda.synchronize()
-        assert_batch_equal(B, host(xd), refs, sp, f"replay {rep}")
+        assert_batch_equal(B, host(xd), refs, sp, f"replay {rep} team {team}")
         junk = torch.ones(1 << 20, device="cuda")
         junk.mul_(2.0)
         torch.cuda.synchronize()
 
 
-def test_batch_edge_cases(device):
+@pytest.mark.parametrize("team", [0, 3])
+def test_batch_edge_cases(team, device):
     """b_s = 0, a one-row system, an indefinite system (breakdown), a start
-    from a nonzero x0, a tight iteration budget and too few sweeps."""
+    from a nonzero x0, a tight iteration budget and too few sweeps; alone
+    and with teams of 3 (uneven row chunks, empty chunks on one-row
+    systems)."""
     mats = [P.poisson2d(5), P.scaled_identity(1, 3.0), P.dense_to_csr(np.diag([1.0, -1.0, 2.0, -2.0])),
             P.poisson2d(9), P.heat2d(12), P.poisson2d(20)]
     A, sp = P.block_diagonal(mats)
@@ -93,8 +134,8 @@ def test_batch_edge_cases(device):
         opts = {"rtol": 1e-10, "inner_rtol": 1e-4, **kw}
         refs = oracle_batch(A, sp, b, x0=x0, **opts)
         xd = dev(x0)
-        B.solve(dev(b), xd, **opts)
-        assert_batch_equal(B, host(xd), refs, sp, str(kw))
+        B.solve(dev(b), xd, team=team, teams=6 if team else 0, **opts)
+        assert_batch_equal(B, host(xd), refs, sp, f"team {team} {kw}")
         if not kw:
             assert refs[0].status == "converged" and not host(xd)[sp[0]:sp[1]].any()
             assert refs[2].status == "breakdown"
@@ -102,22 +143,25 @@ def test_batch_edge_cases(device):
             assert all(r.status == "not_converged" for r in refs if r.k == 0 and r.hist[0] > 0)
 
 
-def test_batch_config_full(device):
+@pytest.mark.parametrize("team", [0, 8])
+def test_batch_config_full(team, device):
     """The uneven batch of 512 shifted Laplacians (n_s in [16, 512]) to 1e-10
-    in one launch: every system converges; sampled systems equal the oracle
-    bit for bit; the true residual of every system, from the oracle's CSR
-    product, is within the tolerance."""
+    in one launch, alone and with teams of 8: every system converges;
+    sampled systems (the largest, solved by a team when there are teams,
+    among them) equal the oracle bit for bit; the true residual of every
+    system, from the oracle's CSR product, is within the tolerance."""
     A, sp, b = P.batch_problem()
-    print(f"\n[case] batch 512 systems n={A.n} nnz={A.nnz}", flush=True)
+    print(f"\n[case] batch 512 systems n={A.n} nnz={A.nnz} team={team}", flush=True)
     B = fk.Batch(A, sp)
     xd = dev(np.zeros(A.n))
-    B.solve(dev(b), xd, rtol=1e-10)
+    B.solve(dev(b), xd, rtol=1e-10, team=team)
     x = host(xd)
     res = B.results()
     assert (res.status == 0).all(), np.unique(res.status, return_counts=True)
     assert (res.rel_res <= 1e-10).all()
     sizes = np.diff(sp)
-    picks = [int(np.argmin(sizes)), int(np.argsort(sizes)[40]), int(np.argsort(sizes)[100])]
+    picks = [int(np.argmin(sizes)), int(np.argsort(sizes)[40]), int(np.argsort(sizes)[100]),
+             int(np.argmax(sizes))]
     for s in picks:
         r0, r1 = int(sp[s]), int(sp[s + 1])
         ref = oracle.solve_mixed(P.system_of(A, sp, s), b[r0:r1], rtol=1e-10, inner_rtol=1e-4)
