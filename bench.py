@@ -15,10 +15,10 @@ are those of the product on the CSR FP64 matrix of the workload, each array
 read once: 12 nnz + 4 (N + 1) for values, column indices and row pointers,
 8 N for one read of p, 8 N for one write of Ap (per iteration, with the
 update's 56 N: 12 nnz + 76 N).  The library reads fewer: it stores this
-matrix in 64-row slices (sliced ELLPACK) with the columns as 16-bit offsets
-from the row, read four at a time, 8 bytes of value per stored entry plus 8
-per group of four offsets and two int32 slice pointers per slice, as
-fk_csr_layout reports them.  Both rates are printed ("achieved" on the CSR
+matrix in 64-row slices with one slot per distinct column offset (column -
+row) of the slice, 8 bytes of value per stored entry, 4 per slot offset of
+a slice, a 4-byte mask of present slots per row and one int32 slice pointer
+per slice, as fk_csr_layout reports them.  Both rates are printed ("achieved" on the CSR
 bytes, "layout_achieved" on the bytes of the layout), and "traffic" is what
 the hardware counters measured.  Durations are measured with HIP
 events on the solver's stream that the device stamps at the start and end of
@@ -60,8 +60,9 @@ def csr_spmv_dot_bytes(n: int, nnz: int) -> int:
 
 def spmv_dot_bytes(n: int, matrix_bytes: int) -> int:
     """Compulsory bytes of one fused SpMV + 2 dots launch: the matrix data of
-    its layout (FP64 values, column indices or 16-bit offsets, row or slice
-    pointers, as fk_csr_layout reports them), one read of p, one write of Ap."""
+    its layout (FP64 values, column indices, 16-bit offsets or slot offsets
+    and row masks, row or slice pointers, as fk_csr_layout reports them),
+    one read of p, one write of Ap."""
     return matrix_bytes + 8 * n + 8 * n
 
 
@@ -252,7 +253,7 @@ def main():
         extras["spmv_layout"] = layout
         extras["spmv_stored_entries"] = entries
         # The same fused product on the other layouts, for comparison.
-        for other in ("sliced16", "sliced", "row_blocks"):
+        for other in ("slots", "sliced16", "sliced", "row_blocks"):
             if other == layout:
                 continue
             Mo = fk.Matrix(A, layout=other)
@@ -567,8 +568,8 @@ def main():
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
                      "frac": achieved / PEAK_HBM_GBS, "traffic": traffic,
                      "kernel": "fused SpMV + <p,Ap>, <Ap,Ap> (" + {
-                         "sliced16": "k_sell_rows<0,3,true>", "sliced": "k_sell_rows<0,3,false>",
-                         "row_blocks": "k_csr_rows<0,3>"}[layout] + ")",
+                         "slots": "k_sell_rows<0,3,2>", "sliced16": "k_sell_rows<0,3,1>",
+                         "sliced": "k_sell_rows<0,3,0>", "row_blocks": "k_csr_rows<0,3>"}[layout] + ")",
                      "layout": layout,
                      "bytes_per_launch": spmv_b, "avg_us": spmv_us,
                      "layout_bytes_per_launch": spmv_layout_b, "layout_achieved": layout_achieved,

@@ -104,7 +104,8 @@ enum {
     FK_LAYOUT_AUTO = 0,        /* the creation rule below                      */
     FK_LAYOUT_ROW_BLOCKS = 1,  /* the CSR arrays, cut into row blocks          */
     FK_LAYOUT_SLICED = 2,      /* the nonzeros regrouped into 64-row slices    */
-    FK_LAYOUT_SLICED16 = 3     /* the same, columns as 16-bit row offsets      */
+    FK_LAYOUT_SLICED16 = 3,    /* the same, columns as 16-bit row offsets      */
+    FK_LAYOUT_SLOTS = 4        /* 64-row slices, one slot per column offset    */
 };
 
 /*
@@ -150,14 +151,25 @@ fk_status fk_csr_blocks(fk_csr A, int32_t *nblocks, int32_t *long_rows);
  *    entry instead of 12 (6 instead of 8 for FP32 values).  Possible when every
  *    column lies within 32767 of its row (banded and stencil matrices);
  *    2 more bytes of device memory per stored entry.
- * fk_csr_create picks a sliced layout when no row has more than 64 nonzeros
- * and the padding adds at most 25 % to the entries read (SLICED16 when the
- * offsets fit, else SLICED), else ROW_BLOCKS.  fk_csr_layout reports the
+ *  - FK_LAYOUT_SLOTS: 64-row slices again, but slice s keeps one slot per
+ *    distinct column offset (column - row) of its rows, in ascending
+ *    order, 4 bytes each for the whole slice, and each row a 32-bit mask of
+ *    the slots it has; slot k of a row holds the value of column row +
+ *    offset_k (0 where absent).  A product reads about 8 bytes per stored
+ *    entry plus 4 per row.  Possible when every row's columns strictly
+ *    ascend (so slot order is CSR order), no slice has more than 32
+ *    distinct offsets (stencils and other structured-grid matrices, at any
+ *    bandwidth) and the slots pad the entries by at most 25 %.  12 more
+ *    bytes of device memory per stored entry and 4 per row.
+ * fk_csr_create picks SLOTS when possible, else a sliced layout when no row
+ * has more than 64 nonzeros and the padding adds at most 25 % to the
+ * entries read (SLICED16 when the offsets fit, else SLICED), else
+ * ROW_BLOCKS.  fk_csr_layout reports the
  * layout in use, the entries its products read per call (nnz, or the slice
  * entries with padding) and, when matrix_bytes is not NULL, the bytes of
  * matrix data one FP64 product reads (values, column indices or offsets,
- * row or slice pointers; the 16-bit offsets are read four at a time, so a
- * row's last group counts whole).
+ * row or slice pointers, slot offsets and row masks; the 16-bit offsets are
+ * read four at a time, so a row's last group counts whole).
  */
 fk_status fk_csr_layout(fk_csr A, int32_t *layout, int64_t *stored_entries, int64_t *matrix_bytes);
 
@@ -165,8 +177,9 @@ fk_status fk_csr_layout(fk_csr A, int32_t *layout, int64_t *stored_entries, int6
  * Force a layout: FK_LAYOUT_ROW_BLOCKS, FK_LAYOUT_SLICED (builds the slices
  * when absent, whatever their padding; FK_E_ARG if they would need more than
  * INT32_MAX entries), FK_LAYOUT_SLICED16 (the same; FK_E_ARG when a column
- * lies more than 32767 from its row) or FK_LAYOUT_AUTO (the creation
- * rule).  Solvers read the
+ * lies more than 32767 from its row), FK_LAYOUT_SLOTS (builds the slots when
+ * absent; FK_E_ARG when the conditions above do not hold) or
+ * FK_LAYOUT_AUTO (the creation rule).  Solvers read the
  * layout when they are created, so FK_E_STATE while any solver exists on A.
  * Runs on hip_stream and returns after it has drained.
  */

@@ -141,35 +141,49 @@ struct fk_csr_s {
     double *sell_vals = nullptr;
     int32_t nslices = 0;      // > 0 once the sliced arrays exist
     int64_t sell_entries = 0;
+    // slot layout (built when every slice has few distinct column offsets)
+    int32_t *dg_ptr = nullptr, *dg_off = nullptr;
+    uint32_t *dg_mask = nullptr;
+    double *dg_vals = nullptr;
+    int32_t dg_nslices = 0;   // > 0 once the slot arrays exist
+    int64_t dg_entries = 0;
     int32_t layout = FK_LAYOUT_ROW_BLOCKS;  // layout the products read
     // scratch reduction state for fk_spmv
     DevState *st = nullptr;
     double *partials = nullptr;
     int solvers = 0;
 
-    bool sliced() const { return layout == FK_LAYOUT_SLICED || layout == FK_LAYOUT_SLICED16; }
+    bool slots() const { return layout == FK_LAYOUT_SLOTS; }
+    bool sliced() const { return layout == FK_LAYOUT_SLICED || layout == FK_LAYOUT_SLICED16 || slots(); }
     DevCsr view() const
     {
+        if (slots())
+            return DevCsr{(int32_t)n, (int32_t)nnz, nblocks, row_ptr, col_idx, vals, blocks, block_j0,
+                          dg_nslices, dg_ptr, nullptr, dg_vals, nullptr, nullptr, dg_off, dg_mask};
         return DevCsr{(int32_t)n,  (int32_t)nnz, nblocks,  row_ptr,
                       col_idx,     vals,         blocks,   block_j0,
                       sliced() ? nslices : 0,    sell_ptr, sell_col,
                       sell_vals,   sell_ptr4,
-                      layout == FK_LAYOUT_SLICED16 ? sell_off4 : nullptr};
+                      layout == FK_LAYOUT_SLICED16 ? sell_off4 : nullptr,
+                      nullptr,     nullptr};
     }
     // Entries the products read: nnz, or the slice entries with padding.
-    int64_t stored_entries() const { return sliced() ? sell_entries : nnz; }
+    int64_t stored_entries() const { return slots() ? dg_entries : sliced() ? sell_entries : nnz; }
     int64_t sell_words4 = 0;  // 8-byte words of the 16-bit column offsets
     // Bytes of matrix data one FP64 product reads: values, column indices
     // (or offsets), row pointers (or slice pointers).
     int64_t matrix_bytes() const
     {
+        if (slots())
+            return 8 * dg_entries + 4 * (dg_entries / SLICE) + 4 * (int64_t)dg_nslices * SLICE +
+                   4 * ((int64_t)dg_nslices + 1);
         if (layout == FK_LAYOUT_SLICED16)
             return 8 * sell_entries + 8 * sell_words4 + 8 * ((int64_t)nslices + 1);
         if (layout == FK_LAYOUT_SLICED)
             return 12 * sell_entries + 4 * ((int64_t)nslices + 1);
         return 12 * nnz + 4 * (n + 1);
     }
-    int spmv_grid() const { return ::spmv_grid(sliced(), sliced() ? nslices : nblocks); }
+    int spmv_grid() const { return ::spmv_grid(sliced(), slots() ? dg_nslices : sliced() ? nslices : nblocks); }
 };
 
 DevCsr fk::internal_csr_view(fk_csr A) { return A->view(); }
@@ -363,8 +377,130 @@ static fk_status build_slices(fk_csr A, const int32_t *rp, const int32_t *ci,
     return FK_OK;
 }
 
+// Slot layout: slice s keeps one slot per distinct column offset
+// (column - row) of its rows, in ascending order, and each row a mask of
+// the slots it has.  Slot order is column order, so a row is still summed
+// left to right in CSR order, provided its columns ascend.  Applies when
+// every row's columns strictly ascend, no slice has more than DG_MAX_SLOTS
+// distinct offsets, and the slots add at most a quarter to the entries.
+// Returns the slot offsets of every slice (offs[ptr[s] .. ptr[s+1])) or
+// false.
+static bool plan_slots(const int32_t *rp, const int32_t *ci, int64_t n, int64_t nnz,
+                       std::vector<int32_t> &ptr, std::vector<int32_t> &offs)
+{
+    if (nnz <= 0)
+        return false;
+    const int64_t ns = (n + SLICE - 1) / SLICE;
+    ptr.assign((size_t)ns + 1, 0);
+    offs.clear();
+    std::vector<int32_t> d;
+    for (int64_t sl = 0; sl < ns; ++sl) {
+        d.clear();
+        for (int64_t r = sl * SLICE; r < std::min<int64_t>(n, (sl + 1) * SLICE); ++r) {
+            for (int32_t j = rp[r]; j < rp[r + 1]; ++j) {
+                if (j > rp[r] && ci[j] <= ci[j - 1])
+                    return false;  // columns must strictly ascend
+                d.push_back((int32_t)((int64_t)ci[j] - r));
+            }
+        }
+        std::sort(d.begin(), d.end());
+        d.erase(std::unique(d.begin(), d.end()), d.end());
+        if ((int64_t)d.size() > DG_MAX_SLOTS)
+            return false;
+        offs.insert(offs.end(), d.begin(), d.end());
+        ptr[(size_t)sl + 1] = (int32_t)offs.size();
+        if ((int64_t)offs.size() * SLICE * 4 > 5 * nnz + 4 * DG_MAX_SLOTS * SLICE)
+            return false;  // early out: padding beyond the quarter
+    }
+    const int64_t entries = (int64_t)offs.size() * SLICE;
+    return 4 * entries <= 5 * nnz && entries <= INT32_MAX;
+}
+
+// Uploads the slot arrays of A from host copies of its row pointers and
+// column indices and the plan of plan_slots; values are gathered on the
+// device from A->vals.
+static fk_status build_slots(fk_csr A, const int32_t *rp, const int32_t *ci, const std::vector<int32_t> &sptr,
+                             const std::vector<int32_t> &offs, hipStream_t s)
+{
+    const int64_t n = A->n;
+    const int64_t ns = (int64_t)sptr.size() - 1;
+    const int64_t entries = (int64_t)offs.size() * SLICE;
+    std::vector<int32_t> eptr, map;
+    std::vector<uint32_t> mask;
+    try {
+        eptr.resize((size_t)ns + 1);
+        map.assign((size_t)std::max<int64_t>(entries, 1), -1);
+        mask.assign((size_t)ns * SLICE, 0u);
+    } catch (const std::bad_alloc &) {
+        return fail(FK_E_OOM, "host allocation failed");
+    }
+    for (int64_t sl = 0; sl <= ns; ++sl)
+        eptr[(size_t)sl] = sptr[(size_t)sl] * SLICE;
+    for (int64_t r = 0; r < n; ++r) {
+        const int64_t sl = r / SLICE, lane = r % SLICE;
+        const int32_t *o0 = offs.data() + sptr[(size_t)sl], *o1 = offs.data() + sptr[(size_t)sl + 1];
+        for (int32_t j = rp[r]; j < rp[r + 1]; ++j) {
+            const int32_t d = (int32_t)((int64_t)ci[j] - r);
+            const int64_t k = std::lower_bound(o0, o1, d) - o0;  // present by construction
+            map[(size_t)(eptr[(size_t)sl] + k * SLICE + lane)] = j;
+            mask[(size_t)r] |= 1u << k;
+        }
+    }
+    int32_t *d_ptr = nullptr, *d_off = nullptr, *d_map = nullptr;
+    uint32_t *d_mask = nullptr;
+    double *d_vals = nullptr;
+    fk_status st = dev_alloc(&d_ptr, eptr.size(), "slot slice offsets");
+    if (st == FK_OK)
+        st = dev_alloc(&d_off, std::max<size_t>(offs.size(), 1), "slot column offsets");
+    if (st == FK_OK)
+        st = dev_alloc(&d_mask, mask.size(), "slot row masks");
+    if (st == FK_OK)
+        st = dev_alloc(&d_vals, map.size(), "slot values");
+    if (st == FK_OK)
+        st = dev_alloc(&d_map, map.size(), "slot map");
+    hipError_t e = hipSuccess;
+    if (st == FK_OK) {
+        e = hipMemcpyAsync(d_ptr, eptr.data(), eptr.size() * 4, hipMemcpyHostToDevice, s);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(d_off, offs.data(), offs.size() * 4, hipMemcpyHostToDevice, s);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(d_mask, mask.data(), mask.size() * 4, hipMemcpyHostToDevice, s);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(d_map, map.data(), map.size() * 4, hipMemcpyHostToDevice, s);
+        if (e == hipSuccess)
+            e = launch_gather_vals((int64_t)map.size(), d_vals, A->vals, d_map, vec_grid((int64_t)map.size()), s);
+        if (e == hipSuccess)
+            e = hipStreamSynchronize(s);
+        if (e != hipSuccess)
+            st = fail(FK_E_HIP, "building the slot layout: %s", hipGetErrorString(e));
+    }
+    dev_free(d_map);
+    if (st != FK_OK) {
+        dev_free(d_ptr);
+        dev_free(d_off);
+        dev_free(d_mask);
+        dev_free(d_vals);
+        return st;
+    }
+    dev_free(A->dg_ptr);
+    dev_free(A->dg_off);
+    dev_free(A->dg_mask);
+    dev_free(A->dg_vals);
+    A->dg_ptr = d_ptr;
+    A->dg_off = d_off;
+    A->dg_mask = d_mask;
+    A->dg_vals = d_vals;
+    A->dg_nslices = (int32_t)ns;
+    A->dg_entries = entries;
+    return FK_OK;
+}
+
 static void csr_release(fk_csr A)
 {
+    dev_free(A->dg_ptr);
+    dev_free(A->dg_off);
+    dev_free(A->dg_mask);
+    dev_free(A->dg_vals);
     dev_free(A->sell_ptr);
     dev_free(A->sell_col);
     dev_free(A->sell_ptr4);
@@ -478,7 +614,17 @@ extern "C" fk_status fk_csr_create(int64_t n, int64_t nnz, const int32_t *row_pt
         } catch (const std::bad_alloc &) {
             CSR_TRY(fail(FK_E_OOM, "host allocation failed"));
         }
-        if (sliced_pays(off, nnz, max_len)) {
+        std::vector<int32_t> sptr, offs;
+        bool slots = false;
+        try {
+            slots = plan_slots(rp, ci, n, nnz, sptr, offs);
+        } catch (const std::bad_alloc &) {
+            CSR_TRY(fail(FK_E_OOM, "host allocation failed"));
+        }
+        if (slots) {
+            CSR_TRY(build_slots(A, rp, ci, sptr, offs, s));
+            A->layout = FK_LAYOUT_SLOTS;
+        } else if (sliced_pays(off, nnz, max_len)) {
             CSR_TRY(build_slices(A, rp, ci, off, s));
             A->layout = A->sell_off4 ? FK_LAYOUT_SLICED16 : FK_LAYOUT_SLICED;
         }
@@ -525,7 +671,7 @@ extern "C" fk_status fk_csr_set_layout(fk_csr A, int32_t layout, void *hip_strea
     if (!A)
         return fail(FK_E_ARG, "NULL matrix");
     if (layout != FK_LAYOUT_AUTO && layout != FK_LAYOUT_ROW_BLOCKS && layout != FK_LAYOUT_SLICED &&
-        layout != FK_LAYOUT_SLICED16)
+        layout != FK_LAYOUT_SLICED16 && layout != FK_LAYOUT_SLOTS)
         return fail(FK_E_ARG, "unknown layout %d", layout);
     if (A->solvers > 0)
         return fail(FK_E_STATE, "%d solver(s) use this matrix; destroy them first", A->solvers);
@@ -533,11 +679,13 @@ extern "C" fk_status fk_csr_set_layout(fk_csr A, int32_t layout, void *hip_strea
         A->layout = FK_LAYOUT_ROW_BLOCKS;
         return FK_OK;
     }
-    if (A->nslices == 0 || layout == FK_LAYOUT_AUTO) {
-        hipStream_t s = reinterpret_cast<hipStream_t>(hip_stream);
-        std::vector<int32_t> rp, ci;
-        std::vector<int64_t> off;
-        int64_t max_len = 0;
+    hipStream_t s = reinterpret_cast<hipStream_t>(hip_stream);
+    std::vector<int32_t> rp, ci;
+    bool have_csr = false;
+    // Host copies of the CSR arrays, read back once when a layout is built.
+    auto read_back = [&]() -> fk_status {
+        if (have_csr)
+            return FK_OK;
         try {
             rp.resize((size_t)A->n + 1);
             ci.resize((size_t)std::max<int64_t>(A->nnz, 1));
@@ -551,6 +699,43 @@ extern "C" fk_status fk_csr_set_layout(fk_csr A, int32_t layout, void *hip_strea
             e = hipStreamSynchronize(s);
         if (e != hipSuccess)
             return fail(FK_E_HIP, "reading the CSR arrays back: %s", hipGetErrorString(e));
+        have_csr = true;
+        return FK_OK;
+    };
+    // The slot layout first (requested, or the creation rule's first choice).
+    if (layout == FK_LAYOUT_SLOTS || layout == FK_LAYOUT_AUTO) {
+        if (A->dg_nslices == 0) {
+            fk_status st = read_back();
+            if (st != FK_OK)
+                return st;
+            std::vector<int32_t> sptr, offs;
+            bool ok = false;
+            try {
+                ok = plan_slots(rp.data(), ci.data(), A->n, A->nnz, sptr, offs);
+            } catch (const std::bad_alloc &) {
+                return fail(FK_E_OOM, "host allocation failed");
+            }
+            if (ok) {
+                st = build_slots(A, rp.data(), ci.data(), sptr, offs, s);
+                if (st != FK_OK)
+                    return st;
+            } else if (layout == FK_LAYOUT_SLOTS) {
+                return fail(FK_E_ARG, "no slot layout: a row's columns do not ascend, a slice has more than %d "
+                            "distinct column offsets, or the slots pad the entries by more than a quarter",
+                            DG_MAX_SLOTS);
+            }
+        }
+        if (A->dg_nslices > 0) {
+            A->layout = FK_LAYOUT_SLOTS;
+            return FK_OK;
+        }
+    }
+    if (A->nslices == 0 || layout == FK_LAYOUT_AUTO) {
+        fk_status st = read_back();
+        if (st != FK_OK)
+            return st;
+        std::vector<int64_t> off;
+        int64_t max_len = 0;
         try {
             off = plan_slices(rp.data(), A->n, &max_len);
         } catch (const std::bad_alloc &) {
@@ -561,7 +746,7 @@ extern "C" fk_status fk_csr_set_layout(fk_csr A, int32_t layout, void *hip_strea
             return FK_OK;
         }
         if (A->nslices == 0) {
-            fk_status st = build_slices(A, rp.data(), ci.data(), off, s);
+            st = build_slices(A, rp.data(), ci.data(), off, s);
             if (st != FK_OK)
                 return st;
         }
@@ -841,9 +1026,10 @@ extern "C" fk_status fk_solver_create(fk_csr A, const fk_opts *o, void *hip_stre
     if (S->mixed) {
         S_HIP(hipMemsetAsync(S->st_outer, 0, sizeof(DevState), S->stream));
         if (A->nnz > 0) {
-            const bool sliced = A->sliced();
+            // the values of the layout the products read, stored_entries() of them
+            const double *src = A->slots() ? A->dg_vals : A->sliced() ? A->sell_vals : A->vals;
             const int64_t m = A->stored_entries();
-            S_HIP(launch_to_f32(m, S->vals32, sliced ? A->sell_vals : A->vals, vec_grid(m), S->stream));
+            S_HIP(launch_to_f32(m, S->vals32, src, vec_grid(m), S->stream));
         }
     }
     S->small = small_path_ok(A, S->o);

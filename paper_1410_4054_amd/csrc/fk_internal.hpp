@@ -172,7 +172,20 @@ struct DevCsr {
     // (the last group of a slice padded to four).
     const int32_t *sell_ptr4;
     const short4 *sell_off4;
+    // Slot sliced layout (when non-null, read instead of both): slice s
+    // stores w_s = (sell_ptr[s+1] - sell_ptr[s]) / SLICE slots, one per
+    // distinct column offset (column - row) of its rows, in ascending order;
+    // slot k of row s*SLICE + l holds the value of column row + dg_off[
+    // sell_ptr[s]/SLICE + k] when bit k of dg_mask[row] is set (else 0).
+    const int32_t *dg_off;
+    const uint32_t *dg_mask;
 };
+
+// Column forms of the sliced products.
+constexpr int COLS_INT32 = 0;  // sell_col
+constexpr int COLS_OFF16 = 1;  // sell_off4
+constexpr int COLS_SLOTS = 2;  // dg_off + dg_mask
+constexpr int DG_MAX_SLOTS = 32;  // slots per slice (bits of a row mask)
 
 constexpr int16_t SELL_PAD = -32768;
 

@@ -661,7 +661,7 @@ __device__ __forceinline__ void reduce_point(dd (&v)[K], const RedArgs &red, int
             return;
         // Lane l adds partials l, l + 64, ... in index order; UB of them
         // are requested before the first is added.
-        constexpr int UB = K <= 1 ? 8 : (K == 2 ? 4 : 2);
+        constexpr int UB = K <= 1 ? 4 : (K == 2 ? 2 : 1);
         for (int j0 = lane; j0 < G; j0 += 64 * UB) {
             dd t[UB][K];
 #pragma unroll
@@ -683,7 +683,7 @@ __device__ __forceinline__ void reduce_point(dd (&v)[K], const RedArgs &red, int
             }
         }
         if (kpub > 0) {
-            constexpr int UP = KP <= 1 ? 8 : 4;
+            constexpr int UP = KP <= 1 ? 2 : 2;
             for (int j0 = lane; j0 < red.npub; j0 += 64 * UP) {
                 dd t[UP][KP > 0 ? KP : 1];
 #pragma unroll
@@ -925,20 +925,34 @@ __global__ __launch_bounds__(WG, FK_SPMV_MIN_WAVES) void k_csr_rows(DevCsr A, Ro
 
 // ------------------------------------------------ sliced-layout products
 
-// Column indices of the lane's row: absolute int32 (-1 = padding), or
-// 16-bit offsets from the row (SELL_PAD = padding) four to a load.
-template <bool NARROW>
+// Column indices of the lane's row: absolute int32 (-1 = padding), 16-bit
+// offsets from the row (SELL_PAD = padding) four to a load, or the slice's
+// slot offsets (one per slice and slot, the same for every lane) with the
+// row's mask of present slots.
+template <int COLS>
 struct SliceCols {
-    const int32_t *__restrict__ col;  // sell_col + e0 + lane
-    const short4 *__restrict__ off4;  // sell_off4 + sell_ptr4[s] + lane
+    const int32_t *__restrict__ col;   // COLS_INT32: sell_col + e0 + lane
+    const short4 *__restrict__ off4;   // COLS_OFF16: sell_off4 + sell_ptr4[s] + lane
+    int slot;                          // COLS_SLOTS: lane l holds slot offset l of the slice
+    uint32_t mask;                     // COLS_SLOTS: dg_mask[row]
     int row;
 };
 
 // Columns of entries k .. k+U-1 (k a multiple of U, U of 4), -1 past width.
-template <int U, bool NARROW>
-__device__ __forceinline__ void slice_cols(const SliceCols<NARROW> &sc, int k, int width, int (&c)[U])
+template <int U, int COLS>
+__device__ __forceinline__ void slice_cols(const SliceCols<COLS> &sc, int k, int width, int (&c)[U])
 {
-    if constexpr (NARROW) {
+    if constexpr (COLS == COLS_SLOTS) {
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            c[u] = -1;
+            if (k + u < width) {
+                const int off = __builtin_amdgcn_readlane(sc.slot, k + u);  // slot k+u, to every lane
+                if (((sc.mask >> (k + u)) & 1u) != 0u)
+                    c[u] = sc.row + off;
+            }
+        }
+    } else if constexpr (COLS == COLS_OFF16) {
         static_assert(U % 4 == 0, "16-bit offsets come four to a load");
 #pragma unroll
         for (int j = 0; j < U / 4; ++j) {
@@ -961,15 +975,15 @@ __device__ __forceinline__ void slice_cols(const SliceCols<NARROW> &sc, int k, i
 // entries k = 0 .. width-1 sit SLICE apart; U of them, with their gathers,
 // are requested before the first is added.  Padding only follows a row's
 // last nonzero and is skipped.
-template <typename T, int U, bool NARROW>
-__device__ __forceinline__ T slice_row_sum(const SliceCols<NARROW> &cols, const T *__restrict__ vals,
+template <typename T, int U, int COLS>
+__device__ __forceinline__ T slice_row_sum(const SliceCols<COLS> &cols, const T *__restrict__ vals,
                                            const T *__restrict__ v, int width)
 {
     T q = T(0);
     for (int k = 0; k < width; k += U) {
         int c[U];
         T a[U], x[U];
-        slice_cols<U, NARROW>(cols, k, width, c);
+        slice_cols<U, COLS>(cols, k, width, c);
 #pragma unroll
         for (int u = 0; u < U; ++u)
             a[u] = k + u < width ? load_stream(vals + (size_t)(k + u) * SLICE) : T(0);
@@ -984,13 +998,31 @@ __device__ __forceinline__ T slice_row_sum(const SliceCols<NARROW> &cols, const 
     return q;
 }
 
+// The column form of slice sl for the lane's row.
+template <int COLS>
+__device__ __forceinline__ SliceCols<COLS> slice_cols_of(const DevCsr &A, int sl, int e0, int lane, int row)
+{
+    SliceCols<COLS> c{nullptr, nullptr, 0, 0u, row};
+    if constexpr (COLS == COLS_INT32)
+        c.col = A.sell_col + e0 + lane;
+    else if constexpr (COLS == COLS_OFF16)
+        c.off4 = A.sell_off4 + A.sell_ptr4[sl] + lane;
+    else {
+        // one coalesced load of the slice's slot offsets (width <= 32 lanes)
+        const int width = (A.sell_ptr[sl + 1] - e0) / SLICE;
+        c.slot = lane < width ? A.dg_off[e0 / SLICE + lane] : 0;
+        c.mask = A.dg_mask[row];  // sized for every row of every slice
+    }
+    return c;
+}
+
 // The products of k_csr_rows on the sliced layout: one wave per slice, one
 // lane per row, no LDS staging and no barrier before the reduction point.
 // Wave w of the grid (logical workgroup order) takes slices w, w + W, ...
 // for W waves: at any moment the chip streams one contiguous window of the
 // slices, each XCD a contiguous eighth of it.  Row sums, epilogues and the
 // reduction are those of k_csr_rows, so y is bitwise identical to it.
-template <int MODE, int DOTS, bool NARROW>
+template <int MODE, int DOTS, int COLS>
 __global__ __launch_bounds__(WG, FK_SPMV_MIN_WAVES) void k_sell_rows(DevCsr A, RowIo io, RedArgs red)
 {
     if (!runs(red))
@@ -1021,11 +1053,10 @@ __global__ __launch_bounds__(WG, FK_SPMV_MIN_WAVES) void k_sell_rows(DevCsr A, R
             if constexpr (NEED_W)
                 wrow = io.w[row];
         }
-        const SliceCols<NARROW> cols{A.sell_col + e0 + lane,
-                                     NARROW ? A.sell_off4 + A.sell_ptr4[sl] + lane : nullptr, row};
+        const SliceCols<COLS> cols = slice_cols_of<COLS>(A, sl, e0, lane, row);
         // (With int32 columns, three double-double accumulators leave room
         // for fewer entries in 64 VGPRs.)
-        const double q = slice_row_sum<double, (KA >= 3 && !NARROW ? FK_SELL_UNROLL / 2 : FK_SELL_UNROLL), NARROW>(
+        const double q = slice_row_sum<double, (KA >= 3 && COLS == COLS_INT32 ? FK_SELL_UNROLL / 2 : FK_SELL_UNROLL), COLS>(
             cols, A.sell_vals + e0 + lane, io.v, width);
         if (live) {
             if constexpr (K > 0)
@@ -1327,7 +1358,7 @@ __global__ __launch_bounds__(WG, FK_SPMV_MIN_WAVES) void k_csr_rows32(DevCsr A, 
 }
 
 // k_csr_rows32 on the sliced layout (vals32 in slice order).
-template <bool NARROW>
+template <int COLS>
 __global__ __launch_bounds__(WG, FK_SPMV_MIN_WAVES) void k_sell_rows32(DevCsr A, const float *vals32,
                                                                         const float *v, float *y,
                                                                         RedArgs red)
@@ -1345,9 +1376,8 @@ __global__ __launch_bounds__(WG, FK_SPMV_MIN_WAVES) void k_sell_rows32(DevCsr A,
         const int row = sl * SLICE + lane;
         const bool live = row < A.n;
         const float vrow = live ? v[row] : 0.f;
-        const SliceCols<NARROW> cols{A.sell_col + e0 + lane,
-                                     NARROW ? A.sell_off4 + A.sell_ptr4[sl] + lane : nullptr, row};
-        const float q = slice_row_sum<float, FK_SELL_UNROLL, NARROW>(cols, vals32 + e0 + lane, v, width);
+        const SliceCols<COLS> cols = slice_cols_of<COLS>(A, sl, e0, lane, row);
+        const float q = slice_row_sum<float, FK_SELL_UNROLL, COLS>(cols, vals32 + e0 + lane, v, width);
         if (live) {
             y[row] = q;
             dd_fma(acc[0], (double)q, (double)vrow);
@@ -2009,10 +2039,12 @@ template <int MODE, int DOTS>
 static hipError_t launch_rows(const DevCsr &A, const RowIo &io, const RedArgs &red, int grid,
                               hipStream_t s)
 {
+    if (A.nslices > 0 && A.dg_mask)
+        return launch(k_sell_rows<MODE, DOTS, COLS_SLOTS>, grid, WG, s, A, io, red);
     if (A.nslices > 0 && A.sell_off4)
-        return launch(k_sell_rows<MODE, DOTS, true>, grid, WG, s, A, io, red);
+        return launch(k_sell_rows<MODE, DOTS, COLS_OFF16>, grid, WG, s, A, io, red);
     if (A.nslices > 0)
-        return launch(k_sell_rows<MODE, DOTS, false>, grid, WG, s, A, io, red);
+        return launch(k_sell_rows<MODE, DOTS, COLS_INT32>, grid, WG, s, A, io, red);
     return launch(k_csr_rows<MODE, DOTS>, grid, WG, s, A, io, red);
 }
 
@@ -2095,10 +2127,12 @@ hipError_t launch_residual32(const DevCsr &A, const double *b, const double *x, 
 hipError_t launch_spmv32(const DevCsr &A, const float *vals32, const float *v, float *y,
                          const RedArgs &red, int grid, hipStream_t s)
 {
+    if (A.nslices > 0 && A.dg_mask)
+        return launch(k_sell_rows32<COLS_SLOTS>, grid, WG, s, A, vals32, v, y, red);
     if (A.nslices > 0 && A.sell_off4)
-        return launch(k_sell_rows32<true>, grid, WG, s, A, vals32, v, y, red);
+        return launch(k_sell_rows32<COLS_OFF16>, grid, WG, s, A, vals32, v, y, red);
     if (A.nslices > 0)
-        return launch(k_sell_rows32<false>, grid, WG, s, A, vals32, v, y, red);
+        return launch(k_sell_rows32<COLS_INT32>, grid, WG, s, A, vals32, v, y, red);
     return launch(k_csr_rows32, grid, WG, s, A, vals32, v, y, red);
 }
 

@@ -191,7 +191,7 @@ def status_str(status: int) -> str:
 
 # ------------------------------------------------------------------ matrix
 
-LAYOUTS = {"auto": 0, "row_blocks": 1, "sliced": 2, "sliced16": 3}
+LAYOUTS = {"auto": 0, "row_blocks": 1, "sliced": 2, "sliced16": 3, "slots": 4}
 
 
 class Matrix:

@@ -21,6 +21,24 @@ def rel(a, b) -> float:
     return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / (nb if nb > 0 else 1.0))
 
 
+def require_layout(A, layout):
+    """Skip the test when a forced slot layout does not apply to A: the
+    library refuses it with FK_E_ARG (test_gpu_kernels pins when it must)."""
+    if layout != "slots":
+        return
+    import pytest
+
+    M = fk.Matrix(A)
+    try:
+        M.set_layout("slots")
+    except fk.FkError as e:
+        if e.status != fk.E_ARG:
+            raise
+        pytest.skip("the slot layout does not apply to this matrix")
+    finally:
+        M.close()
+
+
 def gpu_solve(A, b, x0=None, method="cg_pipelined", rtol=1e-8, max_iter=None, matrix=None, layout=None,
               **kw):
     """Solve on the device through the C ABI; returns (SolveResult, x as numpy).

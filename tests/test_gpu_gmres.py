@@ -10,7 +10,7 @@ import numpy as np
 import pytest
 
 import oracle
-from gpu_util import dev, gpu_solve, host, rel
+from gpu_util import dev, gpu_solve, host, rel, require_layout
 from paper_1410_4054_amd import fk, problems as P
 
 pytestmark = pytest.mark.gpu
@@ -43,12 +43,13 @@ def assert_same(res, x, ref, label):
     assert np.array_equal(x, ref.x), (label, rel(x, ref.x))
 
 
-@pytest.mark.parametrize("layout", ["row_blocks", "sliced", "sliced16"])
+@pytest.mark.parametrize("layout", ["row_blocks", "sliced", "sliced16", "slots"])
 @pytest.mark.parametrize("m", [5, 30])
 @pytest.mark.parametrize("method", list(METHODS))
 @pytest.mark.parametrize("wl", list(WORKLOADS))
 def test_gmres_matches_oracle(wl, method, m, layout, device):
     A, b, x0 = WORKLOADS[wl]()
+    require_layout(A, layout)
     print(f"\n[case] {wl} {method} m={m} n={A.n} layout={layout}", flush=True)
     res, x, ref = run(A, b, x0, method, m, layout=layout)
     assert_same(res, x, ref, f"{wl}/{method}/{m}")

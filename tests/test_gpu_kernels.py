@@ -13,12 +13,20 @@ from paper_1410_4054_amd import fk, problems as P
 pytestmark = pytest.mark.gpu
 
 
-LAYOUTS = ["row_blocks", "sliced", "sliced16"]
+LAYOUTS = ["row_blocks", "sliced", "sliced16", "slots"]
 
 
 def check_spmv(A, seed=0, layout=None):
     rng = np.random.default_rng(seed)
     p = rng.uniform(-1, 1, A.n)
+    if layout == "slots" and _slot_plan(A) is None:
+        # not applicable: refused, and the matrix keeps a working layout
+        M = fk.Matrix(A)
+        with pytest.raises(fk.FkError) as e:
+            M.set_layout("slots")
+        assert e.value.status == fk.E_ARG
+        M.close()
+        return None
     M = fk.Matrix(A, layout=layout)
     if layout is not None:
         assert M.layout()[0] == layout
@@ -80,6 +88,60 @@ def _slice_entries(A):
     return int(pad.reshape(-1, 64).max(axis=1).sum() * 64), int(lens.max(initial=0)), narrow
 
 
+def _slot_plan(A):
+    """The slot layout counted from the CSR: None when a row's columns do
+    not strictly ascend, a 64-row slice has more than 32 distinct column
+    offsets or the slots pad the entries by more than a quarter; else
+    (entries, bytes of matrix data one FP64 product reads)."""
+    if A.nnz == 0:
+        return None
+    lens = np.diff(A.row_ptr)
+    rows = np.repeat(np.arange(A.n, dtype=np.int64), lens)
+    cols = A.col_idx.astype(np.int64)
+    same = rows[1:] == rows[:-1]
+    if np.any(cols[1:][same] <= cols[:-1][same]):
+        return None
+    pairs = np.unique(np.stack([rows // 64, cols - rows]), axis=1)
+    nsl = -(-A.n // 64)
+    per_slice = np.bincount(pairs[0], minlength=nsl)
+    if per_slice.max() > 32:
+        return None
+    slots = int(per_slice.sum())
+    entries = 64 * slots
+    if 4 * entries > 5 * A.nnz:
+        return None
+    return entries, 8 * entries + 4 * slots + 4 * 64 * nsl + 4 * (nsl + 1)
+
+
+def _far_stencil(n=200000, d=40000, seed=5):
+    """Three diagonals at offsets -d, 0, +d (d beyond 16 bits): no 16-bit
+    offsets, but three slots per slice and no padding."""
+    rng = np.random.default_rng(seed)
+    rows, cols = [], []
+    for off in (-d, 0, d):
+        r = np.arange(max(0, -off), min(n, n - off))
+        rows.append(r)
+        cols.append(r + off)
+    rows, cols = np.concatenate(rows), np.concatenate(cols)
+    order = np.lexsort((cols, rows))
+    rows, cols = rows[order], cols[order]
+    rp = np.zeros(n + 1, np.int32)
+    np.add.at(rp, rows + 1, 1)
+    return P.Csr(n, np.cumsum(rp).astype(np.int32), cols.astype(np.int32), rng.uniform(-1, 1, rows.size))
+
+
+def test_spmv_slots_far_offsets(device):
+    """Column offsets of +-40000: SLICED16 refused, SLOTS bit-exact."""
+    A = _far_stencil()
+    assert _slot_plan(A) == (A.nnz, 8 * A.nnz + 4 * (A.nnz // 64) + 4 * 64 * 3125 + 4 * 3126)
+    M = fk.Matrix(A)
+    assert M.layout() == ("slots", A.nnz)
+    assert fk.lib().fk_csr_set_layout(M.handle, fk.LAYOUTS["sliced16"], None) == fk.E_ARG
+    M.close()
+    check_spmv(A, seed=3, layout="slots")
+    check_spmv(A, seed=3, layout="sliced")
+
+
 def _matrix_bytes(A, layout):
     """Bytes of matrix data one FP64 product reads, counted from the CSR."""
     lens = np.diff(A.row_ptr)
@@ -97,9 +159,10 @@ def _matrix_bytes(A, layout):
 @pytest.mark.parametrize("case", ["poisson3d_17", "convdiff2d_50", "random5", "long_row", "padding",
                                   "empty"])
 def test_layout_rule(case, device):
-    """fk_csr_create takes the sliced layout when no row exceeds 64
-    nonzeros and padding adds at most a quarter; the entries it reports
-    are counted here independently."""
+    """fk_csr_create takes the slot layout when it applies, else the sliced
+    layout when no row exceeds 64 nonzeros and padding adds at most a
+    quarter; the entries and bytes it reports are counted here
+    independently."""
     if case in ("poisson3d_17", "convdiff2d_50"):
         A = P.workload(case)[0]
     elif case == "random5":
@@ -113,9 +176,14 @@ def test_layout_rule(case, device):
     entries, longest, narrow = _slice_entries(A)
     sliced = A.nnz > 0 and longest <= 64 and 4 * entries <= 5 * A.nnz
     assert sliced == (case in ("poisson3d_17", "convdiff2d_50", "random5"))
-    auto = ("sliced16" if narrow else "sliced") if sliced else "row_blocks"
+    plan = _slot_plan(A)
+    assert (plan is not None) == (case in ("poisson3d_17", "convdiff2d_50"))
+    auto = "slots" if plan else ("sliced16" if narrow else "sliced") if sliced else "row_blocks"
     M = fk.Matrix(A)
-    assert M.layout() == ((auto, entries) if sliced else ("row_blocks", A.nnz))
+    if plan:
+        assert M.layout() == ("slots", plan[0]) and M.matrix_bytes() == plan[1]
+    else:
+        assert M.layout() == ((auto, entries) if sliced else ("row_blocks", A.nnz))
     M.set_layout("sliced")
     assert M.layout() == ("sliced", entries)
     M.set_layout("row_blocks")
@@ -126,6 +194,13 @@ def test_layout_rule(case, device):
     assert M.matrix_bytes() == _matrix_bytes(A, "sliced16")
     M.set_layout("sliced")
     assert M.matrix_bytes() == _matrix_bytes(A, "sliced")
+    if plan:
+        M.set_layout("slots")
+        assert M.layout() == ("slots", plan[0]) and M.matrix_bytes() == plan[1]
+    else:
+        with pytest.raises(fk.FkError) as e:
+            M.set_layout("slots")
+        assert e.value.status == fk.E_ARG
     M.set_layout("auto")
     assert M.layout()[0] == auto
 
@@ -133,7 +208,7 @@ def test_layout_rule(case, device):
 def test_layout_errors(device):
     A = P.workload("poisson2d_33")[0]
     M = fk.Matrix(A)
-    assert fk.lib().fk_csr_set_layout(M.handle, 4, None) == fk.E_ARG
+    assert fk.lib().fk_csr_set_layout(M.handle, 5, None) == fk.E_ARG
     assert fk.lib().fk_csr_set_layout(None, 1, None) == fk.E_ARG
     # a column 40000 away from its row: no 16-bit offsets, 32-bit ones work
     far = P.Csr(40001, np.array([0, 1] + [2] * 40000, np.int32), np.array([40000, 0], np.int32),

@@ -13,7 +13,7 @@ import scipy.sparse
 
 import oracle
 from golden.make_golden import load
-from gpu_util import dev, host, rel
+from gpu_util import dev, host, rel, require_layout
 from paper_1410_4054_amd import fk, problems as P
 
 pytestmark = pytest.mark.gpu
@@ -71,10 +71,11 @@ def assert_same(res, x, ref, label=""):
     assert np.array_equal(x, ref.x), (label, rel(x, ref.x))
 
 
-@pytest.mark.parametrize("layout", ["row_blocks", "sliced", "sliced16"])
+@pytest.mark.parametrize("layout", ["row_blocks", "sliced", "sliced16", "slots"])
 @pytest.mark.parametrize("wl", list(WORKLOADS))
 def test_mixed_matches_oracle(wl, layout, device):
     A, b, x0 = WORKLOADS[wl]()
+    require_layout(A, layout)
     print(f"\n[case] mixed {wl} n={A.n} nnz={A.nnz} layout={layout}", flush=True)
     ref = oracle.solve_mixed(A, b, x0=x0, rtol=1e-10, inner_rtol=1e-4)
     res, x = mixed_solve(A, b, x0, layout=layout)

@@ -9,7 +9,7 @@ import numpy as np
 import pytest
 
 import oracle
-from gpu_util import dev, gpu_solve, host, rel
+from gpu_util import dev, gpu_solve, host, rel, require_layout
 from gpu_util import gpu_solve as _gpu_solve
 from paper_1410_4054_amd import fk, problems as P
 
@@ -46,14 +46,15 @@ def assert_same_run(res, x, ref, label=""):
 
 
 @pytest.mark.parametrize("small,layout", [(True, None), (False, "row_blocks"), (False, "sliced"),
-                                         (False, "sliced16")],
-                         ids=["auto", "grid-row_blocks", "grid-sliced", "grid-sliced16"])
+                                         (False, "sliced16"), (False, "slots")],
+                         ids=["auto", "grid-row_blocks", "grid-sliced", "grid-sliced16", "grid-slots"])
 @pytest.mark.parametrize("wl,method", CASES, ids=[f"{w}-{m}" for w, m in CASES])
 def test_matches_oracle(wl, method, small, layout, device):
     """small=True lets the library take its single-workgroup solver where it
     applies (the small pipelined cases); small=False forces the grid kernels,
     on either layout of the products."""
     A, b, x0 = WORKLOADS[wl]()
+    require_layout(A, layout)
     print(f"\n[case] {wl} {method} n={A.n} small={small} layout={layout}", flush=True)
     ref = oracle.solve(A, b, x0=x0, method=method, rtol=1e-8, trace=True)
     res, x = gpu_solve(A, b, x0, method=method, rtol=1e-8, small=small, layout=layout)
