@@ -1054,9 +1054,12 @@ __global__ __launch_bounds__(WG, FK_SPMV_MIN_WAVES) void k_sell_rows(DevCsr A, R
                 wrow = io.w[row];
         }
         const SliceCols<COLS> cols = slice_cols_of<COLS>(A, sl, e0, lane, row);
-        // (With int32 columns, three double-double accumulators leave room
-        // for fewer entries in 64 VGPRs.)
-        const double q = slice_row_sum<double, (KA >= 3 && COLS == COLS_INT32 ? FK_SELL_UNROLL / 2 : FK_SELL_UNROLL), COLS>(
+        // (Three double-double accumulators leave room for fewer entries in
+        // 64 VGPRs: 4 with int32 columns, 6 with slots.)
+        constexpr int U = KA < 3 ? FK_SELL_UNROLL
+                                 : COLS == COLS_INT32 ? FK_SELL_UNROLL / 2
+                                 : COLS == COLS_SLOTS ? 6 : FK_SELL_UNROLL;
+        const double q = slice_row_sum<double, U, COLS>(
             cols, A.sell_vals + e0 + lane, io.v, width);
         if (live) {
             if constexpr (K > 0)
