@@ -103,21 +103,6 @@ __device__ __forceinline__ int claim(const BatchArgs &a, bool front)
     }
 }
 
-// Sum of a double-double over lanes 0 .. width-1 (width a power of two, at
-// most 64; the other lanes' values are ignored): an xor butterfly, so every
-// lane of a group of `width` ends with the same sum after log2(width)
-// dependent additions.
-__device__ __forceinline__ dd lanes_sum(dd v, int width)
-{
-    for (int off = width >> 1; off >= 1; off >>= 1) {
-        dd o;
-        o.hi = __shfl_xor(v.hi, off, 64);
-        o.lo = __shfl_xor(v.lo, off, 64);
-        v = dd_add(v, o);
-    }
-    return v;
-}
-
 // A workgroup's place in its team; `epoch` counts the team's meetings.
 struct Team {
     int t, j, T;

@@ -1635,8 +1635,7 @@ __global__ __launch_bounds__(WG) void k_gm_xupdate(int64_t n, double *__restrict
 // path reduces at separate points are reduced together: one reduction per
 // CG iteration ({<r_i,r_i>, <p_i,Ap_i>, <Ap_i,Ap_i>}), two per BiCGStab
 // iteration.  The iteration count is bounded by max_iter.
-constexpr int SWG = 1024;
-constexpr int SWAVES = SWG / 64;
+constexpr int SWG = 1024;  // the most threads (and rows per thread: 8) it takes
 
 // The matrix as the single-workgroup solver reads it: from LDS when it was
 // staged there at the start of the solve, else from global memory.
@@ -1662,16 +1661,17 @@ __host__ __device__ constexpr size_t small_csr_bytes(int64_t n, int64_t nnz)
 }
 
 // Copy the matrix into LDS behind the vectors (8-byte aligned start).
+template <int WGS>
 __device__ __forceinline__ SmallCsr stage_csr(const DevCsr &A, char *base)
 {
     double *va = reinterpret_cast<double *>(base);
     int32_t *ci = reinterpret_cast<int32_t *>(va + A.nnz);
     int32_t *rp = ci + A.nnz;
-    for (int j = threadIdx.x; j < A.nnz; j += SWG) {
+    for (int j = threadIdx.x; j < A.nnz; j += WGS) {
         va[j] = A.vals[j];
         ci[j] = A.col_idx[j];
     }
-    for (int j = threadIdx.x; j <= A.n; j += SWG)
+    for (int j = threadIdx.x; j <= A.n; j += WGS)
         rp[j] = A.row_ptr[j];
     return SmallCsr{rp, ci, va};
 }
@@ -1681,7 +1681,7 @@ __device__ __forceinline__ SmallCsr stage_csr(const DevCsr &A, char *base)
 // finalize steps fins[0..nf) on thread 0, each taking its slice of the
 // rounded sums and applied only while the solve is in state needs[f].  Ends
 // past a barrier, so every thread sees the updated state.
-template <int K>
+template <int K, int NW>
 __device__ __forceinline__ void small_reduce(dd (&v)[K], dd (*lds)[KMAX], DevState &s,
                                              const int *fins, const int *ks, const int *needs,
                                              int nf, double *hist, double *scal)
@@ -1700,8 +1700,8 @@ __device__ __forceinline__ void small_reduce(dd (&v)[K], dd (*lds)[KMAX], DevSta
     if (wave == 0) {
 #pragma unroll
         for (int k = 0; k < K; ++k) {
-            dd t = lane < SWAVES ? lds[lane][k] : dd{0.0, 0.0};
-            v[k] = wave_reduce(t);
+            dd t = lane < NW ? lds[lane][k] : dd{0.0, 0.0};
+            v[k] = lanes_sum(t, NW);
         }
         if (lane == 0) {
             double d[K];
@@ -1719,24 +1719,24 @@ __device__ __forceinline__ void small_reduce(dd (&v)[K], dd (*lds)[KMAX], DevSta
     __syncthreads();
 }
 
-template <int RPT, bool STAGE>
-__global__ __launch_bounds__(SWG) void k_small_cg(DevCsr Ag, const double *__restrict__ b,
+template <int RPT, bool STAGE, int WGS>
+__global__ __launch_bounds__(WGS) void k_small_cg(DevCsr Ag, const double *__restrict__ b,
                                                   double *__restrict__ x, DevState *gst,
                                                   double *hist, double *scal)
 {
     extern __shared__ double pv[];  // p (first x0) for the gathers, n entries; then the matrix
     __shared__ DevState s;
-    __shared__ dd lds[SWAVES][KMAX];
+    __shared__ dd lds[WGS / 64][KMAX];
     const int tid = threadIdx.x;
     const int n = Ag.n;
     if (tid == 0)
         s = *gst;
-    const SmallCsr A = STAGE ? stage_csr(Ag, reinterpret_cast<char *>(pv + n))
+    const SmallCsr A = STAGE ? stage_csr<WGS>(Ag, reinterpret_cast<char *>(pv + n))
                              : SmallCsr{Ag.row_ptr, Ag.col_idx, Ag.vals};
     double xr[RPT], rr[RPT], pr[RPT], apr[RPT];
 #pragma unroll
     for (int k = 0; k < RPT; ++k) {
-        const int i = tid + k * SWG;
+        const int i = tid + k * WGS;
         xr[k] = rr[k] = pr[k] = apr[k] = 0.0;
         if (i < n) {
             xr[k] = x[i];
@@ -1748,7 +1748,7 @@ __global__ __launch_bounds__(SWG) void k_small_cg(DevCsr Ag, const double *__res
         dd acc[2] = {dd{0.0, 0.0}, dd{0.0, 0.0}};
 #pragma unroll
         for (int k = 0; k < RPT; ++k) {
-            const int i = tid + k * SWG;
+            const int i = tid + k * WGS;
             if (i < n) {
                 const double bi = b[i];
                 const double ri = bi - row_sum(A, i, pv);
@@ -1759,12 +1759,12 @@ __global__ __launch_bounds__(SWG) void k_small_cg(DevCsr Ag, const double *__res
             }
         }
         const int fins[1] = {FIN_SETUP}, ks[1] = {2}, needs[1] = {ST_RUNNING};
-        small_reduce<2>(acc, lds, s, fins, ks, needs, 1, hist, scal);
+        small_reduce<2, WGS / 64>(acc, lds, s, fins, ks, needs, 1, hist, scal);
     }
     if (s.status == ST_RUNNING) {  // A p0, alpha_0, beta_0
 #pragma unroll
         for (int k = 0; k < RPT; ++k) {
-            const int i = tid + k * SWG;
+            const int i = tid + k * WGS;
             if (i < n)
                 pv[i] = pr[k];
         }
@@ -1772,7 +1772,7 @@ __global__ __launch_bounds__(SWG) void k_small_cg(DevCsr Ag, const double *__res
         dd acc[2] = {dd{0.0, 0.0}, dd{0.0, 0.0}};
 #pragma unroll
         for (int k = 0; k < RPT; ++k) {
-            const int i = tid + k * SWG;
+            const int i = tid + k * WGS;
             if (i < n) {
                 const double q = row_sum(A, i, pv);
                 apr[k] = q;
@@ -1781,7 +1781,7 @@ __global__ __launch_bounds__(SWG) void k_small_cg(DevCsr Ag, const double *__res
             }
         }
         const int fins[1] = {FIN_CG_ALPHA}, ks[1] = {2}, needs[1] = {ST_RUNNING};
-        small_reduce<2>(acc, lds, s, fins, ks, needs, 1, hist, scal);
+        small_reduce<2, WGS / 64>(acc, lds, s, fins, ks, needs, 1, hist, scal);
     }
     while (s.status == ST_RUNNING) {
         const double alpha = s.alpha, beta = s.beta;
@@ -1789,7 +1789,7 @@ __global__ __launch_bounds__(SWG) void k_small_cg(DevCsr Ag, const double *__res
         // x_i, r_i, p_i and <r_i, r_i>
 #pragma unroll
         for (int k = 0; k < RPT; ++k) {
-            const int i = tid + k * SWG;
+            const int i = tid + k * WGS;
             if (i < n) {
                 const double pi = pr[k];
                 xr[k] = xr[k] + alpha * pi;
@@ -1805,7 +1805,7 @@ __global__ __launch_bounds__(SWG) void k_small_cg(DevCsr Ag, const double *__res
         // A p_i, <p_i, A p_i>, <A p_i, A p_i>
 #pragma unroll
         for (int k = 0; k < RPT; ++k) {
-            const int i = tid + k * SWG;
+            const int i = tid + k * WGS;
             if (i < n) {
                 const double q = row_sum(A, i, pv);
                 apr[k] = q;
@@ -1815,11 +1815,11 @@ __global__ __launch_bounds__(SWG) void k_small_cg(DevCsr Ag, const double *__res
         }
         const int fins[2] = {FIN_CG_RR, FIN_CG_ALPHA}, ks[2] = {1, 2},
                   needs[2] = {ST_RUNNING, ST_RUNNING};
-        small_reduce<3>(acc, lds, s, fins, ks, needs, 2, hist, scal);
+        small_reduce<3, WGS / 64>(acc, lds, s, fins, ks, needs, 2, hist, scal);
     }
 #pragma unroll
     for (int k = 0; k < RPT; ++k) {
-        const int i = tid + k * SWG;
+        const int i = tid + k * WGS;
         if (i < n)
             x[i] = xr[k];
     }
@@ -1827,8 +1827,8 @@ __global__ __launch_bounds__(SWG) void k_small_cg(DevCsr Ag, const double *__res
         *gst = s;
 }
 
-template <int RPT, bool STAGE>
-__global__ __launch_bounds__(SWG) void k_small_bicgstab(DevCsr Ag, const double *__restrict__ b,
+template <int RPT, bool STAGE, int WGS>
+__global__ __launch_bounds__(WGS) void k_small_bicgstab(DevCsr Ag, const double *__restrict__ b,
                                                         double *__restrict__ x, DevState *gst,
                                                         double *hist, double *scal)
 {
@@ -1837,16 +1837,16 @@ __global__ __launch_bounds__(SWG) void k_small_bicgstab(DevCsr Ag, const double 
     double *pv = lv;
     double *sv = lv + n;
     __shared__ DevState s;
-    __shared__ dd lds[SWAVES][KMAX];
+    __shared__ dd lds[WGS / 64][KMAX];
     const int tid = threadIdx.x;
     if (tid == 0)
         s = *gst;
-    const SmallCsr A = STAGE ? stage_csr(Ag, reinterpret_cast<char *>(lv + 2 * n))
+    const SmallCsr A = STAGE ? stage_csr<WGS>(Ag, reinterpret_cast<char *>(lv + 2 * n))
                              : SmallCsr{Ag.row_ptr, Ag.col_idx, Ag.vals};
     double xr[RPT], rr[RPT], pr[RPT], apr[RPT], rsr[RPT], sr[RPT], asr[RPT];
 #pragma unroll
     for (int k = 0; k < RPT; ++k) {
-        const int i = tid + k * SWG;
+        const int i = tid + k * WGS;
         xr[k] = rr[k] = pr[k] = apr[k] = rsr[k] = sr[k] = asr[k] = 0.0;
         if (i < n) {
             xr[k] = x[i];
@@ -1858,7 +1858,7 @@ __global__ __launch_bounds__(SWG) void k_small_bicgstab(DevCsr Ag, const double 
         dd acc[2] = {dd{0.0, 0.0}, dd{0.0, 0.0}};
 #pragma unroll
         for (int k = 0; k < RPT; ++k) {
-            const int i = tid + k * SWG;
+            const int i = tid + k * WGS;
             if (i < n) {
                 const double bi = b[i];
                 const double ri = bi - row_sum(A, i, pv);
@@ -1868,7 +1868,7 @@ __global__ __launch_bounds__(SWG) void k_small_bicgstab(DevCsr Ag, const double 
             }
         }
         const int fins[1] = {FIN_SETUP}, ks[1] = {2}, needs[1] = {ST_RUNNING};
-        small_reduce<2>(acc, lds, s, fins, ks, needs, 1, hist, scal);
+        small_reduce<2, WGS / 64>(acc, lds, s, fins, ks, needs, 1, hist, scal);
     }
     // <r, r0*> and <r, r> of the last update, reduced with the next <Ap, r0*>
     dd carry[2] = {dd{0.0, 0.0}, dd{0.0, 0.0}};
@@ -1877,7 +1877,7 @@ __global__ __launch_bounds__(SWG) void k_small_bicgstab(DevCsr Ag, const double 
         // A p_i and <A p_i, r0*> (with the previous update's inner products)
 #pragma unroll
         for (int k = 0; k < RPT; ++k) {
-            const int i = tid + k * SWG;
+            const int i = tid + k * WGS;
             if (i < n)
                 pv[i] = pr[k];
         }
@@ -1885,7 +1885,7 @@ __global__ __launch_bounds__(SWG) void k_small_bicgstab(DevCsr Ag, const double 
         dd acc1[3] = {carry[0], carry[1], dd{0.0, 0.0}};
 #pragma unroll
         for (int k = 0; k < RPT; ++k) {
-            const int i = tid + k * SWG;
+            const int i = tid + k * WGS;
             if (i < n) {
                 const double q = row_sum(A, i, pv);
                 apr[k] = q;
@@ -1895,7 +1895,7 @@ __global__ __launch_bounds__(SWG) void k_small_bicgstab(DevCsr Ag, const double 
         {
             const int fins[2] = {first ? FIN_NONE : FIN_B_XRP, FIN_B_ALPHA}, ks[2] = {2, 1},
                       needs[2] = {ST_RUNNING, ST_RUNNING};
-            small_reduce<3>(acc1, lds, s, fins, ks, needs, 2, hist, scal);
+            small_reduce<3, WGS / 64>(acc1, lds, s, fins, ks, needs, 2, hist, scal);
         }
         first = false;
         if (s.status != ST_RUNNING)
@@ -1905,7 +1905,7 @@ __global__ __launch_bounds__(SWG) void k_small_bicgstab(DevCsr Ag, const double 
         dd acc2[4] = {dd{0.0, 0.0}, dd{0.0, 0.0}, dd{0.0, 0.0}, dd{0.0, 0.0}};
 #pragma unroll
         for (int k = 0; k < RPT; ++k) {
-            const int i = tid + k * SWG;
+            const int i = tid + k * WGS;
             if (i < n) {
                 const double si = rr[k] - alpha * apr[k];
                 sr[k] = si;
@@ -1916,7 +1916,7 @@ __global__ __launch_bounds__(SWG) void k_small_bicgstab(DevCsr Ag, const double 
         __syncthreads();
 #pragma unroll
         for (int k = 0; k < RPT; ++k) {
-            const int i = tid + k * SWG;
+            const int i = tid + k * WGS;
             if (i < n) {
                 const double q = row_sum(A, i, sv);
                 asr[k] = q;
@@ -1928,7 +1928,7 @@ __global__ __launch_bounds__(SWG) void k_small_bicgstab(DevCsr Ag, const double 
         {
             const int fins[2] = {FIN_B_SS, FIN_B_OMEGA}, ks[2] = {1, 3},
                       needs[2] = {ST_RUNNING, ST_RUNNING};
-            small_reduce<4>(acc2, lds, s, fins, ks, needs, 2, hist, scal);
+            small_reduce<4, WGS / 64>(acc2, lds, s, fins, ks, needs, 2, hist, scal);
         }
         if (s.status == ST_HALF) {
 #pragma unroll
@@ -1947,7 +1947,7 @@ __global__ __launch_bounds__(SWG) void k_small_bicgstab(DevCsr Ag, const double 
         carry[0] = carry[1] = dd{0.0, 0.0};
 #pragma unroll
         for (int k = 0; k < RPT; ++k) {
-            const int i = tid + k * SWG;
+            const int i = tid + k * WGS;
             if (i < n) {
                 const double si = sr[k];
                 const double pi = pr[k];
@@ -1964,13 +1964,13 @@ __global__ __launch_bounds__(SWG) void k_small_bicgstab(DevCsr Ag, const double 
         if (s.it + 1 >= s.max_iter) {
             dd fin2[2] = {carry[0], carry[1]};
             const int fins[1] = {FIN_B_XRP}, ks[1] = {2}, needs[1] = {ST_RUNNING};
-            small_reduce<2>(fin2, lds, s, fins, ks, needs, 1, hist, scal);
+            small_reduce<2, WGS / 64>(fin2, lds, s, fins, ks, needs, 1, hist, scal);
             break;
         }
     }
 #pragma unroll
     for (int k = 0; k < RPT; ++k) {
-        const int i = tid + k * SWG;
+        const int i = tid + k * WGS;
         if (i < n)
             x[i] = xr[k];
     }
@@ -2236,18 +2236,48 @@ int small_rows_per_thread(int64_t n)
     return r <= 1 ? 1 : r <= 2 ? 2 : r <= 4 ? 4 : r <= 8 ? 8 : 0;
 }
 
+// Threads of the single-workgroup solver for n rows: the fewest of 256,
+// 512 and 1024 that keep at most two rows per thread, else 1024 (up to
+// eight).  Every thread joins each reduction's double-double butterfly, so
+// for small systems fewer, fuller waves finish an iteration sooner
+// (measured on 32^2: 1024 threads 5.8 us, 512 threads 4.6 us per CG
+// iteration; on 63^2, 1024 threads stay ahead).
+static int small_threads(int64_t n)
+{
+    return n <= 512 ? 256 : n <= 1024 ? 512 : SWG;
+}
+
+template <bool STAGE, int WGS>
+static hipError_t launch_small_w(int method_bicg, const DevCsr &A, const double *b, double *x,
+                                 DevState *st, double *hist, double *scal, size_t shm, hipStream_t s)
+{
+    const int64_t r = (A.n + WGS - 1) / WGS;
+    const int rpt = r <= 1 ? 1 : r <= 2 ? 2 : r <= 4 ? 4 : r <= 8 ? 8 : 0;
+    switch (rpt * 2 + (method_bicg ? 1 : 0)) {
+    case 2: return launch_shm(k_small_cg<1, STAGE, WGS>, 1, WGS, shm, s, A, b, x, st, hist, scal);
+    case 4: return launch_shm(k_small_cg<2, STAGE, WGS>, 1, WGS, shm, s, A, b, x, st, hist, scal);
+    case 3: return launch_shm(k_small_bicgstab<1, STAGE, WGS>, 1, WGS, shm, s, A, b, x, st, hist, scal);
+    case 5: return launch_shm(k_small_bicgstab<2, STAGE, WGS>, 1, WGS, shm, s, A, b, x, st, hist, scal);
+    default: break;
+    }
+    if constexpr (WGS == SWG) {
+        switch (rpt * 2 + (method_bicg ? 1 : 0)) {
+        case 8: return launch_shm(k_small_cg<4, STAGE, WGS>, 1, WGS, shm, s, A, b, x, st, hist, scal);
+        case 16: return launch_shm(k_small_cg<8, STAGE, WGS>, 1, WGS, shm, s, A, b, x, st, hist, scal);
+        default: break;
+        }
+    }
+    return hipErrorInvalidValue;
+}
+
 template <bool STAGE>
 static hipError_t launch_small_t(int method_bicg, const DevCsr &A, const double *b, double *x,
                                  DevState *st, double *hist, double *scal, size_t shm, hipStream_t s)
 {
-    switch (small_rows_per_thread(A.n) * 2 + (method_bicg ? 1 : 0)) {
-    case 2: return launch_shm(k_small_cg<1, STAGE>, 1, SWG, shm, s, A, b, x, st, hist, scal);
-    case 4: return launch_shm(k_small_cg<2, STAGE>, 1, SWG, shm, s, A, b, x, st, hist, scal);
-    case 8: return launch_shm(k_small_cg<4, STAGE>, 1, SWG, shm, s, A, b, x, st, hist, scal);
-    case 16: return launch_shm(k_small_cg<8, STAGE>, 1, SWG, shm, s, A, b, x, st, hist, scal);
-    case 3: return launch_shm(k_small_bicgstab<1, STAGE>, 1, SWG, shm, s, A, b, x, st, hist, scal);
-    case 5: return launch_shm(k_small_bicgstab<2, STAGE>, 1, SWG, shm, s, A, b, x, st, hist, scal);
-    default: return hipErrorInvalidValue;
+    switch (small_threads(A.n)) {
+    case 256: return launch_small_w<STAGE, 256>(method_bicg, A, b, x, st, hist, scal, shm, s);
+    case 512: return launch_small_w<STAGE, 512>(method_bicg, A, b, x, st, hist, scal, shm, s);
+    default: return launch_small_w<STAGE, SWG>(method_bicg, A, b, x, st, hist, scal, shm, s);
     }
 }
 
