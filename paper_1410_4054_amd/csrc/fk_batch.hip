@@ -692,10 +692,41 @@ __device__ bool solve_team(const BatchArgs &a, int s, Team &tm, dd (*red)[WGS / 
     return true;
 }
 
-// A team's life: its first member claims the largest remaining system and
-// announces it at a team barrier; the team solves it and claims again.
+// A single workgroup's life: claim a system, solve it alone (in LDS when
+// it fits), claim again.  `first`, if not negative, is a system already
+// claimed.
 template <int WGS>
-__device__ void team_loop(const BatchArgs &a, Team tm, dd (*red)[WGS / 64], double *bcast, int32_t *s_sys)
+__device__ void single_loop(const BatchArgs &a, bool front, int first, float *vlds, dd (*red)[WGS / 64],
+                            double *bcast, int32_t *s_sys)
+{
+    for (int s = first;;) {
+        if (s < 0) {
+            if (threadIdx.x == 0)
+                *s_sys = claim(a, front);
+            __syncthreads();
+            s = *s_sys;
+            __syncthreads();
+            if (s < 0)
+                return;
+        }
+        const int n = a.sys_ptr[s + 1] - a.sys_ptr[s];
+        if (n <= a.lds_rows)
+            solve_one<WGS, true>(a, s, vlds, red, bcast);
+        else
+            solve_one<WGS, false>(a, s, vlds, red, bcast);
+        __syncthreads();
+        s = -1;
+    }
+}
+
+// A team's life: its first member claims the largest remaining system and
+// announces it at a team barrier; the team solves it and claims again.  A
+// system that fits one workgroup's LDS is not worth a team, and none after
+// it is larger: the team then dissolves, its first member solves that
+// system alone and every member goes on as a single workgroup.
+template <int WGS>
+__device__ void team_loop(const BatchArgs &a, Team tm, float *vlds, dd (*red)[WGS / 64], double *bcast,
+                          int32_t *s_sys)
 {
     for (;;) {
         if (threadIdx.x == 0 && tm.j == 0)
@@ -707,7 +738,13 @@ __device__ void team_loop(const BatchArgs &a, Team tm, dd (*red)[WGS / 64], doub
         __syncthreads();
         const int s = *s_sys;
         __syncthreads();
-        if (s < 0 || !solve_team<WGS>(a, s, tm, red, bcast))
+        if (s < 0)
+            return;
+        if (a.sys_ptr[s + 1] - a.sys_ptr[s] <= a.lds_rows) {
+            single_loop<WGS>(a, true, tm.j == 0 ? s : -1, vlds, red, bcast, s_sys);
+            return;
+        }
+        if (!solve_team<WGS>(a, s, tm, red, bcast))
             return;
     }
 }
@@ -720,29 +757,13 @@ __global__ __launch_bounds__(WGS) void k_batch_mixed(BatchArgs a)
     __shared__ dd red[3][NW];
     __shared__ double bcast[4];
     __shared__ int32_t s_sys;
-    const int tid = threadIdx.x;
     if ((int)blockIdx.x < a.team * a.nteams) {
-        team_loop<WGS>(a, Team{(int)blockIdx.x / a.team, (int)blockIdx.x % a.team, a.team, 0u}, red, bcast,
-                       &s_sys);
+        team_loop<WGS>(a, Team{(int)blockIdx.x / a.team, (int)blockIdx.x % a.team, a.team, 0u}, vlds, red,
+                       bcast, &s_sys);
         return;
     }
     // Single workgroups: largest first, or smallest first beside teams.
-    const bool front = a.nteams == 0;
-    for (;;) {
-        if (tid == 0)
-            s_sys = claim(a, front);
-        __syncthreads();
-        const int s = s_sys;
-        __syncthreads();
-        if (s < 0)
-            return;
-        const int n = a.sys_ptr[s + 1] - a.sys_ptr[s];
-        if (n <= a.lds_rows)
-            solve_one<WGS, true>(a, s, vlds, red, bcast);
-        else
-            solve_one<WGS, false>(a, s, vlds, red, bcast);
-        __syncthreads();
-    }
+    single_loop<WGS>(a, a.nteams == 0, -1, vlds, red, bcast, &s_sys);
 }
 
 // Before each launch: both claim counts, the team counters and the abort

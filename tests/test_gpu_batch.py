@@ -56,18 +56,21 @@ def test_batch_matches_oracle(small, workgroup, lds_rows, device):
     assert all(r.status == "converged" for r in refs)
 
 
+@pytest.mark.parametrize("lds_rows", [-1, 0], ids=["teams", "dissolve"])
 @pytest.mark.parametrize("team,teams", [(2, 3), (3, 5), (8, 2), (8, 1000)],
                          ids=["t2x3", "t3x5", "t8x2", "t8-all"])
-def test_batch_teams_match_oracle(small, team, teams, device):
+def test_batch_teams_match_oracle(small, team, teams, lds_rows, device):
     """Teams take the largest systems and single workgroups the smallest;
-    teams=1000 is clamped to the resident workgroups, so teams solve
-    everything."""
+    teams=1000 is clamped to the resident workgroups, so teams take
+    everything.  With lds_rows=-1 no system fits LDS and teams solve them;
+    with the default limit every system here fits, so each team dissolves
+    at its first claim and its members go on alone."""
     A, sp, b, refs = small
-    print(f"\n[case] batch 40 systems team={team} teams={teams}", flush=True)
+    print(f"\n[case] batch 40 systems team={team} teams={teams} lds_rows={lds_rows}", flush=True)
     B = fk.Batch(A, sp)
     xd = dev(np.zeros(A.n))
-    B.solve(dev(b), xd, rtol=1e-10, inner_rtol=1e-4, team=team, teams=teams)
-    assert_batch_equal(B, host(xd), refs, sp, f"team{team}x{teams}")
+    B.solve(dev(b), xd, rtol=1e-10, inner_rtol=1e-4, team=team, teams=teams, lds_rows=lds_rows)
+    assert_batch_equal(B, host(xd), refs, sp, f"team{team}x{teams}/lds{lds_rows}")
 
 
 def test_batch_team_gives_up(small, device):
@@ -79,7 +82,7 @@ def test_batch_team_gives_up(small, device):
     B = fk.Batch(A, sp)
     xd = dev(np.zeros(A.n))
     with pytest.raises(RuntimeError, match="team wait"):
-        B.solve(dev(b), xd, rtol=1e-10, inner_rtol=1e-4, team=4, teams=4, spin_limit=1)
+        B.solve(dev(b), xd, rtol=1e-10, inner_rtol=1e-4, team=4, teams=4, spin_limit=1, lds_rows=-1)
     res = B.results()
     assert set(np.unique(res.status)) <= {0, 3} and (res.status == 3).any(), res.status
     x = host(xd)
@@ -88,7 +91,7 @@ def test_batch_team_gives_up(small, device):
             r0, r1 = int(sp[s]), int(sp[s + 1])
             assert np.array_equal(x[r0:r1], ref.x), s
     xd = dev(np.zeros(A.n))
-    B.solve(dev(b), xd, rtol=1e-10, inner_rtol=1e-4, team=4, teams=4)
+    B.solve(dev(b), xd, rtol=1e-10, inner_rtol=1e-4, team=4, teams=4, lds_rows=-1)
     assert_batch_equal(B, host(xd), refs, sp, "after give-up")
 
 
@@ -134,7 +137,7 @@ def test_batch_edge_cases(team, device):
         opts = {"rtol": 1e-10, "inner_rtol": 1e-4, **kw}
         refs = oracle_batch(A, sp, b, x0=x0, **opts)
         xd = dev(x0)
-        B.solve(dev(b), xd, team=team, teams=6 if team else 0, **opts)
+        B.solve(dev(b), xd, team=team, teams=6 if team else 0, lds_rows=-1 if team else 0, **opts)
         assert_batch_equal(B, host(xd), refs, sp, f"team {team} {kw}")
         if not kw:
             assert refs[0].status == "converged" and not host(xd)[sp[0]:sp[1]].any()
