@@ -225,8 +225,7 @@ __device__ bool team_reduce(const BatchArgs &a, Team &tm, dd (&v)[K], double (&o
 }
 
 // Sum K double-double values over the workgroup and return the rounded
-// totals to every thread (a butterfly in each wave, then one over the
-// waves in wave 0: a fixed order, so reproducible).
+// totals to every thread (wave order, then a fixed tree: reproducible).
 template <int K, int NW>
 __device__ __forceinline__ void wg_reduce(dd (&v)[K], double (&out)[K], dd (*lds)[NW], double *bcast)
 {
@@ -240,13 +239,11 @@ __device__ __forceinline__ void wg_reduce(dd (&v)[K], double (&out)[K], dd (*lds
             lds[k][wave] = v[k];
     }
     __syncthreads();
-    if (wave == 0) {
-#pragma unroll
-        for (int k = 0; k < K; ++k) {
-            const dd a = lanes_sum(lane < NW ? lds[k][lane] : dd{0.0, 0.0}, NW);
-            if (lane == 0)
-                bcast[k] = a.hi + a.lo;
-        }
+    if (threadIdx.x < K) {
+        dd a = lds[threadIdx.x][0];
+        for (int w = 1; w < NW; ++w)
+            a = dd_add(a, lds[threadIdx.x][w]);
+        bcast[threadIdx.x] = a.hi + a.lo;
     }
     __syncthreads();
 #pragma unroll
