@@ -79,7 +79,7 @@ def update_bytes(n: int) -> int:
 
 def kernel_source_hash() -> str:
     h = hashlib.sha256()
-    for f in ("fk_kernels.hip", "fk_internal.hpp"):
+    for f in ("fk_kernels.hip", "fk_internal.hpp", "fk_dd.hpp"):
         with open(os.path.join(ROOT, "paper_1410_4054_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
