@@ -154,9 +154,8 @@ def main():
                     help="iterations of the oracle timed for the CPU baseline")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(how it would shard is described in DESIGN.md). Run with --gpus 1.",
-              file=sys.stderr)
+        print("bench.py measures one GPU only: the library has no multi-GPU path. "
+              "Run with --gpus 1.", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
@@ -314,7 +313,7 @@ def main():
         M3g.close()
 
         log("[bench] extras: 192^3, a working set beyond the Infinity Cache")
-        # SURVEY's HBM-true point: 192^3 (N = 7.08M) moves ~0.9 GB per
+        # An HBM-bound point: 192^3 (N = 7.08M) moves ~0.9 GB per
         # iteration, far above the 256 MB Infinity Cache.  100 fixed
         # iterations per solve.
         A5, b5, _ = P.workload("poisson3d_192")
