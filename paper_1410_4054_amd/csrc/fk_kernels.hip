@@ -1484,9 +1484,12 @@ __global__ __launch_bounds__(WG) void k_gm_scale(int64_t n, double *out, const d
 
 // First stage of R[j][i] = <v_j, w> for j0 <= j < j1, all from the same w
 // (classical Gram-Schmidt).  Workgroup g owns a contiguous chunk of rows and
-// keeps GM_JT double-double accumulators at a time; its partials go to
-// part[j][g].  k_gm_multidot_fin does the second stage.
+// keeps GM_JT double-double accumulators at a time; a thread requests GM_RU
+// of its rows (and their GM_JT basis entries) at once, then adds them in row
+// order.  Its partials go to part[j][g]; k_gm_multidot_fin does the second
+// stage.
 constexpr int GM_JT = 8;
+constexpr int GM_RU = 4;
 __global__ __launch_bounds__(WG) void k_gm_multidot(int64_t n, const double *__restrict__ V,
                                                      const double *__restrict__ w, int j0, int j1,
                                                      double *part, DevState *st, uint32_t mask)
@@ -1501,12 +1504,25 @@ __global__ __launch_bounds__(WG) void k_gm_multidot(int64_t n, const double *__r
 #pragma unroll
         for (int q = 0; q < GM_JT; ++q)
             acc[q] = dd{0.0, 0.0};
-        for (int64_t t = lo + threadIdx.x; t < hi; t += WG) {
-            const double wt = w[t];
+        for (int64_t t0 = lo + threadIdx.x; t0 < hi; t0 += GM_RU * WG) {
+            double wt[GM_RU], vv[GM_RU][GM_JT];
 #pragma unroll
-            for (int q = 0; q < GM_JT; ++q)
-                if (jt + q < j1)
-                    dd_fma(acc[q], V[(size_t)(jt + q) * n + t], wt);
+            for (int u = 0; u < GM_RU; ++u) {
+                const int64_t t = t0 + (int64_t)u * WG;
+                wt[u] = t < hi ? w[t] : 0.0;
+#pragma unroll
+                for (int q = 0; q < GM_JT; ++q)
+                    vv[u][q] = (t < hi && jt + q < j1) ? V[(size_t)(jt + q) * n + t] : 0.0;
+            }
+#pragma unroll
+            for (int u = 0; u < GM_RU; ++u) {
+                if (t0 + (int64_t)u * WG < hi) {
+#pragma unroll
+                    for (int q = 0; q < GM_JT; ++q)
+                        if (jt + q < j1)
+                            dd_fma(acc[q], vv[u][q], wt[u]);
+                }
+            }
         }
         // block sums, KMAX at a time
 #pragma unroll
@@ -1553,6 +1569,8 @@ __global__ __launch_bounds__(WG) void k_gm_multidot_fin(int G, int j0, int i, do
 }
 
 // w -= sum_{j=1}^{i-1} R[j][i] v_j (j in order); first stage of <w, w>.
+// A thread updates GM_RU of its elements at once (independent chains, their
+// loads together), then adds them to <w, w> in element order.
 __global__ __launch_bounds__(WG) void k_gm_update(int64_t n, double *__restrict__ w,
                                                    const double *__restrict__ V, int i, int m1, RedArgs red)
 {
@@ -1561,12 +1579,30 @@ __global__ __launch_bounds__(WG) void k_gm_update(int64_t n, double *__restrict_
     const double *R = red.scal;
     dd acc[1] = {dd{0.0, 0.0}};
     const int64_t stride = (int64_t)gridDim.x * WG;
-    for (int64_t t = (int64_t)blockIdx.x * WG + threadIdx.x; t < n; t += stride) {
-        double wt = w[t];
-        for (int j = 1; j < i; ++j)
-            wt = wt - R[(size_t)j * m1 + i] * V[(size_t)j * n + t];
-        w[t] = wt;
-        dd_fma(acc[0], wt, wt);
+    for (int64_t t0 = (int64_t)blockIdx.x * WG + threadIdx.x; t0 < n; t0 += GM_RU * stride) {
+        double wt[GM_RU];
+#pragma unroll
+        for (int u = 0; u < GM_RU; ++u) {
+            const int64_t t = t0 + u * stride;
+            wt[u] = t < n ? w[t] : 0.0;
+        }
+        for (int j = 1; j < i; ++j) {
+            const double rj = R[(size_t)j * m1 + i];
+#pragma unroll
+            for (int u = 0; u < GM_RU; ++u) {
+                const int64_t t = t0 + u * stride;
+                if (t < n)
+                    wt[u] = wt[u] - rj * V[(size_t)j * n + t];
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < GM_RU; ++u) {
+            const int64_t t = t0 + u * stride;
+            if (t < n) {
+                w[t] = wt[u];
+                dd_fma(acc[0], wt[u], wt[u]);
+            }
+        }
     }
     reduce_point<1>(acc, red, blockIdx.x, gridDim.x);
 }
