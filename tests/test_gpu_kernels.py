@@ -142,6 +142,65 @@ def test_spmv_slots_far_offsets(device):
     check_spmv(A, seed=3, layout="sliced")
 
 
+def _banded(n, half, seed=7, descending_row=None):
+    """Rows i with columns i-half .. i+half inside [0, n): 2*half + 1
+    distinct column offsets per slice away from the ends.  descending_row:
+    that row's columns stored in descending order (still valid CSR)."""
+    rng = np.random.default_rng(seed)
+    rp, ci = [0], []
+    for i in range(n):
+        cols = list(range(max(0, i - half), min(n, i + half + 1)))
+        if i == descending_row:
+            cols = cols[::-1]
+        ci.extend(cols)
+        rp.append(len(ci))
+    return P.Csr(n, np.array(rp, np.int32), np.array(ci, np.int32), rng.uniform(-1, 1, len(ci)))
+
+
+@pytest.mark.parametrize("half,slots", [(15, True), (16, False)], ids=["31-offsets", "33-offsets"])
+def test_slots_offset_limit(half, slots, device):
+    """At most 32 distinct column offsets per slice (one mask bit each): a
+    31-diagonal band takes the slot layout, a 33-diagonal band is refused
+    and the creation rule falls back to 16-bit offsets; both products equal
+    the CSR-order sums."""
+    A = _banded(3000, half)
+    assert (_slot_plan(A) is not None) == slots
+    M = fk.Matrix(A)
+    assert M.layout()[0] == ("slots" if slots else "sliced16")
+    M.close()
+    check_spmv(A, seed=half, layout="slots")
+    check_spmv(A, seed=half, layout=None)
+
+
+def test_slots_full_mask(device):
+    """Exactly 32 distinct offsets in a slice: the 32nd slot uses the
+    mask's top bit."""
+    n = 640
+    rng = np.random.default_rng(11)
+    offs = np.array(list(range(-16, 0)) + list(range(1, 17)), dtype=np.int64)
+    rp, ci = [0], []
+    for i in range(n):
+        cols = sorted(int(i + o) for o in offs if 0 <= i + o < n)
+        ci.extend(cols)
+        rp.append(len(ci))
+    A = P.Csr(n, np.array(rp, np.int32), np.array(ci, np.int32), rng.uniform(-1, 1, len(ci)))
+    assert _slot_plan(A) is not None
+    check_spmv(A, seed=2, layout="slots")
+
+
+def test_slots_need_ascending_columns(device):
+    """A row stored with descending columns: slot order would not be CSR
+    order, so the slot layout is refused and the products keep summing
+    that row in its stored order."""
+    A = _banded(1000, 2, descending_row=500)
+    assert _slot_plan(A) is None
+    M = fk.Matrix(A)
+    assert M.layout()[0] == "sliced16"
+    M.close()
+    check_spmv(A, seed=4, layout="slots")  # refused with FK_E_ARG
+    check_spmv(A, seed=4, layout=None)
+
+
 def _matrix_bytes(A, layout):
     """Bytes of matrix data one FP64 product reads, counted from the CSR."""
     lens = np.diff(A.row_ptr)
