@@ -392,8 +392,10 @@ fk_status fk_net_train_step(fk_net N, fk_csr A, int32_t nx, int32_t ny, const do
  * (0 = as many as the resident workgroups hold; fewer if asked for more)
  * take systems from the large end, each system's rows split into one
  * contiguous chunk per member; the remaining resident workgroups take
- * systems alone from the small end.  team = 0 chooses teams of 16 when some
- * system has more rows than lds_rows, else no teams.  Team members meet at barriers
+ * systems alone from the small end.  A team whose next system fits the LDS
+ * limit dissolves: from then on its members solve systems alone.  team = 0
+ * chooses teams of 16 when some system has more rows than lds_rows, else no
+ * teams.  Team members meet at barriers
  * and all-reduces in device memory; every wait is bounded by spin_limit
  * polls (0 = about 4 M, some seconds).  A wait that runs out aborts every
  * team: systems not solved keep status 3 and the call returns FK_E_HIP
