@@ -7,9 +7,9 @@
 //      reduction point, so the test is uniform across the grid);
 //   2. each thread accumulates its share of up to KMAX inner products as
 //      error-free double-double sums (TwoProduct through fma, TwoSum);
-//   3. the workgroup combines them with wave64 cross-lane shuffles and LDS
-//      and thread 0 stores one double-double partial per inner product
-//      (the first reduction stage of Section 2.2);
+//   3. the workgroup combines them with wave64 cross-lane shuffles and LDS,
+//      and wave 0 stores one double-double partial per inner product while
+//      the other waves exit (the first reduction stage of Section 2.2);
 //   4. the second stage runs in the workgroups that arrive last: a
 //      two-level tree of arrival counters (see reduce_point) sums all
 //      partials in a fixed order, rounds once, and the very last workgroup
@@ -1713,7 +1713,7 @@ __device__ __forceinline__ SmallCsr stage_csr(const DevCsr &A, char *base)
 }
 
 // Workgroup reduction of K double-doubles (each wave by shuffles, then the
-// 16 wave results by shuffles in wave 0, a fixed tree), followed by the
+// NW wave results by shuffles in wave 0, a fixed tree), followed by the
 // finalize steps fins[0..nf) on thread 0, each taking its slice of the
 // rounded sums and applied only while the solve is in state needs[f].  Ends
 // past a barrier, so every thread sees the updated state.
