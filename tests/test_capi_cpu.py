@@ -147,3 +147,26 @@ def test_batch_null_arguments():
     assert L.fk_batch_create(0, None, 0, None, None, None, 0, None, None) == fk.E_ARG
     assert L.fk_batch_destroy(None) == fk.E_ARG
     assert L.fk_batch_results(None, None, None, None, None) == fk.E_ARG
+
+
+@pytest.mark.parametrize("cname,pyname", [("fk_opts", "_Opts"), ("fk_batch_opts", "_BatchOpts")])
+def test_struct_layouts_match_the_header(cname, pyname, tmp_path):
+    """The binding's ctypes mirrors of the option structs have the C
+    layout: gcc compiles include/fk.h and reports sizeof and every field's
+    offsetof, compared field by field."""
+    cls = getattr(fk, pyname)
+    names = [f[0] for f in cls._fields_]
+    lines = ['#include <stddef.h>', '#include <stdio.h>', '#include "fk.h"', "int main(void) {",
+             f'    printf("size %zu\\n", sizeof({cname}));']
+    lines += [f'    printf("{n} %zu\\n", offsetof({cname}, {n}));' for n in names]
+    lines += ["    return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c11", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)],
+                   check=True, capture_output=True)
+    out = dict(line.split() for line in subprocess.run([str(exe)], capture_output=True, text=True,
+                                                      check=True).stdout.splitlines())
+    assert int(out["size"]) == ctypes.sizeof(cls)
+    for n in names:
+        assert int(out[n]) == getattr(cls, n).offset, n
