@@ -257,3 +257,23 @@ def test_small_path_rows_per_thread(n, method, device):
     res, x = gpu_solve(A, b, method=method, rtol=1e-9)
     assert fk.Solver(fk.Matrix(A), method=method).uses_small()
     assert_same_run(res, x, ref, f"n={n}")
+
+
+@pytest.mark.parametrize("side,method", [(14, "cg_pipelined"), (20, "cg_pipelined"), (31, "cg_pipelined"),
+                                         (38, "cg_pipelined"), (14, "bicgstab_pipelined"),
+                                         (20, "bicgstab_pipelined"), (31, "bicgstab_pipelined"),
+                                         (38, "bicgstab_pipelined")])
+def test_small_workgroup_sizes(side, method, device):
+    """The single-workgroup solver takes 256, 512 or 1024 threads by size
+    (196 and 400 rows: 256 threads; 961: 512; 1444: 1024 with two rows per
+    thread); every combination follows the oracle's trajectory."""
+    A = P.poisson2d(side) if method == "cg_pipelined" else P.convdiff2d(side)
+    b = P.rhs_uniform(A.n, side)
+    print(f"\n[case] small {method} n={A.n}", flush=True)
+    M = fk.Matrix(A)
+    S = fk.Solver(M, method=method, rtol=1e-8)
+    assert S.uses_small(), A.n
+    S.close()
+    ref = oracle.solve(A, b, method=method, rtol=1e-8)
+    res, x = gpu_solve(A, b, method=method, rtol=1e-8, matrix=M)
+    assert_same_run(res, x, ref, f"small {method} n={A.n}")
