@@ -288,6 +288,14 @@ def main():
         t3, its3 = time_solves(torch, S3, b3d, x3d, 2)
         extras["bicgstab_convdiff2d_1024_iters_per_s"] = its3 / t3
         extras["bicgstab_convdiff2d_1024_k"] = S3.iterations()
+        # Algorithmic bytes of one pipelined BiCGStab iteration on the CSR
+        # matrix, each array read once: two products (12 nnz + 4 (N + 1) of
+        # matrix data and 24 N of vectors each), the s update (24 N) and the
+        # x, r, p update (72 N): 24 nnz + 152 N + 8.
+        bicg_b = 24 * A3.nnz + 152 * A3.n + 8
+        extras["bicgstab_convdiff2d_1024_iteration_algorithmic_bytes"] = bicg_b
+        extras["bicgstab_convdiff2d_1024_iteration_GBps"] = bicg_b * its3 / t3 / 1e9
+        extras["bicgstab_convdiff2d_1024_iteration_frac_of_peak"] = bicg_b * its3 / t3 / 1e9 / PEAK_HBM_GBS
         S3.close(); M3.close()
 
         log("[bench] extras: GMRES(30) 1024^2")
