@@ -26,6 +26,8 @@ METHODS = {
     "bicgstab_pipelined": 3,
 }
 STATUS = {0: "converged", 1: "not_converged", 2: "breakdown", 3: "bad_arg"}
+# inner products of the FP32 inner solver of solve_mixed
+ACC_MODES = {"exact": 0, "f32": 1}
 
 # Slots of one per-iteration trace record (see oracle.c).
 TRACE_SLOTS = {
@@ -63,7 +65,7 @@ class Oracle:
         lib.oracle_solve_mixed.argtypes = [
             ctypes.c_int64, i32p, i32p, f64p, f64p, f64p, ctypes.c_double, ctypes.c_double,
             ctypes.c_int32, ctypes.c_int32, f64p, i32p, ctypes.c_int32,
-            ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
+            ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32), ctypes.c_int32,
         ]
         lib.oracle_solve_mixed.restype = ctypes.c_int
         lib.oracle_solve_gmres.argtypes = [
@@ -76,6 +78,8 @@ class Oracle:
         lib.oracle_spmv_f32.restype = None
         lib.oracle_dot_f32.argtypes = [ctypes.c_int64, f32p, f32p]
         lib.oracle_dot_f32.restype = ctypes.c_double
+        lib.oracle_dot_f32acc.argtypes = [ctypes.c_int64, f32p, f32p]
+        lib.oracle_dot_f32acc.restype = ctypes.c_float
         self.lib = lib
         self.path = path
 
@@ -108,6 +112,14 @@ class Oracle:
         if a.shape != b.shape:
             raise ValueError("shape mismatch")
         return float(self.lib.oracle_dot_f32(a.size, ap, bp))
+
+    def dot_f32acc(self, a, b) -> np.float32:
+        """<a, b> of two FP32 vectors accumulated in FP32, left to right."""
+        a, ap = _f32(a)
+        b, bp = _f32(b)
+        if a.shape != b.shape:
+            raise ValueError("shape mismatch")
+        return np.float32(self.lib.oracle_dot_f32acc(a.size, ap, bp))
 
     def dot(self, a, b) -> float:
         """<a, b> by the compensated dot (twice working precision, one rounding)."""
@@ -183,8 +195,11 @@ class Oracle:
         return Result(x=x, r=r, k=kk, status=STATUS[st], hist=hist[: kk + 1].copy(), trace=None)
 
     def solve_mixed(self, A, b, x0=None, rtol: float = 1e-10, inner_rtol: float = 1e-4,
-                    max_iter: int | None = None, max_outer: int = 50) -> "MixedResult":
-        """Iterative refinement in FP64 around FP32 pipelined CG (oracle.c)."""
+                    max_iter: int | None = None, max_outer: int = 50,
+                    acc: str = "exact") -> "MixedResult":
+        """Iterative refinement in FP64 around FP32 pipelined CG (oracle.c).
+        acc: "exact" (inner products exact sums of the FP32 operands, scalars
+        in FP64) or "f32" (inner products accumulated in FP32, scalars in FP32)."""
         n = A.n
         if max_iter is None:
             max_iter = 10 * n
@@ -203,7 +218,7 @@ class Oracle:
         sw = ctypes.c_int32(0)
         st = self.lib.oracle_solve_mixed(n, rpp, cip, vp, bp, xp, float(rtol), float(inner_rtol),
                                          int(max_iter), int(max_outer), hp, ip, cap,
-                                         ctypes.byref(k), ctypes.byref(sw))
+                                         ctypes.byref(k), ctypes.byref(sw), ACC_MODES[acc])
         J = int(sw.value)
         return MixedResult(x=x, k=int(k.value), sweeps=J, status=STATUS[st],
                            hist=hist[: J + 1].copy(), inner_k=inner[:J].copy())
@@ -260,9 +275,9 @@ def solve(A, b, x0=None, method: str = "cg_pipelined", rtol: float = 1e-8,
 
 
 def solve_mixed(A, b, x0=None, rtol: float = 1e-10, inner_rtol: float = 1e-4,
-                max_iter: int | None = None, max_outer: int = 50) -> "MixedResult":
+                max_iter: int | None = None, max_outer: int = 50, acc: str = "exact") -> "MixedResult":
     return default().solve_mixed(A, b, x0=x0, rtol=rtol, inner_rtol=inner_rtol,
-                                 max_iter=max_iter, max_outer=max_outer)
+                                 max_iter=max_iter, max_outer=max_outer, acc=acc)
 
 
 def solve_gmres(A, b, x0=None, m: int = 30, pipelined: bool = True, rtol: float = 1e-8,

@@ -28,7 +28,9 @@
  *                          solved by Algorithm 2 + Eq. (3) in FP32 storage
  *                          and arithmetic, an extension of the paper's
  *                          pipelined CG (Section 3.1 cites mixed-precision
- *                          pipelined CG as prior work).
+ *                          pipelined CG as prior work); its inner products
+ *                          are either exact sums of the FP32 operands or
+ *                          accumulated in FP32 (oracle_dot_f32acc).
  *
  * Build with -ffp-contract=off: every product and every sum is rounded on its
  * own; the only fused multiply-add is the explicit fma() that extracts the
@@ -610,6 +612,20 @@ double oracle_dot_f32(int64_t n, const float *a, const float *b)
     return p + s;
 }
 
+/* <a, b> accumulated in FP32: each product a_i b_i rounded to FP32, then
+ * added to an FP32 running sum, left to right (recursive summation in single
+ * precision; its error is at most gamma_n sum |a_i b_i|, gamma_n =
+ * n u / (1 - n u), u = 2^-24). */
+float oracle_dot_f32acc(int64_t n, const float *a, const float *b)
+{
+    float acc = 0.0f;
+    for (int64_t i = 0; i < n; ++i) {
+        const float prod = a[i] * b[i];
+        acc = acc + prod;
+    }
+    return acc;
+}
+
 /* q = A p in FP32: every product and every partial row sum rounded to FP32,
  * rows summed left to right in CSR order. */
 void oracle_spmv_f32(int64_t n, const int32_t *rp, const int32_t *ci, const float *v,
@@ -666,6 +682,49 @@ static int cg_pipelined_f32(int64_t n, const int32_t *rp, const int32_t *ci, con
     return status;
 }
 
+/* The same iteration (Algorithm 2 with Eq. (3), d_0 = 0) entirely in FP32:
+ * FP32 vectors, FP32 products, inner products accumulated in FP32
+ * (oracle_dot_f32acc) and the scalars alpha, beta, the tolerance and the
+ * test formed in FP32.  Stops when ||r_i|| <= rtol ||r_0|| or after cap
+ * iterations; r is overwritten by the inner residual.  Returns OR_*. */
+static int cg_pipelined_f32acc(int64_t n, const int32_t *rp, const int32_t *ci, const float *v,
+                               float *r, float *d, float *p, float *ap, double rtol, int64_t cap,
+                               int64_t *k_out)
+{
+    int64_t k = 0;
+    for (int64_t j = 0; j < n; ++j) { d[j] = 0.0f; p[j] = r[j]; }
+    float rr = oracle_dot_f32acc(n, r, r);
+    *k_out = 0;
+    if (rr == 0.0f) return OR_CONVERGED;                    /* r = 0: d = 0, no step */
+    if (!isfinite(rr)) return OR_BREAKDOWN;
+    const float tol = (float)rtol * sqrtf(rr);
+    if (sqrtf(rr) <= tol) return OR_CONVERGED;
+    oracle_spmv_f32(n, rp, ci, v, p, ap);
+    float pap = oracle_dot_f32acc(n, p, ap), apap = oracle_dot_f32acc(n, ap, ap);
+    if (!(pap > 0.0f) || !isfinite(pap) || !isfinite(apap)) return OR_BREAKDOWN;
+    float alpha = rr / pap;
+    float beta = alpha * alpha * apap / rr - 1.0f;          /* Eq. (3) */
+    int status = OR_NOT_CONVERGED;
+    for (int64_t i = 1; i <= cap; ++i) {
+        for (int64_t j = 0; j < n; ++j) d[j] = d[j] + alpha * p[j];
+        for (int64_t j = 0; j < n; ++j) r[j] = r[j] - alpha * ap[j];
+        for (int64_t j = 0; j < n; ++j) p[j] = r[j] + beta * p[j];
+        rr = oracle_dot_f32acc(n, r, r);
+        k = i;
+        if (!isfinite(rr)) { status = OR_BREAKDOWN; break; }
+        if (sqrtf(rr) <= tol) { status = OR_CONVERGED; break; }
+        if (i == cap) break;
+        oracle_spmv_f32(n, rp, ci, v, p, ap);
+        pap = oracle_dot_f32acc(n, p, ap);
+        apap = oracle_dot_f32acc(n, ap, ap);
+        if (!(pap > 0.0f) || !isfinite(pap) || !isfinite(apap)) { status = OR_BREAKDOWN; break; }
+        alpha = rr / pap;
+        beta = alpha * alpha * apap / rr - 1.0f;
+    }
+    *k_out = k;
+    return status;
+}
+
 /*
  * Iterative refinement: for j = 0, 1, ...: r_j = b - A x_j in FP64; stop when
  * ||r_j|| <= rtol ||b||; solve A d = (float) r_j with the FP32 pipelined CG
@@ -674,17 +733,21 @@ static int cg_pipelined_f32(int64_t n, const int32_t *rp, const int32_t *ci, con
  * whose inner solve makes no iteration ends the solve (not converged).
  * hist[j] = ||r_j||/||b|| (j = 0..sweeps, up to cap); inner_k[j] (may be
  * NULL) = inner iterations of sweep j.  *k_out = inner iterations in total.
+ * acc selects the inner solver: 0 = cg_pipelined_f32 (inner products exact
+ * sums of the FP32 operands, scalars in FP64), 1 = cg_pipelined_f32acc
+ * (inner products accumulated in FP32, scalars in FP32).
  * Returns OR_*; b = 0 gives x = 0.
  */
 int oracle_solve_mixed(int64_t n, const int32_t *row_ptr, const int32_t *col_idx,
                        const double *vals, const double *b, double *x, double rtol,
                        double inner_rtol, int32_t max_iter, int32_t max_outer, double *hist,
-                       int32_t *inner_k, int32_t cap, int32_t *k_out, int32_t *sweeps_out)
+                       int32_t *inner_k, int32_t cap, int32_t *k_out, int32_t *sweeps_out,
+                       int32_t acc)
 {
     *k_out = 0;
     *sweeps_out = 0;
     if (n <= 0 || !row_ptr || !col_idx || !vals || !b || !x || max_iter < 0 || max_outer < 0 ||
-        !(rtol >= 0.0) || !(inner_rtol >= 0.0))
+        !(rtol >= 0.0) || !(inner_rtol >= 0.0) || acc < 0 || acc > 1)
         return OR_BAD_ARG;
     const int64_t nnz = row_ptr[n];
     csr_t A = {n, row_ptr, col_idx, vals};
@@ -717,8 +780,10 @@ int oracle_solve_mixed(int64_t n, const int32_t *row_ptr, const int32_t *col_idx
         if (sweeps >= max_outer || used >= max_iter) { status = OR_NOT_CONVERGED; break; }
         for (int64_t j = 0; j < n; ++j) r32[j] = (float)r[j];
         int64_t kj = 0;
-        int st = cg_pipelined_f32(n, row_ptr, col_idx, v32, r32, d, p, ap, inner_rtol,
-                                  (int64_t)max_iter - used, &kj);
+        int st = acc == 0 ? cg_pipelined_f32(n, row_ptr, col_idx, v32, r32, d, p, ap, inner_rtol,
+                                             (int64_t)max_iter - used, &kj)
+                          : cg_pipelined_f32acc(n, row_ptr, col_idx, v32, r32, d, p, ap, inner_rtol,
+                                                (int64_t)max_iter - used, &kj);
         used += kj;
         if (inner_k && sweeps < cap) inner_k[sweeps] = (int32_t)kj;
         if (st == OR_BREAKDOWN) { status = OR_BREAKDOWN; break; }

@@ -387,16 +387,56 @@ def pin_f32_products(O):
         assert abs(Fraction(got) - exact) <= abs(exact) * Fraction(2) ** -52, (n, got, float(exact))
 
 
+def pin_f32acc_dot(O):
+    """The FP32-accumulating dot of the second inner solver: within the
+    recursive-summation bound gamma_n sum |a_i b_i| (u = 2^-24) of the exact
+    rational value; exact when every product and partial sum is a small
+    integer; each product rounded to FP32 before it is added ((1 + 2^-12)^2
+    gives 1 + 2^-11, not the exact 1 + 2^-11 + 2^-24); and the sum kept in
+    FP32 left to right (2^24 + 1 + 1 + 1 + 1 stays 2^24 by round-to-even,
+    where a wider or reordered sum would not)."""
+    u = Fraction(1, 2 ** 24)
+    rng = np.random.default_rng(21)
+    for n in (1, 7, 300, 4000):
+        a = rng.standard_normal(n).astype(np.float32)
+        b = rng.standard_normal(n).astype(np.float32)
+        prods = [Fraction(float(x)) * Fraction(float(y)) for x, y in zip(a, b)]
+        exact = sum(prods)
+        gamma = n * u / (1 - n * u)
+        got = O.dot_f32acc(a, b)
+        assert isinstance(got, np.float32)
+        assert abs(Fraction(float(got)) - exact) <= gamma * sum(abs(t) for t in prods), (n, got)
+    ia = rng.integers(-50, 51, 500).astype(np.float32)
+    ib = rng.integers(-50, 51, 500).astype(np.float32)
+    assert float(O.dot_f32acc(ia, ib)) == float(np.dot(ia.astype(np.int64), ib.astype(np.int64)))
+    one = np.float32(1.0 + 2.0 ** -12)
+    assert float(O.dot_f32acc(np.array([one]), np.array([one]))) == 1.0 + 2.0 ** -11
+    # 2^-25 first, then (1 + 2^-12)^2: rounding the product first gives
+    # 1 + 2^-11 and the sum stays there; one rounding of the exact sum would
+    # give 1 + 2^-11 + 2^-23.
+    sa = np.array([2.0 ** -12, one], dtype=np.float32)
+    sb = np.array([2.0 ** -13, one], dtype=np.float32)
+    assert float(O.dot_f32acc(sa, sb)) == 1.0 + 2.0 ** -11
+    big = np.array([2.0 ** 24, 1, 1, 1, 1], dtype=np.float32)
+    assert float(O.dot_f32acc(big, np.ones(5, np.float32))) == 2.0 ** 24
+    assert float(O.dot_f32acc(big[::-1].copy(), np.ones(5, np.float32))) == 2.0 ** 24 + 4
+    assert float(O.dot_f32acc(np.zeros(0, np.float32), np.zeros(0, np.float32))) == 0.0
+
+
+ACCS = ("exact", "f32")
+
+
 def pin_mixed_identity(O):
     """A = 4 I with b exactly representable in FP32: the inner CG takes one
     step (alpha = 1/4, beta = 0), the FP64 update gives x = b/4 exactly and
     the next residual is 0, so one sweep and one inner iteration."""
     A = P.scaled_identity(12, 4.0)
     b = np.arange(-6.0, 6.0) / 8.0 + 0.03125
-    res = O.solve_mixed(A, b, rtol=1e-14)
-    assert res.status == "converged" and res.sweeps == 1 and res.k == 1, res
-    assert np.array_equal(res.x, b / 4.0)
-    assert res.hist[1] == 0.0 and res.hist[0] == 1.0
+    for acc in ACCS:
+        res = O.solve_mixed(A, b, rtol=1e-14, acc=acc)
+        assert res.status == "converged" and res.sweeps == 1 and res.k == 1, (acc, res)
+        assert np.array_equal(res.x, b / 4.0)
+        assert res.hist[1] == 0.0 and res.hist[0] == 1.0
 
 
 def pin_mixed_eigen_termination(O):
@@ -407,9 +447,10 @@ def pin_mixed_eigen_termination(O):
     A = P.poisson2d(n)
     picks = [(1, 2), (3, 3), (6, 1)]
     b = sum((i + 1.0) * P.laplacian_eigvec_2d(n, j, k) for i, (j, k) in enumerate(picks))
-    res = O.solve_mixed(A, b, rtol=1e-10, inner_rtol=1e-3)
-    assert res.status == "converged", res
-    assert res.inner_k[0] == len(picks), res.inner_k
+    for acc in ACCS:
+        res = O.solve_mixed(A, b, rtol=1e-10, inner_rtol=1e-3, acc=acc)
+        assert res.status == "converged", (acc, res)
+        assert res.inner_k[0] == len(picks), (acc, res.inner_k)
 
 
 def pin_mixed_exact_poisson(O):
@@ -423,14 +464,15 @@ def pin_mixed_exact_poisson(O):
         (P.poisson3d(15), _dst_solve_3d(15, P.rhs_uniform(15 ** 3, 0))),
     ):
         b = P.rhs_uniform(A.n, 0)
-        res = O.solve_mixed(A, b, rtol=rtol, inner_rtol=1e-4)
-        assert res.status == "converged", res
-        assert _rel(res.x, xs) <= kappa * rtol * 1.01, _rel(res.x, xs)
-        tr = float(np.linalg.norm(b - A.to_scipy() @ res.x) / np.linalg.norm(b))
-        assert tr <= rtol and abs(res.hist[-1] - tr) <= 1e-3 * tr, (tr, res.hist)
-        assert res.hist[0] == 1.0
-        assert np.all(res.hist[1:] <= 1e-3 * res.hist[:-1]), res.hist
-        assert res.k == int(res.inner_k.sum())
+        for acc in ACCS:
+            res = O.solve_mixed(A, b, rtol=rtol, inner_rtol=1e-4, acc=acc)
+            assert res.status == "converged", (acc, res)
+            assert _rel(res.x, xs) <= kappa * rtol * 1.01, (acc, _rel(res.x, xs))
+            tr = float(np.linalg.norm(b - A.to_scipy() @ res.x) / np.linalg.norm(b))
+            assert tr <= rtol and abs(res.hist[-1] - tr) <= 1e-3 * tr, (acc, tr, res.hist)
+            assert res.hist[0] == 1.0
+            assert np.all(res.hist[1:] <= 1e-3 * res.hist[:-1]), (acc, res.hist)
+            assert res.k == int(res.inner_k.sum())
 
 
 def pin_mixed_fp32_floor(O):
@@ -440,13 +482,14 @@ def pin_mixed_fp32_floor(O):
     recorded history entry."""
     A = P.poisson2d(31)
     b = P.rhs_uniform(A.n, 1)
-    res = O.solve_mixed(A, b, rtol=1e-14, inner_rtol=1e-13, max_iter=400, max_outer=1)
-    assert res.sweeps == 1 and res.status == "not_converged", res
-    tr = float(np.linalg.norm(b - A.to_scipy() @ res.x) / np.linalg.norm(b))
-    assert 1e-9 < tr < 1e-4, tr
-    assert abs(res.hist[1] - tr) <= 1e-6 * tr, (res.hist, tr)
-    r64 = O.solve(A, b, method="cg_pipelined", rtol=0.0, max_iter=res.k)
-    assert O.true_residual(A, b, r64.x) < 1e-3 * tr
+    for acc in ACCS:
+        res = O.solve_mixed(A, b, rtol=1e-14, inner_rtol=1e-13, max_iter=400, max_outer=1, acc=acc)
+        assert res.sweeps == 1 and res.status == "not_converged", (acc, res)
+        tr = float(np.linalg.norm(b - A.to_scipy() @ res.x) / np.linalg.norm(b))
+        assert 1e-9 < tr < 1e-4, (acc, tr)
+        assert abs(res.hist[1] - tr) <= 1e-6 * tr, (acc, res.hist, tr)
+        r64 = O.solve(A, b, method="cg_pipelined", rtol=0.0, max_iter=res.k)
+        assert O.true_residual(A, b, r64.x) < 1e-3 * tr
 
 
 def pin_mixed_special_cases(O):
@@ -456,23 +499,24 @@ def pin_mixed_special_cases(O):
     the system gives no sweep."""
     A = P.poisson2d(10)
     b = P.rhs_uniform(A.n, 3)
-    z = O.solve_mixed(A, np.zeros(A.n), x0=np.ones(A.n))
-    assert z.status == "converged" and z.k == 0 and z.sweeps == 0 and not z.x.any()
-    r5 = O.solve_mixed(A, b, max_iter=5)
-    assert r5.status == "not_converged" and r5.k == 5 and r5.sweeps == 1, r5
-    r2 = O.solve_mixed(A, b, inner_rtol=0.5, max_outer=2)
-    assert r2.status == "not_converged" and r2.sweeps == 2 and len(r2.hist) == 3, r2
-    assert r2.hist[2] < r2.hist[1] < r2.hist[0]
-    s = O.solve_mixed(A, b, inner_rtol=2.0)
-    assert s.status == "not_converged" and s.k == 0 and s.sweeps == 0, s
     Ad = P.random_spd_dense(30, 50.0, seed=8)
     Ac = P.dense_to_csr(Ad)
     bd = np.random.default_rng(9).standard_normal(30)
     xs = np.linalg.solve(Ad, bd)
-    res = O.solve_mixed(Ac, bd, rtol=1e-12)
-    assert res.status == "converged" and _rel(res.x, xs) < 1e-10, res
-    w = O.solve_mixed(Ac, bd, x0=xs, rtol=1e-10)
-    assert w.status == "converged" and w.k == 0 and w.sweeps == 0, w
+    for acc in ACCS:
+        z = O.solve_mixed(A, np.zeros(A.n), x0=np.ones(A.n), acc=acc)
+        assert z.status == "converged" and z.k == 0 and z.sweeps == 0 and not z.x.any()
+        r5 = O.solve_mixed(A, b, max_iter=5, acc=acc)
+        assert r5.status == "not_converged" and r5.k == 5 and r5.sweeps == 1, (acc, r5)
+        r2 = O.solve_mixed(A, b, inner_rtol=0.5, max_outer=2, acc=acc)
+        assert r2.status == "not_converged" and r2.sweeps == 2 and len(r2.hist) == 3, (acc, r2)
+        assert r2.hist[2] < r2.hist[1] < r2.hist[0]
+        s = O.solve_mixed(A, b, inner_rtol=2.0, acc=acc)
+        assert s.status == "not_converged" and s.k == 0 and s.sweeps == 0, (acc, s)
+        res = O.solve_mixed(Ac, bd, rtol=1e-12, acc=acc)
+        assert res.status == "converged" and _rel(res.x, xs) < 1e-10, (acc, res)
+        w = O.solve_mixed(Ac, bd, x0=xs, rtol=1e-10, acc=acc)
+        assert w.status == "converged" and w.k == 0 and w.sweeps == 0, (acc, w)
 
 
 PINS = [
@@ -492,6 +536,7 @@ PINS = [
     pin_gmres_least_squares,
     pin_gmres_termination_and_restarts,
     pin_f32_products,
+    pin_f32acc_dot,
     pin_mixed_identity,
     pin_mixed_eigen_termination,
     pin_mixed_exact_poisson,

@@ -52,6 +52,15 @@ MUTATIONS = [
     ("f32_cg_direction_sign", "p[j] = r[j] + bf * p[j];", "p[j] = r[j] - bf * p[j];", None),
     ("f32_cg_beta_unrounded_alpha", "const float af = (float)alpha, bf = (float)beta;",
      "const float af = (float)(0.5 * alpha), bf = (float)beta;", None),
+    ("f32acc_dot_wide_accumulator", "float acc = 0.0f;", "double acc = 0.0;", 0),
+    ("f32acc_dot_unrounded_product", "const float prod = a[i] * b[i];",
+     "const double prod = (double)a[i] * b[i];", None),
+    ("f32acc_cg_residual_wrong_operand", "r[j] = r[j] - alpha * ap[j];", "r[j] = r[j] - alpha * p[j];", 1),
+    ("f32acc_cg_direction_sign", "p[j] = r[j] + beta * p[j];", "p[j] = r[j] - beta * p[j];", 2),
+    ("f32acc_cg_correction_sign", "d[j] = d[j] + alpha * p[j];", "d[j] = d[j] - alpha * p[j];", None),
+    ("f32acc_eq3_drops_alpha", "beta = alpha * alpha * apap / rr - 1.0f;", "beta = alpha * apap / rr - 1.0f;",
+     None),
+    ("f32acc_converged_on_squared_norm", "if (sqrtf(rr) <= tol)", "if (rr <= tol)", None),
     ("mixed_update_sign", "x[j] = x[j] + (double)d[j];", "x[j] = x[j] - (double)d[j];", None),
     ("mixed_solves_b_not_residual", "r32[j] = (float)r[j];", "r32[j] = (float)b[j];", None),
     ("mixed_inner_tol_absolute", "double tol = rtol * sqrt(rr);", "double tol = rtol;", None),
