@@ -69,7 +69,12 @@ typedef enum {
     FK_BICGSTAB_CLASSICAL = 3,  /* Algorithm 3, one kernel per operation         */
     FK_CG_MIXED = 4,            /* FP64 iterative refinement around FP32 Algorithm 2 */
     FK_GMRES_PIPELINED = 5,     /* Algorithm 6: restarted GMRES(m), 4 kernels/iteration */
-    FK_GMRES_CLASSICAL = 6      /* Algorithm 5: residual updated in the loop (+1 kernel) */
+    FK_GMRES_CLASSICAL = 6,     /* Algorithm 5: residual updated in the loop (+1 kernel) */
+    FK_CG_MIXED_F32 = 7,        /* FK_CG_MIXED with FP32-accumulated inner products */
+    FK_CG_PIPELINED_SPLIT = 8,  /* Algorithm 2 with the product's dots in their own
+                                   kernel (Section 3.1's alternative): 3 kernels */
+    FK_BICGSTAB_PIPELINED_SPLIT = 9  /* Algorithm 4 with both products' dots in their
+                                   own kernels (Section 3.2's alternative): 6 kernels */
 } fk_method;
 
 /* Rows with more nonzeros than this are summed by a fixed tree, not left to right. */
@@ -81,8 +86,12 @@ typedef struct {
     double rtol;             /* stop when ||r_k||_2 <= rtol * ||b||_2 (>= 0)   */
     int32_t max_iter;        /* >= 0; iterations allowed (0 = setup only);
                                 FK_CG_MIXED: inner iterations over all sweeps  */
-    int32_t record_history;  /* nonzero: keep ||r_i||/||b|| for i = 0..k
-                                (FK_CG_MIXED: one entry per refinement sweep)  */
+    int32_t record_history;  /* >= 0.  0: no history.  Otherwise keep
+                                ||r_i||/||b|| for i = 0..min(k, cap-1) with
+                                cap = min(max_iter + 1, FK_HISTORY_DEFAULT)
+                                when 1, min(max_iter + 1, record_history) when
+                                larger (FK_CG_MIXED: one entry per refinement
+                                sweep, at most max_outer + 1)                 */
     int32_t unroll;          /* iterations enqueued between status polls (0 = 32) */
     int32_t flags;           /* FK_FLAG_* bits                                  */
     double inner_rtol;       /* FK_CG_MIXED: inner stop ||r_in|| <= inner_rtol *
@@ -96,6 +105,13 @@ typedef struct {
 #define FK_FLAG_GRAPH 1      /* replay the enqueued iterations from a hipGraph */
 #define FK_FLAG_PROFILE 2    /* time every kernel with HIP events              */
 #define FK_FLAG_NO_SMALL 4   /* never use the single-workgroup solver           */
+#define FK_FLAG_SCALARS 8    /* with record_history: also keep alpha, beta, omega
+                                and the tested <r,r> per iteration (4 doubles
+                                per history entry; fk_get_scalars)             */
+
+/* History entries kept by default (record_history = 1): 512 KiB of device
+ * memory, whatever max_iter is. */
+#define FK_HISTORY_DEFAULT 65536
 
 enum { FK_PTR_HOST = 0, FK_PTR_DEVICE = 1 };
 
@@ -187,9 +203,17 @@ fk_status fk_csr_set_layout(fk_csr A, int32_t layout, void *hip_stream);
 
 /*
  * Create a solver for A with options *o, bound to hip_stream.  Allocates the
- * library-owned workspace (the method's work vectors, the per-workgroup
- * partial-sum buffer and the device scalars; about 3n doubles for CG and 6n
- * for BiCGStab) once, so fk_solve allocates nothing.
+ * library-owned workspace once, so fk_solve allocates nothing: the method's
+ * work vectors (r, p, A p for Algorithm 2; r, r0*, p, A p, s, A s for
+ * Algorithm 4: about 3n and 6n doubles), the buffer of per-workgroup
+ * partial sums that the first reduction stage writes and the second reads
+ * (Section 2.2, the two-stage reduction; Section 3.1, the partial results of
+ * the three inner products of an iteration in one buffer), and the device
+ * scalars alpha, beta, omega, <r,r> that the paper keeps on the host between
+ * kernels (Section 3.1), plus the history buffers record_history asks for.
+ * FK_E_ARG for an unknown method, negative sizes, non-finite or negative
+ * tolerances or unknown flags; FK_E_OOM when an allocation fails (nothing is
+ * left allocated).
  *
  * Pipelined solves of small systems (n <= 8192 for CG, n <= 2048 for
  * BiCGStab, nnz <= 65536, no row longer than FK_LONG_ROW, vectors fitting
@@ -218,6 +242,14 @@ fk_status fk_solver_create(fk_csr A, const fk_opts *o, void *hip_stream, fk_solv
  * fk_get_refinements gives the number of sweeps (corrections applied).
  * Workspace: 4n floats plus nnz FP32 matrix values.
  *
+ * FK_CG_MIXED_F32: the same refinement, but the inner solver accumulates in
+ * FP32 throughout: each inner product adds FP32-rounded products to FP32
+ * sums (per thread, then fixed-order trees over lanes, waves and
+ * workgroups), and alpha, beta (Eq. (3)), the inner norm and its test are
+ * formed in FP32.  The sums are reproducible run to run for a given launch
+ * shape but not equal to a sequential FP32 sum; each is within the FP32
+ * bound gamma_n sum |a_i b_i| of the exact value.
+ *
  * FK_GMRES_PIPELINED / FK_GMRES_CLASSICAL (restarted simpler GMRES(m) with
  * classical Gram-Schmidt, Section 3.3): a cycle starts from r0 = b - A x
  * (its true norm rho0 is the history entry at the restart and decides
@@ -236,30 +268,40 @@ fk_status fk_solver_create(fk_csr A, const fk_opts *o, void *hip_stream, fk_solv
  * sum_{j>=2} eta_j v_{j-1}).  k counts products A v over all cycles.  A cycle
  * with no step is a breakdown.  Workspace: (m+2) n doubles.
  *
- * Solve A x = b.  b_dev, x_dev: caller-owned device float64[n]; x holds x0 on
- * entry and x_k on return.  Work is enqueued on the solver's stream and the
+ * Solve A x = b (the problem of Section 1, by the method the solver was
+ * created with: Algorithms 1-6 of Section 3, the setup and iteration steps
+ * in the paper's order).  b_dev, x_dev: caller-owned device float64[n]; x
+ * holds x0 on entry and x_k on return.  Work is enqueued on the solver's stream and the
  * call returns once it has completed.  Returns FK_OK (converged),
  * FK_NOT_CONVERGED (x = x_{max_iter}), FK_BREAKDOWN (x = last finite iterate
  * before the failing step) or an error.  b = 0 gives x = 0, k = 0, FK_OK.
  */
 fk_status fk_solve(fk_solver S, const double *b_dev, double *x_dev);
 
-/* Iterations k of the last solve: number of solution updates performed. */
+/* Iterations k of the last solve: the number of solution updates performed,
+ * i.e. passes through the loop body of Algorithms 1-4 (index i of the loop
+ * when it stops, plus one); GMRES: products A v over all cycles (Section 3.3).
+ * FK_E_STATE before the first completed solve. */
 fk_status fk_get_iterations(fk_solver S, int32_t *k);
 
 /* ||r_k||_2 / ||b||_2 of the last solve, from the recursively updated residual
  * (pipelined BiCGStab: from the expansion of <r_{k}, r_{k}> in Section 3.2). */
 fk_status fk_get_residual(fk_solver S, double *rel_res);
 
-/* Residual history of the last solve: out[i] = ||r_i||/||b||, i = 0..k.
- * Writes min(cap, k+1) values and sets *len = k+1.  Needs record_history.
- * FK_CG_MIXED: out[j] = ||b - A x_j||/||b|| for sweeps j = 0..J, *len = J+1. */
+/* Residual history of the last solve: out[i] = ||r_i||/||b||, i = 0..k, the
+ * norm of the recursively updated residual that the paper monitors once per
+ * iteration through <r_i, r_i> (Section 3.1; Section 3.2: the expansion of
+ * <r_{i+1}, r_{i+1}> for BiCGStab).  Sets *len to the number of entries kept,
+ * min(k+1, the history capacity of record_history) and writes min(cap, *len)
+ * of them.  FK_E_STATE without record_history or before a solve.
+ * FK_CG_MIXED: out[j] = ||b - A x_j||/||b|| for sweeps j = 0..J. */
 fk_status fk_get_residual_history(fk_solver S, double *out, int32_t cap, int32_t *len);
 
 /* Per-iteration scalars of the last solve (for diagnostics): for iteration
- * i < min(cap, k), out[4*i + 0..3] = alpha_i, beta_i, omega_i (0 for CG),
- * and the A-expanded (BiCGStab) or plain <r,r> used for the test.
- * Needs record_history; not recorded for FK_CG_MIXED or GMRES (FK_E_STATE). */
+ * i < *len = min(k, history capacity), out[4*i + 0..3] = alpha_i, beta_i,
+ * omega_i (0 for CG), and the A-expanded (BiCGStab) or plain <r,r> used for
+ * the test; min(cap, *len) iterations are written.  Needs record_history and
+ * FK_FLAG_SCALARS; not recorded for FK_CG_MIXED or GMRES (FK_E_STATE). */
 fk_status fk_get_scalars(fk_solver S, double *out, int32_t cap, int32_t *len);
 
 /* Average device time per launch of each kernel kind during the last solve
@@ -294,6 +336,19 @@ fk_status fk_get_refinements(fk_solver S, int32_t *sweeps);
  * p_dev, q_dev: device float64[n], must not alias.  Synchronous.
  */
 fk_status fk_spmv(fk_csr A, const double *p_dev, double *q_dev, double *dots_host, void *hip_stream);
+
+/*
+ * q = A p in FP32, the inner product kernel of FK_CG_MIXED / FK_CG_MIXED_F32
+ * (Section 2.2's fused kernel in single precision): the values of A rounded
+ * to FP32 (once, at the first call after a layout change, kept with the
+ * matrix), each row summed left to right in FP32.  If dots_host is not NULL
+ * it receives {<p,q>, <q,q>}: exact sums of the FP32 operands rounded to
+ * FP64 (f32acc = 0) or FP32 accumulations (f32acc = 1; the float returned
+ * as a double).  p_dev, q_dev: device float32[n], must not alias.  Shares
+ * the matrix's reduction scratch with fk_spmv.  Synchronous.
+ */
+fk_status fk_spmv32(fk_csr A, const float *p_dev, float *q_dev, int32_t f32acc, double *dots_host,
+                    void *hip_stream);
 
 /* <a, b> over n >= 0 device doubles, written to *out_host.  Synchronous. */
 fk_status fk_dot(int64_t n, const double *a_dev, const double *b_dev, double *out_host, void *hip_stream);

@@ -310,3 +310,33 @@ class MixedResult:
     status: str
     hist: np.ndarray    # ||b - A x_j||/||b||, j = 0..sweeps
     inner_k: np.ndarray  # inner iterations of each sweep
+
+
+class TimingOracle:
+    """The OpenMP timing build of oracle.c (oracle.build.build_timing): only
+    oracle_cg_classical_omp, Algorithm 1 over `threads` threads in static row
+    chunks.  Used to time the oracle on the host's cores, never for parity."""
+
+    def __init__(self, path: str):
+        lib = ctypes.CDLL(path)
+        i32p = ctypes.POINTER(ctypes.c_int32)
+        f64p = ctypes.POINTER(ctypes.c_double)
+        lib.oracle_cg_classical_omp.argtypes = [
+            ctypes.c_int32, ctypes.c_int64, i32p, i32p, f64p, f64p, f64p, ctypes.c_double,
+            ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)]
+        lib.oracle_cg_classical_omp.restype = ctypes.c_int
+        self.lib = lib
+
+    def cg_classical(self, A, b, threads: int, x0=None, rtol: float = 1e-8, max_iter: int | None = None):
+        """Returns (status, k, x)."""
+        rp, rpp = _i32(A.row_ptr)
+        ci, cip = _i32(A.col_idx)
+        v, vp = _f64(A.vals)
+        b, bp = _f64(b)
+        x = np.zeros(A.n) if x0 is None else np.array(x0, dtype=np.float64, copy=True)
+        _, xp = _f64(x)
+        k = ctypes.c_int32(0)
+        st = self.lib.oracle_cg_classical_omp(int(threads), A.n, rpp, cip, vp, bp, xp, float(rtol),
+                                              int(10 * A.n if max_iter is None else max_iter),
+                                              ctypes.byref(k))
+        return STATUS[st], int(k.value), x

@@ -30,5 +30,20 @@ def build(verbose: bool = False, src: str | None = None, out: str | None = None)
     return out
 
 
+def build_timing(out: str, src: str | None = None, verbose: bool = False) -> str:
+    """The timing build of the same source: -O3 for the machine it runs on,
+    OpenMP on (which adds oracle_cg_classical_omp), still without FMA
+    contraction.  Timing only; parity uses the build above."""
+    src = src or os.path.join(HERE, "oracle.c")
+    tmp = out + f".tmp{os.getpid()}"
+    cmd = ["gcc", "-std=c11", "-O3", "-march=native", "-fopenmp", "-fPIC", "-shared",
+           "-ffp-contract=off", "-fno-fast-math", "-Wall", "-Wextra", "-o", tmp, src, "-lm"]
+    if verbose:
+        print(" ".join(cmd), file=sys.stderr)
+    subprocess.run(cmd, check=True)
+    os.replace(tmp, out)
+    return out
+
+
 if __name__ == "__main__":
     print(build(verbose=True))

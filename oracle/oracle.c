@@ -797,3 +797,102 @@ done:
     free(r); free(v32); free(r32); free(d); free(p); free(ap);
     return status;
 }
+
+/* ------------------------------------------------ timing build (OpenMP) */
+
+#ifdef _OPENMP
+#include <omp.h>
+
+/*
+ * Compiled only into the timing build (gcc -fopenmp); the parity build has
+ * no OpenMP and none of this.  Algorithm 1 exactly as cg_classical, with the
+ * rows of the product and of every vector update split over `threads`
+ * threads in static contiguous chunks, and each inner product computed per
+ * chunk by the compensated dot of oracle_dot, the chunk results added in
+ * chunk order (TwoSum).  The result depends on the thread count, never on
+ * scheduling.  For timing the oracle on the host's cores; no history.
+ */
+static void omp_chunk(int64_t n, int t, int T, int64_t *lo, int64_t *hi)
+{
+    *lo = n * t / T;
+    *hi = n * (t + 1) / T;
+}
+
+static double omp_dot(int64_t n, const double *a, const double *b, double *part, int T)
+{
+#pragma omp parallel num_threads(T)
+    {
+        int64_t lo, hi;
+        omp_chunk(n, omp_get_thread_num(), T, &lo, &hi);
+        part[omp_get_thread_num()] = dot_compensated(hi - lo, a + lo, b + lo);
+    }
+    double s = part[0], c = 0.0;
+    for (int t = 1; t < T; ++t) {
+        double e;
+        two_sum(s, part[t], &s, &e);
+        c = c + e;
+    }
+    return s + c;
+}
+
+static void omp_matvec(const csr_t *A, const double *p, double *q, int T)
+{
+#pragma omp parallel num_threads(T)
+    {
+        int64_t lo, hi;
+        omp_chunk(A->n, omp_get_thread_num(), T, &lo, &hi);
+        for (int64_t i = lo; i < hi; ++i) {
+            double acc = 0.0;
+            for (int64_t j = A->rp[i]; j < A->rp[i + 1]; ++j)
+                acc = acc + A->v[j] * p[A->ci[j]];
+            q[i] = acc;
+        }
+    }
+}
+
+int oracle_cg_classical_omp(int32_t threads, int64_t n, const int32_t *row_ptr, const int32_t *col_idx,
+                            const double *vals, const double *b, double *x, double rtol, int32_t max_iter,
+                            int32_t *k_out)
+{
+    *k_out = 0;
+    if (threads < 1 || n <= 0 || !row_ptr || !col_idx || !vals || !b || !x || max_iter < 0)
+        return OR_BAD_ARG;
+    const int T = threads;
+    csr_t A = {n, row_ptr, col_idx, vals};
+    double *r = vec(n), *p = vec(n), *q = vec(n), *part = vec(T);
+    int status = OR_NOT_CONVERGED;
+    int32_t k = 0;
+    if (!r || !p || !q || !part) { status = OR_BAD_ARG; goto done; }
+
+    double bnorm = sqrt(omp_dot(n, b, b, part, T));
+    double tol = rtol * bnorm;
+    omp_matvec(&A, x, q, T);
+#pragma omp parallel for schedule(static) num_threads(T)
+    for (int64_t j = 0; j < n; ++j) { r[j] = b[j] - q[j]; p[j] = r[j]; }
+    double rr = omp_dot(n, r, r, part, T);
+    if (!finite(rr)) { status = OR_BREAKDOWN; goto done; }
+    if (sqrt(rr) <= tol) { status = OR_CONVERGED; goto done; }
+    for (int32_t i = 0; i < max_iter; ++i) {
+        omp_matvec(&A, p, q, T);                                /* A p_i */
+        double pq = omp_dot(n, p, q, part, T);                  /* <p_i, A p_i> */
+        if (!(pq > 0.0) || !finite(pq)) { status = OR_BREAKDOWN; break; }
+        double alpha = rr / pq;
+#pragma omp parallel for schedule(static) num_threads(T)
+        for (int64_t j = 0; j < n; ++j) x[j] = x[j] + alpha * p[j];
+#pragma omp parallel for schedule(static) num_threads(T)
+        for (int64_t j = 0; j < n; ++j) r[j] = r[j] - alpha * q[j];
+        double rr_new = omp_dot(n, r, r, part, T);              /* <r_{i+1}, r_{i+1}> */
+        k = i + 1;
+        if (!finite(rr_new)) { status = OR_BREAKDOWN; break; }
+        if (sqrt(rr_new) <= tol) { status = OR_CONVERGED; break; }
+        double beta = rr_new / rr;
+#pragma omp parallel for schedule(static) num_threads(T)
+        for (int64_t j = 0; j < n; ++j) p[j] = r[j] + beta * p[j];
+        rr = rr_new;
+    }
+done:
+    free(r); free(p); free(q); free(part);
+    *k_out = k;
+    return status;
+}
+#endif /* _OPENMP */

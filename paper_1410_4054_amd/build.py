@@ -49,11 +49,16 @@ def build(verbose: bool = False, out: str | None = None) -> str:
     hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
     objdir = os.path.join(ROOT, "_build", os.path.basename(out or "libfk.so"))
     os.makedirs(objdir, exist_ok=True)
-    objs = []
-    for src in SOURCES:
-        obj = os.path.join(objdir, src.replace(".hip", ".o"))
-        _run([hipcc, *HIPCC_FLAGS, *extra_flags(), "-c", os.path.join(CSRC, src), "-o", obj], verbose)
-        objs.append(obj)
+    objs = [os.path.join(objdir, src.replace(".hip", ".o")) for src in SOURCES]
+    # the sources compile independently: one hipcc per source, side by side
+    from concurrent.futures import ThreadPoolExecutor
+
+    with ThreadPoolExecutor(max_workers=len(SOURCES)) as pool:
+        jobs = [pool.submit(_run, [hipcc, *HIPCC_FLAGS, *extra_flags(), "-c", os.path.join(CSRC, src),
+                                   "-o", obj], verbose)
+                for src, obj in zip(SOURCES, objs)]
+        for j in jobs:
+            j.result()
     out = out or library_path()
     tmp = out + f".tmp{os.getpid()}"
     _run([hipcc, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs], verbose)

@@ -148,24 +148,28 @@ struct fk_csr_s {
     int32_t dg_nslices = 0;   // > 0 once the slot arrays exist
     int64_t dg_entries = 0;
     int32_t layout = FK_LAYOUT_ROW_BLOCKS;  // layout the products read
-    // scratch reduction state for fk_spmv
+    // scratch reduction state for fk_spmv / fk_spmv32
     DevState *st = nullptr;
     double *partials = nullptr;
     int solvers = 0;
+    // FP32 values for fk_spmv32, in the order of the layout they were made for
+    float *vals32 = nullptr;
+    int32_t vals32_layout = -1;
 
     bool slots() const { return layout == FK_LAYOUT_SLOTS; }
     bool sliced() const { return layout == FK_LAYOUT_SLICED || layout == FK_LAYOUT_SLICED16 || slots(); }
     DevCsr view() const
     {
+        const int32_t sw = sweep_grid() > 0 ? 1 : 0;
         if (slots())
             return DevCsr{(int32_t)n, (int32_t)nnz, nblocks, row_ptr, col_idx, vals, blocks, block_j0,
-                          dg_nslices, dg_ptr, nullptr, dg_vals, nullptr, nullptr, dg_off, dg_mask};
+                          dg_nslices, dg_ptr, nullptr, dg_vals, nullptr, nullptr, dg_off, dg_mask, sw};
         return DevCsr{(int32_t)n,  (int32_t)nnz, nblocks,  row_ptr,
                       col_idx,     vals,         blocks,   block_j0,
                       sliced() ? nslices : 0,    sell_ptr, sell_col,
                       sell_vals,   sell_ptr4,
                       layout == FK_LAYOUT_SLICED16 ? sell_off4 : nullptr,
-                      nullptr,     nullptr};
+                      nullptr,     nullptr,      sliced() ? sw : 0};
     }
     // Entries the products read: nnz, or the slice entries with padding.
     int64_t stored_entries() const { return slots() ? dg_entries : sliced() ? sell_entries : nnz; }
@@ -183,7 +187,27 @@ struct fk_csr_s {
             return 12 * sell_entries + 4 * ((int64_t)nslices + 1);
         return 12 * nnz + 4 * (n + 1);
     }
-    int spmv_grid() const { return ::spmv_grid(sliced(), slots() ? dg_nslices : sliced() ? nslices : nblocks); }
+    int32_t cus = 0;    // compute units of the device (resident workgroups = 8 per CU)
+    int32_t sweep = 0;  // sliced products in sweep order (DevCsr::sweep)
+    int64_t slices() const { return slots() ? dg_nslices : sliced() ? nslices : 0; }
+    // Workgroups of a sweep-order product: as many as are resident at once
+    // (8 per CU at the product kernels' register cap), fewer for small
+    // matrices (at least one slice per wave); 0 when not in sweep order.
+    int sweep_grid() const
+    {
+        if (!sweep || !sliced() || cus <= 0)
+            return 0;
+        int64_t g = std::min<int64_t>((int64_t)8 * cus, (slices() + WAVES - 1) / WAVES);
+        g &= ~(int64_t)7;
+        return (int)g;
+    }
+    int spmv_grid() const
+    {
+        const int sg = sweep_grid();
+        if (sg > 0)
+            return sg;
+        return ::spmv_grid(sliced(), slots() ? dg_nslices : sliced() ? nslices : nblocks);
+    }
 };
 
 DevCsr fk::internal_csr_view(fk_csr A) { return A->view(); }
@@ -513,6 +537,7 @@ static void csr_release(fk_csr A)
     dev_free(A->block_j0);
     dev_free(A->st);
     dev_free(A->partials);
+    dev_free(A->vals32);
 }
 
 extern "C" fk_status fk_csr_create(int64_t n, int64_t nnz, const int32_t *row_ptr,
@@ -559,6 +584,9 @@ extern "C" fk_status fk_csr_create(int64_t n, int64_t nnz, const int32_t *row_pt
     A->n = n;
     A->nnz = nnz;
     (void)hipGetDevice(&A->device);
+    if (hipDeviceGetAttribute(&A->cus, hipDeviceAttributeMultiprocessorCount, A->device) != hipSuccess)
+        A->cus = 0;
+    A->sweep = env_int("FK_SELL_SWEEP", 0, 0, 1);
     std::vector<int32_t> blocks, block_j0;
     try {
         blocks = plan_blocks(rp, n, &A->long_rows);
@@ -809,6 +837,7 @@ struct fk_solver_s {
     // FK_CG_MIXED: FP32 inner vectors and matrix values; the refinement's
     // own state (st is the inner solver's); sweeps of the last solve.
     bool mixed = false;
+    bool f32acc = false;  // FK_CG_MIXED_F32: inner dots and scalars in FP32
     float *r32 = nullptr, *p32 = nullptr, *ap32 = nullptr, *d32 = nullptr, *vals32 = nullptr;
     DevState *st_outer = nullptr;
     int32_t sweeps = 0;
@@ -880,7 +909,10 @@ static void solver_release(fk_solver S)
     S->graph = nullptr;
 }
 
-static bool is_bicg(int m) { return m == FK_BICGSTAB_PIPELINED || m == FK_BICGSTAB_CLASSICAL; }
+static bool is_bicg(int m)
+{
+    return m == FK_BICGSTAB_PIPELINED || m == FK_BICGSTAB_CLASSICAL || m == FK_BICGSTAB_PIPELINED_SPLIT;
+}
 static bool is_gmres(int m) { return m == FK_GMRES_PIPELINED || m == FK_GMRES_CLASSICAL; }
 
 static size_t max_lds_per_workgroup(int device)
@@ -917,7 +949,7 @@ extern "C" fk_status fk_solver_create(fk_csr A, const fk_opts *o, void *hip_stre
     *out = nullptr;
     if (!A || !o)
         return fail(FK_E_ARG, "NULL argument");
-    if (o->method < FK_CG_PIPELINED || o->method > FK_GMRES_CLASSICAL)
+    if (o->method < FK_CG_PIPELINED || o->method > FK_BICGSTAB_PIPELINED_SPLIT)
         return fail(FK_E_ARG, "unknown method %d", o->method);
     if (o->restart < 0 || o->restart > GM_MAX)
         return fail(FK_E_ARG, "restart outside [0, %d]", GM_MAX);
@@ -931,8 +963,10 @@ extern "C" fk_status fk_solver_create(fk_csr A, const fk_opts *o, void *hip_stre
         return fail(FK_E_ARG, "max_iter < 0");
     if (o->unroll < 0 || o->unroll > 4096)
         return fail(FK_E_ARG, "unroll outside [0, 4096]");
-    if (o->flags & ~(FK_FLAG_GRAPH | FK_FLAG_PROFILE | FK_FLAG_NO_SMALL))
+    if (o->flags & ~(FK_FLAG_GRAPH | FK_FLAG_PROFILE | FK_FLAG_NO_SMALL | FK_FLAG_SCALARS))
         return fail(FK_E_ARG, "unknown flags 0x%x", o->flags);
+    if (o->record_history < 0)
+        return fail(FK_E_ARG, "record_history < 0");
 
     fk_solver S = new (std::nothrow) fk_solver_s;
     if (!S)
@@ -941,7 +975,8 @@ extern "C" fk_status fk_solver_create(fk_csr A, const fk_opts *o, void *hip_stre
     S->o = *o;
     if (S->o.unroll == 0)
         S->o.unroll = 32;
-    S->mixed = o->method == FK_CG_MIXED;
+    S->mixed = o->method == FK_CG_MIXED || o->method == FK_CG_MIXED_F32;
+    S->f32acc = o->method == FK_CG_MIXED_F32;
     S->gmres = is_gmres(o->method);
     S->gm = o->restart == 0 ? 30 : o->restart;
     if (S->o.inner_rtol == 0.0)
@@ -1005,13 +1040,18 @@ extern "C" fk_status fk_solver_create(fk_csr A, const fk_opts *o, void *hip_stre
     }
     S_TRY(dev_alloc(&S->partials, RED_SCRATCH_DOUBLES, "partials"));
     S_TRY(dev_alloc(&S->st, 1, "state"));
+    // History: entries 0 .. cap-1 are kept (the device drops later ones), cap
+    // = min(iterations + 1, FK_HISTORY_DEFAULT or the count asked for), so a
+    // large max_iter does not size the buffers.
+    const int64_t hist_want = o->record_history == 1 ? FK_HISTORY_DEFAULT : o->record_history;
     if (o->record_history && S->mixed) {
-        S->hist_cap = (int32_t)std::min<int64_t>((int64_t)S->o.max_outer + 1, INT32_MAX);
+        S->hist_cap = (int32_t)std::min<int64_t>((int64_t)S->o.max_outer + 1, hist_want);
         S_TRY(dev_alloc(&S->hist, (size_t)S->hist_cap, "history"));
     } else if (o->record_history) {
-        S->hist_cap = (int32_t)std::min<int64_t>((int64_t)o->max_iter + 1, INT32_MAX);
+        S->hist_cap = (int32_t)std::min<int64_t>((int64_t)o->max_iter + 1, hist_want);
         S_TRY(dev_alloc(&S->hist, (size_t)S->hist_cap, "history"));
-        S_TRY(dev_alloc(&S->scal, (size_t)S->hist_cap * 4, "scalars"));
+        if ((o->flags & FK_FLAG_SCALARS) && !S->mixed && !S->gmres)
+            S_TRY(dev_alloc(&S->scal, (size_t)S->hist_cap * 4, "scalars"));
     }
     S_HIP(hipHostMalloc(reinterpret_cast<void **>(&S->h_init), 3 * sizeof(DevState), hipHostMallocDefault));
     S_HIP(hipHostMalloc(reinterpret_cast<void **>(&S->h_status), 2 * sizeof(int32_t), hipHostMallocDefault));
@@ -1107,9 +1147,11 @@ hipError_t enqueue_setup(fk_solver S, Enq &q, const double *b, double *x)
     hipStream_t st = S->stream;
     if (S->mixed) {
         // Inner solve of A d = r32 from d_0 = 0: p_0 = r_0 = r32.
-        ENQ(FK_KERNEL_SETUP, launch_inner_setup32(n, S->r32, S->p32, S->d32, S->red(FIN_SETUP, RUN_ACTIVE), gv, st));
+        const bool f = S->f32acc;
+        ENQ(FK_KERNEL_SETUP, launch_inner_setup32(n, S->r32, S->p32, S->d32,
+                                                  S->red(f ? FIN_SETUP32 : FIN_SETUP, RUN_ACTIVE), gv, st, f));
         ENQ(FK_KERNEL_SPMV_DOT, launch_spmv32(A, S->vals32, S->p32, S->ap32,
-                                              S->red(FIN_CG_ALPHA, RUN_ACTIVE), gs, st));
+                                              S->red(f ? FIN_CG_ALPHA32 : FIN_CG_ALPHA, RUN_ACTIVE), gs, st, f));
         return hipSuccess;
     }
     double *rs = is_bicg(S->o.method) ? S->rs : nullptr;
@@ -1121,6 +1163,10 @@ hipError_t enqueue_setup(fk_solver S, Enq &q, const double *b, double *x)
     if (S->o.method == FK_CG_PIPELINED)
         ENQ(FK_KERNEL_SPMV_DOT, launch_spmv_dots(A, S->p, S->ap, nullptr, D_YV | D_YY,
                                                  S->red(FIN_CG_ALPHA, RUN_ACTIVE), gs, st));
+    if (S->o.method == FK_CG_PIPELINED_SPLIT) {
+        ENQ(FK_KERNEL_SPMV, launch_spmv_dots(A, S->p, S->ap, nullptr, 0, S->red(FIN_NONE, RUN_ACTIVE), gs, st));
+        ENQ(FK_KERNEL_DOT, launch_dot(n, S->ap, S->p, S->ap, 2, S->red(FIN_CG_ALPHA, RUN_ACTIVE), gv, st));
+    }
     return hipSuccess;
 }
 
@@ -1142,6 +1188,27 @@ hipError_t enqueue_iteration(fk_solver S, Enq &q, double *x, bool last)
         ENQ(FK_KERNEL_UPDATE_DOT, launch_cg_update(n, x, S->r, S->p, S->ap, S->red(FIN_PUBLISH, RUN_ACTIVE), gv, st));
         ENQ(FK_KERNEL_SPMV_DOT, launch_spmv_dots(A, S->p, S->ap, nullptr, D_YV | D_YY,
                                                  S->red_fold(FIN_CG_RR_ALPHA, RUN_ACTIVE, gv, 1), gs, st));
+        break;
+    case FK_CG_PIPELINED_SPLIT:
+        // Section 3.1's alternative: the product and its two dots in separate
+        // kernels (3 launches, one more pass over p and A p).
+        ENQ(FK_KERNEL_UPDATE_DOT, launch_cg_update(n, x, S->r, S->p, S->ap, S->red(FIN_PUBLISH, RUN_ACTIVE), gv, st));
+        ENQ(FK_KERNEL_SPMV, launch_spmv_dots(A, S->p, S->ap, nullptr, 0, S->red(FIN_NONE, RUN_ACTIVE), gs, st));
+        ENQ(FK_KERNEL_DOT, launch_dot(n, S->ap, S->p, S->ap, 2, S->red_fold(FIN_CG_RR_ALPHA, RUN_ACTIVE, gv, 1),
+                                      gv, st));
+        break;
+    case FK_BICGSTAB_PIPELINED_SPLIT:
+        // Section 3.2's alternative: both products without dots, each
+        // followed by a dot kernel (6 launches per iteration).
+        ENQ(FK_KERNEL_SPMV, launch_spmv_dots(A, S->p, S->ap, nullptr, 0, S->red(FIN_NONE, RUN_ACTIVE), gs, st));
+        ENQ(FK_KERNEL_DOT, launch_dot(n, S->ap, S->rs, nullptr, 1, S->red_fold(FIN_B_RHO_ALPHA, RUN_ACTIVE, gv, 2),
+                                      gv, st));
+        ENQ(FK_KERNEL_UPDATE_DOT, launch_bicg_s(n, S->r, S->ap, S->s, S->red(FIN_PUBLISH, RUN_ACTIVE), gv, st));
+        ENQ(FK_KERNEL_SPMV, launch_spmv_dots(A, S->s, S->as, nullptr, 0, S->red(FIN_NONE, RUN_ACTIVE), gs, st));
+        ENQ(FK_KERNEL_DOT, launch_dot(n, S->as, S->s, S->as, 3, S->red_fold(FIN_B_SS_OMEGA, RUN_ACTIVE, gv, 1), gv,
+                                      st, S->rs));
+        ENQ(FK_KERNEL_UPDATE_DOT, launch_bicg_xrp(n, x, S->r, S->p, S->s, S->as, S->ap, S->rs,
+                                                  S->red(FIN_B_XRP_PUB, RUN_BICG_UPDATE), gv, st));
         break;
     case FK_CG_CLASSICAL:
         ENQ(FK_KERNEL_SPMV, launch_spmv_dots(A, S->p, S->ap, nullptr, 0, S->red(FIN_NONE, RUN_ACTIVE), gs, st));
@@ -1182,12 +1249,17 @@ hipError_t enqueue_iteration(fk_solver S, Enq &q, double *x, bool last)
             ENQ(FK_KERNEL_AXPY, launch_xpay(n, S->p, S->r, S->ap, ds, RUN_ACTIVE, gv, st));
         break;
     case FK_CG_MIXED:
+    case FK_CG_MIXED_F32: {
         // Algorithm 2 in FP32 on the correction d (x is not touched).
+        const bool f = S->f32acc;
         ENQ(FK_KERNEL_UPDATE_DOT, launch_cg_update32(n, S->d32, S->r32, S->p32, S->ap32,
-                                                     S->red(FIN_PUBLISH, RUN_ACTIVE), gv, st));
+                                                     S->red(FIN_PUBLISH, RUN_ACTIVE), gv, st, f));
         ENQ(FK_KERNEL_SPMV_DOT, launch_spmv32(A, S->vals32, S->p32, S->ap32,
-                                              S->red_fold(FIN_CG_RR_ALPHA, RUN_ACTIVE, gv, 1), gs, st));
+                                              S->red_fold(f ? FIN_CG_RR_ALPHA32 : FIN_CG_RR_ALPHA, RUN_ACTIVE,
+                                                          gv, 1),
+                                              gs, st, f));
         break;
+    }
     default:
         return hipErrorInvalidValue;
     }
@@ -1633,8 +1705,8 @@ extern "C" fk_status fk_get_residual_history(fk_solver S, double *out, int32_t c
         return fail(FK_E_STATE, "no completed solve");
     if (!S->hist)
         return fail(FK_E_STATE, "solver created without record_history");
-    *len = S->mixed ? S->sweeps + 1 : S->last.it + 1;
-    const int32_t m = std::min(std::min(cap, *len), S->hist_cap);
+    *len = std::min(S->mixed ? S->sweeps + 1 : S->last.it + 1, S->hist_cap);
+    const int32_t m = std::min(cap, *len);
     if (m > 0)
         HIP_TRY(hipMemcpyAsync(out, S->hist, (size_t)m * sizeof(double), hipMemcpyDeviceToHost, S->stream));
     HIP_TRY(hipStreamSynchronize(S->stream));
@@ -1650,9 +1722,9 @@ extern "C" fk_status fk_get_scalars(fk_solver S, double *out, int32_t cap, int32
     if (S->mixed || S->gmres)
         return fail(FK_E_STATE, "no per-iteration scalars for this method");
     if (!S->scal)
-        return fail(FK_E_STATE, "solver created without record_history");
-    *len = S->last.it;
-    const int32_t m = std::min(std::min(cap, *len), S->hist_cap);
+        return fail(FK_E_STATE, "solver created without record_history and FK_FLAG_SCALARS");
+    *len = std::min(S->last.it, S->hist_cap);
+    const int32_t m = std::min(cap, *len);
     if (m > 0)
         HIP_TRY(hipMemcpyAsync(out, S->scal, (size_t)m * 4 * sizeof(double), hipMemcpyDeviceToHost, S->stream));
     HIP_TRY(hipStreamSynchronize(S->stream));
@@ -1691,6 +1763,41 @@ extern "C" fk_status fk_spmv(fk_csr A, const double *p, double *q, double *dots_
         dots_host[1] = d[1];
     } else {
         HIP_TRY(hipStreamSynchronize(s));
+    }
+    return FK_OK;
+}
+
+extern "C" fk_status fk_spmv32(fk_csr A, const float *p, float *q, int32_t f32acc, double *dots_host,
+                               void *hip_stream)
+{
+    if (!A || !p || !q)
+        return fail(FK_E_ARG, "NULL argument");
+    if ((const void *)p == (const void *)q)
+        return fail(FK_E_ARG, "p and q must not alias");
+    if (f32acc != 0 && f32acc != 1)
+        return fail(FK_E_ARG, "f32acc must be 0 or 1");
+    hipStream_t s = (hipStream_t)hip_stream;
+    if (A->nnz > 0 && A->vals32_layout != A->layout) {
+        // the FP32 values in the order the current layout's products read them
+        dev_free(A->vals32);
+        A->vals32_layout = -1;
+        const int64_t m = A->stored_entries();
+        fk_status fs = dev_alloc(&A->vals32, (size_t)m, "FP32 values");
+        if (fs != FK_OK)
+            return fs;
+        const double *src = A->slots() ? A->dg_vals : A->sliced() ? A->sell_vals : A->vals;
+        HIP_TRY(launch_to_f32(m, A->vals32, src, vec_grid(m), s));
+        A->vals32_layout = A->layout;
+    }
+    RedArgs red{A->st, A->partials, nullptr, nullptr, FIN_NONE, RUN_ALWAYS};
+    HIP_TRY(launch_spmv32(A->view(), A->vals32, p, q, red, A->spmv_grid(), s, f32acc != 0));
+    double d[KMAX];
+    HIP_TRY(hipMemcpyAsync(d, reinterpret_cast<const char *>(A->st) + offsetof(DevState, dots), sizeof d,
+                           hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    if (dots_host) {
+        dots_host[0] = d[0];
+        dots_host[1] = d[1];
     }
     return FK_OK;
 }

@@ -123,6 +123,12 @@ enum Fin : int32_t {
                         // the previous update, if any): rho, then FIN_B_ALPHA
     FIN_B_XRP_PUB,      // the x, r, p update: publishes <r,r0*>, <r,r> while the
                         // solve runs; after a decision, finalizes (FIN_B_XRP role)
+    // The FP32-accumulating inner solver: the dots arrive as FP32 values and
+    // the scalars of Algorithm 2 are formed in FP32 (held in the state's
+    // doubles, which represent them exactly).
+    FIN_SETUP32,        // d = {<r0,r0>, <r0,r0>}: FIN_SETUP with an FP32 tolerance
+    FIN_CG_ALPHA32,     // d = {<p,Ap>, <Ap,Ap>}: alpha_i, beta_i (Eq. (3)) in FP32
+    FIN_CG_RR_ALPHA32,  // d = {<p,Ap>, <Ap,Ap>, <r,r>}: FIN_CG_RR_ALPHA in FP32
 };
 
 // Everything a reduction point needs.
@@ -179,6 +185,13 @@ struct DevCsr {
     // sell_ptr[s]/SLICE + k] when bit k of dg_mask[row] is set (else 0).
     const int32_t *dg_off;
     const uint32_t *dg_mask;
+    // Order in which the waves of a sliced product take the slices:
+    // 0 = wave w of W takes slices w, w + W, ... (grid stride, XCD-major
+    // workgroup numbering); 1 = sweep: the x-th eighth of the slices belongs
+    // to XCD x, whose waves take consecutive slices side by side and move
+    // through the eighth together (a sliding window; the grid then holds no
+    // more workgroups than are resident at once).
+    int32_t sweep;
 };
 
 // Column forms of the sliced products.
@@ -215,8 +228,9 @@ hipError_t launch_bicg_xrp(int64_t n, double *x, double *r, double *p, const dou
                            const double *as, const double *ap, const double *rs,
                            const RedArgs &red, int grid, hipStream_t s);
 // Classical (unfused) building blocks.
+// <a,b> (ndots 1); <a,b>, <a,c> (2); <a,b>, <a,c>, <a,e> (3).
 hipError_t launch_dot(int64_t n, const double *a, const double *b, const double *c,
-                      int ndots, const RedArgs &red, int grid, hipStream_t s);
+                      int ndots, const RedArgs &red, int grid, hipStream_t s, const double *e = nullptr);
 // out = y + coef * x (negative = 0) or y - coef * x (negative = 1),
 // coef = state->alpha (which = 0) or state->omega (which = 1)
 hipError_t launch_axpy(int64_t n, double *out, const double *y, const double *x, int which,
@@ -236,20 +250,21 @@ hipError_t launch_axpby(int64_t n, double alpha, const double *x, double beta, c
 // r32 = (float)(b - A x) with FP64 <r,r>, <b,b> (FIN_MIX_OUTER).
 hipError_t launch_residual32(const DevCsr &A, const double *b, const double *x, float *r32,
                              const RedArgs &red, int grid, hipStream_t s);
-// y = A32 v with FP32 <y,v>, <y,y> (FIN_CG_ALPHA on the inner state).
-// vals32 holds the FP32 values in the layout A's products read: CSR order
-// (nnz entries) for row blocks, slice order (sell_ptr[nslices] entries)
-// for the sliced layout.
+// y = A32 v with the FP32 dots <y,v>, <y,y> (FIN_CG_ALPHA or FIN_CG_ALPHA32
+// on the inner state), accumulated exactly (double-double) or, with
+// f32acc, in FP32.  vals32 holds the FP32 values in the layout A's products
+// read: CSR order (nnz entries) for row blocks, slice order
+// (sell_ptr[nslices] entries) for the sliced layout.
 hipError_t launch_spmv32(const DevCsr &A, const float *vals32, const float *v, float *y,
-                         const RedArgs &red, int grid, hipStream_t s);
+                         const RedArgs &red, int grid, hipStream_t s, bool f32acc);
 // out[e] = map[e] >= 0 ? vals[map[e]] : 0 (the values of the sliced layout).
 hipError_t launch_gather_vals(int64_t n, double *out, const double *vals, const int32_t *map,
                               int grid, hipStream_t s);
 hipError_t launch_cg_update32(int64_t n, float *d, float *r, float *p, const float *ap,
-                              const RedArgs &red, int grid, hipStream_t s);
-// p = r, d = 0, FP32 <r,r> twice (FIN_SETUP on the inner state).
+                              const RedArgs &red, int grid, hipStream_t s, bool f32acc);
+// p = r, d = 0, FP32 <r,r> twice (FIN_SETUP / FIN_SETUP32 on the inner state).
 hipError_t launch_inner_setup32(int64_t n, const float *r, float *p, float *d, const RedArgs &red,
-                                int grid, hipStream_t s);
+                                int grid, hipStream_t s, bool f32acc);
 hipError_t launch_add32(int64_t n, double *x, const float *d, int grid, hipStream_t s);
 hipError_t launch_to_f32(int64_t n, float *out, const double *in, int grid, hipStream_t s);
 
@@ -295,6 +310,11 @@ hipError_t launch_small(int method_bicg, const DevCsr &A, const double *b, doubl
                         double *hist, double *scal, bool stage, hipStream_t s);
 hipError_t launch_zero(double *x, int64_t n, DevState *st, uint32_t run_mask, int grid,
                        hipStream_t s);
+// x[0 .. n) = 0, unconditionally.
+hipError_t launch_clear(double *x, int64_t n, int grid, hipStream_t s);
+// *st = the state a multi-kernel solve starts from (running, rtol, max_iter,
+// hist_cap, everything else zero), written by a one-thread kernel.
+hipError_t launch_state_init(DevState *st, double rtol, int32_t max_iter, int32_t hist_cap, hipStream_t s);
 
 // Shared by the C ABI sources: record the thread's error message and
 // return `s`; the device view of a matrix handle.

@@ -193,6 +193,38 @@ __device__ void cg_rr(DevState *st, double rr, double *hist, double *scal)
         st->status = ST_NOT_CONVERGED;
 }
 
+// Algorithm 2 in FP32 (the FP32-accumulating inner solver): the same steps
+// with alpha_i, beta_i (Eq. (3)), the norm and the test formed in FP32.
+// The state's doubles hold the FP32 values exactly.
+__device__ void cg_alpha32(DevState *st, float pap, float apap)
+{
+    if (!(pap > 0.0f) || !isfinite(pap) || !isfinite(apap)) {
+        st->status = ST_BREAKDOWN;
+        return;
+    }
+    const float rr = (float)st->rr;
+    const float alpha = rr / pap;
+    const float beta = alpha * alpha * apap / rr - 1.0f;  // Eq. (3)
+    st->alpha = alpha;
+    st->beta = beta;
+    if (st->it >= st->max_iter)
+        st->status = ST_NOT_CONVERGED;
+}
+
+__device__ void cg_rr32(DevState *st, float rr)
+{
+    const int it = st->it + 1;
+    st->it = it;
+    st->rr = rr;
+    st->last_rel = (double)sqrtf(rr) / st->bnorm;
+    if (!isfinite(rr))
+        st->status = ST_BREAKDOWN;
+    else if (sqrtf(rr) <= (float)st->tol)
+        st->status = ST_CONVERGED;
+    else if (it >= st->max_iter)
+        st->status = ST_NOT_CONVERGED;
+}
+
 // Algorithm 4: omega_i = <As,s>/<As,As>, beta_i = -<As,r0*>/<Ap,r0*> (the
 // form of Section 3.2), and <r_{i+1}, r_{i+1}> expanded in <s,s>, <s,As>,
 // <As,As>.
@@ -259,6 +291,38 @@ __device__ void finalize(DevState *st, int fin, const double *d, int K, double *
     }
     case FIN_CG_ALPHA:  // Algorithm 2: d = {<p_i,Ap_i>, <Ap_i,Ap_i>}
         cg_alpha(st, d[0], d[1], scal);
+        break;
+    case FIN_SETUP32: {  // FP32 inner start: d = {<r0,r0>, <r0,r0>} (FP32 values)
+        const float rr = (float)d[0];
+        st->it = 0;
+        st->rho_pub = 0;
+        st->rr = rr;
+        if (rr == 0.0f) {
+            st->bnorm = 0.0;
+            st->tol = 0.0;
+            st->last_rel = 0.0;
+            st->status = ST_ZERO_RHS;
+            break;
+        }
+        if (!isfinite(rr)) {
+            st->status = ST_BREAKDOWN;
+            break;
+        }
+        const float tol = (float)st->rtol * sqrtf(rr);
+        st->bnorm = (double)sqrtf(rr);
+        st->tol = tol;
+        st->last_rel = 1.0;
+        if (sqrtf(rr) <= tol)
+            st->status = ST_CONVERGED;
+        break;
+    }
+    case FIN_CG_ALPHA32:  // d = {<p_i,Ap_i>, <Ap_i,Ap_i>} (FP32 values)
+        cg_alpha32(st, (float)d[0], (float)d[1]);
+        break;
+    case FIN_CG_RR_ALPHA32:  // d = {<p_i,Ap_i>, <Ap_i,Ap_i>, <r_i,r_i>} (FP32 values)
+        cg_rr32(st, (float)d[2]);
+        if (st->status == ST_RUNNING)
+            cg_alpha32(st, (float)d[0], (float)d[1]);
         break;
     case FIN_CG_RR:  // Algorithm 2: d = {<r_i,r_i>}
         cg_rr(st, d[0], hist, scal);
@@ -576,10 +640,46 @@ __device__ __forceinline__ uint32_t wave_bcast(uint32_t x)
     return (uint32_t)__builtin_amdgcn_readfirstlane((int)x);
 }
 
-template <int K>
-__device__ __forceinline__ void reduce_point(dd (&v)[K], const RedArgs &red, int g, int G)
+// How a reduction point accumulates.  AccDD: double-double sums of exact
+// FP64 products, rounded once (the FP64 path and the exact FP32 mode).
+// AccF32: plain FP32 sums (the FP32-accumulating inner solver); a partial is
+// stored as the double holding the float, exactly.  Either way every sum
+// has a fixed order that depends only on the launch shape.
+struct AccDD {
+    using T = dd;
+    __device__ static T zero() { return dd{0.0, 0.0}; }
+    __device__ static T add(T a, T b) { return dd_add(a, b); }
+    __device__ static T wave(T v) { return wave_reduce(v); }
+    __device__ static void store(double *slot, T v)
+    {
+        store_coherent(slot, v.hi);
+        store_coherent(slot + 1, v.lo);
+    }
+    __device__ static T load(const double *slot) { return dd{load_coherent(slot), load_coherent(slot + 1)}; }
+    __device__ static double round(T v) { return v.hi + v.lo; }
+};
+
+struct AccF32 {
+    using T = float;
+    __device__ static T zero() { return 0.0f; }
+    __device__ static T add(T a, T b) { return a + b; }
+    __device__ static T wave(T v)
+    {
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1)
+            v = v + __shfl_xor(v, off, 64);
+        return v;
+    }
+    __device__ static void store(double *slot, T v) { store_coherent(slot, (double)v); }
+    __device__ static T load(const double *slot) { return (float)load_coherent(slot); }
+    __device__ static double round(T v) { return (double)v; }
+};
+
+template <int K, typename ACC = AccDD>
+__device__ __forceinline__ void reduce_point(typename ACC::T (&v)[K], const RedArgs &red, int g, int G)
 {
-    __shared__ dd lds[WAVES][KMAX];
+    using T = typename ACC::T;
+    __shared__ T lds[WAVES][KMAX];
     double *const part1 = red.partials;
     double *const part2 = red.partials + RED_L2_OFFSET;
     double *const pub = red.partials + RED_PUB_OFFSET;
@@ -593,7 +693,7 @@ __device__ __forceinline__ void reduce_point(dd (&v)[K], const RedArgs &red, int
 
 #pragma unroll
     for (int k = 0; k < K; ++k)
-        v[k] = wave_reduce(v[k]);
+        v[k] = ACC::wave(v[k]);
     if (wave > 0 && lane == 0) {
 #pragma unroll
         for (int k = 0; k < K; ++k)
@@ -605,29 +705,23 @@ __device__ __forceinline__ void reduce_point(dd (&v)[K], const RedArgs &red, int
 #pragma unroll
     for (int k = 0; k < K; ++k)
         for (int w = 1; w < WAVES; ++w)
-            v[k] = dd_add(v[k], lds[w][k]);
+            v[k] = ACC::add(v[k], lds[w][k]);
 
     if (red.fin == FIN_PUBLISH) {
         // First stage only; a later reduction point of the same solver, in
         // a later kernel, folds these partials into its own second stage.
         if (lane == 0) {
 #pragma unroll
-            for (int k = 0; k < K; ++k) {
-                double *slot = pub + 2 * ((size_t)k * GMAX + g);
-                store_coherent(slot, v[k].hi);
-                store_coherent(slot + 1, v[k].lo);
-            }
+            for (int k = 0; k < K; ++k)
+                ACC::store(pub + 2 * ((size_t)k * GMAX + g), v[k]);
         }
         return;
     }
     uint32_t prev = 0;
     if (lane == 0) {
 #pragma unroll
-        for (int k = 0; k < K; ++k) {
-            double *slot = part1 + 2 * ((size_t)k * GMAX + g);
-            store_coherent(slot, v[k].hi);
-            store_coherent(slot + 1, v[k].lo);
-        }
+        for (int k = 0; k < K; ++k)
+            ACC::store(part1 + 2 * ((size_t)k * GMAX + g), v[k]);
         // The partial stores must have reached the coherence point before
         // another workgroup can observe this arrival.
         __builtin_amdgcn_s_waitcnt(0);
@@ -641,10 +735,10 @@ __device__ __forceinline__ void reduce_point(dd (&v)[K], const RedArgs &red, int
     constexpr int KT = K + KP;
     const int kpub = KP > 0 ? red.kpub : 0;
     const int kt = K + kpub;
-    dd acc[KT];
+    T acc[KT];
 #pragma unroll
     for (int k = 0; k < KT; ++k)
-        acc[k] = dd{0.0, 0.0};
+        acc[k] = ACC::zero();
 
     // Few partials: the last group only signals, and the very last
     // workgroup sums every partial itself (one load round trip instead of
@@ -663,14 +757,14 @@ __device__ __forceinline__ void reduce_point(dd (&v)[K], const RedArgs &red, int
         // are requested before the first is added.
         constexpr int UB = K <= 1 ? 4 : (K == 2 ? 2 : 1);
         for (int j0 = lane; j0 < G; j0 += 64 * UB) {
-            dd t[UB][K];
+            T t[UB][K];
 #pragma unroll
             for (int u = 0; u < UB; ++u) {
 #pragma unroll
                 for (int k = 0; k < K; ++k) {
                     const double *slot = part1 + 2 * ((size_t)k * GMAX + j0 + 64 * u);
                     if (j0 + 64 * u < G)
-                        t[u][k] = dd{load_coherent(slot), load_coherent(slot + 1)};
+                        t[u][k] = ACC::load(slot);
                 }
             }
 #pragma unroll
@@ -678,21 +772,21 @@ __device__ __forceinline__ void reduce_point(dd (&v)[K], const RedArgs &red, int
                 if (j0 + 64 * u < G) {
 #pragma unroll
                     for (int k = 0; k < K; ++k)
-                        acc[k] = dd_add(acc[k], t[u][k]);
+                        acc[k] = ACC::add(acc[k], t[u][k]);
                 }
             }
         }
         if (kpub > 0) {
             constexpr int UP = KP <= 1 ? 2 : 2;
             for (int j0 = lane; j0 < red.npub; j0 += 64 * UP) {
-                dd t[UP][KP > 0 ? KP : 1];
+                T t[UP][KP > 0 ? KP : 1];
 #pragma unroll
                 for (int u = 0; u < UP; ++u) {
 #pragma unroll
                     for (int k = 0; k < KP; ++k) {
                         const double *slot = pub + 2 * ((size_t)k * GMAX + j0 + 64 * u);
                         if (k < kpub && j0 + 64 * u < red.npub)
-                            t[u][k] = dd{load_coherent(slot), load_coherent(slot + 1)};
+                            t[u][k] = ACC::load(slot);
                     }
                 }
 #pragma unroll
@@ -701,7 +795,7 @@ __device__ __forceinline__ void reduce_point(dd (&v)[K], const RedArgs &red, int
 #pragma unroll
                         for (int k = 0; k < KP; ++k)
                             if (k < kpub)
-                                acc[K + k] = dd_add(acc[K + k], t[u][k]);
+                                acc[K + k] = ACC::add(acc[K + k], t[u][k]);
                     }
                 }
             }
@@ -711,10 +805,8 @@ __device__ __forceinline__ void reduce_point(dd (&v)[K], const RedArgs &red, int
         // group's share of the published partials (dots K .. K + kpub - 1).
 #pragma unroll
         for (int k = 0; k < K; ++k) {
-            if (lane < gsize) {
-                const double *slot = part1 + 2 * ((size_t)k * GMAX + gbase + lane);
-                acc[k] = dd{load_coherent(slot), load_coherent(slot + 1)};
-            }
+            if (lane < gsize)
+                acc[k] = ACC::load(part1 + 2 * ((size_t)k * GMAX + gbase + lane));
         }
         if (kpub > 0) {
             const int p0 = (int)(((int64_t)red.npub * grp) / ngroups);
@@ -722,24 +814,19 @@ __device__ __forceinline__ void reduce_point(dd (&v)[K], const RedArgs &red, int
             for (int j = p0 + lane; j < p1; j += 64) {
 #pragma unroll
                 for (int k = 0; k < KP; ++k) {
-                    if (k < kpub) {
-                        const double *slot = pub + 2 * ((size_t)k * GMAX + j);
-                        acc[K + k] = dd_add(acc[K + k], dd{load_coherent(slot), load_coherent(slot + 1)});
-                    }
+                    if (k < kpub)
+                        acc[K + k] = ACC::add(acc[K + k], ACC::load(pub + 2 * ((size_t)k * GMAX + j)));
                 }
             }
         }
 #pragma unroll
         for (int k = 0; k < KT; ++k)
-            acc[k] = wave_reduce(acc[k]);
+            acc[k] = ACC::wave(acc[k]);
         if (lane == 0) {
 #pragma unroll
             for (int k = 0; k < KT; ++k) {
-                if (k < kt) {
-                    double *slot = part2 + 2 * ((size_t)k * RNGROUPS_MAX + grp);
-                    store_coherent(slot, acc[k].hi);
-                    store_coherent(slot + 1, acc[k].lo);
-                }
+                if (k < kt)
+                    ACC::store(part2 + 2 * ((size_t)k * RNGROUPS_MAX + grp), acc[k]);
             }
             __hip_atomic_store(cnt + (size_t)grp * CNT_STRIDE, 0u, __ATOMIC_RELAXED,
                                __HIP_MEMORY_SCOPE_AGENT);
@@ -753,21 +840,19 @@ __device__ __forceinline__ void reduce_point(dd (&v)[K], const RedArgs &red, int
         // Last group: sum the group sums, one per lane.
 #pragma unroll
         for (int k = 0; k < KT; ++k) {
-            acc[k] = dd{0.0, 0.0};
-            if (k < kt && lane < ngroups) {
-                const double *slot = part2 + 2 * ((size_t)k * RNGROUPS_MAX + lane);
-                acc[k] = dd{load_coherent(slot), load_coherent(slot + 1)};
-            }
+            acc[k] = ACC::zero();
+            if (k < kt && lane < ngroups)
+                acc[k] = ACC::load(part2 + 2 * ((size_t)k * RNGROUPS_MAX + lane));
         }
     }
 #pragma unroll
     for (int k = 0; k < KT; ++k)
-        acc[k] = wave_reduce(acc[k]);
+        acc[k] = ACC::wave(acc[k]);
     if (lane == 0) {
         double d[KT > 0 ? KT : 1];
 #pragma unroll
         for (int k = 0; k < KT; ++k)
-            d[k] = acc[k].hi + acc[k].lo;
+            d[k] = ACC::round(acc[k]);
         __hip_atomic_store(cnt + (size_t)RNGROUPS_MAX * CNT_STRIDE, 0u, __ATOMIC_RELAXED,
                            __HIP_MEMORY_SCOPE_AGENT);
         finalize(red.st, red.fin, d, kt, red.hist, red.scal);
@@ -936,11 +1021,42 @@ struct SliceCols {
     int slot;                          // COLS_SLOTS: lane l holds slot offset l of the slice
     uint32_t mask;                     // COLS_SLOTS: dg_mask[row]
     int row;
+    int safe_row;                      // min(row, n - 1): an address every lane may read
 };
 
-// Columns of entries k .. k+U-1 (k a multiple of U, U of 4), -1 past width.
+// The loads behind the columns of entries k .. k+U-1 (COLS_INT32: the
+// columns themselves; COLS_OFF16: the packed offsets; COLS_SLOTS: none, the
+// slice's slot offsets and the row's mask are loaded once per slice).
 template <int U, int COLS>
-__device__ __forceinline__ void slice_cols(const SliceCols<COLS> &sc, int k, int width, int (&c)[U])
+struct ColsRaw {
+    int32_t c[COLS == COLS_INT32 ? U : 1];
+    short4 o[COLS == COLS_OFF16 ? (U + 3) / 4 : 1];
+};
+
+// Phase 1: issue those loads (k a multiple of U, U a multiple of 4 for
+// 16-bit offsets); entries past width are not read.
+template <int U, int COLS>
+__device__ __forceinline__ void cols_issue(const SliceCols<COLS> &sc, int k, int width, ColsRaw<U, COLS> &r)
+{
+    if constexpr (COLS == COLS_OFF16) {
+        static_assert(U % 4 == 0, "16-bit offsets come four to a load");
+#pragma unroll
+        for (int j = 0; j < U / 4; ++j) {
+            r.o[j] = make_short4(SELL_PAD, SELL_PAD, SELL_PAD, SELL_PAD);
+            if (k + 4 * j < width)
+                r.o[j] = load_stream(sc.off4 + (size_t)(k / 4 + j) * SLICE);
+        }
+    } else if constexpr (COLS == COLS_INT32) {
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            r.c[u] = k + u < width ? load_stream(sc.col + (size_t)(k + u) * SLICE) : -1;
+    }
+}
+
+// Phase 2: the columns of entries k .. k+U-1, -1 for padding and past width.
+template <int U, int COLS>
+__device__ __forceinline__ void cols_decode(const SliceCols<COLS> &sc, int k, int width, const ColsRaw<U, COLS> &r,
+                                            int (&c)[U])
 {
     if constexpr (COLS == COLS_SLOTS) {
 #pragma unroll
@@ -953,13 +1069,9 @@ __device__ __forceinline__ void slice_cols(const SliceCols<COLS> &sc, int k, int
             }
         }
     } else if constexpr (COLS == COLS_OFF16) {
-        static_assert(U % 4 == 0, "16-bit offsets come four to a load");
 #pragma unroll
         for (int j = 0; j < U / 4; ++j) {
-            short4 o = make_short4(SELL_PAD, SELL_PAD, SELL_PAD, SELL_PAD);
-            if (k + 4 * j < width)
-                o = load_stream(sc.off4 + (size_t)(k / 4 + j) * SLICE);
-            const int16_t os[4] = {o.x, o.y, o.z, o.w};
+            const int16_t os[4] = {r.o[j].x, r.o[j].y, r.o[j].z, r.o[j].w};
 #pragma unroll
             for (int i = 0; i < 4; ++i)
                 c[4 * j + i] = (k + 4 * j + i < width && os[i] != SELL_PAD) ? sc.row + (int)os[i] : -1;
@@ -967,50 +1079,112 @@ __device__ __forceinline__ void slice_cols(const SliceCols<COLS> &sc, int k, int
     } else {
 #pragma unroll
         for (int u = 0; u < U; ++u)
-            c[u] = k + u < width ? load_stream(sc.col + (size_t)(k + u) * SLICE) : -1;
+            c[u] = r.c[u];
     }
 }
 
-// One row of a slice summed left to right (the row's CSR order): the lane's
-// entries k = 0 .. width-1 sit SLICE apart; U of them, with their gathers,
-// are requested before the first is added.  Padding only follows a row's
-// last nonzero and is skipped.
+// Entries k .. k+U-1 of one row of a slice, added to q left to right (the
+// row's CSR order).  The column loads and the value loads are all issued
+// before the first is waited for; then the U gathers; then the sums.
+// width is uniform over the wave, so every test on it is a scalar branch.
+// Padding only follows a row's last nonzero and is skipped.
+template <typename T, int U, int COLS>
+__device__ __forceinline__ void slice_row_chunk(const SliceCols<COLS> &cols, const T *__restrict__ vals,
+                                                const T *__restrict__ v, int k, int width, T &q)
+{
+    ColsRaw<U, COLS> raw;
+    cols_issue<U, COLS>(cols, k, width, raw);
+    // Every load below is unconditional, so the chunk is straight-line code
+    // and the compiler waits for exactly the loads it needs: entries past
+    // width re-read the slice's last entry (a cache hit) and a padding
+    // entry gathers the lane's own, clamped row; neither product is added.
+    T a[U], x[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+        a[u] = load_stream(vals + (size_t)min(k + u, width - 1) * SLICE);
+    int c[U];
+    cols_decode<U, COLS>(cols, k, width, raw, c);
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+        x[u] = v[c[u] >= 0 ? c[u] : cols.safe_row];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        const T t = q + a[u] * x[u];
+        q = c[u] >= 0 ? t : q;
+    }
+}
+
+// One row of a slice summed left to right: the lane's entries k = 0 ..
+// width-1 sit SLICE apart.  A slice of at most U entries per row (every
+// stencil here) takes one straight-line chunk, so the compiler can count
+// the loads in flight exactly; wider slices loop over chunks of U.
 template <typename T, int U, int COLS>
 __device__ __forceinline__ T slice_row_sum(const SliceCols<COLS> &cols, const T *__restrict__ vals,
                                            const T *__restrict__ v, int width)
 {
     T q = T(0);
-    for (int k = 0; k < width; k += U) {
-        int c[U];
-        T a[U], x[U];
-        slice_cols<U, COLS>(cols, k, width, c);
+    if constexpr (COLS == COLS_SLOTS) {
+        // at most DG_MAX_SLOTS slots: a fixed sequence of chunks, no loop
 #pragma unroll
-        for (int u = 0; u < U; ++u)
-            a[u] = k + u < width ? load_stream(vals + (size_t)(k + u) * SLICE) : T(0);
-#pragma unroll
-        for (int u = 0; u < U; ++u)
-            x[u] = c[u] >= 0 ? v[c[u]] : T(0);
-#pragma unroll
-        for (int u = 0; u < U; ++u)
-            if (c[u] >= 0)
-                q = q + a[u] * x[u];
+        for (int k = 0; k < DG_MAX_SLOTS; k += U)
+            if (k < width)
+                slice_row_chunk<T, U, COLS>(cols, vals, v, k, width, q);
+    } else {
+        for (int k = 0; k < width; k += U)
+            slice_row_chunk<T, U, COLS>(cols, vals, v, k, width, q);
     }
     return q;
+}
+
+// Start and width of slice sl, read once per wave and held as uniform values.
+__device__ __forceinline__ void slice_extent(const DevCsr &A, int sl, int &e0, int &width)
+{
+    e0 = __builtin_amdgcn_readfirstlane(A.sell_ptr[sl]);
+    const int e1 = __builtin_amdgcn_readfirstlane(A.sell_ptr[sl + 1]);
+    width = (e1 - e0) / SLICE;
+}
+
+// The slices the calling wave takes: first, first + step, ... below end
+// (DevCsr::sweep).  Workgroups are dealt to the eight XCDs round robin, so
+// blockIdx.x & 7 is the workgroup's XCD; in sweep mode the grid is a
+// multiple of 8 and no larger than what is resident at once, so each XCD's
+// waves form one window of consecutive slices that advances through the
+// XCD's eighth of the matrix: the gathers of a slice's neighbouring planes
+// (rows +- n^2 for a 3D stencil) find them in the XCD's own L2, fetched by
+// the window a moment earlier or later.
+__device__ __forceinline__ void slice_range(const DevCsr &A, int &first, int &end, int &step)
+{
+    constexpr int WPG = WG / SLICE;  // waves per workgroup
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / SLICE));
+    if (A.sweep) {
+        const int g8 = gridDim.x >> 3;
+        const int x = blockIdx.x & 7;
+        const int per = (A.nslices + 7) >> 3;
+        first = x * per + (int)(blockIdx.x >> 3) * WPG + wave;
+        end = min(A.nslices, (x + 1) * per);
+        step = g8 * WPG;
+    } else {
+        first = logical_wg() * WPG + wave;
+        end = A.nslices;
+        step = gridDim.x * WPG;
+    }
 }
 
 // The column form of slice sl for the lane's row.
 template <int COLS>
 __device__ __forceinline__ SliceCols<COLS> slice_cols_of(const DevCsr &A, int sl, int e0, int lane, int row)
 {
-    SliceCols<COLS> c{nullptr, nullptr, 0, 0u, row};
+    SliceCols<COLS> c{nullptr, nullptr, 0, 0u, row, min(row, A.n - 1)};
     if constexpr (COLS == COLS_INT32)
         c.col = A.sell_col + e0 + lane;
     else if constexpr (COLS == COLS_OFF16)
-        c.off4 = A.sell_off4 + A.sell_ptr4[sl] + lane;
+        c.off4 = A.sell_off4 + __builtin_amdgcn_readfirstlane(A.sell_ptr4[sl]) + lane;
     else {
-        // one coalesced load of the slice's slot offsets (width <= 32 lanes)
-        const int width = (A.sell_ptr[sl + 1] - e0) / SLICE;
-        c.slot = lane < width ? A.dg_off[e0 / SLICE + lane] : 0;
+        // one coalesced load of the slice's slot offsets (width <= 32 lanes;
+        // lanes past width read the last slot and do not use it)
+        // (the caller skips empty slices, so width >= 1 here)
+        const int width = (__builtin_amdgcn_readfirstlane(A.sell_ptr[sl + 1]) - e0) / SLICE;
+        c.slot = A.dg_off[e0 / SLICE + min(lane, width - 1)];
         c.mask = A.dg_mask[row];  // sized for every row of every slice
     }
     return c;
@@ -1034,33 +1208,35 @@ __global__ __launch_bounds__(WG, FK_SPMV_MIN_WAVES) void k_sell_rows(DevCsr A, R
     const int G = gridDim.x;
     const int g = logical_wg();
     const int lane = threadIdx.x & (SLICE - 1);
-    const int nw = G * (WG / SLICE);
+    int sl0, sl_end, sl_step;
+    slice_range(A, sl0, sl_end, sl_step);
 
     dd acc[KA];
 #pragma unroll
     for (int k = 0; k < KA; ++k)
         acc[k] = dd{0.0, 0.0};
 
-    for (int sl = g * (WG / SLICE) + (int)(threadIdx.x / SLICE); sl < A.nslices; sl += nw) {
-        const int e0 = A.sell_ptr[sl];
-        const int width = (A.sell_ptr[sl + 1] - e0) / SLICE;
+    for (int sl = sl0; sl < sl_end; sl += sl_step) {
+        int e0, width;
+        slice_extent(A, sl, e0, width);
         const int row = sl * SLICE + lane;
         const bool live = row < A.n;
+        const int srow = min(row, A.n - 1);  // read by every lane, used by live ones
         double vrow = 0.0, wrow = 0.0;
-        if (live) {
-            if constexpr (NEED_V)
-                vrow = io.v[row];
-            if constexpr (NEED_W)
-                wrow = io.w[row];
-        }
-        const SliceCols<COLS> cols = slice_cols_of<COLS>(A, sl, e0, lane, row);
+        if constexpr (NEED_V)
+            vrow = io.v[srow];
+        if constexpr (NEED_W)
+            wrow = io.w[srow];
         // (Three double-double accumulators leave room for fewer entries in
         // 64 VGPRs: 4 with int32 columns, 6 with slots.)
         constexpr int U = KA < 3 ? FK_SELL_UNROLL
                                  : COLS == COLS_INT32 ? FK_SELL_UNROLL / 2
                                  : COLS == COLS_SLOTS ? 6 : FK_SELL_UNROLL;
-        const double q = slice_row_sum<double, U, COLS>(
-            cols, A.sell_vals + e0 + lane, io.v, width);
+        double q = 0.0;
+        if (width > 0) {  // uniform: a slice of empty rows reads nothing
+            const SliceCols<COLS> cols = slice_cols_of<COLS>(A, sl, e0, lane, row);
+            q = slice_row_sum<double, U, COLS>(cols, A.sell_vals + e0 + lane, io.v, width);
+        }
         if (live) {
             if constexpr (K > 0)
                 row_epilogue<MODE, DOTS, KA>(io, row, q, vrow, wrow, acc);
@@ -1183,10 +1359,14 @@ __global__ __launch_bounds__(WG) void k_bicg_xrp(int64_t n, double *__restrict__
 // ------------------------------------------- classical building blocks
 
 // First stage of <a,b> (and <a,c> when NDOT == 2).
+// <a, b>, and <a, c>, <a, e> for NDOT = 2, 3: the dots of the classical
+// forms, and the separate dot kernels of the split variants of Sections 3.1
+// and 3.2 (the product's dots computed in a kernel of their own).
 template <int NDOT>
 __global__ __launch_bounds__(WG) void k_dot(int64_t n, const double *__restrict__ a,
                                              const double *__restrict__ b,
-                                             const double *__restrict__ c, RedArgs red)
+                                             const double *__restrict__ c,
+                                             const double *__restrict__ e, RedArgs red)
 {
     if (!runs(red))
         return;
@@ -1198,8 +1378,10 @@ __global__ __launch_bounds__(WG) void k_dot(int64_t n, const double *__restrict_
     for (int64_t i = (int64_t)blockIdx.x * WG + threadIdx.x; i < n; i += stride) {
         const double ai = a[i];
         dd_fma(acc[0], ai, b[i]);
-        if constexpr (NDOT == 2)
+        if constexpr (NDOT >= 2)
             dd_fma(acc[1], ai, c[i]);
+        if constexpr (NDOT >= 3)
+            dd_fma(acc[2], ai, e[i]);
     }
     reduce_point<NDOT>(acc, red, blockIdx.x, gridDim.x);
 }
@@ -1263,6 +1445,29 @@ __global__ __launch_bounds__(WG) void k_zero(double *__restrict__ x, int64_t n,
         x[i] = 0.0;
 }
 
+// x[0 .. n) = 0 unconditionally (scratch that must start at zero).
+__global__ __launch_bounds__(WG) void k_clear(double *__restrict__ x, int64_t n)
+{
+    const int64_t stride = (int64_t)gridDim.x * WG;
+    for (int64_t i = (int64_t)blockIdx.x * WG + threadIdx.x; i < n; i += stride)
+        x[i] = 0.0;
+}
+
+// The state a multi-kernel solve starts from, written by the device (every
+// field zero except these).
+__global__ __launch_bounds__(64) void k_state_init(DevState *st, double rtol, int32_t max_iter,
+                                                    int32_t hist_cap)
+{
+    if (threadIdx.x != 0)
+        return;
+    DevState s{};
+    s.status = ST_RUNNING;
+    s.rtol = rtol;
+    s.max_iter = max_iter;
+    s.hist_cap = hist_cap;
+    *st = s;
+}
+
 // ------------------------------------- mixed precision: FP32 inner solver
 
 // Fixed-order workgroup sum of one float (long CSR rows of the FP32 product).
@@ -1283,12 +1488,39 @@ __device__ __forceinline__ float block_sum_f(float v, float *lds)
     return s;
 }
 
+// The two dot accumulators of the FP32 products: exact (the product of two
+// floats is exact in FP64, summed in double-double as on the FP64 path, so
+// independent of the launch shape) or FP32 (product rounded to FP32, added
+// to an FP32 sum).
+template <bool F32ACC>
+struct Dots32 {
+    using ACC = AccDD;
+    dd a[2] = {dd{0.0, 0.0}, dd{0.0, 0.0}};
+    __device__ void add(float q, float vrow)
+    {
+        dd_fma(a[0], (double)q, (double)vrow);
+        dd_fma(a[1], (double)q, (double)q);
+    }
+};
+
+template <>
+struct Dots32<true> {
+    using ACC = AccF32;
+    float a[2] = {0.0f, 0.0f};
+    __device__ void add(float q, float vrow)
+    {
+        const float qv = q * vrow;
+        const float qq = q * q;
+        a[0] = a[0] + qv;
+        a[1] = a[1] + qq;
+    }
+};
+
 // y = A v in FP32 storage and arithmetic (values rounded to FP32 once, when
 // the solver is created), each row summed left to right in FP32, fused with
-// the first stage of <y, v>, <y, y>: the product kernel of the inner
-// pipelined CG of the mixed-precision method.  The product of two floats is
-// exact in FP64, so the dots accumulate exact products in double-double, as
-// on the FP64 path, and do not depend on the launch shape.
+// the first stage of <y, v>, <y, y> (Dots32<F32ACC>): the product kernel of
+// the inner pipelined CG of the mixed-precision methods.
+template <bool F32ACC>
 __global__ __launch_bounds__(WG, FK_SPMV_MIN_WAVES) void k_csr_rows32(DevCsr A, const float *vals32,
                                                                        const float *v, float *y,
                                                                        RedArgs red)
@@ -1303,7 +1535,7 @@ __global__ __launch_bounds__(WG, FK_SPMV_MIN_WAVES) void k_csr_rows32(DevCsr A, 
     const int b_begin = (int)(((int64_t)A.nblocks * g) / G);
     const int b_end = (int)(((int64_t)A.nblocks * (g + 1)) / G);
     const int tid = threadIdx.x;
-    dd acc[2] = {dd{0.0, 0.0}, dd{0.0, 0.0}};
+    Dots32<F32ACC> acc;
     for (int blk = b_begin; blk < b_end; ++blk) {
         const int r0 = A.blocks[blk];
         const int r1 = A.blocks[blk + 1];
@@ -1341,8 +1573,7 @@ __global__ __launch_bounds__(WG, FK_SPMV_MIN_WAVES) void k_csr_rows32(DevCsr A, 
                 for (int e = e0; e < e1; ++e)
                     q = q + prod[e];
                 y[r0 + tid] = q;
-                dd_fma(acc[0], (double)q, (double)vrow);
-                dd_fma(acc[1], (double)q, (double)q);
+                acc.add(q, vrow);
             }
             __syncthreads();
         } else {
@@ -1352,16 +1583,15 @@ __global__ __launch_bounds__(WG, FK_SPMV_MIN_WAVES) void k_csr_rows32(DevCsr A, 
             const float q = block_sum_f(part, red_lds);
             if (tid == 0) {
                 y[r0] = q;
-                dd_fma(acc[0], (double)q, (double)v[r0]);
-                dd_fma(acc[1], (double)q, (double)q);
+                acc.add(q, v[r0]);
             }
         }
     }
-    reduce_point<2>(acc, red, g, G);
+    reduce_point<2, typename Dots32<F32ACC>::ACC>(acc.a, red, g, G);
 }
 
 // k_csr_rows32 on the sliced layout (vals32 in slice order).
-template <int COLS>
+template <int COLS, bool F32ACC>
 __global__ __launch_bounds__(WG, FK_SPMV_MIN_WAVES) void k_sell_rows32(DevCsr A, const float *vals32,
                                                                         const float *v, float *y,
                                                                         RedArgs red)
@@ -1371,27 +1601,32 @@ __global__ __launch_bounds__(WG, FK_SPMV_MIN_WAVES) void k_sell_rows32(DevCsr A,
     const int G = gridDim.x;
     const int g = logical_wg();
     const int lane = threadIdx.x & (SLICE - 1);
-    const int nw = G * (WG / SLICE);
-    dd acc[2] = {dd{0.0, 0.0}, dd{0.0, 0.0}};
-    for (int sl = g * (WG / SLICE) + (int)(threadIdx.x / SLICE); sl < A.nslices; sl += nw) {
-        const int e0 = A.sell_ptr[sl];
-        const int width = (A.sell_ptr[sl + 1] - e0) / SLICE;
+    int sl0, sl_end, sl_step;
+    slice_range(A, sl0, sl_end, sl_step);
+    Dots32<F32ACC> acc;
+    for (int sl = sl0; sl < sl_end; sl += sl_step) {
+        int e0, width;
+        slice_extent(A, sl, e0, width);
         const int row = sl * SLICE + lane;
         const bool live = row < A.n;
-        const float vrow = live ? v[row] : 0.f;
-        const SliceCols<COLS> cols = slice_cols_of<COLS>(A, sl, e0, lane, row);
-        const float q = slice_row_sum<float, FK_SELL_UNROLL, COLS>(cols, vals32 + e0 + lane, v, width);
+        const float vrow = v[min(row, A.n - 1)];
+        float q = 0.f;
+        if (width > 0) {  // uniform: a slice of empty rows reads nothing
+            const SliceCols<COLS> cols = slice_cols_of<COLS>(A, sl, e0, lane, row);
+            q = slice_row_sum<float, FK_SELL_UNROLL, COLS>(cols, vals32 + e0 + lane, v, width);
+        }
         if (live) {
             y[row] = q;
-            dd_fma(acc[0], (double)q, (double)vrow);
-            dd_fma(acc[1], (double)q, (double)q);
+            acc.add(q, vrow);
         }
     }
-    reduce_point<2>(acc, red, g, G);
+    reduce_point<2, typename Dots32<F32ACC>::ACC>(acc.a, red, g, G);
 }
 
-// Inner FP32 update of Algorithm 2 (alpha, beta rounded to FP32):
-// d += alpha p; r -= alpha A p; p = r + beta p; first stage of <r, r>.
+// Inner FP32 update of Algorithm 2 (alpha, beta held in FP32):
+// d += alpha p; r -= alpha A p; p = r + beta p; first stage of <r, r>
+// (Dots32<F32ACC>: both slots take <r, r>, the first is reduced).
+template <bool F32ACC>
 __global__ __launch_bounds__(WG) void k_cg_update32(int64_t n, float *__restrict__ d,
                                                      float *__restrict__ r, float *__restrict__ p,
                                                      const float *__restrict__ ap, RedArgs red)
@@ -1400,7 +1635,7 @@ __global__ __launch_bounds__(WG) void k_cg_update32(int64_t n, float *__restrict
         return;
     const float alpha = (float)red.st->alpha;
     const float beta = (float)red.st->beta;
-    dd acc[1] = {dd{0.0, 0.0}};
+    typename Dots32<F32ACC>::ACC::T acc[1] = {Dots32<F32ACC>::ACC::zero()};
     const int64_t stride = (int64_t)gridDim.x * WG;
 #pragma unroll FK_VEC_UNROLL
     for (int64_t i = (int64_t)blockIdx.x * WG + threadIdx.x; i < n; i += stride) {
@@ -1409,29 +1644,34 @@ __global__ __launch_bounds__(WG) void k_cg_update32(int64_t n, float *__restrict
         const float ri = r[i] - alpha * ap[i];
         r[i] = ri;
         p[i] = ri + beta * pi;
-        dd_fma(acc[0], (double)ri, (double)ri);
+        if constexpr (F32ACC) {
+            const float rr = ri * ri;
+            acc[0] = acc[0] + rr;
+        } else {
+            dd_fma(acc[0], (double)ri, (double)ri);
+        }
     }
-    reduce_point<1>(acc, red, blockIdx.x, gridDim.x);
+    reduce_point<1, typename Dots32<F32ACC>::ACC>(acc, red, blockIdx.x, gridDim.x);
 }
 
 // Inner start (d0 = 0): p = r, d = 0, first stage of <r, r> (reported twice,
 // as the residual norm and as the norm of the inner right-hand side).
+template <bool F32ACC>
 __global__ __launch_bounds__(WG) void k_inner_setup32(int64_t n, const float *__restrict__ r,
                                                        float *__restrict__ p, float *__restrict__ d,
                                                        RedArgs red)
 {
     if (!runs(red))
         return;
-    dd acc[2] = {dd{0.0, 0.0}, dd{0.0, 0.0}};
+    Dots32<F32ACC> acc;
     const int64_t stride = (int64_t)gridDim.x * WG;
     for (int64_t i = (int64_t)blockIdx.x * WG + threadIdx.x; i < n; i += stride) {
         const float ri = r[i];
         p[i] = ri;
         d[i] = 0.f;
-        dd_fma(acc[0], (double)ri, (double)ri);
-        dd_fma(acc[1], (double)ri, (double)ri);
+        acc.add(ri, ri);
     }
-    reduce_point<2>(acc, red, blockIdx.x, gridDim.x);
+    reduce_point<2, typename Dots32<F32ACC>::ACC>(acc.a, red, blockIdx.x, gridDim.x);
 }
 
 // out = alpha x + beta y.
@@ -2163,28 +2403,40 @@ hipError_t launch_residual32(const DevCsr &A, const double *b, const double *x, 
     return launch_rows<ROW_RESID32, 0>(A, io, red, grid, s);
 }
 
-hipError_t launch_spmv32(const DevCsr &A, const float *vals32, const float *v, float *y,
-                         const RedArgs &red, int grid, hipStream_t s)
+template <bool F32ACC>
+static hipError_t launch_spmv32_t(const DevCsr &A, const float *vals32, const float *v, float *y,
+                                  const RedArgs &red, int grid, hipStream_t s)
 {
     if (A.nslices > 0 && A.dg_mask)
-        return launch(k_sell_rows32<COLS_SLOTS>, grid, WG, s, A, vals32, v, y, red);
+        return launch(k_sell_rows32<COLS_SLOTS, F32ACC>, grid, WG, s, A, vals32, v, y, red);
     if (A.nslices > 0 && A.sell_off4)
-        return launch(k_sell_rows32<COLS_OFF16>, grid, WG, s, A, vals32, v, y, red);
+        return launch(k_sell_rows32<COLS_OFF16, F32ACC>, grid, WG, s, A, vals32, v, y, red);
     if (A.nslices > 0)
-        return launch(k_sell_rows32<COLS_INT32>, grid, WG, s, A, vals32, v, y, red);
-    return launch(k_csr_rows32, grid, WG, s, A, vals32, v, y, red);
+        return launch(k_sell_rows32<COLS_INT32, F32ACC>, grid, WG, s, A, vals32, v, y, red);
+    return launch(k_csr_rows32<F32ACC>, grid, WG, s, A, vals32, v, y, red);
+}
+
+hipError_t launch_spmv32(const DevCsr &A, const float *vals32, const float *v, float *y,
+                         const RedArgs &red, int grid, hipStream_t s, bool f32acc)
+{
+    return f32acc ? launch_spmv32_t<true>(A, vals32, v, y, red, grid, s)
+                  : launch_spmv32_t<false>(A, vals32, v, y, red, grid, s);
 }
 
 hipError_t launch_cg_update32(int64_t n, float *d, float *r, float *p, const float *ap,
-                              const RedArgs &red, int grid, hipStream_t s)
+                              const RedArgs &red, int grid, hipStream_t s, bool f32acc)
 {
-    return launch(k_cg_update32, grid, WG, s, n, d, r, p, ap, red);
+    if (f32acc)
+        return launch(k_cg_update32<true>, grid, WG, s, n, d, r, p, ap, red);
+    return launch(k_cg_update32<false>, grid, WG, s, n, d, r, p, ap, red);
 }
 
 hipError_t launch_inner_setup32(int64_t n, const float *r, float *p, float *d, const RedArgs &red,
-                                int grid, hipStream_t s)
+                                int grid, hipStream_t s, bool f32acc)
 {
-    return launch(k_inner_setup32, grid, WG, s, n, r, p, d, red);
+    if (f32acc)
+        return launch(k_inner_setup32<true>, grid, WG, s, n, r, p, d, red);
+    return launch(k_inner_setup32<false>, grid, WG, s, n, r, p, d, red);
 }
 
 hipError_t launch_axpby(int64_t n, double alpha, const double *x, double beta, const double *y,
@@ -2223,12 +2475,14 @@ hipError_t launch_bicg_xrp(int64_t n, double *x, double *r, double *p, const dou
 }
 
 hipError_t launch_dot(int64_t n, const double *a, const double *b, const double *c, int ndots,
-                      const RedArgs &red, int grid, hipStream_t s)
+                      const RedArgs &red, int grid, hipStream_t s, const double *e)
 {
     if (ndots == 1)
-        return launch(k_dot<1>, grid, WG, s, n, a, b, c, red);
+        return launch(k_dot<1>, grid, WG, s, n, a, b, c, e, red);
     if (ndots == 2)
-        return launch(k_dot<2>, grid, WG, s, n, a, b, c, red);
+        return launch(k_dot<2>, grid, WG, s, n, a, b, c, e, red);
+    if (ndots == 3)
+        return launch(k_dot<3>, grid, WG, s, n, a, b, c, e, red);
     return hipErrorInvalidValue;
 }
 
@@ -2254,6 +2508,16 @@ hipError_t launch_zero(double *x, int64_t n, DevState *st, uint32_t run_mask, in
                        hipStream_t s)
 {
     return launch(k_zero, grid, WG, s, x, n, st, run_mask);
+}
+
+hipError_t launch_clear(double *x, int64_t n, int grid, hipStream_t s)
+{
+    return launch(k_clear, grid, WG, s, x, n);
+}
+
+hipError_t launch_state_init(DevState *st, double rtol, int32_t max_iter, int32_t hist_cap, hipStream_t s)
+{
+    return launch(k_state_init, 1, 64, s, st, rtol, max_iter, hist_cap);
 }
 
 size_t small_lds_bytes(int method_bicg, int64_t n)

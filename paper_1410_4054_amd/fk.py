@@ -24,10 +24,15 @@ STATUS_NAMES = {
 }
 # fk_method
 METHODS = {"cg_pipelined": 0, "cg_classical": 1, "bicgstab_pipelined": 2, "bicgstab_classical": 3,
-           "cg_mixed": 4, "gmres_pipelined": 5, "gmres_classical": 6}
+           "cg_mixed": 4, "gmres_pipelined": 5, "gmres_classical": 6, "cg_mixed_f32": 7,
+           "cg_pipelined_split": 8, "bicgstab_pipelined_split": 9}
+# methods that record per-iteration scalars (alpha, beta, omega, <r,r>)
+SCALAR_METHODS = ("cg_pipelined", "cg_classical", "bicgstab_pipelined", "bicgstab_classical",
+                  "cg_pipelined_split", "bicgstab_pipelined_split")
 FLAG_GRAPH = 1
 FLAG_PROFILE = 2
 FLAG_NO_SMALL = 4
+FLAG_SCALARS = 8
 PTR_HOST, PTR_DEVICE = 0, 1
 KERNEL_KINDS = ("setup", "spmv_dot", "update_dot", "spmv", "dot", "axpy", "small", "residual")
 LONG_ROW = 2048
@@ -109,6 +114,7 @@ def lib():
             "fk_solver_uses_small": [vp, P(i32)],
             "fk_get_refinements": [vp, P(i32)],
             "fk_spmv": [vp, vp, vp, P(f64), vp],
+            "fk_spmv32": [vp, vp, vp, i32, P(f64), vp],
             "fk_dot": [i64, vp, vp, P(f64), vp],
             "fk_copy": [vp, vp, i64, vp],
             "fk_axpby": [i64, f64, vp, f64, vp, vp, vp],
@@ -147,7 +153,8 @@ def exported_symbols() -> list[str]:
         "fk_csr_set_layout",
         "fk_solver_create", "fk_solve", "fk_get_iterations", "fk_get_residual",
         "fk_get_residual_history", "fk_get_scalars", "fk_get_kernel_times",
-        "fk_solver_destroy", "fk_solver_uses_small", "fk_get_refinements", "fk_spmv", "fk_dot", "fk_copy",
+        "fk_solver_destroy", "fk_solver_uses_small", "fk_get_refinements", "fk_spmv", "fk_spmv32", "fk_dot",
+        "fk_copy",
         "fk_axpby", "fk_net_num_weights", "fk_net_create", "fk_net_destroy", "fk_net_get_weights",
         "fk_net_set_weights", "fk_net_forward", "fk_net_guess", "fk_net_gradient", "fk_net_train_step",
         "fk_batch_create", "fk_batch_destroy", "fk_batch_shape", "fk_batch_solve", "fk_batch_results",
@@ -266,6 +273,21 @@ def spmv(A: Matrix, p, q, dots: bool = False, stream=None):
     return (out[0], out[1]) if dots else None
 
 
+def spmv32(A: Matrix, p, q, f32acc: bool = False, stream=None) -> tuple[float, float]:
+    """q = A p in FP32 (float32 tensors); returns (<p,q>, <q,q>), exact sums of
+    the FP32 operands (f32acc False) or FP32 accumulations (f32acc True)."""
+    import torch
+
+    for t, nm in ((p, "p"), (q, "q")):
+        if not (t.is_cuda and t.dtype == torch.float32 and t.is_contiguous() and t.numel() == A.n):
+            raise ValueError(f"{nm} must be a contiguous float32 CUDA tensor of {A.n} elements")
+    out = (ctypes.c_double * 2)()
+    st = lib().fk_spmv32(A.handle, ctypes.c_void_p(p.data_ptr()), ctypes.c_void_p(q.data_ptr()),
+                         1 if f32acc else 0, out, ctypes.c_void_p(_stream_ptr(stream)))
+    _check(st, "fk_spmv32")
+    return out[0], out[1]
+
+
 def dot(a, b, stream=None) -> float:
     n = a.numel()
     out = ctypes.c_double()
@@ -305,13 +327,16 @@ class Solver:
     """fk_solver handle: workspace for one matrix, method and option set."""
 
     def __init__(self, A: Matrix, method: str = "cg_pipelined", rtol: float = 1e-8,
-                 max_iter: int | None = None, record_history: bool = True, unroll: int = 32,
+                 max_iter: int | None = None, record_history: bool | int = True, unroll: int = 32,
                  graph: bool = False, profile: bool = False, small: bool = True,
-                 inner_rtol: float = 0.0, max_outer: int = 0, restart: int = 0, stream=None):
+                 inner_rtol: float = 0.0, max_outer: int = 0, restart: int = 0, stream=None,
+                 record_scalars: bool = False):
         """small=False forces the multi-kernel path even where the
         single-workgroup solver applies.  inner_rtol, max_outer: options of
         method "cg_mixed" (0 = library defaults 1e-4 and 50); restart: the
-        GMRES restart length m (0 = 30)."""
+        GMRES restart length m (0 = 30).  record_history: True keeps up to
+        FK_HISTORY_DEFAULT entries, an int > 1 that many; record_scalars
+        also keeps alpha, beta, omega and <r,r> per iteration."""
         import torch
 
         self.A = A
@@ -322,8 +347,9 @@ class Solver:
             stream = torch.cuda.Stream()
         self.stream = stream
         flags = ((FLAG_GRAPH if graph else 0) | (FLAG_PROFILE if profile else 0)
-                 | (0 if small else FLAG_NO_SMALL))
-        o = _Opts(METHODS[method], float(rtol), int(max_iter), int(bool(record_history)),
+                 | (0 if small else FLAG_NO_SMALL) | (FLAG_SCALARS if record_scalars else 0))
+        rh = int(record_history) if not isinstance(record_history, bool) else int(record_history)
+        o = _Opts(METHODS[method], float(rtol), int(max_iter), rh,
                   int(unroll), flags, float(inner_rtol), int(max_outer), int(restart))
         h = ctypes.c_void_p()
         st = lib().fk_solver_create(A.handle, ctypes.byref(o), ctypes.c_void_p(_stream_ptr(stream)),
@@ -365,7 +391,7 @@ class Solver:
         return v.value
 
     def history(self) -> np.ndarray:
-        k = self.refinements() if self.method == "cg_mixed" else self.iterations()
+        k = self.refinements() if self.method in ("cg_mixed", "cg_mixed_f32") else self.iterations()
         buf = np.empty(k + 1)
         ln = ctypes.c_int32()
         _check(lib().fk_get_residual_history(self._h, buf.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
@@ -403,11 +429,13 @@ class Solver:
 def solve(A: Matrix, b, x, method: str = "cg_pipelined", rtol: float = 1e-8,
           max_iter: int | None = None, record_history: bool = True, **kw) -> SolveResult:
     """One-shot solve of A x = b on the device (x holds x0 on entry)."""
-    S = Solver(A, method=method, rtol=rtol, max_iter=max_iter, record_history=record_history, **kw)
+    want_scal = bool(record_history) and method in SCALAR_METHODS
+    S = Solver(A, method=method, rtol=rtol, max_iter=max_iter, record_history=record_history,
+               record_scalars=want_scal, **kw)
     try:
         st = S.solve(b, x)
         hist = S.history() if record_history else None
-        scal = S.scalars() if record_history and method in METHODS and METHODS[method] < 4 else None
+        scal = S.scalars() if want_scal else None
         return SolveResult(STATUS_NAMES[st], S.iterations(), S.residual(), hist, scal,
                            S.refinements())
     finally:

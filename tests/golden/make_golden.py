@@ -2,14 +2,17 @@
 
 Calls only the CPU oracle (oracle/) and the seeded input generators; never
 the GPU library.  For each case it stores the iteration count, status, the
-residual history ||r_i||/||b|| (all of it, as exact hex floats), and the
-iterate at 4099 evenly spaced indices plus its 2-norm.
+residual history ||r_i||/||b|| (all of it, as exact hex floats), the
+SHA-256 of the whole iterate's bytes (float64, little-endian) with its
+2-norm as an exact hex float (a machine-independent sum), and the iterate at 4099 evenly spaced indices
+(a readable sample of the same vector).
 
     python tests/golden/make_golden.py            # all cases
     python tests/golden/make_golden.py NAME ...   # selected cases
 """
 from __future__ import annotations
 
+import hashlib
 import json
 import os
 import sys
@@ -36,6 +39,20 @@ CASES = {
 }
 INNER_RTOL = 1e-4
 NSAMPLES = 4099
+
+
+def x_norm(x) -> float:
+    """||x||_2 from the correctly rounded sum of the rounded squares (math.fsum):
+    the same bits on every machine, unlike a BLAS norm."""
+    import math
+
+    x = np.asarray(x, dtype=np.float64)
+    return math.sqrt(math.fsum((x * x).tolist()))
+
+
+def x_sha256(x) -> str:
+    """SHA-256 of a float64 vector's bytes, little-endian."""
+    return hashlib.sha256(np.ascontiguousarray(x, dtype="<f8").tobytes()).hexdigest()
 
 
 def sample_indices(n: int) -> np.ndarray:
@@ -69,6 +86,8 @@ def make(name: str) -> dict:
         "x_index": idx.tolist(),
         "x_sample_hex": [float(v).hex() for v in res.x[idx]],
         "x_norm": float(np.linalg.norm(res.x)),
+        "x_norm_hex": x_norm(res.x).hex(),
+        "x_sha256": x_sha256(res.x),
         "oracle_seconds": round(dt, 2),
         "made_by": "tests/golden/make_golden.py (CPU oracle only)",
     }

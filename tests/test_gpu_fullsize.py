@@ -1,13 +1,14 @@
 """The benchmark workloads at full size, in the benchmark's launch
 configuration, against values stored by tests/golden/make_golden.py (CPU
-oracle only): iteration count, the whole residual history, the iterate at
-4099 sampled rows and its norm, and the true residual of the GPU iterate
-computed by the oracle's product."""
+oracle only): iteration count, the whole residual history, the whole
+iterate (SHA-256 of its bytes: the GPU reproduces the oracle's iterate bit
+for bit) and its norm as an exact hex float, and the true residual of the
+GPU iterate computed by the oracle's product."""
 import numpy as np
 import pytest
 
 import oracle
-from golden.make_golden import load
+from golden.make_golden import load, x_norm, x_sha256
 from gpu_util import gpu_solve
 from paper_1410_4054_amd import problems as P
 
@@ -34,12 +35,12 @@ def test_full_size_against_oracle(name, device):
     res, x = gpu_solve(A, b, x0, method=g["method"], rtol=g["rtol"], max_iter=g["max_iter"])
     hist = np.array([float.fromhex(h) for h in g["history_hex"]])
     assert res.status == g["status"] and res.k == g["k"], (res.status, res.k, g["k"])
-    np.testing.assert_allclose(res.history, hist, rtol=1e-13, atol=0)
+    assert np.array_equal(res.history, hist)
     idx = np.array(g["x_index"])
     xs = np.array([float.fromhex(h) for h in g["x_sample_hex"]])
-    scale = np.abs(xs).max()
-    assert np.abs(x[idx] - xs).max() <= 1e-10 * scale
-    assert abs(np.linalg.norm(x) / g["x_norm"] - 1.0) <= 1e-10
+    assert np.array_equal(x[idx], xs)
+    assert x_sha256(x) == g["x_sha256"]
+    assert x_norm(x).hex() == g["x_norm_hex"]
     if g["status"] == "converged":
         assert oracle.true_residual(A, b, x) <= g["rtol"] * 1.5
 

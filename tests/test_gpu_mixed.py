@@ -12,7 +12,7 @@ import pytest
 import scipy.sparse
 
 import oracle
-from golden.make_golden import load
+from golden.make_golden import load, x_sha256
 from gpu_util import dev, host, rel, require_layout
 from paper_1410_4054_amd import fk, problems as P
 
@@ -186,4 +186,5 @@ def test_mixed_full_size(device):
     idx = np.array(g["x_index"])
     xs = np.array([float.fromhex(h) for h in g["x_sample_hex"]])
     assert np.array_equal(x[idx], xs)
+    assert x_sha256(x) == g["x_sha256"]
     assert oracle.true_residual(A, b, x) <= g["rtol"]

@@ -1,0 +1,241 @@
+"""The FP32-accumulating refinement (method "cg_mixed_f32": FP32 vectors,
+FP32 products, inner products accumulated in FP32 by fixed-order trees,
+scalars of Algorithm 2 in FP32) and its product kernel, through the C ABI.
+
+A tree of FP32 additions and the oracle's left-to-right FP32 sum round
+differently, so this mode is judged by stated tolerances instead of bit
+equality:
+  - the FP32 product rows: bit for bit against the oracle (both sum each
+    row left to right in FP32);
+  - its inner products: within the FP32 recursive-summation bound
+    gamma_n sum |a_i b_i| (u = 2^-24) of the exact value, as the oracle's
+    sequential FP32 dot is, hence within twice that of the oracle's;
+  - solves: true FP64 residual <= rtol (computed by the oracle), and
+    ||x - x*|| / ||x*|| <= kappa * rtol against the FP64 solution x* (the
+    sine-transform solution where one exists, else the oracle's FP64 CG
+    to 1e-13), printed per case; sweeps and inner iterations close to the
+    oracle's FP32-accumulating refinement on the same input;
+  - determinism: a fixed launch shape gives the same bits every run and in
+    every driver mode (batch size, graph replay)."""
+from fractions import Fraction
+
+import numpy as np
+import pytest
+import scipy.fft
+import scipy.sparse
+
+import oracle
+from gpu_util import dev, host, rel, require_layout
+from paper_1410_4054_amd import fk, problems as P
+
+pytestmark = pytest.mark.gpu
+
+U32 = 2.0 ** -24
+
+
+def _gamma(n):
+    return n * U32 / (1.0 - n * U32)
+
+
+def _dst_2d(n, b):
+    t = np.pi * np.arange(1, n + 1) / (n + 1)
+    lam = 4.0 - 2.0 * np.cos(t)[:, None] - 2.0 * np.cos(t)[None, :]
+    bh = scipy.fft.dstn(b.reshape(n, n), type=1, norm="ortho")
+    return scipy.fft.idstn(bh / lam, type=1, norm="ortho").ravel(), lam.max() / lam.min()
+
+
+def _dst_3d(n, b):
+    t = np.pi * np.arange(1, n + 1) / (n + 1)
+    c = np.cos(t)
+    lam = 6.0 - 2.0 * (c[:, None, None] + c[None, :, None] + c[None, None, :])
+    bh = scipy.fft.dstn(b.reshape(n, n, n), type=1, norm="ortho")
+    return scipy.fft.idstn(bh / lam, type=1, norm="ortho").ravel(), lam.max() / lam.min()
+
+
+def _random_spd_csr(n, seed):
+    R = P.random_csr(n, 4, seed=seed, empty_rows=7, long_rows={17: 2600}).to_scipy()
+    S = abs(R + R.T).tocsr()
+    S.setdiag(0.0)
+    S.eliminate_zeros()
+    d = np.asarray(abs(S).sum(axis=1)).ravel() + 1.0
+    M = (-S + scipy.sparse.diags(d)).tocsr()
+    M.sort_indices()
+    return P.Csr(n, M.indptr.astype(np.int32), M.indices.astype(np.int32), M.data.astype(np.float64))
+
+
+def _reference(name):
+    """(A, b, x*, kappa): x* the FP64 solution (sine transform or oracle FP64
+    CG to 1e-13), kappa the 2-norm condition number (closed form or LAPACK)."""
+    if name.startswith("poisson2d_"):
+        n = int(name.split("_")[1])
+        A, b, _ = P.workload(name)
+        xs, kappa = _dst_2d(n, b)
+        return A, b, xs, kappa
+    if name.startswith("poisson3d_"):
+        n = int(name.split("_")[1])
+        A, b, _ = P.workload(name)
+        xs, kappa = _dst_3d(n, b)
+        return A, b, xs, kappa
+    if name == "heat2d_48":
+        A, b, _ = P.workload(name)
+    elif name == "shifted2d_45":
+        rng = np.random.default_rng(7)
+        shift = rng.uniform(0.0, 0.1, 45 * 45)
+        b = rng.uniform(-1.0, 1.0, 45 * 45)
+        A = P.poisson2d(45, diag_shift=shift)
+    elif name == "random_spd_csr":
+        A = _random_spd_csr(3000, 11)
+        b = P.rhs_uniform(3000, 11)
+    else:
+        raise KeyError(name)
+    lam = np.linalg.eigvalsh(A.to_scipy().toarray())
+    xs = oracle.solve(A, b, method="cg_pipelined", rtol=1e-13).x
+    return A, b, xs, float(lam.max() / lam.min())
+
+
+def f32_solve(A, b, x0=None, rtol=1e-10, inner_rtol=1e-4, max_iter=None, max_outer=0, layout=None,
+              matrix=None, **kw):
+    M = matrix or fk.Matrix(A, layout=layout)
+    bd = dev(b)
+    xd = dev(np.zeros(A.n) if x0 is None else x0)
+    res = fk.solve(M, bd, xd, method="cg_mixed_f32", rtol=rtol, max_iter=max_iter,
+                   inner_rtol=inner_rtol, max_outer=max_outer, **kw)
+    if matrix is None:
+        M.close()
+    return res, host(xd)
+
+
+KERNEL_CASES = {
+    "random_3000": lambda: P.random_csr(3000, 5, seed=4, empty_rows=9, long_rows={11: 2500, 12: 70}),
+    "poisson2d_37": lambda: P.poisson2d(37),
+    "poisson3d_24": lambda: P.poisson3d(24),
+    "convdiff2d_61": lambda: P.convdiff2d(61),
+}
+
+
+@pytest.mark.parametrize("layout", ["row_blocks", "sliced", "sliced16", "slots"])
+@pytest.mark.parametrize("case", list(KERNEL_CASES))
+def test_spmv32_rows_and_dots(case, layout, device):
+    import torch
+
+    A = KERNEL_CASES[case]()
+    require_layout(A, layout)
+    print(f"\n[case] spmv32 {case} n={A.n} nnz={A.nnz} layout={layout}", flush=True)
+    p = np.random.default_rng(5).uniform(-1, 1, A.n).astype(np.float32)
+    qo = oracle.default().spmv_f32(A, p)
+    M = fk.Matrix(A, layout=layout)
+    pd = torch.as_tensor(p, device="cuda")
+    qd = torch.zeros_like(pd)
+    d_exact = fk.spmv32(M, pd, qd, f32acc=False)
+    q = qd.cpu().numpy()
+    assert np.array_equal(q, qo)
+    d_f32 = fk.spmv32(M, pd, qd, f32acc=True)
+    assert np.array_equal(qd.cpu().numpy(), qo)
+    d_f32_again = fk.spmv32(M, pd, qd, f32acc=True)
+    assert d_f32 == d_f32_again  # same launch shape, same bits
+    M.close()
+    # exact mode: the exact sums rounded once, as the oracle's FP32 dot
+    assert d_exact[0] == oracle.default().dot_f32(p, q)
+    assert d_exact[1] == oracle.default().dot_f32(q, q)
+    for k, (a, b) in enumerate(((q, p), (q, q))):
+        exact = sum(Fraction(float(x)) * Fraction(float(y)) for x, y in zip(a, b))
+        absum = float(np.sum(np.abs(a.astype(np.float64) * b.astype(np.float64))))
+        bound = _gamma(A.n) * absum
+        got = d_f32[k]
+        assert got == float(np.float32(got))  # an FP32 value
+        seq = float(oracle.default().dot_f32acc(a, b))
+        err_gpu = abs(float(Fraction(got) - exact))
+        err_seq = abs(float(Fraction(seq) - exact))
+        print(f"[result] dot{k}: |gpu - exact| = {err_gpu:.3e}, |oracle seq - exact| = {err_seq:.3e}, "
+              f"gamma_n sum|ab| = {bound:.3e}", flush=True)
+        assert err_gpu <= bound
+        assert abs(got - seq) <= 2 * bound
+
+
+SOLVE_CASES = ["poisson2d_32", "poisson2d_37", "poisson3d_24", "heat2d_48", "shifted2d_45", "random_spd_csr"]
+
+
+@pytest.mark.parametrize("layout", ["row_blocks", "slots"])
+@pytest.mark.parametrize("name", SOLVE_CASES)
+def test_mixed_f32_solve(name, layout, device):
+    A, b, xs, kappa = _reference(name)
+    require_layout(A, layout)
+    rtol = 1e-10
+    print(f"\n[case] cg_mixed_f32 {name} n={A.n} layout={layout} kappa={kappa:.1f}", flush=True)
+    ref = oracle.solve_mixed(A, b, rtol=rtol, inner_rtol=1e-4, acc="f32")
+    res, x = f32_solve(A, b, rtol=rtol, layout=layout)
+    tr = oracle.true_residual(A, b, x)
+    err = rel(x, xs)
+    print(f"[result] {name}: sweeps={res.sweeps} (oracle {ref.sweeps}) inner k={res.k} (oracle {ref.k}) "
+          f"true residual {tr:.2e} ||x - x*||/||x*|| = {err:.2e} <= kappa*rtol = {kappa * rtol:.2e}",
+          flush=True)
+    assert res.status == ref.status == "converged"
+    assert tr <= rtol
+    assert err <= kappa * rtol
+    assert abs(res.history[-1] - tr) <= 1e-3 * tr
+    # FP32 trajectories that round differently stay close: same number of
+    # sweeps within one, inner iterations within 10 % (+2).
+    assert abs(res.sweeps - ref.sweeps) <= 1
+    assert abs(res.k - ref.k) <= 0.1 * ref.k + 2
+
+
+@pytest.mark.parametrize("unroll,graph", [(1, False), (7, False), (16, True)])
+def test_mixed_f32_deterministic(unroll, graph, device):
+    """Driver modes enqueue the same launches: bit-identical results."""
+    A, b, _ = P.workload("poisson3d_24")
+    M = fk.Matrix(A)
+    base, xb = f32_solve(A, b, rtol=1e-11, matrix=M)
+    res, x = f32_solve(A, b, rtol=1e-11, matrix=M, unroll=unroll, graph=graph)
+    M.close()
+    assert res.status == base.status == "converged"
+    assert res.k == base.k and res.sweeps == base.sweeps
+    assert np.array_equal(res.history, base.history)
+    assert np.array_equal(x, xb)
+
+
+def test_mixed_f32_edge_cases(device):
+    """b = 0; inner tolerance >= 1 (no inner step); limits; n = 1; the 4I
+    system exact in FP32; an indefinite matrix (breakdown)."""
+    A, b, _ = P.workload("poisson2d_16")
+    z, zx = f32_solve(A, np.zeros(A.n), np.ones(A.n))
+    assert z.status == "converged" and z.k == 0 and z.sweeps == 0 and not zx.any()
+    s, _ = f32_solve(A, b, inner_rtol=2.0)
+    assert s.status == "not_converged" and s.k == 0 and s.sweeps == 0
+    r5, _ = f32_solve(A, b, max_iter=5)
+    assert r5.status == "not_converged" and r5.k == 5 and r5.sweeps == 1
+    r2, _ = f32_solve(A, b, inner_rtol=0.5, max_outer=2)
+    assert r2.status == "not_converged" and r2.sweeps == 2 and len(r2.history) == 3
+    assert r2.history[2] < r2.history[1] < r2.history[0]
+    one = P.scaled_identity(1, 3.0)
+    res, x = f32_solve(one, np.array([2.0]), rtol=1e-12)
+    ref = oracle.solve_mixed(one, np.array([2.0]), rtol=1e-12, acc="f32")
+    assert res.status == ref.status == "converged" and res.k == ref.k and np.array_equal(x, ref.x)
+    I4 = P.scaled_identity(12, 4.0)
+    bi = np.arange(-6.0, 6.0) / 8.0 + 0.03125
+    res, x = f32_solve(I4, bi, rtol=1e-14)
+    assert res.status == "converged" and res.sweeps == 1 and res.k == 1
+    assert np.array_equal(x, bi / 4.0)
+    Ai = P.dense_to_csr(np.diag([1.0, -1.0, 2.0, -2.0]))
+    res, _ = f32_solve(Ai, np.ones(4))
+    assert res.status == oracle.solve_mixed(Ai, np.ones(4), acc="f32").status == "breakdown"
+
+
+def test_mixed_f32_full_size(device):
+    """128^3 Poisson to 1e-10 (the benchmark's matrix): the exact mode and the
+    FP32-accumulating mode both reach the tolerance; the error against the
+    sine-transform solution is within kappa * rtol."""
+    A, b, _ = P.workload("poisson3d_128")
+    xs, kappa = _dst_3d(128, b)
+    M = fk.Matrix(A)
+    for method in ("cg_mixed", "cg_mixed_f32"):
+        bd = dev(b)
+        xd = dev(np.zeros(A.n))
+        print(f"\n[case] {method} poisson3d_128 rtol 1e-10", flush=True)
+        res = fk.solve(M, bd, xd, method=method, rtol=1e-10)
+        x = host(xd)
+        tr = oracle.true_residual(A, b, x)
+        err = rel(x, xs)
+        print(f"[result] {method}: sweeps={res.sweeps} inner k={res.k} true residual {tr:.2e} "
+              f"||x - x*||/||x*|| = {err:.2e} (kappa*rtol = {kappa * 1e-10:.2e})", flush=True)
+        assert res.status == "converged" and tr <= 1e-10 and err <= kappa * 1e-10
+    M.close()
