@@ -128,9 +128,20 @@ def test_spmv32_rows_and_dots(case, layout, device):
     qd = torch.zeros_like(pd)
     d_exact = fk.spmv32(M, pd, qd, f32acc=False)
     q = qd.cpu().numpy()
-    assert np.array_equal(q, qo)
+    # Every row is summed left to right in FP32 as the oracle sums it, except
+    # that the row-block kernel sums a row longer than FK_LONG_ROW by a fixed
+    # tree over the workgroup: such a row is within gamma_len sum |a_j p_j|
+    # of its exact value, as the oracle's is, so within twice that of it.
+    lens = np.diff(A.row_ptr)
+    short = lens <= (fk.LONG_ROW if M.layout()[0] == "row_blocks" else np.inf)
+    assert np.array_equal(q[short], qo[short])
+    vals32 = A.vals.astype(np.float32).astype(np.float64)
+    for i in np.flatnonzero(~short):
+        j0, j1 = A.row_ptr[i], A.row_ptr[i + 1]
+        absum = float(np.sum(np.abs(vals32[j0:j1] * p[A.col_idx[j0:j1]].astype(np.float64))))
+        assert abs(float(q[i]) - float(qo[i])) <= 2 * _gamma(int(lens[i])) * absum, i
     d_f32 = fk.spmv32(M, pd, qd, f32acc=True)
-    assert np.array_equal(qd.cpu().numpy(), qo)
+    assert np.array_equal(qd.cpu().numpy(), q)
     d_f32_again = fk.spmv32(M, pd, qd, f32acc=True)
     assert d_f32 == d_f32_again  # same launch shape, same bits
     M.close()
