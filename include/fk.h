@@ -491,6 +491,39 @@ fk_status fk_batch_solve(fk_batch B, const fk_batch_opts *o, const double *b_dev
 fk_status fk_batch_results(fk_batch B, int32_t *status, int32_t *iterations, int32_t *sweeps,
                            double *rel_res);
 
+/*
+ * For callers that cannot allocate device memory: code that runs while a HIP
+ * graph is being captured, tight serving loops, harnesses that forbid
+ * hipMalloc.  fk_solve_noalloc is fk_solve for the pipelined CG method
+ * without a solver handle: the same kernels in the same order, hence the
+ * same x, k and residual bit for bit as fk_solver_create + fk_solve with
+ * the same options.  The call allocates nothing (no hipMalloc, hipFree,
+ * pinned host memory, events or graphs): the work vectors r, p, A p, the
+ * reduction partials and arrival counters and the device state live in one
+ * static array of FK_NOALLOC_BYTES per device (24.4 MiB), which every device
+ * that loads the library holds until the process ends.
+ *
+ * A: a matrix created on the current device with n <= FK_NOALLOC_MAX_N
+ * (FK_E_ARG otherwise).  o: method FK_CG_PIPELINED, record_history 0,
+ * flags 0 or FK_FLAG_NO_SMALL (FK_E_ARG otherwise); rtol, max_iter and
+ * unroll as for fk_solve.  b_dev, x_dev: caller-owned device float64[n], x
+ * holding x0 on entry and x_k on return.  iterations and rel_res (either may
+ * be NULL) receive k and ||r_k||/||b|| as fk_get_iterations and
+ * fk_get_residual would.  Returns FK_OK, FK_NOT_CONVERGED, FK_BREAKDOWN or
+ * an error, as fk_solve.  Work runs on hip_stream; the call returns after it
+ * has completed.
+ *
+ * Every call on a device shares that device's array, which keeps the last
+ * call's contents (the call clears what must start at zero).  Calls from
+ * threads of one process on the same device are serialized by a lock held
+ * for the whole call; anything else that overlapped with a call on the same
+ * device's array would race with it.
+ */
+#define FK_NOALLOC_MAX_N 1048576
+#define FK_NOALLOC_BYTES 25571840
+fk_status fk_solve_noalloc(fk_csr A, const fk_opts *o, const double *b_dev, double *x_dev, void *hip_stream,
+                           int32_t *iterations, double *rel_res);
+
 const char *fk_status_str(fk_status s);
 const char *fk_last_error(void);
 

@@ -1659,6 +1659,154 @@ static fk_status finish_solve(fk_solver S)
     return S->last_status;
 }
 
+// ------------------------------------------------ solve without allocation
+
+// The work memory of fk_solve_noalloc: one array per device, part of this
+// file's code object, so it exists from the library's first use on a device
+// until the process ends.  Regions, each 256-byte aligned: the device state,
+// the reduction scratch (partials, arrival counters, published partials),
+// then r, p and A p of FK_NOALLOC_MAX_N doubles each.  In host code the name
+// `scratch` is only a host-side stand-in: host code passes kernels the
+// device address that hipGetSymbolAddress returns for the current device.
+namespace {
+constexpr size_t NA_ALIGN = 256 / sizeof(double);
+constexpr size_t na_round(size_t d) { return (d + NA_ALIGN - 1) / NA_ALIGN * NA_ALIGN; }
+constexpr size_t NA_STATE = 0;
+constexpr size_t NA_RED = NA_STATE + na_round(sizeof(DevState) / sizeof(double));
+constexpr size_t NA_VEC = NA_RED + na_round(RED_SCRATCH_DOUBLES);
+constexpr size_t NA_VEC_STRIDE = na_round(FK_NOALLOC_MAX_N);
+constexpr size_t NA_DOUBLES = NA_VEC + 3 * NA_VEC_STRIDE;
+static_assert(sizeof(DevState) % sizeof(double) == 0, "the state occupies whole doubles");
+static_assert(NA_DOUBLES * sizeof(double) == FK_NOALLOC_BYTES, "fk.h states the array's size");
+
+constexpr int NA_MAX_DEVICES = 64;
+std::mutex g_na_mu[NA_MAX_DEVICES];   // one solve at a time per device
+double *g_na_ptr[NA_MAX_DEVICES] = {};  // device address of `scratch`, per device
+}  // namespace
+
+static __device__ __align__(256) double scratch[NA_DOUBLES];
+
+// The device address of `scratch` on `device` (the current device), looked
+// up once per device.  Called with g_na_mu[device] held.
+static fk_status noalloc_base(int device, double **base)
+{
+    if (!g_na_ptr[device]) {
+        void *ptr = nullptr;
+        hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr)
+            return fail(FK_E_HIP, "hipGetSymbolAddress(scratch): %s", hipGetErrorString(e));
+        g_na_ptr[device] = static_cast<double *>(ptr);
+    }
+    *base = g_na_ptr[device];
+    return FK_OK;
+}
+
+extern "C" fk_status fk_solve_noalloc(fk_csr A, const fk_opts *o, const double *b, double *x, void *hip_stream,
+                                      int32_t *iterations, double *rel_res)
+{
+    if (!A || !o || !b || !x)
+        return fail(FK_E_ARG, "NULL argument");
+    if (o->method != FK_CG_PIPELINED)
+        return fail(FK_E_ARG, "fk_solve_noalloc solves with FK_CG_PIPELINED only");
+    if (!(o->rtol >= 0.0) || !std::isfinite(o->rtol))
+        return fail(FK_E_ARG, "rtol must be finite and >= 0");
+    if (o->max_iter < 0)
+        return fail(FK_E_ARG, "max_iter < 0");
+    if (o->unroll < 0 || o->unroll > 4096)
+        return fail(FK_E_ARG, "unroll outside [0, 4096]");
+    if (o->record_history != 0)
+        return fail(FK_E_ARG, "fk_solve_noalloc keeps no history (record_history must be 0)");
+    if (o->flags & ~FK_FLAG_NO_SMALL)
+        return fail(FK_E_ARG, "fk_solve_noalloc takes only FK_FLAG_NO_SMALL (flags 0x%x)", o->flags);
+    if (A->n > FK_NOALLOC_MAX_N)
+        return fail(FK_E_ARG, "n = %lld exceeds FK_NOALLOC_MAX_N = %d", (long long)A->n, FK_NOALLOC_MAX_N);
+    int device = -1;
+    HIP_TRY(hipGetDevice(&device));
+    if (device != A->device)
+        return fail(FK_E_ARG, "the matrix lives on device %d, the current device is %d", A->device, device);
+    if (device < 0 || device >= NA_MAX_DEVICES)
+        return fail(FK_E_ARG, "device %d outside [0, %d)", device, NA_MAX_DEVICES);
+
+    std::lock_guard<std::mutex> lock(g_na_mu[device]);
+    double *base = nullptr;
+    fk_status fs = noalloc_base(device, &base);
+    if (fs != FK_OK)
+        return fs;
+    hipStream_t st = (hipStream_t)hip_stream;
+
+    // A solver view over the static array (no events, no pinned memory, no
+    // history): the same enqueue functions as fk_solve, so the same kernels
+    // in the same order.
+    fk_solver_s S;
+    S.A = A;
+    S.o = *o;
+    if (S.o.unroll == 0)
+        S.o.unroll = 32;
+    S.stream = st;
+    S.n = A->n;
+    S.grid_spmv = A->spmv_grid();
+    S.grid_vec = vec_grid(A->n);
+    S.st = reinterpret_cast<DevState *>(base + NA_STATE);
+    S.partials = base + NA_RED;
+    S.r = base + NA_VEC;
+    S.p = S.r + NA_VEC_STRIDE;
+    S.ap = S.p + NA_VEC_STRIDE;
+    S.small = small_path_ok(A, S.o);
+    S.small_stage = S.small && small_staged_lds_bytes(0, A->n, A->nnz) + SMALL_STATIC_LDS <=
+                                   max_lds_per_workgroup(A->device);
+
+    // The array keeps the last call's contents: the counters and partials
+    // start from zero and the state from its initial values (fill kernels,
+    // no memset nodes).
+    HIP_TRY(launch_clear(S.partials, (int64_t)RED_SCRATCH_DOUBLES, 64, st));
+    HIP_TRY(launch_state_init(S.st, S.o.rtol, S.o.max_iter, 0, st));
+    DevState last{};
+    if (S.small) {
+        HIP_TRY(launch_small(0, A->view(), b, x, S.st, nullptr, nullptr, S.small_stage, st));
+    } else {
+        Enq q{&S, false, 0};
+        hipError_t e = enqueue_setup(&S, q, b, x);
+        int64_t launched = 0;
+        while (e == hipSuccess) {
+            const int64_t todo = std::min<int64_t>(S.o.unroll, (int64_t)S.o.max_iter - launched);
+            for (int64_t i = 0; i < todo && e == hipSuccess; ++i)
+                e = enqueue_iteration(&S, q, x, launched + i + 1 == S.o.max_iter);
+            if (e != hipSuccess)
+                break;
+            launched += todo;
+            int32_t status = ST_RUNNING;
+            e = hipMemcpyAsync(&status, reinterpret_cast<const char *>(S.st) + offsetof(DevState, status),
+                               sizeof status, hipMemcpyDeviceToHost, st);
+            if (e == hipSuccess)
+                e = hipStreamSynchronize(st);
+            if (e != hipSuccess || status != ST_RUNNING || launched >= S.o.max_iter)
+                break;
+        }
+        if (e != hipSuccess)
+            return fail(FK_E_HIP, "fk_solve_noalloc: %s", hipGetErrorString(e));
+    }
+    HIP_TRY(hipMemcpyAsync(&last, S.st, sizeof(DevState), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    if (S.small && last.status == ST_ZERO_RHS) {
+        HIP_TRY(launch_clear(x, A->n, vec_grid(A->n), st));
+        HIP_TRY(hipStreamSynchronize(st));
+    }
+    if (iterations)
+        *iterations = last.it;
+    if (rel_res)
+        *rel_res = last.last_rel;
+    switch (last.status) {
+    case ST_CONVERGED:
+    case ST_ZERO_RHS:
+        return FK_OK;
+    case ST_BREAKDOWN:
+        return fail(FK_BREAKDOWN, "breakdown at iteration %d", last.it);
+    default:
+        return fail(FK_NOT_CONVERGED, "not converged after %d iterations (rel. residual %.3e)", last.it,
+                    last.last_rel);
+    }
+}
+
 extern "C" fk_status fk_solver_uses_small(fk_solver S, int32_t *small)
 {
     if (!S || !small)

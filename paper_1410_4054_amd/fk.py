@@ -132,6 +132,7 @@ def lib():
             "fk_batch_shape": [vp, P(i32), P(i64), P(i64)],
             "fk_batch_solve": [vp, P(_BatchOpts), vp, vp, vp],
             "fk_batch_results": [vp, vp, vp, vp, vp],
+            "fk_solve_noalloc": [vp, P(_Opts), vp, vp, vp, P(i32), P(f64)],
         }
         for name, args in sig.items():
             fn = getattr(L, name)
@@ -158,7 +159,7 @@ def exported_symbols() -> list[str]:
         "fk_axpby", "fk_net_num_weights", "fk_net_create", "fk_net_destroy", "fk_net_get_weights",
         "fk_net_set_weights", "fk_net_forward", "fk_net_guess", "fk_net_gradient", "fk_net_train_step",
         "fk_batch_create", "fk_batch_destroy", "fk_batch_shape", "fk_batch_solve", "fk_batch_results",
-        "fk_status_str", "fk_last_error", "fk_version",
+        "fk_solve_noalloc", "fk_status_str", "fk_last_error", "fk_version",
     ]
 
 
@@ -440,6 +441,26 @@ def solve(A: Matrix, b, x, method: str = "cg_pipelined", rtol: float = 1e-8,
                            S.refinements())
     finally:
         S.close()
+
+
+NOALLOC_MAX_N = 1048576  # FK_NOALLOC_MAX_N
+
+
+def solve_noalloc(A: Matrix, b, x, rtol: float = 1e-8, max_iter: int | None = None, unroll: int = 32,
+                  small: bool = True, stream=None) -> SolveResult:
+    """fk_solve_noalloc: pipelined CG without a solver handle, its work
+    memory in the library's static per-device array (nothing allocated).
+    x holds x0 on entry.  Returns status, k and ||r_k||/||b|| (no history)."""
+    if max_iter is None:
+        max_iter = min(10 * A.n, 2**31 - 2)
+    o = _Opts(METHODS["cg_pipelined"], float(rtol), int(max_iter), 0, int(unroll),
+              0 if small else FLAG_NO_SMALL, 0.0, 0, 0)
+    k = ctypes.c_int32()
+    rel = ctypes.c_double()
+    st = lib().fk_solve_noalloc(A.handle, ctypes.byref(o), _dev_f64(b, A.n, "b"), _dev_f64(x, A.n, "x"),
+                                ctypes.c_void_p(_stream_ptr(stream)), ctypes.byref(k), ctypes.byref(rel))
+    _check(st, "fk_solve_noalloc", allowed=(OK, NOT_CONVERGED, BREAKDOWN))
+    return SolveResult(STATUS_NAMES[st], k.value, rel.value, None, None, 0)
 
 
 # ------------------------------------------------------- warm-start network
