@@ -73,8 +73,13 @@ typedef enum {
     FK_CG_MIXED_F32 = 7,        /* FK_CG_MIXED with FP32-accumulated inner products */
     FK_CG_PIPELINED_SPLIT = 8,  /* Algorithm 2 with the product's dots in their own
                                    kernel (Section 3.1's alternative): 3 kernels */
-    FK_BICGSTAB_PIPELINED_SPLIT = 9  /* Algorithm 4 with both products' dots in their
+    FK_BICGSTAB_PIPELINED_SPLIT = 9, /* Algorithm 4 with both products' dots in their
                                    own kernels (Section 3.2's alternative): 6 kernels */
+    FK_BICGSTAB_PIPELINED_2K = 10  /* Algorithm 4 in 2 kernels/iteration: each vector
+                                   update of Section 3.2 folded into the product
+                                   that follows it (the product recomputes the
+                                   updated vector where it gathers it); the same
+                                   iterates, bit for bit, as FK_BICGSTAB_PIPELINED */
 } fk_method;
 
 /* Rows with more nonzeros than this are summed by a fixed tree, not left to right. */
@@ -202,6 +207,26 @@ fk_status fk_csr_layout(fk_csr A, int32_t *layout, int64_t *stored_entries, int6
 fk_status fk_csr_set_layout(fk_csr A, int32_t layout, void *hip_stream);
 
 /*
+ * Streaming mode of the sliced products (the fused SpMV + inner products of
+ * Section 2.2 on the slice layouts; no effect on ROW_BLOCKS).  On, the
+ * products load the matrix data non-temporally and each XCD's workgroups
+ * sweep one contiguous eighth of the slices together, so that the vector
+ * lines one slice gathers are still cached when the neighbouring planes'
+ * slices gather them again.  Off, ordinary loads and a grid-stride order.
+ * Results are bitwise the same either way; only the speed differs.
+ * mode: -1 = by size (on when the matrix data one product reads plus four
+ * FP64 vectors of length n exceed 256 MiB, the MI355X's Infinity Cache),
+ * 0 = off, 1 = on.  The environment variables FK_STREAM (-1/0/1) and
+ * FK_SELL_SWEEP (0/1, the order alone) set the default of a new matrix.
+ * Solvers read the mode when they are created, so FK_E_STATE while any
+ * solver exists on A; FK_E_ARG for another mode.
+ * fk_csr_stream reports whether the mode is on and (when sweep is not NULL)
+ * whether the products run in sweep order.
+ */
+fk_status fk_csr_set_stream(fk_csr A, int32_t mode);
+fk_status fk_csr_stream(fk_csr A, int32_t *streaming, int32_t *sweep);
+
+/*
  * Create a solver for A with options *o, bound to hip_stream.  Allocates the
  * library-owned workspace once, so fk_solve allocates nothing: the method's
  * work vectors (r, p, A p for Algorithm 2; r, r0*, p, A p, s, A s for
@@ -309,8 +334,10 @@ fk_status fk_get_scalars(fk_solver S, double *out, int32_t cap, int32_t *len);
  * avg_us[kind] and count[kind] are written for kind < cap. */
 enum {
     FK_KERNEL_SETUP = 0,       /* r0 = b - A x0 and its reductions            */
-    FK_KERNEL_SPMV_DOT = 1,    /* fused CSR product + first-stage dots        */
-    FK_KERNEL_UPDATE_DOT = 2,  /* fused vector updates + first-stage dot(s)   */
+    FK_KERNEL_SPMV_DOT = 1,    /* fused CSR product + first-stage dots
+                                  (FK_BICGSTAB_PIPELINED_2K: s_i, A s_i)      */
+    FK_KERNEL_UPDATE_DOT = 2,  /* fused vector updates + first-stage dot(s)
+                                  (FK_BICGSTAB_PIPELINED_2K: x, r, p, A p)    */
     FK_KERNEL_SPMV = 3,        /* plain CSR product (classical)               */
     FK_KERNEL_DOT = 4,         /* plain dot (classical)                        */
     FK_KERNEL_AXPY = 5,        /* plain vector update (classical)             */

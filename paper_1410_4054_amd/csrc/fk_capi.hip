@@ -161,15 +161,16 @@ struct fk_csr_s {
     DevCsr view() const
     {
         const int32_t sw = sweep_grid() > 0 ? 1 : 0;
+        const int32_t nt = streaming() ? 1 : 0;
         if (slots())
             return DevCsr{(int32_t)n, (int32_t)nnz, nblocks, row_ptr, col_idx, vals, blocks, block_j0,
-                          dg_nslices, dg_ptr, nullptr, dg_vals, nullptr, nullptr, dg_off, dg_mask, sw};
+                          dg_nslices, dg_ptr, nullptr, dg_vals, nullptr, nullptr, dg_off, dg_mask, sw, nt};
         return DevCsr{(int32_t)n,  (int32_t)nnz, nblocks,  row_ptr,
                       col_idx,     vals,         blocks,   block_j0,
                       sliced() ? nslices : 0,    sell_ptr, sell_col,
                       sell_vals,   sell_ptr4,
                       layout == FK_LAYOUT_SLICED16 ? sell_off4 : nullptr,
-                      nullptr,     nullptr,      sliced() ? sw : 0};
+                      nullptr,     nullptr,      sliced() ? sw : 0, sliced() ? nt : 0};
     }
     // Entries the products read: nnz, or the slice entries with padding.
     int64_t stored_entries() const { return slots() ? dg_entries : sliced() ? sell_entries : nnz; }
@@ -188,14 +189,33 @@ struct fk_csr_s {
         return 12 * nnz + 4 * (n + 1);
     }
     int32_t cus = 0;    // compute units of the device (resident workgroups = 8 per CU)
-    int32_t sweep = 0;  // sliced products in sweep order (DevCsr::sweep)
+    // Streaming mode of the sliced products (non-temporal matrix loads and
+    // sweep order): -1 = by size (below), 0 = off, 1 = on (FK_STREAM);
+    // FK_SELL_SWEEP = 0 / 1 overrides the order alone.
+    int32_t stream_req = -1;
+    int32_t sweep_req = -1;
     int64_t slices() const { return slots() ? dg_nslices : sliced() ? nslices : 0; }
+    // By size: the matrix data one product reads plus four FP64 vectors (those
+    // of a pipelined CG iteration) exceed the 256 MiB Infinity Cache of the
+    // MI355X.  Below that the cache keeps the matrix from one product to the
+    // next (128^3 Poisson: 126 MB + 67 MB), and non-temporal loads, which do
+    // not leave lines in it, cost a quarter of the product's speed; above it
+    // (160^3, 192^3) they keep the gathered vector lines in L2 and the cache.
+    bool streaming() const
+    {
+        if (!sliced())
+            return false;
+        if (stream_req >= 0)
+            return stream_req != 0;
+        return matrix_bytes() + 32 * n > ((int64_t)256 << 20);
+    }
+    bool sweep_on() const { return sweep_req >= 0 ? sweep_req != 0 : streaming(); }
     // Workgroups of a sweep-order product: as many as are resident at once
     // (8 per CU at the product kernels' register cap), fewer for small
     // matrices (at least one slice per wave); 0 when not in sweep order.
     int sweep_grid() const
     {
-        if (!sweep || !sliced() || cus <= 0)
+        if (!sweep_on() || !sliced() || cus <= 0)
             return 0;
         int64_t g = std::min<int64_t>((int64_t)8 * cus, (slices() + WAVES - 1) / WAVES);
         g &= ~(int64_t)7;
@@ -586,7 +606,8 @@ extern "C" fk_status fk_csr_create(int64_t n, int64_t nnz, const int32_t *row_pt
     (void)hipGetDevice(&A->device);
     if (hipDeviceGetAttribute(&A->cus, hipDeviceAttributeMultiprocessorCount, A->device) != hipSuccess)
         A->cus = 0;
-    A->sweep = env_int("FK_SELL_SWEEP", 0, 0, 1);
+    A->stream_req = env_int("FK_STREAM", -1, -1, 1);
+    A->sweep_req = env_int("FK_SELL_SWEEP", -1, -1, 1);
     std::vector<int32_t> blocks, block_j0;
     try {
         blocks = plan_blocks(rp, n, &A->long_rows);
@@ -691,6 +712,29 @@ extern "C" fk_status fk_csr_layout(fk_csr A, int32_t *layout, int64_t *stored_en
     *stored_entries = A->stored_entries();
     if (matrix_bytes)
         *matrix_bytes = A->matrix_bytes();
+    return FK_OK;
+}
+
+extern "C" fk_status fk_csr_set_stream(fk_csr A, int32_t mode)
+{
+    if (!A)
+        return fail(FK_E_ARG, "NULL matrix");
+    if (mode < -1 || mode > 1)
+        return fail(FK_E_ARG, "stream mode must be -1, 0 or 1 (got %d)", mode);
+    if (A->solvers > 0)
+        return fail(FK_E_STATE, "%d solver(s) use this matrix; destroy them first", A->solvers);
+    A->stream_req = mode;
+    A->sweep_req = -1;
+    return FK_OK;
+}
+
+extern "C" fk_status fk_csr_stream(fk_csr A, int32_t *streaming, int32_t *sweep)
+{
+    if (!A || !streaming)
+        return fail(FK_E_ARG, "NULL argument");
+    *streaming = A->streaming() ? 1 : 0;
+    if (sweep)
+        *sweep = A->sweep_grid() > 0 ? 1 : 0;
     return FK_OK;
 }
 
@@ -809,6 +853,8 @@ struct fk_solver_s {
     hipStream_t stream = nullptr;
     int64_t n = 0;
     double *r = nullptr, *p = nullptr, *ap = nullptr, *s = nullptr, *as = nullptr, *rs = nullptr;
+    // FK_BICGSTAB_PIPELINED_2K: the second buffers of p and A p
+    double *p2 = nullptr, *ap2 = nullptr;
     double *partials = nullptr, *hist = nullptr, *scal = nullptr;
     DevState *st = nullptr;
     int32_t hist_cap = 0;
@@ -870,6 +916,8 @@ static void solver_release(fk_solver S)
     dev_free(S->r);
     dev_free(S->p);
     dev_free(S->ap);
+    dev_free(S->p2);
+    dev_free(S->ap2);
     dev_free(S->s);
     dev_free(S->as);
     dev_free(S->rs);
@@ -911,8 +959,11 @@ static void solver_release(fk_solver S)
 
 static bool is_bicg(int m)
 {
-    return m == FK_BICGSTAB_PIPELINED || m == FK_BICGSTAB_CLASSICAL || m == FK_BICGSTAB_PIPELINED_SPLIT;
+    return m == FK_BICGSTAB_PIPELINED || m == FK_BICGSTAB_CLASSICAL || m == FK_BICGSTAB_PIPELINED_SPLIT ||
+           m == FK_BICGSTAB_PIPELINED_2K;
 }
+// Algorithm 4 with the four-kernel or the two-kernel schedule (same iterates).
+static bool is_bicg_pipelined(int m) { return m == FK_BICGSTAB_PIPELINED || m == FK_BICGSTAB_PIPELINED_2K; }
 static bool is_gmres(int m) { return m == FK_GMRES_PIPELINED || m == FK_GMRES_CLASSICAL; }
 
 static size_t max_lds_per_workgroup(int device)
@@ -933,9 +984,9 @@ static bool small_path_ok(fk_csr A, const fk_opts &o)
 {
     if (o.flags & FK_FLAG_NO_SMALL)
         return false;
-    if (o.method != FK_CG_PIPELINED && o.method != FK_BICGSTAB_PIPELINED)
+    if (o.method != FK_CG_PIPELINED && !is_bicg_pipelined(o.method))
         return false;
-    const bool bicg = o.method == FK_BICGSTAB_PIPELINED;
+    const bool bicg = is_bicg_pipelined(o.method);
     const int rpt = small_rows_per_thread(A->n);
     if (rpt == 0 || (bicg && rpt > 2) || A->nnz > 65536 || A->long_rows > 0)
         return false;
@@ -949,7 +1000,7 @@ extern "C" fk_status fk_solver_create(fk_csr A, const fk_opts *o, void *hip_stre
     *out = nullptr;
     if (!A || !o)
         return fail(FK_E_ARG, "NULL argument");
-    if (o->method < FK_CG_PIPELINED || o->method > FK_BICGSTAB_PIPELINED_SPLIT)
+    if (o->method < FK_CG_PIPELINED || o->method > FK_BICGSTAB_PIPELINED_2K)
         return fail(FK_E_ARG, "unknown method %d", o->method);
     if (o->restart < 0 || o->restart > GM_MAX)
         return fail(FK_E_ARG, "restart outside [0, %d]", GM_MAX);
@@ -1038,6 +1089,10 @@ extern "C" fk_status fk_solver_create(fk_csr A, const fk_opts *o, void *hip_stre
         S_TRY(dev_alloc(&S->as, n, "As"));
         S_TRY(dev_alloc(&S->rs, n, "r0*"));
     }
+    if (o->method == FK_BICGSTAB_PIPELINED_2K) {
+        S_TRY(dev_alloc(&S->p2, n, "p (second buffer)"));
+        S_TRY(dev_alloc(&S->ap2, n, "Ap (second buffer)"));
+    }
     S_TRY(dev_alloc(&S->partials, RED_SCRATCH_DOUBLES, "partials"));
     S_TRY(dev_alloc(&S->st, 1, "state"));
     // History: entries 0 .. cap-1 are kept (the device drops later ones), cap
@@ -1074,7 +1129,7 @@ extern "C" fk_status fk_solver_create(fk_csr A, const fk_opts *o, void *hip_stre
     }
     S->small = small_path_ok(A, S->o);
     S->small_stage = S->small &&
-                     small_staged_lds_bytes(o->method == FK_BICGSTAB_PIPELINED, A->n, A->nnz) +
+                     small_staged_lds_bytes(is_bicg_pipelined(o->method), A->n, A->nnz) +
                              SMALL_STATIC_LDS <= max_lds_per_workgroup(A->device);
     S_HIP(hipStreamSynchronize(S->stream));
 #undef S_TRY
@@ -1167,6 +1222,11 @@ hipError_t enqueue_setup(fk_solver S, Enq &q, const double *b, double *x)
         ENQ(FK_KERNEL_SPMV, launch_spmv_dots(A, S->p, S->ap, nullptr, 0, S->red(FIN_NONE, RUN_ACTIVE), gs, st));
         ENQ(FK_KERNEL_DOT, launch_dot(n, S->ap, S->p, S->ap, 2, S->red(FIN_CG_ALPHA, RUN_ACTIVE), gv, st));
     }
+    if (S->o.method == FK_BICGSTAB_PIPELINED_2K)
+        // A p_0 + <Ap_0, r0*>: rho_0 comes from the setup, then alpha_0; p_0
+        // and A p_0 sit in the first buffers (iteration count 0).
+        ENQ(FK_KERNEL_SPMV_DOT, launch_spmv_dots(A, S->p, S->ap, S->rs, D_YW,
+                                                 S->red(FIN_B_RHO_ALPHA, RUN_ACTIVE), gs, st));
     return hipSuccess;
 }
 
@@ -1232,6 +1292,16 @@ hipError_t enqueue_iteration(fk_solver S, Enq &q, double *x, bool last)
         ENQ(FK_KERNEL_UPDATE_DOT, launch_bicg_xrp(n, x, S->r, S->p, S->s, S->as, S->ap, S->rs,
                                                   S->red(FIN_B_XRP_PUB, RUN_BICG_UPDATE), gv, st));
         break;
+    case FK_BICGSTAB_PIPELINED_2K: {
+        // s_i and A s_i (+ <As,s>, <As,As>, <As,r0*>, <s,s>: half-step test,
+        // omega_i, beta_i, decision on i+1); then x, r, p of iteration i+1
+        // and A p_{i+1} (+ <Ap,r0*>, <r,r0*>, <r,r>: rho, alpha), or, after
+        // a decision, the last x, r and the final reduction.
+        const Bicg2Io io{x, S->r, S->s, S->as, S->rs, {S->p, S->p2}, {S->ap, S->ap2}};
+        ENQ(FK_KERNEL_SPMV_DOT, launch_bicg2_sas(A, io, S->red(FIN_B_SS_OMEGA, RUN_ACTIVE), gs, st));
+        ENQ(FK_KERNEL_UPDATE_DOT, launch_bicg2_xap(A, io, S->red(FIN_B_XRP_ALPHA, RUN_BICG_UPDATE), gs, st));
+        break;
+    }
     case FK_BICGSTAB_CLASSICAL:
         ENQ(FK_KERNEL_SPMV, launch_spmv_dots(A, S->p, S->ap, nullptr, 0, S->red(FIN_NONE, RUN_ACTIVE), gs, st));
         ENQ(FK_KERNEL_DOT, launch_dot(n, S->ap, S->rs, nullptr, 1, S->red(FIN_B_ALPHA, RUN_ACTIVE), gv, st));
@@ -1597,7 +1667,7 @@ extern "C" fk_status fk_solve(fk_solver S, const double *b, double *x)
         init.hist_cap = S->hist_cap;
         S->h_init[0] = init;
         HIP_TRY(hipMemcpyAsync(S->st, &S->h_init[0], sizeof(DevState), hipMemcpyHostToDevice, S->stream));
-        const bool bicg = S->o.method == FK_BICGSTAB_PIPELINED;
+        const bool bicg = is_bicg_pipelined(S->o.method);
         std::vector<hipEvent_t> &pool = S->prof_ev[0];
         if (profile) {
             while (pool.size() < 2) {

@@ -129,6 +129,8 @@ enum Fin : int32_t {
     FIN_SETUP32,        // d = {<r0,r0>, <r0,r0>}: FIN_SETUP with an FP32 tolerance
     FIN_CG_ALPHA32,     // d = {<p,Ap>, <Ap,Ap>}: alpha_i, beta_i (Eq. (3)) in FP32
     FIN_CG_RR_ALPHA32,  // d = {<p,Ap>, <Ap,Ap>, <r,r>}: FIN_CG_RR_ALPHA in FP32
+    FIN_B_XRP_ALPHA,    // d = {<Ap,r0*>, <r,r0*>, <r,r>} of one launch (the x, r, p
+                        // update fused with the next product): rho, then FIN_B_ALPHA
 };
 
 // Everything a reduction point needs.
@@ -192,6 +194,10 @@ struct DevCsr {
     // through the eighth together (a sliding window; the grid then holds no
     // more workgroups than are resident at once).
     int32_t sweep;
+    // 1: the sliced products load the matrix data non-temporally (the
+    // matrix and the vectors of an iteration exceed the Infinity Cache, so
+    // the matrix comes from HBM every launch anyway); 0: ordinary loads.
+    int32_t stream;
 };
 
 // Column forms of the sliced products.
@@ -227,6 +233,17 @@ hipError_t launch_bicg_s(int64_t n, const double *r, const double *ap, double *s
 hipError_t launch_bicg_xrp(int64_t n, double *x, double *r, double *p, const double *sv,
                            const double *as, const double *ap, const double *rs,
                            const RedArgs &red, int grid, hipStream_t s);
+// The two-kernel BiCGStab iteration (updates folded into the products; see
+// fk_kernels.hip): the vectors, with p_i and A p_i in two buffers each,
+// selected by the parity of the device's iteration count.
+struct Bicg2Io {
+    double *x, *r, *s, *as;
+    const double *rs;  // r0*
+    double *p[2];
+    double *ap[2];
+};
+hipError_t launch_bicg2_sas(const DevCsr &A, const Bicg2Io &io, const RedArgs &red, int grid, hipStream_t s);
+hipError_t launch_bicg2_xap(const DevCsr &A, const Bicg2Io &io, const RedArgs &red, int grid, hipStream_t s);
 // Classical (unfused) building blocks.
 // <a,b> (ndots 1); <a,b>, <a,c> (2); <a,b>, <a,c>, <a,e> (3).
 hipError_t launch_dot(int64_t n, const double *a, const double *b, const double *c,

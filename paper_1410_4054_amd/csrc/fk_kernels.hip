@@ -38,12 +38,6 @@
 #ifndef FK_SPMV_MIN_WAVES
 #define FK_SPMV_MIN_WAVES 8
 #endif
-// Stream the CSR values and column indices with non-temporal loads (they
-// are read once per product; keeping them out of the caches leaves room for
-// the vectors that are read again).
-#ifndef FK_NT_CSR
-#define FK_NT_CSR 0
-#endif
 // Unroll factor of the grid-stride loops of the per-iteration vector-update
 // kernels (measured: 4 beats 1 and 2 on MI355X).
 #ifndef FK_VEC_UNROLL
@@ -115,13 +109,26 @@ __device__ __forceinline__ double load_coherent(const double *p)
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-template <typename T>
+// A load of the matrix stream.  NT: non-temporal (the products of a matrix
+// whose data and vectors exceed the Infinity Cache read each entry once per
+// launch from HBM; marking those loads non-temporal keeps them from evicting
+// the vector lines that neighbouring slices gather again).  Below that size
+// the cache holds the matrix from one product to the next, and ordinary
+// loads keep it there.
+template <bool NT = false, typename T>
 __device__ __forceinline__ T load_stream(const T *p)
 {
-    if constexpr (FK_NT_CSR != 0)
-        return __builtin_nontemporal_load(p);
-    else
+    if constexpr (NT) {
+        if constexpr (sizeof(T) == 8 && !std::is_arithmetic_v<T>) {
+            // packed 16-bit offsets: one 8-byte non-temporal load
+            const uint64_t u = __builtin_nontemporal_load(reinterpret_cast<const uint64_t *>(p));
+            return __builtin_bit_cast(T, u);
+        } else {
+            return __builtin_nontemporal_load(p);
+        }
+    } else {
         return *p;
+    }
 }
 
 __device__ __forceinline__ bool runs(const RedArgs &red)
@@ -345,6 +352,12 @@ __device__ void finalize(DevState *st, int fin, const double *d, int K, double *
             st->rr = d[2];
             st->rho_pub = 0;
         }
+        b_alpha(st, d[0], scal);
+        break;
+    case FIN_B_XRP_ALPHA:  // d = {<Ap_{i+1}, r0*>, <r_{i+1}, r0*>, <r_{i+1}, r_{i+1}>}
+        // (two-kernel schedule: the update and the product in one launch)
+        st->rho = d[1];
+        st->rr = d[2];
         b_alpha(st, d[0], scal);
         break;
     case FIN_B_SS: {  // d = {<s_i, s_i>}: half-step test
@@ -1035,7 +1048,7 @@ struct ColsRaw {
 
 // Phase 1: issue those loads (k a multiple of U, U a multiple of 4 for
 // 16-bit offsets); entries past width are not read.
-template <int U, int COLS>
+template <int U, int COLS, bool NT>
 __device__ __forceinline__ void cols_issue(const SliceCols<COLS> &sc, int k, int width, ColsRaw<U, COLS> &r)
 {
     if constexpr (COLS == COLS_OFF16) {
@@ -1044,12 +1057,12 @@ __device__ __forceinline__ void cols_issue(const SliceCols<COLS> &sc, int k, int
         for (int j = 0; j < U / 4; ++j) {
             r.o[j] = make_short4(SELL_PAD, SELL_PAD, SELL_PAD, SELL_PAD);
             if (k + 4 * j < width)
-                r.o[j] = load_stream(sc.off4 + (size_t)(k / 4 + j) * SLICE);
+                r.o[j] = load_stream<NT>(sc.off4 + (size_t)(k / 4 + j) * SLICE);
         }
     } else if constexpr (COLS == COLS_INT32) {
 #pragma unroll
         for (int u = 0; u < U; ++u)
-            r.c[u] = k + u < width ? load_stream(sc.col + (size_t)(k + u) * SLICE) : -1;
+            r.c[u] = k + u < width ? load_stream<NT>(sc.col + (size_t)(k + u) * SLICE) : -1;
     }
 }
 
@@ -1083,17 +1096,26 @@ __device__ __forceinline__ void cols_decode(const SliceCols<COLS> &sc, int k, in
     }
 }
 
+// The vector a sliced product multiplies, read where the row gathers it.
+// VecOf: a stored vector.  The fused BiCGStab products below take sources
+// that recompute the vector from others at each gathered index instead.
+template <typename T>
+struct VecOf {
+    const T *__restrict__ v;
+    __device__ __forceinline__ T at(int c) const { return v[c]; }
+};
+
 // Entries k .. k+U-1 of one row of a slice, added to q left to right (the
 // row's CSR order).  The column loads and the value loads are all issued
 // before the first is waited for; then the U gathers; then the sums.
 // width is uniform over the wave, so every test on it is a scalar branch.
 // Padding only follows a row's last nonzero and is skipped.
-template <typename T, int U, int COLS>
+template <typename T, int U, int COLS, bool NT, typename SRC>
 __device__ __forceinline__ void slice_row_chunk(const SliceCols<COLS> &cols, const T *__restrict__ vals,
-                                                const T *__restrict__ v, int k, int width, T &q)
+                                                const SRC &v, int k, int width, T &q)
 {
     ColsRaw<U, COLS> raw;
-    cols_issue<U, COLS>(cols, k, width, raw);
+    cols_issue<U, COLS, NT>(cols, k, width, raw);
     // Every load below is unconditional, so the chunk is straight-line code
     // and the compiler waits for exactly the loads it needs: entries past
     // width re-read the slice's last entry (a cache hit) and a padding
@@ -1101,12 +1123,12 @@ __device__ __forceinline__ void slice_row_chunk(const SliceCols<COLS> &cols, con
     T a[U], x[U];
 #pragma unroll
     for (int u = 0; u < U; ++u)
-        a[u] = load_stream(vals + (size_t)min(k + u, width - 1) * SLICE);
+        a[u] = load_stream<NT>(vals + (size_t)min(k + u, width - 1) * SLICE);
     int c[U];
     cols_decode<U, COLS>(cols, k, width, raw, c);
 #pragma unroll
     for (int u = 0; u < U; ++u)
-        x[u] = v[c[u] >= 0 ? c[u] : cols.safe_row];
+        x[u] = v.at(c[u] >= 0 ? c[u] : cols.safe_row);
 #pragma unroll
     for (int u = 0; u < U; ++u) {
         const T t = q + a[u] * x[u];
@@ -1118,9 +1140,9 @@ __device__ __forceinline__ void slice_row_chunk(const SliceCols<COLS> &cols, con
 // width-1 sit SLICE apart.  A slice of at most U entries per row (every
 // stencil here) takes one straight-line chunk, so the compiler can count
 // the loads in flight exactly; wider slices loop over chunks of U.
-template <typename T, int U, int COLS>
+template <typename T, int U, int COLS, bool NT, typename SRC>
 __device__ __forceinline__ T slice_row_sum(const SliceCols<COLS> &cols, const T *__restrict__ vals,
-                                           const T *__restrict__ v, int width)
+                                           const SRC &v, int width)
 {
     T q = T(0);
     if constexpr (COLS == COLS_SLOTS) {
@@ -1128,13 +1150,14 @@ __device__ __forceinline__ T slice_row_sum(const SliceCols<COLS> &cols, const T 
 #pragma unroll
         for (int k = 0; k < DG_MAX_SLOTS; k += U)
             if (k < width)
-                slice_row_chunk<T, U, COLS>(cols, vals, v, k, width, q);
+                slice_row_chunk<T, U, COLS, NT>(cols, vals, v, k, width, q);
     } else {
         for (int k = 0; k < width; k += U)
-            slice_row_chunk<T, U, COLS>(cols, vals, v, k, width, q);
+            slice_row_chunk<T, U, COLS, NT>(cols, vals, v, k, width, q);
     }
     return q;
 }
+
 
 // Start and width of slice sl, read once per wave and held as uniform values.
 __device__ __forceinline__ void slice_extent(const DevCsr &A, int sl, int &e0, int &width)
@@ -1196,7 +1219,9 @@ __device__ __forceinline__ SliceCols<COLS> slice_cols_of(const DevCsr &A, int sl
 // for W waves: at any moment the chip streams one contiguous window of the
 // slices, each XCD a contiguous eighth of it.  Row sums, epilogues and the
 // reduction are those of k_csr_rows, so y is bitwise identical to it.
-template <int MODE, int DOTS, int COLS>
+// NT: the matrix loads non-temporal (DevCsr::stream; a template parameter,
+// not a branch, so that each kernel keeps the registers of one path).
+template <int MODE, int DOTS, int COLS, bool NT>
 __global__ __launch_bounds__(WG, FK_SPMV_MIN_WAVES) void k_sell_rows(DevCsr A, RowIo io, RedArgs red)
 {
     if (!runs(red))
@@ -1235,7 +1260,7 @@ __global__ __launch_bounds__(WG, FK_SPMV_MIN_WAVES) void k_sell_rows(DevCsr A, R
         double q = 0.0;
         if (width > 0) {  // uniform: a slice of empty rows reads nothing
             const SliceCols<COLS> cols = slice_cols_of<COLS>(A, sl, e0, lane, row);
-            q = slice_row_sum<double, U, COLS>(cols, A.sell_vals + e0 + lane, io.v, width);
+            q = slice_row_sum<double, U, COLS, NT>(cols, A.sell_vals + e0 + lane, VecOf<double>{io.v}, width);
         }
         if (live) {
             if constexpr (K > 0)
@@ -1259,6 +1284,291 @@ __global__ __launch_bounds__(WG) void k_gather_vals(int64_t n, double *__restric
         const int32_t j = map[i];
         out[i] = j >= 0 ? vals[j] : 0.0;
     }
+}
+
+// ------------------------------------------- BiCGStab in two kernels
+//
+// Algorithm 4 with each vector update folded into the product that follows
+// it: wherever the product gathers the vector it multiplies, it recomputes
+// that vector's entry from the vectors of the update, with the update's own
+// expression, so the product sees bitwise the vector the four-kernel
+// schedule would have stored.  Two launches per iteration instead of four,
+// one full reduction each:
+//   k_*_bicg_sas: s_i = r_i - alpha_i A p_i (stored for the own rows,
+//     recomputed at gathered columns); A s_i; <As,s>, <As,As>, <As,r0*>, <s,s>
+//     (FIN_B_SS_OMEGA: half-step test, omega_i, beta_i, expanded rr, decision);
+//   k_*_bicg_xap: x_{i+1}, r_{i+1} = s_i - omega_i A s_i and
+//     p_{i+1} = r_{i+1} + beta_i (p_i - omega_i A p_i) for the own rows,
+//     p_{i+1} recomputed at gathered columns; A p_{i+1}; <Ap,r0*>, <r,r0*>,
+//     <r,r> (FIN_B_XRP_ALPHA: rho_{i+1}, alpha_{i+1}).
+// The product of p_{i+1} gathers p_i and A p_i while it writes p_{i+1} and
+// A p_{i+1}, so those two alternate between two buffers by the parity of i
+// (the device's iteration count, so graph replays and batches agree).  After
+// a decision (half step, converged, budget, breakdown) the xap launch only
+// finishes x and r, and its own reduction ends the solve (FIN_B_XRP_PUB).
+
+// s_i = r_i - alpha_i A p_i, as k_bicg_s writes it.
+struct VecS {
+    const double *__restrict__ r;
+    const double *__restrict__ ap;
+    double alpha;
+    __device__ __forceinline__ double at(int c) const { return r[c] - alpha * ap[c]; }
+};
+
+// p_{i+1} = (s_i - omega_i A s_i) + beta_i (p_i - omega_i A p_i), as
+// k_bicg_xrp writes it.
+struct VecP {
+    const double *__restrict__ s;
+    const double *__restrict__ as;
+    const double *__restrict__ p;
+    const double *__restrict__ ap;
+    double omega, beta;
+    __device__ __forceinline__ double at(int c) const
+    {
+        const double ri = s[c] - omega * as[c];
+        return ri + beta * (p[c] - omega * ap[c]);
+    }
+};
+
+// The s, A s step: own-row inputs, loaded before the row sum.
+struct BicgSas {
+    static constexpr int K = 4;
+    Bicg2Io io;
+    VecS src;
+    struct Own {
+        double s, rs;
+    };
+    __device__ __forceinline__ Own load(int srow) const { return Own{src.at(srow), io.rs[srow]}; }
+    __device__ __forceinline__ void row(int row, double q, const Own &o, dd (&acc)[K]) const
+    {
+        io.s[row] = o.s;
+        io.as[row] = q;
+        dd_fma(acc[0], q, o.s);
+        dd_fma(acc[1], q, q);
+        dd_fma(acc[2], q, o.rs);
+        dd_fma(acc[3], o.s, o.s);
+    }
+};
+
+// The x, r, p, A p step.
+struct BicgXap {
+    static constexpr int K = 3;
+    Bicg2Io io;
+    VecP src;
+    double alpha;
+    double *__restrict__ p_new;
+    double *__restrict__ ap_new;
+    struct Own {
+        double x, s, p, as, ap, rs;
+    };
+    __device__ __forceinline__ Own load(int srow) const
+    {
+        return Own{io.x[srow], src.s[srow], src.p[srow], src.as[srow], src.ap[srow], io.rs[srow]};
+    }
+    __device__ __forceinline__ void row(int row, double q, const Own &o, dd (&acc)[K]) const
+    {
+        io.x[row] = o.x + alpha * o.p + src.omega * o.s;
+        const double ri = o.s - src.omega * o.as;
+        io.r[row] = ri;
+        p_new[row] = ri + src.beta * (o.p - src.omega * o.ap);
+        ap_new[row] = q;
+        dd_fma(acc[0], q, o.rs);
+        dd_fma(acc[1], ri, o.rs);
+        dd_fma(acc[2], ri, ri);
+    }
+};
+
+// The step's policy from the solver state: the buffers of p_i, A p_i by the
+// parity of the iteration count and the scalars of the last reductions.
+__device__ __forceinline__ BicgSas bicg_sas_of(const Bicg2Io &io, const DevState *st)
+{
+    const int cur = st->it & 1;
+    return BicgSas{io, VecS{io.r, io.ap[cur], st->alpha}};
+}
+
+__device__ __forceinline__ BicgXap bicg_xap_of(const Bicg2Io &io, const DevState *st)
+{
+    const int old = (st->it - 1) & 1, nw = st->it & 1;
+    return BicgXap{io, VecP{io.s, io.as, io.p[old], io.ap[old], st->omega, st->beta}, st->alpha, io.p[nw],
+                   io.ap[nw]};
+}
+
+// After a decision: x_{i+1} = x_i + alpha_i p_i and r_{i+1} = s_i (half step),
+// or x_{i+1}, r_{i+1} of the full step; the last reduction of the solve
+// (FIN_B_XRP_PUB with <r,r0*>, <r,r>) then sets the final status.
+__device__ void bicg2_finish(const Bicg2Io &io, int64_t n, const RedArgs &red)
+{
+    const DevState *st = red.st;
+    const bool half = st->status == ST_HALF;
+    const double alpha = st->alpha, omega = st->omega;
+    // p_i: not yet advanced after the half step, one behind after a decision
+    const double *__restrict__ p = io.p[half ? (st->it & 1) : ((st->it - 1) & 1)];
+    dd acc[2] = {dd{0.0, 0.0}, dd{0.0, 0.0}};
+    const int64_t stride = (int64_t)gridDim.x * WG;
+    for (int64_t i = (int64_t)blockIdx.x * WG + threadIdx.x; i < n; i += stride) {
+        if (half) {
+            io.x[i] = io.x[i] + alpha * p[i];
+            io.r[i] = io.s[i];
+        } else {
+            const double si = io.s[i];
+            io.x[i] = io.x[i] + alpha * p[i] + omega * si;
+            const double ri = si - omega * io.as[i];
+            io.r[i] = ri;
+            dd_fma(acc[0], ri, io.rs[i]);
+            dd_fma(acc[1], ri, ri);
+        }
+    }
+    RedArgs rd = red;
+    rd.fin = FIN_B_XRP_PUB;
+    reduce_point<2>(acc, rd, blockIdx.x, gridDim.x);
+}
+
+#ifndef FK_FUSED_MIN_WAVES
+#define FK_FUSED_MIN_WAVES 4
+#endif
+// Entries of a row requested together by the fused products (each entry
+// gathers two or four vectors).
+#ifndef FK_FUSED_UNROLL
+#define FK_FUSED_UNROLL 5
+#endif
+
+// A fused step on the sliced layouts: one wave per slice, one lane per row,
+// as k_sell_rows.
+template <typename POL, int COLS, bool NT>
+__device__ __forceinline__ void sell_fused(const DevCsr &A, const POL &pol, const RedArgs &red)
+{
+    const int G = gridDim.x;
+    const int g = logical_wg();
+    const int lane = threadIdx.x & (SLICE - 1);
+    int sl0, sl_end, sl_step;
+    slice_range(A, sl0, sl_end, sl_step);
+    dd acc[POL::K];
+#pragma unroll
+    for (int k = 0; k < POL::K; ++k)
+        acc[k] = dd{0.0, 0.0};
+    for (int sl = sl0; sl < sl_end; sl += sl_step) {
+        int e0, width;
+        slice_extent(A, sl, e0, width);
+        const int row = sl * SLICE + lane;
+        const typename POL::Own own = pol.load(min(row, A.n - 1));
+        double q = 0.0;
+        if (width > 0) {
+            // (16-bit offsets come four to a load)
+            constexpr int U = COLS == COLS_OFF16 ? (FK_FUSED_UNROLL + 3) / 4 * 4 : FK_FUSED_UNROLL;
+            const SliceCols<COLS> cols = slice_cols_of<COLS>(A, sl, e0, lane, row);
+            q = slice_row_sum<double, U, COLS, NT>(cols, A.sell_vals + e0 + lane, pol.src, width);
+        }
+        if (row < A.n)
+            pol.row(row, q, own, acc);
+    }
+    reduce_point<POL::K>(acc, red, g, G);
+}
+
+// The same on row blocks (as k_csr_rows: products staged in LDS, one
+// thread sums a row left to right; a row longer than NNZ_MAX by a fixed
+// tree over the workgroup).
+template <typename POL>
+__device__ __forceinline__ void csr_fused(const DevCsr &A, const POL &pol, const RedArgs &red)
+{
+    __shared__ double prod[NNZ_MAX];
+    __shared__ int32_t rptr[WG + 1];
+    __shared__ double red_lds[WAVES];
+    const int G = gridDim.x;
+    const int g = logical_wg();
+    const int b_begin = (int)(((int64_t)A.nblocks * g) / G);
+    const int b_end = (int)(((int64_t)A.nblocks * (g + 1)) / G);
+    const int tid = threadIdx.x;
+    dd acc[POL::K];
+#pragma unroll
+    for (int k = 0; k < POL::K; ++k)
+        acc[k] = dd{0.0, 0.0};
+    for (int blk = b_begin; blk < b_end; ++blk) {
+        const int r0 = A.blocks[blk];
+        const int r1 = A.blocks[blk + 1];
+        const int j0 = A.block_j0[blk];
+        const int nrows = r1 - r0;
+        const int nz = A.block_j0[blk + 1] - j0;
+        if (nz <= NNZ_MAX) {
+            typename POL::Own own{};
+            if (tid < nrows) {
+                own = pol.load(r0 + tid);
+                rptr[tid] = A.row_ptr[r0 + tid] - j0;
+            }
+            if (tid == 0)
+                rptr[nrows] = nz;
+            int ci[ITEMS];
+            double va[ITEMS];
+#pragma unroll
+            for (int i = 0; i < ITEMS; ++i) {
+                const int e = tid + i * WG;
+                if (e < nz) {
+                    ci[i] = A.col_idx[j0 + e];
+                    va[i] = A.vals[j0 + e];
+                }
+            }
+#pragma unroll
+            for (int i = 0; i < ITEMS; ++i) {
+                const int e = tid + i * WG;
+                if (e < nz)
+                    prod[e] = va[i] * pol.src.at(ci[i]);
+            }
+            __syncthreads();
+            if (tid < nrows) {
+                const int e0 = rptr[tid], e1 = rptr[tid + 1];
+                double q = 0.0;
+                for (int e = e0; e < e1; ++e)
+                    q = q + prod[e];
+                pol.row(r0 + tid, q, own, acc);
+            }
+            __syncthreads();
+        } else {
+            double part = 0.0;
+            for (int e = tid; e < nz; e += WG)
+                part = part + A.vals[j0 + e] * pol.src.at(A.col_idx[j0 + e]);
+            const double q = block_sum(part, red_lds);
+            if (tid == 0)
+                pol.row(r0, q, pol.load(r0), acc);
+        }
+    }
+    reduce_point<POL::K>(acc, red, g, G);
+}
+
+template <int COLS, bool NT>
+__global__ __launch_bounds__(WG, FK_FUSED_MIN_WAVES) void k_sell_bicg_sas(DevCsr A, Bicg2Io io, RedArgs red)
+{
+    if (!runs(red))
+        return;
+    sell_fused<BicgSas, COLS, NT>(A, bicg_sas_of(io, red.st), red);
+}
+
+template <int COLS, bool NT>
+__global__ __launch_bounds__(WG, FK_FUSED_MIN_WAVES) void k_sell_bicg_xap(DevCsr A, Bicg2Io io, RedArgs red)
+{
+    if (!runs(red))
+        return;
+    if (red.st->status != ST_RUNNING) {  // uniform: the state is read-only here
+        bicg2_finish(io, A.n, red);
+        return;
+    }
+    sell_fused<BicgXap, COLS, NT>(A, bicg_xap_of(io, red.st), red);
+}
+
+__global__ __launch_bounds__(WG, FK_FUSED_MIN_WAVES) void k_csr_bicg_sas(DevCsr A, Bicg2Io io, RedArgs red)
+{
+    if (!runs(red))
+        return;
+    csr_fused<BicgSas>(A, bicg_sas_of(io, red.st), red);
+}
+
+__global__ __launch_bounds__(WG, FK_FUSED_MIN_WAVES) void k_csr_bicg_xap(DevCsr A, Bicg2Io io, RedArgs red)
+{
+    if (!runs(red))
+        return;
+    if (red.st->status != ST_RUNNING) {
+        bicg2_finish(io, A.n, red);
+        return;
+    }
+    csr_fused<BicgXap>(A, bicg_xap_of(io, red.st), red);
 }
 
 // --------------------------------------------------- fused vector updates
@@ -1591,7 +1901,7 @@ __global__ __launch_bounds__(WG, FK_SPMV_MIN_WAVES) void k_csr_rows32(DevCsr A, 
 }
 
 // k_csr_rows32 on the sliced layout (vals32 in slice order).
-template <int COLS, bool F32ACC>
+template <int COLS, bool F32ACC, bool NT>
 __global__ __launch_bounds__(WG, FK_SPMV_MIN_WAVES) void k_sell_rows32(DevCsr A, const float *vals32,
                                                                         const float *v, float *y,
                                                                         RedArgs red)
@@ -1613,7 +1923,7 @@ __global__ __launch_bounds__(WG, FK_SPMV_MIN_WAVES) void k_sell_rows32(DevCsr A,
         float q = 0.f;
         if (width > 0) {  // uniform: a slice of empty rows reads nothing
             const SliceCols<COLS> cols = slice_cols_of<COLS>(A, sl, e0, lane, row);
-            q = slice_row_sum<float, FK_SELL_UNROLL, COLS>(cols, vals32 + e0 + lane, v, width);
+            q = slice_row_sum<float, FK_SELL_UNROLL, COLS, NT>(cols, vals32 + e0 + lane, VecOf<float>{v}, width);
         }
         if (live) {
             y[row] = q;
@@ -2314,16 +2624,24 @@ void set_launch_timing(hipEvent_t start, hipEvent_t stop)
 }
 
 // The product kernel of A's layout.
+template <int MODE, int DOTS, bool NT>
+static hipError_t launch_sell(const DevCsr &A, const RowIo &io, const RedArgs &red, int grid, hipStream_t s)
+{
+    if (A.dg_mask)
+        return launch(k_sell_rows<MODE, DOTS, COLS_SLOTS, NT>, grid, WG, s, A, io, red);
+    if (A.sell_off4)
+        return launch(k_sell_rows<MODE, DOTS, COLS_OFF16, NT>, grid, WG, s, A, io, red);
+    return launch(k_sell_rows<MODE, DOTS, COLS_INT32, NT>, grid, WG, s, A, io, red);
+}
+
 template <int MODE, int DOTS>
 static hipError_t launch_rows(const DevCsr &A, const RowIo &io, const RedArgs &red, int grid,
                               hipStream_t s)
 {
-    if (A.nslices > 0 && A.dg_mask)
-        return launch(k_sell_rows<MODE, DOTS, COLS_SLOTS>, grid, WG, s, A, io, red);
-    if (A.nslices > 0 && A.sell_off4)
-        return launch(k_sell_rows<MODE, DOTS, COLS_OFF16>, grid, WG, s, A, io, red);
+    if (A.nslices > 0 && A.stream)
+        return launch_sell<MODE, DOTS, true>(A, io, red, grid, s);
     if (A.nslices > 0)
-        return launch(k_sell_rows<MODE, DOTS, COLS_INT32>, grid, WG, s, A, io, red);
+        return launch_sell<MODE, DOTS, false>(A, io, red, grid, s);
     return launch(k_csr_rows<MODE, DOTS>, grid, WG, s, A, io, red);
 }
 
@@ -2346,6 +2664,42 @@ hipError_t launch_residual0(const DevCsr &A, const double *b, const double *x, d
 {
     RowIo io{x, r, b, p, rs, nullptr};
     return launch_rows<ROW_RESID, 0>(A, io, red, grid, s);
+}
+
+template <bool XAP, int COLS, bool NT>
+static auto bicg2_kernel()
+{
+    if constexpr (XAP)
+        return k_sell_bicg_xap<COLS, NT>;
+    else
+        return k_sell_bicg_sas<COLS, NT>;
+}
+
+template <bool XAP, bool NT>
+static hipError_t launch_bicg2_sell(const DevCsr &A, const Bicg2Io &io, const RedArgs &red, int grid,
+                                    hipStream_t s)
+{
+    if (A.dg_mask)
+        return launch(bicg2_kernel<XAP, COLS_SLOTS, NT>(), grid, WG, s, A, io, red);
+    if (A.sell_off4)
+        return launch(bicg2_kernel<XAP, COLS_OFF16, NT>(), grid, WG, s, A, io, red);
+    return launch(bicg2_kernel<XAP, COLS_INT32, NT>(), grid, WG, s, A, io, red);
+}
+
+hipError_t launch_bicg2_sas(const DevCsr &A, const Bicg2Io &io, const RedArgs &red, int grid, hipStream_t s)
+{
+    if (A.nslices > 0)
+        return A.stream ? launch_bicg2_sell<false, true>(A, io, red, grid, s)
+                        : launch_bicg2_sell<false, false>(A, io, red, grid, s);
+    return launch(k_csr_bicg_sas, grid, WG, s, A, io, red);
+}
+
+hipError_t launch_bicg2_xap(const DevCsr &A, const Bicg2Io &io, const RedArgs &red, int grid, hipStream_t s)
+{
+    if (A.nslices > 0)
+        return A.stream ? launch_bicg2_sell<true, true>(A, io, red, grid, s)
+                        : launch_bicg2_sell<true, false>(A, io, red, grid, s);
+    return launch(k_csr_bicg_xap, grid, WG, s, A, io, red);
 }
 
 hipError_t launch_gather_vals(int64_t n, double *out, const double *vals, const int32_t *map,
@@ -2403,16 +2757,24 @@ hipError_t launch_residual32(const DevCsr &A, const double *b, const double *x, 
     return launch_rows<ROW_RESID32, 0>(A, io, red, grid, s);
 }
 
+template <bool F32ACC, bool NT>
+static hipError_t launch_sell32(const DevCsr &A, const float *vals32, const float *v, float *y,
+                                const RedArgs &red, int grid, hipStream_t s)
+{
+    if (A.dg_mask)
+        return launch(k_sell_rows32<COLS_SLOTS, F32ACC, NT>, grid, WG, s, A, vals32, v, y, red);
+    if (A.sell_off4)
+        return launch(k_sell_rows32<COLS_OFF16, F32ACC, NT>, grid, WG, s, A, vals32, v, y, red);
+    return launch(k_sell_rows32<COLS_INT32, F32ACC, NT>, grid, WG, s, A, vals32, v, y, red);
+}
+
 template <bool F32ACC>
 static hipError_t launch_spmv32_t(const DevCsr &A, const float *vals32, const float *v, float *y,
                                   const RedArgs &red, int grid, hipStream_t s)
 {
-    if (A.nslices > 0 && A.dg_mask)
-        return launch(k_sell_rows32<COLS_SLOTS, F32ACC>, grid, WG, s, A, vals32, v, y, red);
-    if (A.nslices > 0 && A.sell_off4)
-        return launch(k_sell_rows32<COLS_OFF16, F32ACC>, grid, WG, s, A, vals32, v, y, red);
     if (A.nslices > 0)
-        return launch(k_sell_rows32<COLS_INT32, F32ACC>, grid, WG, s, A, vals32, v, y, red);
+        return A.stream ? launch_sell32<F32ACC, true>(A, vals32, v, y, red, grid, s)
+                        : launch_sell32<F32ACC, false>(A, vals32, v, y, red, grid, s);
     return launch(k_csr_rows32<F32ACC>, grid, WG, s, A, vals32, v, y, red);
 }
 

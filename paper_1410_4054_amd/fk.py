@@ -25,10 +25,10 @@ STATUS_NAMES = {
 # fk_method
 METHODS = {"cg_pipelined": 0, "cg_classical": 1, "bicgstab_pipelined": 2, "bicgstab_classical": 3,
            "cg_mixed": 4, "gmres_pipelined": 5, "gmres_classical": 6, "cg_mixed_f32": 7,
-           "cg_pipelined_split": 8, "bicgstab_pipelined_split": 9}
+           "cg_pipelined_split": 8, "bicgstab_pipelined_split": 9, "bicgstab_pipelined_2k": 10}
 # methods that record per-iteration scalars (alpha, beta, omega, <r,r>)
 SCALAR_METHODS = ("cg_pipelined", "cg_classical", "bicgstab_pipelined", "bicgstab_classical",
-                  "cg_pipelined_split", "bicgstab_pipelined_split")
+                  "cg_pipelined_split", "bicgstab_pipelined_split", "bicgstab_pipelined_2k")
 FLAG_GRAPH = 1
 FLAG_PROFILE = 2
 FLAG_NO_SMALL = 4
@@ -103,6 +103,8 @@ def lib():
             "fk_csr_blocks": [vp, P(i32), P(i32)],
             "fk_csr_layout": [vp, P(i32), P(i64), P(i64)],
             "fk_csr_set_layout": [vp, i32, vp],
+            "fk_csr_set_stream": [vp, i32],
+            "fk_csr_stream": [vp, P(i32), P(i32)],
             "fk_solver_create": [vp, P(_Opts), vp, P(vp)],
             "fk_solve": [vp, vp, vp],
             "fk_get_iterations": [vp, P(i32)],
@@ -151,7 +153,7 @@ def exported_symbols() -> list[str]:
     """Names every caller may rely on (the declarations of include/fk.h)."""
     return [
         "fk_csr_create", "fk_csr_destroy", "fk_csr_shape", "fk_csr_blocks", "fk_csr_layout",
-        "fk_csr_set_layout",
+        "fk_csr_set_layout", "fk_csr_set_stream", "fk_csr_stream",
         "fk_solver_create", "fk_solve", "fk_get_iterations", "fk_get_residual",
         "fk_get_residual_history", "fk_get_scalars", "fk_get_kernel_times",
         "fk_solver_destroy", "fk_solver_uses_small", "fk_get_refinements", "fk_spmv", "fk_spmv32", "fk_dot",
@@ -251,6 +253,16 @@ class Matrix:
             raise ValueError(f"layout must be one of {sorted(LAYOUTS)}")
         st = lib().fk_csr_set_layout(self._h, LAYOUTS[layout], ctypes.c_void_p(_stream_ptr(stream)))
         _check(st, "fk_csr_set_layout")
+
+    def set_stream(self, mode: int):
+        """Streaming mode of the sliced products: -1 by size, 0 off, 1 on."""
+        _check(lib().fk_csr_set_stream(self._h, int(mode)), "fk_csr_set_stream")
+
+    def stream(self) -> tuple[bool, bool]:
+        """(streaming mode on, products in sweep order)."""
+        on, sw = ctypes.c_int32(), ctypes.c_int32()
+        _check(lib().fk_csr_stream(self._h, ctypes.byref(on), ctypes.byref(sw)), "fk_csr_stream")
+        return bool(on.value), bool(sw.value)
 
     def close(self):
         if self._h:

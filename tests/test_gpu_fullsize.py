@@ -17,6 +17,11 @@ pytestmark = pytest.mark.gpu
 NAMES = ["poisson3d_128_cg_pipelined", "poisson3d_128_cg_classical",
          "poisson3d_128_cg_pipelined_30", "convdiff2d_1024_bicgstab_pipelined",
          "convdiff2d_1024_bicgstab_pipelined_30"]
+# (stored case, GPU method): the two-kernel schedule of Algorithm 4 must
+# reproduce the same stored iterates as the four-kernel one.
+CASES = [(name, None) for name in NAMES] + \
+        [("convdiff2d_1024_bicgstab_pipelined", "bicgstab_pipelined_2k"),
+         ("convdiff2d_1024_bicgstab_pipelined_30", "bicgstab_pipelined_2k")]
 _inputs = {}
 
 
@@ -27,12 +32,13 @@ def inputs(workload):
     return _inputs[workload]
 
 
-@pytest.mark.parametrize("name", NAMES)
-def test_full_size_against_oracle(name, device):
+@pytest.mark.parametrize("name,method", CASES, ids=[f"{n}-{m or 'stored'}" for n, m in CASES])
+def test_full_size_against_oracle(name, method, device):
     g = load(name)
     A, b, x0 = inputs(g["workload"])
-    print(f"\n[case] {name} n={A.n} nnz={A.nnz}", flush=True)
-    res, x = gpu_solve(A, b, x0, method=g["method"], rtol=g["rtol"], max_iter=g["max_iter"])
+    method = method or g["method"]
+    print(f"\n[case] {name} {method} n={A.n} nnz={A.nnz}", flush=True)
+    res, x = gpu_solve(A, b, x0, method=method, rtol=g["rtol"], max_iter=g["max_iter"])
     hist = np.array([float.fromhex(h) for h in g["history_hex"]])
     assert res.status == g["status"] and res.k == g["k"], (res.status, res.k, g["k"])
     assert np.array_equal(res.history, hist)
