@@ -547,7 +547,7 @@ fk_status fk_batch_results(fk_batch B, int32_t *status, int32_t *iterations, int
  * device's array would race with it.
  */
 #define FK_NOALLOC_MAX_N 1048576
-#define FK_NOALLOC_BYTES 25571840
+#define FK_NOALLOC_BYTES 25563392
 fk_status fk_solve_noalloc(fk_csr A, const fk_opts *o, const double *b_dev, double *x_dev, void *hip_stream,
                            int32_t *iterations, double *rel_res);
 

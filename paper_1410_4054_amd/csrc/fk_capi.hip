@@ -653,7 +653,7 @@ extern "C" fk_status fk_csr_create(int64_t n, int64_t nnz, const int32_t *row_pt
     CSR_HIP(hipMemcpyAsync(A->blocks, blocks.data(), blocks.size() * 4, hipMemcpyHostToDevice, s));
     CSR_HIP(hipMemcpyAsync(A->block_j0, block_j0.data(), block_j0.size() * 4, hipMemcpyHostToDevice, s));
     CSR_HIP(hipMemsetAsync(A->st, 0, sizeof(DevState), s));
-    CSR_HIP(hipMemsetAsync(A->partials, 0, RED_SCRATCH_DOUBLES * sizeof(double), s));
+    CSR_HIP(launch_red_init(A->partials, s));
     CSR_HIP(hipStreamSynchronize(s));
     {
         int64_t max_len = 0;
@@ -865,6 +865,7 @@ struct fk_solver_s {
     hipEvent_t poll_ev[2] = {nullptr, nullptr};
     DevState last{};
     bool solved = false;
+    bool red_dirty = false;  // a reduction gave up: rewrite the scratch's markers first
     fk_status last_status = FK_E_STATE;
     int grid_spmv = 1, grid_vec = 1;
     // profiling
@@ -1113,7 +1114,7 @@ extern "C" fk_status fk_solver_create(fk_csr A, const fk_opts *o, void *hip_stre
     for (auto &e : S->poll_ev)
         S_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
     S_HIP(hipMemsetAsync(S->st, 0, sizeof(DevState), S->stream));
-    S_HIP(hipMemsetAsync(S->partials, 0, RED_SCRATCH_DOUBLES * sizeof(double), S->stream));
+    S_HIP(launch_red_init(S->partials, S->stream));
     if (S->gmres) {
         S_HIP(hipMemsetAsync(S->gR, 0, ((size_t)S->gm + 1) * ((size_t)S->gm + 1) * sizeof(double), S->stream));
         S_HIP(hipMemsetAsync(S->gpart, 0, GM_PART_DOUBLES * sizeof(double), S->stream));
@@ -1374,6 +1375,14 @@ hipError_t mixed_outer(fk_solver S, const double *b, double *x, bool add, bool p
 
 #undef ENQ
 
+// A reduction point that gave up waiting (DevState::red_fault) voids the
+// solve: report it, and rewrite the scratch's empty markers before the next.
+static fk_status reduction_fault(fk_solver S)
+{
+    S->red_dirty = true;
+    return fail(FK_E_HIP, "a cross-workgroup reduction did not complete; the solve is void");
+}
+
 hipError_t enqueue_poll(fk_solver S, int slot)
 {
     const char *status_addr = reinterpret_cast<const char *>(S->st) + offsetof(DevState, status);
@@ -1495,6 +1504,8 @@ static fk_status run_batches(fk_solver S, const double *b, double *x, double rto
     HIP_TRY(hipMemcpyAsync(&S->h_init[2], S->st, sizeof(DevState), hipMemcpyDeviceToHost, S->stream));
     HIP_TRY(hipStreamSynchronize(S->stream));
     S->last = S->h_init[2];
+    if (S->last.red_fault)
+        return reduction_fault(S);
     return FK_OK;
 }
 
@@ -1561,6 +1572,8 @@ static fk_status solve_gmres(fk_solver S, const double *b, double *x, bool profi
         if (profile)
             harvest_profile(S, 0);
         DevState cur = S->h_init[2];
+        if (cur.red_fault)
+            return reduction_fault(S);
         if (cur.status == ST_ZERO_RHS) {
             HIP_TRY(hipMemsetAsync(x, 0, (size_t)n * sizeof(double), st));
             HIP_TRY(hipStreamSynchronize(st));
@@ -1607,6 +1620,8 @@ static fk_status solve_mixed(fk_solver S, const double *b, double *x, bool profi
     if (e != hipSuccess)
         return fail(FK_E_HIP, "refinement residual: %s", hipGetErrorString(e));
     DevState outer = S->h_init[2];
+    if (outer.red_fault)
+        return reduction_fault(S);
     int64_t used = 0;
     while (outer.status == ST_RUNNING) {
         if (S->sweeps >= S->o.max_outer || used >= S->o.max_iter) {
@@ -1630,6 +1645,8 @@ static fk_status solve_mixed(fk_solver S, const double *b, double *x, bool profi
             return fail(FK_E_HIP, "refinement step: %s", hipGetErrorString(e));
         S->sweeps++;
         outer = S->h_init[2];
+        if (outer.red_fault)
+            return reduction_fault(S);
     }
     if (outer.status == ST_ZERO_RHS) {
         HIP_TRY(hipMemsetAsync(x, 0, (size_t)S->n * sizeof(double), S->stream));
@@ -1646,6 +1663,10 @@ extern "C" fk_status fk_solve(fk_solver S, const double *b, double *x)
         return fail(FK_E_ARG, "NULL argument");
     S->solved = false;
     S->sweeps = 0;
+    if (S->red_dirty) {
+        HIP_TRY(launch_red_init(S->partials, S->stream));
+        S->red_dirty = false;
+    }
     const bool profile = (S->o.flags & FK_FLAG_PROFILE) != 0;
     const bool graph = !profile && (S->o.flags & FK_FLAG_GRAPH) != 0 && S->stream != nullptr;
     if (profile) {
@@ -1825,10 +1846,10 @@ extern "C" fk_status fk_solve_noalloc(fk_csr A, const fk_opts *o, const double *
     S.small_stage = S.small && small_staged_lds_bytes(0, A->n, A->nnz) + SMALL_STATIC_LDS <=
                                    max_lds_per_workgroup(A->device);
 
-    // The array keeps the last call's contents: the counters and partials
-    // start from zero and the state from its initial values (fill kernels,
-    // no memset nodes).
-    HIP_TRY(launch_clear(S.partials, (int64_t)RED_SCRATCH_DOUBLES, 64, st));
+    // The array keeps the last call's contents: the partial slots start
+    // empty and the state from its initial values (fill kernels, no memset
+    // nodes).
+    HIP_TRY(launch_red_init(S.partials, st));
     HIP_TRY(launch_state_init(S.st, S.o.rtol, S.o.max_iter, 0, st));
     DevState last{};
     if (S.small) {
@@ -1865,6 +1886,8 @@ extern "C" fk_status fk_solve_noalloc(fk_csr A, const fk_opts *o, const double *
         *iterations = last.it;
     if (rel_res)
         *rel_res = last.last_rel;
+    if (last.red_fault)
+        return fail(FK_E_HIP, "a cross-workgroup reduction did not complete; the solve is void");
     switch (last.status) {
     case ST_CONVERGED:
     case ST_ZERO_RHS:
@@ -1962,6 +1985,16 @@ extern "C" fk_status fk_get_kernel_times(fk_solver S, double *avg_us, int32_t *c
 
 // ------------------------------------------------------- kernel entry points
 
+// A reduction of one of the kernel entry points gave up waiting: clear the
+// fault, rewrite the scratch's empty markers and report the call void.
+static fk_status scratch_fault(DevState *st, double *partials, hipStream_t s)
+{
+    (void)hipMemsetAsync(reinterpret_cast<char *>(st) + offsetof(DevState, red_fault), 0, sizeof(int32_t), s);
+    (void)launch_red_init(partials, s);
+    (void)hipStreamSynchronize(s);
+    return fail(FK_E_HIP, "a cross-workgroup reduction did not complete; the result is void");
+}
+
 extern "C" fk_status fk_spmv(fk_csr A, const double *p, double *q, double *dots_host, void *hip_stream)
 {
     if (!A || !p || !q)
@@ -1973,12 +2006,13 @@ extern "C" fk_status fk_spmv(fk_csr A, const double *p, double *q, double *dots_
     RedArgs red{A->st, A->partials, nullptr, nullptr, FIN_NONE, RUN_ALWAYS};
     HIP_TRY(launch_spmv_dots(A->view(), p, q, nullptr, dots, red, A->spmv_grid(), s));
     if (dots_host) {
-        double d[KMAX];
-        HIP_TRY(hipMemcpyAsync(d, reinterpret_cast<const char *>(A->st) + offsetof(DevState, dots),
-                               sizeof d, hipMemcpyDeviceToHost, s));
+        DevState d;
+        HIP_TRY(hipMemcpyAsync(&d, A->st, sizeof d, hipMemcpyDeviceToHost, s));
         HIP_TRY(hipStreamSynchronize(s));
-        dots_host[0] = d[0];
-        dots_host[1] = d[1];
+        if (d.red_fault)
+            return scratch_fault(A->st, A->partials, s);
+        dots_host[0] = d.dots[0];
+        dots_host[1] = d.dots[1];
     } else {
         HIP_TRY(hipStreamSynchronize(s));
     }
@@ -2009,13 +2043,14 @@ extern "C" fk_status fk_spmv32(fk_csr A, const float *p, float *q, int32_t f32ac
     }
     RedArgs red{A->st, A->partials, nullptr, nullptr, FIN_NONE, RUN_ALWAYS};
     HIP_TRY(launch_spmv32(A->view(), A->vals32, p, q, red, A->spmv_grid(), s, f32acc != 0));
-    double d[KMAX];
-    HIP_TRY(hipMemcpyAsync(d, reinterpret_cast<const char *>(A->st) + offsetof(DevState, dots), sizeof d,
-                           hipMemcpyDeviceToHost, s));
+    DevState d;
+    HIP_TRY(hipMemcpyAsync(&d, A->st, sizeof d, hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
+    if (d.red_fault)
+        return scratch_fault(A->st, A->partials, s);
     if (dots_host) {
-        dots_host[0] = d[0];
-        dots_host[1] = d[1];
+        dots_host[0] = d.dots[0];
+        dots_host[1] = d.dots[1];
     }
     return FK_OK;
 }
@@ -2046,13 +2081,16 @@ extern "C" fk_status fk_dot(int64_t n, const double *a, const double *b, double 
             return st;
         }
         HIP_TRY(hipMemsetAsync(g_dot_st, 0, sizeof(DevState), s));
-        HIP_TRY(hipMemsetAsync(g_dot_partials, 0, RED_SCRATCH_DOUBLES * sizeof(double), s));
+        HIP_TRY(launch_red_init(g_dot_partials, s));
     }
     RedArgs red{g_dot_st, g_dot_partials, nullptr, nullptr, FIN_NONE, RUN_ALWAYS};
     HIP_TRY(launch_dot(n, a, b, nullptr, 1, red, vec_grid(n), s));
-    HIP_TRY(hipMemcpyAsync(out, reinterpret_cast<const char *>(g_dot_st) + offsetof(DevState, dots),
-                           sizeof(double), hipMemcpyDeviceToHost, s));
+    DevState d;
+    HIP_TRY(hipMemcpyAsync(&d, g_dot_st, sizeof d, hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
+    if (d.red_fault)
+        return scratch_fault(g_dot_st, g_dot_partials, s);
+    *out = d.dots[0];
     return FK_OK;
 }
 

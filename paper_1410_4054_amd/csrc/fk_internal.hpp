@@ -19,29 +19,25 @@ constexpr int ITEMS = NNZ_MAX / WG;  // staged products per thread per block
 constexpr int KMAX = 4;
 // Upper bound on workgroups of one launch (size of the partial-sum buffer).
 constexpr int GMAX = 4096;
-// The second reduction stage is a two-level tree: workgroups arrive in
-// groups of RGROUP; the last of each group sums the group, the last group
-// sums the group sums.
+// The second reduction stage is a two-level tree: workgroups form groups
+// of RGROUP; the last of each group sums the group, the last group's
+// leader sums the group sums.
 constexpr int RGROUP = 64;
-// A launch with at most this many double-double partials (workgroups times
-// dots, published ones included) is summed by one wave of its last
-// workgroup alone.
-#ifndef FK_FLAT_PARTIALS
-#define FK_FLAT_PARTIALS 1024
-#endif
-constexpr int FLAT_PARTIALS = FK_FLAT_PARTIALS;
 constexpr int RNGROUPS_MAX = GMAX / RGROUP;
 constexpr int CNT_STRIDE = 32;  // uint32 per arrival counter (one 128-byte line each)
 // Published first-stage partials (FIN_PUBLISH) of at most this many dots.
 constexpr int KPUB = 2;
 // Layout of the reduction scratch (doubles): level-1 partials [KMAX][GMAX]
-// double-double, level-2 partials [KMAX][RNGROUPS_MAX] double-double,
-// RNGROUPS_MAX + 1 arrival counters, then published partials [KPUB][GMAX]
+// double-double, level-2 partials [KMAX][RNGROUPS_MAX] double-double (both
+// holding RED_EMPTY between launches: launch_red_init writes it, the
+// leaders put it back), then published partials [KPUB][GMAX]
 // double-double.
 constexpr size_t RED_L2_OFFSET = (size_t)2 * KMAX * GMAX;
-constexpr size_t RED_CNT_OFFSET = RED_L2_OFFSET + (size_t)2 * KMAX * RNGROUPS_MAX;
-constexpr size_t RED_PUB_OFFSET = RED_CNT_OFFSET + ((size_t)(RNGROUPS_MAX + 1) * CNT_STRIDE * 4 + 7) / 8;
+constexpr size_t RED_PUB_OFFSET = RED_L2_OFFSET + (size_t)2 * KMAX * RNGROUPS_MAX;
 constexpr size_t RED_SCRATCH_DOUBLES = RED_PUB_OFFSET + (size_t)2 * KPUB * GMAX;
+// The bits of an empty partial slot: a signalling NaN, which no
+// floating-point operation returns.
+constexpr uint64_t RED_EMPTY = 0x7ff40000deadbeefull;
 
 // Solver state kept on the device; only the last workgroup of a reduction
 // writes it, every kernel reads `status` first and returns unless it is one
@@ -88,7 +84,7 @@ struct alignas(128) DevState {
     int32_t gi;       // GMRES: step of the current cycle (1-based, next to do)
     int32_t gm;       // GMRES: restart length m
     int32_t rho_pub;  // BiCGStab: <r,r0*>, <r,r> published by the last update
-    uint32_t pad;
+    int32_t red_fault;  // a reduction point gave up waiting (the solve is void)
 };
 
 // What the last workgroup does with the reduced inner products.
@@ -329,6 +325,9 @@ hipError_t launch_zero(double *x, int64_t n, DevState *st, uint32_t run_mask, in
                        hipStream_t s);
 // x[0 .. n) = 0, unconditionally.
 hipError_t launch_clear(double *x, int64_t n, int grid, hipStream_t s);
+// A reduction scratch of RED_SCRATCH_DOUBLES ready for its first use: the
+// partial slots empty (RED_EMPTY), the published partials zero.
+hipError_t launch_red_init(double *partials, hipStream_t s);
 // *st = the state a multi-kernel solve starts from (running, rtol, max_iter,
 // hist_cap, everything else zero), written by a one-thread kernel.
 hipError_t launch_state_init(DevState *st, double rtol, int32_t max_iter, int32_t hist_cap, hipStream_t s);

@@ -619,45 +619,57 @@ __device__ void finalize(DevState *st, int fin, const double *d, int K, double *
 //
 // First stage.  Each wave sums its lanes' partials (butterfly); waves 1 ..
 // WAVES-1 leave theirs in LDS, meet wave 0 at one barrier and exit.  Wave 0
-// adds them in wave order and carries on alone: the stores, the wait for
-// them and the arrival below hold one wave of the workgroup, not four, and
-// there is no further barrier.
+// adds them in wave order.
 //
-// Second stage.  Workgroup g stores its partials and arrives at the counter
-// of group g / RGROUP; the last arrival of a group arrives at the top
-// counter, and the last of those finishes:
-//  - with at most FLAT_PARTIALS partials in all, it sums every partial
-//    itself (lane l takes indices l, l + 64, ..., then the butterfly);
-//  - else as a two-level tree: the last arrival of each group first sums
-//    that group's partials (one per lane; RGROUP is the wave width) and
-//    stores the group sum, and the last group sums the group sums (at most
-//    GMAX / RGROUP = 64, again one per lane).
-// Either way the result is rounded once and finalized.
-// The order of every sum depends only on the grid size, never on timing.
-// Counters are reset by the workgroup that saw the last arrival, so the
-// scratch is ready for the next launch.
+// Second stage, without arrival counters.  Workgroup g of a group of RGROUP
+// consecutive (logical) workgroups stores its partials into its own slots
+// and ends at once: no wait for the stores, no atomic.  The group's last
+// workgroup, its leader, reads the other members' slots, one member per
+// lane, polling until none holds the empty marker any more, adds them with
+// its own in a lane butterfly (a fixed order), puts the empty marker back
+// and stores the group sum the same way; the leader of the last group,
+// workgroup G-1, collects the group sums likewise, rounds once and runs the
+// scalar recurrences (finalize).  A slot is read only after the value
+// written into it has arrived (each double is stored and read whole, and
+// the marker is a signalling NaN, which no arithmetic returns), so no store
+// needs to be waited for, and the critical path after the last workgroup's
+// rows is two store-to-poll hand-overs instead of arrival round trips.
+// Forward progress: at most GMAX / RGROUP leaders poll at once, each holding
+// one workgroup slot, and the members they wait for need none of them, so
+// the other slots run every member to the end whatever the dispatch order.
+// Every poll loop is bounded (RED_SPIN_LIMIT); running out sets red_fault
+// and ends the solve with a breakdown, which the host reports as an error
+// (and rewrites the markers before the next use).
 //
 // Published partials.  With fin == FIN_PUBLISH a kernel only stores its
-// workgroup partials (first stage) and ends: no counter, no finalize.  A
-// reduction point in a later kernel with kpub > 0 folds them in: the last
-// arrival of group j also sums the j-th of ngroups equal slices of the npub
-// published partials, so they ride the same two levels as the kernel's own
-// dots and cost no extra round trip.  Algorithm 2 needs <r_i, r_i> only with
-// the product's two dots (alpha_i and beta_i need all three), which is what
-// lets the update kernel publish it instead of reducing it.
+// workgroup partials (first stage) and ends.  A reduction point in a later
+// kernel with kpub > 0 folds them in: the leader of group j also sums the
+// j-th of ngroups equal slices of the npub published partials (complete
+// since the earlier kernel ended), so they ride the same two levels as the
+// kernel's own dots.  Algorithm 2 needs <r_i, r_i> only with the product's
+// two dots (alpha_i and beta_i need all three), which is what lets the
+// update kernel publish it instead of reducing it.
 static_assert(RGROUP == 64 && GMAX / RGROUP <= 64, "group and top level are one wave64 each");
 
-// Lane 0's value of a wave-uniform arrival count, in every lane.
-__device__ __forceinline__ uint32_t wave_bcast(uint32_t x)
+// Polls a leader makes before it gives a reduction up (each waits for a
+// load from the device's coherence point; 2^22 of them take seconds).
+#ifndef FK_RED_SPIN_LIMIT
+#define FK_RED_SPIN_LIMIT (1 << 22)
+#endif
+
+__device__ __forceinline__ bool red_empty(double x)
 {
-    return (uint32_t)__builtin_amdgcn_readfirstlane((int)x);
+    return (uint64_t)__double_as_longlong(x) == RED_EMPTY;
 }
+
+__device__ __forceinline__ double red_empty_value() { return __longlong_as_double((long long)RED_EMPTY); }
 
 // How a reduction point accumulates.  AccDD: double-double sums of exact
 // FP64 products, rounded once (the FP64 path and the exact FP32 mode).
 // AccF32: plain FP32 sums (the FP32-accumulating inner solver); a partial is
 // stored as the double holding the float, exactly.  Either way every sum
-// has a fixed order that depends only on the launch shape.
+// has a fixed order that depends only on the launch shape.  A slot is two
+// doubles; `take` reads one and reports whether it has been written.
 struct AccDD {
     using T = dd;
     __device__ static T zero() { return dd{0.0, 0.0}; }
@@ -669,6 +681,16 @@ struct AccDD {
         store_coherent(slot + 1, v.lo);
     }
     __device__ static T load(const double *slot) { return dd{load_coherent(slot), load_coherent(slot + 1)}; }
+    __device__ static bool take(const double *slot, T &out)
+    {
+        out = load(slot);
+        return !red_empty(out.hi) && !red_empty(out.lo);
+    }
+    __device__ static void clear(double *slot)
+    {
+        store_coherent(slot, red_empty_value());
+        store_coherent(slot + 1, red_empty_value());
+    }
     __device__ static double round(T v) { return v.hi + v.lo; }
 };
 
@@ -685,8 +707,44 @@ struct AccF32 {
     }
     __device__ static void store(double *slot, T v) { store_coherent(slot, (double)v); }
     __device__ static T load(const double *slot) { return (float)load_coherent(slot); }
+    __device__ static bool take(const double *slot, T &out)
+    {
+        const double d = load_coherent(slot);
+        out = (float)d;
+        return !red_empty(d);
+    }
+    __device__ static void clear(double *slot) { store_coherent(slot, red_empty_value()); }
     __device__ static double round(T v) { return (double)v; }
 };
+
+// Lane l < count (other than `own`) reads the K slots of member l (slot of
+// dot k at base + 2 (k * stride + l)) until all have been written; lane
+// `own` takes `mine`, lanes from count on take zero.  Returns false when the
+// poll limit ran out.
+template <int K, typename ACC>
+__device__ __forceinline__ bool collect(const double *base, int stride, int count, int own,
+                                        const typename ACC::T (&mine)[K], typename ACC::T (&out)[K])
+{
+    const int lane = threadIdx.x & 63;
+    bool ok = lane >= count || lane == own;
+#pragma unroll
+    for (int k = 0; k < K; ++k)
+        out[k] = lane == own ? mine[k] : ACC::zero();
+    for (int spin = 0;; ++spin) {
+        if (!ok) {
+            bool all = true;
+#pragma unroll
+            for (int k = 0; k < K; ++k)
+                all = ACC::take(base + 2 * ((size_t)k * stride + lane), out[k]) && all;
+            ok = all;
+        }
+        if (__builtin_amdgcn_ballot_w64(!ok) == 0)
+            return true;
+        if (spin >= FK_RED_SPIN_LIMIT)
+            return false;
+        __builtin_amdgcn_s_sleep(1);
+    }
+}
 
 template <int K, typename ACC = AccDD>
 __device__ __forceinline__ void reduce_point(typename ACC::T (&v)[K], const RedArgs &red, int g, int G)
@@ -696,7 +754,6 @@ __device__ __forceinline__ void reduce_point(typename ACC::T (&v)[K], const RedA
     double *const part1 = red.partials;
     double *const part2 = red.partials + RED_L2_OFFSET;
     double *const pub = red.partials + RED_PUB_OFFSET;
-    uint32_t *const cnt = reinterpret_cast<uint32_t *>(red.partials + RED_CNT_OFFSET);
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
     const int ngroups = (G + RGROUP - 1) / RGROUP;
@@ -730,144 +787,91 @@ __device__ __forceinline__ void reduce_point(typename ACC::T (&v)[K], const RedA
         }
         return;
     }
-    uint32_t prev = 0;
-    if (lane == 0) {
+    const int own = gsize - 1;  // the leader's lane: the group's last member
+    if (g != gbase + own) {
+        if (lane == 0) {
 #pragma unroll
-        for (int k = 0; k < K; ++k)
-            ACC::store(part1 + 2 * ((size_t)k * GMAX + g), v[k]);
-        // The partial stores must have reached the coherence point before
-        // another workgroup can observe this arrival.
-        __builtin_amdgcn_s_waitcnt(0);
-        prev = __hip_atomic_fetch_add(cnt + (size_t)grp * CNT_STRIDE, 1u, __ATOMIC_RELAXED,
-                                      __HIP_MEMORY_SCOPE_AGENT);
-    }
-    if (wave_bcast(prev) != (uint32_t)(gsize - 1))
+            for (int k = 0; k < K; ++k)
+                ACC::store(part1 + 2 * ((size_t)k * GMAX + g), v[k]);
+        }
         return;
+    }
 
+    // Group leader.
     constexpr int KP = (K + KPUB <= KMAX) ? KPUB : KMAX - K;
     constexpr int KT = K + KP;
     const int kpub = KP > 0 ? red.kpub : 0;
     const int kt = K + kpub;
+    T mem[K];
+    bool done = collect<K, ACC>(part1 + 2 * (size_t)gbase, GMAX, gsize, own, v, mem);
     T acc[KT];
 #pragma unroll
-    for (int k = 0; k < KT; ++k)
+    for (int k = 0; k < K; ++k)
+        acc[k] = mem[k];
+#pragma unroll
+    for (int k = K; k < KT; ++k)
         acc[k] = ACC::zero();
-
-    // Few partials: the last group only signals, and the very last
-    // workgroup sums every partial itself (one load round trip instead of
-    // a load, a store and a second arrival).  Many: two levels of sums.
-    const bool flat = (int64_t)G * K + (int64_t)red.npub * kpub <= FLAT_PARTIALS;
-    if (flat) {
-        if (lane == 0) {
-            __hip_atomic_store(cnt + (size_t)grp * CNT_STRIDE, 0u, __ATOMIC_RELAXED,
-                               __HIP_MEMORY_SCOPE_AGENT);
-            prev = __hip_atomic_fetch_add(cnt + (size_t)RNGROUPS_MAX * CNT_STRIDE, 1u,
-                                          __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        }
-        if (wave_bcast(prev) != (uint32_t)(ngroups - 1))
-            return;
-        // Lane l adds partials l, l + 64, ... in index order; UB of them
-        // are requested before the first is added.
-        constexpr int UB = K <= 1 ? 4 : (K == 2 ? 2 : 1);
-        for (int j0 = lane; j0 < G; j0 += 64 * UB) {
-            T t[UB][K];
+    if (kpub > 0) {
+        // this group's share of the published partials, in index order
+        const int p0 = (int)(((int64_t)red.npub * grp) / ngroups);
+        const int p1 = (int)(((int64_t)red.npub * (grp + 1)) / ngroups);
+        for (int j = p0 + lane; j < p1; j += 64) {
 #pragma unroll
-            for (int u = 0; u < UB; ++u) {
-#pragma unroll
-                for (int k = 0; k < K; ++k) {
-                    const double *slot = part1 + 2 * ((size_t)k * GMAX + j0 + 64 * u);
-                    if (j0 + 64 * u < G)
-                        t[u][k] = ACC::load(slot);
-                }
+            for (int k = 0; k < KP; ++k) {
+                if (k < kpub)
+                    acc[K + k] = ACC::add(acc[K + k], ACC::load(pub + 2 * ((size_t)k * GMAX + j)));
             }
-#pragma unroll
-            for (int u = 0; u < UB; ++u) {
-                if (j0 + 64 * u < G) {
-#pragma unroll
-                    for (int k = 0; k < K; ++k)
-                        acc[k] = ACC::add(acc[k], t[u][k]);
-                }
-            }
-        }
-        if (kpub > 0) {
-            constexpr int UP = KP <= 1 ? 2 : 2;
-            for (int j0 = lane; j0 < red.npub; j0 += 64 * UP) {
-                T t[UP][KP > 0 ? KP : 1];
-#pragma unroll
-                for (int u = 0; u < UP; ++u) {
-#pragma unroll
-                    for (int k = 0; k < KP; ++k) {
-                        const double *slot = pub + 2 * ((size_t)k * GMAX + j0 + 64 * u);
-                        if (k < kpub && j0 + 64 * u < red.npub)
-                            t[u][k] = ACC::load(slot);
-                    }
-                }
-#pragma unroll
-                for (int u = 0; u < UP; ++u) {
-                    if (j0 + 64 * u < red.npub) {
-#pragma unroll
-                        for (int k = 0; k < KP; ++k)
-                            if (k < kpub)
-                                acc[K + k] = ACC::add(acc[K + k], t[u][k]);
-                    }
-                }
-            }
-        }
-    } else {
-        // Last arrival of the group: sum the group's partials, and this
-        // group's share of the published partials (dots K .. K + kpub - 1).
-#pragma unroll
-        for (int k = 0; k < K; ++k) {
-            if (lane < gsize)
-                acc[k] = ACC::load(part1 + 2 * ((size_t)k * GMAX + gbase + lane));
-        }
-        if (kpub > 0) {
-            const int p0 = (int)(((int64_t)red.npub * grp) / ngroups);
-            const int p1 = (int)(((int64_t)red.npub * (grp + 1)) / ngroups);
-            for (int j = p0 + lane; j < p1; j += 64) {
-#pragma unroll
-                for (int k = 0; k < KP; ++k) {
-                    if (k < kpub)
-                        acc[K + k] = ACC::add(acc[K + k], ACC::load(pub + 2 * ((size_t)k * GMAX + j)));
-                }
-            }
-        }
-#pragma unroll
-        for (int k = 0; k < KT; ++k)
-            acc[k] = ACC::wave(acc[k]);
-        if (lane == 0) {
-#pragma unroll
-            for (int k = 0; k < KT; ++k) {
-                if (k < kt)
-                    ACC::store(part2 + 2 * ((size_t)k * RNGROUPS_MAX + grp), acc[k]);
-            }
-            __hip_atomic_store(cnt + (size_t)grp * CNT_STRIDE, 0u, __ATOMIC_RELAXED,
-                               __HIP_MEMORY_SCOPE_AGENT);
-            __builtin_amdgcn_s_waitcnt(0);
-            prev = __hip_atomic_fetch_add(cnt + (size_t)RNGROUPS_MAX * CNT_STRIDE, 1u,
-                                          __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        }
-        if (wave_bcast(prev) != (uint32_t)(ngroups - 1))
-            return;
-
-        // Last group: sum the group sums, one per lane.
-#pragma unroll
-        for (int k = 0; k < KT; ++k) {
-            acc[k] = ACC::zero();
-            if (k < kt && lane < ngroups)
-                acc[k] = ACC::load(part2 + 2 * ((size_t)k * RNGROUPS_MAX + lane));
         }
     }
 #pragma unroll
     for (int k = 0; k < KT; ++k)
         acc[k] = ACC::wave(acc[k]);
+    // the members' slots are free again for the next launch
+    if (lane < gsize && lane != own) {
+#pragma unroll
+        for (int k = 0; k < K; ++k)
+            ACC::clear(part1 + 2 * ((size_t)k * GMAX + gbase + lane));
+    }
+    if (ngroups > 1) {
+        const int top = ngroups - 1;
+        if (grp != top) {
+            if (lane == 0) {
+                // all KT slots (those past kt hold zero), which the top
+                // leader collects whatever kpub is
+#pragma unroll
+                for (int k = 0; k < KT; ++k)
+                    ACC::store(part2 + 2 * ((size_t)k * RNGROUPS_MAX + grp), acc[k]);
+                // a leader that gave up voids the reduction and stops the
+                // solve; the top leader still receives a sum and ends
+                if (!done) {
+                    red.st->red_fault = 1;
+                    red.st->status = ST_BREAKDOWN;
+                }
+            }
+            return;
+        }
+        // Leader of the last group: collect the group sums.
+        T sums[KT];
+        done = collect<KT, ACC>(part2, RNGROUPS_MAX, ngroups, top, acc, sums) && done;
+#pragma unroll
+        for (int k = 0; k < KT; ++k)
+            acc[k] = ACC::wave(sums[k]);
+        if (lane < top) {
+#pragma unroll
+            for (int k = 0; k < KT; ++k)
+                ACC::clear(part2 + 2 * ((size_t)k * RNGROUPS_MAX + lane));
+        }
+    }
     if (lane == 0) {
+        if (!done) {
+            red.st->red_fault = 1;
+            red.st->status = ST_BREAKDOWN;
+            return;
+        }
         double d[KT > 0 ? KT : 1];
 #pragma unroll
         for (int k = 0; k < KT; ++k)
             d[k] = ACC::round(acc[k]);
-        __hip_atomic_store(cnt + (size_t)RNGROUPS_MAX * CNT_STRIDE, 0u, __ATOMIC_RELAXED,
-                           __HIP_MEMORY_SCOPE_AGENT);
         finalize(red.st, red.fin, d, kt, red.hist, red.scal);
     }
 }
@@ -1761,6 +1765,15 @@ __global__ __launch_bounds__(WG) void k_clear(double *__restrict__ x, int64_t n)
     const int64_t stride = (int64_t)gridDim.x * WG;
     for (int64_t i = (int64_t)blockIdx.x * WG + threadIdx.x; i < n; i += stride)
         x[i] = 0.0;
+}
+
+// The reduction scratch before its first use: partial slots empty, the
+// published partials zero.
+__global__ __launch_bounds__(WG) void k_red_init(double *__restrict__ part)
+{
+    const double empty = __longlong_as_double((long long)RED_EMPTY);
+    for (size_t i = (size_t)blockIdx.x * WG + threadIdx.x; i < RED_SCRATCH_DOUBLES; i += (size_t)gridDim.x * WG)
+        part[i] = i < RED_PUB_OFFSET ? empty : 0.0;
 }
 
 // The state a multi-kernel solve starts from, written by the device (every
@@ -2870,6 +2883,11 @@ hipError_t launch_zero(double *x, int64_t n, DevState *st, uint32_t run_mask, in
                        hipStream_t s)
 {
     return launch(k_zero, grid, WG, s, x, n, st, run_mask);
+}
+
+hipError_t launch_red_init(double *partials, hipStream_t s)
+{
+    return launch(k_red_init, 64, WG, s, partials);
 }
 
 hipError_t launch_clear(double *x, int64_t n, int grid, hipStream_t s)
