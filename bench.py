@@ -211,10 +211,42 @@ def run_case(spec: str, steps: int, warmup: int, layout_arg=None):
 
     from paper_1410_4054_amd import fk, problems as P
 
+    torch.cuda.set_device(0)
+    if spec == "batch512":
+        # The 512-system batch (FP32 inner CG + FP64 refinement to 1e-10) in
+        # one launch, the default launch shape, `steps` solves.
+        Ab, spb, bb = P.batch_problem()
+        B = fk.Batch(Ab, spb)
+        bbd = torch.as_tensor(bb, device="cuda")
+        xbd = torch.zeros_like(bbd)
+        for rep in range(warmup + steps):
+            if rep == warmup:
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+            xbd.zero_()
+            B.solve(bbd, xbd, rtol=1e-10)
+        torch.cuda.synchronize()
+        t = (time.perf_counter() - t0) / max(steps, 1)
+        res = B.results()
+        print(json.dumps({"case": spec, "systems": B.count, "seconds_per_solve": t,
+                          "solves_per_s": B.count / t, "all_converged": bool((res.status == 0).all()),
+                          "inner_iterations": int(res.iterations.sum())}), flush=True)
+        return
+    if spec == "heat512":
+        # The learned initial guess: training (3000 steps of the recipe), then
+        # the 400 steps of seed 0 with the learned guess.
+        from paper_1410_4054_amd import warmstart as W
+
+        net, losses, tdata, ttrain = W.train_recipe()
+        T = W.Transient(512, 0)
+        r, _ = T.run("learned", net=net, passes=W.RECIPE["passes"])
+        print(json.dumps({"case": spec, "training_seconds": ttrain, "cg_iterations": r.total_iterations,
+                          "solves_per_s": r.solves_per_s}), flush=True)
+        net.close()
+        return
     parts = spec.split(":")
     wl, method = parts[0], parts[1]
     iters = int(parts[2]) if len(parts) > 2 else None
-    torch.cuda.set_device(0)
     m_rand = re.fullmatch(r"random(\d+)_(\d+)", wl)
     if m_rand:
         # Section 2.2's microbenchmark matrix: k uniformly random columns per row
@@ -307,8 +339,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=20.0,
                     help="seconds of host time the CPU baseline's thread sweep may use")
     ap.add_argument("--case", default=None,
-                    help="WORKLOAD:METHOD[:ITERS]: time that case alone (for profiler runs) "
-                         "instead of the benchmark")
+                    help="WORKLOAD:METHOD[:ITERS], batch512 or heat512: time that case alone (for "
+                         "profiler runs) instead of the benchmark")
     ap.add_argument("--layout", default=None,
                     help="with --case: force the products' layout (row_blocks, sliced, sliced16, slots)")
     args = ap.parse_args()
@@ -439,26 +471,43 @@ def main():
         extras["iteration_layout_frac_of_peak"] = per_it_layout * value / 1e9 / PEAK_HBM_GBS
         extras["copy_kernel_GBps_1GiB"] = copy_bandwidth(torch, fk)
 
-        log("[bench] extras: BiCGStab 1024^2")
-        # Nonsymmetric workload: pipelined BiCGStab on 1024^2 convection-diffusion.
+        log("[bench] extras: BiCGStab 1024^2, four and two kernels per iteration")
+        # Nonsymmetric workload: pipelined BiCGStab on 1024^2 convection-
+        # diffusion, in Section 3.2's four-kernel schedule and with each
+        # vector update folded into the following product (two kernels).
         A3, b3, _ = P.workload("convdiff2d_1024")
         M3 = fk.Matrix(A3)
         b3d = torch.as_tensor(b3, device="cuda")
         x3d = torch.zeros_like(b3d)
-        S3 = fk.Solver(M3, method="bicgstab_pipelined", rtol=RTOL, record_history=False)
-        x3d.zero_(); S3.solve(b3d, x3d)
-        t3, its3 = time_solves(torch, S3, b3d, x3d, 2)
-        extras["bicgstab_convdiff2d_1024_iters_per_s"] = its3 / t3
-        extras["bicgstab_convdiff2d_1024_k"] = S3.iterations()
         # Algorithmic bytes of one pipelined BiCGStab iteration on the CSR
         # matrix, each array read once: two products (12 nnz + 4 (N + 1) of
         # matrix data and 24 N of vectors each), the s update (24 N) and the
-        # x, r, p update (72 N): 24 nnz + 152 N + 8.
+        # x, r, p update (72 N): 24 nnz + 152 N + 8.  The two-kernel
+        # schedule moves 24 nnz + 128 N + 8 of them (its products read r, A p
+        # and p, A p where the four-kernel one reads s and p).
         bicg_b = 24 * A3.nnz + 152 * A3.n + 8
+        moved = {"bicgstab_pipelined": 2 * M3.matrix_bytes() + 144 * A3.n,
+                 "bicgstab_pipelined_2k": 2 * M3.matrix_bytes() + 120 * A3.n}
         extras["bicgstab_convdiff2d_1024_iteration_algorithmic_bytes"] = bicg_b
-        extras["bicgstab_convdiff2d_1024_iteration_GBps"] = bicg_b * its3 / t3 / 1e9
-        extras["bicgstab_convdiff2d_1024_iteration_frac_of_peak"] = bicg_b * its3 / t3 / 1e9 / PEAK_HBM_GBS
-        S3.close(); M3.close()
+        for method, tag in (("bicgstab_pipelined", "bicgstab"), ("bicgstab_pipelined_2k", "bicgstab_2k")):
+            S3 = fk.Solver(M3, method=method, rtol=RTOL, record_history=False)
+            x3d.zero_(); S3.solve(b3d, x3d)
+            t3, its3 = time_solves(torch, S3, b3d, x3d, 3)
+            extras[f"{tag}_convdiff2d_1024_iters_per_s"] = its3 / t3
+            extras[f"{tag}_convdiff2d_1024_us_per_iter"] = t3 / its3 * 1e6
+            extras[f"{tag}_convdiff2d_1024_k"] = S3.iterations()
+            extras[f"{tag}_convdiff2d_1024_iteration_GBps"] = bicg_b * its3 / t3 / 1e9
+            extras[f"{tag}_convdiff2d_1024_iteration_frac_of_peak"] = bicg_b * its3 / t3 / 1e9 / PEAK_HBM_GBS
+            extras[f"{tag}_convdiff2d_1024_iteration_layout_bytes"] = moved[method]
+            extras[f"{tag}_convdiff2d_1024_iteration_layout_frac_of_peak"] = (
+                moved[method] * its3 / t3 / 1e9 / PEAK_HBM_GBS)
+            S3.close()
+            S3 = fk.Solver(M3, method=method, rtol=RTOL, record_history=False, profile=True)
+            x3d.zero_(); S3.solve(b3d, x3d)
+            kt3 = S3.kernel_times()
+            S3.close()
+            extras[f"{tag}_convdiff2d_1024_kernel_us"] = {k: v[0] for k, v in kt3.items() if v[1]}
+        M3.close()
 
         log("[bench] extras: GMRES(30) 1024^2")
         # GMRES(30) on the nonsymmetric workload: two cycles of 30 iterations,
@@ -502,6 +551,7 @@ def main():
         csr5 = csr_spmv_dot_bytes(A5.n, A5.nnz) + update_bytes(A5.n)
         lay5_b = spmv_dot_bytes(A5.n, M5.matrix_bytes()) + update_bytes(A5.n)
         extras["poisson3d_192_layout"] = lay5
+        extras["poisson3d_192_streaming_mode"] = M5.stream()[0]
         extras["poisson3d_192_iters_per_s"] = its5 / t5
         extras["poisson3d_192_spmv_dot_us"] = kt5["spmv_dot"][0]
         extras["poisson3d_192_update_dot_us"] = kt5["update_dot"][0]
@@ -545,9 +595,13 @@ def main():
         extras["poisson2d_size_sweep_us_per_iter_30fixed_median10"] = sweep
 
         log("[bench] extras: fused vs unfused SpMV + dot, random 4 and 28 nonzeros per row")
-        # The kernel-fusion example of Section 2.2: q = A p and <p, q> with
-        # the result on the host, as one fused launch or as a product then a
-        # dot; median of 20 calls.
+        # The kernel-fusion example of Section 2.2 on its random matrices (k
+        # uniformly random columns per row): the product with <p,q>, <q,q>
+        # fused, the product then a separate dot kernel, and the product
+        # alone; device time per launch (HIP events stamped at kernel start
+        # and end, 50 launches); at N = 10^6 also GB/s on the CSR bytes
+        # (12 nnz + 4 (N + 1) + 16 N for the product; the split pair reads p
+        # and q once more) and on the counters' basis, 128-byte lines.
         fusion = {}
         for k in (4, 28):
             for nrow in (1000, 10000, 100000, 1000000):
@@ -555,22 +609,52 @@ def main():
                 Mr = fk.Matrix(Ar)
                 pr = torch.rand(nrow, dtype=torch.float64, device="cuda")
                 qr = torch.zeros_like(pr)
-                res = {}
-                for label in ("fused", "unfused"):
-                    times = []
-                    for rep in range(23):
-                        torch.cuda.synchronize()
-                        t = time.perf_counter()
-                        if label == "fused":
-                            fk.spmv(Mr, pr, qr, dots=True)
-                        else:
-                            fk.spmv(Mr, pr, qr)
-                            fk.dot(pr, qr)
-                        times.append(time.perf_counter() - t)
-                    res[label + "_us"] = float(np.median(times[3:])) * 1e6
+                res = {"layout": Mr.layout()[0]}
+                for mode in ("fused", "split", "product"):
+                    fk.spmv_time(Mr, pr, qr, mode=mode, reps=5)
+                    res[mode + "_us"] = fk.spmv_time(Mr, pr, qr, mode=mode, reps=50)
+                res["fused_over_split"] = res["split_us"] / res["fused_us"]
+                if nrow == 1000000:
+                    csr_b = 12 * Ar.nnz + 4 * (nrow + 1) + 16 * nrow
+                    res["csr_bytes"] = csr_b
+                    res["fused_csr_GBps"] = csr_b / (res["fused_us"] * 1e-6) / 1e9
+                    res["fused_csr_frac"] = res["fused_csr_GBps"] / PEAK_HBM_GBS
+                    res["product_csr_GBps"] = csr_b / (res["product_us"] * 1e-6) / 1e9
                 Mr.close()
                 fusion[f"{k}nnz_n{nrow}"] = res
-        extras["spmv_dot_fusion_host_result"] = fusion
+        extras["spmv_dot_fusion_device_us"] = fusion
+
+        # The paper's own figures (its hardware), beside the same ratios here.
+        sw = extras["poisson2d_size_sweep_us_per_iter_30fixed_median10"]
+        extras["paper_reference"] = {
+            "fused_spmv_dot_gain_4nnz_small_n": {
+                "paper": "about 20 % faster fused than unfused up to 1e4 unknowns (Tesla C2050, Section 2.2)",
+                "mi355x_split_over_fused_n1e3_n1e4": [fusion["4nnz_n1000"]["fused_over_split"],
+                                                      fusion["4nnz_n10000"]["fused_over_split"]]},
+            "fused_spmv_dot_gain_4nnz_large_n": {
+                "paper": "a few percent above 1e5 unknowns (Tesla C2050, Section 2.2)",
+                "mi355x_split_over_fused_n1e5_n1e6": [fusion["4nnz_n100000"]["fused_over_split"],
+                                                      fusion["4nnz_n1000000"]["fused_over_split"]]},
+            "fused_spmv_dot_gain_28nnz": {
+                "paper": "up to 10 % at small N, none at large N (Tesla C2050, Section 2.2)",
+                "mi355x_split_over_fused_n1e3_n1e6": [fusion["28nnz_n1000"]["fused_over_split"],
+                                                      fusion["28nnz_n1000000"]["fused_over_split"]]},
+            "pipelined_vs_classical_small_n": {
+                "paper": "about 2x (Tesla C2050, K20m), 3x CG and 4x BiCGStab (FirePro W9000, W9100) "
+                         "for 2D Poisson at small N (Section 4.1)",
+                "mi355x_classical_over_pipelined_cg_n225_n961_n3969": [
+                    sw[k]["cg_classical"] / sw[k]["cg_pipelined"] for k in ("225", "961", "3969")],
+                "mi355x_classical_over_pipelined_bicgstab_n225_n961_n3969": [
+                    sw[k]["bicgstab_classical"] / sw[k]["bicgstab_pipelined"] for k in ("225", "961", "3969")]},
+            "latency_floor": {
+                "paper": "time per iteration flat below 1e4 unknowns (1e5 on AMD), the AMD floor about twice "
+                         "NVIDIA's (Section 4.1)",
+                "mi355x_cg_pipelined_us_per_iter_n225_to_n261121": [sw[k]["cg_pipelined"] for k in sorted(sw, key=int)]},
+            "gpu_vs_cpu_crossover": {
+                "paper": "pipelined GPU solvers beat PETSc on a dual Xeon E5-2620 from about 3,000 unknowns "
+                         "(Section 4.1)",
+                "mi355x": "see cpu_baseline (the oracle's classical CG on this host's cores)"},
+        }
 
         log("[bench] extras: mixed precision 128^3")
         # Mixed precision: FP64 iterative refinement around FP32 pipelined CG,
@@ -776,8 +860,8 @@ def main():
         "roofline": {"bound": "hbm", "achieved": layout_achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
                      "frac": layout_achieved / PEAK_HBM_GBS, "traffic": traffic,
                      "kernel": "fused SpMV + <p,Ap>, <Ap,Ap> (" + {
-                         "slots": "k_sell_rows<0,3,2>", "sliced16": "k_sell_rows<0,3,1>",
-                         "sliced": "k_sell_rows<0,3,0>", "row_blocks": "k_csr_rows<0,3>"}[layout] + ")",
+                         "slots": "k_sell_rows<0,3,2,false>", "sliced16": "k_sell_rows<0,3,1,false>",
+                         "sliced": "k_sell_rows<0,3,0,false>", "row_blocks": "k_csr_rows<0,3>"}[layout] + ")",
                      "layout": layout,
                      "bytes_basis": "the layout's own arrays, each read once, + p read once + Ap written once",
                      "bytes_per_launch": spmv_layout_b, "avg_us": spmv_us,

@@ -365,6 +365,19 @@ fk_status fk_get_refinements(fk_solver S, int32_t *sweeps);
 fk_status fk_spmv(fk_csr A, const double *p_dev, double *q_dev, double *dots_host, void *hip_stream);
 
 /*
+ * The kernel time of q = A p (Section 2.2's product): `reps` launches back
+ * to back, each carrying two HIP events that the device stamps when the
+ * kernel itself starts and ends; *avg_us receives their average duration.
+ * mode 0: the product alone; 1: fused with the first stage of <p,q>, <q,q>
+ * and their second stage (as fk_spmv with dots); 2: the product, then a
+ * separate kernel for the two inner products (Section 2.2's unfused pair;
+ * the average is that of the pair, each kernel timed on its own).
+ * FK_E_ARG for reps < 1 or another mode.  Synchronous.
+ */
+fk_status fk_spmv_time(fk_csr A, const double *p_dev, double *q_dev, int32_t mode, int32_t reps,
+                       double *avg_us, void *hip_stream);
+
+/*
  * q = A p in FP32, the inner product kernel of FK_CG_MIXED / FK_CG_MIXED_F32
  * (Section 2.2's fused kernel in single precision): the values of A rounded
  * to FP32 (once, at the first call after a layout change, kept with the

@@ -868,6 +868,8 @@ struct fk_solver_s {
     bool red_dirty = false;  // a reduction gave up: rewrite the scratch's markers first
     fk_status last_status = FK_E_STATE;
     int grid_spmv = 1, grid_vec = 1;
+    // FK_BICGSTAB_PIPELINED_2K: workgroups of its two fused steps
+    int grid_sas = 1, grid_xap = 1;
     // profiling
     std::vector<hipEvent_t> prof_ev[2];  // one event pool per batch slot
     std::vector<TimedLaunch> prof_batch[2];
@@ -1039,6 +1041,31 @@ extern "C" fk_status fk_solver_create(fk_csr A, const fk_opts *o, void *hip_stre
     S->n = A->n;
     S->grid_spmv = A->spmv_grid();
     S->grid_vec = vec_grid(A->n);
+    if (o->method == FK_BICGSTAB_PIPELINED_2K) {
+        // One round of resident workgroups, at most 4 per CU and never more
+        // than the product grid; on the sliced layouts sized so that every
+        // wave takes the same number of slices (a wave with one slice more
+        // than the others sets the launch's end).  Measured on 1024^2
+        // convection-diffusion (16384 slices): the xap step holds 4
+        // workgroups per CU, and 1024 of them (4 slices per wave) beat 2048
+        // (two rounds) by 6 %; for the sas step (7 per CU resident) 1024
+        // beat 1368 (3 slices per wave) and 2048 by 4-6 %.
+        for (int xap = 0; xap < 2; ++xap) {
+            const int per_cu = std::min(bicg2_per_cu(A->view(), xap != 0), 4);
+            int64_t g = S->grid_spmv;
+            if (per_cu > 0 && A->cus > 0 && g > (int64_t)per_cu * A->cus) {
+                g = (int64_t)per_cu * A->cus;
+                const int64_t sl = A->slices();
+                if (sl > 0) {
+                    const int64_t spw = (sl + (int64_t)WAVES * g - 1) / ((int64_t)WAVES * g);
+                    g = (sl + (int64_t)WAVES * spw - 1) / ((int64_t)WAVES * spw);
+                }
+            }
+            if (g >= 8)
+                g = (g + 7) & ~(int64_t)7;
+            (xap ? S->grid_xap : S->grid_sas) = (int)std::max<int64_t>(g, 1);
+        }
+    }
     const size_t n = (size_t)A->n;
 #define S_TRY(expr)                                                                        \
     do {                                                                                   \
@@ -1299,8 +1326,9 @@ hipError_t enqueue_iteration(fk_solver S, Enq &q, double *x, bool last)
         // and A p_{i+1} (+ <Ap,r0*>, <r,r0*>, <r,r>: rho, alpha), or, after
         // a decision, the last x, r and the final reduction.
         const Bicg2Io io{x, S->r, S->s, S->as, S->rs, {S->p, S->p2}, {S->ap, S->ap2}};
-        ENQ(FK_KERNEL_SPMV_DOT, launch_bicg2_sas(A, io, S->red(FIN_B_SS_OMEGA, RUN_ACTIVE), gs, st));
-        ENQ(FK_KERNEL_UPDATE_DOT, launch_bicg2_xap(A, io, S->red(FIN_B_XRP_ALPHA, RUN_BICG_UPDATE), gs, st));
+        ENQ(FK_KERNEL_SPMV_DOT, launch_bicg2_sas(A, io, S->red(FIN_B_SS_OMEGA, RUN_ACTIVE), S->grid_sas, st));
+        ENQ(FK_KERNEL_UPDATE_DOT,
+            launch_bicg2_xap(A, io, S->red(FIN_B_XRP_ALPHA, RUN_BICG_UPDATE), S->grid_xap, st));
         break;
     }
     case FK_BICGSTAB_CLASSICAL:
@@ -2016,6 +2044,61 @@ extern "C" fk_status fk_spmv(fk_csr A, const double *p, double *q, double *dots_
     } else {
         HIP_TRY(hipStreamSynchronize(s));
     }
+    return FK_OK;
+}
+
+extern "C" fk_status fk_spmv_time(fk_csr A, const double *p, double *q, int32_t mode, int32_t reps,
+                                  double *avg_us, void *hip_stream)
+{
+    if (!A || !p || !q || !avg_us)
+        return fail(FK_E_ARG, "NULL argument");
+    if ((const void *)p == (const void *)q)
+        return fail(FK_E_ARG, "p and q must not alias");
+    if (reps < 1 || mode < 0 || mode > 2)
+        return fail(FK_E_ARG, "reps must be >= 1 and mode 0, 1 or 2");
+    hipStream_t s = (hipStream_t)hip_stream;
+    const int kernels = mode == 2 ? 2 : 1;
+    std::vector<hipEvent_t> ev((size_t)2 * kernels * reps, nullptr);
+    auto release = [&]() {
+        for (auto e : ev)
+            if (e)
+                (void)hipEventDestroy(e);
+    };
+    for (auto &e : ev) {
+        if (hipEventCreate(&e) != hipSuccess) {
+            release();
+            return fail(FK_E_HIP, "hipEventCreate failed");
+        }
+    }
+    hipError_t e = hipSuccess;
+    for (int r = 0; r < reps && e == hipSuccess; ++r) {
+        hipEvent_t *pe = &ev[(size_t)2 * kernels * r];
+        RedArgs red{A->st, A->partials, nullptr, nullptr, FIN_NONE, RUN_ALWAYS};
+        set_launch_timing(pe[0], pe[1]);
+        e = launch_spmv_dots(A->view(), p, q, nullptr, mode == 1 ? (D_YV | D_YY) : 0, red, A->spmv_grid(), s);
+        if (e == hipSuccess && mode == 2) {
+            set_launch_timing(pe[2], pe[3]);
+            e = launch_dot(A->n, q, p, q, 2, red, vec_grid(A->n), s);
+        }
+    }
+    set_launch_timing(nullptr, nullptr);
+    if (e == hipSuccess)
+        e = hipStreamSynchronize(s);
+    double total = 0.0;
+    for (size_t i = 0; e == hipSuccess && i < ev.size(); i += 2) {
+        float ms = 0.f;
+        e = hipEventElapsedTime(&ms, ev[i], ev[i + 1]);
+        total += ms;
+    }
+    release();
+    if (e != hipSuccess)
+        return fail(FK_E_HIP, "fk_spmv_time: %s", hipGetErrorString(e));
+    DevState d;
+    HIP_TRY(hipMemcpyAsync(&d, A->st, sizeof d, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    if (d.red_fault)
+        return scratch_fault(A->st, A->partials, s);
+    *avg_us = 1000.0 * total / reps;
     return FK_OK;
 }
 

@@ -239,6 +239,8 @@ struct Bicg2Io {
     double *ap[2];
 };
 hipError_t launch_bicg2_sas(const DevCsr &A, const Bicg2Io &io, const RedArgs &red, int grid, hipStream_t s);
+// Workgroups of the sas (xap = false) or xap step resident per compute unit.
+int bicg2_per_cu(const DevCsr &A, bool xap);
 hipError_t launch_bicg2_xap(const DevCsr &A, const Bicg2Io &io, const RedArgs &red, int grid, hipStream_t s);
 // Classical (unfused) building blocks.
 // <a,b> (ndots 1); <a,b>, <a,c> (2); <a,b>, <a,c>, <a,e> (3).

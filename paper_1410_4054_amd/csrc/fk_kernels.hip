@@ -2699,6 +2699,28 @@ static hipError_t launch_bicg2_sell(const DevCsr &A, const Bicg2Io &io, const Re
     return launch(bicg2_kernel<XAP, COLS_INT32, NT>(), grid, WG, s, A, io, red);
 }
 
+// Workgroups of one fused step resident per compute unit (the occupancy of
+// the kernel its launch would take), 0 when the query fails.
+int bicg2_per_cu(const DevCsr &A, bool xap)
+{
+    int n = 0;
+    hipError_t e;
+    const bool nt = A.stream != 0;
+    auto q = [&](auto kern) { return hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, kern, WG, 0); };
+    if (A.nslices > 0 && A.dg_mask)
+        e = xap ? (nt ? q(k_sell_bicg_xap<COLS_SLOTS, true>) : q(k_sell_bicg_xap<COLS_SLOTS, false>))
+                : (nt ? q(k_sell_bicg_sas<COLS_SLOTS, true>) : q(k_sell_bicg_sas<COLS_SLOTS, false>));
+    else if (A.nslices > 0 && A.sell_off4)
+        e = xap ? (nt ? q(k_sell_bicg_xap<COLS_OFF16, true>) : q(k_sell_bicg_xap<COLS_OFF16, false>))
+                : (nt ? q(k_sell_bicg_sas<COLS_OFF16, true>) : q(k_sell_bicg_sas<COLS_OFF16, false>));
+    else if (A.nslices > 0)
+        e = xap ? (nt ? q(k_sell_bicg_xap<COLS_INT32, true>) : q(k_sell_bicg_xap<COLS_INT32, false>))
+                : (nt ? q(k_sell_bicg_sas<COLS_INT32, true>) : q(k_sell_bicg_sas<COLS_INT32, false>));
+    else
+        e = xap ? q(k_csr_bicg_xap) : q(k_csr_bicg_sas);
+    return e == hipSuccess ? n : 0;
+}
+
 hipError_t launch_bicg2_sas(const DevCsr &A, const Bicg2Io &io, const RedArgs &red, int grid, hipStream_t s)
 {
     if (A.nslices > 0)

@@ -116,6 +116,7 @@ def lib():
             "fk_solver_uses_small": [vp, P(i32)],
             "fk_get_refinements": [vp, P(i32)],
             "fk_spmv": [vp, vp, vp, P(f64), vp],
+            "fk_spmv_time": [vp, vp, vp, i32, i32, P(f64), vp],
             "fk_spmv32": [vp, vp, vp, i32, P(f64), vp],
             "fk_dot": [i64, vp, vp, P(f64), vp],
             "fk_copy": [vp, vp, i64, vp],
@@ -156,7 +157,8 @@ def exported_symbols() -> list[str]:
         "fk_csr_set_layout", "fk_csr_set_stream", "fk_csr_stream",
         "fk_solver_create", "fk_solve", "fk_get_iterations", "fk_get_residual",
         "fk_get_residual_history", "fk_get_scalars", "fk_get_kernel_times",
-        "fk_solver_destroy", "fk_solver_uses_small", "fk_get_refinements", "fk_spmv", "fk_spmv32", "fk_dot",
+        "fk_solver_destroy", "fk_solver_uses_small", "fk_get_refinements", "fk_spmv", "fk_spmv_time",
+        "fk_spmv32", "fk_dot",
         "fk_copy",
         "fk_axpby", "fk_net_num_weights", "fk_net_create", "fk_net_destroy", "fk_net_get_weights",
         "fk_net_set_weights", "fk_net_forward", "fk_net_guess", "fk_net_gradient", "fk_net_train_step",
@@ -284,6 +286,21 @@ def spmv(A: Matrix, p, q, dots: bool = False, stream=None):
                        out if dots else None, ctypes.c_void_p(_stream_ptr(stream)))
     _check(st, "fk_spmv")
     return (out[0], out[1]) if dots else None
+
+
+SPMV_TIME_MODES = {"product": 0, "fused": 1, "split": 2}
+
+
+def spmv_time(A: Matrix, p, q, mode: str = "fused", reps: int = 50, stream=None) -> float:
+    """Average kernel time in microseconds of q = A p over `reps` launches:
+    "product" alone, "fused" with <p,q>, <q,q>, or "split" (product, then a
+    separate dot kernel; the pair's time)."""
+    n = A.n
+    us = ctypes.c_double()
+    _check(lib().fk_spmv_time(A.handle, _dev_f64(p, n, "p"), _dev_f64(q, n, "q"), SPMV_TIME_MODES[mode],
+                              int(reps), ctypes.byref(us), ctypes.c_void_p(_stream_ptr(stream))),
+           "fk_spmv_time")
+    return us.value
 
 
 def spmv32(A: Matrix, p, q, f32acc: bool = False, stream=None) -> tuple[float, float]:

@@ -3,6 +3,8 @@ first-stage reductions, the device dot, the copy kernel.  The oracle sums
 each row left to right, as the HIP kernels do for rows of at most
 FK_LONG_ROW nonzeros, so those rows must agree bit for bit; inner products
 are rounded once from an (almost) exact sum on both sides."""
+import ctypes
+
 import numpy as np
 import pytest
 
@@ -349,3 +351,25 @@ def test_copy(nbytes, device):
     fk.copy(dst, src, nbytes)
     torch.cuda.synchronize()
     assert torch.equal(dst, src)
+
+
+@pytest.mark.parametrize("mode", ["product", "fused", "split"])
+def test_spmv_time(mode, device):
+    """fk_spmv_time runs the product it times: q equals the oracle's A p and
+    the fused reduction still completes; bad arguments are refused."""
+    A = P.random_csr(5000, 4, seed=4)
+    p = np.random.default_rng(7).uniform(-1, 1, A.n)
+    M = fk.Matrix(A)
+    pd, qd = dev(p), dev(np.zeros(A.n))
+    us = fk.spmv_time(M, pd, qd, mode=mode, reps=5)
+    assert us > 0.0
+    assert np.array_equal(host(qd), oracle.spmv(A, p))
+    dots = fk.spmv(M, pd, qd, dots=True)
+    assert dots[1] == oracle.dot(host(qd), host(qd))
+    L = fk.lib()
+    out = ctypes.c_double()
+    for reps, md in ((0, 1), (1, 3), (1, -1)):
+        st = L.fk_spmv_time(M.handle, ctypes.c_void_p(pd.data_ptr()), ctypes.c_void_p(qd.data_ptr()), md, reps,
+                            ctypes.byref(out), None)
+        assert st == fk.E_ARG
+    M.close()
