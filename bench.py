@@ -569,7 +569,8 @@ def main():
         log("[bench] extras: size sweep, 2D Poisson n^2, n = 15 .. 511")
         # The x-axis of the paper's Fig. 4: time per iteration (median of 10
         # runs of 30 fixed iterations) of the pipelined and classical
-        # methods.  Pipelined solves of up to 8192 (CG) / 2048 (BiCGStab)
+        # methods, and of the one-kernel CG and two-kernel BiCGStab
+        # schedules.  Pipelined solves of up to 8192 (CG) / 2048 (BiCGStab)
         # unknowns run in the single-workgroup kernel.
         sweep = {}
         for nn in (15, 31, 63, 127, 255, 511):
@@ -578,7 +579,8 @@ def main():
             bsd = torch.as_tensor(bs, device="cuda")
             xsd = torch.zeros_like(bsd)
             row = {}
-            for method in ("cg_pipelined", "cg_classical", "bicgstab_pipelined", "bicgstab_classical"):
+            for method in ("cg_pipelined", "cg_pipelined_1k", "cg_classical", "bicgstab_pipelined",
+                           "bicgstab_pipelined_2k", "bicgstab_classical"):
                 Ssw = fk.Solver(Ms, method=method, rtol=0.0, max_iter=30, record_history=False)
                 times = []
                 for _ in range(11):

@@ -75,11 +75,14 @@ typedef enum {
                                    kernel (Section 3.1's alternative): 3 kernels */
     FK_BICGSTAB_PIPELINED_SPLIT = 9, /* Algorithm 4 with both products' dots in their
                                    own kernels (Section 3.2's alternative): 6 kernels */
-    FK_BICGSTAB_PIPELINED_2K = 10  /* Algorithm 4 in 2 kernels/iteration: each vector
+    FK_BICGSTAB_PIPELINED_2K = 10, /* Algorithm 4 in 2 kernels/iteration: each vector
                                    update of Section 3.2 folded into the product
                                    that follows it (the product recomputes the
                                    updated vector where it gathers it); the same
                                    iterates, bit for bit, as FK_BICGSTAB_PIPELINED */
+    FK_CG_PIPELINED_1K = 11    /* Algorithm 2 + Eq. (3) in 1 kernel/iteration: the
+                                   x, r, p update folded into the product the same
+                                   way; the same iterates as FK_CG_PIPELINED */
 } fk_method;
 
 /* Rows with more nonzeros than this are summed by a fixed tree, not left to right. */
@@ -335,7 +338,8 @@ fk_status fk_get_scalars(fk_solver S, double *out, int32_t cap, int32_t *len);
 enum {
     FK_KERNEL_SETUP = 0,       /* r0 = b - A x0 and its reductions            */
     FK_KERNEL_SPMV_DOT = 1,    /* fused CSR product + first-stage dots
-                                  (FK_BICGSTAB_PIPELINED_2K: s_i, A s_i)      */
+                                  (FK_BICGSTAB_PIPELINED_2K: s_i, A s_i;
+                                  FK_CG_PIPELINED_1K: x, r, p and A p)       */
     FK_KERNEL_UPDATE_DOT = 2,  /* fused vector updates + first-stage dot(s)
                                   (FK_BICGSTAB_PIPELINED_2K: x, r, p, A p)    */
     FK_KERNEL_SPMV = 3,        /* plain CSR product (classical)               */

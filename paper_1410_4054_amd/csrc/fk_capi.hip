@@ -146,6 +146,8 @@ struct fk_csr_s {
     uint32_t *dg_mask = nullptr;
     double *dg_vals = nullptr;
     int32_t dg_nslices = 0;   // > 0 once the slot arrays exist
+    int32_t dg_max_width = 0;    // most slots of any slice
+    int32_t sell_max_width = 0;  // most entries per row of any slice (sliced layouts)
     int64_t dg_entries = 0;
     int32_t layout = FK_LAYOUT_ROW_BLOCKS;  // layout the products read
     // scratch reduction state for fk_spmv / fk_spmv32
@@ -164,13 +166,15 @@ struct fk_csr_s {
         const int32_t nt = streaming() ? 1 : 0;
         if (slots())
             return DevCsr{(int32_t)n, (int32_t)nnz, nblocks, row_ptr, col_idx, vals, blocks, block_j0,
-                          dg_nslices, dg_ptr, nullptr, dg_vals, nullptr, nullptr, dg_off, dg_mask, sw, nt};
+                          dg_nslices, dg_ptr, nullptr, dg_vals, nullptr, nullptr, dg_off, dg_mask, sw, nt,
+                          dg_max_width};
         return DevCsr{(int32_t)n,  (int32_t)nnz, nblocks,  row_ptr,
                       col_idx,     vals,         blocks,   block_j0,
                       sliced() ? nslices : 0,    sell_ptr, sell_col,
                       sell_vals,   sell_ptr4,
                       layout == FK_LAYOUT_SLICED16 ? sell_off4 : nullptr,
-                      nullptr,     nullptr,      sliced() ? sw : 0, sliced() ? nt : 0};
+                      nullptr,     nullptr,      sliced() ? sw : 0, sliced() ? nt : 0,
+                      sliced() ? sell_max_width : 0};
     }
     // Entries the products read: nnz, or the slice entries with padding.
     int64_t stored_entries() const { return slots() ? dg_entries : sliced() ? sell_entries : nnz; }
@@ -418,6 +422,10 @@ static fk_status build_slices(fk_csr A, const int32_t *rp, const int32_t *ci,
     A->sell_vals = d_vals;
     A->nslices = (int32_t)ns;
     A->sell_entries = entries;
+    int64_t mw = 0;
+    for (int64_t sl = 0; sl < ns; ++sl)
+        mw = std::max<int64_t>(mw, (off[(size_t)sl + 1] - off[(size_t)sl]) / SLICE);
+    A->sell_max_width = (int32_t)mw;
     return FK_OK;
 }
 
@@ -536,6 +544,10 @@ static fk_status build_slots(fk_csr A, const int32_t *rp, const int32_t *ci, con
     A->dg_vals = d_vals;
     A->dg_nslices = (int32_t)ns;
     A->dg_entries = entries;
+    int32_t mw = 0;
+    for (int64_t sl = 0; sl < ns; ++sl)
+        mw = std::max(mw, sptr[(size_t)sl + 1] - sptr[(size_t)sl]);
+    A->dg_max_width = mw;
     return FK_OK;
 }
 
@@ -853,8 +865,9 @@ struct fk_solver_s {
     hipStream_t stream = nullptr;
     int64_t n = 0;
     double *r = nullptr, *p = nullptr, *ap = nullptr, *s = nullptr, *as = nullptr, *rs = nullptr;
-    // FK_BICGSTAB_PIPELINED_2K: the second buffers of p and A p
-    double *p2 = nullptr, *ap2 = nullptr;
+    // FK_BICGSTAB_PIPELINED_2K: the second buffers of p and A p;
+    // FK_CG_PIPELINED_1K: of r, p and A p
+    double *p2 = nullptr, *ap2 = nullptr, *r2 = nullptr;
     double *partials = nullptr, *hist = nullptr, *scal = nullptr;
     DevState *st = nullptr;
     int32_t hist_cap = 0;
@@ -868,7 +881,8 @@ struct fk_solver_s {
     bool red_dirty = false;  // a reduction gave up: rewrite the scratch's markers first
     fk_status last_status = FK_E_STATE;
     int grid_spmv = 1, grid_vec = 1;
-    // FK_BICGSTAB_PIPELINED_2K: workgroups of its two fused steps
+    // FK_BICGSTAB_PIPELINED_2K: workgroups of its two fused steps;
+    // FK_CG_PIPELINED_1K: of its one (grid_xap)
     int grid_sas = 1, grid_xap = 1;
     // profiling
     std::vector<hipEvent_t> prof_ev[2];  // one event pool per batch slot
@@ -921,6 +935,7 @@ static void solver_release(fk_solver S)
     dev_free(S->ap);
     dev_free(S->p2);
     dev_free(S->ap2);
+    dev_free(S->r2);
     dev_free(S->s);
     dev_free(S->as);
     dev_free(S->rs);
@@ -987,13 +1002,39 @@ static bool small_path_ok(fk_csr A, const fk_opts &o)
 {
     if (o.flags & FK_FLAG_NO_SMALL)
         return false;
-    if (o.method != FK_CG_PIPELINED && !is_bicg_pipelined(o.method))
+    if (o.method != FK_CG_PIPELINED && o.method != FK_CG_PIPELINED_1K && !is_bicg_pipelined(o.method))
         return false;
     const bool bicg = is_bicg_pipelined(o.method);
     const int rpt = small_rows_per_thread(A->n);
     if (rpt == 0 || (bicg && rpt > 2) || A->nnz > 65536 || A->long_rows > 0)
         return false;
     return small_lds_bytes(bicg, A->n) + SMALL_STATIC_LDS <= max_lds_per_workgroup(A->device);
+}
+
+// Workgroups of a fused product-and-update step (the two-kernel BiCGStab,
+// the one-kernel CG): one round of resident workgroups, at most 4 per CU
+// and never more than the product grid; on the sliced layouts sized so that
+// every wave takes the same number of slices (a wave with one slice more
+// than the others sets the launch's end).  Measured on 1024^2
+// convection-diffusion (16384 slices): the BiCGStab x, r, p, A p step holds
+// 4 workgroups per CU, and 1024 of them (4 slices per wave) beat 2048 (two
+// rounds) by 6 %; for its s, A s step (7 per CU resident) 1024 beat 1368
+// (3 slices per wave) and 2048 by 4-6 %.
+static int fused_grid(fk_csr A, int step, int grid_spmv)
+{
+    const int per_cu = std::min(fused_per_cu(A->view(), step), 4);
+    int64_t g = grid_spmv;
+    if (per_cu > 0 && A->cus > 0 && g > (int64_t)per_cu * A->cus) {
+        g = (int64_t)per_cu * A->cus;
+        const int64_t sl = A->slices();
+        if (sl > 0) {
+            const int64_t spw = (sl + (int64_t)WAVES * g - 1) / ((int64_t)WAVES * g);
+            g = (sl + (int64_t)WAVES * spw - 1) / ((int64_t)WAVES * spw);
+        }
+    }
+    if (g >= 8)
+        g = (g + 7) & ~(int64_t)7;
+    return (int)std::max<int64_t>(g, 1);
 }
 
 extern "C" fk_status fk_solver_create(fk_csr A, const fk_opts *o, void *hip_stream, fk_solver *out)
@@ -1003,7 +1044,7 @@ extern "C" fk_status fk_solver_create(fk_csr A, const fk_opts *o, void *hip_stre
     *out = nullptr;
     if (!A || !o)
         return fail(FK_E_ARG, "NULL argument");
-    if (o->method < FK_CG_PIPELINED || o->method > FK_BICGSTAB_PIPELINED_2K)
+    if (o->method < FK_CG_PIPELINED || o->method > FK_CG_PIPELINED_1K)
         return fail(FK_E_ARG, "unknown method %d", o->method);
     if (o->restart < 0 || o->restart > GM_MAX)
         return fail(FK_E_ARG, "restart outside [0, %d]", GM_MAX);
@@ -1042,30 +1083,11 @@ extern "C" fk_status fk_solver_create(fk_csr A, const fk_opts *o, void *hip_stre
     S->grid_spmv = A->spmv_grid();
     S->grid_vec = vec_grid(A->n);
     if (o->method == FK_BICGSTAB_PIPELINED_2K) {
-        // One round of resident workgroups, at most 4 per CU and never more
-        // than the product grid; on the sliced layouts sized so that every
-        // wave takes the same number of slices (a wave with one slice more
-        // than the others sets the launch's end).  Measured on 1024^2
-        // convection-diffusion (16384 slices): the xap step holds 4
-        // workgroups per CU, and 1024 of them (4 slices per wave) beat 2048
-        // (two rounds) by 6 %; for the sas step (7 per CU resident) 1024
-        // beat 1368 (3 slices per wave) and 2048 by 4-6 %.
-        for (int xap = 0; xap < 2; ++xap) {
-            const int per_cu = std::min(bicg2_per_cu(A->view(), xap != 0), 4);
-            int64_t g = S->grid_spmv;
-            if (per_cu > 0 && A->cus > 0 && g > (int64_t)per_cu * A->cus) {
-                g = (int64_t)per_cu * A->cus;
-                const int64_t sl = A->slices();
-                if (sl > 0) {
-                    const int64_t spw = (sl + (int64_t)WAVES * g - 1) / ((int64_t)WAVES * g);
-                    g = (sl + (int64_t)WAVES * spw - 1) / ((int64_t)WAVES * spw);
-                }
-            }
-            if (g >= 8)
-                g = (g + 7) & ~(int64_t)7;
-            (xap ? S->grid_xap : S->grid_sas) = (int)std::max<int64_t>(g, 1);
-        }
+        S->grid_sas = fused_grid(A, FUSED_BICG_SAS, S->grid_spmv);
+        S->grid_xap = fused_grid(A, FUSED_BICG_XAP, S->grid_spmv);
     }
+    if (o->method == FK_CG_PIPELINED_1K)
+        S->grid_xap = fused_grid(A, FUSED_CG_XAP, S->grid_spmv);
     const size_t n = (size_t)A->n;
 #define S_TRY(expr)                                                                        \
     do {                                                                                   \
@@ -1117,8 +1139,10 @@ extern "C" fk_status fk_solver_create(fk_csr A, const fk_opts *o, void *hip_stre
         S_TRY(dev_alloc(&S->as, n, "As"));
         S_TRY(dev_alloc(&S->rs, n, "r0*"));
     }
-    if (o->method == FK_BICGSTAB_PIPELINED_2K) {
+    if (o->method == FK_BICGSTAB_PIPELINED_2K || o->method == FK_CG_PIPELINED_1K) {
         S_TRY(dev_alloc(&S->p2, n, "p (second buffer)"));
+        if (o->method == FK_CG_PIPELINED_1K)
+            S_TRY(dev_alloc(&S->r2, n, "r (second buffer)"));
         S_TRY(dev_alloc(&S->ap2, n, "Ap (second buffer)"));
     }
     S_TRY(dev_alloc(&S->partials, RED_SCRATCH_DOUBLES, "partials"));
@@ -1243,7 +1267,7 @@ hipError_t enqueue_setup(fk_solver S, Enq &q, const double *b, double *x)
     hipError_t ez = launch_zero(x, n, S->st, 1u << ST_ZERO_RHS, gv, st);
     if (ez != hipSuccess)
         return ez;
-    if (S->o.method == FK_CG_PIPELINED)
+    if (S->o.method == FK_CG_PIPELINED || S->o.method == FK_CG_PIPELINED_1K)
         ENQ(FK_KERNEL_SPMV_DOT, launch_spmv_dots(A, S->p, S->ap, nullptr, D_YV | D_YY,
                                                  S->red(FIN_CG_ALPHA, RUN_ACTIVE), gs, st));
     if (S->o.method == FK_CG_PIPELINED_SPLIT) {
@@ -1277,6 +1301,13 @@ hipError_t enqueue_iteration(fk_solver S, Enq &q, double *x, bool last)
         ENQ(FK_KERNEL_SPMV_DOT, launch_spmv_dots(A, S->p, S->ap, nullptr, D_YV | D_YY,
                                                  S->red_fold(FIN_CG_RR_ALPHA, RUN_ACTIVE, gv, 1), gs, st));
         break;
+    case FK_CG_PIPELINED_1K: {
+        // x, r, p of iteration i and A p_i + <p_i,Ap_i>, <Ap_i,Ap_i>, <r_i,r_i>
+        // in one launch: convergence on r_i, then alpha_i, beta_i.
+        const Cg1Io io{x, {S->r, S->r2}, {S->p, S->p2}, {S->ap, S->ap2}};
+        ENQ(FK_KERNEL_SPMV_DOT, launch_cg1_xap(A, io, S->red(FIN_CG_RR_ALPHA, RUN_ACTIVE), S->grid_xap, st));
+        break;
+    }
     case FK_CG_PIPELINED_SPLIT:
         // Section 3.1's alternative: the product and its two dots in separate
         // kernels (3 launches, one more pass over p and A p).

@@ -194,6 +194,8 @@ struct DevCsr {
     // matrix and the vectors of an iteration exceed the Infinity Cache, so
     // the matrix comes from HBM every launch anyway); 0: ordinary loads.
     int32_t stream;
+    // Sliced layouts: the most entries (or slots) per row of any slice.
+    int32_t max_width;
 };
 
 // Column forms of the sliced products.
@@ -239,8 +241,18 @@ struct Bicg2Io {
     double *ap[2];
 };
 hipError_t launch_bicg2_sas(const DevCsr &A, const Bicg2Io &io, const RedArgs &red, int grid, hipStream_t s);
-// Workgroups of the sas (xap = false) or xap step resident per compute unit.
-int bicg2_per_cu(const DevCsr &A, bool xap);
+// CG in one kernel per iteration: the x, r, p update of iteration i folded
+// into A p_i (r, p, A p in two buffers each, by the parity of the count).
+struct Cg1Io {
+    double *x;
+    double *r[2];
+    double *p[2];
+    double *ap[2];
+};
+hipError_t launch_cg1_xap(const DevCsr &A, const Cg1Io &io, const RedArgs &red, int grid, hipStream_t s);
+// Workgroups of a fused step resident per compute unit.
+enum FusedStep : int { FUSED_BICG_SAS = 0, FUSED_BICG_XAP = 1, FUSED_CG_XAP = 2 };
+int fused_per_cu(const DevCsr &A, int step);
 hipError_t launch_bicg2_xap(const DevCsr &A, const Bicg2Io &io, const RedArgs &red, int grid, hipStream_t s);
 // Classical (unfused) building blocks.
 // <a,b> (ndots 1); <a,b>, <a,c> (2); <a,b>, <a,c>, <a,e> (3).

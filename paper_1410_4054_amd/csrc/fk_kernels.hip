@@ -1311,6 +1311,18 @@ __global__ __launch_bounds__(WG) void k_gather_vals(int64_t n, double *__restric
 // a decision (half step, converged, budget, breakdown) the xap launch only
 // finishes x and r, and its own reduction ends the solve (FIN_B_XRP_PUB).
 
+#ifndef FK_FUSED_MIN_WAVES
+#define FK_FUSED_MIN_WAVES 4
+#endif
+// Entries of a row requested together by the fused products (each entry
+// gathers two or four vectors).
+#ifndef FK_FUSED_UNROLL
+#define FK_FUSED_UNROLL 5
+#endif
+#ifndef FK_FUSED_UNROLL_CG
+#define FK_FUSED_UNROLL_CG 7
+#endif
+
 // s_i = r_i - alpha_i A p_i, as k_bicg_s writes it.
 struct VecS {
     const double *__restrict__ r;
@@ -1337,6 +1349,7 @@ struct VecP {
 // The s, A s step: own-row inputs, loaded before the row sum.
 struct BicgSas {
     static constexpr int K = 4;
+    static constexpr int U = FK_FUSED_UNROLL;  // entries requested together (two gathers each)
     Bicg2Io io;
     VecS src;
     struct Own {
@@ -1357,6 +1370,7 @@ struct BicgSas {
 // The x, r, p, A p step.
 struct BicgXap {
     static constexpr int K = 3;
+    static constexpr int U = FK_FUSED_UNROLL;  // (four gathers each)
     Bicg2Io io;
     VecP src;
     double alpha;
@@ -1381,6 +1395,67 @@ struct BicgXap {
         dd_fma(acc[2], ri, ri);
     }
 };
+
+// CG in one kernel per iteration (Algorithm 2): the x, r, p update of
+// iteration i folded into the product A p_i the same way.  The product
+// recomputes p_i = (r_{i-1} - alpha A p_{i-1}) + beta p_{i-1} at every
+// gathered column, as k_cg_update writes it.
+struct VecCgP {
+    const double *__restrict__ r;
+    const double *__restrict__ ap;
+    const double *__restrict__ p;
+    double alpha, beta;
+    __device__ __forceinline__ double at(int c) const
+    {
+        const double ri = r[c] - alpha * ap[c];
+        return ri + beta * p[c];
+    }
+};
+
+// UW: entries requested together (three gathers each): 5 for slices of at
+// most 5 entries per row (2D 5-point stencils, one chunk with nothing
+// wasted), else 7 (the 7-point stencil in one chunk).
+template <int UW>
+struct CgXap {
+    static constexpr int K = 3;
+    static constexpr int U = UW;
+    Cg1Io io;
+    VecCgP src;
+    double *__restrict__ r_new;
+    double *__restrict__ p_new;
+    double *__restrict__ ap_new;
+    struct Own {
+        double x, r, p, ap;
+    };
+    __device__ __forceinline__ Own load(int srow) const
+    {
+        return Own{io.x[srow], src.r[srow], src.p[srow], src.ap[srow]};
+    }
+    // {<p_i,Ap_i>, <Ap_i,Ap_i>, <r_i,r_i>}, the dots of FIN_CG_RR_ALPHA
+    __device__ __forceinline__ void row(int row, double q, const Own &o, dd (&acc)[K]) const
+    {
+        io.x[row] = o.x + src.alpha * o.p;
+        const double ri = o.r - src.alpha * o.ap;
+        r_new[row] = ri;
+        const double pi = ri + src.beta * o.p;
+        p_new[row] = pi;
+        ap_new[row] = q;
+        dd_fma(acc[0], q, pi);
+        dd_fma(acc[1], q, q);
+        dd_fma(acc[2], ri, ri);
+    }
+};
+
+// r_{i-1}, p_{i-1}, A p_{i-1} sit in buffer (i-1) & 1 and r_i, p_i, A p_i go
+// to i & 1 (all three are gathered while the launch writes the new ones);
+// the device's count holds i - 1 when the launch starts.
+template <int UW>
+__device__ __forceinline__ CgXap<UW> cg_xap_of(const Cg1Io &io, const DevState *st)
+{
+    const int old = st->it & 1, nw = (st->it + 1) & 1;
+    return CgXap<UW>{io, VecCgP{io.r[old], io.ap[old], io.p[old], st->alpha, st->beta}, io.r[nw], io.p[nw],
+                     io.ap[nw]};
+}
 
 // The step's policy from the solver state: the buffers of p_i, A p_i by the
 // parity of the iteration count and the scalars of the last reductions.
@@ -1427,14 +1502,6 @@ __device__ void bicg2_finish(const Bicg2Io &io, int64_t n, const RedArgs &red)
     reduce_point<2>(acc, rd, blockIdx.x, gridDim.x);
 }
 
-#ifndef FK_FUSED_MIN_WAVES
-#define FK_FUSED_MIN_WAVES 4
-#endif
-// Entries of a row requested together by the fused products (each entry
-// gathers two or four vectors).
-#ifndef FK_FUSED_UNROLL
-#define FK_FUSED_UNROLL 5
-#endif
 
 // A fused step on the sliced layouts: one wave per slice, one lane per row,
 // as k_sell_rows.
@@ -1458,7 +1525,7 @@ __device__ __forceinline__ void sell_fused(const DevCsr &A, const POL &pol, cons
         double q = 0.0;
         if (width > 0) {
             // (16-bit offsets come four to a load)
-            constexpr int U = COLS == COLS_OFF16 ? (FK_FUSED_UNROLL + 3) / 4 * 4 : FK_FUSED_UNROLL;
+            constexpr int U = COLS == COLS_OFF16 ? (POL::U + 3) / 4 * 4 : POL::U;
             const SliceCols<COLS> cols = slice_cols_of<COLS>(A, sl, e0, lane, row);
             q = slice_row_sum<double, U, COLS, NT>(cols, A.sell_vals + e0 + lane, pol.src, width);
         }
@@ -1573,6 +1640,21 @@ __global__ __launch_bounds__(WG, FK_FUSED_MIN_WAVES) void k_csr_bicg_xap(DevCsr 
         return;
     }
     csr_fused<BicgXap>(A, bicg_xap_of(io, red.st), red);
+}
+
+template <int COLS, bool NT, int UW>
+__global__ __launch_bounds__(WG, FK_FUSED_MIN_WAVES) void k_sell_cg_xap(DevCsr A, Cg1Io io, RedArgs red)
+{
+    if (!runs(red))
+        return;
+    sell_fused<CgXap<UW>, COLS, NT>(A, cg_xap_of<UW>(io, red.st), red);
+}
+
+__global__ __launch_bounds__(WG, FK_FUSED_MIN_WAVES) void k_csr_cg_xap(DevCsr A, Cg1Io io, RedArgs red)
+{
+    if (!runs(red))
+        return;
+    csr_fused<CgXap<FK_FUSED_UNROLL_CG>>(A, cg_xap_of<FK_FUSED_UNROLL_CG>(io, red.st), red);
 }
 
 // --------------------------------------------------- fused vector updates
@@ -2701,24 +2783,70 @@ static hipError_t launch_bicg2_sell(const DevCsr &A, const Bicg2Io &io, const Re
 
 // Workgroups of one fused step resident per compute unit (the occupancy of
 // the kernel its launch would take), 0 when the query fails.
-int bicg2_per_cu(const DevCsr &A, bool xap)
+template <typename KS, typename KC>
+static int fused_occupancy(const DevCsr &A, KS sell_slots, KS sell_off16, KS sell_int32, KC csr)
 {
     int n = 0;
     hipError_t e;
-    const bool nt = A.stream != 0;
-    auto q = [&](auto kern) { return hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, kern, WG, 0); };
     if (A.nslices > 0 && A.dg_mask)
-        e = xap ? (nt ? q(k_sell_bicg_xap<COLS_SLOTS, true>) : q(k_sell_bicg_xap<COLS_SLOTS, false>))
-                : (nt ? q(k_sell_bicg_sas<COLS_SLOTS, true>) : q(k_sell_bicg_sas<COLS_SLOTS, false>));
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, sell_slots, WG, 0);
     else if (A.nslices > 0 && A.sell_off4)
-        e = xap ? (nt ? q(k_sell_bicg_xap<COLS_OFF16, true>) : q(k_sell_bicg_xap<COLS_OFF16, false>))
-                : (nt ? q(k_sell_bicg_sas<COLS_OFF16, true>) : q(k_sell_bicg_sas<COLS_OFF16, false>));
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, sell_off16, WG, 0);
     else if (A.nslices > 0)
-        e = xap ? (nt ? q(k_sell_bicg_xap<COLS_INT32, true>) : q(k_sell_bicg_xap<COLS_INT32, false>))
-                : (nt ? q(k_sell_bicg_sas<COLS_INT32, true>) : q(k_sell_bicg_sas<COLS_INT32, false>));
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, sell_int32, WG, 0);
     else
-        e = xap ? q(k_csr_bicg_xap) : q(k_csr_bicg_sas);
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, csr, WG, 0);
     return e == hipSuccess ? n : 0;
+}
+
+int fused_per_cu(const DevCsr &A, int step)
+{
+    const bool nt = A.stream != 0;
+    switch (step) {
+    case FUSED_BICG_SAS:
+        return nt ? fused_occupancy(A, k_sell_bicg_sas<COLS_SLOTS, true>, k_sell_bicg_sas<COLS_OFF16, true>,
+                                    k_sell_bicg_sas<COLS_INT32, true>, k_csr_bicg_sas)
+                  : fused_occupancy(A, k_sell_bicg_sas<COLS_SLOTS, false>, k_sell_bicg_sas<COLS_OFF16, false>,
+                                    k_sell_bicg_sas<COLS_INT32, false>, k_csr_bicg_sas);
+    case FUSED_BICG_XAP:
+        return nt ? fused_occupancy(A, k_sell_bicg_xap<COLS_SLOTS, true>, k_sell_bicg_xap<COLS_OFF16, true>,
+                                    k_sell_bicg_xap<COLS_INT32, true>, k_csr_bicg_xap)
+                  : fused_occupancy(A, k_sell_bicg_xap<COLS_SLOTS, false>, k_sell_bicg_xap<COLS_OFF16, false>,
+                                    k_sell_bicg_xap<COLS_INT32, false>, k_csr_bicg_xap);
+    case FUSED_CG_XAP:
+        if (A.max_width <= 5)
+            return nt ? fused_occupancy(A, k_sell_cg_xap<COLS_SLOTS, true, 5>, k_sell_cg_xap<COLS_OFF16, true, 5>,
+                                        k_sell_cg_xap<COLS_INT32, true, 5>, k_csr_cg_xap)
+                      : fused_occupancy(A, k_sell_cg_xap<COLS_SLOTS, false, 5>, k_sell_cg_xap<COLS_OFF16, false, 5>,
+                                        k_sell_cg_xap<COLS_INT32, false, 5>, k_csr_cg_xap);
+        return nt ? fused_occupancy(A, k_sell_cg_xap<COLS_SLOTS, true, 7>, k_sell_cg_xap<COLS_OFF16, true, 7>,
+                                    k_sell_cg_xap<COLS_INT32, true, 7>, k_csr_cg_xap)
+                  : fused_occupancy(A, k_sell_cg_xap<COLS_SLOTS, false, 7>, k_sell_cg_xap<COLS_OFF16, false, 7>,
+                                    k_sell_cg_xap<COLS_INT32, false, 7>, k_csr_cg_xap);
+    default:
+        return 0;
+    }
+}
+
+template <bool NT, int UW>
+static hipError_t launch_cg1_sell(const DevCsr &A, const Cg1Io &io, const RedArgs &red, int grid, hipStream_t s)
+{
+    if (A.dg_mask)
+        return launch(k_sell_cg_xap<COLS_SLOTS, NT, UW>, grid, WG, s, A, io, red);
+    if (A.sell_off4)
+        return launch(k_sell_cg_xap<COLS_OFF16, NT, UW>, grid, WG, s, A, io, red);
+    return launch(k_sell_cg_xap<COLS_INT32, NT, UW>, grid, WG, s, A, io, red);
+}
+
+// Measured on 2D Poisson 511^2 (5 entries per row): 5 entries per chunk
+// 63,500 iterations/s against 57,500 with 7; on 3D 128^3 (7) the reverse.
+hipError_t launch_cg1_xap(const DevCsr &A, const Cg1Io &io, const RedArgs &red, int grid, hipStream_t s)
+{
+    if (A.nslices > 0 && A.max_width <= 5)
+        return A.stream ? launch_cg1_sell<true, 5>(A, io, red, grid, s) : launch_cg1_sell<false, 5>(A, io, red, grid, s);
+    if (A.nslices > 0)
+        return A.stream ? launch_cg1_sell<true, 7>(A, io, red, grid, s) : launch_cg1_sell<false, 7>(A, io, red, grid, s);
+    return launch(k_csr_cg_xap, grid, WG, s, A, io, red);
 }
 
 hipError_t launch_bicg2_sas(const DevCsr &A, const Bicg2Io &io, const RedArgs &red, int grid, hipStream_t s)

@@ -25,10 +25,11 @@ STATUS_NAMES = {
 # fk_method
 METHODS = {"cg_pipelined": 0, "cg_classical": 1, "bicgstab_pipelined": 2, "bicgstab_classical": 3,
            "cg_mixed": 4, "gmres_pipelined": 5, "gmres_classical": 6, "cg_mixed_f32": 7,
-           "cg_pipelined_split": 8, "bicgstab_pipelined_split": 9, "bicgstab_pipelined_2k": 10}
+           "cg_pipelined_split": 8, "bicgstab_pipelined_split": 9, "bicgstab_pipelined_2k": 10,
+           "cg_pipelined_1k": 11}
 # methods that record per-iteration scalars (alpha, beta, omega, <r,r>)
 SCALAR_METHODS = ("cg_pipelined", "cg_classical", "bicgstab_pipelined", "bicgstab_classical",
-                  "cg_pipelined_split", "bicgstab_pipelined_split", "bicgstab_pipelined_2k")
+                  "cg_pipelined_split", "bicgstab_pipelined_split", "bicgstab_pipelined_2k", "cg_pipelined_1k")
 FLAG_GRAPH = 1
 FLAG_PROFILE = 2
 FLAG_NO_SMALL = 4

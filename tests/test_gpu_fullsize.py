@@ -17,11 +17,14 @@ pytestmark = pytest.mark.gpu
 NAMES = ["poisson3d_128_cg_pipelined", "poisson3d_128_cg_classical",
          "poisson3d_128_cg_pipelined_30", "convdiff2d_1024_bicgstab_pipelined",
          "convdiff2d_1024_bicgstab_pipelined_30"]
-# (stored case, GPU method): the two-kernel schedule of Algorithm 4 must
-# reproduce the same stored iterates as the four-kernel one.
+# (stored case, GPU method): the two-kernel schedule of Algorithm 4 and the
+# one-kernel schedule of Algorithm 2 must reproduce the stored iterates of
+# the schedules the oracle's values were written for.
 CASES = [(name, None) for name in NAMES] + \
         [("convdiff2d_1024_bicgstab_pipelined", "bicgstab_pipelined_2k"),
-         ("convdiff2d_1024_bicgstab_pipelined_30", "bicgstab_pipelined_2k")]
+         ("convdiff2d_1024_bicgstab_pipelined_30", "bicgstab_pipelined_2k"),
+         ("poisson3d_128_cg_pipelined", "cg_pipelined_1k"),
+         ("poisson3d_128_cg_pipelined_30", "cg_pipelined_1k")]
 _inputs = {}
 
 

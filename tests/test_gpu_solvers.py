@@ -15,15 +15,16 @@ from paper_1410_4054_amd import fk, problems as P
 
 pytestmark = pytest.mark.gpu
 
-CG = ["cg_pipelined", "cg_classical"]
+CG = ["cg_pipelined", "cg_classical", "cg_pipelined_1k"]
 BICG = ["bicgstab_pipelined", "bicgstab_classical", "bicgstab_pipelined_2k"]
 ALL = CG + BICG
 
 
 def oracle_method(method):
     """The oracle's method for a GPU method: the two-kernel schedule of
-    Algorithm 4 computes the four-kernel schedule's iterates."""
-    return {"bicgstab_pipelined_2k": "bicgstab_pipelined"}.get(method, method)
+    Algorithm 4 computes the four-kernel schedule's iterates, the one-kernel
+    schedule of Algorithm 2 the two-kernel one's."""
+    return {"bicgstab_pipelined_2k": "bicgstab_pipelined", "cg_pipelined_1k": "cg_pipelined"}.get(method, method)
 
 
 def _random_nonsym(n, seed):

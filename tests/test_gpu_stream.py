@@ -68,6 +68,8 @@ def test_stream_products_ragged(n, device):
 
 
 @pytest.mark.parametrize("wl,method", [("poisson3d_24", "cg_pipelined"), ("poisson3d_24", "cg_classical"),
+                                       ("poisson3d_24", "cg_pipelined_1k"),
+                                       ("convdiff2d_64", "bicgstab_pipelined_2k"),
                                        ("convdiff2d_64", "bicgstab_pipelined"),
                                        ("convdiff2d_64", "bicgstab_pipelined_split"),
                                        ("poisson3d_24", "cg_mixed"), ("poisson3d_24", "cg_mixed_f32")])
@@ -95,7 +97,8 @@ def test_stream_solves_match_normal(wl, method, device):
     assert np.array_equal(x0, x1)
     assert np.array_equal(r0.history, r1.history)
     if "mixed" not in method:
-        ref = oracle.solve(A, b, method=method.replace("_split", ""), rtol=rtol, trace=True)
+        base = method.replace("_split", "").replace("_2k", "").replace("_1k", "")
+        ref = oracle.solve(A, b, method=base, rtol=rtol, trace=True)
         assert r1.k == ref.k
         assert rel(x1, ref.x) <= 1e-10
 
