@@ -732,6 +732,14 @@ def main():
                 r, _ = T.run(pol, net=net, passes=W.RECIPE["passes"])
                 extras[f"heat512_400steps_{pol}_total_cg_iterations"] = r.total_iterations
                 extras[f"heat512_400steps_{pol}_solves_per_s"] = r.solves_per_s
+            del T
+            # the same steps with CG in one kernel per iteration (same iterates)
+            T = W.Transient(512, 0, method="cg_pipelined_1k")
+            for pol in W.POLICIES:
+                T.run(pol, net=net, passes=W.RECIPE["passes"])
+                r, _ = T.run(pol, net=net, passes=W.RECIPE["passes"])
+                extras[f"heat512_400steps_{pol}_cg1k_total_cg_iterations"] = r.total_iterations
+                extras[f"heat512_400steps_{pol}_cg1k_solves_per_s"] = r.solves_per_s
             net.close()
             del T
 

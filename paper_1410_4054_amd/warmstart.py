@@ -46,7 +46,9 @@ class Transient:
     """One transient problem resident on the device."""
 
     def __init__(self, n: int = 512, seed: int = 0, steps: int = 400, rtol: float = 1e-8,
-                 unroll: int = 4, device: str = "cuda"):
+                 unroll: int = 4, device: str = "cuda", method: str = "cg_pipelined"):
+        """method: the CG schedule that solves each step ("cg_pipelined", two
+        kernels per iteration, or "cg_pipelined_1k", one; same iterates)."""
         import torch
 
         A, u0, source = P.heat_transient(n, seed, steps)
@@ -62,7 +64,8 @@ class Transient:
         for m in range(1, steps + 1):
             self.sources[m - 1].copy_(torch.as_tensor(source(m)))
         self.unroll = unroll
-        self.solver = fk.Solver(self.M, method="cg_pipelined", rtol=rtol, record_history=False,
+        self.method = method
+        self.solver = fk.Solver(self.M, method=method, rtol=rtol, record_history=False,
                                 unroll=unroll, small=False)
         self.device = device
 
@@ -78,7 +81,7 @@ class Transient:
             raise ValueError("the learned policy needs a network")
         solver = self.solver
         if rtol is not None and rtol != self.rtol:
-            solver = fk.Solver(self.M, method="cg_pipelined", rtol=rtol, record_history=False,
+            solver = fk.Solver(self.M, method=self.method, rtol=rtol, record_history=False,
                                unroll=self.unroll, small=False)
         N = self.N
         traj = torch.empty((self.steps + 1, N), dtype=torch.float64, device=self.device) if keep else None
