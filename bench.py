@@ -570,8 +570,9 @@ def main():
         # The x-axis of the paper's Fig. 4: time per iteration (median of 10
         # runs of 30 fixed iterations) of the pipelined and classical
         # methods, and of the one-kernel CG and two-kernel BiCGStab
-        # schedules.  Pipelined solves of up to 8192 (CG) / 2048 (BiCGStab)
-        # unknowns run in the single-workgroup kernel.
+        # schedules.  Pipelined solves of up to 4096 (CG; 3072 for the
+        # one-kernel CG) / 2048 (BiCGStab) unknowns run in the
+        # single-workgroup kernel.
         sweep = {}
         for nn in (15, 31, 63, 127, 255, 511):
             As, bs, _ = P.workload(f"poisson2d_{nn}")

@@ -243,7 +243,8 @@ fk_status fk_csr_stream(fk_csr A, int32_t *streaming, int32_t *sweep);
  * tolerances or unknown flags; FK_E_OOM when an allocation fails (nothing is
  * left allocated).
  *
- * Pipelined solves of small systems (n <= 8192 for CG, n <= 2048 for
+ * Pipelined solves of small systems (n <= 4096 for CG, 3072 for the
+ * one-kernel CG, n <= 2048 for
  * BiCGStab, nnz <= 65536, no row longer than FK_LONG_ROW, vectors fitting
  * the device's LDS) run as one single-workgroup kernel per solve, whose
  * iterates equal those of the multi-kernel path; FK_FLAG_NO_SMALL disables

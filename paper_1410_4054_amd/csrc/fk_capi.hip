@@ -1008,6 +1008,14 @@ static bool small_path_ok(fk_csr A, const fk_opts &o)
     const int rpt = small_rows_per_thread(A->n);
     if (rpt == 0 || (bicg && rpt > 2) || A->nnz > 65536 || A->long_rows > 0)
         return false;
+    // Where the grid kernels overtake one workgroup (2D Poisson, 30 fixed
+    // iterations, us per iteration, one workgroup / grid): two-kernel CG
+    // 12.2 / 15.0 at n = 3,969, 16.2 / 16.6 at 6,400, 18.8 / 14.8 at 8,100;
+    // one-kernel CG 9.8 / 11.4 at 2,500, 12.3 / 11.7 at 3,969.
+    if (o.method == FK_CG_PIPELINED && A->n > 4096)
+        return false;
+    if (o.method == FK_CG_PIPELINED_1K && A->n > 3072)
+        return false;
     return small_lds_bytes(bicg, A->n) + SMALL_STATIC_LDS <= max_lds_per_workgroup(A->device);
 }
 

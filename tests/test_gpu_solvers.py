@@ -236,7 +236,7 @@ def test_small_path_selection(device):
     S = fk.Solver(M, method="cg_pipelined", small=False)
     assert not S.uses_small()
     S.close()
-    big = fk.Matrix(P.workload("poisson3d_24")[0])  # n = 13824 > 8192
+    big = fk.Matrix(P.workload("poisson3d_24")[0])  # n = 13824 > 4096
     S = fk.Solver(big, method="cg_pipelined")
     assert not S.uses_small()
     S.close()
@@ -253,16 +253,20 @@ def test_small_path_selection(device):
         S.close()
 
 
-@pytest.mark.parametrize("n,method", [(90, "cg_pipelined"), (60, "cg_pipelined"), (45, "cg_pipelined"),
-                                      (2, "cg_pipelined"), (40, "bicgstab_pipelined"),
-                                      (31, "bicgstab_pipelined")])
-def test_small_path_rows_per_thread(n, method, device):
-    """1, 2, 4 and 8 rows per thread of the single-workgroup solver."""
+@pytest.mark.parametrize("n,method,small", [(90, "cg_pipelined", False), (64, "cg_pipelined", True),
+                                            (60, "cg_pipelined", True), (45, "cg_pipelined", True),
+                                            (2, "cg_pipelined", True), (55, "cg_pipelined_1k", True),
+                                            (56, "cg_pipelined_1k", False), (40, "bicgstab_pipelined", True),
+                                            (31, "bicgstab_pipelined", True)])
+def test_small_path_rows_per_thread(n, method, small, device):
+    """1, 2 and 4 rows per thread of the single-workgroup solver, and the
+    sizes where the grid kernels take over (n > 4096 for the two-kernel
+    CG, n > 3072 for the one-kernel CG)."""
     A = P.poisson2d(n) if method.startswith("cg") else P.convdiff2d(n)
     b = P.rhs_uniform(A.n, 7)
     ref = oracle.solve(A, b, method=oracle_method(method), rtol=1e-9)
     res, x = gpu_solve(A, b, method=method, rtol=1e-9)
-    assert fk.Solver(fk.Matrix(A), method=method).uses_small()
+    assert fk.Solver(fk.Matrix(A), method=method).uses_small() is small
     assert_same_run(res, x, ref, f"n={n}")
 
 
