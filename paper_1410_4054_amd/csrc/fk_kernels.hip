@@ -698,13 +698,7 @@ struct AccF32 {
     using T = float;
     __device__ static T zero() { return 0.0f; }
     __device__ static T add(T a, T b) { return a + b; }
-    __device__ static T wave(T v)
-    {
-#pragma unroll
-        for (int off = 32; off >= 1; off >>= 1)
-            v = v + __shfl_xor(v, off, 64);
-        return v;
-    }
+    __device__ static T wave(T v) { return wave_sum(v); }
     __device__ static void store(double *slot, T v) { store_coherent(slot, (double)v); }
     __device__ static T load(const double *slot) { return (float)load_coherent(slot); }
     __device__ static bool take(const double *slot, T &out)
