@@ -755,6 +755,14 @@ __device__ __forceinline__ void reduce_point(typename ACC::T (&v)[K], const RedA
     const int gbase = grp * RGROUP;
     const int gsize = min(RGROUP, G - gbase);
 
+    // The workgroup that runs finalize asks for the state's lines now, so
+    // that they are in its XCD's L2 when finalize reads them (the matrix
+    // stream has long evicted them since the kernel read the status).
+    double state_line = 0.0;
+    const bool finalizer = g == G - 1 && wave == 0 && red.fin != FIN_PUBLISH;
+    if (finalizer && lane < (int)(sizeof(DevState) / 128))
+        state_line = ((const double *)red.st)[16 * lane];
+
 #pragma unroll
     for (int k = 0; k < K; ++k)
         v[k] = ACC::wave(v[k]);
@@ -817,15 +825,11 @@ __device__ __forceinline__ void reduce_point(typename ACC::T (&v)[K], const RedA
             }
         }
     }
+    // (slots past kt hold zero in every lane: no sum to form)
 #pragma unroll
     for (int k = 0; k < KT; ++k)
-        acc[k] = ACC::wave(acc[k]);
-    // the members' slots are free again for the next launch
-    if (lane < gsize && lane != own) {
-#pragma unroll
-        for (int k = 0; k < K; ++k)
-            ACC::clear(part1 + 2 * ((size_t)k * GMAX + gbase + lane));
-    }
+        if (k < kt)
+            acc[k] = ACC::wave(acc[k]);
     if (ngroups > 1) {
         const int top = ngroups - 1;
         if (grp != top) {
@@ -842,6 +846,12 @@ __device__ __forceinline__ void reduce_point(typename ACC::T (&v)[K], const RedA
                     red.st->status = ST_BREAKDOWN;
                 }
             }
+            // the members' slots are free again for the next launch
+            if (lane < gsize && lane != own) {
+#pragma unroll
+                for (int k = 0; k < K; ++k)
+                    ACC::clear(part1 + 2 * ((size_t)k * GMAX + gbase + lane));
+            }
             return;
         }
         // Leader of the last group: collect the group sums.
@@ -849,13 +859,21 @@ __device__ __forceinline__ void reduce_point(typename ACC::T (&v)[K], const RedA
         done = collect<KT, ACC>(part2, RNGROUPS_MAX, ngroups, top, acc, sums) && done;
 #pragma unroll
         for (int k = 0; k < KT; ++k)
-            acc[k] = ACC::wave(sums[k]);
+            if (k < kt)
+                acc[k] = ACC::wave(sums[k]);
         if (lane < top) {
 #pragma unroll
             for (int k = 0; k < KT; ++k)
                 ACC::clear(part2 + 2 * ((size_t)k * RNGROUPS_MAX + lane));
         }
     }
+    // the members' slots (of the last group) are free again
+    if (lane < gsize && lane != own) {
+#pragma unroll
+        for (int k = 0; k < K; ++k)
+            ACC::clear(part1 + 2 * ((size_t)k * GMAX + gbase + lane));
+    }
+    asm volatile("" ::"v"(state_line));
     if (lane == 0) {
         if (!done) {
             red.st->red_fault = 1;
