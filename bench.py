@@ -192,6 +192,15 @@ def case_bytes(method: str, n: int, nnz: int, matrix_bytes: int) -> dict:
             # x, r, p update 72 N
             k = {"spmv_dot": m + 24 * n, "update_dot": (24 * n + 72 * n) / 2}
             it = 2 * m + 48 * n + 24 * n + 72 * n
+        elif method == "bicgstab_pipelined_2k":
+            # s, A s step: r, A p, r0* read, A s written; x, r, p, A p step:
+            # x, r, A s, p, A p, r0* read, x, r, p, A p written
+            k = {"spmv_dot": m + 32 * n, "update_dot": m + 80 * n}
+            it = 2 * m + 112 * n
+        elif method == "cg_pipelined_1k":
+            # x, r, p, A p read and written once
+            k = {"spmv_dot": m + 64 * n}
+            it = m + 64 * n
         else:
             k, it = {}, None
         out[tag] = {"kernels": k, "iteration": it}
@@ -483,11 +492,11 @@ def main():
         # matrix, each array read once: two products (12 nnz + 4 (N + 1) of
         # matrix data and 24 N of vectors each), the s update (24 N) and the
         # x, r, p update (72 N): 24 nnz + 152 N + 8.  The two-kernel
-        # schedule moves 24 nnz + 128 N + 8 of them (its products read r, A p
-        # and p, A p where the four-kernel one reads s and p).
+        # schedule moves 24 nnz + 120 N + 8 (it never stores s; its products
+        # read r, A p and p, A p where the four-kernel one reads s and p).
         bicg_b = 24 * A3.nnz + 152 * A3.n + 8
         moved = {"bicgstab_pipelined": 2 * M3.matrix_bytes() + 144 * A3.n,
-                 "bicgstab_pipelined_2k": 2 * M3.matrix_bytes() + 120 * A3.n}
+                 "bicgstab_pipelined_2k": 2 * M3.matrix_bytes() + 112 * A3.n}
         extras["bicgstab_convdiff2d_1024_iteration_algorithmic_bytes"] = bicg_b
         for method, tag in (("bicgstab_pipelined", "bicgstab"), ("bicgstab_pipelined_2k", "bicgstab_2k")):
             S3 = fk.Solver(M3, method=method, rtol=RTOL, record_history=False)

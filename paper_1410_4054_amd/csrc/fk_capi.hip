@@ -865,8 +865,8 @@ struct fk_solver_s {
     hipStream_t stream = nullptr;
     int64_t n = 0;
     double *r = nullptr, *p = nullptr, *ap = nullptr, *s = nullptr, *as = nullptr, *rs = nullptr;
-    // FK_BICGSTAB_PIPELINED_2K: the second buffers of p and A p;
-    // FK_CG_PIPELINED_1K: of r, p and A p
+    // FK_BICGSTAB_PIPELINED_2K and FK_CG_PIPELINED_1K: the second buffers
+    // of r, p and A p
     double *p2 = nullptr, *ap2 = nullptr, *r2 = nullptr;
     double *partials = nullptr, *hist = nullptr, *scal = nullptr;
     DevState *st = nullptr;
@@ -1143,14 +1143,14 @@ extern "C" fk_status fk_solver_create(fk_csr A, const fk_opts *o, void *hip_stre
         S_TRY(dev_alloc(&S->ap, n, "Ap"));
     }
     if (is_bicg(o->method)) {
-        S_TRY(dev_alloc(&S->s, n, "s"));
+        if (o->method != FK_BICGSTAB_PIPELINED_2K)  // (which never stores s)
+            S_TRY(dev_alloc(&S->s, n, "s"));
         S_TRY(dev_alloc(&S->as, n, "As"));
         S_TRY(dev_alloc(&S->rs, n, "r0*"));
     }
     if (o->method == FK_BICGSTAB_PIPELINED_2K || o->method == FK_CG_PIPELINED_1K) {
         S_TRY(dev_alloc(&S->p2, n, "p (second buffer)"));
-        if (o->method == FK_CG_PIPELINED_1K)
-            S_TRY(dev_alloc(&S->r2, n, "r (second buffer)"));
+        S_TRY(dev_alloc(&S->r2, n, "r (second buffer)"));
         S_TRY(dev_alloc(&S->ap2, n, "Ap (second buffer)"));
     }
     S_TRY(dev_alloc(&S->partials, RED_SCRATCH_DOUBLES, "partials"));
@@ -1364,7 +1364,7 @@ hipError_t enqueue_iteration(fk_solver S, Enq &q, double *x, bool last)
         // omega_i, beta_i, decision on i+1); then x, r, p of iteration i+1
         // and A p_{i+1} (+ <Ap,r0*>, <r,r0*>, <r,r>: rho, alpha), or, after
         // a decision, the last x, r and the final reduction.
-        const Bicg2Io io{x, S->r, S->s, S->as, S->rs, {S->p, S->p2}, {S->ap, S->ap2}};
+        const Bicg2Io io{x, {S->r, S->r2}, S->as, S->rs, {S->p, S->p2}, {S->ap, S->ap2}};
         ENQ(FK_KERNEL_SPMV_DOT, launch_bicg2_sas(A, io, S->red(FIN_B_SS_OMEGA, RUN_ACTIVE), S->grid_sas, st));
         ENQ(FK_KERNEL_UPDATE_DOT,
             launch_bicg2_xap(A, io, S->red(FIN_B_XRP_ALPHA, RUN_BICG_UPDATE), S->grid_xap, st));

@@ -232,10 +232,13 @@ hipError_t launch_bicg_xrp(int64_t n, double *x, double *r, double *p, const dou
                            const double *as, const double *ap, const double *rs,
                            const RedArgs &red, int grid, hipStream_t s);
 // The two-kernel BiCGStab iteration (updates folded into the products; see
-// fk_kernels.hip): the vectors, with p_i and A p_i in two buffers each,
-// selected by the parity of the device's iteration count.
+// fk_kernels.hip): the vectors, with r_i, p_i and A p_i in two buffers
+// each, selected by the parity of the device's iteration count (s_i is
+// never stored: both steps recompute it from r_i and A p_i).
 struct Bicg2Io {
-    double *x, *r, *s, *as;
+    double *x;
+    double *r[2];
+    double *as;
     const double *rs;  // r0*
     double *p[2];
     double *ap[2];

@@ -1310,18 +1310,21 @@ __global__ __launch_bounds__(WG) void k_gather_vals(int64_t n, double *__restric
 // expression, so the product sees bitwise the vector the four-kernel
 // schedule would have stored.  Two launches per iteration instead of four,
 // one full reduction each:
-//   k_*_bicg_sas: s_i = r_i - alpha_i A p_i (stored for the own rows,
-//     recomputed at gathered columns); A s_i; <As,s>, <As,As>, <As,r0*>, <s,s>
-//     (FIN_B_SS_OMEGA: half-step test, omega_i, beta_i, expanded rr, decision);
+//   k_*_bicg_sas: s_i = r_i - alpha_i A p_i (formed for the own rows and at
+//     gathered columns, never stored); A s_i; <As,s>, <As,As>, <As,r0*>,
+//     <s,s> (FIN_B_SS_OMEGA: half-step test, omega_i, beta_i, expanded rr,
+//     decision);
 //   k_*_bicg_xap: x_{i+1}, r_{i+1} = s_i - omega_i A s_i and
-//     p_{i+1} = r_{i+1} + beta_i (p_i - omega_i A p_i) for the own rows,
-//     p_{i+1} recomputed at gathered columns; A p_{i+1}; <Ap,r0*>, <r,r0*>,
-//     <r,r> (FIN_B_XRP_ALPHA: rho_{i+1}, alpha_{i+1}).
-// The product of p_{i+1} gathers p_i and A p_i while it writes p_{i+1} and
-// A p_{i+1}, so those two alternate between two buffers by the parity of i
-// (the device's iteration count, so graph replays and batches agree).  After
-// a decision (half step, converged, budget, breakdown) the xap launch only
-// finishes x and r, and its own reduction ends the solve (FIN_B_XRP_PUB).
+//     p_{i+1} = r_{i+1} + beta_i (p_i - omega_i A p_i) for the own rows
+//     (s_i formed again from r_i and A p_i), p_{i+1} recomputed at gathered
+//     columns; A p_{i+1}; <Ap,r0*>, <r,r0*>, <r,r> (FIN_B_XRP_ALPHA:
+//     rho_{i+1}, alpha_{i+1}).
+// The product of p_{i+1} gathers r_i, p_i and A p_i while it writes r_{i+1},
+// p_{i+1} and A p_{i+1}, so those three alternate between two buffers by
+// the parity of i (the device's iteration count, so graph replays and
+// batches agree).  After a decision (half step, converged, budget,
+// breakdown) the xap launch only finishes x and r, and its own reduction
+// ends the solve (FIN_B_XRP_PUB).
 
 #ifndef FK_FUSED_MIN_WAVES
 #define FK_FUSED_MIN_WAVES 4
@@ -1343,17 +1346,18 @@ struct VecS {
     __device__ __forceinline__ double at(int c) const { return r[c] - alpha * ap[c]; }
 };
 
-// p_{i+1} = (s_i - omega_i A s_i) + beta_i (p_i - omega_i A p_i), as
-// k_bicg_xrp writes it.
+// p_{i+1} = (s_i - omega_i A s_i) + beta_i (p_i - omega_i A p_i) with
+// s_i = r_i - alpha_i A p_i, as k_bicg_s and k_bicg_xrp write them.
 struct VecP {
-    const double *__restrict__ s;
+    const double *__restrict__ r;
     const double *__restrict__ as;
     const double *__restrict__ p;
     const double *__restrict__ ap;
-    double omega, beta;
+    double alpha, omega, beta;
     __device__ __forceinline__ double at(int c) const
     {
-        const double ri = s[c] - omega * as[c];
+        const double si = r[c] - alpha * ap[c];
+        const double ri = si - omega * as[c];
         return ri + beta * (p[c] - omega * ap[c]);
     }
 };
@@ -1370,7 +1374,6 @@ struct BicgSas {
     __device__ __forceinline__ Own load(int srow) const { return Own{src.at(srow), io.rs[srow]}; }
     __device__ __forceinline__ void row(int row, double q, const Own &o, dd (&acc)[K]) const
     {
-        io.s[row] = o.s;
         io.as[row] = q;
         dd_fma(acc[0], q, o.s);
         dd_fma(acc[1], q, q);
@@ -1385,21 +1388,22 @@ struct BicgXap {
     static constexpr int U = FK_FUSED_UNROLL;  // (four gathers each)
     Bicg2Io io;
     VecP src;
-    double alpha;
+    double *__restrict__ r_new;
     double *__restrict__ p_new;
     double *__restrict__ ap_new;
     struct Own {
-        double x, s, p, as, ap, rs;
+        double x, r, p, as, ap, rs;
     };
     __device__ __forceinline__ Own load(int srow) const
     {
-        return Own{io.x[srow], src.s[srow], src.p[srow], src.as[srow], src.ap[srow], io.rs[srow]};
+        return Own{io.x[srow], src.r[srow], src.p[srow], src.as[srow], src.ap[srow], io.rs[srow]};
     }
     __device__ __forceinline__ void row(int row, double q, const Own &o, dd (&acc)[K]) const
     {
-        io.x[row] = o.x + alpha * o.p + src.omega * o.s;
-        const double ri = o.s - src.omega * o.as;
-        io.r[row] = ri;
+        const double si = o.r - src.alpha * o.ap;
+        io.x[row] = o.x + src.alpha * o.p + src.omega * si;
+        const double ri = si - src.omega * o.as;
+        r_new[row] = ri;
         p_new[row] = ri + src.beta * (o.p - src.omega * o.ap);
         ap_new[row] = q;
         dd_fma(acc[0], q, o.rs);
@@ -1474,14 +1478,15 @@ __device__ __forceinline__ CgXap<UW> cg_xap_of(const Cg1Io &io, const DevState *
 __device__ __forceinline__ BicgSas bicg_sas_of(const Bicg2Io &io, const DevState *st)
 {
     const int cur = st->it & 1;
-    return BicgSas{io, VecS{io.r, io.ap[cur], st->alpha}};
+    return BicgSas{io, VecS{io.r[cur], io.ap[cur], st->alpha}};
 }
 
+// (the s step's reduction has counted iteration i + 1 already)
 __device__ __forceinline__ BicgXap bicg_xap_of(const Bicg2Io &io, const DevState *st)
 {
     const int old = (st->it - 1) & 1, nw = st->it & 1;
-    return BicgXap{io, VecP{io.s, io.as, io.p[old], io.ap[old], st->omega, st->beta}, st->alpha, io.p[nw],
-                   io.ap[nw]};
+    return BicgXap{io, VecP{io.r[old], io.as, io.p[old], io.ap[old], st->alpha, st->omega, st->beta},
+                   io.r[nw], io.p[nw], io.ap[nw]};
 }
 
 // After a decision: x_{i+1} = x_i + alpha_i p_i and r_{i+1} = s_i (half step),
@@ -1492,19 +1497,23 @@ __device__ void bicg2_finish(const Bicg2Io &io, int64_t n, const RedArgs &red)
     const DevState *st = red.st;
     const bool half = st->status == ST_HALF;
     const double alpha = st->alpha, omega = st->omega;
-    // p_i: not yet advanced after the half step, one behind after a decision
-    const double *__restrict__ p = io.p[half ? (st->it & 1) : ((st->it - 1) & 1)];
+    // the buffers of iteration i: the count not yet advanced after the half
+    // step, one ahead after a decision
+    const int cur = half ? (st->it & 1) : ((st->it - 1) & 1);
+    const double *__restrict__ p = io.p[cur];
+    const double *__restrict__ ap = io.ap[cur];
+    double *__restrict__ r = io.r[cur];  // r_{i+1} replaces r_i element by element
     dd acc[2] = {dd{0.0, 0.0}, dd{0.0, 0.0}};
     const int64_t stride = (int64_t)gridDim.x * WG;
     for (int64_t i = (int64_t)blockIdx.x * WG + threadIdx.x; i < n; i += stride) {
+        const double si = r[i] - alpha * ap[i];
         if (half) {
             io.x[i] = io.x[i] + alpha * p[i];
-            io.r[i] = io.s[i];
+            r[i] = si;
         } else {
-            const double si = io.s[i];
             io.x[i] = io.x[i] + alpha * p[i] + omega * si;
             const double ri = si - omega * io.as[i];
-            io.r[i] = ri;
+            r[i] = ri;
             dd_fma(acc[0], ri, io.rs[i]);
             dd_fma(acc[1], ri, ri);
         }
