@@ -233,7 +233,9 @@ fk_status fk_csr_stream(fk_csr A, int32_t *streaming, int32_t *sweep);
  * Create a solver for A with options *o, bound to hip_stream.  Allocates the
  * library-owned workspace once, so fk_solve allocates nothing: the method's
  * work vectors (r, p, A p for Algorithm 2; r, r0*, p, A p, s, A s for
- * Algorithm 4: about 3n and 6n doubles), the buffer of per-workgroup
+ * Algorithm 4: about 3n and 6n doubles; the one-kernel CG and the
+ * two-kernel BiCGStab keep r, p and A p in two buffers each, the latter
+ * without s), the buffer of per-workgroup
  * partial sums that the first reduction stage writes and the second reads
  * (Section 2.2, the two-stage reduction; Section 3.1, the partial results of
  * the three inner products of an iteration in one buffer), and the device
@@ -339,7 +341,8 @@ fk_status fk_get_scalars(fk_solver S, double *out, int32_t cap, int32_t *len);
 enum {
     FK_KERNEL_SETUP = 0,       /* r0 = b - A x0 and its reductions            */
     FK_KERNEL_SPMV_DOT = 1,    /* fused CSR product + first-stage dots
-                                  (FK_BICGSTAB_PIPELINED_2K: s_i, A s_i;
+                                  (FK_BICGSTAB_PIPELINED_2K: A s_i, with s_i
+                                  formed but not stored;
                                   FK_CG_PIPELINED_1K: x, r, p and A p)       */
     FK_KERNEL_UPDATE_DOT = 2,  /* fused vector updates + first-stage dot(s)
                                   (FK_BICGSTAB_PIPELINED_2K: x, r, p, A p)    */

@@ -7,13 +7,13 @@
 //      reduction point, so the test is uniform across the grid);
 //   2. each thread accumulates its share of up to KMAX inner products as
 //      error-free double-double sums (TwoProduct through fma, TwoSum);
-//   3. the workgroup combines them with wave64 cross-lane shuffles and LDS,
+//   3. the workgroup combines them with a wave64 DPP tree and LDS,
 //      and wave 0 stores one double-double partial per inner product while
 //      the other waves exit (the first reduction stage of Section 2.2);
-//   4. the second stage runs in the workgroups that arrive last: a
-//      two-level tree of arrival counters (see reduce_point) sums all
-//      partials in a fixed order, rounds once, and the very last workgroup
-//      evaluates the scalar recurrences (alpha, beta, omega, convergence)
+//   4. the second stage runs in polling group leaders: a two-level tree
+//      (see reduce_point) sums all partials in a fixed order, rounds once,
+//      and the last workgroup evaluates the scalar recurrences (alpha,
+//      beta, omega, convergence)
 //      on the device.
 // Partials are published with agent-scope (device-coherent) atomic stores
 // and read back with agent-scope atomic loads, and the store counter is
@@ -617,7 +617,7 @@ __device__ void finalize(DevState *st, int fin, const double *d, int K, double *
 // The reduction point at the end of a kernel; every thread of every
 // workgroup of the grid must call it exactly once, and return right after.
 //
-// First stage.  Each wave sums its lanes' partials (butterfly); waves 1 ..
+// First stage.  Each wave sums its lanes' partials (wave_sum); waves 1 ..
 // WAVES-1 leave theirs in LDS, meet wave 0 at one barrier and exit.  Wave 0
 // adds them in wave order.
 //
@@ -626,7 +626,7 @@ __device__ void finalize(DevState *st, int fin, const double *d, int K, double *
 // and ends at once: no wait for the stores, no atomic.  The group's last
 // workgroup, its leader, reads the other members' slots, one member per
 // lane, polling until none holds the empty marker any more, adds them with
-// its own in a lane butterfly (a fixed order), puts the empty marker back
+// its own in a wave tree (a fixed order), puts the empty marker back
 // and stores the group sum the same way; the leader of the last group,
 // workgroup G-1, collects the group sums likewise, rounds once and runs the
 // scalar recurrences (finalize).  A slot is read only after the value
@@ -2378,8 +2378,8 @@ __device__ __forceinline__ SmallCsr stage_csr(const DevCsr &A, char *base)
     return SmallCsr{rp, ci, va};
 }
 
-// Workgroup reduction of K double-doubles (each wave by shuffles, then the
-// NW wave results by shuffles in wave 0, a fixed tree), followed by the
+// Workgroup reduction of K double-doubles (each wave by its DPP tree, then
+// the NW wave results by shuffles in wave 0, a fixed tree), followed by the
 // finalize steps fins[0..nf) on thread 0, each taking its slice of the
 // rounded sums and applied only while the solve is in state needs[f].  Ends
 // past a barrier, so every thread sees the updated state.
