@@ -1030,7 +1030,10 @@ static bool small_path_ok(fk_csr A, const fk_opts &o)
 // (3 slices per wave) and 2048 by 4-6 %.
 static int fused_grid(fk_csr A, int step, int grid_spmv)
 {
-    const int per_cu = std::min(fused_per_cu(A->view(), step), 4);
+    // at most 4 per CU (FK_FUSED_PER_CU): more waves per SIMD, each with
+    // fewer entries in flight, measured slower
+    static const int cap = env_int("FK_FUSED_PER_CU", 4, 1, 8);
+    const int per_cu = std::min(fused_per_cu(A->view(), step), cap);
     int64_t g = grid_spmv;
     if (per_cu > 0 && A->cus > 0 && g > (int64_t)per_cu * A->cus) {
         g = (int64_t)per_cu * A->cus;

@@ -156,6 +156,38 @@ def test_edge_cases(method, small, device):
         assert_same_run(res, x, ref, "scaled identity")
 
 
+def _half_step_exits():
+    """convdiff2d_20 with tolerances at which the oracle's pipelined BiCGStab
+    leaves after the half step of iteration k >= 2 (no omega in its last
+    trace row), one for each parity of k - 1: the buffers the two-kernel
+    schedule holds r_i, p_i and A p_i in.  Found on the CPU, by the oracle
+    alone."""
+    A, b, _ = P.workload("convdiff2d_20")
+    found = {}
+    for e in np.linspace(2.0, 12.0, 81):
+        rtol = 10.0 ** -e
+        ref = oracle.solve(A, b, method="bicgstab_pipelined", rtol=rtol, trace=True)
+        if ref.status == "converged" and ref.k >= 2 and np.isnan(ref.t("omega")[-1]):
+            found.setdefault((ref.k - 1) & 1, rtol)
+        if len(found) == 2:
+            break
+    return A, b, found
+
+
+@pytest.mark.parametrize("small", [True, False], ids=["auto", "grid"])
+@pytest.mark.parametrize("method", BICG)
+def test_half_step_exit_later(method, small, device):
+    """A half-step exit after several iterations, with the iteration count
+    of either parity: x_{i+1} = x_i + alpha_i p_i from the right buffers."""
+    A, b, found = _half_step_exits()
+    assert set(found) == {0, 1}
+    for parity, rtol in sorted(found.items()):
+        ref = oracle.solve(A, b, method=oracle_method(method), rtol=rtol, trace=True)
+        print(f"\n[case] half step {method} parity {parity} rtol={rtol:.3e} k={ref.k} small={small}", flush=True)
+        res, x = gpu_solve(A, b, method=method, rtol=rtol, small=small)
+        assert_same_run(res, x, ref, f"half step, parity {parity}")
+
+
 @pytest.mark.parametrize("small", [True, False], ids=["auto", "grid"])
 @pytest.mark.parametrize("method", ALL)
 def test_breakdown(method, small, device):
