@@ -2337,7 +2337,7 @@ __global__ __launch_bounds__(WG) void k_gm_xupdate(int64_t n, double *__restrict
 // path reduces at separate points are reduced together: one reduction per
 // CG iteration ({<r_i,r_i>, <p_i,Ap_i>, <Ap_i,Ap_i>}), two per BiCGStab
 // iteration.  The iteration count is bounded by max_iter.
-constexpr int SWG = 1024;  // the most threads (and rows per thread: 8) it takes
+constexpr int SWG = 1024;  // the most threads (and rows per thread: 4) it takes
 
 // The matrix as the single-workgroup solver reads it: from LDS when it was
 // staged there at the start of the solve, else from global memory.
@@ -3084,12 +3084,12 @@ size_t small_staged_lds_bytes(int method_bicg, int64_t n, int64_t nnz)
 int small_rows_per_thread(int64_t n)
 {
     const int64_t r = (n + SWG - 1) / SWG;
-    return r <= 1 ? 1 : r <= 2 ? 2 : r <= 4 ? 4 : r <= 8 ? 8 : 0;
+    return r <= 1 ? 1 : r <= 2 ? 2 : r <= 4 ? 4 : 0;
 }
 
 // Threads of the single-workgroup solver for n rows: the fewest of 256,
 // 512 and 1024 that keep at most two rows per thread, else 1024 (up to
-// eight).  Every thread joins each reduction's double-double butterfly, so
+// four).  Every thread joins each reduction's double-double butterfly, so
 // for small systems fewer, fuller waves finish an iteration sooner
 // (measured on 32^2: 1024 threads 5.8 us, 512 threads 4.6 us per CG
 // iteration; on 63^2, 1024 threads stay ahead).
@@ -3103,7 +3103,7 @@ static hipError_t launch_small_w(int method_bicg, const DevCsr &A, const double 
                                  DevState *st, double *hist, double *scal, size_t shm, hipStream_t s)
 {
     const int64_t r = (A.n + WGS - 1) / WGS;
-    const int rpt = r <= 1 ? 1 : r <= 2 ? 2 : r <= 4 ? 4 : r <= 8 ? 8 : 0;
+    const int rpt = r <= 1 ? 1 : r <= 2 ? 2 : r <= 4 ? 4 : 0;
     switch (rpt * 2 + (method_bicg ? 1 : 0)) {
     case 2: return launch_shm(k_small_cg<1, STAGE, WGS>, 1, WGS, shm, s, A, b, x, st, hist, scal);
     case 4: return launch_shm(k_small_cg<2, STAGE, WGS>, 1, WGS, shm, s, A, b, x, st, hist, scal);
@@ -3114,7 +3114,6 @@ static hipError_t launch_small_w(int method_bicg, const DevCsr &A, const double 
     if constexpr (WGS == SWG) {
         switch (rpt * 2 + (method_bicg ? 1 : 0)) {
         case 8: return launch_shm(k_small_cg<4, STAGE, WGS>, 1, WGS, shm, s, A, b, x, st, hist, scal);
-        case 16: return launch_shm(k_small_cg<8, STAGE, WGS>, 1, WGS, shm, s, A, b, x, st, hist, scal);
         default: break;
         }
     }
