@@ -164,6 +164,19 @@ def cpu_baseline(A, b, budget_s: float = 20.0):
     return rates[best], best, rates, runs[best]
 
 
+def slot_chunk(A) -> int:
+    """Entries the slot-layout products request together for A: the most
+    distinct column offsets (column - row) of any 64-row slice, as 5, 7 or 8
+    (the library's rule, which names the kernel instance)."""
+    import numpy as np
+
+    rows = np.repeat(np.arange(A.n, dtype=np.int64), np.diff(A.row_ptr))
+    span = 2 * A.n + 1
+    keys = np.unique((rows // 64) * span + (A.col_idx.astype(np.int64) - rows + A.n))
+    width = int(np.bincount(keys // span).max()) if keys.size else 0
+    return 5 if width <= 5 else 7 if width <= 7 else 8
+
+
 def case_bytes(method: str, n: int, nnz: int, matrix_bytes: int) -> dict:
     """Algorithmic bytes per launch of each kernel kind of one iteration of
     `method`, on the CSR FP64 matrix ("csr") and on the layout the library
@@ -880,8 +893,9 @@ def main():
         "roofline": {"bound": "hbm", "achieved": layout_achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
                      "frac": layout_achieved / PEAK_HBM_GBS, "traffic": traffic,
                      "kernel": "fused SpMV + <p,Ap>, <Ap,Ap> (" + {
-                         "slots": "k_sell_rows<0,3,2,false>", "sliced16": "k_sell_rows<0,3,1,false>",
-                         "sliced": "k_sell_rows<0,3,0,false>", "row_blocks": "k_csr_rows<0,3>"}[layout] + ")",
+                         "slots": f"k_sell_rows<0,3,2,false,{slot_chunk(A)}>",
+                         "sliced16": "k_sell_rows<0,3,1,false,8>",
+                         "sliced": "k_sell_rows<0,3,0,false,8>", "row_blocks": "k_csr_rows<0,3>"}[layout] + ")",
                      "layout": layout,
                      "bytes_basis": "the layout's own arrays, each read once, + p read once + Ap written once",
                      "bytes_per_launch": spmv_layout_b, "avg_us": spmv_us,

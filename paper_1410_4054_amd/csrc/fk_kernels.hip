@@ -1237,7 +1237,10 @@ __device__ __forceinline__ SliceCols<COLS> slice_cols_of(const DevCsr &A, int sl
 // reduction are those of k_csr_rows, so y is bitwise identical to it.
 // NT: the matrix loads non-temporal (DevCsr::stream; a template parameter,
 // not a branch, so that each kernel keeps the registers of one path).
-template <int MODE, int DOTS, int COLS, bool NT>
+// SU: slot-layout entries requested together, the widest slice's count
+// (5 or 7) or 8; a chunk wider than the matrix's slices costs a predicated
+// slot on every row (192^3: 110 against 105 us per product with 8 and 7).
+template <int MODE, int DOTS, int COLS, bool NT, int SU = FK_SELL_UNROLL>
 __global__ __launch_bounds__(WG, FK_SPMV_MIN_WAVES) void k_sell_rows(DevCsr A, RowIo io, RedArgs red)
 {
     if (!runs(red))
@@ -1270,9 +1273,9 @@ __global__ __launch_bounds__(WG, FK_SPMV_MIN_WAVES) void k_sell_rows(DevCsr A, R
             wrow = io.w[srow];
         // (Three double-double accumulators leave room for fewer entries in
         // 64 VGPRs: 4 with int32 columns, 6 with slots.)
-        constexpr int U = KA < 3 ? FK_SELL_UNROLL
-                                 : COLS == COLS_INT32 ? FK_SELL_UNROLL / 2
-                                 : COLS == COLS_SLOTS ? 6 : FK_SELL_UNROLL;
+        constexpr int U = COLS == COLS_SLOTS ? (KA < 3 || SU < 6 ? SU : 6)
+                          : KA < 3 ? FK_SELL_UNROLL
+                          : COLS == COLS_INT32 ? FK_SELL_UNROLL / 2 : FK_SELL_UNROLL;
         double q = 0.0;
         if (width > 0) {  // uniform: a slice of empty rows reads nothing
             const SliceCols<COLS> cols = slice_cols_of<COLS>(A, sl, e0, lane, row);
@@ -2017,7 +2020,7 @@ __global__ __launch_bounds__(WG, FK_SPMV_MIN_WAVES) void k_csr_rows32(DevCsr A, 
 }
 
 // k_csr_rows32 on the sliced layout (vals32 in slice order).
-template <int COLS, bool F32ACC, bool NT>
+template <int COLS, bool F32ACC, bool NT, int SU = FK_SELL_UNROLL>
 __global__ __launch_bounds__(WG, FK_SPMV_MIN_WAVES) void k_sell_rows32(DevCsr A, const float *vals32,
                                                                         const float *v, float *y,
                                                                         RedArgs red)
@@ -2039,7 +2042,8 @@ __global__ __launch_bounds__(WG, FK_SPMV_MIN_WAVES) void k_sell_rows32(DevCsr A,
         float q = 0.f;
         if (width > 0) {  // uniform: a slice of empty rows reads nothing
             const SliceCols<COLS> cols = slice_cols_of<COLS>(A, sl, e0, lane, row);
-            q = slice_row_sum<float, FK_SELL_UNROLL, COLS, NT>(cols, vals32 + e0 + lane, VecOf<float>{v}, width);
+            q = slice_row_sum<float, COLS == COLS_SLOTS ? SU : FK_SELL_UNROLL, COLS, NT>(cols, vals32 + e0 + lane,
+                                                                                     VecOf<float>{v}, width);
         }
         if (live) {
             y[row] = q;
@@ -2743,8 +2747,13 @@ void set_launch_timing(hipEvent_t start, hipEvent_t stop)
 template <int MODE, int DOTS, bool NT>
 static hipError_t launch_sell(const DevCsr &A, const RowIo &io, const RedArgs &red, int grid, hipStream_t s)
 {
-    if (A.dg_mask)
+    if (A.dg_mask) {
+        if (A.max_width <= 5)
+            return launch(k_sell_rows<MODE, DOTS, COLS_SLOTS, NT, 5>, grid, WG, s, A, io, red);
+        if (A.max_width <= 7)
+            return launch(k_sell_rows<MODE, DOTS, COLS_SLOTS, NT, 7>, grid, WG, s, A, io, red);
         return launch(k_sell_rows<MODE, DOTS, COLS_SLOTS, NT>, grid, WG, s, A, io, red);
+    }
     if (A.sell_off4)
         return launch(k_sell_rows<MODE, DOTS, COLS_OFF16, NT>, grid, WG, s, A, io, red);
     return launch(k_sell_rows<MODE, DOTS, COLS_INT32, NT>, grid, WG, s, A, io, red);
@@ -2945,8 +2954,13 @@ template <bool F32ACC, bool NT>
 static hipError_t launch_sell32(const DevCsr &A, const float *vals32, const float *v, float *y,
                                 const RedArgs &red, int grid, hipStream_t s)
 {
-    if (A.dg_mask)
+    if (A.dg_mask) {
+        if (A.max_width <= 5)
+            return launch(k_sell_rows32<COLS_SLOTS, F32ACC, NT, 5>, grid, WG, s, A, vals32, v, y, red);
+        if (A.max_width <= 7)
+            return launch(k_sell_rows32<COLS_SLOTS, F32ACC, NT, 7>, grid, WG, s, A, vals32, v, y, red);
         return launch(k_sell_rows32<COLS_SLOTS, F32ACC, NT>, grid, WG, s, A, vals32, v, y, red);
+    }
     if (A.sell_off4)
         return launch(k_sell_rows32<COLS_OFF16, F32ACC, NT>, grid, WG, s, A, vals32, v, y, red);
     return launch(k_sell_rows32<COLS_INT32, F32ACC, NT>, grid, WG, s, A, vals32, v, y, red);
