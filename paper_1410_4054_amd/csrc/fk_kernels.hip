@@ -1237,9 +1237,10 @@ __device__ __forceinline__ SliceCols<COLS> slice_cols_of(const DevCsr &A, int sl
 // reduction are those of k_csr_rows, so y is bitwise identical to it.
 // NT: the matrix loads non-temporal (DevCsr::stream; a template parameter,
 // not a branch, so that each kernel keeps the registers of one path).
-// SU: slot-layout entries requested together, the widest slice's count
-// (5 or 7) or 8; a chunk wider than the matrix's slices costs a predicated
-// slot on every row (192^3: 110 against 105 us per product with 8 and 7).
+// SU: entries requested together, from the widest slice: 5 or 7 slots (the
+// slot layout), 4 entries (the other sliced layouts), else FK_SELL_UNROLL;
+// a chunk wider than the matrix's slices costs a predicated entry on every
+// row (192^3: 110 against 105 us per product with 8 and 7 slots).
 template <int MODE, int DOTS, int COLS, bool NT, int SU = FK_SELL_UNROLL>
 __global__ __launch_bounds__(WG, FK_SPMV_MIN_WAVES) void k_sell_rows(DevCsr A, RowIo io, RedArgs red)
 {
@@ -1274,6 +1275,7 @@ __global__ __launch_bounds__(WG, FK_SPMV_MIN_WAVES) void k_sell_rows(DevCsr A, R
         // (Three double-double accumulators leave room for fewer entries in
         // 64 VGPRs: 4 with int32 columns, 6 with slots.)
         constexpr int U = COLS == COLS_SLOTS ? (KA < 3 || SU < 6 ? SU : 6)
+                          : SU < FK_SELL_UNROLL ? SU
                           : KA < 3 ? FK_SELL_UNROLL
                           : COLS == COLS_INT32 ? FK_SELL_UNROLL / 2 : FK_SELL_UNROLL;
         double q = 0.0;
@@ -2754,8 +2756,13 @@ static hipError_t launch_sell(const DevCsr &A, const RowIo &io, const RedArgs &r
             return launch(k_sell_rows<MODE, DOTS, COLS_SLOTS, NT, 7>, grid, WG, s, A, io, red);
         return launch(k_sell_rows<MODE, DOTS, COLS_SLOTS, NT>, grid, WG, s, A, io, red);
     }
-    if (A.sell_off4)
+    if (A.sell_off4) {
+        if (A.max_width <= 4)
+            return launch(k_sell_rows<MODE, DOTS, COLS_OFF16, NT, 4>, grid, WG, s, A, io, red);
         return launch(k_sell_rows<MODE, DOTS, COLS_OFF16, NT>, grid, WG, s, A, io, red);
+    }
+    if (A.max_width <= 4)
+        return launch(k_sell_rows<MODE, DOTS, COLS_INT32, NT, 4>, grid, WG, s, A, io, red);
     return launch(k_sell_rows<MODE, DOTS, COLS_INT32, NT>, grid, WG, s, A, io, red);
 }
 
